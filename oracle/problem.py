@@ -1,0 +1,56 @@
+"""Assemble the oracle for one workload and run time steps.
+
+Oracle code: test infrastructure only.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import delta, flow, operators, solvers
+from .grid import Grid
+
+# solver selectors (same numbering as the workload definitions)
+JACOBI_PCG = 0
+AMG_PCG = 1
+
+
+class Problem:
+    def __init__(self, wl, poisson_solver=None, vel_rtol=None, poisson_rtol=None):
+        self.wl = wl
+        self.grid = Grid(wl.xf, wl.yf)
+        self.E_hat, self.E = delta.interpolation_matrices(self.grid, wl.xb, wl.yb)
+        self.ops = operators.Operators(self.grid, self.E, wl.nu, wl.dt)
+        self.ub = np.concatenate([np.asarray(wl.ubx, float), np.asarray(wl.uby, float)])
+        self.solver = wl.poisson_solver if poisson_solver is None else poisson_solver
+        self.vel_rtol = wl.vel_rtol if vel_rtol is None else vel_rtol
+        self.poisson_rtol = wl.poisson_rtol if poisson_rtol is None else poisson_rtol
+        self.H = None
+        if self.solver != JACOBI_PCG:
+            self.H = solvers.SAHierarchy(self.ops.K, theta=wl.amg_theta,
+                                         coarse_max=wl.amg_coarse_max,
+                                         max_levels=wl.amg_max_levels,
+                                         pre=wl.amg_pre, post=wl.amg_post)
+
+    def solve_poisson(self, rhs, x0, rtol=None, maxit=None):
+        rtol = self.poisson_rtol if rtol is None else rtol
+        maxit = self.wl.poisson_maxit if maxit is None else maxit
+        if self.H is None:
+            return solvers.jacobi_pcg(self.ops.K, rhs, x0, rtol, maxit)
+        return solvers.amg_pcg(self.H, self.ops.K, rhs, x0, rtol, maxit)
+
+    def initial_state(self):
+        return flow.initial_state(self.ops, self.wl.uinf, self.wl.alpha)
+
+    def step(self, state):
+        return flow.step(self.ops, state, self.ub, self.wl.uinf, self.wl.alpha,
+                         self.vel_rtol, self.wl.vel_maxit, self.solve_poisson)
+
+    def run(self, nsteps, state=None, callback=None):
+        state = self.initial_state() if state is None else state
+        infos = []
+        for _ in range(nsteps):
+            state, info = self.step(state)
+            infos.append(info)
+            if callback is not None:
+                callback(state, info)
+        return state, infos

@@ -1,0 +1,236 @@
+"""Synthetic workload generators for the cylinder-flow problems.
+
+This module is the one place both the HIP library and the CPU oracle take
+their inputs from.  It holds no arithmetic of the method itself: it only
+produces the problem definition (grid face coordinates, Lagrangian point
+positions, viscosity, time step, boundary data and solver settings) that
+the immersed-boundary projection method then operates on.
+
+The grids follow the recipe of the paper's impulsively started cylinder
+runs (Sec. 5.2, Table "gridinfo"): a square domain of side 30 centred on
+the body, a uniform patch of width h around the cylinder, and geometric
+(exponential) stretching outside it.  The body is a circle of diameter 1
+sampled by equally spaced Lagrangian points (Sec. 2, the discussion after
+the discrete delta function asks for a spacing close to h).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Dict, List, Optional
+
+import numpy as np
+
+# Solver selectors shared with the C header (ibpm.h): keep the values equal.
+SOLVER_JACOBI_PCG = 0
+SOLVER_AMG_PCG = 1
+SOLVER_AMG_PCG_MIXED = 2
+SOLVER_AMG_FCG_LEARNED = 3
+
+
+def stretch_ratio(n_side: int, h: float, width: float) -> float:
+    """Ratio r such that cells h*r, h*r^2, ..., h*r^n_side fill `width`.
+
+    Bisection on the geometric sum; used only to lay out grid faces.
+    """
+    if n_side <= 0:
+        raise ValueError("n_side must be positive")
+    if n_side * h >= width:
+        raise ValueError("uniform cells already fill the width")
+    lo, hi = 1.0, 8.0
+    for _ in range(200):
+        r = 0.5 * (lo + hi)
+        s = h * r * (r ** n_side - 1.0) / (r - 1.0)
+        if s > width:
+            hi = r
+        else:
+            lo = r
+    return 0.5 * (lo + hi)
+
+
+def uniform_faces(n: int, lo: float, hi: float) -> np.ndarray:
+    """n+1 equally spaced face coordinates on [lo, hi]."""
+    h = (hi - lo) / n
+    k = np.arange(n + 1, dtype=np.float64)
+    f = lo + k * h
+    f[-1] = hi
+    return f
+
+
+def stretched_faces(n: int, half_domain: float, half_box: float, h: float) -> np.ndarray:
+    """Faces of an n-cell line: uniform width h on [-half_box, half_box],
+    geometric stretching to +-half_domain outside.  Exactly symmetric
+    about 0 (the left half is the mirror image of the right half)."""
+    n_uni = int(round(2.0 * half_box / h))
+    if (n - n_uni) % 2 != 0 or n_uni % 2 != 0:
+        raise ValueError("cell counts must split symmetrically")
+    n_side = (n - n_uni) // 2
+    r = stretch_ratio(n_side, h, half_domain - half_box)
+    half_uni = n_uni // 2
+    right = [k * h for k in range(half_uni + 1)]  # 0 .. half_box
+    x = right[-1]
+    w = h
+    for _ in range(n_side):
+        w *= r
+        x += w
+        right.append(x)
+    right[-1] = half_domain
+    right = np.asarray(right, dtype=np.float64)
+    return np.concatenate([-right[:0:-1], right])
+
+
+def circle_points(n_b: int, cx: float = 0.0, cy: float = 0.0, radius: float = 0.5):
+    """n_b equally spaced points on a circle, k = 0 .. n_b-1 counter-clockwise
+    from angle 0."""
+    th = 2.0 * np.pi * np.arange(n_b, dtype=np.float64) / n_b
+    return cx + radius * np.cos(th), cy + radius * np.sin(th)
+
+
+@dataclasses.dataclass
+class Workload:
+    """Complete problem definition for one run of the method."""
+    name: str
+    xf: np.ndarray            # nx+1 x-face coordinates
+    yf: np.ndarray            # ny+1 y-face coordinates
+    xb: np.ndarray            # n_b Lagrangian x positions
+    yb: np.ndarray            # n_b Lagrangian y positions
+    ubx: np.ndarray           # n_b prescribed body x-velocity
+    uby: np.ndarray           # n_b prescribed body y-velocity
+    nu: float                 # kinematic viscosity (U D / Re)
+    dt: float                 # time step
+    nsteps: int               # steps of the run
+    uinf: float = 1.0         # freestream speed
+    alpha: float = 0.0        # inflow angle (radians)
+    vel_rtol: float = 1e-8    # velocity solve relative residual target
+    vel_maxit: int = 2000
+    poisson_solver: int = SOLVER_AMG_PCG
+    poisson_rtol: float = 1e-8
+    poisson_maxit: int = 2000
+    amg_theta: float = 0.0    # strength threshold
+    amg_pre: int = 2          # pre-smoothing Jacobi sweeps
+    amg_post: int = 2         # post-smoothing Jacobi sweeps
+    amg_coarse_max: int = 256
+    amg_max_levels: int = 12
+    description: str = ""
+
+    @property
+    def nx(self) -> int:
+        return len(self.xf) - 1
+
+    @property
+    def ny(self) -> int:
+        return len(self.yf) - 1
+
+    @property
+    def nb(self) -> int:
+        return len(self.xb)
+
+    @property
+    def n_q(self) -> int:
+        return (self.nx - 1) * self.ny + self.nx * (self.ny - 1)
+
+    @property
+    def n_lambda(self) -> int:
+        return self.nx * self.ny + 2 * self.nb
+
+    def replace(self, **kw) -> "Workload":
+        return dataclasses.replace(self, **kw)
+
+
+def _body(n_b, cx=0.0, cy=0.0):
+    xb, yb = circle_points(n_b, cx, cy)
+    return xb, yb, np.zeros(n_b), np.zeros(n_b)
+
+
+def cylinder_small(n: int = 96, n_b: int = 60, steps: int = 20) -> Workload:
+    """2-D flow past a fixed cylinder (D=1), Re=40, uniform n x n grid on
+    [-2,2]^2, Jacobi-preconditioned CG for both solves (the small case)."""
+    xf = uniform_faces(n, -2.0, 2.0)
+    xb, yb, ubx, uby = _body(n_b)
+    return Workload(name=f"cylinder_re40_uniform_{n}x{n}", xf=xf, yf=xf.copy(),
+                    xb=xb, yb=yb, ubx=ubx, uby=uby, nu=1.0 / 40.0, dt=0.01,
+                    nsteps=steps, poisson_solver=SOLVER_JACOBI_PCG,
+                    description=f"Re 40 cylinder, uniform {n}^2 on [-2,2]^2, {n_b} points, "
+                                "dt 0.01, Jacobi-PCG both solves, rtol 1e-8")
+
+
+def cylinder_stretched(n: int, h: float, n_b: int, re: float, dt: float, steps: int,
+                       cx: float = 0.0, cy: float = 0.0, alpha: float = 0.0,
+                       solver: int = SOLVER_AMG_PCG) -> Workload:
+    """Cylinder in [-15,15]^2, uniform patch [-1,1]^2 with spacing h, geometric
+    stretching outside; n x n cells."""
+    xf = stretched_faces(n, 15.0, 1.0, h)
+    xb, yb, ubx, uby = _body(n_b, cx, cy)
+    return Workload(name=f"cylinder_re{int(re)}_stretched_{n}x{n}", xf=xf, yf=xf.copy(),
+                    xb=xb, yb=yb, ubx=ubx, uby=uby, nu=1.0 / re, dt=dt, nsteps=steps,
+                    alpha=alpha, poisson_solver=solver,
+                    description=f"Re {re:g} cylinder, {n}^2 stretched grid on [-15,15]^2, "
+                                f"uniform box [-1,1]^2 h={h}, {n_b} points, dt {dt}")
+
+
+def cylinder_512(steps: int = 200) -> Workload:
+    """The 512^2 Re 40 AMG-PCG workload (262,458 Poisson unknowns)."""
+    return cylinder_stretched(512, 0.02, 157, 40.0, 0.005, steps)
+
+
+def cylinder_1024(steps: int = 500) -> Workload:
+    """1024^2 Re 100 workload used for the mixed-precision comparison."""
+    return cylinder_stretched(1024, 0.01, 314, 100.0, 0.0025, steps,
+                              solver=SOLVER_AMG_PCG_MIXED)
+
+
+def cylinder_2048(steps: int = 2000) -> Workload:
+    """2048^2 (4.2M cells) Re 100 workload."""
+    return cylinder_stretched(2048, 0.005, 628, 100.0, 0.002, steps)
+
+
+def cylinder_512_re100(steps: int = 200) -> Workload:
+    """512^2 Re 100 grid used for the learned-preconditioner study."""
+    return cylinder_stretched(512, 0.02, 157, 100.0, 0.005, steps,
+                              solver=SOLVER_AMG_FCG_LEARNED)
+
+
+def harvest_variants(seed: int, count: int = 1) -> List[Dict[str, float]]:
+    """Randomised cylinder centres (within +-0.46, keeping the delta support
+    inside the uniform patch) and inflow angles (+-10 degrees), seeded."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        cx, cy = rng.uniform(-0.46, 0.46, size=2)
+        a = rng.uniform(-10.0, 10.0) * math.pi / 180.0
+        out.append({"cx": float(cx), "cy": float(cy), "alpha": float(a)})
+    return out
+
+
+def tiny(nx: int = 12, ny: int = 10, n_b: int = 6, radius: float = 0.25,
+         stretched: bool = False, dt: float = 0.01, nu: float = 0.05) -> Workload:
+    """Small grids for brute-force dense checks: a body of a few points in
+    the middle of a [-1,1]^2 box.  The stretched variant keeps a uniform
+    patch [-0.5,0.5]^2 of 8x8 cells (h = 1/8) and stretches the rest out to
+    [-1.5,1.5]^2, so nx and ny must be even and at least 10."""
+    if stretched:
+        xf = stretched_faces(nx, 1.5, 0.5, 0.125)
+        yf = stretched_faces(ny, 1.5, 0.5, 0.125)
+    else:
+        xf, yf = uniform_faces(nx, -1.0, 1.0), uniform_faces(ny, -1.0, 1.0)
+    if n_b > 0:
+        xb, yb = circle_points(n_b, 0.0, 0.0, radius)
+    else:
+        xb, yb = np.zeros(0), np.zeros(0)
+    return Workload(name=f"tiny_{nx}x{ny}_{n_b}", xf=xf, yf=yf, xb=xb, yb=yb,
+                    ubx=np.zeros(n_b), uby=np.zeros(n_b), nu=nu, dt=dt, nsteps=2,
+                    poisson_solver=SOLVER_JACOBI_PCG)
+
+
+def random_vector(n: int, seed: int) -> np.ndarray:
+    """Seeded standard-normal FP64 vector."""
+    return np.random.default_rng(seed).standard_normal(n)
+
+
+WORKLOADS = {
+    "cylinder_small": cylinder_small,
+    "cylinder_512": cylinder_512,
+    "cylinder_1024": cylinder_1024,
+    "cylinder_2048": cylinder_2048,
+    "cylinder_512_re100": cylinder_512_re100,
+}
