@@ -1,0 +1,211 @@
+/*
+ * ibpm.h -- C ABI of the MI355X immersed-boundary projection library.
+ *
+ * The library advances the discrete incompressible Navier-Stokes equations
+ * with an immersed boundary by the projection method of Taira & Colonius as
+ * used in Layton, Krishnan & Barba, "cuIBM -- A GPU-accelerated Immersed
+ * Boundary Method" (arXiv:1109.3524), Sec. 2: per time step
+ *     A q*            = r1                     (Eq. 11a, velocity solve)
+ *     Q^T B^N Q lambda = Q^T q* - r2           (Eq. 11b, pressure + forces)
+ *     q^{n+1}         = q* - B^N Q lambda      (Eq. 11c, projection)
+ * with Q = [G, E^T], E the regularised-delta interpolation (Eqs. 5-7),
+ * lambda = (phi, f~), B^1 = dt Mf^{-1} (first-order approximation of A^{-1}).
+ * Every step runs on the GPU in hand-written HIP kernels for gfx950.
+ *
+ * Conventions shared by all calls
+ *  - Grid: nx x ny cells with face lines xf[0..nx], yf[0..ny] (strictly
+ *    increasing, non-uniform allowed; uniform under every delta support).
+ *  - Flux vector q (length n_q = (nx-1)*ny + nx*(ny-1)): first the u faces
+ *    u_{i,j} at (xf[i], yc_j), i = 1..nx-1, j = 0..ny-1, x index fastest,
+ *    stored as q = u * dy_j; then the v faces v_{i,j} at (xc_i, yf[j]),
+ *    i = 0..nx-1, j = 1..ny-1, stored as q = v * dx_i.
+ *  - lambda (length n_lambda = nx*ny + 2*nb): cell pressures phi (x fastest),
+ *    then the nb x-forces, then the nb y-forces on the Lagrangian points.
+ *    Pressure cell 0 is pinned (its row and column carry only the diagonal,
+ *    Sec. 2 last paragraph), so phi[0] = 0 when rhs[0] = 0.
+ *  - Device pointers are HIP device memory owned by the caller (for example
+ *    torch tensors); they must stay valid until the work queued on the
+ *    context's stream has completed.  Host pointers are read during the
+ *    call only.
+ *  - Every call queues work on the stream given to ibpm_build_operators and
+ *    returns without waiting, except where a host output (stats, forces,
+ *    walls) is requested: then it waits for the stream.
+ *  - Return codes: IBPM_OK or a negative IBPM_E* code; ibpm_last_error()
+ *    returns a text description.  No C++ exception crosses this boundary.
+ *  - One context serves one stream; calls on one context must not overlap.
+ */
+#ifndef IBPM_H
+#define IBPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IBPM_OK        0
+#define IBPM_EINVAL   -1   /* bad shape or parameter, delta support on a non-uniform patch */
+#define IBPM_ENOMEM   -2   /* device or host allocation failed */
+#define IBPM_ENOTCONV -3   /* iteration limit reached; outputs hold the last iterate */
+#define IBPM_EHIP     -4   /* a HIP runtime call failed */
+#define IBPM_ENAN     -5   /* a residual norm became NaN or Inf */
+
+/* Poisson solvers (Sec. 3: CG with diagonal or smoothed-aggregation AMG
+ * preconditioning).  The velocity solve always uses Jacobi-PCG. */
+#define IBPM_SOLVER_JACOBI_PCG       0
+#define IBPM_SOLVER_AMG_PCG          1
+#define IBPM_SOLVER_AMG_PCG_MIXED    2   /* reserved: FP32 inner AMG-PCG in FP64 refinement */
+#define IBPM_SOLVER_AMG_FCG_LEARNED  3   /* reserved: flexible CG with a learned stage */
+
+typedef struct ibpm_ctx ibpm_ctx;
+
+typedef struct ibpm_params {
+    int32_t nx, ny;              /* cells per direction, >= 4 */
+    const double *xf, *yf;       /* host, nx+1 and ny+1 face coordinates */
+    int32_t nb;                  /* Lagrangian points, >= 0 */
+    const double *xb, *yb;       /* host, nb point positions */
+    const double *ubx, *uby;     /* host, nb prescribed body velocity; NULL means 0 */
+    double nu;                   /* kinematic viscosity, > 0 */
+    double dt;                   /* time step, > 0 */
+    double uinf, alpha;          /* freestream speed and inflow angle (radians) */
+    int32_t bn_order;            /* order N of B^N; only 1 is supported */
+    double vel_rtol;             /* velocity solve: ||r|| <= vel_rtol ||b|| */
+    int32_t vel_maxit;
+    int32_t poisson_solver;      /* IBPM_SOLVER_* */
+    double poisson_rtol;
+    int32_t poisson_maxit;
+    double amg_theta;            /* strength threshold (0 = every connection strong) */
+    int32_t amg_pre, amg_post;   /* Jacobi sweeps before / after the coarse correction */
+    int32_t amg_coarse_max;      /* stop coarsening at or below this many unknowns */
+    int32_t amg_max_levels;
+} ibpm_params;
+
+typedef struct ibpm_solve_stats {
+    int32_t iters;        /* Krylov iterations */
+    int32_t status;       /* IBPM_OK, IBPM_ENOTCONV or IBPM_ENAN */
+    double relres;        /* true residual ||b - K x|| / ||b|| recomputed at exit */
+    double ms;            /* wall time of the call */
+} ibpm_solve_stats;
+
+typedef struct ibpm_step_stats {
+    int32_t steps;              /* steps taken */
+    int32_t vel_iters;          /* summed over the steps */
+    int32_t poisson_iters;      /* summed over the steps */
+    int32_t last_vel_iters, last_poisson_iters;
+    double vel_relres_max;      /* largest true relative residual over the steps */
+    double poisson_relres_max;
+    double fx, fy;              /* body force of the last step (sum of f~), C_d = 2 fx / (U^2 D) */
+    double ms;                  /* wall time of the call */
+    double vel_ms, poisson_ms;  /* wall time of the solves, summed over the steps */
+} ibpm_step_stats;
+
+/* Build every operator of Sec. 2 for the given grid and body, the
+ * smoothed-aggregation hierarchy when an AMG solver is selected (Sec. 3),
+ * and upload them to the current HIP device.  `stream` is a hipStream_t
+ * (NULL = the null stream) on which all later work of the context is
+ * queued.  On success *out owns all device memory of the context.
+ * Errors: IBPM_EINVAL (shapes, parameters, delta support not uniform),
+ * IBPM_ENOMEM, IBPM_EHIP. */
+int ibpm_build_operators(const ibpm_params *p, void *stream, ibpm_ctx **out);
+
+/* Free the context and all its device memory (waits for its stream). */
+int ibpm_destroy(ibpm_ctx *ctx);
+
+/* Text of the last error on this context ("" if none; also valid for NULL). */
+const char *ibpm_last_error(const ibpm_ctx *ctx);
+
+/* Sizes of the flux and lambda vectors. */
+int ibpm_sizes(const ibpm_ctx *ctx, int64_t *n_q, int64_t *n_lambda);
+
+/* Impulsive start (Sec. 5.2): q = freestream everywhere (device, n_q),
+ * conv_prev = 0 (device, n_q), lambda = 0 (device, n_lambda), wall values
+ * freestream and the step counter reset to 0. */
+int ibpm_init_state(ibpm_ctx *ctx, double *q, double *conv_prev, double *lambda);
+
+/* Advance nsteps time steps of Eq. (11) in place.
+ *   q         device n_q, in: q^n, out: q^{n+nsteps}
+ *   conv_prev device n_q, in: N(q^{n-1}) (ignored on step 0, where the
+ *             Adams-Bashforth history is taken as N(q^0)), out: N(q^{n+nsteps-1})
+ *   lambda    device n_lambda, in: warm start, out: last (phi, f~)
+ *   stats     host, may be NULL (then the call does not wait).
+ * Returns IBPM_ENOTCONV / IBPM_ENAN if a solve failed (the step is still
+ * completed with the last iterate). */
+int ibpm_step(ibpm_ctx *ctx, int32_t nsteps, double *q, double *conv_prev,
+              double *lambda, ibpm_step_stats *stats);
+
+/* Solve K lambda = rhs with K = Q^T B^1 Q pinned (Eq. 11b) by the selected
+ * Poisson solver.  rhs device n_lambda; lambda device n_lambda, in: initial
+ * guess, out: solution.  stats host, may be NULL. */
+int ibpm_solve_poisson(ibpm_ctx *ctx, const double *rhs, double *lambda,
+                       ibpm_solve_stats *stats);
+
+/* Solve A q = rhs (Eq. 11a) by Jacobi-PCG; q in: initial guess, out: solution. */
+int ibpm_solve_velocity(ibpm_ctx *ctx, const double *rhs, double *q,
+                        ibpm_solve_stats *stats);
+
+/* y = K x (pinned Q^T B^1 Q), x and y device n_lambda, distinct. */
+int ibpm_apply_K(ibpm_ctx *ctx, const double *x, double *y);
+
+/* y = A x (Mf/dt - nu/2 L on interior faces), x and y device n_q, distinct. */
+int ibpm_apply_A(ibpm_ctx *ctx, const double *x, double *y);
+
+/* Single stages of one step, for checking each kernel:
+ *   walls:   wall values n -> n+1 from q^n (convective outflow + mass balance)
+ *            into the context's "next" walls (does not swap them in);
+ *   rhs1:    r1 (device n_q) and N(q^n) (conv_now, device n_q) from q^n and
+ *            conv_prev, using the current and next walls; conv_prev is only
+ *            read (step counter 0 means N(q^{-1}) = N(q^n));
+ *   rhs2:    Poisson right-hand side [-D q* + bc2 ; E q* - u_B] (pinned
+ *            entry zeroed) with the next walls;
+ *   project: q_out = q* - B^1 Q lambda (Eq. 11c); q_out may alias qstar. */
+int ibpm_stage_walls(ibpm_ctx *ctx, const double *q);
+int ibpm_stage_rhs1(ibpm_ctx *ctx, const double *q, const double *conv_prev,
+                    double *r1, double *conv_now);
+int ibpm_stage_rhs2(ibpm_ctx *ctx, const double *qstar, double *rhs);
+int ibpm_stage_project(ibpm_ctx *ctx, const double *qstar, const double *lambda,
+                       double *q_out);
+
+/* Wall values, packed on the host as
+ *   uL[ny] uR[ny] vB[nx] vT[nx] uBt[nx+1] uTt[nx+1] vLt[ny+1] vRt[ny+1]
+ * (4*nx + 4*ny + 4 doubles).  which = 0: current walls, 1: next walls. */
+int ibpm_get_walls(ibpm_ctx *ctx, int32_t which, double *host);
+int ibpm_set_walls(ibpm_ctx *ctx, int32_t which, const double *host);
+
+/* Step counter (0 = the next step is the first, AB2 start-up). */
+int ibpm_get_step(const ibpm_ctx *ctx, int64_t *step);
+int ibpm_set_step(ibpm_ctx *ctx, int64_t step);
+
+/* Body force (sum of f~ over the points) of the last step or stage project. */
+int ibpm_get_forces(ibpm_ctx *ctx, double *fx, double *fy);
+
+/* Smoothed-aggregation hierarchy: number of levels, and per level (host
+ * arrays of length >= levels) the unknowns and stored non-zeros. */
+int ibpm_hierarchy_info(const ibpm_ctx *ctx, int32_t *levels, int64_t *sizes,
+                        int64_t *nnz);
+
+/* Aggregate index of every unknown of `level` (host, sizes[level] int32s). */
+int ibpm_get_aggregates(const ibpm_ctx *ctx, int32_t level, int32_t *agg);
+
+/* Kernels that ibpm_time_kernel can time (the launch configuration and
+ * operands are those of the time step). */
+#define IBPM_KERNEL_K0_JACOBI     0   /* damped Jacobi sweep with K, finest AMG level */
+#define IBPM_KERNEL_K0_PCG_SPMV   1   /* p = z + beta p; q = K p; p . q */
+#define IBPM_KERNEL_A_PCG_SPMV    2   /* velocity: p = D^{-1} r + beta p; q = A p; p . q */
+#define IBPM_KERNEL_K0_RESIDUAL   3   /* r = b - K x, finest AMG level */
+#define IBPM_KERNEL_RESTRICT0     4   /* b1 = P0^T r (finest to first coarse level) */
+#define IBPM_KERNEL_PROLONG0      5   /* x += P0 x1 */
+#define IBPM_KERNEL_PCG_UPDATE_K  6   /* x += a p; r -= a q; r . r */
+
+/* Time `reps` back-to-back launches of one kernel of the solver on the
+ * context's stream with HIP events and return the mean duration of one
+ * launch (ms) and the algorithmic bytes of one launch (every operand read
+ * once, every result written once).  Overwrites the context's work vectors
+ * (not the caller's).  Needs an AMG context for kernels 0, 3, 4, 5. */
+int ibpm_time_kernel(ibpm_ctx *ctx, int32_t kernel, int32_t reps, double *avg_ms,
+                     double *bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBPM_H */

@@ -1,0 +1,136 @@
+// Device data views and kernel launchers (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace ibpm {
+
+constexpr int kBlock = 256;        // threads per block (4 wave64)
+constexpr int kMaxParts = 2048;    // upper bound on blocks of a reducing kernel
+
+// Tensor-product staggered grid; metric arrays live on the device.
+struct GridView {
+    int nx, ny;
+    int n_u, n_v, n_q, n_cell;
+    const double *dx, *dy, *Dx, *Dy;      // nx, ny, nx+1, ny+1
+    const double *idx, *idy, *iDx, *iDy;  // reciprocals
+};
+
+// Packed wall values: uL[ny] uR[ny] vB[nx] vT[nx] uBt[nx+1] uTt[nx+1] vLt[ny+1] vRt[ny+1]
+struct WallOffsets {
+    int uL, uR, vB, vT, uBt, uTt, vLt, vRt, total;
+    __host__ __device__ static WallOffsets make(int nx, int ny) {
+        WallOffsets o;
+        o.uL = 0;
+        o.uR = ny;
+        o.vB = 2 * ny;
+        o.vT = 2 * ny + nx;
+        o.uBt = 2 * ny + 2 * nx;
+        o.uTt = 2 * ny + 3 * nx + 1;
+        o.vLt = 2 * ny + 4 * nx + 2;
+        o.vRt = 3 * ny + 4 * nx + 3;
+        o.total = 4 * ny + 4 * nx + 4;
+        return o;
+    }
+};
+
+struct CSRView {
+    int nrows, ncols;
+    const int32_t *ptr, *col;
+    const double *val;
+};
+
+// Level-0 Poisson operator K = Q^T B^1 Q (pinned), matrix-free pressure
+// stencil plus stored coupling rows.
+struct K0View {
+    GridView g;
+    double dt;
+    int nb, n;                       // n = n_cell + 2 nb
+    int cb_i0, cb_i1, cb_j0, cb_j1;  // box of cells coupled to forces
+    CSRView cf;                      // box cells -> (force 0..2nb-1, value)
+    CSRView kf;                      // force rows, columns in lambda numbering
+    const double *kf_diag;
+};
+
+// Velocity operator A = Mf/dt - (nu/2) L on interior faces (matrix-free).
+struct AView {
+    GridView g;
+    double dt, idt, nu;
+};
+
+// Device-side state of one Krylov solve.  Written only by the last block
+// of a reducing kernel; read by every later kernel of the stream.
+enum : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_NAN = 3, ST_ZERO_RHS = 4 };
+struct SolveStatus {
+    double bb, rr, rz, pq, beta, tol2, true_rr;
+    double fx, fy;
+    int iter, maxit, done, first;
+    unsigned int counter;
+    int pad;
+};
+
+// --- launchers (all asynchronous on `s`) ---------------------------------
+// step stages
+void launch_walls_update(hipStream_t s, GridView g, const double *w0, double *w1,
+                         const double *q, double uconv, double dt, double ly);
+void launch_momentum_rhs(hipStream_t s, GridView g, const double *q, const double *conv_prev,
+                         double *conv_now, double *r1, const double *w0, const double *w1,
+                         double nu, double dt, int first_step);
+void launch_poisson_rhs(hipStream_t s, GridView g, int nb, const double *qstar, const double *w1,
+                        CSRView E, const double *ub, double *rhs);
+void launch_project(hipStream_t s, GridView g, double dt, int nb, const double *qstar,
+                    const double *lam, double *qout, CSRView etu, int fu_i0, int fu_i1, int fu_j0,
+                    int fu_j1, CSRView etv, int fv_i0, int fv_i1, int fv_j0, int fv_j1);
+void launch_forces(hipStream_t s, int n_cell, int nb, const double *lam, SolveStatus *st);
+void launch_init_state(hipStream_t s, GridView g, double *q, double *conv, double *lam, int n_lam,
+                       double U, double V);
+void launch_fill_walls(hipStream_t s, GridView g, double *w, double U, double V);
+
+// operators
+void launch_apply_K0(hipStream_t s, const K0View &K, const double *x, double *y);
+void launch_apply_A(hipStream_t s, const AView &A, const double *x, double *y);
+
+// Krylov pieces; `op` selects K0 (0) or A (1) through the overloads
+void launch_pcg_init(hipStream_t s, const K0View &K, const double *b, const double *x, double *r,
+                     SolveStatus *st, double *parts, bool jacobi, double rtol2, int maxit);
+void launch_pcg_init(hipStream_t s, const AView &A, const double *b, const double *x, double *r,
+                     SolveStatus *st, double *parts, bool jacobi, double rtol2, int maxit);
+void launch_pcg_spmv(hipStream_t s, const K0View &K, const double *src, const double *pold,
+                     double *pnew, double *q, SolveStatus *st, double *parts, bool jacobi);
+void launch_pcg_spmv(hipStream_t s, const AView &A, const double *src, const double *pold,
+                     double *pnew, double *q, SolveStatus *st, double *parts, bool jacobi);
+void launch_pcg_update(hipStream_t s, const K0View &K, double *x, double *r, const double *p,
+                       const double *q, SolveStatus *st, double *parts, bool jacobi);
+void launch_pcg_update(hipStream_t s, const AView &A, double *x, double *r, const double *p,
+                       const double *q, SolveStatus *st, double *parts, bool jacobi);
+void launch_true_residual(hipStream_t s, const K0View &K, const double *b, const double *x,
+                          SolveStatus *st, double *parts);
+void launch_true_residual(hipStream_t s, const AView &A, const double *b, const double *x,
+                          SolveStatus *st, double *parts);
+void launch_dot_rz(hipStream_t s, int n, const double *r, const double *z, SolveStatus *st,
+                   double *parts);
+void launch_zero_if_zero_rhs(hipStream_t s, double *x, int n, const SolveStatus *st);
+
+// V-cycle pieces, predicated on st->done
+void launch_k0_jacobi_first(hipStream_t s, const K0View &K, double omega, const double *b,
+                            double *x, const SolveStatus *st);
+void launch_k0_jacobi(hipStream_t s, const K0View &K, double omega, const double *b,
+                      const double *xin, double *xout, const SolveStatus *st);
+void launch_k0_jacobi_rz(hipStream_t s, const K0View &K, double omega, const double *b,
+                         const double *xin, double *xout, SolveStatus *st, double *parts);
+void launch_k0_residual(hipStream_t s, const K0View &K, const double *b, const double *x, double *r,
+                        const SolveStatus *st);
+void launch_csr_jacobi_first(hipStream_t s, CSRView A, const double *wdinv, const double *b,
+                             double *x, const SolveStatus *st);
+void launch_csr_jacobi(hipStream_t s, CSRView A, const double *wdinv, const double *b,
+                       const double *xin, double *xout, const SolveStatus *st);
+void launch_csr_residual(hipStream_t s, CSRView A, const double *b, const double *x, double *r,
+                         const SolveStatus *st);
+void launch_csr_spmv(hipStream_t s, CSRView A, const double *x, double *y, const SolveStatus *st);
+void launch_csr_spmv_add(hipStream_t s, CSRView A, const double *x, double *y,
+                         const SolveStatus *st);
+void launch_dense_solve(hipStream_t s, int n, const double *inv_colmajor, const double *b, double *x,
+                        const SolveStatus *st);
+
+}  // namespace ibpm

@@ -1,0 +1,603 @@
+// Host-side assembly: grid metrics, the regularised-delta interpolation E,
+// the pinned matrix K = Q^T B^1 Q (stencil part, coupling rows), and the
+// smoothed-aggregation hierarchy used by the AMG preconditioner.
+//
+// Discretisation (Sec. 2 of Layton, Krishnan & Barba; the symmetrising
+// transformation it defers to Taira & Colonius is written out here):
+//   q = R u with R = diag(dy_j | dx_i);  momentum rows scaled by
+//   M = diag(Dx_i | Dy_j);  Mf = M R^{-1};  B^1 = dt Mf^{-1};
+//   G = -D^T with D the interior-face divergence;  E = E^ R^{-1} with
+//   E^_{k,i} = dA_i d_h(x_i - xi_k) d_h(y_i - eta_k)   (Eq. 7),
+//   dA = Dx_i dy_j on u faces and dx_i Dy_j on v faces;
+//   K = Q^T B^1 Q with Q = [G, E^T], pressure cell 0 pinned.
+#include "setup.h"
+
+#include <algorithm>
+#include <cmath>
+#include <map>
+#include <stdexcept>
+
+namespace ibpm {
+
+namespace {
+
+void fail(const std::string &msg) { throw std::runtime_error(msg); }
+
+// index of the cell [f[i], f[i+1]) holding x (clamped to the grid)
+int cell_of(const std::vector<double> &f, double x) {
+    int n = (int)f.size() - 1;
+    int i = (int)(std::upper_bound(f.begin(), f.end(), x) - f.begin()) - 1;
+    return std::min(std::max(i, 0), n - 1);
+}
+
+// width h of the cell holding x; every cell within two cells must share it
+double local_width(const std::vector<double> &f, const std::vector<double> &w, double x,
+                   const char *axis) {
+    int n = (int)w.size();
+    int i0 = cell_of(f, x);
+    if (i0 < 2 || i0 > n - 3)
+        fail(std::string("Lagrangian point too close to the domain edge along ") + axis);
+    double h = w[i0];
+    for (int i = i0 - 2; i <= i0 + 2; ++i)
+        if (std::fabs(w[i] - h) > 1e-9 * h)
+            fail(std::string("grid is not uniform under the delta support along ") + axis);
+    return h;
+}
+
+double delta_h(double r, double h) { return roma_phi(r / h) / h; }
+
+}  // namespace
+
+// Eq. (6): three-point regularised delta for unit spacing.  The inner
+// branch is taken to include s = 0.
+double roma_phi(double s) {
+    s = std::fabs(s);
+    if (s <= 0.5) return (1.0 + std::sqrt(1.0 - 3.0 * (s * s))) / 3.0;
+    if (s <= 1.5) {
+        double t = 1.0 - s;
+        return (5.0 - 3.0 * s - std::sqrt(1.0 - 3.0 * (t * t))) / 6.0;
+    }
+    return 0.0;
+}
+
+void build_grid(GridMetrics &g, int nx, int ny, const double *xf, const double *yf) {
+    if (nx < 4 || ny < 4) fail("need at least 4 cells per direction");
+    if (!xf || !yf) fail("face arrays must not be NULL");
+    g.nx = nx;
+    g.ny = ny;
+    g.xf.assign(xf, xf + nx + 1);
+    g.yf.assign(yf, yf + ny + 1);
+    g.dx.resize(nx);
+    g.dy.resize(ny);
+    g.xc.resize(nx);
+    g.yc.resize(ny);
+    for (int i = 0; i < nx; ++i) {
+        g.dx[i] = g.xf[i + 1] - g.xf[i];
+        if (!(g.dx[i] > 0)) fail("x faces must be strictly increasing");
+        g.xc[i] = 0.5 * (g.xf[i] + g.xf[i + 1]);
+    }
+    for (int j = 0; j < ny; ++j) {
+        g.dy[j] = g.yf[j + 1] - g.yf[j];
+        if (!(g.dy[j] > 0)) fail("y faces must be strictly increasing");
+        g.yc[j] = 0.5 * (g.yf[j] + g.yf[j + 1]);
+    }
+    g.Dx.resize(nx + 1);
+    g.Dy.resize(ny + 1);
+    g.Dx[0] = 0.5 * g.dx[0];
+    for (int i = 1; i < nx; ++i) g.Dx[i] = 0.5 * (g.dx[i - 1] + g.dx[i]);
+    g.Dx[nx] = 0.5 * g.dx[nx - 1];
+    g.Dy[0] = 0.5 * g.dy[0];
+    for (int j = 1; j < ny; ++j) g.Dy[j] = 0.5 * (g.dy[j - 1] + g.dy[j]);
+    g.Dy[ny] = 0.5 * g.dy[ny - 1];
+    g.n_u = (int64_t)(nx - 1) * ny;
+    g.n_v = (int64_t)nx * (ny - 1);
+    g.n_q = g.n_u + g.n_v;
+    g.n_cell = (int64_t)nx * ny;
+    if (g.n_q + 2 > INT32_MAX / 2) fail("grid too large for 32-bit indices");
+}
+
+namespace {
+
+void build_E(Model &m, const double *xb, const double *yb) {
+    const GridMetrics &g = m.g;
+    int nb = m.nb;
+    CSR &E = m.E;
+    E.nrows = 2 * nb;
+    E.ncols = (int32_t)g.n_q;
+    E.ptr.assign(2 * nb + 1, 0);
+    std::vector<std::vector<std::pair<int32_t, double>>> rows(2 * nb);
+    for (int k = 0; k < nb; ++k) {
+        double X = xb[k], Y = yb[k];
+        double hx = local_width(g.xf, g.dx, X, "x");
+        double hy = local_width(g.yf, g.dy, Y, "y");
+        int i0 = cell_of(g.xf, X), j0 = cell_of(g.yf, Y);
+        // u row k: faces x_i (i = 1..nx-1) at yc_j
+        for (int j = std::max(0, j0 - 2); j <= std::min(g.ny - 1, j0 + 2); ++j) {
+            if (!(std::fabs(g.yc[j] - Y) < 1.5 * hy)) continue;
+            for (int i = std::max(1, i0 - 2); i <= std::min(g.nx - 1, i0 + 3); ++i) {
+                if (!(std::fabs(g.xf[i] - X) < 1.5 * hx)) continue;
+                double w = g.Dx[i] * g.dy[j] * delta_h(g.xf[i] - X, hx) * delta_h(g.yc[j] - Y, hy);
+                rows[k].push_back({(int32_t)g.uidx(i, j), w * (1.0 / g.dy[j])});
+            }
+        }
+        // v row nb+k: faces y_j (j = 1..ny-1) at xc_i
+        for (int j = std::max(1, j0 - 2); j <= std::min(g.ny - 1, j0 + 3); ++j) {
+            if (!(std::fabs(g.yf[j] - Y) < 1.5 * hy)) continue;
+            for (int i = std::max(0, i0 - 2); i <= std::min(g.nx - 1, i0 + 2); ++i) {
+                if (!(std::fabs(g.xc[i] - X) < 1.5 * hx)) continue;
+                double w = g.dx[i] * g.Dy[j] * delta_h(g.xc[i] - X, hx) * delta_h(g.yf[j] - Y, hy);
+                rows[nb + k].push_back({(int32_t)g.vidx(i, j), w * (1.0 / g.dx[i])});
+            }
+        }
+    }
+    for (int r = 0; r < 2 * nb; ++r) {
+        std::sort(rows[r].begin(), rows[r].end());
+        for (auto &e : rows[r]) {
+            E.col.push_back(e.first);
+            E.val.push_back(e.second);
+        }
+        E.ptr[r + 1] = (int32_t)E.col.size();
+    }
+}
+
+// decode a flux index into (is_v, i, j)
+inline void face_of(const GridMetrics &g, int64_t f, bool &is_v, int &i, int &j) {
+    if (f < g.n_u) {
+        is_v = false;
+        j = (int)(f / (g.nx - 1));
+        i = (int)(f % (g.nx - 1)) + 1;
+    } else {
+        is_v = true;
+        int64_t r = f - g.n_u;
+        j = (int)(r / g.nx) + 1;
+        i = (int)(r % g.nx);
+    }
+}
+
+// B^1 on a face: dt / (M / R)
+inline double b1_face(const Model &m, bool is_v, int i, int j) {
+    const GridMetrics &g = m.g;
+    double Mf = is_v ? g.Dy[j] / g.dx[i] : g.Dx[i] / g.dy[j];
+    return m.dt / Mf;
+}
+
+void build_coupling(Model &m) {
+    const GridMetrics &g = m.g;
+    int nb = m.nb;
+    int64_t nc = g.n_cell;
+    const CSR &E = m.E;
+    // cell -> (force, value) for K_{phi f} = G^T B^1 E^T (pinned cell 0 dropped)
+    std::map<int64_t, std::map<int32_t, double>> cf;
+    // face -> list of (force row, E value), for K_ff and for E^T gathers
+    std::map<int64_t, std::vector<std::pair<int32_t, double>>> ft;
+    for (int k = 0; k < 2 * nb; ++k) {
+        for (int p = E.ptr[k]; p < E.ptr[k + 1]; ++p) {
+            int64_t f = E.col[p];
+            double e = E.val[p];
+            bool is_v;
+            int i, j;
+            face_of(g, f, is_v, i, j);
+            double t = b1_face(m, is_v, i, j) * e;
+            // G^T: a face adds +1 to the cell on its high side, -1 to the low side
+            int64_t c_hi = (int64_t)j * g.nx + i;
+            int64_t c_lo = is_v ? (int64_t)(j - 1) * g.nx + i : (int64_t)j * g.nx + (i - 1);
+            if (c_hi != 0) cf[c_hi][k] += t;
+            if (c_lo != 0) cf[c_lo][k] -= t;
+            ft[f].push_back({k, e});
+        }
+    }
+    // bounding box of coupled cells
+    m.cb_i0 = g.nx; m.cb_i1 = -1; m.cb_j0 = g.ny; m.cb_j1 = -1;
+    for (auto &kv : cf) {
+        int i = (int)(kv.first % g.nx), j = (int)(kv.first / g.nx);
+        m.cb_i0 = std::min(m.cb_i0, i); m.cb_i1 = std::max(m.cb_i1, i);
+        m.cb_j0 = std::min(m.cb_j0, j); m.cb_j1 = std::max(m.cb_j1, j);
+    }
+    if (cf.empty()) { m.cb_i0 = 0; m.cb_i1 = -1; m.cb_j0 = 0; m.cb_j1 = -1; }
+    int bw = m.cb_i1 - m.cb_i0 + 1, bh = m.cb_j1 - m.cb_j0 + 1;
+    m.Kcf = CSR();
+    m.Kcf.nrows = std::max(0, bw * bh);
+    m.Kcf.ncols = 2 * nb;
+    m.Kcf.ptr.assign(m.Kcf.nrows + 1, 0);
+    for (int jj = 0; jj < bh; ++jj)
+        for (int ii = 0; ii < bw; ++ii) {
+            int r = jj * bw + ii;
+            int64_t c = (int64_t)(m.cb_j0 + jj) * g.nx + (m.cb_i0 + ii);
+            auto it = cf.find(c);
+            if (it != cf.end())
+                for (auto &e : it->second) {
+                    m.Kcf.col.push_back(e.first);
+                    m.Kcf.val.push_back(e.second);
+                }
+            m.Kcf.ptr[r + 1] = (int32_t)m.Kcf.col.size();
+        }
+    // force rows: K_{f phi} (transpose of the cell coupling) and K_ff
+    std::vector<std::map<int64_t, double>> frow(2 * nb);
+    for (auto &kv : cf)
+        for (auto &e : kv.second) frow[e.first][kv.first] = e.second;
+    for (auto &kv : ft) {
+        bool is_v;
+        int i, j;
+        face_of(g, kv.first, is_v, i, j);
+        double b1 = b1_face(m, is_v, i, j);
+        for (auto &a : kv.second)
+            for (auto &b : kv.second) frow[a.first][nc + b.first] += (a.second * b1) * b.second;
+    }
+    m.Kf = CSR();
+    m.Kf.nrows = 2 * nb;
+    m.Kf.ncols = (int32_t)(nc + 2 * nb);
+    m.Kf.ptr.assign(2 * nb + 1, 0);
+    m.Kf_diag.assign(2 * nb, 0.0);
+    for (int k = 0; k < 2 * nb; ++k) {
+        for (auto &e : frow[k]) {
+            m.Kf.col.push_back((int32_t)e.first);
+            m.Kf.val.push_back(e.second);
+            if (e.first == nc + k) m.Kf_diag[k] = e.second;
+        }
+        m.Kf.ptr[k + 1] = (int32_t)m.Kf.col.size();
+    }
+    // E^T gathers by face, u and v separately, over the face boxes
+    m.fu_i0 = g.nx; m.fu_i1 = -1; m.fu_j0 = g.ny; m.fu_j1 = -1;
+    m.fv_i0 = g.nx; m.fv_i1 = -1; m.fv_j0 = g.ny; m.fv_j1 = -1;
+    for (auto &kv : ft) {
+        bool is_v;
+        int i, j;
+        face_of(g, kv.first, is_v, i, j);
+        if (!is_v) {
+            m.fu_i0 = std::min(m.fu_i0, i); m.fu_i1 = std::max(m.fu_i1, i);
+            m.fu_j0 = std::min(m.fu_j0, j); m.fu_j1 = std::max(m.fu_j1, j);
+        } else {
+            m.fv_i0 = std::min(m.fv_i0, i); m.fv_i1 = std::max(m.fv_i1, i);
+            m.fv_j0 = std::min(m.fv_j0, j); m.fv_j1 = std::max(m.fv_j1, j);
+        }
+    }
+    auto make_gather = [&](CSR &out, bool want_v, int i0, int i1, int j0, int j1) {
+        out = CSR();
+        int w = i1 - i0 + 1, h = j1 - j0 + 1;
+        out.nrows = std::max(0, w * h);
+        out.ncols = nb;
+        out.ptr.assign(out.nrows + 1, 0);
+        for (int jj = 0; jj < h; ++jj)
+            for (int ii = 0; ii < w; ++ii) {
+                int i = i0 + ii, j = j0 + jj;
+                int64_t f = want_v ? g.vidx(i, j) : g.uidx(i, j);
+                auto it = ft.find(f);
+                if (it != ft.end()) {
+                    std::vector<std::pair<int32_t, double>> es = it->second;
+                    std::sort(es.begin(), es.end());
+                    for (auto &e : es) {
+                        out.col.push_back(want_v ? e.first - nb : e.first);
+                        out.val.push_back(e.second);
+                    }
+                }
+                out.ptr[jj * w + ii + 1] = (int32_t)out.col.size();
+            }
+    };
+    if (m.fu_i1 < 0) { m.fu_i0 = 1; m.fu_i1 = 0; m.fu_j0 = 0; m.fu_j1 = -1; }
+    if (m.fv_i1 < 0) { m.fv_i0 = 0; m.fv_i1 = -1; m.fv_j0 = 1; m.fv_j1 = 0; }
+    make_gather(m.Etu, false, m.fu_i0, m.fu_i1, m.fu_j0, m.fu_j1);
+    make_gather(m.Etv, true, m.fv_i0, m.fv_i1, m.fv_j0, m.fv_j1);
+}
+
+// Full pinned K in CSR (pressure stencil + coupling + force rows).
+void build_full_K(Model &m) {
+    const GridMetrics &g = m.g;
+    int nx = g.nx, ny = g.ny;
+    int64_t nc = g.n_cell;
+    int nb = m.nb;
+    CSR &K = m.K;
+    K = CSR();
+    K.nrows = K.ncols = (int32_t)(nc + 2 * nb);
+    K.ptr.assign(K.nrows + 1, 0);
+    K.col.reserve(5 * nc + m.Kcf.nnz() + m.Kf.nnz());
+    K.val.reserve(K.col.capacity());
+    int bw = m.cb_i1 - m.cb_i0 + 1;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int64_t c = (int64_t)j * nx + i;
+            // B^1 on the four faces (0 where the face is a wall)
+            double bw_ = i > 0 ? b1_face(m, false, i, j) : 0.0;
+            double be_ = i < nx - 1 ? b1_face(m, false, i + 1, j) : 0.0;
+            double bs_ = j > 0 ? b1_face(m, true, i, j) : 0.0;
+            double bn_ = j < ny - 1 ? b1_face(m, true, i, j + 1) : 0.0;
+            double diag = ((bw_ + be_) + bs_) + bn_;
+            auto push = [&](int64_t col, double v) {
+                K.col.push_back((int32_t)col);
+                K.val.push_back(v);
+            };
+            if (c == 0) {
+                push(0, diag);
+            } else {
+                if (j > 0 && c - nx != 0) push(c - nx, -bs_);
+                if (i > 0 && c - 1 != 0) push(c - 1, -bw_);
+                push(c, diag);
+                if (i < nx - 1) push(c + 1, -be_);
+                if (j < ny - 1) push(c + nx, -bn_);
+                if (i >= m.cb_i0 && i <= m.cb_i1 && j >= m.cb_j0 && j <= m.cb_j1) {
+                    int r = (j - m.cb_j0) * bw + (i - m.cb_i0);
+                    for (int p = m.Kcf.ptr[r]; p < m.Kcf.ptr[r + 1]; ++p)
+                        push(nc + m.Kcf.col[p], m.Kcf.val[p]);
+                }
+            }
+            K.ptr[c + 1] = (int32_t)K.col.size();
+        }
+    for (int k = 0; k < 2 * nb; ++k) {
+        for (int p = m.Kf.ptr[k]; p < m.Kf.ptr[k + 1]; ++p) {
+            K.col.push_back(m.Kf.col[p]);
+            K.val.push_back(m.Kf.val[p]);
+        }
+        K.ptr[nc + k + 1] = (int32_t)K.col.size();
+    }
+}
+
+}  // namespace
+
+void build_model(Model &m, int nx, int ny, const double *xf, const double *yf, int nb,
+                 const double *xb, const double *yb, const double *ubx, const double *uby,
+                 double nu, double dt) {
+    build_grid(m.g, nx, ny, xf, yf);
+    if (nb < 0) fail("nb must be >= 0");
+    if (nb > 0 && (!xb || !yb)) fail("body point arrays must not be NULL");
+    if (!(nu > 0) || !(dt > 0)) fail("nu and dt must be positive");
+    m.nb = nb;
+    m.nu = nu;
+    m.dt = dt;
+    m.ub.assign(2 * nb, 0.0);
+    for (int k = 0; k < nb; ++k) {
+        if (ubx) m.ub[k] = ubx[k];
+        if (uby) m.ub[nb + k] = uby[k];
+    }
+    build_E(m, xb, yb);
+    build_coupling(m);
+    build_full_K(m);
+}
+
+// ---------------------------------------------------------------------------
+// sparse helpers
+
+CSR csr_transpose(const CSR &A) {
+    CSR T;
+    T.nrows = A.ncols;
+    T.ncols = A.nrows;
+    T.ptr.assign(T.nrows + 1, 0);
+    for (int32_t c : A.col) T.ptr[c + 1]++;
+    for (int r = 0; r < T.nrows; ++r) T.ptr[r + 1] += T.ptr[r];
+    T.col.resize(A.col.size());
+    T.val.resize(A.val.size());
+    std::vector<int32_t> pos(T.ptr.begin(), T.ptr.end() - 1);
+    for (int r = 0; r < A.nrows; ++r)
+        for (int p = A.ptr[r]; p < A.ptr[r + 1]; ++p) {
+            int32_t q = pos[A.col[p]]++;
+            T.col[q] = r;
+            T.val[q] = A.val[p];
+        }
+    return T;
+}
+
+// Gustavson product with a dense accumulator; output rows sorted.
+CSR csr_multiply(const CSR &A, const CSR &B) {
+    if (A.ncols != B.nrows) fail("csr_multiply: shape mismatch");
+    CSR C;
+    C.nrows = A.nrows;
+    C.ncols = B.ncols;
+    C.ptr.assign(C.nrows + 1, 0);
+    std::vector<double> acc(B.ncols, 0.0);
+    std::vector<int32_t> mark(B.ncols, -1);
+    std::vector<int32_t> cols;
+    for (int r = 0; r < A.nrows; ++r) {
+        cols.clear();
+        for (int p = A.ptr[r]; p < A.ptr[r + 1]; ++p) {
+            int32_t k = A.col[p];
+            double a = A.val[p];
+            for (int q = B.ptr[k]; q < B.ptr[k + 1]; ++q) {
+                int32_t c = B.col[q];
+                if (mark[c] != r) {
+                    mark[c] = r;
+                    acc[c] = a * B.val[q];
+                    cols.push_back(c);
+                } else {
+                    acc[c] += a * B.val[q];
+                }
+            }
+        }
+        std::sort(cols.begin(), cols.end());
+        for (int32_t c : cols) {
+            C.col.push_back(c);
+            C.val.push_back(acc[c]);
+        }
+        C.ptr[r + 1] = (int32_t)C.col.size();
+    }
+    return C;
+}
+
+// ---------------------------------------------------------------------------
+// smoothed aggregation (Sec. 3: PCG with a smoothed-aggregation AMG
+// preconditioner).  Reading of the unstated parameters: strength
+// |a_ij| >= max(theta, 1e-12) sqrt(|a_ii a_jj|); three greedy aggregation
+// passes in natural order; constant tentative prolongator; one damped
+// Jacobi smoothing step of it with weight 4 / (3 rho), rho the Gershgorin
+// bound of D^{-1} A; Galerkin coarse operator.
+
+namespace {
+
+double diag_of(const CSR &A, int r) {
+    for (int p = A.ptr[r]; p < A.ptr[r + 1]; ++p)
+        if (A.col[p] == r) return A.val[p];
+    return 0.0;
+}
+
+double gershgorin(const CSR &A, const std::vector<double> &d) {
+    double rho = 0.0;
+    for (int r = 0; r < A.nrows; ++r) {
+        double s = 0.0;
+        for (int p = A.ptr[r]; p < A.ptr[r + 1]; ++p) s += std::fabs(A.val[p]);
+        rho = std::max(rho, s / std::fabs(d[r]));
+    }
+    return rho;
+}
+
+// strong-neighbour lists (sorted, excluding the diagonal)
+void strength_graph(const CSR &A, const std::vector<double> &d, double theta,
+                    std::vector<int32_t> &sptr, std::vector<int32_t> &sidx) {
+    double thr = std::max(theta, 1e-12);
+    sptr.assign(A.nrows + 1, 0);
+    sidx.clear();
+    for (int r = 0; r < A.nrows; ++r) {
+        for (int p = A.ptr[r]; p < A.ptr[r + 1]; ++p) {
+            int c = A.col[p];
+            if (c == r) continue;
+            if (std::fabs(A.val[p]) >= thr * std::sqrt(std::fabs(d[r] * d[c]))) sidx.push_back(c);
+        }
+        sptr[r + 1] = (int32_t)sidx.size();
+    }
+}
+
+int32_t aggregate(int n, const std::vector<int32_t> &sptr, const std::vector<int32_t> &sidx,
+                  std::vector<int32_t> &agg) {
+    agg.assign(n, -1);
+    int32_t nagg = 0;
+    // pass 1: a node whose strong neighbours are all free roots an aggregate
+    for (int i = 0; i < n; ++i) {
+        if (agg[i] != -1) continue;
+        bool free_nbhd = true;
+        for (int p = sptr[i]; p < sptr[i + 1]; ++p)
+            if (agg[sidx[p]] != -1) { free_nbhd = false; break; }
+        if (!free_nbhd) continue;
+        agg[i] = nagg;
+        for (int p = sptr[i]; p < sptr[i + 1]; ++p) agg[sidx[p]] = nagg;
+        ++nagg;
+    }
+    std::vector<int32_t> pass1 = agg;
+    // pass 2: join the aggregate of the lowest-index neighbour taken in pass 1
+    for (int i = 0; i < n; ++i) {
+        if (agg[i] != -1) continue;
+        for (int p = sptr[i]; p < sptr[i + 1]; ++p)
+            if (pass1[sidx[p]] != -1) { agg[i] = pass1[sidx[p]]; break; }
+    }
+    // pass 3: remaining nodes root aggregates with their free neighbours
+    for (int i = 0; i < n; ++i) {
+        if (agg[i] != -1) continue;
+        agg[i] = nagg;
+        for (int p = sptr[i]; p < sptr[i + 1]; ++p)
+            if (agg[sidx[p]] == -1) agg[sidx[p]] = nagg;
+        ++nagg;
+    }
+    return nagg;
+}
+
+// P = T - w D^{-1} A T with T_{i,agg(i)} = 1
+CSR smoothed_prolongator(const CSR &A, const std::vector<double> &d,
+                         const std::vector<int32_t> &agg, int32_t nagg, double w) {
+    CSR P;
+    P.nrows = A.nrows;
+    P.ncols = nagg;
+    P.ptr.assign(A.nrows + 1, 0);
+    std::vector<double> acc(nagg, 0.0);
+    std::vector<int32_t> mark(nagg, -1);
+    std::vector<int32_t> cols;
+    for (int r = 0; r < A.nrows; ++r) {
+        cols.clear();
+        for (int p = A.ptr[r]; p < A.ptr[r + 1]; ++p) {
+            int32_t a = agg[A.col[p]];
+            if (mark[a] != r) { mark[a] = r; acc[a] = A.val[p]; cols.push_back(a); }
+            else acc[a] += A.val[p];
+        }
+        if (mark[agg[r]] != r) { mark[agg[r]] = r; acc[agg[r]] = 0.0; cols.push_back(agg[r]); }
+        std::sort(cols.begin(), cols.end());
+        double dinv = 1.0 / d[r];
+        for (int32_t a : cols) {
+            double t = (a == agg[r]) ? 1.0 : 0.0;
+            P.col.push_back(a);
+            P.val.push_back(t - w * (dinv * acc[a]));
+        }
+        P.ptr[r + 1] = (int32_t)P.col.size();
+    }
+    return P;
+}
+
+void finish_level(Level &L) {
+    int n = L.A.nrows;
+    std::vector<double> d(n);
+    for (int r = 0; r < n; ++r) {
+        d[r] = diag_of(L.A, r);
+        if (!(d[r] > 0)) fail("AMG: non-positive diagonal");
+    }
+    L.omega = 4.0 / (3.0 * gershgorin(L.A, d));
+    L.wdinv.resize(n);
+    for (int r = 0; r < n; ++r) L.wdinv[r] = L.omega / d[r];
+}
+
+// dense Cholesky (lower) and explicit inverse, column-major output
+void dense_spd_inverse(const CSR &A, std::vector<double> &inv) {
+    int n = A.nrows;
+    std::vector<double> M((size_t)n * n, 0.0);   // row-major
+    for (int r = 0; r < n; ++r)
+        for (int p = A.ptr[r]; p < A.ptr[r + 1]; ++p) M[(size_t)r * n + A.col[p]] = A.val[p];
+    // Cholesky in place (lower)
+    for (int j = 0; j < n; ++j) {
+        double s = M[(size_t)j * n + j];
+        for (int k = 0; k < j; ++k) s -= M[(size_t)j * n + k] * M[(size_t)j * n + k];
+        if (!(s > 0)) fail("AMG: coarsest operator is not positive definite");
+        double ljj = std::sqrt(s);
+        M[(size_t)j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double t = M[(size_t)i * n + j];
+            for (int k = 0; k < j; ++k) t -= M[(size_t)i * n + k] * M[(size_t)j * n + k];
+            M[(size_t)i * n + j] = t / ljj;
+        }
+    }
+    inv.assign((size_t)n * n, 0.0);
+    std::vector<double> y(n);
+    for (int c = 0; c < n; ++c) {
+        // L y = e_c
+        for (int i = 0; i < n; ++i) {
+            double t = (i == c) ? 1.0 : 0.0;
+            for (int k = 0; k < i; ++k) t -= M[(size_t)i * n + k] * y[k];
+            y[i] = t / M[(size_t)i * n + i];
+        }
+        // L^T x = y
+        for (int i = n - 1; i >= 0; --i) {
+            double t = y[i];
+            for (int k = i + 1; k < n; ++k) t -= M[(size_t)k * n + i] * y[k];
+            y[i] = t / M[(size_t)i * n + i];
+        }
+        for (int i = 0; i < n; ++i) inv[(size_t)c * n + i] = y[i];
+    }
+}
+
+}  // namespace
+
+void build_hierarchy(Hierarchy &h, const CSR &K, const AmgParams &prm) {
+    h.levels.clear();
+    h.levels.emplace_back();
+    h.levels[0].A = K;
+    finish_level(h.levels[0]);
+    while (h.levels.back().A.nrows > prm.coarse_max && (int)h.levels.size() < prm.max_levels) {
+        Level &L = h.levels.back();
+        int n = L.A.nrows;
+        std::vector<double> d(n);
+        for (int r = 0; r < n; ++r) d[r] = diag_of(L.A, r);
+        std::vector<int32_t> sptr, sidx;
+        strength_graph(L.A, d, prm.theta, sptr, sidx);
+        std::vector<int32_t> agg;
+        int32_t nagg = aggregate(n, sptr, sidx, agg);
+        if (nagg >= n) break;
+        double w = 4.0 / (3.0 * gershgorin(L.A, d));
+        CSR P = smoothed_prolongator(L.A, d, agg, nagg, w);
+        CSR R = csr_transpose(P);
+        CSR RA = csr_multiply(R, L.A);
+        CSR Ac = csr_multiply(RA, P);
+        L.P = std::move(P);
+        L.R = std::move(R);
+        L.agg = std::move(agg);
+        h.levels.emplace_back();
+        h.levels.back().A = std::move(Ac);
+        finish_level(h.levels.back());
+    }
+    const CSR &Ac = h.levels.back().A;
+    if (Ac.nrows > 4096) fail("AMG: coarsest level too large for a dense solve");
+    h.n_coarse = Ac.nrows;
+    dense_spd_inverse(Ac, h.coarse_inv);
+}
+
+}  // namespace ibpm

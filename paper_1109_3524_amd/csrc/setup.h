@@ -1,0 +1,83 @@
+// Host-side assembly of the operators of the immersed-boundary projection
+// method and of the smoothed-aggregation hierarchy.  Pure C++ (no HIP): the
+// results are uploaded to the device by the context code.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace ibpm {
+
+// Compressed sparse rows, int32 indices.
+struct CSR {
+    int32_t nrows = 0, ncols = 0;
+    std::vector<int32_t> ptr;   // nrows + 1
+    std::vector<int32_t> col;
+    std::vector<double> val;
+    int64_t nnz() const { return (int64_t)col.size(); }
+};
+
+struct GridMetrics {
+    int32_t nx = 0, ny = 0;
+    std::vector<double> xf, yf;      // faces
+    std::vector<double> dx, dy;      // cell widths
+    std::vector<double> xc, yc;      // cell centres
+    std::vector<double> Dx, Dy;      // nx+1 / ny+1 distances across face lines
+    int64_t n_u = 0, n_v = 0, n_q = 0, n_cell = 0;
+    int64_t uidx(int i, int j) const { return (int64_t)j * (nx - 1) + (i - 1); }
+    int64_t vidx(int i, int j) const { return n_u + (int64_t)(j - 1) * nx + i; }
+};
+
+// Everything the device needs for the level-0 operators.
+struct Model {
+    GridMetrics g;
+    int32_t nb = 0;
+    double nu = 0, dt = 0;
+    std::vector<double> ub;          // 2nb prescribed body velocity (x then y)
+    CSR E;                           // 2nb x n_q interpolation (flux form)
+    // bounding boxes of the delta supports (inclusive), for gathers
+    int32_t cb_i0 = 0, cb_i1 = -1, cb_j0 = 0, cb_j1 = -1;  // cells with force coupling
+    CSR Kcf;                         // rows: bbox cells (row-major in the box), cols: force index 0..2nb-1
+    CSR Kf;                          // 2nb force rows of K, cols in lambda numbering
+    std::vector<double> Kf_diag;     // 2nb
+    int32_t fu_i0 = 0, fu_i1 = -1, fu_j0 = 0, fu_j1 = -1;  // u faces touched by E
+    int32_t fv_i0 = 0, fv_i1 = -1, fv_j0 = 0, fv_j1 = -1;  // v faces touched by E
+    CSR Etu;                         // rows: u faces of the box, cols: force index 0..nb-1
+    CSR Etv;                         // rows: v faces of the box, cols: force index 0..nb-1
+    CSR K;                           // full pinned K (for the hierarchy setup)
+};
+
+struct Level {
+    CSR A;                           // operator of this level (level 0: copy of K)
+    std::vector<double> wdinv;       // omega / a_ii
+    double omega = 0;
+    CSR P, R;                        // prolongator to this level from the next, and P^T
+    std::vector<int32_t> agg;
+};
+
+struct Hierarchy {
+    std::vector<Level> levels;
+    std::vector<double> coarse_inv;  // column-major inverse of the coarsest operator
+    int32_t n_coarse = 0;
+};
+
+struct AmgParams {
+    double theta = 0.0;
+    int coarse_max = 256;
+    int max_levels = 12;
+};
+
+// Throws std::runtime_error with a message on invalid input.
+void build_grid(GridMetrics &g, int nx, int ny, const double *xf, const double *yf);
+void build_model(Model &m, int nx, int ny, const double *xf, const double *yf, int nb,
+                 const double *xb, const double *yb, const double *ubx, const double *uby,
+                 double nu, double dt);
+void build_hierarchy(Hierarchy &h, const CSR &K, const AmgParams &p);
+
+// helpers exposed for the host tests
+double roma_phi(double s);
+CSR csr_transpose(const CSR &A);
+CSR csr_multiply(const CSR &A, const CSR &B);
+
+}  // namespace ibpm

@@ -1,0 +1,355 @@
+"""Thin Python binding of the C ABI in include/ibpm.h (ctypes).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+of libibpm.so.  PyTorch provides device memory (float64 CUDA tensors) and
+the stream; the library queues all work on the stream that was current
+when the context was built.  If the shared library is missing this module
+raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+from . import workloads as W
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibpm.so")
+
+IBPM_OK = 0
+IBPM_EINVAL = -1
+IBPM_ENOMEM = -2
+IBPM_ENOTCONV = -3
+IBPM_EHIP = -4
+IBPM_ENAN = -5
+_CODES = {IBPM_EINVAL: "EINVAL", IBPM_ENOMEM: "ENOMEM", IBPM_ENOTCONV: "ENOTCONV",
+          IBPM_EHIP: "EHIP", IBPM_ENAN: "ENAN"}
+
+# every symbol the header declares (checked by the tests)
+EXPORTED = (
+    "ibpm_build_operators", "ibpm_destroy", "ibpm_last_error", "ibpm_sizes",
+    "ibpm_init_state", "ibpm_step", "ibpm_solve_poisson", "ibpm_solve_velocity",
+    "ibpm_apply_K", "ibpm_apply_A", "ibpm_stage_walls", "ibpm_stage_rhs1",
+    "ibpm_stage_rhs2", "ibpm_stage_project", "ibpm_get_walls", "ibpm_set_walls",
+    "ibpm_get_step", "ibpm_set_step", "ibpm_get_forces", "ibpm_hierarchy_info",
+    "ibpm_get_aggregates", "ibpm_time_kernel",
+)
+
+KERNELS = {"k0_jacobi": 0, "k0_pcg_spmv": 1, "a_pcg_spmv": 2, "k0_residual": 3,
+           "restrict0": 4, "prolong0": 5, "pcg_update_k": 6}
+
+
+class IBPMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("xf", ctypes.POINTER(ctypes.c_double)), ("yf", ctypes.POINTER(ctypes.c_double)),
+        ("nb", ctypes.c_int32),
+        ("xb", ctypes.POINTER(ctypes.c_double)), ("yb", ctypes.POINTER(ctypes.c_double)),
+        ("ubx", ctypes.POINTER(ctypes.c_double)), ("uby", ctypes.POINTER(ctypes.c_double)),
+        ("nu", ctypes.c_double), ("dt", ctypes.c_double),
+        ("uinf", ctypes.c_double), ("alpha", ctypes.c_double),
+        ("bn_order", ctypes.c_int32),
+        ("vel_rtol", ctypes.c_double), ("vel_maxit", ctypes.c_int32),
+        ("poisson_solver", ctypes.c_int32), ("poisson_rtol", ctypes.c_double),
+        ("poisson_maxit", ctypes.c_int32),
+        ("amg_theta", ctypes.c_double), ("amg_pre", ctypes.c_int32), ("amg_post", ctypes.c_int32),
+        ("amg_coarse_max", ctypes.c_int32), ("amg_max_levels", ctypes.c_int32),
+    ]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("relres", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class StepStats(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("vel_iters", ctypes.c_int32),
+                ("poisson_iters", ctypes.c_int32), ("last_vel_iters", ctypes.c_int32),
+                ("last_poisson_iters", ctypes.c_int32), ("vel_relres_max", ctypes.c_double),
+                ("poisson_relres_max", ctypes.c_double), ("fx", ctypes.c_double),
+                ("fy", ctypes.c_double), ("ms", ctypes.c_double),
+                ("vel_ms", ctypes.c_double), ("poisson_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load libibpm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1109_3524_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    D = ctypes.POINTER(ctypes.c_double)
+    i32, i64 = ctypes.c_int32, ctypes.c_int64
+    sig = {
+        "ibpm_build_operators": [ctypes.POINTER(Params), P, ctypes.POINTER(P)],
+        "ibpm_destroy": [P],
+        "ibpm_sizes": [P, ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "ibpm_init_state": [P, P, P, P],
+        "ibpm_step": [P, i32, P, P, P, ctypes.POINTER(StepStats)],
+        "ibpm_solve_poisson": [P, P, P, ctypes.POINTER(SolveStats)],
+        "ibpm_solve_velocity": [P, P, P, ctypes.POINTER(SolveStats)],
+        "ibpm_apply_K": [P, P, P],
+        "ibpm_apply_A": [P, P, P],
+        "ibpm_stage_walls": [P, P],
+        "ibpm_stage_rhs1": [P, P, P, P, P],
+        "ibpm_stage_rhs2": [P, P, P],
+        "ibpm_stage_project": [P, P, P, P],
+        "ibpm_get_walls": [P, i32, D],
+        "ibpm_set_walls": [P, i32, D],
+        "ibpm_get_step": [P, ctypes.POINTER(i64)],
+        "ibpm_set_step": [P, i64],
+        "ibpm_get_forces": [P, D, D],
+        "ibpm_hierarchy_info": [P, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "ibpm_get_aggregates": [P, i32, ctypes.POINTER(i32)],
+        "ibpm_time_kernel": [P, i32, i32, D, D],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.ibpm_last_error.argtypes = [P]
+    L.ibpm_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def params_from_workload(wl: W.Workload, **over) -> dict:
+    p = dict(nx=wl.nx, ny=wl.ny, xf=wl.xf, yf=wl.yf, nb=wl.nb, xb=wl.xb, yb=wl.yb,
+             ubx=wl.ubx, uby=wl.uby, nu=wl.nu, dt=wl.dt, uinf=wl.uinf, alpha=wl.alpha,
+             bn_order=1, vel_rtol=wl.vel_rtol, vel_maxit=wl.vel_maxit,
+             poisson_solver=wl.poisson_solver, poisson_rtol=wl.poisson_rtol,
+             poisson_maxit=wl.poisson_maxit, amg_theta=wl.amg_theta, amg_pre=wl.amg_pre,
+             amg_post=wl.amg_post, amg_coarse_max=wl.amg_coarse_max,
+             amg_max_levels=wl.amg_max_levels)
+    p.update(over)
+    return p
+
+
+class Context:
+    """One library context (operators, hierarchy, work memory) on one stream."""
+
+    def __init__(self, wl: W.Workload, **overrides):
+        import torch
+        self._torch = torch
+        L = load()
+        p = params_from_workload(wl, **overrides)
+        self._arrays = {}
+        st = Params()
+        for k, _ in Params._fields_:
+            v = p[k]
+            if k in ("xf", "yf", "xb", "yb", "ubx", "uby"):
+                a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+                if a.size == 0:
+                    a = np.zeros(1)
+                self._arrays[k] = a
+                setattr(st, k, _dptr(a))
+            else:
+                setattr(st, k, v)
+        self.params = p
+        self.wl = wl
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = L.ibpm_build_operators(ctypes.byref(st), ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(h))
+        self._h = h
+        if rc != IBPM_OK:
+            msg = L.ibpm_last_error(h).decode() if h.value else ""
+            if h.value:
+                L.ibpm_destroy(h)
+            self._h = ctypes.c_void_p()
+            raise IBPMError(rc, msg)
+        nq, nl = ctypes.c_int64(), ctypes.c_int64()
+        self._check(L.ibpm_sizes(h, ctypes.byref(nq), ctypes.byref(nl)))
+        self.n_q, self.n_lambda = nq.value, nl.value
+        self.nx, self.ny, self.nb = wl.nx, wl.ny, wl.nb
+
+    # -- helpers -------------------------------------------------------------
+    def _check(self, rc, allow=()):
+        if rc != IBPM_OK and rc not in allow:
+            raise IBPMError(rc, load().ibpm_last_error(self._h).decode())
+        return rc
+
+    def _vec(self, t, n, name):
+        torch = self._torch
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float64:
+            raise TypeError(f"{name} must be a float64 CUDA tensor")
+        if not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name} must be contiguous with {n} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def zeros_q(self):
+        return self._torch.zeros(self.n_q, dtype=self._torch.float64, device=self.device)
+
+    def zeros_lambda(self):
+        return self._torch.zeros(self.n_lambda, dtype=self._torch.float64, device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().ibpm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- calls ---------------------------------------------------------------
+    def init_state(self, q=None, conv=None, lam=None):
+        q = self.zeros_q() if q is None else q
+        conv = self.zeros_q() if conv is None else conv
+        lam = self.zeros_lambda() if lam is None else lam
+        self._check(load().ibpm_init_state(self._h, self._vec(q, self.n_q, "q"),
+                                           self._vec(conv, self.n_q, "conv"),
+                                           self._vec(lam, self.n_lambda, "lambda")))
+        return q, conv, lam
+
+    def step(self, q, conv, lam, nsteps=1, stats=True, allow_fail=False):
+        s = StepStats() if stats else None
+        rc = load().ibpm_step(self._h, int(nsteps), self._vec(q, self.n_q, "q"),
+                              self._vec(conv, self.n_q, "conv"),
+                              self._vec(lam, self.n_lambda, "lambda"),
+                              ctypes.byref(s) if s is not None else None)
+        self._check(rc, allow=(IBPM_ENOTCONV,) if allow_fail else ())
+        return s.as_dict() if s is not None else None
+
+    def solve_poisson(self, rhs, lam, allow_fail=False):
+        s = SolveStats()
+        rc = load().ibpm_solve_poisson(self._h, self._vec(rhs, self.n_lambda, "rhs"),
+                                       self._vec(lam, self.n_lambda, "lambda"), ctypes.byref(s))
+        self._check(rc, allow=(IBPM_ENOTCONV, IBPM_ENAN) if allow_fail else ())
+        return s.as_dict()
+
+    def solve_velocity(self, rhs, q, allow_fail=False):
+        s = SolveStats()
+        rc = load().ibpm_solve_velocity(self._h, self._vec(rhs, self.n_q, "rhs"),
+                                        self._vec(q, self.n_q, "q"), ctypes.byref(s))
+        self._check(rc, allow=(IBPM_ENOTCONV, IBPM_ENAN) if allow_fail else ())
+        return s.as_dict()
+
+    def apply_K(self, x, y=None):
+        y = self.zeros_lambda() if y is None else y
+        self._check(load().ibpm_apply_K(self._h, self._vec(x, self.n_lambda, "x"),
+                                        self._vec(y, self.n_lambda, "y")))
+        return y
+
+    def apply_A(self, x, y=None):
+        y = self.zeros_q() if y is None else y
+        self._check(load().ibpm_apply_A(self._h, self._vec(x, self.n_q, "x"),
+                                        self._vec(y, self.n_q, "y")))
+        return y
+
+    def stage_walls(self, q):
+        self._check(load().ibpm_stage_walls(self._h, self._vec(q, self.n_q, "q")))
+
+    def stage_rhs1(self, q, conv_prev, r1=None, conv_now=None):
+        r1 = self.zeros_q() if r1 is None else r1
+        conv_now = self.zeros_q() if conv_now is None else conv_now
+        self._check(load().ibpm_stage_rhs1(self._h, self._vec(q, self.n_q, "q"),
+                                           self._vec(conv_prev, self.n_q, "conv_prev"),
+                                           self._vec(r1, self.n_q, "r1"),
+                                           self._vec(conv_now, self.n_q, "conv_now")))
+        return r1, conv_now
+
+    def stage_rhs2(self, qstar, rhs=None):
+        rhs = self.zeros_lambda() if rhs is None else rhs
+        self._check(load().ibpm_stage_rhs2(self._h, self._vec(qstar, self.n_q, "qstar"),
+                                           self._vec(rhs, self.n_lambda, "rhs")))
+        return rhs
+
+    def stage_project(self, qstar, lam, qout=None):
+        qout = self.zeros_q() if qout is None else qout
+        self._check(load().ibpm_stage_project(self._h, self._vec(qstar, self.n_q, "qstar"),
+                                              self._vec(lam, self.n_lambda, "lambda"),
+                                              self._vec(qout, self.n_q, "qout")))
+        return qout
+
+    def walls_size(self):
+        return 4 * self.nx + 4 * self.ny + 4
+
+    def get_walls(self, which=0):
+        out = np.zeros(self.walls_size())
+        self._check(load().ibpm_get_walls(self._h, int(which), _dptr(out)))
+        return out
+
+    def set_walls(self, which, values):
+        a = np.ascontiguousarray(np.asarray(values, dtype=np.float64))
+        if a.size != self.walls_size():
+            raise ValueError("wrong wall array size")
+        self._check(load().ibpm_set_walls(self._h, int(which), _dptr(a)))
+
+    def get_step(self):
+        s = ctypes.c_int64()
+        self._check(load().ibpm_get_step(self._h, ctypes.byref(s)))
+        return s.value
+
+    def set_step(self, step):
+        self._check(load().ibpm_set_step(self._h, int(step)))
+
+    def forces(self):
+        fx, fy = ctypes.c_double(), ctypes.c_double()
+        self._check(load().ibpm_get_forces(self._h, ctypes.byref(fx), ctypes.byref(fy)))
+        return fx.value, fy.value
+
+    def hierarchy(self):
+        lv = ctypes.c_int32()
+        sizes = (ctypes.c_int64 * 64)()
+        nnz = (ctypes.c_int64 * 64)()
+        self._check(load().ibpm_hierarchy_info(self._h, ctypes.byref(lv), sizes, nnz))
+        return [int(sizes[i]) for i in range(lv.value)], [int(nnz[i]) for i in range(lv.value)]
+
+    def time_kernel(self, name, reps=200):
+        """Mean duration (ms) of one launch of a solver kernel and its
+        algorithmic bytes, timed with HIP events on the context's stream."""
+        ms, by = ctypes.c_double(), ctypes.c_double()
+        self._check(load().ibpm_time_kernel(self._h, KERNELS[name], int(reps),
+                                            ctypes.byref(ms), ctypes.byref(by)))
+        return ms.value, by.value
+
+    def aggregates(self, level):
+        sizes, _ = self.hierarchy()
+        out = np.zeros(sizes[level], dtype=np.int32)
+        self._check(load().ibpm_get_aggregates(self._h, int(level),
+                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))))
+        return out
+
+
+def unpack_walls(w: np.ndarray, nx: int, ny: int) -> dict:
+    """Split a packed wall array into its eight parts (layout of ibpm.h)."""
+    sizes = [("uL", ny), ("uR", ny), ("vB", nx), ("vT", nx), ("uBt", nx + 1), ("uTt", nx + 1),
+             ("vLt", ny + 1), ("vRt", ny + 1)]
+    out, o = {}, 0
+    for k, n in sizes:
+        out[k] = w[o:o + n].copy()
+        o += n
+    return out
+
+
+def pack_walls(parts: dict) -> np.ndarray:
+    return np.concatenate([np.asarray(parts[k], dtype=np.float64)
+                           for k in ("uL", "uR", "vB", "vT", "uBt", "uTt", "vLt", "vRt")])

@@ -1,0 +1,316 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle on
+the same seeded inputs.
+
+Bar (FP64): operators and stages agree to round-off (1e-12 relative to the
+largest entry); solves and time steps run at a 1e-12 relative residual on
+both sides agree to 1e-10 relative L2 in velocity and in lambda; the
+smoothed-aggregation aggregates, being integer work, agree exactly."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_1109_3524_amd import ibpm
+from paper_1109_3524_amd import workloads as W
+from oracle import flow, solvers
+from oracle.problem import Problem
+
+pytestmark = pytest.mark.gpu
+
+TIGHT = 1e-12
+
+
+def _t(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _n(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _maxrel(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+def _walls_pack(w):
+    return ibpm.pack_walls({k: getattr(w, k) for k in ("uL", "uR", "vB", "vT", "uBt", "uTt", "vLt", "vRt")})
+
+
+WORKLOADS = {
+    "tiny_stretched": lambda: W.tiny(16, 14, 8, 0.2, stretched=True, dt=0.02, nu=0.05),
+    "cyl96": lambda: W.cylinder_small(96, 60),
+    "cyl512": lambda: W.cylinder_512(),
+}
+
+
+@pytest.mark.parametrize("name", list(WORKLOADS))
+def test_operators_match_oracle(name):
+    wl = WORKLOADS[name]()
+    print(f"[apply] {name}", flush=True)
+    P = Problem(wl, poisson_solver=0)
+    ctx = ibpm.Context(wl, poisson_solver=0)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(ctx.n_lambda)
+    y = _n(ctx.apply_K(_t(x)))
+    assert _maxrel(y, P.ops.K @ x) < 1e-13
+    xq = rng.standard_normal(ctx.n_q)
+    yq = _n(ctx.apply_A(_t(xq)))
+    assert _maxrel(yq, P.ops.A @ xq) < 1e-13
+    ctx.close()
+
+
+def _oracle_state(P, steps):
+    st = P.initial_state()
+    for _ in range(steps):
+        st, _ = P.step(st)
+    return st
+
+
+@pytest.mark.parametrize("name", ["tiny_stretched", "cyl96"])
+def test_stages_match_oracle(name):
+    wl = WORKLOADS[name]()
+    print(f"[stages] {name}", flush=True)
+    P = Problem(wl, poisson_solver=0, vel_rtol=TIGHT, poisson_rtol=TIGHT)
+    g, o = P.grid, P.ops
+    st = _oracle_state(P, 2)
+    ctx = ibpm.Context(wl, poisson_solver=0)
+    ctx.set_walls(0, _walls_pack(st.walls))
+    ctx.set_step(st.step)
+    q = _t(st.q)
+    # walls n -> n+1
+    ctx.stage_walls(q)
+    w1_ref = flow.update_walls(g, st.walls, st.q, wl.uinf, wl.alpha, o.dt)
+    w1 = ctx.get_walls(1)
+    assert _maxrel(w1, _walls_pack(w1_ref)) < 1e-13
+    # momentum right-hand side and convection
+    r1, conv_now = ctx.stage_rhs1(q, _t(st.conv_prev))
+    conv_ref = flow.convection(g, st.q, st.walls)
+    r1_ref = flow.momentum_rhs(o, st.q, conv_ref, st.conv_prev, st.walls, w1_ref)
+    assert _maxrel(_n(conv_now), conv_ref) < 1e-12
+    assert _maxrel(_n(r1), r1_ref) < 1e-12
+    # Poisson right-hand side from the oracle's q*
+    dinv = 1.0 / o.A.diagonal()
+    qs, _, _ = solvers.pcg(o.apply_A, r1_ref, st.q, lambda r: dinv * r, TIGHT, 5000)
+    rhs = _n(ctx.stage_rhs2(_t(qs)))
+    rhs_ref = flow.poisson_rhs(o, qs, w1_ref, P.ub)
+    assert _maxrel(rhs, rhs_ref) < 1e-12
+    # projection and forces from the oracle's lambda
+    lam, _, _ = P.solve_poisson(rhs_ref, st.lam, rtol=TIGHT, maxit=20000)
+    qn = _n(ctx.stage_project(_t(qs), _t(lam)))
+    assert _maxrel(qn, flow.project(o, qs, lam)) < 1e-13
+    fx, fy = ctx.forces()
+    fx_ref, fy_ref = flow.body_force(o, lam)
+    assert abs(fx - fx_ref) <= 1e-12 * abs(fx_ref) + 1e-14
+    assert abs(fy - fy_ref) <= 1e-12 * abs(fx_ref) + 1e-14
+    # first step uses the current convection twice (AB2 start-up)
+    ctx.set_step(0)
+    r1b, _ = ctx.stage_rhs1(q, _t(np.full(g.n_q, 1e30)))
+    r1b_ref = flow.momentum_rhs(o, st.q, conv_ref, conv_ref, st.walls, w1_ref)
+    assert _maxrel(_n(r1b), r1b_ref) < 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", ["cyl96", "cyl512"])
+def test_aggregates_match_oracle_exactly(name):
+    wl = WORKLOADS[name]()
+    print(f"[aggregates] {name}", flush=True)
+    P = Problem(wl, poisson_solver=1)
+    ctx = ibpm.Context(wl, poisson_solver=1)
+    sizes, nnz = ctx.hierarchy()
+    assert sizes == P.H.sizes()
+    for l in range(len(sizes) - 1):
+        np.testing.assert_array_equal(ctx.aggregates(l), P.H.levels[l].agg)
+    ctx.close()
+
+
+@pytest.mark.parametrize("solver", [0, 1])
+def test_poisson_solve_matches_oracle(solver):
+    wl = W.cylinder_small(96, 60)
+    print(f"[poisson] solver {solver}", flush=True)
+    P = Problem(wl, poisson_solver=solver, vel_rtol=TIGHT, poisson_rtol=TIGHT)
+    st = _oracle_state(P, 1)
+    o = P.ops
+    w1 = flow.update_walls(P.grid, st.walls, st.q, wl.uinf, wl.alpha, o.dt)
+    conv = flow.convection(P.grid, st.q, st.walls)
+    r1 = flow.momentum_rhs(o, st.q, conv, st.conv_prev, st.walls, w1)
+    dinv = 1.0 / o.A.diagonal()
+    qs, _, _ = solvers.pcg(o.apply_A, r1, st.q, lambda r: dinv * r, TIGHT, 5000)
+    rhs = flow.poisson_rhs(o, qs, w1, P.ub)
+    x0 = np.zeros_like(rhs)
+    ref, it_ref, res_ref = P.solve_poisson(rhs, x0, rtol=TIGHT, maxit=50000)
+    ctx = ibpm.Context(wl, poisson_solver=solver, poisson_rtol=TIGHT, poisson_maxit=50000)
+    lam = _t(x0)
+    s = ctx.solve_poisson(_t(rhs), lam)
+    assert s["relres"] <= TIGHT * 1.01
+    assert _rel(_n(lam), ref) < 1e-10
+    # production tolerance: same algorithm, so the iteration counts agree
+    ref8, it8, _ = P.solve_poisson(rhs, x0, rtol=1e-8)
+    ctx8 = ibpm.Context(wl, poisson_solver=solver, poisson_rtol=1e-8)
+    lam8 = _t(x0)
+    s8 = ctx8.solve_poisson(_t(rhs), lam8)
+    print(f"  iters gpu {s8['iters']} oracle {it8}; diff at 1e-8 {_rel(_n(lam8), ref8):.2e}")
+    assert abs(s8["iters"] - it8) <= 2
+    assert s8["relres"] <= 1e-8
+    ctx.close()
+    ctx8.close()
+
+
+def test_velocity_solve_matches_oracle():
+    wl = W.cylinder_512()
+    P = Problem(wl, poisson_solver=0)
+    o = P.ops
+    rng = np.random.default_rng(3)
+    b = o.A @ (rng.standard_normal(o.n_q))
+    x0 = np.zeros_like(b)
+    ref, it_ref, _ = solvers.jacobi_pcg(o.A, b, x0, TIGHT, 5000)
+    ctx = ibpm.Context(wl, poisson_solver=0, vel_rtol=TIGHT)
+    x = _t(x0)
+    s = ctx.solve_velocity(_t(b), x)
+    assert _rel(_n(x), ref) < 1e-10
+    assert abs(s["iters"] - it_ref) <= 1
+    ctx.close()
+
+
+def _run_both(wl, steps, solver, rtol):
+    ctx = ibpm.Context(wl, poisson_solver=solver, vel_rtol=rtol, poisson_rtol=rtol,
+                       poisson_maxit=50000)
+    q, conv, lam = ctx.init_state()
+    gstats = [ctx.step(q, conv, lam, 1) for _ in range(steps)]
+    P = Problem(wl, poisson_solver=solver, vel_rtol=rtol, poisson_rtol=rtol)
+    P.wl = wl.replace(poisson_maxit=50000)
+    st, infos = P.run(steps)
+    R = P.grid.R_diag()
+    eu = _rel(_n(q) / R, st.q / R)
+    el = _rel(_n(lam), st.lam)
+    ctx.close()
+    return eu, el, gstats, infos
+
+
+def test_trajectory_96_twenty_steps_jacobi():
+    wl = W.cylinder_small(96, 60)
+    eu, el, g, o = _run_both(wl, 20, 0, TIGHT)
+    print(f"  96^2 x 20 steps: velocity {eu:.2e} lambda {el:.2e}; Fx {g[-1]['fx']:.12f} vs {o[-1].fx:.12f}")
+    assert eu < 1e-10 and el < 1e-10
+    assert abs(g[-1]["fx"] - o[-1].fx) < 1e-9 * abs(o[-1].fx)
+
+
+def test_trajectory_96_amg_production_tolerance():
+    """At the production tolerance the two runs follow the same iteration
+    counts; differences are reported, the bar is the solver tolerance."""
+    wl = W.cylinder_small(96, 60)
+    eu, el, g, o = _run_both(wl, 10, 1, 1e-8)
+    print(f"  96^2 x 10 steps at 1e-8: velocity {eu:.2e} lambda {el:.2e}")
+    assert eu < 1e-7 and el < 1e-6
+    its_g = [s["last_poisson_iters"] for s in g]
+    its_o = [i.poisson_iters for i in o]
+    assert max(abs(a - b) for a, b in zip(its_g, its_o)) <= 2
+
+
+@pytest.mark.timeout(900)
+def test_trajectory_512_amg_two_steps():
+    wl = W.cylinder_512()
+    eu, el, g, o = _run_both(wl, 2, 1, TIGHT)
+    print(f"  512^2 x 2 steps AMG: velocity {eu:.2e} lambda {el:.2e}; iters {[s['last_poisson_iters'] for s in g]}")
+    assert eu < 1e-10 and el < 1e-10
+
+
+def test_uniform_flow_without_body_stays_uniform():
+    wl = W.tiny(16, 14, 0, stretched=True).replace(alpha=0.2)
+    ctx = ibpm.Context(wl, poisson_solver=0, vel_rtol=TIGHT, poisson_rtol=TIGHT)
+    q, conv, lam = ctx.init_state()
+    q0 = _n(q).copy()
+    ctx.step(q, conv, lam, 3)
+    assert np.abs(_n(q) - q0).max() < 1e-13
+    assert np.abs(_n(lam)).max() < 1e-12
+    ctx.close()
+
+
+def test_solver_edge_cases():
+    wl = W.cylinder_small(48, 30)
+    ctx = ibpm.Context(wl, poisson_solver=1, poisson_rtol=1e-8, poisson_maxit=3)
+    n = ctx.n_lambda
+    # zero right-hand side: zero solution, no iterations
+    lam = _t(np.ones(n))
+    s = ctx.solve_poisson(_t(np.zeros(n)), lam)
+    assert s["iters"] == 0 and np.all(_n(lam) == 0.0)
+    # iteration limit
+    rhs = np.random.default_rng(1).standard_normal(n)
+    rhs[0] = 0.0
+    lam = _t(np.zeros(n))
+    with pytest.raises(ibpm.IBPMError) as e:
+        ctx.solve_poisson(_t(rhs), lam)
+    assert e.value.code == ibpm.IBPM_ENOTCONV
+    s = ctx.solve_poisson(_t(rhs), _t(np.zeros(n)), allow_fail=True)
+    assert s["iters"] == 3 and s["status"] == ibpm.IBPM_ENOTCONV and s["relres"] > 1e-8
+    # NaN in the right-hand side
+    bad = rhs.copy()
+    bad[5] = np.nan
+    with pytest.raises(ibpm.IBPMError) as e:
+        ctx.solve_poisson(_t(bad), _t(np.zeros(n)))
+    assert e.value.code == ibpm.IBPM_ENAN
+    # already converged initial guess: zero iterations
+    ctx2 = ibpm.Context(wl, poisson_solver=1, poisson_rtol=1e-6)
+    x = _t(np.zeros(n))
+    ctx2.solve_poisson(_t(rhs), x)
+    s = ctx2.solve_poisson(_t(rhs), x)
+    assert s["iters"] == 0
+    # wrong tensor types are refused by the binding
+    with pytest.raises(TypeError):
+        ctx2.solve_poisson(torch.zeros(n, dtype=torch.float32, device="cuda"), x)
+    ctx.close()
+    ctx2.close()
+
+
+def test_runs_are_bitwise_deterministic():
+    wl = W.cylinder_small(96, 60)
+    outs = []
+    for _ in range(2):
+        ctx = ibpm.Context(wl, poisson_solver=1)
+        q, conv, lam = ctx.init_state()
+        ctx.step(q, conv, lam, 3)
+        outs.append((_n(q).copy(), _n(lam).copy()))
+        ctx.close()
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.timeout(600)
+def test_full_size_2048_operators_and_stages():
+    """Largest workload (2048^2, 4.2M cells, 628 points) in the launch
+    configuration of the time step: the Poisson operator, the velocity
+    operator and the right-hand-side stages against the oracle on every
+    row."""
+    wl = W.cylinder_2048()
+    print("[2048] oracle assembly", flush=True)
+    P = Problem(wl, poisson_solver=0)
+    g, o = P.grid, P.ops
+    ctx = ibpm.Context(wl, poisson_solver=0)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(ctx.n_lambda)
+    assert _maxrel(_n(ctx.apply_K(_t(x))), o.K @ x) < 1e-13
+    xq = rng.standard_normal(ctx.n_q)
+    assert _maxrel(_n(ctx.apply_A(_t(xq))), o.A @ xq) < 1e-13
+    # a perturbed freestream state
+    st = P.initial_state()
+    qn = st.q * (1.0 + 0.05 * rng.standard_normal(g.n_q))
+    conv_prev = flow.convection(g, st.q, st.walls)
+    ctx.set_step(3)
+    q = _t(qn)
+    ctx.stage_walls(q)
+    w1 = flow.update_walls(g, st.walls, qn, wl.uinf, wl.alpha, o.dt)
+    r1, conv_now = ctx.stage_rhs1(q, _t(conv_prev))
+    conv_ref = flow.convection(g, qn, st.walls)
+    assert _maxrel(_n(conv_now), conv_ref) < 1e-12
+    assert _maxrel(_n(r1), flow.momentum_rhs(o, qn, conv_ref, conv_prev, st.walls, w1)) < 1e-12
+    rhs = _n(ctx.stage_rhs2(q))
+    assert _maxrel(rhs, flow.poisson_rhs(o, qn, w1, P.ub)) < 1e-12
+    lam = rng.standard_normal(ctx.n_lambda)
+    assert _maxrel(_n(ctx.stage_project(q, _t(lam))), flow.project(o, qn, lam)) < 1e-13
+    ctx.close()
