@@ -10,12 +10,14 @@ constexpr int kBlock = 256;        // threads per block (4 wave64)
 constexpr int kMaxParts = 2048;    // upper bound on blocks of a reducing kernel
 
 // Tensor-product staggered grid; metric arrays live on the device.
-struct GridView {
+template <class T>
+struct GridT {
     int nx, ny;
     int n_u, n_v, n_q, n_cell;
-    const double *dx, *dy, *Dx, *Dy;      // nx, ny, nx+1, ny+1
-    const double *idx, *idy, *iDx, *iDy;  // reciprocals
+    const T *dx, *dy, *Dx, *Dy;      // nx, ny, nx+1, ny+1
+    const T *idx, *idy, *iDx, *iDy;  // reciprocals
 };
+using GridView = GridT<double>;
 
 // Packed wall values: uL[ny] uR[ny] vB[nx] vT[nx] uBt[nx+1] uTt[nx+1] vLt[ny+1] vRt[ny+1]
 struct WallOffsets {
@@ -35,25 +37,29 @@ struct WallOffsets {
     }
 };
 
-struct CSRView {
+template <class T>
+struct CSRT {
     int nrows, ncols;
     const int32_t *ptr, *col;
-    const double *val;
+    const T *val;
 };
+using CSRView = CSRT<double>;
 
 // Level-0 Poisson operator K = Q^T B^1 Q (pinned), matrix-free pressure
-// stencil plus stored coupling rows.
-struct K0View {
-    GridView g;
-    double dt;
+// stencil plus stored coupling rows, in precision T.
+template <class T>
+struct K0T {
+    GridT<T> g;
+    T dt;
     int nb, n;                       // n = n_cell + 2 nb
     int cb_i0, cb_i1, cb_j0, cb_j1;  // box of cells coupled to forces
-    CSRView cf;                      // box cells -> (force 0..2nb-1, value)
-    CSRView kf;                      // force rows, columns in lambda numbering
-    const double *kf_diag;
+    CSRT<T> cf;                      // box cells -> (force 0..2nb-1, value)
+    CSRT<T> kf;                      // force rows, columns in lambda numbering
+    const T *kf_diag;
 };
+using K0View = K0T<double>;
 
-// Velocity operator A = Mf/dt - (nu/2) L on interior faces (matrix-free).
+// Velocity operator A = Mf/dt - (nu/2) L on interior faces (matrix-free, FP64).
 struct AView {
     GridView g;
     double dt, idt, nu;
@@ -71,7 +77,7 @@ struct SolveStatus {
 };
 
 // --- launchers (all asynchronous on `s`) ---------------------------------
-// step stages
+// step stages (FP64)
 void launch_walls_update(hipStream_t s, GridView g, const double *w0, double *w1,
                          const double *q, double uconv, double dt, double ly);
 void launch_momentum_rhs(hipStream_t s, GridView g, const double *q, const double *conv_prev,
@@ -91,46 +97,61 @@ void launch_fill_walls(hipStream_t s, GridView g, double *w, double U, double V)
 void launch_apply_K0(hipStream_t s, const K0View &K, const double *x, double *y);
 void launch_apply_A(hipStream_t s, const AView &A, const double *x, double *y);
 
-// Krylov pieces; `op` selects K0 (0) or A (1) through the overloads
-void launch_pcg_init(hipStream_t s, const K0View &K, const double *b, const double *x, double *r,
-                     SolveStatus *st, double *parts, bool jacobi, double rtol2, int maxit);
-void launch_pcg_init(hipStream_t s, const AView &A, const double *b, const double *x, double *r,
-                     SolveStatus *st, double *parts, bool jacobi, double rtol2, int maxit);
-void launch_pcg_spmv(hipStream_t s, const K0View &K, const double *src, const double *pold,
-                     double *pnew, double *q, SolveStatus *st, double *parts, bool jacobi);
-void launch_pcg_spmv(hipStream_t s, const AView &A, const double *src, const double *pold,
-                     double *pnew, double *q, SolveStatus *st, double *parts, bool jacobi);
-void launch_pcg_update(hipStream_t s, const K0View &K, double *x, double *r, const double *p,
-                       const double *q, SolveStatus *st, double *parts, bool jacobi);
-void launch_pcg_update(hipStream_t s, const AView &A, double *x, double *r, const double *p,
-                       const double *q, SolveStatus *st, double *parts, bool jacobi);
-void launch_true_residual(hipStream_t s, const K0View &K, const double *b, const double *x,
-                          SolveStatus *st, double *parts);
-void launch_true_residual(hipStream_t s, const AView &A, const double *b, const double *x,
-                          SolveStatus *st, double *parts);
-void launch_dot_rz(hipStream_t s, int n, const double *r, const double *z, SolveStatus *st,
-                   double *parts);
-void launch_zero_if_zero_rhs(hipStream_t s, double *x, int n, const SolveStatus *st);
+// Krylov pieces.  Op is K0T<T> (vectors of T) or AView (vectors of double);
+// dot products always accumulate in FP64.
+template <class Op, class T>
+void launch_pcg_init(hipStream_t s, const Op &op, const T *b, const T *x, T *r, SolveStatus *st,
+                     double *parts, bool jacobi, double rtol2, int maxit);
+template <class T>
+void launch_pcg_init_zero(hipStream_t s, int n, const T *b, T *x, T *r, SolveStatus *st,
+                          double *parts, double rtol2, int maxit);
+template <class Op, class T>
+void launch_pcg_spmv(hipStream_t s, const Op &op, const T *src, const T *pold, T *pnew, T *q,
+                     SolveStatus *st, double *parts, bool jacobi);
+template <class Op, class T>
+void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, const T *p, const T *q,
+                       SolveStatus *st, double *parts, bool jacobi);
+template <class Op, class T>
+void launch_true_residual(hipStream_t s, const Op &op, const T *b, const T *x, SolveStatus *st,
+                          double *parts);
+template <class T>
+void launch_dot_rz(hipStream_t s, int n, const T *r, const T *z, SolveStatus *st, double *parts);
+template <class T>
+void launch_zero_if_zero_rhs(hipStream_t s, T *x, int n, const SolveStatus *st);
 
 // V-cycle pieces, predicated on st->done
-void launch_k0_jacobi_first(hipStream_t s, const K0View &K, double omega, const double *b,
-                            double *x, const SolveStatus *st);
-void launch_k0_jacobi(hipStream_t s, const K0View &K, double omega, const double *b,
-                      const double *xin, double *xout, const SolveStatus *st);
-void launch_k0_jacobi_rz(hipStream_t s, const K0View &K, double omega, const double *b,
-                         const double *xin, double *xout, SolveStatus *st, double *parts);
-void launch_k0_residual(hipStream_t s, const K0View &K, const double *b, const double *x, double *r,
+template <class T>
+void launch_k0_jacobi_first(hipStream_t s, const K0T<T> &K, double omega, const T *b, T *x,
+                            const SolveStatus *st);
+template <class T>
+void launch_k0_jacobi(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
+                      T *xout, const SolveStatus *st);
+template <class T>
+void launch_k0_jacobi_rz(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
+                         T *xout, SolveStatus *st, double *parts);
+template <class T>
+void launch_k0_residual(hipStream_t s, const K0T<T> &K, const T *b, const T *x, T *r,
                         const SolveStatus *st);
-void launch_csr_jacobi_first(hipStream_t s, CSRView A, const double *wdinv, const double *b,
-                             double *x, const SolveStatus *st);
-void launch_csr_jacobi(hipStream_t s, CSRView A, const double *wdinv, const double *b,
-                       const double *xin, double *xout, const SolveStatus *st);
-void launch_csr_residual(hipStream_t s, CSRView A, const double *b, const double *x, double *r,
+template <class T>
+void launch_csr_jacobi_first(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b, T *x,
+                             const SolveStatus *st);
+template <class T>
+void launch_csr_jacobi(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b, const T *xin,
+                       T *xout, const SolveStatus *st);
+template <class T>
+void launch_csr_residual(hipStream_t s, CSRT<T> A, const T *b, const T *x, T *r,
                          const SolveStatus *st);
-void launch_csr_spmv(hipStream_t s, CSRView A, const double *x, double *y, const SolveStatus *st);
-void launch_csr_spmv_add(hipStream_t s, CSRView A, const double *x, double *y,
-                         const SolveStatus *st);
-void launch_dense_solve(hipStream_t s, int n, const double *inv_colmajor, const double *b, double *x,
+template <class T>
+void launch_csr_spmv(hipStream_t s, CSRT<T> A, const T *x, T *y, const SolveStatus *st);
+template <class T>
+void launch_csr_spmv_add(hipStream_t s, CSRT<T> A, const T *x, T *y, const SolveStatus *st);
+template <class T>
+void launch_dense_solve(hipStream_t s, int n, const double *inv_colmajor, const T *b, T *x,
                         const SolveStatus *st);
+
+// mixed precision: FP64 outer residual r = b - K x (also cast to FP32) and x += d
+void launch_outer_residual(hipStream_t s, const K0View &K, const double *b, const double *x,
+                           float *r32, SolveStatus *st, double *parts, int first);
+void launch_add_correction(hipStream_t s, int n, double *x, const float *d);
 
 }  // namespace ibpm

@@ -9,6 +9,10 @@
 // per-block partials, and the last block to finish (an integer atomic
 // counter decides which) sums the partials in a fixed order.  No floating-
 // point atomics are used anywhere.
+//
+// The solver kernels are templates on the vector precision T (double, or
+// float for the mixed-precision inner solve); dot products always
+// accumulate in double.
 #include "kernels.h"
 
 namespace ibpm {
@@ -94,25 +98,27 @@ __device__ bool grid_sum(double (&v)[N], double *parts, SolveStatus *st, double 
     return true;
 }
 
+__device__ __forceinline__ bool bad(double v) { return !(v == v) || v > 1e300; }
+
 // ---------------------------------------------------------------------------
 // operator rows
 
-// Row `row` of K = Q^T B^1 Q (pinned).  x(c) gives the operand.  Also
-// returns the diagonal.  Pressure rows: the 5-point stencil with
-// coefficients B^1 = dt * dy_j / Dx_i (u faces) and dt * dx_i / Dy_j (v
-// faces) on interior faces, plus stored force coupling inside the box.
-template <class X>
-__device__ __forceinline__ double k0_row(const K0View &K, int row, X x, double &diag) {
-    const GridView &g = K.g;
+// Row `row` of K = Q^T B^1 Q (pinned) in precision T.  x(c) gives the
+// operand.  Also returns the diagonal.  Pressure rows: the 5-point stencil
+// with coefficients B^1 = dt * dy_j / Dx_i (u faces) and dt * dx_i / Dy_j
+// (v faces) on interior faces, plus the stored force coupling inside the box.
+template <class T, class X>
+__device__ __forceinline__ T k0_row(const K0T<T> &K, int row, X x, T &diag) {
+    const GridT<T> &g = K.g;
     if (row < g.n_cell) {
         int j = row / g.nx;
         int i = row - j * g.nx;
-        double bw = i > 0 ? K.dt * g.dy[j] * g.iDx[i] : 0.0;
-        double be = i < g.nx - 1 ? K.dt * g.dy[j] * g.iDx[i + 1] : 0.0;
-        double bs = j > 0 ? K.dt * g.dx[i] * g.iDy[j] : 0.0;
-        double bn = j < g.ny - 1 ? K.dt * g.dx[i] * g.iDy[j + 1] : 0.0;
+        T bw = i > 0 ? K.dt * g.dy[j] * g.iDx[i] : T(0);
+        T be = i < g.nx - 1 ? K.dt * g.dy[j] * g.iDx[i + 1] : T(0);
+        T bs = j > 0 ? K.dt * g.dx[i] * g.iDy[j] : T(0);
+        T bn = j < g.ny - 1 ? K.dt * g.dx[i] * g.iDy[j + 1] : T(0);
         diag = ((bw + be) + bs) + bn;
-        double y = diag * x(row);
+        T y = diag * x(row);
         if (row == 0) return y;
         if (j > 0 && row - g.nx != 0) y -= bs * x(row - g.nx);
         if (i > 0 && row - 1 != 0) y -= bw * x(row - 1);
@@ -127,20 +133,21 @@ __device__ __forceinline__ double k0_row(const K0View &K, int row, X x, double &
     }
     int k = row - g.n_cell;
     diag = K.kf_diag[k];
-    double y = 0.0;
+    T y = T(0);
     for (int p = K.kf.ptr[k]; p < K.kf.ptr[k + 1]; ++p) y += K.kf.val[p] * x(K.kf.col[p]);
     return y;
 }
 
-__device__ __forceinline__ double k0_diag(const K0View &K, int row) {
-    const GridView &g = K.g;
+template <class T>
+__device__ __forceinline__ T k0_diag(const K0T<T> &K, int row) {
+    const GridT<T> &g = K.g;
     if (row < g.n_cell) {
         int j = row / g.nx;
         int i = row - j * g.nx;
-        double bw = i > 0 ? K.dt * g.dy[j] * g.iDx[i] : 0.0;
-        double be = i < g.nx - 1 ? K.dt * g.dy[j] * g.iDx[i + 1] : 0.0;
-        double bs = j > 0 ? K.dt * g.dx[i] * g.iDy[j] : 0.0;
-        double bn = j < g.ny - 1 ? K.dt * g.dx[i] * g.iDy[j + 1] : 0.0;
+        T bw = i > 0 ? K.dt * g.dy[j] * g.iDx[i] : T(0);
+        T be = i < g.nx - 1 ? K.dt * g.dy[j] * g.iDx[i + 1] : T(0);
+        T bs = j > 0 ? K.dt * g.dx[i] * g.iDy[j] : T(0);
+        T bn = j < g.ny - 1 ? K.dt * g.dx[i] * g.iDy[j + 1] : T(0);
         return ((bw + be) + bs) + bn;
     }
     return K.kf_diag[row - g.n_cell];
@@ -192,40 +199,42 @@ __device__ __forceinline__ double a_diag(const AView &A, int f) {
 }
 
 // overloads so the Krylov kernels can be written once
-template <class X>
-__device__ __forceinline__ double op_row(const K0View &K, int r, X x, double &d) {
+template <class T, class X>
+__device__ __forceinline__ T op_row(const K0T<T> &K, int r, X x, T &d) {
     return k0_row(K, r, x, d);
 }
 template <class X>
 __device__ __forceinline__ double op_row(const AView &A, int r, X x, double &d) {
     return a_row(A, r, x, d);
 }
-__device__ __forceinline__ double op_diag(const K0View &K, int r) { return k0_diag(K, r); }
+template <class T>
+__device__ __forceinline__ T op_diag(const K0T<T> &K, int r) { return k0_diag(K, r); }
 __device__ __forceinline__ double op_diag(const AView &A, int r) { return a_diag(A, r); }
-__host__ __device__ inline int op_n(const K0View &K) { return K.n; }
+template <class T>
+__host__ __device__ inline int op_n(const K0T<T> &K) { return K.n; }
 __host__ __device__ inline int op_n(const AView &A) { return A.g.n_q; }
 
 // ---------------------------------------------------------------------------
 // Krylov kernels
 
-template <class Op>
-__global__ __launch_bounds__(kBlock) void k_pcg_init(Op op, const double *b, const double *x,
-                                                     double *r, SolveStatus *st, double *parts,
-                                                     int jacobi, double rtol2, int maxit) {
+template <class Op, class T>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(Op op, const T *b, const T *x, T *r,
+                                                     SolveStatus *st, double *parts, int jacobi,
+                                                     double rtol2, int maxit) {
     const int n = op_n(op);
-    Tiles T = my_tiles(n);
+    Tiles Tl = my_tiles(n);
     double v[3] = {0.0, 0.0, 0.0};   // bb, rr, rz
-    for (int t = T.t0; t < T.t1; ++t) {
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < n) {
-            double d;
-            double ax = op_row(op, row, [&](int c) { return x[c]; }, d);
-            double bi = b[row];
-            double ri = bi - ax;
+            T d;
+            T ax = op_row(op, row, [&](int c) { return x[c]; }, d);
+            T bi = b[row];
+            T ri = bi - ax;
             r[row] = ri;
-            v[0] += bi * bi;
-            v[1] += ri * ri;
-            if (jacobi) v[2] += ri * ri / d;
+            v[0] += (double)bi * (double)bi;
+            v[1] += (double)ri * (double)ri;
+            if (jacobi) v[2] += (double)ri * (double)ri / (double)d;
         }
     }
     double tot[3];
@@ -240,7 +249,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Op op, const double *b, con
         st->done = ST_RUNNING;
         if (tot[0] == 0.0) {
             st->done = ST_ZERO_RHS;
-        } else if (!(tot[1] == tot[1]) || tot[1] > 1e300) {
+        } else if (bad(tot[1])) {
             st->done = ST_NAN;
         } else if (tot[1] <= rtol2 * tot[0]) {
             st->done = ST_CONVERGED;
@@ -252,29 +261,58 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Op op, const double *b, con
     }
 }
 
-// p_new = z + beta p_old (z = D^{-1} r for Jacobi), q = op p_new, pq = p_new . q
-template <class Op>
-__global__ __launch_bounds__(kBlock) void k_pcg_spmv(Op op, const double *src, const double *pold,
-                                                     double *pnew, double *q, SolveStatus *st,
-                                                     double *parts, int jacobi) {
-    if (st->done) return;
-    const int n = op_n(op);
-    const double beta = st->beta;
-    Tiles T = my_tiles(n);
+// x = 0, r = b (initial guess zero; used by the inner mixed-precision solve)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_pcg_init_zero(int n, const T *b, T *x, T *r,
+                                                          SolveStatus *st, double *parts,
+                                                          double rtol2, int maxit) {
+    Tiles Tl = my_tiles(n);
     double v[1] = {0.0};
-    auto pval = [&](int c) {
-        double z = jacobi ? src[c] / op_diag(op, c) : src[c];
-        return z + beta * pold[c];
-    };
-    for (int t = T.t0; t < T.t1; ++t) {
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < n) {
-            double d;
-            double qi = op_row(op, row, pval, d);
-            double pi = pval(row);
+            T bi = b[row];
+            x[row] = T(0);
+            r[row] = bi;
+            v[0] += (double)bi * (double)bi;
+        }
+    }
+    double tot[1];
+    if (grid_sum<1>(v, parts, st, tot) && threadIdx.x == 0) {
+        st->bb = tot[0];
+        st->rr = tot[0];
+        st->tol2 = rtol2;
+        st->maxit = maxit;
+        st->iter = 0;
+        st->beta = 0.0;
+        st->first = 1;
+        st->done = tot[0] == 0.0 ? ST_ZERO_RHS : (bad(tot[0]) ? ST_NAN : ST_RUNNING);
+    }
+}
+
+// p_new = z + beta p_old (z = D^{-1} r for Jacobi), q = op p_new, pq = p_new . q
+template <class Op, class T>
+__global__ __launch_bounds__(kBlock) void k_pcg_spmv(Op op, const T *src, const T *pold, T *pnew,
+                                                     T *q, SolveStatus *st, double *parts,
+                                                     int jacobi) {
+    if (st->done) return;
+    const int n = op_n(op);
+    const T beta = (T)st->beta;
+    Tiles Tl = my_tiles(n);
+    double v[1] = {0.0};
+    auto pval = [&](int c) {
+        T z = jacobi ? src[c] / op_diag(op, c) : src[c];
+        return z + beta * pold[c];
+    };
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
+        int row = t * kBlock + threadIdx.x;
+        if (row < n) {
+            T d;
+            T qi = op_row(op, row, pval, d);
+            T pi = pval(row);
             pnew[row] = pi;
             q[row] = qi;
-            v[0] += pi * qi;
+            v[0] += (double)pi * (double)qi;
         }
     }
     double tot[1];
@@ -282,30 +320,29 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv(Op op, const double *src, c
 }
 
 // x += alpha p, r -= alpha q; convergence test on ||r||^2
-template <class Op>
-__global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, double *x, double *r, const double *p,
-                                                       const double *q, SolveStatus *st,
-                                                       double *parts, int jacobi) {
+template <class Op, class T>
+__global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *x, T *r, const T *p, const T *q,
+                                                       SolveStatus *st, double *parts, int jacobi) {
     if (st->done) return;
     const int n = op_n(op);
-    const double alpha = st->rz / st->pq;
-    Tiles T = my_tiles(n);
+    const T alpha = (T)(st->rz / st->pq);
+    Tiles Tl = my_tiles(n);
     double v[2] = {0.0, 0.0};
-    for (int t = T.t0; t < T.t1; ++t) {
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < n) {
             x[row] += alpha * p[row];
-            double ri = r[row] - alpha * q[row];
+            T ri = r[row] - alpha * q[row];
             r[row] = ri;
-            v[0] += ri * ri;
-            if (jacobi) v[1] += ri * ri / op_diag(op, row);
+            v[0] += (double)ri * (double)ri;
+            if (jacobi) v[1] += (double)ri * (double)ri / (double)op_diag(op, row);
         }
     }
     double tot[2];
     if (grid_sum<2>(v, parts, st, tot) && threadIdx.x == 0) {
         st->rr = tot[0];
         st->iter += 1;
-        if (!(tot[0] == tot[0]) || tot[0] > 1e300) st->done = ST_NAN;
+        if (bad(tot[0])) st->done = ST_NAN;
         else if (tot[0] <= st->tol2 * st->bb) st->done = ST_CONVERGED;
         else if (st->iter >= st->maxit) st->done = ST_MAXIT;
         if (jacobi) {
@@ -315,88 +352,113 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, double *x, double 
     }
 }
 
-template <class Op>
-__global__ __launch_bounds__(kBlock) void k_true_residual(Op op, const double *b, const double *x,
+template <class Op, class T>
+__global__ __launch_bounds__(kBlock) void k_true_residual(Op op, const T *b, const T *x,
                                                           SolveStatus *st, double *parts) {
     const int n = op_n(op);
-    Tiles T = my_tiles(n);
+    Tiles Tl = my_tiles(n);
     double v[1] = {0.0};
-    for (int t = T.t0; t < T.t1; ++t) {
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < n) {
-            double d;
-            double ri = b[row] - op_row(op, row, [&](int c) { return x[c]; }, d);
-            v[0] += ri * ri;
+            T d;
+            T ri = b[row] - op_row(op, row, [&](int c) { return x[c]; }, d);
+            v[0] += (double)ri * (double)ri;
         }
     }
     double tot[1];
     if (grid_sum<1>(v, parts, st, tot) && threadIdx.x == 0) st->true_rr = tot[0];
 }
 
-__global__ __launch_bounds__(kBlock) void k_zero_if_zero_rhs(double *x, int n,
-                                                             const SolveStatus *st) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_zero_if_zero_rhs(T *x, int n, const SolveStatus *st) {
     if (st->done != ST_ZERO_RHS) return;
     int i = blockIdx.x * kBlock + threadIdx.x;
-    if (i < n) x[i] = 0.0;
+    if (i < n) x[i] = T(0);
 }
 
-template <class Op>
-__global__ __launch_bounds__(kBlock) void k_apply(Op op, const double *x, double *y) {
+template <class Op, class T>
+__global__ __launch_bounds__(kBlock) void k_apply(Op op, const T *x, T *y) {
     const int n = op_n(op);
-    Tiles T = my_tiles(n);
-    for (int t = T.t0; t < T.t1; ++t) {
+    Tiles Tl = my_tiles(n);
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < n) {
-            double d;
+            T d;
             y[row] = op_row(op, row, [&](int c) { return x[c]; }, d);
         }
+    }
+}
+
+// r . z for the PCG when the preconditioner wrote z directly (one-level AMG)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dot_rz(int n, const T *r, const T *z, SolveStatus *st,
+                                                   double *parts) {
+    if (st->done) return;
+    Tiles Tl = my_tiles(n);
+    double v[1] = {0.0};
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
+        int row = t * kBlock + threadIdx.x;
+        if (row < n) v[0] += (double)r[row] * (double)z[row];
+    }
+    double tot[1];
+    if (grid_sum<1>(v, parts, st, tot) && threadIdx.x == 0) {
+        if (st->first) {
+            st->beta = 0.0;
+            st->first = 0;
+        } else {
+            st->beta = tot[0] / st->rz;
+        }
+        st->rz = tot[0];
     }
 }
 
 // ---------------------------------------------------------------------------
 // V-cycle on level 0 (K0)
 
-__global__ __launch_bounds__(kBlock) void k_k0_jacobi_first(K0View K, double omega, const double *b,
-                                                            double *x, const SolveStatus *st) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi_first(K0T<T> K, T omega, const T *b, T *x,
+                                                            const SolveStatus *st) {
     if (st->done) return;
-    Tiles T = my_tiles(K.n);
-    for (int t = T.t0; t < T.t1; ++t) {
+    Tiles Tl = my_tiles(K.n);
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < K.n) x[row] = omega / k0_diag(K, row) * b[row];
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_k0_jacobi(K0View K, double omega, const double *b,
-                                                      const double *xin, double *xout,
-                                                      const SolveStatus *st) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi(K0T<T> K, T omega, const T *b, const T *xin,
+                                                      T *xout, const SolveStatus *st) {
     if (st->done) return;
-    Tiles T = my_tiles(K.n);
-    for (int t = T.t0; t < T.t1; ++t) {
+    Tiles Tl = my_tiles(K.n);
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < K.n) {
-            double d;
-            double ax = k0_row(K, row, [&](int c) { return xin[c]; }, d);
+            T d;
+            T ax = k0_row(K, row, [&](int c) { return xin[c]; }, d);
             xout[row] = xin[row] + omega / d * (b[row] - ax);
         }
     }
 }
 
 // last post-smoothing sweep: also forms r . z for the PCG (b is the PCG residual)
-__global__ __launch_bounds__(kBlock) void k_k0_jacobi_rz(K0View K, double omega, const double *b,
-                                                         const double *xin, double *xout,
-                                                         SolveStatus *st, double *parts) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi_rz(K0T<T> K, T omega, const T *b,
+                                                         const T *xin, T *xout, SolveStatus *st,
+                                                         double *parts) {
     if (st->done) return;
-    Tiles T = my_tiles(K.n);
+    Tiles Tl = my_tiles(K.n);
     double v[1] = {0.0};
-    for (int t = T.t0; t < T.t1; ++t) {
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < K.n) {
-            double d;
-            double ax = k0_row(K, row, [&](int c) { return xin[c]; }, d);
-            double bi = b[row];
-            double z = xin[row] + omega / d * (bi - ax);
+            T d;
+            T ax = k0_row(K, row, [&](int c) { return xin[c]; }, d);
+            T bi = b[row];
+            T z = xin[row] + omega / d * (bi - ax);
             xout[row] = z;
-            v[0] += bi * z;
+            v[0] += (double)bi * (double)z;
         }
     }
     double tot[1];
@@ -411,36 +473,15 @@ __global__ __launch_bounds__(kBlock) void k_k0_jacobi_rz(K0View K, double omega,
     }
 }
 
-// r . z for the PCG when the preconditioner wrote z directly (one-level AMG)
-__global__ __launch_bounds__(kBlock) void k_dot_rz(int n, const double *r, const double *z,
-                                                   SolveStatus *st, double *parts) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_k0_residual(K0T<T> K, const T *b, const T *x, T *r,
+                                                        const SolveStatus *st) {
     if (st->done) return;
-    Tiles T = my_tiles(n);
-    double v[1] = {0.0};
-    for (int t = T.t0; t < T.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < n) v[0] += r[row] * z[row];
-    }
-    double tot[1];
-    if (grid_sum<1>(v, parts, st, tot) && threadIdx.x == 0) {
-        if (st->first) {
-            st->beta = 0.0;
-            st->first = 0;
-        } else {
-            st->beta = tot[0] / st->rz;
-        }
-        st->rz = tot[0];
-    }
-}
-
-__global__ __launch_bounds__(kBlock) void k_k0_residual(K0View K, const double *b, const double *x,
-                                                        double *r, const SolveStatus *st) {
-    if (st->done) return;
-    Tiles T = my_tiles(K.n);
-    for (int t = T.t0; t < T.t1; ++t) {
+    Tiles Tl = my_tiles(K.n);
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < K.n) {
-            double d;
+            T d;
             r[row] = b[row] - k0_row(K, row, [&](int c) { return x[c]; }, d);
         }
     }
@@ -449,75 +490,118 @@ __global__ __launch_bounds__(kBlock) void k_k0_residual(K0View K, const double *
 // ---------------------------------------------------------------------------
 // V-cycle on coarse levels (CSR), one row per thread
 
-__device__ __forceinline__ double csr_dot(const CSRView &A, int row, const double *x) {
-    double y = 0.0;
+template <class T>
+__device__ __forceinline__ T csr_dot(const CSRT<T> &A, int row, const T *x) {
+    T y = T(0);
     for (int p = A.ptr[row]; p < A.ptr[row + 1]; ++p) y += A.val[p] * x[A.col[p]];
     return y;
 }
 
-__global__ __launch_bounds__(kBlock) void k_csr_jacobi_first(CSRView A, const double *wdinv,
-                                                             const double *b, double *x,
-                                                             const SolveStatus *st) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_csr_jacobi_first(CSRT<T> A, const T *wdinv, const T *b,
+                                                             T *x, const SolveStatus *st) {
     if (st->done) return;
-    Tiles T = my_tiles(A.nrows);
-    for (int t = T.t0; t < T.t1; ++t) {
+    Tiles Tl = my_tiles(A.nrows);
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < A.nrows) x[row] = wdinv[row] * b[row];
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_csr_jacobi(CSRView A, const double *wdinv,
-                                                       const double *b, const double *xin,
-                                                       double *xout, const SolveStatus *st) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_csr_jacobi(CSRT<T> A, const T *wdinv, const T *b,
+                                                       const T *xin, T *xout,
+                                                       const SolveStatus *st) {
     if (st->done) return;
-    Tiles T = my_tiles(A.nrows);
-    for (int t = T.t0; t < T.t1; ++t) {
+    Tiles Tl = my_tiles(A.nrows);
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < A.nrows) xout[row] = xin[row] + wdinv[row] * (b[row] - csr_dot(A, row, xin));
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_csr_residual(CSRView A, const double *b,
-                                                         const double *x, double *r,
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_csr_residual(CSRT<T> A, const T *b, const T *x, T *r,
                                                          const SolveStatus *st) {
     if (st->done) return;
-    Tiles T = my_tiles(A.nrows);
-    for (int t = T.t0; t < T.t1; ++t) {
+    Tiles Tl = my_tiles(A.nrows);
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < A.nrows) r[row] = b[row] - csr_dot(A, row, x);
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_csr_spmv(CSRView A, const double *x, double *y,
-                                                     int add, const SolveStatus *st) {
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_csr_spmv(CSRT<T> A, const T *x, T *y, int add,
+                                                     const SolveStatus *st) {
     if (st && st->done) return;
-    Tiles T = my_tiles(A.nrows);
-    for (int t = T.t0; t < T.t1; ++t) {
+    Tiles Tl = my_tiles(A.nrows);
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < A.nrows) {
-            double v = csr_dot(A, row, x);
+            T v = csr_dot(A, row, x);
             y[row] = add ? y[row] + v : v;
         }
     }
 }
 
-// x = Ainv b with Ainv dense, column-major (coalesced over rows)
-__global__ __launch_bounds__(kBlock) void k_dense_solve(int n, const double *inv, const double *b,
-                                                        double *x, const SolveStatus *st) {
+// x = Ainv b with Ainv dense FP64, column-major (coalesced over rows);
+// FP64 accumulation whatever T is (the coarsest solve stays FP64)
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dense_solve(int n, const double *inv, const T *b, T *x,
+                                                        const SolveStatus *st) {
     if (st->done) return;
     __shared__ double sb[kBlock];
     int row = blockIdx.x * kBlock + threadIdx.x;
     double acc = 0.0;
     for (int c0 = 0; c0 < n; c0 += kBlock) {
         int c = c0 + threadIdx.x;
-        sb[threadIdx.x] = c < n ? b[c] : 0.0;
+        sb[threadIdx.x] = c < n ? (double)b[c] : 0.0;
         __syncthreads();
         int m = min(kBlock, n - c0);
         if (row < n)
             for (int k = 0; k < m; ++k) acc += inv[(size_t)(c0 + k) * n + row] * sb[k];
         __syncthreads();
     }
-    if (row < n) x[row] = acc;
+    if (row < n) x[row] = (T)acc;
+}
+
+// ---------------------------------------------------------------------------
+// mixed precision outer loop (FP64)
+
+// r = b - K x in FP64, r32 = (float) r, ||r||^2 (and ||b||^2 when first)
+__global__ __launch_bounds__(kBlock) void k_outer_residual(K0View K, const double *b,
+                                                           const double *x, float *r32,
+                                                           SolveStatus *st, double *parts,
+                                                           int first) {
+    Tiles Tl = my_tiles(K.n);
+    double v[2] = {0.0, 0.0};
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
+        int row = t * kBlock + threadIdx.x;
+        if (row < K.n) {
+            double d;
+            double bi = b[row];
+            double ri = bi - k0_row(K, row, [&](int c) { return x[c]; }, d);
+            r32[row] = (float)ri;
+            v[0] += ri * ri;
+            v[1] += bi * bi;
+        }
+    }
+    double tot[2];
+    if (grid_sum<2>(v, parts, st, tot) && threadIdx.x == 0) {
+        st->rr = tot[0];
+        if (first) {
+            st->bb = tot[1];
+            st->iter = 0;
+        } else {
+            st->iter += 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_add_correction(int n, double *x, const float *d) {
+    int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) x[i] += (double)d[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -758,6 +842,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_walls(GridView g, double *w, do
     }
 }
 
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -805,91 +890,160 @@ void launch_fill_walls(hipStream_t s, GridView g, double *w, double U, double V)
 }
 
 void launch_apply_K0(hipStream_t s, const K0View &K, const double *x, double *y) {
-    LAUNCH(k_apply<K0View>, grid_for(K.n), K, x, y);
+    LAUNCH((k_apply<K0View, double>), grid_for(K.n), K, x, y);
 }
 
 void launch_apply_A(hipStream_t s, const AView &A, const double *x, double *y) {
-    LAUNCH(k_apply<AView>, grid_for(A.g.n_q), A, x, y);
+    LAUNCH((k_apply<AView, double>), grid_for(A.g.n_q), A, x, y);
 }
 
-#define KRYLOV_LAUNCHERS(OP)                                                                       \
-    void launch_pcg_init(hipStream_t s, const OP &op, const double *b, const double *x, double *r, \
-                         SolveStatus *st, double *parts, bool jacobi, double rtol2, int maxit) {  \
-        LAUNCH(k_pcg_init<OP>, grid_for(op_n(op)), op, b, x, r, st, parts, (int)jacobi, rtol2,     \
-               maxit);                                                                             \
-    }                                                                                              \
-    void launch_pcg_spmv(hipStream_t s, const OP &op, const double *src, const double *pold,      \
-                         double *pnew, double *q, SolveStatus *st, double *parts, bool jacobi) {  \
-        LAUNCH(k_pcg_spmv<OP>, grid_for(op_n(op)), op, src, pold, pnew, q, st, parts, (int)jacobi);\
-    }                                                                                              \
-    void launch_pcg_update(hipStream_t s, const OP &op, double *x, double *r, const double *p,    \
-                           const double *q, SolveStatus *st, double *parts, bool jacobi) {        \
-        LAUNCH(k_pcg_update<OP>, grid_for(op_n(op)), op, x, r, p, q, st, parts, (int)jacobi);      \
-    }                                                                                              \
-    void launch_true_residual(hipStream_t s, const OP &op, const double *b, const double *x,      \
-                              SolveStatus *st, double *parts) {                                   \
-        LAUNCH(k_true_residual<OP>, grid_for(op_n(op)), op, b, x, st, parts);                      \
-    }
-
-KRYLOV_LAUNCHERS(K0View)
-KRYLOV_LAUNCHERS(AView)
-
-void launch_zero_if_zero_rhs(hipStream_t s, double *x, int n, const SolveStatus *st) {
-    LAUNCH(k_zero_if_zero_rhs, (n + kBlock - 1) / kBlock, x, n, st);
+template <class Op, class T>
+void launch_pcg_init(hipStream_t s, const Op &op, const T *b, const T *x, T *r, SolveStatus *st,
+                     double *parts, bool jacobi, double rtol2, int maxit) {
+    LAUNCH((k_pcg_init<Op, T>), grid_for(op_n(op)), op, b, x, r, st, parts, (int)jacobi, rtol2, maxit);
 }
 
-void launch_k0_jacobi_first(hipStream_t s, const K0View &K, double omega, const double *b,
-                            double *x, const SolveStatus *st) {
-    LAUNCH(k_k0_jacobi_first, grid_for(K.n), K, omega, b, x, st);
+template <class T>
+void launch_pcg_init_zero(hipStream_t s, int n, const T *b, T *x, T *r, SolveStatus *st,
+                          double *parts, double rtol2, int maxit) {
+    LAUNCH((k_pcg_init_zero<T>), grid_for(n), n, b, x, r, st, parts, rtol2, maxit);
 }
 
-void launch_k0_jacobi(hipStream_t s, const K0View &K, double omega, const double *b,
-                      const double *xin, double *xout, const SolveStatus *st) {
-    LAUNCH(k_k0_jacobi, grid_for(K.n), K, omega, b, xin, xout, st);
+template <class Op, class T>
+void launch_pcg_spmv(hipStream_t s, const Op &op, const T *src, const T *pold, T *pnew, T *q,
+                     SolveStatus *st, double *parts, bool jacobi) {
+    LAUNCH((k_pcg_spmv<Op, T>), grid_for(op_n(op)), op, src, pold, pnew, q, st, parts, (int)jacobi);
 }
 
-void launch_k0_jacobi_rz(hipStream_t s, const K0View &K, double omega, const double *b,
-                         const double *xin, double *xout, SolveStatus *st, double *parts) {
-    LAUNCH(k_k0_jacobi_rz, grid_for(K.n), K, omega, b, xin, xout, st, parts);
+template <class Op, class T>
+void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, const T *p, const T *q,
+                       SolveStatus *st, double *parts, bool jacobi) {
+    LAUNCH((k_pcg_update<Op, T>), grid_for(op_n(op)), op, x, r, p, q, st, parts, (int)jacobi);
 }
 
-void launch_dot_rz(hipStream_t s, int n, const double *r, const double *z, SolveStatus *st,
-                   double *parts) {
-    LAUNCH(k_dot_rz, grid_for(n), n, r, z, st, parts);
+template <class Op, class T>
+void launch_true_residual(hipStream_t s, const Op &op, const T *b, const T *x, SolveStatus *st,
+                          double *parts) {
+    LAUNCH((k_true_residual<Op, T>), grid_for(op_n(op)), op, b, x, st, parts);
 }
 
-void launch_k0_residual(hipStream_t s, const K0View &K, const double *b, const double *x, double *r,
+template <class T>
+void launch_dot_rz(hipStream_t s, int n, const T *r, const T *z, SolveStatus *st, double *parts) {
+    LAUNCH((k_dot_rz<T>), grid_for(n), n, r, z, st, parts);
+}
+
+template <class T>
+void launch_zero_if_zero_rhs(hipStream_t s, T *x, int n, const SolveStatus *st) {
+    LAUNCH((k_zero_if_zero_rhs<T>), (n + kBlock - 1) / kBlock, x, n, st);
+}
+
+template <class T>
+void launch_k0_jacobi_first(hipStream_t s, const K0T<T> &K, double omega, const T *b, T *x,
+                            const SolveStatus *st) {
+    LAUNCH((k_k0_jacobi_first<T>), grid_for(K.n), K, (T)omega, b, x, st);
+}
+
+template <class T>
+void launch_k0_jacobi(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
+                      T *xout, const SolveStatus *st) {
+    LAUNCH((k_k0_jacobi<T>), grid_for(K.n), K, (T)omega, b, xin, xout, st);
+}
+
+template <class T>
+void launch_k0_jacobi_rz(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
+                         T *xout, SolveStatus *st, double *parts) {
+    LAUNCH((k_k0_jacobi_rz<T>), grid_for(K.n), K, (T)omega, b, xin, xout, st, parts);
+}
+
+template <class T>
+void launch_k0_residual(hipStream_t s, const K0T<T> &K, const T *b, const T *x, T *r,
                         const SolveStatus *st) {
-    LAUNCH(k_k0_residual, grid_for(K.n), K, b, x, r, st);
+    LAUNCH((k_k0_residual<T>), grid_for(K.n), K, b, x, r, st);
 }
 
-void launch_csr_jacobi_first(hipStream_t s, CSRView A, const double *wdinv, const double *b,
-                             double *x, const SolveStatus *st) {
-    LAUNCH(k_csr_jacobi_first, grid_for(A.nrows), A, wdinv, b, x, st);
+template <class T>
+void launch_csr_jacobi_first(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b, T *x,
+                             const SolveStatus *st) {
+    LAUNCH((k_csr_jacobi_first<T>), grid_for(A.nrows), A, wdinv, b, x, st);
 }
 
-void launch_csr_jacobi(hipStream_t s, CSRView A, const double *wdinv, const double *b,
-                       const double *xin, double *xout, const SolveStatus *st) {
-    LAUNCH(k_csr_jacobi, grid_for(A.nrows), A, wdinv, b, xin, xout, st);
+template <class T>
+void launch_csr_jacobi(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b, const T *xin,
+                       T *xout, const SolveStatus *st) {
+    LAUNCH((k_csr_jacobi<T>), grid_for(A.nrows), A, wdinv, b, xin, xout, st);
 }
 
-void launch_csr_residual(hipStream_t s, CSRView A, const double *b, const double *x, double *r,
+template <class T>
+void launch_csr_residual(hipStream_t s, CSRT<T> A, const T *b, const T *x, T *r,
                          const SolveStatus *st) {
-    LAUNCH(k_csr_residual, grid_for(A.nrows), A, b, x, r, st);
+    LAUNCH((k_csr_residual<T>), grid_for(A.nrows), A, b, x, r, st);
 }
 
-void launch_csr_spmv(hipStream_t s, CSRView A, const double *x, double *y, const SolveStatus *st) {
-    LAUNCH(k_csr_spmv, grid_for(A.nrows), A, x, y, 0, st);
+template <class T>
+void launch_csr_spmv(hipStream_t s, CSRT<T> A, const T *x, T *y, const SolveStatus *st) {
+    LAUNCH((k_csr_spmv<T>), grid_for(A.nrows), A, x, y, 0, st);
 }
 
-void launch_csr_spmv_add(hipStream_t s, CSRView A, const double *x, double *y,
-                         const SolveStatus *st) {
-    LAUNCH(k_csr_spmv, grid_for(A.nrows), A, x, y, 1, st);
+template <class T>
+void launch_csr_spmv_add(hipStream_t s, CSRT<T> A, const T *x, T *y, const SolveStatus *st) {
+    LAUNCH((k_csr_spmv<T>), grid_for(A.nrows), A, x, y, 1, st);
 }
 
-void launch_dense_solve(hipStream_t s, int n, const double *inv, const double *b, double *x,
+template <class T>
+void launch_dense_solve(hipStream_t s, int n, const double *inv, const T *b, T *x,
                         const SolveStatus *st) {
-    LAUNCH(k_dense_solve, (n + kBlock - 1) / kBlock, n, inv, b, x, st);
+    LAUNCH((k_dense_solve<T>), (n + kBlock - 1) / kBlock, n, inv, b, x, st);
 }
+
+void launch_outer_residual(hipStream_t s, const K0View &K, const double *b, const double *x,
+                           float *r32, SolveStatus *st, double *parts, int first) {
+    LAUNCH(k_outer_residual, grid_for(K.n), K, b, x, r32, st, parts, first);
+}
+
+void launch_add_correction(hipStream_t s, int n, double *x, const float *d) {
+    LAUNCH(k_add_correction, (n + kBlock - 1) / kBlock, n, x, d);
+}
+
+// explicit instantiations
+#define INST_OP(OP, T)                                                                           \
+    template void launch_pcg_init<OP, T>(hipStream_t, const OP &, const T *, const T *, T *,     \
+                                         SolveStatus *, double *, bool, double, int);            \
+    template void launch_pcg_spmv<OP, T>(hipStream_t, const OP &, const T *, const T *, T *, T *, \
+                                         SolveStatus *, double *, bool);                         \
+    template void launch_pcg_update<OP, T>(hipStream_t, const OP &, T *, T *, const T *,         \
+                                           const T *, SolveStatus *, double *, bool);            \
+    template void launch_true_residual<OP, T>(hipStream_t, const OP &, const T *, const T *,     \
+                                              SolveStatus *, double *);
+INST_OP(K0View, double)
+INST_OP(AView, double)
+INST_OP(K0T<float>, float)
+
+#define INST_T(T)                                                                                \
+    template void launch_pcg_init_zero<T>(hipStream_t, int, const T *, T *, T *, SolveStatus *,  \
+                                          double *, double, int);                                \
+    template void launch_dot_rz<T>(hipStream_t, int, const T *, const T *, SolveStatus *,        \
+                                   double *);                                                    \
+    template void launch_zero_if_zero_rhs<T>(hipStream_t, T *, int, const SolveStatus *);        \
+    template void launch_k0_jacobi_first<T>(hipStream_t, const K0T<T> &, double, const T *, T *, \
+                                            const SolveStatus *);                                \
+    template void launch_k0_jacobi<T>(hipStream_t, const K0T<T> &, double, const T *, const T *, \
+                                      T *, const SolveStatus *);                                 \
+    template void launch_k0_jacobi_rz<T>(hipStream_t, const K0T<T> &, double, const T *,         \
+                                         const T *, T *, SolveStatus *, double *);               \
+    template void launch_k0_residual<T>(hipStream_t, const K0T<T> &, const T *, const T *, T *,  \
+                                        const SolveStatus *);                                    \
+    template void launch_csr_jacobi_first<T>(hipStream_t, CSRT<T>, const T *, const T *, T *,    \
+                                             const SolveStatus *);                               \
+    template void launch_csr_jacobi<T>(hipStream_t, CSRT<T>, const T *, const T *, const T *,    \
+                                       T *, const SolveStatus *);                                \
+    template void launch_csr_residual<T>(hipStream_t, CSRT<T>, const T *, const T *, T *,        \
+                                         const SolveStatus *);                                   \
+    template void launch_csr_spmv<T>(hipStream_t, CSRT<T>, const T *, T *, const SolveStatus *); \
+    template void launch_csr_spmv_add<T>(hipStream_t, CSRT<T>, const T *, T *,                   \
+                                         const SolveStatus *);                                   \
+    template void launch_dense_solve<T>(hipStream_t, int, const double *, const T *, T *,        \
+                                        const SolveStatus *);
+INST_T(double)
+INST_T(float)
 
 }  // namespace ibpm

@@ -40,7 +40,11 @@ def stretch_ratio(n_side: int, h: float, width: float) -> float:
     lo, hi = 1.0, 8.0
     for _ in range(200):
         r = 0.5 * (lo + hi)
-        s = h * r * (r ** n_side - 1.0) / (r - 1.0)
+        # geometric sum; the log guard avoids overflow of r**n_side for large r
+        if n_side * math.log(r) > 700.0:
+            s = math.inf
+        else:
+            s = h * r * (r ** n_side - 1.0) / (r - 1.0)
         if s > width:
             hi = r
         else:
