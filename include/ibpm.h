@@ -54,7 +54,7 @@ extern "C" {
  * preconditioning).  The velocity solve always uses Jacobi-PCG. */
 #define IBPM_SOLVER_JACOBI_PCG       0
 #define IBPM_SOLVER_AMG_PCG          1
-#define IBPM_SOLVER_AMG_PCG_MIXED    2   /* reserved: FP32 inner AMG-PCG in FP64 refinement */
+#define IBPM_SOLVER_AMG_PCG_MIXED    2   /* FP32 inner AMG-PCG inside FP64 iterative refinement */
 #define IBPM_SOLVER_AMG_FCG_LEARNED  3   /* reserved: flexible CG with a learned stage */
 
 typedef struct ibpm_ctx ibpm_ctx;
@@ -85,6 +85,8 @@ typedef struct ibpm_solve_stats {
     int32_t status;       /* IBPM_OK, IBPM_ENOTCONV or IBPM_ENAN */
     double relres;        /* true residual ||b - K x|| / ||b|| recomputed at exit */
     double ms;            /* wall time of the call */
+    int32_t outer_iters;  /* refinement steps (mixed precision), else 1 */
+    int32_t fallbacks;    /* switches to the plain AMG-PCG (learned stage), else 0 */
 } ibpm_solve_stats;
 
 typedef struct ibpm_step_stats {
@@ -195,12 +197,13 @@ int ibpm_get_aggregates(const ibpm_ctx *ctx, int32_t level, int32_t *agg);
 #define IBPM_KERNEL_RESTRICT0     4   /* b1 = P0^T r (finest to first coarse level) */
 #define IBPM_KERNEL_PROLONG0      5   /* x += P0 x1 */
 #define IBPM_KERNEL_PCG_UPDATE_K  6   /* x += a p; r -= a q; r . r */
+#define IBPM_KERNEL_COARSE_CYCLE  7   /* the V-cycle on the small levels, one work-group */
 
 /* Time `reps` back-to-back launches of one kernel of the solver on the
  * context's stream with HIP events and return the mean duration of one
  * launch (ms) and the algorithmic bytes of one launch (every operand read
  * once, every result written once).  Overwrites the context's work vectors
- * (not the caller's).  Needs an AMG context for kernels 0, 3, 4, 5. */
+ * (not the caller's).  Needs an AMG context for kernels 0, 3, 4, 5, 7. */
 int ibpm_time_kernel(ibpm_ctx *ctx, int32_t kernel, int32_t reps, double *avg_ms,
                      double *bytes);
 

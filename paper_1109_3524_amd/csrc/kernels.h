@@ -7,7 +7,7 @@
 namespace ibpm {
 
 constexpr int kBlock = 256;        // threads per block (4 wave64)
-constexpr int kMaxParts = 2048;    // upper bound on blocks of a reducing kernel
+constexpr int kMaxParts = 8192;    // upper bound on blocks of a reducing kernel
 
 // Tensor-product staggered grid; metric arrays live on the device.
 template <class T>
@@ -99,17 +99,20 @@ void launch_apply_A(hipStream_t s, const AView &A, const double *x, double *y);
 
 // Krylov pieces.  Op is K0T<T> (vectors of T) or AView (vectors of double);
 // dot products always accumulate in FP64.
+// r = b - op x (and z = D^{-1} r for Jacobi preconditioning)
 template <class Op, class T>
-void launch_pcg_init(hipStream_t s, const Op &op, const T *b, const T *x, T *r, SolveStatus *st,
-                     double *parts, bool jacobi, double rtol2, int maxit);
+void launch_pcg_init(hipStream_t s, const Op &op, const T *b, const T *x, T *r, T *z,
+                     SolveStatus *st, double *parts, bool jacobi, double rtol2, int maxit);
 template <class T>
 void launch_pcg_init_zero(hipStream_t s, int n, const T *b, T *x, T *r, SolveStatus *st,
                           double *parts, double rtol2, int maxit);
+// p_new = z + beta p_old; q = op p_new
 template <class Op, class T>
-void launch_pcg_spmv(hipStream_t s, const Op &op, const T *src, const T *pold, T *pnew, T *q,
-                     SolveStatus *st, double *parts, bool jacobi);
+void launch_pcg_spmv(hipStream_t s, const Op &op, const T *z, const T *pold, T *pnew, T *q,
+                     SolveStatus *st, double *parts);
+// x += alpha p; r -= alpha q (and z = D^{-1} r for Jacobi)
 template <class Op, class T>
-void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, const T *p, const T *q,
+void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, T *z, const T *p, const T *q,
                        SolveStatus *st, double *parts, bool jacobi);
 template <class Op, class T>
 void launch_true_residual(hipStream_t s, const Op &op, const T *b, const T *x, SolveStatus *st,
@@ -148,6 +151,36 @@ void launch_csr_spmv_add(hipStream_t s, CSRT<T> A, const T *x, T *y, const Solve
 template <class T>
 void launch_dense_solve(hipStream_t s, int n, const double *inv_colmajor, const T *b, T *x,
                         const SolveStatus *st);
+
+// CSR kernels with `lanes` threads per row (1, 2, 4, ..., 64; a power of two)
+template <class T>
+void launch_csrv_jacobi(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b,
+                        const T *xin, T *xout, const SolveStatus *st);
+template <class T>
+void launch_csrv_residual(hipStream_t s, CSRT<T> A, int lanes, const T *b, const T *x, T *r,
+                          const SolveStatus *st);
+template <class T>
+void launch_csrv_spmv(hipStream_t s, CSRT<T> A, int lanes, const T *x, T *y, bool add,
+                      const SolveStatus *st);
+
+// Coarse levels handled together by one work-group (levels lc .. L-1).
+template <class T>
+struct CoarseLevel {
+    int n;
+    CSRT<T> A;
+    const T *wdinv;
+    CSRT<T> P;     // n x n_next (unused on the coarsest level)
+    CSRT<T> R;     // n_next x n
+    T *b, *xa, *xb, *r;
+};
+constexpr int kCoarseBlock = 1024;
+constexpr int kCoarseRows = 1024;
+constexpr int kMaxLevels = 16;
+// V-cycle on levels lc..L-1 in one kernel; the input is lv[lc].b, the result
+// is left in lv[lc].xa
+template <class T>
+void launch_coarse_cycle(hipStream_t s, const CoarseLevel<T> *lv_dev, int lc, int L, int pre,
+                         int post, const double *inv, int n_coarse, const SolveStatus *st);
 
 // mixed precision: FP64 outer residual r = b - K x (also cast to FP32) and x += d
 void launch_outer_residual(hipStream_t s, const K0View &K, const double *b, const double *x,

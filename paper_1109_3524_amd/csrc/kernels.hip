@@ -15,6 +15,8 @@
 // accumulate in double.
 #include "kernels.h"
 
+#include <stdexcept>
+
 namespace ibpm {
 
 namespace {
@@ -64,78 +66,198 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
     __syncthreads();
 }
 
-// Per-block partial sums; returns true in every thread of the last block,
-// where `tot` (valid in thread 0) holds the grid-wide sums in fixed order.
+// Per-block partial sums of N values: block tree in LDS (fixed order), then
+// one store per value.  The grid-wide sums are formed by k_finalize, a
+// one-block kernel queued right after, which adds the partials in block
+// order: deterministic, and with no fences or atomics between blocks.
 template <int N>
-__device__ bool grid_sum(double (&v)[N], double *parts, SolveStatus *st, double (&tot)[N]) {
+__device__ __forceinline__ void write_parts(double (&v)[N], double *parts) {
     block_sum<N>(v);
-    __shared__ int is_last;
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < N; ++k) parts[k * kMaxParts + blockIdx.x] = v[k];
-        __threadfence();
-        unsigned prev = atomicAdd(&st->counter, 1u);
-        is_last = (prev == gridDim.x - 1);
     }
-    __syncthreads();
-    if (!is_last) return false;
-    __threadfence();
-    double acc[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
-#pragma unroll
-        for (int k = 0; k < N; ++k)
-            acc[k] += __hip_atomic_load(&parts[k * kMaxParts + b], __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT);
-    }
-    block_sum<N>(acc);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < N; ++k) tot[k] = acc[k];
-        st->counter = 0;
-    }
-    return true;
 }
 
 __device__ __forceinline__ bool bad(double v) { return !(v == v) || v > 1e300; }
 
 // ---------------------------------------------------------------------------
-// operator rows
+// Level-0 operators as 2-D walks.  A block is 64 x 4 threads; thread (tx, ty)
+// takes unknown column i = 64 bx + tx and the R rows j = (4 by + ty) R + r,
+// walking up the column so that the south / centre / north operands stay in
+// registers (each is loaded once), east / west come from the neighbouring
+// lanes' loads (L1), and the 1-D metrics of a row are wave-uniform.  Rows
+// that are not on the tensor grid (the 2 nb force rows of K) are taken by
+// one extra band of blocks.  Every block reaches the reduction at the end.
 
-// Row `row` of K = Q^T B^1 Q (pinned) in precision T.  x(c) gives the
-// operand.  Also returns the diagonal.  Pressure rows: the 5-point stencil
-// with coefficients B^1 = dt * dy_j / Dx_i (u faces) and dt * dx_i / Dy_j
-// (v faces) on interior faces, plus the stored force coupling inside the box.
-template <class T, class X>
-__device__ __forceinline__ T k0_row(const K0T<T> &K, int row, X x, T &diag) {
+template <int R>
+__host__ __device__ inline int walk_by(int nj) { return (nj + 4 * R - 1) / (4 * R); }
+
+// Pressure and force rows of K = Q^T B^1 Q (pinned), precision T.
+// act(row, Kx, diag, x_row) is called once per row.
+template <int R, class T, class XV, class ACT>
+__device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
     const GridT<T> &g = K.g;
-    if (row < g.n_cell) {
-        int j = row / g.nx;
-        int i = row - j * g.nx;
-        T bw = i > 0 ? K.dt * g.dy[j] * g.iDx[i] : T(0);
-        T be = i < g.nx - 1 ? K.dt * g.dy[j] * g.iDx[i + 1] : T(0);
-        T bs = j > 0 ? K.dt * g.dx[i] * g.iDy[j] : T(0);
-        T bn = j < g.ny - 1 ? K.dt * g.dx[i] * g.iDy[j + 1] : T(0);
-        diag = ((bw + be) + bs) + bn;
-        T y = diag * x(row);
-        if (row == 0) return y;
-        if (j > 0 && row - g.nx != 0) y -= bs * x(row - g.nx);
-        if (i > 0 && row - 1 != 0) y -= bw * x(row - 1);
-        if (i < g.nx - 1) y -= be * x(row + 1);
-        if (j < g.ny - 1) y -= bn * x(row + g.nx);
-        if (i >= K.cb_i0 && i <= K.cb_i1 && j >= K.cb_j0 && j <= K.cb_j1) {
-            int r = (j - K.cb_j0) * (K.cb_i1 - K.cb_i0 + 1) + (i - K.cb_i0);
-            for (int p = K.cf.ptr[r]; p < K.cf.ptr[r + 1]; ++p)
-                y += K.cf.val[p] * x(g.n_cell + K.cf.col[p]);
+    const int nx = g.nx, ny = g.ny;
+    const int gy = walk_by<R>(ny);
+    if ((int)blockIdx.y < gy) {
+        const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+        const int j0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * R;
+        if (i < nx && j0 < ny) {
+            const T dt = K.dt;
+            const T dxi = g.dx[i];
+            const T cw = i > 0 ? dt * g.iDx[i] : T(0);
+            const T ce = i < nx - 1 ? dt * g.iDx[i + 1] : T(0);
+            const bool in_box_i = i >= K.cb_i0 && i <= K.cb_i1;
+            const int bw_ = K.cb_i1 - K.cb_i0 + 1;
+            int row = j0 * nx + i;
+            T xs = j0 > 0 ? xv(row - nx) : T(0);
+            T xc = xv(row);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int j = j0 + r;
+                if (j >= ny) break;
+                const T xn = j < ny - 1 ? xv(row + nx) : T(0);
+                const T xw = i > 0 ? xv(row - 1) : T(0);
+                const T xe = i < nx - 1 ? xv(row + 1) : T(0);
+                const T dyj = g.dy[j];
+                const T bw = cw * dyj, be = ce * dyj;
+                const T bs = j > 0 ? dt * dxi * g.iDy[j] : T(0);
+                const T bn = j < ny - 1 ? dt * dxi * g.iDy[j + 1] : T(0);
+                const T diag = ((bw + be) + bs) + bn;
+                T y = diag * xc;
+                if (row != 0) {
+                    if (row - nx != 0) y -= bs * xs;
+                    if (row - 1 != 0) y -= bw * xw;
+                    y -= be * xe;
+                    y -= bn * xn;
+                    if (in_box_i && j >= K.cb_j0 && j <= K.cb_j1) {
+                        const int rb = (j - K.cb_j0) * bw_ + (i - K.cb_i0);
+                        for (int p = K.cf.ptr[rb]; p < K.cf.ptr[rb + 1]; ++p)
+                            y += K.cf.val[p] * xv(g.n_cell + K.cf.col[p]);
+                    }
+                }
+                act(row, y, diag, xc);
+                xs = xc;
+                xc = xn;
+                row += nx;
+            }
         }
-        return y;
+    } else {
+        const int t = (((int)blockIdx.y - gy) * gridDim.x + blockIdx.x) * kBlock + threadIdx.x;
+        if (t < 2 * K.nb) {
+            T y = T(0);
+            for (int p = K.kf.ptr[t]; p < K.kf.ptr[t + 1]; ++p) y += K.kf.val[p] * xv(K.kf.col[p]);
+            act(g.n_cell + t, y, K.kf_diag[t], xv(g.n_cell + t));
+        }
     }
-    int k = row - g.n_cell;
-    diag = K.kf_diag[k];
-    T y = T(0);
-    for (int p = K.kf.ptr[k]; p < K.kf.ptr[k + 1]; ++p) y += K.kf.val[p] * x(K.kf.col[p]);
-    return y;
+}
+
+template <int R, class T>
+inline dim3 k0_grid(const K0T<T> &K) {
+    int gx = (K.g.nx + 63) / 64;
+    int extra = (2 * K.nb + gx * kBlock - 1) / (gx * kBlock);
+    return dim3(gx, walk_by<R>(K.g.ny) + extra);
+}
+
+// Velocity rows of A = Mf/dt - (nu/2) M Lhat R^{-1}: u faces (nx-1) x ny,
+// then v faces nx x (ny-1).  Wall neighbours contribute through the
+// right-hand side.
+template <int R, class XV, class ACT>
+__device__ __forceinline__ void a_walk(const AView &A, XV xv, ACT act) {
+    const GridView &g = A.g;
+    const int nx = g.nx, ny = g.ny, nxm = nx - 1;
+    const double hnu = 0.5 * A.nu;
+    const int gyu = walk_by<R>(ny);
+    if ((int)blockIdx.y < gyu) {
+        const int i = blockIdx.x * 64 + (threadIdx.x & 63) + 1;       // 1..nx-1
+        const int j0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * R;
+        if (i <= nx - 1 && j0 < ny) {
+            const double idxi = g.idx[i], idxm = g.idx[i - 1], iDxi = g.iDx[i], Dxi = g.Dx[i];
+            int f = j0 * nxm + (i - 1);
+            double us = j0 > 0 ? xv(f - nxm) * g.idy[j0 - 1] : 0.0;
+            double xc = xv(f);
+            double uc = xc * g.idy[j0];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int j = j0 + r;
+                if (j >= ny) break;
+                const double idyj = g.idy[j];
+                const double xn = j < ny - 1 ? xv(f + nxm) : 0.0;
+                const double un = j < ny - 1 ? xn * g.idy[j + 1] : 0.0;
+                const double uE = i < nx - 1 ? xv(f + 1) * idyj : 0.0;
+                const double uW = i > 1 ? xv(f - 1) * idyj : 0.0;
+                const double lapx = ((uE - uc) * idxi - (uc - uW) * idxm) * iDxi;
+                const double lapy = ((un - uc) * g.iDy[j + 1] - (uc - us) * g.iDy[j]) * idyj;
+                const double mf = Dxi * idyj;
+                const double diag = mf * A.idt + hnu * ((idxi + idxm) * idyj +
+                                                         Dxi * (g.iDy[j + 1] + g.iDy[j]) * idyj * idyj);
+                act(f, mf * A.idt * xc - hnu * (Dxi * (lapx + lapy)), diag, xc);
+                us = uc;
+                uc = un;
+                xc = xn;
+                f += nxm;
+            }
+        }
+    } else {
+        const int by = blockIdx.y - gyu;
+        const int i = blockIdx.x * 64 + (threadIdx.x & 63);           // 0..nx-1
+        const int j0 = (by * 4 + (threadIdx.x >> 6)) * R + 1;        // 1..ny-1
+        if (i < nx && j0 <= ny - 1) {
+            const double idxi = g.idx[i], dxr = g.iDx[i + 1], dxl = g.iDx[i];
+            const double idxe = i < nx - 1 ? g.idx[i + 1] : 0.0, idxw = i > 0 ? g.idx[i - 1] : 0.0;
+            int f = g.n_u + (j0 - 1) * nx + i;
+            double vs = j0 > 1 ? xv(f - nx) * idxi : 0.0;
+            double xc = xv(f);
+            double vc = xc * idxi;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int j = j0 + r;
+                if (j > ny - 1) break;
+                const double xn = j < ny - 1 ? xv(f + nx) : 0.0;
+                const double vn = xn * idxi;
+                const double vE = i < nx - 1 ? xv(f + 1) * idxe : 0.0;
+                const double vW = i > 0 ? xv(f - 1) * idxw : 0.0;
+                const double lapx = ((vE - vc) * dxr - (vc - vW) * dxl) * idxi;
+                const double lapy = ((vn - vc) * g.idy[j] - (vc - vs) * g.idy[j - 1]) * g.iDy[j];
+                const double Dyj = g.Dy[j];
+                const double mf = Dyj * idxi;
+                const double diag = mf * A.idt + hnu * (Dyj * (dxr + dxl) * idxi * idxi +
+                                                         (g.idy[j] + g.idy[j - 1]) * idxi);
+                act(f, mf * A.idt * xc - hnu * (Dyj * (lapx + lapy)), diag, xc);
+                vs = vc;
+                vc = vn;
+                xc = xn;
+                f += nx;
+            }
+        }
+    }
+}
+
+template <int R>
+inline dim3 a_grid(const AView &A) {
+    int gx = (A.g.nx + 63) / 64;
+    return dim3(gx, walk_by<R>(A.g.ny) + walk_by<R>(A.g.ny - 1));
+}
+
+// diagonal of A for one face (used by elementwise kernels)
+__device__ __forceinline__ double a_diag(const AView &A, int f) {
+    const GridView &g = A.g;
+    const double hnu = 0.5 * A.nu;
+    if (f < g.n_u) {
+        int nxm = g.nx - 1;
+        int j = f / nxm;
+        int i = f - j * nxm + 1;
+        double idyj = g.idy[j];
+        return g.Dx[i] * idyj * A.idt +
+               hnu * ((g.idx[i] + g.idx[i - 1]) * idyj + g.Dx[i] * (g.iDy[j + 1] + g.iDy[j]) * idyj * idyj);
+    }
+    int r = f - g.n_u;
+    int j = r / g.nx + 1;
+    int i = r - (j - 1) * g.nx;
+    double idxi = g.idx[i];
+    return g.Dy[j] * idxi * A.idt +
+           hnu * (g.Dy[j] * (g.iDx[i + 1] + g.iDx[i]) * idxi * idxi + (g.idy[j] + g.idy[j - 1]) * idxi);
 }
 
 template <class T>
@@ -144,8 +266,8 @@ __device__ __forceinline__ T k0_diag(const K0T<T> &K, int row) {
     if (row < g.n_cell) {
         int j = row / g.nx;
         int i = row - j * g.nx;
-        T bw = i > 0 ? K.dt * g.dy[j] * g.iDx[i] : T(0);
-        T be = i < g.nx - 1 ? K.dt * g.dy[j] * g.iDx[i + 1] : T(0);
+        T bw = i > 0 ? K.dt * g.iDx[i] * g.dy[j] : T(0);
+        T be = i < g.nx - 1 ? K.dt * g.iDx[i + 1] * g.dy[j] : T(0);
         T bs = j > 0 ? K.dt * g.dx[i] * g.iDy[j] : T(0);
         T bn = j < g.ny - 1 ? K.dt * g.dx[i] * g.iDy[j + 1] : T(0);
         return ((bw + be) + bs) + bn;
@@ -153,112 +275,178 @@ __device__ __forceinline__ T k0_diag(const K0T<T> &K, int row) {
     return K.kf_diag[row - g.n_cell];
 }
 
-// Row f of A = Mf/dt - (nu/2) M Lhat R^{-1} on interior faces (wall
-// neighbours contribute through the right-hand side).
-template <class X>
-__device__ __forceinline__ double a_row(const AView &A, int f, X x, double &diag) {
-    const GridView &g = A.g;
-    if (f < g.n_u) {
-        int nxm = g.nx - 1;
-        int j = f / nxm;
-        int i = f - j * nxm + 1;
-        double idyj = g.idy[j];
-        double u = x(f) * idyj;
-        double uE = i < g.nx - 1 ? x(f + 1) * idyj : 0.0;
-        double uW = i > 1 ? x(f - 1) * idyj : 0.0;
-        double uN = j < g.ny - 1 ? x(f + nxm) * g.idy[j + 1] : 0.0;
-        double uS = j > 0 ? x(f - nxm) * g.idy[j - 1] : 0.0;
-        double lapx = ((uE - u) * g.idx[i] - (u - uW) * g.idx[i - 1]) * g.iDx[i];
-        double lapy = ((uN - u) * g.iDy[j + 1] - (u - uS) * g.iDy[j]) * idyj;
-        double mf = g.Dx[i] * idyj;
-        diag = mf * A.idt + 0.5 * A.nu * ((g.idx[i] + g.idx[i - 1]) * idyj +
-                                          g.Dx[i] * (g.iDy[j + 1] + g.iDy[j]) * idyj * idyj);
-        return mf * A.idt * x(f) - 0.5 * A.nu * (g.Dx[i] * (lapx + lapy));
-    }
-    int r = f - g.n_u;
-    int j = r / g.nx + 1;
-    int i = r - (j - 1) * g.nx;
-    double idxi = g.idx[i];
-    double v = x(f) * idxi;
-    double vE = i < g.nx - 1 ? x(f + 1) * g.idx[i + 1] : 0.0;
-    double vW = i > 0 ? x(f - 1) * g.idx[i - 1] : 0.0;
-    double vN = j < g.ny - 1 ? x(f + g.nx) * idxi : 0.0;
-    double vS = j > 1 ? x(f - g.nx) * idxi : 0.0;
-    double lapx = ((vE - v) * g.iDx[i + 1] - (v - vW) * g.iDx[i]) * idxi;
-    double lapy = ((vN - v) * g.idy[j] - (v - vS) * g.idy[j - 1]) * g.iDy[j];
-    double mf = g.Dy[j] * idxi;
-    diag = mf * A.idt + 0.5 * A.nu * (g.Dy[j] * (g.iDx[i + 1] + g.iDx[i]) * idxi * idxi +
-                                      (g.idy[j] + g.idy[j - 1]) * idxi);
-    return mf * A.idt * x(f) - 0.5 * A.nu * (g.Dy[j] * (lapx + lapy));
-}
-
-__device__ __forceinline__ double a_diag(const AView &A, int f) {
-    double d;
-    a_row(A, f, [](int) { return 0.0; }, d);
-    return d;
-}
-
-// overloads so the Krylov kernels can be written once
-template <class T, class X>
-__device__ __forceinline__ T op_row(const K0T<T> &K, int r, X x, T &d) {
-    return k0_row(K, r, x, d);
-}
-template <class X>
-__device__ __forceinline__ double op_row(const AView &A, int r, X x, double &d) {
-    return a_row(A, r, x, d);
-}
+// walker dispatch over the operator type
+template <int R, class T, class XV, class ACT>
+__device__ __forceinline__ void op_walk(const K0T<T> &K, XV xv, ACT act) { k0_walk<R>(K, xv, act); }
+template <int R, class XV, class ACT>
+__device__ __forceinline__ void op_walk(const AView &A, XV xv, ACT act) { a_walk<R>(A, xv, act); }
 template <class T>
 __device__ __forceinline__ T op_diag(const K0T<T> &K, int r) { return k0_diag(K, r); }
 __device__ __forceinline__ double op_diag(const AView &A, int r) { return a_diag(A, r); }
 template <class T>
 __host__ __device__ inline int op_n(const K0T<T> &K) { return K.n; }
 __host__ __device__ inline int op_n(const AView &A) { return A.g.n_q; }
+template <int R, class T>
+inline dim3 op_grid(const K0T<T> &K) { return k0_grid<R>(K); }
+template <int R>
+inline dim3 op_grid(const AView &A) { return a_grid<R>(A); }
+
+__device__ __forceinline__ int block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
+
+// Per-block partials at the linear block index (the 2-D grids)
+template <int N>
+__device__ __forceinline__ void write_parts2(double (&v)[N], double *parts) {
+    block_sum<N>(v);
+    if (threadIdx.x == 0) {
+        const int b = block_linear();
+#pragma unroll
+        for (int k = 0; k < N; ++k) parts[k * kMaxParts + b] = v[k];
+    }
+}
 
 // ---------------------------------------------------------------------------
-// Krylov kernels
+// Krylov kernels on the level-0 operators (vectors of T; dots in FP64)
 
+// r = b - op x; z = D^{-1} r for Jacobi; sums bb, rr, rz
+template <int R, class Op, class T>
+__global__ __launch_bounds__(kBlock) void k_pcg_init(Op op, const T *b, const T *x, T *r, T *z,
+                                                     double *parts, int jacobi) {
+    double v[3] = {0.0, 0.0, 0.0};
+    op_walk<R>(op, [&](int c) { return x[c]; }, [&](int row, T ax, T d, T) {
+        T bi = b[row];
+        T ri = bi - ax;
+        r[row] = ri;
+        v[0] += (double)bi * (double)bi;
+        v[1] += (double)ri * (double)ri;
+        if (jacobi) {
+            T zi = ri / d;
+            z[row] = zi;
+            v[2] += (double)ri * (double)zi;
+        }
+    });
+    write_parts2<3>(v, parts);
+}
+
+// p_new = z + beta p_old, q = op p_new, pq = p_new . q
+template <int R, class Op, class T>
+__global__ __launch_bounds__(kBlock) void k_pcg_spmv(Op op, const T *z, const T *pold, T *pnew,
+                                                     T *q, SolveStatus *st, double *parts) {
+    if (st->done) return;
+    const T beta = (T)st->beta;
+    double v[1] = {0.0};
+    op_walk<R>(op, [&](int c) { return z[c] + beta * pold[c]; }, [&](int row, T qi, T, T) {
+        T pi = z[row] + beta * pold[row];
+        pnew[row] = pi;
+        q[row] = qi;
+        v[0] += (double)pi * (double)qi;
+    });
+    write_parts2<1>(v, parts);
+}
+
+// sum (b - op x)^2
+template <int R, class Op, class T>
+__global__ __launch_bounds__(kBlock) void k_true_residual(Op op, const T *b, const T *x,
+                                                          double *parts) {
+    double v[1] = {0.0};
+    op_walk<R>(op, [&](int c) { return x[c]; }, [&](int row, T ax, T, T) {
+        T ri = b[row] - ax;
+        v[0] += (double)ri * (double)ri;
+    });
+    write_parts2<1>(v, parts);
+}
+
+template <int R, class Op, class T>
+__global__ __launch_bounds__(kBlock) void k_apply(Op op, const T *x, T *y) {
+    op_walk<R>(op, [&](int c) { return x[c]; }, [&](int row, T ax, T, T) { y[row] = ax; });
+}
+
+// x += alpha p, r -= alpha q (z = D^{-1} r for Jacobi); sums rr, rz
 template <class Op, class T>
-__global__ __launch_bounds__(kBlock) void k_pcg_init(Op op, const T *b, const T *x, T *r,
-                                                     SolveStatus *st, double *parts, int jacobi,
-                                                     double rtol2, int maxit) {
+__global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *x, T *r, T *z, const T *p,
+                                                       const T *q, SolveStatus *st, double *parts,
+                                                       int jacobi) {
+    if (st->done) return;
     const int n = op_n(op);
+    const T alpha = (T)(st->rz / st->pq);
     Tiles Tl = my_tiles(n);
-    double v[3] = {0.0, 0.0, 0.0};   // bb, rr, rz
+    double v[2] = {0.0, 0.0};
     for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < n) {
-            T d;
-            T ax = op_row(op, row, [&](int c) { return x[c]; }, d);
-            T bi = b[row];
-            T ri = bi - ax;
+            x[row] += alpha * p[row];
+            T ri = r[row] - alpha * q[row];
             r[row] = ri;
-            v[0] += (double)bi * (double)bi;
-            v[1] += (double)ri * (double)ri;
-            if (jacobi) v[2] += (double)ri * (double)ri / (double)d;
+            v[0] += (double)ri * (double)ri;
+            if (jacobi) {
+                T zi = ri / op_diag(op, row);
+                z[row] = zi;
+                v[1] += (double)ri * (double)zi;
+            }
         }
     }
-    double tot[3];
-    if (grid_sum<3>(v, parts, st, tot) && threadIdx.x == 0) {
-        st->bb = tot[0];
-        st->rr = tot[1];
-        st->tol2 = rtol2;
-        st->maxit = maxit;
-        st->iter = 0;
-        st->beta = 0.0;
-        st->first = 1;
-        st->done = ST_RUNNING;
-        if (tot[0] == 0.0) {
-            st->done = ST_ZERO_RHS;
-        } else if (bad(tot[1])) {
-            st->done = ST_NAN;
-        } else if (tot[1] <= rtol2 * tot[0]) {
-            st->done = ST_CONVERGED;
-        }
-        if (jacobi) {
-            st->rz = tot[2];
-            st->first = 0;
-        }
+    write_parts<2>(v, parts);
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle on level 0 (K0)
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi_first(K0T<T> K, T omega, const T *b, T *x,
+                                                            const SolveStatus *st) {
+    if (st->done) return;
+    Tiles Tl = my_tiles(K.n);
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
+        int row = t * kBlock + threadIdx.x;
+        if (row < K.n) x[row] = omega / k0_diag(K, row) * b[row];
     }
+}
+
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi(K0T<T> K, T omega, const T *b, const T *xin,
+                                                      T *xout, const SolveStatus *st) {
+    if (st->done) return;
+    k0_walk<R>(K, [&](int c) { return xin[c]; }, [&](int row, T ax, T d, T xr) {
+        xout[row] = xr + omega / d * (b[row] - ax);
+    });
+}
+
+// last post-smoothing sweep: also forms r . z for the PCG (b is the PCG residual)
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi_rz(K0T<T> K, T omega, const T *b,
+                                                         const T *xin, T *xout, SolveStatus *st,
+                                                         double *parts) {
+    if (st->done) return;
+    double v[1] = {0.0};
+    k0_walk<R>(K, [&](int c) { return xin[c]; }, [&](int row, T ax, T d, T xr) {
+        T bi = b[row];
+        T z = xr + omega / d * (bi - ax);
+        xout[row] = z;
+        v[0] += (double)bi * (double)z;
+    });
+    write_parts2<1>(v, parts);
+}
+
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_k0_residual(K0T<T> K, const T *b, const T *x, T *r,
+                                                        const SolveStatus *st) {
+    if (st->done) return;
+    k0_walk<R>(K, [&](int c) { return x[c]; }, [&](int row, T ax, T, T) { r[row] = b[row] - ax; });
+}
+
+// mixed precision outer loop: r = b - K x in FP64, r32 = (float) r, ||r||^2, ||b||^2
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_outer_residual(K0View K, const double *b,
+                                                           const double *x, float *r32,
+                                                           double *parts) {
+    double v[2] = {0.0, 0.0};
+    k0_walk<R>(K, [&](int c) { return x[c]; }, [&](int row, double ax, double, double) {
+        double bi = b[row];
+        double ri = bi - ax;
+        r32[row] = (float)ri;
+        v[0] += ri * ri;
+        v[1] += bi * bi;
+    });
+    write_parts2<2>(v, parts);
 }
 
 // x = 0, r = b (initial guess zero; used by the inner mixed-precision solve)
@@ -277,97 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init_zero(int n, const T *b, T *
             v[0] += (double)bi * (double)bi;
         }
     }
-    double tot[1];
-    if (grid_sum<1>(v, parts, st, tot) && threadIdx.x == 0) {
-        st->bb = tot[0];
-        st->rr = tot[0];
-        st->tol2 = rtol2;
-        st->maxit = maxit;
-        st->iter = 0;
-        st->beta = 0.0;
-        st->first = 1;
-        st->done = tot[0] == 0.0 ? ST_ZERO_RHS : (bad(tot[0]) ? ST_NAN : ST_RUNNING);
-    }
-}
-
-// p_new = z + beta p_old (z = D^{-1} r for Jacobi), q = op p_new, pq = p_new . q
-template <class Op, class T>
-__global__ __launch_bounds__(kBlock) void k_pcg_spmv(Op op, const T *src, const T *pold, T *pnew,
-                                                     T *q, SolveStatus *st, double *parts,
-                                                     int jacobi) {
-    if (st->done) return;
-    const int n = op_n(op);
-    const T beta = (T)st->beta;
-    Tiles Tl = my_tiles(n);
-    double v[1] = {0.0};
-    auto pval = [&](int c) {
-        T z = jacobi ? src[c] / op_diag(op, c) : src[c];
-        return z + beta * pold[c];
-    };
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < n) {
-            T d;
-            T qi = op_row(op, row, pval, d);
-            T pi = pval(row);
-            pnew[row] = pi;
-            q[row] = qi;
-            v[0] += (double)pi * (double)qi;
-        }
-    }
-    double tot[1];
-    if (grid_sum<1>(v, parts, st, tot) && threadIdx.x == 0) st->pq = tot[0];
-}
-
-// x += alpha p, r -= alpha q; convergence test on ||r||^2
-template <class Op, class T>
-__global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *x, T *r, const T *p, const T *q,
-                                                       SolveStatus *st, double *parts, int jacobi) {
-    if (st->done) return;
-    const int n = op_n(op);
-    const T alpha = (T)(st->rz / st->pq);
-    Tiles Tl = my_tiles(n);
-    double v[2] = {0.0, 0.0};
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < n) {
-            x[row] += alpha * p[row];
-            T ri = r[row] - alpha * q[row];
-            r[row] = ri;
-            v[0] += (double)ri * (double)ri;
-            if (jacobi) v[1] += (double)ri * (double)ri / (double)op_diag(op, row);
-        }
-    }
-    double tot[2];
-    if (grid_sum<2>(v, parts, st, tot) && threadIdx.x == 0) {
-        st->rr = tot[0];
-        st->iter += 1;
-        if (bad(tot[0])) st->done = ST_NAN;
-        else if (tot[0] <= st->tol2 * st->bb) st->done = ST_CONVERGED;
-        else if (st->iter >= st->maxit) st->done = ST_MAXIT;
-        if (jacobi) {
-            st->beta = tot[1] / st->rz;
-            st->rz = tot[1];
-        }
-    }
-}
-
-template <class Op, class T>
-__global__ __launch_bounds__(kBlock) void k_true_residual(Op op, const T *b, const T *x,
-                                                          SolveStatus *st, double *parts) {
-    const int n = op_n(op);
-    Tiles Tl = my_tiles(n);
-    double v[1] = {0.0};
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < n) {
-            T d;
-            T ri = b[row] - op_row(op, row, [&](int c) { return x[c]; }, d);
-            v[0] += (double)ri * (double)ri;
-        }
-    }
-    double tot[1];
-    if (grid_sum<1>(v, parts, st, tot) && threadIdx.x == 0) st->true_rr = tot[0];
+    write_parts<1>(v, parts);
 }
 
 template <class T>
@@ -375,19 +473,6 @@ __global__ __launch_bounds__(kBlock) void k_zero_if_zero_rhs(T *x, int n, const 
     if (st->done != ST_ZERO_RHS) return;
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) x[i] = T(0);
-}
-
-template <class Op, class T>
-__global__ __launch_bounds__(kBlock) void k_apply(Op op, const T *x, T *y) {
-    const int n = op_n(op);
-    Tiles Tl = my_tiles(n);
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < n) {
-            T d;
-            y[row] = op_row(op, row, [&](int c) { return x[c]; }, d);
-        }
-    }
 }
 
 // r . z for the PCG when the preconditioner wrote z directly (one-level AMG)
@@ -401,89 +486,86 @@ __global__ __launch_bounds__(kBlock) void k_dot_rz(int n, const T *r, const T *z
         int row = t * kBlock + threadIdx.x;
         if (row < n) v[0] += (double)r[row] * (double)z[row];
     }
-    double tot[1];
-    if (grid_sum<1>(v, parts, st, tot) && threadIdx.x == 0) {
+    write_parts<1>(v, parts);
+}
+
+// Grid-wide sums of the partials written by the previous kernel (G blocks)
+// and the status update that goes with them.  One block.
+enum : int { FIN_INIT = 0, FIN_INIT_ZERO, FIN_PQ, FIN_UPDATE, FIN_TRUE, FIN_RZ, FIN_OUTER };
+
+__global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const double *parts,
+                                                     SolveStatus *st, int flag, double rtol2,
+                                                     int maxit) {
+    if ((kind == FIN_PQ || kind == FIN_UPDATE || kind == FIN_RZ) && st->done) return;
+    const int N = (kind == FIN_INIT) ? 3 : (kind == FIN_UPDATE || kind == FIN_OUTER) ? 2 : 1;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < G; b += kBlock)
+        for (int k = 0; k < N; ++k) acc[k] += parts[k * kMaxParts + b];
+    block_sum<3>(acc);
+    if (threadIdx.x != 0) return;
+    switch (kind) {
+    case FIN_INIT:   // acc = (bb, rr, rz); flag = jacobi
+        st->bb = acc[0];
+        st->rr = acc[1];
+        st->tol2 = rtol2;
+        st->maxit = maxit;
+        st->iter = 0;
+        st->beta = 0.0;
+        st->first = 1;
+        st->done = ST_RUNNING;
+        if (acc[0] == 0.0) st->done = ST_ZERO_RHS;
+        else if (bad(acc[1])) st->done = ST_NAN;
+        else if (acc[1] <= rtol2 * acc[0]) st->done = ST_CONVERGED;
+        if (flag) {
+            st->rz = acc[2];
+            st->first = 0;
+        }
+        break;
+    case FIN_INIT_ZERO:   // acc = (bb)
+        st->bb = acc[0];
+        st->rr = acc[0];
+        st->tol2 = rtol2;
+        st->maxit = maxit;
+        st->iter = 0;
+        st->beta = 0.0;
+        st->first = 1;
+        st->done = acc[0] == 0.0 ? ST_ZERO_RHS : (bad(acc[0]) ? ST_NAN : ST_RUNNING);
+        break;
+    case FIN_PQ:
+        st->pq = acc[0];
+        break;
+    case FIN_UPDATE:   // acc = (rr, rz); flag = jacobi
+        st->rr = acc[0];
+        st->iter += 1;
+        if (bad(acc[0])) st->done = ST_NAN;
+        else if (acc[0] <= st->tol2 * st->bb) st->done = ST_CONVERGED;
+        else if (st->iter >= st->maxit) st->done = ST_MAXIT;
+        if (flag) {
+            st->beta = acc[1] / st->rz;
+            st->rz = acc[1];
+        }
+        break;
+    case FIN_TRUE:
+        st->true_rr = acc[0];
+        break;
+    case FIN_RZ:
         if (st->first) {
             st->beta = 0.0;
             st->first = 0;
         } else {
-            st->beta = tot[0] / st->rz;
+            st->beta = acc[0] / st->rz;
         }
-        st->rz = tot[0];
-    }
-}
-
-// ---------------------------------------------------------------------------
-// V-cycle on level 0 (K0)
-
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_k0_jacobi_first(K0T<T> K, T omega, const T *b, T *x,
-                                                            const SolveStatus *st) {
-    if (st->done) return;
-    Tiles Tl = my_tiles(K.n);
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < K.n) x[row] = omega / k0_diag(K, row) * b[row];
-    }
-}
-
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_k0_jacobi(K0T<T> K, T omega, const T *b, const T *xin,
-                                                      T *xout, const SolveStatus *st) {
-    if (st->done) return;
-    Tiles Tl = my_tiles(K.n);
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < K.n) {
-            T d;
-            T ax = k0_row(K, row, [&](int c) { return xin[c]; }, d);
-            xout[row] = xin[row] + omega / d * (b[row] - ax);
-        }
-    }
-}
-
-// last post-smoothing sweep: also forms r . z for the PCG (b is the PCG residual)
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_k0_jacobi_rz(K0T<T> K, T omega, const T *b,
-                                                         const T *xin, T *xout, SolveStatus *st,
-                                                         double *parts) {
-    if (st->done) return;
-    Tiles Tl = my_tiles(K.n);
-    double v[1] = {0.0};
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < K.n) {
-            T d;
-            T ax = k0_row(K, row, [&](int c) { return xin[c]; }, d);
-            T bi = b[row];
-            T z = xin[row] + omega / d * (bi - ax);
-            xout[row] = z;
-            v[0] += (double)bi * (double)z;
-        }
-    }
-    double tot[1];
-    if (grid_sum<1>(v, parts, st, tot) && threadIdx.x == 0) {
-        if (st->first) {
-            st->beta = 0.0;
-            st->first = 0;
+        st->rz = acc[0];
+        break;
+    case FIN_OUTER:   // acc = (rr, bb); flag = first outer residual
+        st->rr = acc[0];
+        if (flag) {
+            st->bb = acc[1];
+            st->iter = 0;
         } else {
-            st->beta = tot[0] / st->rz;
+            st->iter += 1;
         }
-        st->rz = tot[0];
-    }
-}
-
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_k0_residual(K0T<T> K, const T *b, const T *x, T *r,
-                                                        const SolveStatus *st) {
-    if (st->done) return;
-    Tiles Tl = my_tiles(K.n);
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < K.n) {
-            T d;
-            r[row] = b[row] - k0_row(K, row, [&](int c) { return x[c]; }, d);
-        }
+        break;
     }
 }
 
@@ -567,37 +649,121 @@ __global__ __launch_bounds__(kBlock) void k_dense_solve(int n, const double *inv
 }
 
 // ---------------------------------------------------------------------------
-// mixed precision outer loop (FP64)
+// CSR with a subgroup of L lanes per row: lane k takes entries k, k+L, ...,
+// then a butterfly over the subgroup (fixed order, so deterministic)
 
-// r = b - K x in FP64, r32 = (float) r, ||r||^2 (and ||b||^2 when first)
-__global__ __launch_bounds__(kBlock) void k_outer_residual(K0View K, const double *b,
-                                                           const double *x, float *r32,
-                                                           SolveStatus *st, double *parts,
-                                                           int first) {
-    Tiles Tl = my_tiles(K.n);
-    double v[2] = {0.0, 0.0};
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < K.n) {
-            double d;
-            double bi = b[row];
-            double ri = bi - k0_row(K, row, [&](int c) { return x[c]; }, d);
-            r32[row] = (float)ri;
-            v[0] += ri * ri;
-            v[1] += bi * bi;
-        }
-    }
-    double tot[2];
-    if (grid_sum<2>(v, parts, st, tot) && threadIdx.x == 0) {
-        st->rr = tot[0];
-        if (first) {
-            st->bb = tot[1];
-            st->iter = 0;
-        } else {
-            st->iter += 1;
-        }
-    }
+template <class T, int L>
+__device__ __forceinline__ T csrv_dot(const CSRT<T> &A, int row, const T *x, int lane) {
+    T y = T(0);
+    const int e = A.ptr[row + 1];
+    for (int p = A.ptr[row] + lane; p < e; p += L) y += A.val[p] * x[A.col[p]];
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) y += __shfl_xor(y, off, L);
+    return y;
 }
+
+template <class T, int L>
+__global__ __launch_bounds__(kBlock) void k_csrv_jacobi(CSRT<T> A, const T *wdinv, const T *b,
+                                                        const T *xin, T *xout,
+                                                        const SolveStatus *st) {
+    if (st->done) return;
+    const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    if (row >= A.nrows) return;
+    T ax = csrv_dot<T, L>(A, row, xin, lane);
+    if (lane == 0) xout[row] = xin[row] + wdinv[row] * (b[row] - ax);
+}
+
+template <class T, int L>
+__global__ __launch_bounds__(kBlock) void k_csrv_residual(CSRT<T> A, const T *b, const T *x, T *r,
+                                                          const SolveStatus *st) {
+    if (st->done) return;
+    const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    if (row >= A.nrows) return;
+    T ax = csrv_dot<T, L>(A, row, x, lane);
+    if (lane == 0) r[row] = b[row] - ax;
+}
+
+template <class T, int L>
+__global__ __launch_bounds__(kBlock) void k_csrv_spmv(CSRT<T> A, const T *x, T *y, int add,
+                                                      const SolveStatus *st) {
+    if (st && st->done) return;
+    const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    if (row >= A.nrows) return;
+    T v = csrv_dot<T, L>(A, row, x, lane);
+    if (lane == 0) y[row] = add ? y[row] + v : v;
+}
+
+// ---------------------------------------------------------------------------
+// the small coarse levels, all in one work-group (barriers instead of launches)
+
+template <class T>
+__device__ __forceinline__ T csr_row(const CSRT<T> &A, int row, const T *x) {
+    T y = T(0);
+    for (int p = A.ptr[row]; p < A.ptr[row + 1]; ++p) y += A.val[p] * x[A.col[p]];
+    return y;
+}
+
+template <class T>
+__global__ __launch_bounds__(kCoarseBlock) void k_coarse_cycle(const CoarseLevel<T> *lv, int lc,
+                                                               int L, int pre, int post,
+                                                               const double *inv, int nc,
+                                                               const SolveStatus *st) {
+    if (st->done) return;
+    const int tid = threadIdx.x;
+    T *cur[kMaxLevels];
+    for (int l = lc; l < L - 1; ++l) {
+        const CoarseLevel<T> d = lv[l];
+        T *a = d.xa, *o = d.xb;
+        for (int i = tid; i < d.n; i += kCoarseBlock) a[i] = d.wdinv[i] * d.b[i];
+        __syncthreads();
+        for (int k = 1; k < pre; ++k) {
+            for (int i = tid; i < d.n; i += kCoarseBlock)
+                o[i] = a[i] + d.wdinv[i] * (d.b[i] - csr_row(d.A, i, a));
+            __syncthreads();
+            T *t = a; a = o; o = t;
+        }
+        cur[l] = a;
+        for (int i = tid; i < d.n; i += kCoarseBlock) d.r[i] = d.b[i] - csr_row(d.A, i, a);
+        __syncthreads();
+        T *bn = lv[l + 1].b;
+        for (int i = tid; i < d.R.nrows; i += kCoarseBlock) bn[i] = csr_row(d.R, i, d.r);
+        __syncthreads();
+    }
+    {
+        const CoarseLevel<T> c = lv[L - 1];
+        for (int i = tid; i < nc; i += kCoarseBlock) {
+            double acc = 0.0;
+            for (int k = 0; k < nc; ++k) acc += inv[(size_t)k * nc + i] * (double)c.b[k];
+            c.xa[i] = (T)acc;
+        }
+        __syncthreads();
+        cur[L - 1] = c.xa;
+    }
+    for (int l = L - 2; l >= lc; --l) {
+        const CoarseLevel<T> d = lv[l];
+        T *a = cur[l];
+        T *o = (a == d.xa) ? d.xb : d.xa;
+        const T *xc = cur[l + 1];
+        for (int i = tid; i < d.n; i += kCoarseBlock) a[i] += csr_row(d.P, i, xc);
+        __syncthreads();
+        for (int k = 0; k < post; ++k) {
+            for (int i = tid; i < d.n; i += kCoarseBlock)
+                o[i] = a[i] + d.wdinv[i] * (d.b[i] - csr_row(d.A, i, a));
+            __syncthreads();
+            T *t = a; a = o; o = t;
+        }
+        cur[l] = a;
+    }
+    const CoarseLevel<T> d = lv[lc];
+    if (cur[lc] != d.xa)
+        for (int i = tid; i < d.n; i += kCoarseBlock) d.xa[i] = cur[lc][i];
+}
+
+// ---------------------------------------------------------------------------
+// mixed precision: x += d
 
 __global__ __launch_bounds__(kBlock) void k_add_correction(int n, double *x, const float *d) {
     int i = blockIdx.x * kBlock + threadIdx.x;
@@ -889,47 +1055,96 @@ void launch_fill_walls(hipStream_t s, GridView g, double *w, double U, double V)
     LAUNCH(k_fill_walls, 1, g, w, U, V);
 }
 
+
+// walk depth: the smallest R in {1, 2, 4, 8, 16} that keeps the grid within
+// 4096 blocks (the partial-sum buffer holds kMaxParts = 8192)
+template <class Op>
+static int pick_R(const Op &op) {
+    for (int R : {1, 2, 4, 8}) {
+        dim3 gd = R == 1 ? op_grid<1>(op) : R == 2 ? op_grid<2>(op) : R == 4 ? op_grid<4>(op) : op_grid<8>(op);
+        if ((long)gd.x * gd.y <= 4096) return R;
+    }
+    dim3 gd = op_grid<16>(op);
+    if ((long)gd.x * gd.y > kMaxParts) throw std::runtime_error("grid too large for the reduction buffer");
+    return 16;
+}
+
+#define WALK_SWITCH(R, BODY)                                   \
+    switch (R) {                                               \
+    case 1: { constexpr int RR = 1; BODY; } break;             \
+    case 2: { constexpr int RR = 2; BODY; } break;             \
+    case 4: { constexpr int RR = 4; BODY; } break;             \
+    case 8: { constexpr int RR = 8; BODY; } break;             \
+    default: { constexpr int RR = 16; BODY; } break;           \
+    }
+
+#define LAUNCH2(kernel, grid, ...) hipLaunchKernelGGL(kernel, grid, dim3(kBlock), 0, s, __VA_ARGS__)
+
 void launch_apply_K0(hipStream_t s, const K0View &K, const double *x, double *y) {
-    LAUNCH((k_apply<K0View, double>), grid_for(K.n), K, x, y);
+    WALK_SWITCH(pick_R(K), LAUNCH2((k_apply<RR, K0View, double>), op_grid<RR>(K), K, x, y))
 }
 
 void launch_apply_A(hipStream_t s, const AView &A, const double *x, double *y) {
-    LAUNCH((k_apply<AView, double>), grid_for(A.g.n_q), A, x, y);
+    WALK_SWITCH(pick_R(A), LAUNCH2((k_apply<RR, AView, double>), op_grid<RR>(A), A, x, y))
 }
 
 template <class Op, class T>
-void launch_pcg_init(hipStream_t s, const Op &op, const T *b, const T *x, T *r, SolveStatus *st,
-                     double *parts, bool jacobi, double rtol2, int maxit) {
-    LAUNCH((k_pcg_init<Op, T>), grid_for(op_n(op)), op, b, x, r, st, parts, (int)jacobi, rtol2, maxit);
+void launch_pcg_init(hipStream_t s, const Op &op, const T *b, const T *x, T *r, T *z,
+                     SolveStatus *st, double *parts, bool jacobi, double rtol2, int maxit) {
+    int G = 0;
+    WALK_SWITCH(pick_R(op), {
+        dim3 gd = op_grid<RR>(op);
+        G = gd.x * gd.y;
+        LAUNCH2((k_pcg_init<RR, Op, T>), gd, op, b, x, r, z, parts, (int)jacobi);
+    })
+    LAUNCH(k_finalize, 1, (int)FIN_INIT, G, parts, st, (int)jacobi, rtol2, maxit);
 }
 
 template <class T>
 void launch_pcg_init_zero(hipStream_t s, int n, const T *b, T *x, T *r, SolveStatus *st,
                           double *parts, double rtol2, int maxit) {
-    LAUNCH((k_pcg_init_zero<T>), grid_for(n), n, b, x, r, st, parts, rtol2, maxit);
+    int G = grid_for(n);
+    LAUNCH((k_pcg_init_zero<T>), G, n, b, x, r, st, parts, rtol2, maxit);
+    LAUNCH(k_finalize, 1, (int)FIN_INIT_ZERO, G, parts, st, 0, rtol2, maxit);
 }
 
 template <class Op, class T>
-void launch_pcg_spmv(hipStream_t s, const Op &op, const T *src, const T *pold, T *pnew, T *q,
-                     SolveStatus *st, double *parts, bool jacobi) {
-    LAUNCH((k_pcg_spmv<Op, T>), grid_for(op_n(op)), op, src, pold, pnew, q, st, parts, (int)jacobi);
+void launch_pcg_spmv(hipStream_t s, const Op &op, const T *z, const T *pold, T *pnew, T *q,
+                     SolveStatus *st, double *parts) {
+    int G = 0;
+    WALK_SWITCH(pick_R(op), {
+        dim3 gd = op_grid<RR>(op);
+        G = gd.x * gd.y;
+        LAUNCH2((k_pcg_spmv<RR, Op, T>), gd, op, z, pold, pnew, q, st, parts);
+    })
+    LAUNCH(k_finalize, 1, (int)FIN_PQ, G, parts, st, 0, 0.0, 0);
 }
 
 template <class Op, class T>
-void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, const T *p, const T *q,
+void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, T *z, const T *p, const T *q,
                        SolveStatus *st, double *parts, bool jacobi) {
-    LAUNCH((k_pcg_update<Op, T>), grid_for(op_n(op)), op, x, r, p, q, st, parts, (int)jacobi);
+    int G = grid_for(op_n(op));
+    LAUNCH((k_pcg_update<Op, T>), G, op, x, r, z, p, q, st, parts, (int)jacobi);
+    LAUNCH(k_finalize, 1, (int)FIN_UPDATE, G, parts, st, (int)jacobi, 0.0, 0);
 }
 
 template <class Op, class T>
 void launch_true_residual(hipStream_t s, const Op &op, const T *b, const T *x, SolveStatus *st,
                           double *parts) {
-    LAUNCH((k_true_residual<Op, T>), grid_for(op_n(op)), op, b, x, st, parts);
+    int G = 0;
+    WALK_SWITCH(pick_R(op), {
+        dim3 gd = op_grid<RR>(op);
+        G = gd.x * gd.y;
+        LAUNCH2((k_true_residual<RR, Op, T>), gd, op, b, x, parts);
+    })
+    LAUNCH(k_finalize, 1, (int)FIN_TRUE, G, parts, st, 0, 0.0, 0);
 }
 
 template <class T>
 void launch_dot_rz(hipStream_t s, int n, const T *r, const T *z, SolveStatus *st, double *parts) {
-    LAUNCH((k_dot_rz<T>), grid_for(n), n, r, z, st, parts);
+    int G = grid_for(n);
+    LAUNCH((k_dot_rz<T>), G, n, r, z, st, parts);
+    LAUNCH(k_finalize, 1, (int)FIN_RZ, G, parts, st, 0, 0.0, 0);
 }
 
 template <class T>
@@ -946,19 +1161,25 @@ void launch_k0_jacobi_first(hipStream_t s, const K0T<T> &K, double omega, const 
 template <class T>
 void launch_k0_jacobi(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
                       T *xout, const SolveStatus *st) {
-    LAUNCH((k_k0_jacobi<T>), grid_for(K.n), K, (T)omega, b, xin, xout, st);
+    WALK_SWITCH(pick_R(K), LAUNCH2((k_k0_jacobi<RR, T>), op_grid<RR>(K), K, (T)omega, b, xin, xout, st))
 }
 
 template <class T>
 void launch_k0_jacobi_rz(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
                          T *xout, SolveStatus *st, double *parts) {
-    LAUNCH((k_k0_jacobi_rz<T>), grid_for(K.n), K, (T)omega, b, xin, xout, st, parts);
+    int G = 0;
+    WALK_SWITCH(pick_R(K), {
+        dim3 gd = op_grid<RR>(K);
+        G = gd.x * gd.y;
+        LAUNCH2((k_k0_jacobi_rz<RR, T>), gd, K, (T)omega, b, xin, xout, st, parts);
+    })
+    LAUNCH(k_finalize, 1, (int)FIN_RZ, G, parts, st, 0, 0.0, 0);
 }
 
 template <class T>
 void launch_k0_residual(hipStream_t s, const K0T<T> &K, const T *b, const T *x, T *r,
                         const SolveStatus *st) {
-    LAUNCH((k_k0_residual<T>), grid_for(K.n), K, b, x, r, st);
+    WALK_SWITCH(pick_R(K), LAUNCH2((k_k0_residual<RR, T>), op_grid<RR>(K), K, b, x, r, st))
 }
 
 template <class T>
@@ -995,9 +1216,68 @@ void launch_dense_solve(hipStream_t s, int n, const double *inv, const T *b, T *
     LAUNCH((k_dense_solve<T>), (n + kBlock - 1) / kBlock, n, inv, b, x, st);
 }
 
+template <class T, int L>
+static void csrv_dispatch_jacobi(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b,
+                                 const T *xin, T *xout, const SolveStatus *st) {
+    int nb = (A.nrows + kBlock / L - 1) / (kBlock / L);
+    LAUNCH((k_csrv_jacobi<T, L>), nb > 0 ? nb : 1, A, wdinv, b, xin, xout, st);
+}
+template <class T, int L>
+static void csrv_dispatch_residual(hipStream_t s, CSRT<T> A, const T *b, const T *x, T *r,
+                                   const SolveStatus *st) {
+    int nb = (A.nrows + kBlock / L - 1) / (kBlock / L);
+    LAUNCH((k_csrv_residual<T, L>), nb > 0 ? nb : 1, A, b, x, r, st);
+}
+template <class T, int L>
+static void csrv_dispatch_spmv(hipStream_t s, CSRT<T> A, const T *x, T *y, int add,
+                               const SolveStatus *st) {
+    int nb = (A.nrows + kBlock / L - 1) / (kBlock / L);
+    LAUNCH((k_csrv_spmv<T, L>), nb > 0 ? nb : 1, A, x, y, add, st);
+}
+
+#define CSRV_SWITCH(FN, ...)                              \
+    switch (lanes) {                                      \
+    case 1: FN<T, 1>(s, __VA_ARGS__); break;              \
+    case 2: FN<T, 2>(s, __VA_ARGS__); break;              \
+    case 4: FN<T, 4>(s, __VA_ARGS__); break;              \
+    case 8: FN<T, 8>(s, __VA_ARGS__); break;              \
+    case 16: FN<T, 16>(s, __VA_ARGS__); break;            \
+    case 32: FN<T, 32>(s, __VA_ARGS__); break;            \
+    default: FN<T, 64>(s, __VA_ARGS__); break;            \
+    }
+
+template <class T>
+void launch_csrv_jacobi(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b,
+                        const T *xin, T *xout, const SolveStatus *st) {
+    CSRV_SWITCH(csrv_dispatch_jacobi, A, wdinv, b, xin, xout, st)
+}
+template <class T>
+void launch_csrv_residual(hipStream_t s, CSRT<T> A, int lanes, const T *b, const T *x, T *r,
+                          const SolveStatus *st) {
+    CSRV_SWITCH(csrv_dispatch_residual, A, b, x, r, st)
+}
+template <class T>
+void launch_csrv_spmv(hipStream_t s, CSRT<T> A, int lanes, const T *x, T *y, bool add,
+                      const SolveStatus *st) {
+    CSRV_SWITCH(csrv_dispatch_spmv, A, x, y, (int)add, st)
+}
+
+template <class T>
+void launch_coarse_cycle(hipStream_t s, const CoarseLevel<T> *lv_dev, int lc, int L, int pre,
+                         int post, const double *inv, int n_coarse, const SolveStatus *st) {
+    hipLaunchKernelGGL((k_coarse_cycle<T>), dim3(1), dim3(kCoarseBlock), 0, s, lv_dev, lc, L, pre,
+                       post, inv, n_coarse, st);
+}
+
 void launch_outer_residual(hipStream_t s, const K0View &K, const double *b, const double *x,
                            float *r32, SolveStatus *st, double *parts, int first) {
-    LAUNCH(k_outer_residual, grid_for(K.n), K, b, x, r32, st, parts, first);
+    int G = 0;
+    WALK_SWITCH(pick_R(K), {
+        dim3 gd = op_grid<RR>(K);
+        G = gd.x * gd.y;
+        LAUNCH2((k_outer_residual<RR>), gd, K, b, x, r32, parts);
+    })
+    LAUNCH(k_finalize, 1, (int)FIN_OUTER, G, parts, st, first, 0.0, 0);
 }
 
 void launch_add_correction(hipStream_t s, int n, double *x, const float *d) {
@@ -1006,11 +1286,11 @@ void launch_add_correction(hipStream_t s, int n, double *x, const float *d) {
 
 // explicit instantiations
 #define INST_OP(OP, T)                                                                           \
-    template void launch_pcg_init<OP, T>(hipStream_t, const OP &, const T *, const T *, T *,     \
+    template void launch_pcg_init<OP, T>(hipStream_t, const OP &, const T *, const T *, T *, T *,\
                                          SolveStatus *, double *, bool, double, int);            \
     template void launch_pcg_spmv<OP, T>(hipStream_t, const OP &, const T *, const T *, T *, T *, \
-                                         SolveStatus *, double *, bool);                         \
-    template void launch_pcg_update<OP, T>(hipStream_t, const OP &, T *, T *, const T *,         \
+                                         SolveStatus *, double *);                               \
+    template void launch_pcg_update<OP, T>(hipStream_t, const OP &, T *, T *, T *, const T *,    \
                                            const T *, SolveStatus *, double *, bool);            \
     template void launch_true_residual<OP, T>(hipStream_t, const OP &, const T *, const T *,     \
                                               SolveStatus *, double *);
@@ -1045,5 +1325,17 @@ INST_OP(K0T<float>, float)
                                         const SolveStatus *);
 INST_T(double)
 INST_T(float)
+
+#define INST_V(T)                                                                                \
+    template void launch_csrv_jacobi<T>(hipStream_t, CSRT<T>, int, const T *, const T *,         \
+                                        const T *, T *, const SolveStatus *);                    \
+    template void launch_csrv_residual<T>(hipStream_t, CSRT<T>, int, const T *, const T *, T *,  \
+                                          const SolveStatus *);                                  \
+    template void launch_csrv_spmv<T>(hipStream_t, CSRT<T>, int, const T *, T *, bool,           \
+                                      const SolveStatus *);                                      \
+    template void launch_coarse_cycle<T>(hipStream_t, const CoarseLevel<T> *, int, int, int, int, \
+                                         const double *, int, const SolveStatus *);
+INST_V(double)
+INST_V(float)
 
 }  // namespace ibpm

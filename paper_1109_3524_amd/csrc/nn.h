@@ -1,0 +1,78 @@
+// Residual-to-correction network: 3x3 convolutions on the cell grid with
+// BF16 operands and FP32 accumulation on the gfx950 matrix cores.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace ibpm {
+
+using bf16 = __hip_bfloat16;
+
+constexpr int kNNLayers = 6;
+constexpr int kNNWidth = 32;        // hidden channels (and padded output channels)
+constexpr int kNNIn = 5;            // input channels (padded to 8)
+constexpr int kNNInPad = 8;
+constexpr int kNNOut = 3;           // output channels (padded to 32)
+constexpr int kConvTile = 128;      // pixels of one image row per block (4 waves x 32)
+
+// K of the implicit GEMM padded to the MFMA step (16)
+__host__ __device__ constexpr int conv_kp(int cin) { return ((9 * cin + 15) / 16) * 16; }
+
+// Cell-centre delta weights between Lagrangian points and cells (for the
+// force channels): both directions as CSR (cells of the box -> points and
+// points -> cells), weights phi((xc - xi)/h) phi((yc - eta)/h).
+struct CellDelta {
+    int i0, i1, j0, j1;         // box of cells
+    CSRView c2p;                // box cell -> (point, weight)
+    CSRView p2c;                // point -> (cell index, weight)
+};
+
+// One 3x3 convolution layer: Y = conv(X, W) on an H x W image, HWC layout.
+//   X      input, CIN channels (8 or 32), BF16 (TIn = bf16) or FP32 (TIn = float)
+//   mask   optional BF16 [H][W][CIN]; where mask <= 0 the input is read as 0
+//          (the ReLU derivative in the backward pass)
+//   Wp     packed weights [32][conv_kp(CIN)] BF16 (out channel major, k = tap*CIN + c)
+//   Y32    optional FP32 [H][W][32] pre-activation output
+//   Y16    optional BF16 [H][W][32] output after ReLU (relu != 0) or as is
+template <class TIn, int CIN>
+void launch_conv3x3(hipStream_t s, int H, int W, const TIn *X, const bf16 *mask, const bf16 *Wp,
+                    float *Y32, bf16 *Y16, int relu);
+
+// Weight gradient of one layer for one image: per-block partials
+// [blocks][32][kp] of dW[n][k] = sum_p dY[p][n] X[p + tap][c]; dY is FP32
+// [H][W][32] masked by `mask` (BF16 [H][W][32], > 0 keeps) when given.
+template <int CIN>
+void launch_conv3x3_dw(hipStream_t s, int H, int W, const bf16 *X, const float *dY,
+                       const bf16 *mask, float *partials);
+int conv_dw_blocks(int H, int W);
+// grad[n][k] += sum over blocks of partials (fixed order)
+void launch_dw_reduce(hipStream_t s, int blocks, int nk, const float *partials, float *grad);
+
+// Master FP32 weights [32][kp] -> BF16 packed forward weights and the
+// flipped / transposed weights used by the input-gradient convolution.
+void launch_pack_weights(hipStream_t s, int cin, int cout, const float *master, bf16 *fwd,
+                         bf16 *bwd);
+
+// Adam step on n FP32 parameters (bias-corrected, step t >= 1)
+void launch_adam(hipStream_t s, int n, float *w, const float *g, float *m, float *v, int t,
+                 float lr, float beta1, float beta2, float eps);
+
+// features: residual r (lambda layout, FP64) scaled by 1/scale -> X [H][W][8] BF16
+//   ch0 pressure residual, ch1/ch2 force residuals spread to cell centres,
+//   ch3/ch4 log of the cell widths over the finest width, ch5-7 zero
+void launch_nn_features(hipStream_t s, GridView g, int nb, const double *r, const double *scale,
+                        double inv_hmin, CellDelta cd, bf16 *X);
+// network output Y32 [H][W][32] -> correction e (lambda layout, FP64) times
+// scale/dt: pressure from channel 0, forces interpolated from channels 1, 2
+void launch_nn_output(hipStream_t s, int n_cell, int nb, const float *Y32, const double *scale,
+                      double inv_dt, CellDelta cd, double *e);
+// training loss (normalised squared error per part, pressure and force) of
+// Y32 against the target t (lambda layout, FP32, already scaled) and dL/dY32
+void launch_nn_loss(hipStream_t s, int n_cell, int nb, const float *Y32, const float *t,
+                    CellDelta cd, float *dY, double *parts, SolveStatus *st);
+
+}  // namespace ibpm

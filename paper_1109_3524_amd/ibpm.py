@@ -39,7 +39,7 @@ EXPORTED = (
 )
 
 KERNELS = {"k0_jacobi": 0, "k0_pcg_spmv": 1, "a_pcg_spmv": 2, "k0_residual": 3,
-           "restrict0": 4, "prolong0": 5, "pcg_update_k": 6}
+           "restrict0": 4, "prolong0": 5, "pcg_update_k": 6, "coarse_cycle": 7}
 
 
 class IBPMError(RuntimeError):
@@ -68,7 +68,8 @@ class Params(ctypes.Structure):
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("relres", ctypes.c_double), ("ms", ctypes.c_double)]
+                ("relres", ctypes.c_double), ("ms", ctypes.c_double),
+                ("outer_iters", ctypes.c_int32), ("fallbacks", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

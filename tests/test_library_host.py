@@ -61,6 +61,7 @@ def _params(wl, **over):
     (dict(vel_maxit=0), "maxit"),
     (dict(nu=-1.0), "positive"),
     (dict(poisson_solver=7), "solver"),
+    (dict(poisson_solver=2, amg_pre=0), "sweep"),
 ])
 def test_invalid_parameters_are_rejected_on_the_host(over, msg):
     L = ibpm.load()
