@@ -55,7 +55,7 @@ extern "C" {
 #define IBPM_SOLVER_JACOBI_PCG       0
 #define IBPM_SOLVER_AMG_PCG          1
 #define IBPM_SOLVER_AMG_PCG_MIXED    2   /* FP32 inner AMG-PCG inside FP64 iterative refinement */
-#define IBPM_SOLVER_AMG_FCG_LEARNED  3   /* reserved: flexible CG with a learned stage */
+#define IBPM_SOLVER_AMG_FCG_LEARNED  3   /* flexible CG, AMG V-cycle plus a learned stage */
 
 typedef struct ibpm_ctx ibpm_ctx;
 
@@ -206,6 +206,67 @@ int ibpm_get_aggregates(const ibpm_ctx *ctx, int32_t level, int32_t *agg);
  * (not the caller's).  Needs an AMG context for kernels 0, 3, 4, 5, 7. */
 int ibpm_time_kernel(ibpm_ctx *ctx, int32_t kernel, int32_t reps, double *avg_ms,
                      double *bytes);
+
+/* ------------------------------------------------------------------------
+ * Learned preconditioner stage (an addition to the paper's method).
+ * A network of six 3x3 convolutions on the cell grid (input 5 channels:
+ * pressure residual, the two force residuals spread to cell centres with the
+ * delta of Eq. 6, log of the two cell widths over the finest width; 32
+ * hidden channels with ReLU; 3 output channels: pressure correction and two
+ * force fields interpolated back to the points), no biases, zero padding,
+ * BF16 operands and FP32 accumulation.  Its input is scaled by the RMS s of
+ * the residual and its output by s / dt.  Solver IBPM_SOLVER_AMG_FCG_LEARNED
+ * uses it in flexible CG: M(r) = z0 + w N(r - K z0) with z0 the AMG V-cycle
+ * and w = (d . r1) / (d . K d); when the residual stalls (a chunk of >= 8
+ * iterations reducing it by < 5 %) or turns NaN the solve falls back to plain
+ * AMG-PCG from the current iterate (ibpm_solve_stats.fallbacks).
+ * Weights are given per layer as [out][in][3][3] FP32, layers concatenated:
+ * IBPM_NN_PARAMS values in all.  Images are ny x nx x channels (channel
+ * fastest) FP32 device arrays.
+ * ------------------------------------------------------------------------ */
+#define IBPM_NN_PARAMS 39168
+
+/* Allocate the network of this context and draw He-normal weights from a
+ * seeded counter-based generator. */
+int ibpm_nn_init(ibpm_ctx *ctx, uint64_t seed);
+int ibpm_nn_get_weights(ibpm_ctx *ctx, float *host, int64_t n);
+int ibpm_nn_set_weights(ibpm_ctx *ctx, const float *host, int64_t n);
+
+/* One layer on the device, for checking the matrix-core kernels:
+ *   mode 0: out = conv(x, W) (pre-activation, ny x nx x 32; x has 8
+ *           channels for layer 0, 32 otherwise, BF16-representable values)
+ *   mode 1: out = input gradient of conv for the output gradient dy masked
+ *           by mask > 0 (mask optional, ny x nx x 32), ny x nx x 32
+ *   mode 2: out = weight gradient for input x and output gradient dy (masked),
+ *           the layer's [out][in][3][3] FP32 (device) */
+int ibpm_nn_layer(ibpm_ctx *ctx, int32_t layer, int32_t mode, const float *x, const float *dy,
+                  const float *mask, float *out);
+
+/* e = learned correction for the residual r (lambda layout, FP64 device). */
+int ibpm_nn_apply(ibpm_ctx *ctx, const double *r, double *e);
+
+/* One pass of Adam (lr, betas 0.9/0.999) over the samples order[0..norder)
+ * in batches: r1 and e1 hold nsamples (residual after the V-cycle, remaining
+ * error) pairs in lambda layout, FP32 device.  The loss per sample is
+ * |N_phi - t_phi|^2/|t_phi|^2 + |N_f - t_f|^2/|t_f|^2 with t = e1 dt / s;
+ * *mean_loss (host) receives the mean over the pass. */
+int ibpm_nn_train(ibpm_ctx *ctx, const float *r1, const float *e1, int32_t nsamples,
+                  const int32_t *order, int32_t norder, int32_t batch, float lr,
+                  double *mean_loss);
+
+/* Loss of one pair (r1, e1: FP32 device, lambda layout, as for training) in
+ * *loss (host) and its gradient with respect to every weight in grad (host,
+ * IBPM_NN_PARAMS values, layout of ibpm_nn_get_weights); no update. */
+int ibpm_nn_loss_grad(ibpm_ctx *ctx, const float *r1, const float *e1, double *loss,
+                      float *grad);
+
+/* Training pairs from an AMG-PCG solve of K x = rhs started at x (device,
+ * updated): before each of the first npairs iterations it stores
+ * r1 = r - K V(r) and e1 = x* - x - V(r) (FP32, lambda layout, pair k at
+ * offset k * n_lambda), x* being the converged solution given by the caller.
+ * *nout (host) receives the number of pairs (fewer if the solve converged). */
+int ibpm_harvest(ibpm_ctx *ctx, const double *rhs, double *x, const double *xstar,
+                 int32_t npairs, float *r1_out, float *e1_out, int32_t *nout);
 
 #ifdef __cplusplus
 }

@@ -98,6 +98,37 @@ def backward(weights, acts, dout):
     return grads
 
 
+def forward_bf16(weights, x, keep=False):
+    """The network as the library stores it: input, weights and every hidden
+    activation rounded to BF16 (after the ReLU), arithmetic in FP64; the
+    output of the last layer is not rounded."""
+    wq = [bf16_round(W) for W in weights]
+    h = bf16_round(x)
+    acts = [h]
+    for l, W in enumerate(wq):
+        h = conv3x3(h, W)
+        if l < len(wq) - 1:
+            h = bf16_round(np.maximum(h, 0.0))
+        acts.append(h)
+    return (h, acts) if keep else h
+
+
+def backward_bf16(weights, acts, dout):
+    """Gradients for forward_bf16: the gradient reaching each layer is masked
+    by that layer's ReLU and rounded to BF16 before it meets the BF16
+    activations (weight gradient) or the BF16 weights (input gradient)."""
+    wq = [bf16_round(W) for W in weights]
+    grads = [None] * len(wq)
+    g = dout
+    for l in range(len(wq) - 1, -1, -1):
+        if l < len(wq) - 1:
+            g = g * (acts[l + 1] > 0.0)
+        g = bf16_round(g)
+        grads[l] = conv3x3_grad_weight(acts[l], g)
+        g = conv3x3_grad_input(g, wq[l])
+    return grads
+
+
 def nmse_loss(pred, target):
     """Normalised mean squared error sum((p - t)^2) / sum(t^2) and dL/dp."""
     den = float(np.sum(target * target))

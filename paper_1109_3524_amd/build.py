@@ -36,7 +36,7 @@ def build(verbose: bool = True) -> str:
     o = os.path.join(BUILD, "setup.o")
     _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "setup.cpp"), "-o", o])
     objs.append(o)
-    for name in ("kernels.hip", "api.hip"):
+    for name in ("kernels.hip", "nn.hip", "api.hip"):
         o = os.path.join(BUILD, name.replace(".hip", ".o"))
         _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, name), "-o", o])
         objs.append(o)

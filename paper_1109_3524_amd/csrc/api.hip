@@ -14,6 +14,7 @@
 
 #include "../../include/ibpm.h"
 #include "kernels.h"
+#include "nn.h"
 #include "setup.h"
 
 using namespace ibpm;
@@ -74,6 +75,27 @@ struct PrecSet {
     T *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
 };
 
+// The residual-to-correction network (weights, Adam moments, activations)
+struct NNState {
+    bool ready = false, train_ready = false;
+    int H = 0, W = 0;
+    int cin[kNNLayers] = {kNNInPad, 32, 32, 32, 32, 32};
+    int kp[kNNLayers] = {};
+    float *master[kNNLayers] = {}, *grad[kNNLayers] = {}, *m[kNNLayers] = {}, *v[kNNLayers] = {};
+    bf16 *fwd[kNNLayers] = {}, *bwd[kNNLayers] = {};
+    bf16 *act[kNNLayers] = {};        // act[0]: features [H][W][8]; act[l]: output of layer l-1
+    float *y32 = nullptr;             // network output [H][W][32]
+    float *g[2] = {nullptr, nullptr}; // gradients [H][W][32]
+    float *partials = nullptr, *fdiff = nullptr;
+    double *scale = nullptr, *sparts = nullptr, *losses = nullptr;
+    double *d = nullptr, *r1 = nullptr, *z0 = nullptr;   // learned-stage work vectors
+    SolveStatus *st = nullptr;
+    CellDelta cd{};
+    int adam_t = 0;
+    double inv_hmin = 1.0;
+    int max_losses = 0;
+};
+
 }  // namespace
 
 struct ibpm_ctx {
@@ -104,6 +126,8 @@ struct ibpm_ctx {
     double *parts = nullptr;
     SolveStatus *host_st = nullptr;   // pinned
     int est_vel = 8, est_poi = 32, est_inner = 32;
+    bool learned = false;
+    NNState nn;
 
     template <class T>
     T *dalloc(size_t n) {
@@ -189,14 +213,15 @@ int guarded(ibpm_ctx *c, F &&f) {
 // Every kernel is predicated on st->done.
 
 template <class T>
-void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *st) {
+void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *st,
+                    bool with_rz = true) {
     hipStream_t s = c->stream;
     const int pre = c->prm.amg_pre, post = c->prm.amg_post;
     const int L = (int)P.lev.size();
     const K0T<T> &K = P.K0;
     if (L == 1) {
         launch_dense_solve(s, K.n, c->coarse_inv, r, z, st);
-        launch_dot_rz(s, K.n, r, z, st, c->parts);
+        if (with_rz) launch_dot_rz(s, K.n, r, z, st, c->parts);
         return;
     }
     std::vector<T *> cur(L);
@@ -249,7 +274,8 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
             launch_k0_jacobi(s, K, l0.omega, r, (const T *)a, b, st);
             std::swap(a, b);
         }
-        launch_k0_jacobi_rz(s, K, l0.omega, r, (const T *)a, z, st, c->parts);
+        if (with_rz) launch_k0_jacobi_rz(s, K, l0.omega, r, (const T *)a, z, st, c->parts);
+        else launch_k0_jacobi(s, K, l0.omega, r, (const T *)a, z, st);
     }
 }
 
@@ -398,7 +424,340 @@ int solve_poisson_mixed(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_
     return code;
 }
 
+// ---------------------------------------------------------------------------
+// residual-to-correction network
+
+size_t img(const NNState &N, int ch) { return (size_t)N.H * N.W * ch; }
+
+void nn_alloc(ibpm_ctx *c) {
+    NNState &N = c->nn;
+    if (N.ready) return;
+    const Model &m = c->m;
+    N.H = m.g.ny;
+    N.W = m.g.nx;
+    for (int l = 0; l < kNNLayers; ++l) {
+        N.kp[l] = conv_kp(N.cin[l]);
+        size_t np = (size_t)32 * N.kp[l];
+        N.master[l] = c->dalloc<float>(np);
+        N.fwd[l] = c->dalloc<bf16>(np);
+        N.bwd[l] = c->dalloc<bf16>((size_t)32 * conv_kp(32));
+        N.act[l] = c->dalloc<bf16>(img(N, l == 0 ? kNNInPad : 32));
+    }
+    N.y32 = c->dalloc<float>(img(N, 32));
+    N.scale = c->dalloc<double>(2);
+    N.sparts = c->dalloc<double>(1024);
+    const int n = c->p64.K0.n;
+    N.d = c->dalloc<double>(n);
+    N.r1 = c->dalloc<double>(n);
+    N.z0 = c->dalloc<double>(n);
+    N.st = c->dalloc<SolveStatus>(1);
+    HIPCHECK(hipMemsetAsync(N.st, 0, sizeof(SolveStatus), c->stream));
+    DevCSR c2p = c->upload_csr<double>(m.Dc2p), p2c = c->upload_csr<double>(m.Dp2c);
+    N.cd.i0 = m.dc_i0; N.cd.i1 = m.dc_i1; N.cd.j0 = m.dc_j0; N.cd.j1 = m.dc_j1;
+    N.cd.c2p = c2p.view();
+    N.cd.p2c = p2c.view();
+    N.inv_hmin = 1.0 / m.hmin;
+    N.ready = true;
+}
+
+void nn_alloc_training(ibpm_ctx *c) {
+    NNState &N = c->nn;
+    if (N.train_ready) return;
+    for (int l = 0; l < kNNLayers; ++l) {
+        size_t np = (size_t)32 * N.kp[l];
+        N.grad[l] = c->dalloc<float>(np);
+        N.m[l] = c->dalloc<float>(np);
+        N.v[l] = c->dalloc<float>(np);
+        HIPCHECK(hipMemsetAsync(N.m[l], 0, np * sizeof(float), c->stream));
+        HIPCHECK(hipMemsetAsync(N.v[l], 0, np * sizeof(float), c->stream));
+    }
+    N.g[0] = c->dalloc<float>(img(N, 32));
+    N.g[1] = c->dalloc<float>(img(N, 32));
+    N.partials = c->dalloc<float>((size_t)conv_dw_blocks(N.H, N.W) * 32 * conv_kp(32));
+    N.fdiff = c->dalloc<float>(2 * c->m.nb + 1);
+    N.train_ready = true;
+}
+
+void nn_pack(ibpm_ctx *c) {
+    NNState &N = c->nn;
+    for (int l = 0; l < kNNLayers; ++l)
+        launch_pack_weights(c->stream, N.cin[l], 32, N.master[l], N.fwd[l], N.bwd[l]);
+}
+
+// real channel counts of layer l (the stored tensors are padded)
+int nn_cin_real(int l) { return l == 0 ? kNNIn : kNNWidth; }
+int nn_cout_real(int l) { return l == kNNLayers - 1 ? kNNOut : kNNWidth; }
+int64_t nn_param_count() {
+    int64_t n = 0;
+    for (int l = 0; l < kNNLayers; ++l) n += (int64_t)nn_cout_real(l) * nn_cin_real(l) * 9;
+    return n;
+}
+
+// weights given as [out][in][3][3] per layer (layers concatenated) <-> master [32][kp]
+void nn_set_master(ibpm_ctx *c, const float *pt) {
+    NNState &N = c->nn;
+    int64_t off = 0;
+    for (int l = 0; l < kNNLayers; ++l) {
+        std::vector<float> mst((size_t)32 * N.kp[l], 0.0f);
+        int ci = nn_cin_real(l), co = nn_cout_real(l);
+        for (int o = 0; o < co; ++o)
+            for (int cc = 0; cc < ci; ++cc)
+                for (int t = 0; t < 9; ++t) mst[(size_t)o * N.kp[l] + t * N.cin[l] + cc] = pt[off + ((int64_t)o * ci + cc) * 9 + t];
+        off += (int64_t)co * ci * 9;
+        HIPCHECK(hipMemcpyAsync(N.master[l], mst.data(), mst.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+        HIPCHECK(hipStreamSynchronize(c->stream));
+    }
+    nn_pack(c);
+    N.adam_t = 0;
+    if (N.train_ready)
+        for (int l = 0; l < kNNLayers; ++l) {
+            size_t np = (size_t)32 * N.kp[l];
+            HIPCHECK(hipMemsetAsync(N.m[l], 0, np * sizeof(float), c->stream));
+            HIPCHECK(hipMemsetAsync(N.v[l], 0, np * sizeof(float), c->stream));
+        }
+}
+
+void nn_get_master(ibpm_ctx *c, float *pt) {
+    NNState &N = c->nn;
+    int64_t off = 0;
+    for (int l = 0; l < kNNLayers; ++l) {
+        std::vector<float> mst((size_t)32 * N.kp[l]);
+        HIPCHECK(hipMemcpyAsync(mst.data(), N.master[l], mst.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(hipStreamSynchronize(c->stream));
+        int ci = nn_cin_real(l), co = nn_cout_real(l);
+        for (int o = 0; o < co; ++o)
+            for (int cc = 0; cc < ci; ++cc)
+                for (int t = 0; t < 9; ++t) pt[off + ((int64_t)o * ci + cc) * 9 + t] = mst[(size_t)o * N.kp[l] + t * N.cin[l] + cc];
+        off += (int64_t)co * ci * 9;
+    }
+}
+
+// He-normal initial weights from a counter-based generator (splitmix64 +
+// Box-Muller), so an initialisation is reproducible from its seed
+void nn_init_weights(ibpm_ctx *c, uint64_t seed) {
+    std::vector<float> pt((size_t)nn_param_count());
+    uint64_t ctr = 0;
+    auto next = [&]() {
+        uint64_t z = (seed + 0x9e3779b97f4a7c15ULL * (++ctr));
+        z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+        z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+        z ^= z >> 31;
+        return ((z >> 11) + 0.5) * (1.0 / 9007199254740992.0);
+    };
+    int64_t off = 0;
+    for (int l = 0; l < kNNLayers; ++l) {
+        int ci = nn_cin_real(l), co = nn_cout_real(l);
+        double sd = std::sqrt(2.0 / (9.0 * ci));
+        for (int64_t k = 0; k < (int64_t)co * ci * 9; ++k) {
+            double u1 = next(), u2 = next();
+            pt[off + k] = (float)(sd * std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2));
+        }
+        off += (int64_t)co * ci * 9;
+    }
+    nn_set_master(c, pt.data());
+}
+
+// forward pass from the features in act[0]; the output goes to y32
+void nn_forward(ibpm_ctx *c) {
+    NNState &N = c->nn;
+    hipStream_t s = c->stream;
+    for (int l = 0; l < kNNLayers; ++l) {
+        const bool last = l == kNNLayers - 1;
+        float *y32 = last ? N.y32 : nullptr;
+        bf16 *y16 = last ? nullptr : N.act[l + 1];
+        if (N.cin[l] == kNNInPad)
+            launch_conv3x3<bf16, kNNInPad>(s, N.H, N.W, N.act[l], nullptr, N.fwd[l], y32, y16, last ? 0 : 1);
+        else
+            launch_conv3x3<bf16, 32>(s, N.H, N.W, N.act[l], nullptr, N.fwd[l], y32, y16, last ? 0 : 1);
+    }
+}
+
+// e = correction for the residual r (lambda layout): scale, features,
+// network, output (pressure and interpolated forces) times scale / dt
+void nn_apply(ibpm_ctx *c, const double *r, double *e) {
+    NNState &N = c->nn;
+    hipStream_t s = c->stream;
+    const Model &m = c->m;
+    launch_nn_scale(s, c->p64.K0.n, r, N.sparts, N.scale);
+    launch_nn_features(s, c->g, m.nb, r, (const double *)N.scale, N.inv_hmin, N.cd, N.act[0]);
+    nn_forward(c);
+    launch_nn_output(s, (int)m.g.n_cell, m.nb, N.y32, N.scale, 1.0 / c->prm.dt, N.cd, e);
+}
+
+// loss of one (residual, error) pair and its gradient, added to N.grad;
+// the loss value is copied to the device double `loss`
+void nn_sample_grad(ibpm_ctx *c, const float *r, const float *t, double *loss) {
+    NNState &N = c->nn;
+    hipStream_t s = c->stream;
+    const Model &m = c->m;
+    const int n = c->p64.K0.n;
+    launch_nn_scale(s, n, r, N.sparts, N.scale);
+    launch_nn_features(s, c->g, m.nb, r, (const double *)N.scale, N.inv_hmin, N.cd, N.act[0]);
+    nn_forward(c);
+    launch_nn_loss(s, c->g, m.nb, N.y32, t, N.scale, c->prm.dt, N.cd, N.fdiff, N.g[0], c->parts, N.st);
+    HIPCHECK(hipMemcpyAsync(loss, &N.st->rr, sizeof(double), hipMemcpyDeviceToDevice, s));
+    int cur = 0;
+    for (int l = kNNLayers - 1; l >= 0; --l) {
+        // the ReLU derivative of this layer's output masks the incoming gradient
+        const bf16 *mask = (l == kNNLayers - 1) ? nullptr : N.act[l + 1];
+        const int blocks = conv_dw_blocks(N.H, N.W);
+        if (N.cin[l] == kNNInPad)
+            launch_conv3x3_dw<kNNInPad>(s, N.H, N.W, N.act[l], N.g[cur], mask, N.partials);
+        else
+            launch_conv3x3_dw<32>(s, N.H, N.W, N.act[l], N.g[cur], mask, N.partials);
+        launch_dw_reduce(s, blocks, 32 * N.kp[l], N.partials, N.grad[l]);
+        if (l > 0) {
+            launch_conv3x3<float, 32>(s, N.H, N.W, N.g[cur], mask, N.bwd[l], N.g[1 - cur], nullptr, 0);
+            cur = 1 - cur;
+        }
+    }
+}
+
+// master-layout [32][kp] gradients -> [out][in][3][3] per layer (host)
+void nn_get_grads(ibpm_ctx *c, float *pt) {
+    NNState &N = c->nn;
+    int64_t off = 0;
+    for (int l = 0; l < kNNLayers; ++l) {
+        std::vector<float> g((size_t)32 * N.kp[l]);
+        HIPCHECK(hipMemcpyAsync(g.data(), N.grad[l], g.size() * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+        HIPCHECK(hipStreamSynchronize(c->stream));
+        int ci = nn_cin_real(l), co = nn_cout_real(l);
+        for (int o = 0; o < co; ++o)
+            for (int cc = 0; cc < ci; ++cc)
+                for (int t = 0; t < 9; ++t) pt[off + ((int64_t)o * ci + cc) * 9 + t] = g[(size_t)o * N.kp[l] + t * N.cin[l] + cc];
+        off += (int64_t)co * ci * 9;
+    }
+}
+
+// one training pass over `order` (indices into the sample set) in batches
+double nn_train(ibpm_ctx *c, const float *r1, const float *e1, int S, const int32_t *order,
+                int nord, int batch, float lr) {
+    NNState &N = c->nn;
+    nn_alloc_training(c);
+    hipStream_t s = c->stream;
+    const Model &m = c->m;
+    const int n = c->p64.K0.n;
+    if (N.max_losses < nord) {
+        N.losses = c->dalloc<double>(nord);
+        N.max_losses = nord;
+    }
+    for (int b0 = 0; b0 < nord; b0 += batch) {
+        const int b1 = std::min(nord, b0 + batch);
+        for (int l = 0; l < kNNLayers; ++l)
+            HIPCHECK(hipMemsetAsync(N.grad[l], 0, (size_t)32 * N.kp[l] * sizeof(float), s));
+        for (int q = b0; q < b1; ++q) {
+            const int idx = order[q];
+            if (idx < 0 || idx >= S) throw InvalidArg("sample index out of range");
+            nn_sample_grad(c, r1 + (size_t)idx * n, e1 + (size_t)idx * n, N.losses + q);
+        }
+        // Adam on the summed batch gradient (its step does not depend on the
+        // gradient's scale, so the sum serves as well as the mean)
+        N.adam_t += 1;
+        for (int l = 0; l < kNNLayers; ++l)
+            launch_adam(s, 32 * N.kp[l], N.master[l], N.grad[l], N.m[l], N.v[l], N.adam_t, lr, 0.9f,
+                        0.999f, 1e-8f);
+        nn_pack(c);
+    }
+    std::vector<double> h(nord);
+    HIPCHECK(hipMemcpyAsync(h.data(), N.losses, nord * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    double mean = 0;
+    for (double v : h) mean += v;
+    return nord ? mean / nord : 0.0;
+}
+
+// Flexible CG (one-term recurrence) with the preconditioner
+//   M(r) = z0 + w d,  z0 = V(r),  r1 = r - K z0,  d = network(r1),
+//   w = (d . r1) / (d . K d)  (energy-optimal; 0 if the direction is useless)
+// and a fall-back to plain AMG-PCG from the current iterate if the residual
+// stalls or turns into NaN.
+void learned_precond(ibpm_ctx *c, const double *r, double *z, SolveStatus *st) {
+    NNState &N = c->nn;
+    PrecSet<double> &P = c->p64;
+    hipStream_t s = c->stream;
+    enqueue_vcycle(c, P, r, N.z0, st, false);
+    launch_k0_residual(s, P.K0, r, (const double *)N.z0, N.r1, st);
+    nn_apply(c, N.r1, N.d);
+    launch_kd_omega(s, P.K0, N.d, N.r1, N.st, c->parts);
+    launch_axpy_omega(s, P.K0.n, N.z0, N.d, N.st, z, st);
+}
+
+int solve_poisson_learned(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
+    if (!c->nn.ready) throw InvalidArg("the learned solver needs network weights (ibpm_nn_init or ibpm_nn_set_weights)");
+    hipStream_t s = c->stream;
+    auto t0 = std::chrono::steady_clock::now();
+    PrecSet<double> &P = c->p64;
+    const K0View &K = P.K0;
+    const int n = K.n;
+    SolveStatus *st = c->st_poi;
+    const double rtol = c->prm.poisson_rtol;
+    const int maxit = c->prm.poisson_maxit;
+    launch_pcg_init(s, K, rhs, (const double *)lam, P.r, (double *)nullptr, st, c->parts, false, rtol * rtol, maxit);
+    learned_precond(c, P.r, P.z, st);
+    int curp = 0, chunk = std::max(1, (int)(0.8 * c->est_poi)), queued = 0;
+    double last_rr = -1, chunk_rr = -1;
+    int last_it = 0, fallbacks = 0;
+    bool stall = false;
+    for (;;) {
+        for (int k = 0; k < chunk; ++k) {
+            launch_fcg_spmv(s, K, P.z, P.p[curp], P.p[1 - curp], P.q, P.r, st, c->parts);
+            curp = 1 - curp;
+            launch_pcg_update(s, K, lam, P.r, (double *)nullptr, (const double *)P.p[curp], (const double *)P.q, st, c->parts, false);
+            learned_precond(c, P.r, P.z, st);
+            launch_fcg_beta(s, n, P.z, P.q, st, c->parts);
+        }
+        queued += chunk;
+        c->read_status(st);
+        const SolveStatus &h = *c->host_st;
+        if (h.done != ST_RUNNING || queued > maxit + 1) break;
+        // stall: a chunk of at least 8 iterations that reduced ||r|| by less than 5 %
+        if (chunk_rr > 0 && h.iter - last_it >= 8 && h.rr > 0.9025 * chunk_rr) {
+            stall = true;
+            break;
+        }
+        int rem = 8;
+        if (last_rr > 0 && h.iter > last_it && h.rr < last_rr) {
+            double rate = std::log(h.rr / last_rr) / (h.iter - last_it);
+            double need = std::log(h.tol2 * h.bb / h.rr);
+            if (rate < 0) rem = (int)std::ceil(need / rate);
+        }
+        last_rr = h.rr;
+        chunk_rr = h.rr;
+        last_it = h.iter;
+        chunk = std::min(std::max(rem, 8), 64);
+    }
+    int fcg_iters = c->host_st->iter;
+    bool nan = c->host_st->done == ST_NAN;
+    int code = IBPM_OK;
+    ibpm_solve_stats fb{};
+    if (stall || nan) {
+        // plain AMG-PCG from the current iterate (from zero if it is not finite)
+        if (nan) HIPCHECK(hipMemsetAsync(lam, 0, n * sizeof(double), s));
+        fallbacks = 1;
+        code = solve_poisson_fp64(c, rhs, lam, &fb);
+    } else {
+        launch_zero_if_zero_rhs(s, lam, n, st);
+        launch_true_residual(s, K, rhs, (const double *)lam, st, c->parts);
+        c->read_status(st);
+        const SolveStatus &h = *c->host_st;
+        if (h.iter > 0) c->est_poi = h.iter;
+        if (h.done == ST_MAXIT) code = IBPM_ENOTCONV;
+        fb.relres = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    if (out) {
+        out->iters = fcg_iters + fb.iters;
+        out->status = code;
+        out->relres = fb.relres;
+        out->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        out->outer_iters = 1;
+        out->fallbacks = fallbacks;
+    }
+    return code;
+}
+
 int solve_poisson_impl(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
+    if (c->learned) return solve_poisson_learned(c, rhs, lam, out);
     if (c->mixed) return solve_poisson_mixed(c, rhs, lam, out);
     return solve_poisson_fp64(c, rhs, lam, out);
 }
@@ -439,9 +798,8 @@ void check_params(const ibpm_params *p) {
     if (p->bn_order != 1) throw InvalidArg("only B^N with N = 1 is supported");
     if (!(p->vel_rtol > 0) || !(p->poisson_rtol > 0)) throw InvalidArg("tolerances must be > 0");
     if (p->vel_maxit < 1 || p->poisson_maxit < 1) throw InvalidArg("maxit must be >= 1");
-    if (p->poisson_solver != IBPM_SOLVER_JACOBI_PCG && p->poisson_solver != IBPM_SOLVER_AMG_PCG &&
-        p->poisson_solver != IBPM_SOLVER_AMG_PCG_MIXED)
-        throw InvalidArg("Poisson solver not available in this build");
+    if (p->poisson_solver < IBPM_SOLVER_JACOBI_PCG || p->poisson_solver > IBPM_SOLVER_AMG_FCG_LEARNED)
+        throw InvalidArg("unknown Poisson solver");
     if (p->poisson_solver != IBPM_SOLVER_JACOBI_PCG) {
         if (p->amg_pre < 1 || p->amg_post < 1) throw InvalidArg("AMG needs >= 1 pre and post sweep");
         if (p->amg_coarse_max < 1 || p->amg_max_levels < 1) throw InvalidArg("bad AMG limits");
@@ -564,6 +922,7 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     }
     c->amg = p->poisson_solver != IBPM_SOLVER_JACOBI_PCG;
     c->mixed = p->poisson_solver == IBPM_SOLVER_AMG_PCG_MIXED;
+    c->learned = p->poisson_solver == IBPM_SOLVER_AMG_FCG_LEARNED;
     if (c->amg) {
         AmgParams ap;
         ap.theta = p->amg_theta;
@@ -957,6 +1316,144 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
         (void)hipEventDestroy(e1);
         *avg_ms = ms / reps;
         if (bytes) *bytes = by;
+        return IBPM_OK;
+    });
+}
+
+int ibpm_nn_init(ibpm_ctx *c, uint64_t seed) {
+    return guarded(c, [&] {
+        nn_alloc(c);
+        nn_init_weights(c, seed);
+        HIPCHECK(hipStreamSynchronize(c->stream));
+        return IBPM_OK;
+    });
+}
+
+int ibpm_nn_get_weights(ibpm_ctx *c, float *host, int64_t n) {
+    return guarded(c, [&] {
+        if (!c->nn.ready) throw InvalidArg("network not initialised");
+        if (!host || n != nn_param_count()) throw InvalidArg("wrong weight count");
+        nn_get_master(c, host);
+        return IBPM_OK;
+    });
+}
+
+int ibpm_nn_set_weights(ibpm_ctx *c, const float *host, int64_t n) {
+    return guarded(c, [&] {
+        if (!host || n != nn_param_count()) throw InvalidArg("wrong weight count");
+        nn_alloc(c);
+        nn_set_master(c, host);
+        HIPCHECK(hipStreamSynchronize(c->stream));
+        return IBPM_OK;
+    });
+}
+
+int ibpm_nn_layer(ibpm_ctx *c, int32_t layer, int32_t mode, const float *x, const float *dy,
+                  const float *mask, float *out) {
+    return guarded(c, [&] {
+        NNState &N = c->nn;
+        if (!N.ready) throw InvalidArg("network not initialised");
+        if (layer < 0 || layer >= kNNLayers || mode < 0 || mode > 2 || !out) throw InvalidArg("bad arguments");
+        if ((mode != 1 && !x) || (mode != 0 && !dy)) throw InvalidArg("missing operand");
+        hipStream_t s = c->stream;
+        const int cin = N.cin[layer];
+        bf16 *xb = N.act[1], *mb = mask ? N.act[2] : nullptr;
+        if (x) launch_to_bf16(s, img(N, cin), x, xb);
+        if (mask) launch_to_bf16(s, img(N, 32), mask, mb);
+        if (mode == 0) {
+            if (cin == kNNInPad) launch_conv3x3<bf16, kNNInPad>(s, N.H, N.W, xb, nullptr, N.fwd[layer], out, nullptr, 0);
+            else launch_conv3x3<bf16, 32>(s, N.H, N.W, xb, nullptr, N.fwd[layer], out, nullptr, 0);
+        } else if (mode == 1) {
+            launch_conv3x3<float, 32>(s, N.H, N.W, dy, mb, N.bwd[layer], out, nullptr, 0);
+        } else {
+            nn_alloc_training(c);
+            const int blocks = conv_dw_blocks(N.H, N.W);
+            if (cin == kNNInPad) launch_conv3x3_dw<kNNInPad>(s, N.H, N.W, xb, dy, mb, N.partials);
+            else launch_conv3x3_dw<32>(s, N.H, N.W, xb, dy, mb, N.partials);
+            HIPCHECK(hipMemsetAsync(N.grad[layer], 0, (size_t)32 * N.kp[layer] * sizeof(float), s));
+            launch_dw_reduce(s, blocks, 32 * N.kp[layer], N.partials, N.grad[layer]);
+            std::vector<float> mst((size_t)32 * N.kp[layer]);
+            HIPCHECK(hipMemcpyAsync(mst.data(), N.grad[layer], mst.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+            HIPCHECK(hipStreamSynchronize(s));
+            const int ci = nn_cin_real(layer), co = nn_cout_real(layer);
+            std::vector<float> pt((size_t)co * ci * 9);
+            for (int o = 0; o < co; ++o)
+                for (int cc = 0; cc < ci; ++cc)
+                    for (int t = 0; t < 9; ++t) pt[((size_t)o * ci + cc) * 9 + t] = mst[(size_t)o * N.kp[layer] + t * cin + cc];
+            HIPCHECK(hipMemcpyAsync(out, pt.data(), pt.size() * sizeof(float), hipMemcpyHostToDevice, s));
+        }
+        HIPCHECK(hipStreamSynchronize(s));
+        return IBPM_OK;
+    });
+}
+
+int ibpm_nn_apply(ibpm_ctx *c, const double *r, double *e) {
+    return guarded(c, [&] {
+        if (!c->nn.ready) throw InvalidArg("network not initialised");
+        if (!r || !e) throw InvalidArg("NULL vector");
+        nn_apply(c, r, e);
+        return IBPM_OK;
+    });
+}
+
+int ibpm_nn_train(ibpm_ctx *c, const float *r1, const float *e1, int32_t nsamples,
+                  const int32_t *order, int32_t norder, int32_t batch, float lr, double *mean_loss) {
+    return guarded(c, [&] {
+        if (!c->nn.ready) throw InvalidArg("network not initialised");
+        if (!r1 || !e1 || !order || nsamples < 1 || norder < 1 || batch < 1 || !(lr > 0))
+            throw InvalidArg("bad arguments");
+        double l = nn_train(c, r1, e1, nsamples, order, norder, batch, lr);
+        if (mean_loss) *mean_loss = l;
+        return IBPM_OK;
+    });
+}
+
+int ibpm_nn_loss_grad(ibpm_ctx *c, const float *r1, const float *e1, double *loss, float *grad) {
+    return guarded(c, [&] {
+        NNState &N = c->nn;
+        if (!N.ready) throw InvalidArg("network not initialised");
+        if (!r1 || !e1 || !loss || !grad) throw InvalidArg("NULL argument");
+        nn_alloc_training(c);
+        if (N.max_losses < 1) {
+            N.losses = c->dalloc<double>(1);
+            N.max_losses = 1;
+        }
+        for (int l = 0; l < kNNLayers; ++l)
+            HIPCHECK(hipMemsetAsync(N.grad[l], 0, (size_t)32 * N.kp[l] * sizeof(float), c->stream));
+        nn_sample_grad(c, r1, e1, N.losses);
+        HIPCHECK(hipMemcpyAsync(loss, N.losses, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        nn_get_grads(c, grad);
+        return IBPM_OK;
+    });
+}
+
+int ibpm_harvest(ibpm_ctx *c, const double *rhs, double *x, const double *xstar, int32_t npairs,
+                 float *r1_out, float *e1_out, int32_t *nout) {
+    return guarded(c, [&] {
+        if (!c->amg) throw InvalidArg("harvesting needs an AMG context");
+        if (!rhs || !x || !xstar || !r1_out || !e1_out || npairs < 1) throw InvalidArg("bad arguments");
+        hipStream_t s = c->stream;
+        PrecSet<double> &P = c->p64;
+        const K0View &K = P.K0;
+        const int n = K.n;
+        SolveStatus *st = c->st_poi;
+        const double rtol = c->prm.poisson_rtol;
+        launch_pcg_init(s, K, rhs, (const double *)x, P.r, (double *)nullptr, st, c->parts, false, rtol * rtol, c->prm.poisson_maxit);
+        enqueue_vcycle(c, P, (const double *)P.r, P.z, st);
+        int k = 0, curp = 0;
+        for (; k < npairs; ++k) {
+            c->read_status(st);
+            if (c->host_st->done != ST_RUNNING) break;
+            // r1 = r - K V(r) (FP32) and e1 = x* - x - V(r)
+            launch_outer_residual(s, K, P.r, P.z, r1_out + (size_t)k * n, c->st_bench, c->parts, 1);
+            launch_harvest_e1(s, n, xstar, x, P.z, e1_out + (size_t)k * n);
+            launch_pcg_spmv(s, K, (const double *)P.z, (const double *)P.p[curp], P.p[1 - curp], P.q, st, c->parts);
+            curp = 1 - curp;
+            launch_pcg_update(s, K, x, P.r, (double *)nullptr, (const double *)P.p[curp], (const double *)P.q, st, c->parts, false);
+            enqueue_vcycle(c, P, (const double *)P.r, P.z, st);
+        }
+        HIPCHECK(hipStreamSynchronize(s));
+        if (nout) *nout = k;
         return IBPM_OK;
     });
 }

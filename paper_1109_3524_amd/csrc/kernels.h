@@ -182,6 +182,23 @@ template <class T>
 void launch_coarse_cycle(hipStream_t s, const CoarseLevel<T> *lv_dev, int lc, int L, int pre,
                          int post, const double *inv, int n_coarse, const SolveStatus *st);
 
+// flexible CG with a learned stage (FP64):
+//   p_new = z + beta p_old, q = K p_new, st->pq = p.q, st->rz = p.r
+void launch_fcg_spmv(hipStream_t s, const K0View &K, const double *z, const double *pold,
+                     double *pnew, double *q, const double *r, SolveStatus *st, double *parts);
+//   stw->beta = (d.r1) / (d.K d) (0 if not positive)
+void launch_kd_omega(hipStream_t s, const K0View &K, const double *d, const double *r1,
+                     SolveStatus *stw, double *parts);
+//   z = z0 + stw->beta d
+void launch_axpy_omega(hipStream_t s, int n, const double *z0, const double *d,
+                       const SolveStatus *stw, double *z, const SolveStatus *st);
+//   st->beta = -(z.q) / st->pq
+void launch_fcg_beta(hipStream_t s, int n, const double *z, const double *q, SolveStatus *st,
+                     double *parts);
+// harvest: e1 = x* - x - z (FP32)
+void launch_harvest_e1(hipStream_t s, int n, const double *xstar, const double *x, const double *z,
+                       float *e1);
+
 // mixed precision: FP64 outer residual r = b - K x (also cast to FP32) and x += d
 void launch_outer_residual(hipStream_t s, const K0View &K, const double *b, const double *x,
                            float *r32, SolveStatus *st, double *parts, int first);

@@ -491,13 +491,21 @@ __global__ __launch_bounds__(kBlock) void k_dot_rz(int n, const T *r, const T *z
 
 // Grid-wide sums of the partials written by the previous kernel (G blocks)
 // and the status update that goes with them.  One block.
-enum : int { FIN_INIT = 0, FIN_INIT_ZERO, FIN_PQ, FIN_UPDATE, FIN_TRUE, FIN_RZ, FIN_OUTER };
+enum : int {
+    FIN_INIT = 0, FIN_INIT_ZERO, FIN_PQ, FIN_UPDATE, FIN_TRUE, FIN_RZ, FIN_OUTER,
+    FIN_FCG_PQ, FIN_OMEGA, FIN_FCG_BETA
+};
 
 __global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const double *parts,
                                                      SolveStatus *st, int flag, double rtol2,
                                                      int maxit) {
-    if ((kind == FIN_PQ || kind == FIN_UPDATE || kind == FIN_RZ) && st->done) return;
-    const int N = (kind == FIN_INIT) ? 3 : (kind == FIN_UPDATE || kind == FIN_OUTER) ? 2 : 1;
+    if ((kind == FIN_PQ || kind == FIN_UPDATE || kind == FIN_RZ || kind == FIN_FCG_PQ ||
+         kind == FIN_FCG_BETA) && st->done)
+        return;
+    const int N = (kind == FIN_INIT) ? 3
+                  : (kind == FIN_UPDATE || kind == FIN_OUTER || kind == FIN_FCG_PQ || kind == FIN_OMEGA)
+                      ? 2
+                      : 1;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < G; b += kBlock)
         for (int k = 0; k < N; ++k) acc[k] += parts[k * kMaxParts + b];
@@ -557,6 +565,18 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const doub
         }
         st->rz = acc[0];
         break;
+    case FIN_FCG_PQ:   // acc = (p.q, p.r): the flexible-CG step length is (p.r)/(p.q)
+        st->pq = acc[0];
+        st->rz = acc[1];
+        break;
+    case FIN_OMEGA: {  // acc = (d.r1, d.K d): energy-optimal weight of the learned correction
+        double w = (acc[1] > 0.0 && !bad(acc[0]) && !bad(acc[1])) ? acc[0] / acc[1] : 0.0;
+        st->beta = w;
+        break;
+    }
+    case FIN_FCG_BETA:   // acc = z.q (q of the current direction)
+        st->beta = -acc[0] / st->pq;
+        break;
     case FIN_OUTER:   // acc = (rr, bb); flag = first outer residual
         st->rr = acc[0];
         if (flag) {
@@ -567,6 +587,70 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const doub
         }
         break;
     }
+}
+
+// ---------------------------------------------------------------------------
+// flexible CG with the learned stage
+
+// p_new = z + beta p_old, q = K p_new; sums p.q and p.r
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_fcg_spmv(K0T<T> K, const T *z, const T *pold, T *pnew,
+                                                     T *q, const T *r, SolveStatus *st,
+                                                     double *parts) {
+    if (st->done) return;
+    const T beta = (T)st->beta;
+    double v[2] = {0.0, 0.0};
+    k0_walk<R>(K, [&](int c) { return z[c] + beta * pold[c]; }, [&](int row, T qi, T, T pi) {
+        pnew[row] = pi;
+        q[row] = qi;
+        v[0] += (double)pi * (double)qi;
+        v[1] += (double)pi * (double)r[row];
+    });
+    write_parts2<2>(v, parts);
+}
+
+// sums d.r1 and d.(K d)
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_kd_dots(K0View K, const double *d, const double *r1,
+                                                    double *parts) {
+    double v[2] = {0.0, 0.0};
+    k0_walk<R>(K, [&](int c) { return d[c]; }, [&](int row, double kd, double, double dr) {
+        v[0] += dr * r1[row];
+        v[1] += dr * kd;
+    });
+    write_parts2<2>(v, parts);
+}
+
+// z = z0 + omega d (omega from the learned-stage status); omega = 0 drops the
+// correction altogether, so a non-finite network output never reaches z
+__global__ __launch_bounds__(kBlock) void k_axpy_omega(int n, const double *z0, const double *d,
+                                                       const SolveStatus *stw, double *z,
+                                                       const SolveStatus *st) {
+    if (st->done) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const double w = stw->beta;
+    if (i < n) z[i] = w != 0.0 ? z0[i] + w * d[i] : z0[i];
+}
+
+// generic predicated dot product a . b into a finalize kind
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_dot(int n, const T *a, const T *b, SolveStatus *st,
+                                                double *parts) {
+    if (st->done) return;
+    Tiles Tl = my_tiles(n);
+    double v[1] = {0.0};
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
+        int row = t * kBlock + threadIdx.x;
+        if (row < n) v[0] += (double)a[row] * (double)b[row];
+    }
+    write_parts<1>(v, parts);
+}
+
+// harvest: e1 = x* - x - z in FP32
+__global__ __launch_bounds__(kBlock) void k_harvest_e1(int n, const double *xstar, const double *x,
+                                                       const double *z, float *e1) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) e1[i] = (float)(xstar[i] - x[i] - z[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1267,6 +1351,45 @@ void launch_coarse_cycle(hipStream_t s, const CoarseLevel<T> *lv_dev, int lc, in
                          int post, const double *inv, int n_coarse, const SolveStatus *st) {
     hipLaunchKernelGGL((k_coarse_cycle<T>), dim3(1), dim3(kCoarseBlock), 0, s, lv_dev, lc, L, pre,
                        post, inv, n_coarse, st);
+}
+
+void launch_fcg_spmv(hipStream_t s, const K0View &K, const double *z, const double *pold,
+                     double *pnew, double *q, const double *r, SolveStatus *st, double *parts) {
+    int G = 0;
+    WALK_SWITCH(pick_R(K), {
+        dim3 gd = op_grid<RR>(K);
+        G = gd.x * gd.y;
+        LAUNCH2((k_fcg_spmv<RR, double>), gd, K, z, pold, pnew, q, r, st, parts);
+    })
+    LAUNCH(k_finalize, 1, (int)FIN_FCG_PQ, G, parts, st, 0, 0.0, 0);
+}
+
+void launch_kd_omega(hipStream_t s, const K0View &K, const double *d, const double *r1,
+                     SolveStatus *stw, double *parts) {
+    int G = 0;
+    WALK_SWITCH(pick_R(K), {
+        dim3 gd = op_grid<RR>(K);
+        G = gd.x * gd.y;
+        LAUNCH2((k_kd_dots<RR>), gd, K, d, r1, parts);
+    })
+    LAUNCH(k_finalize, 1, (int)FIN_OMEGA, G, parts, stw, 0, 0.0, 0);
+}
+
+void launch_axpy_omega(hipStream_t s, int n, const double *z0, const double *d,
+                       const SolveStatus *stw, double *z, const SolveStatus *st) {
+    LAUNCH(k_axpy_omega, (n + kBlock - 1) / kBlock, n, z0, d, stw, z, st);
+}
+
+void launch_fcg_beta(hipStream_t s, int n, const double *z, const double *q, SolveStatus *st,
+                     double *parts) {
+    int G = grid_for(n);
+    LAUNCH((k_dot<double>), G, n, z, q, st, parts);
+    LAUNCH(k_finalize, 1, (int)FIN_FCG_BETA, G, parts, st, 0, 0.0, 0);
+}
+
+void launch_harvest_e1(hipStream_t s, int n, const double *xstar, const double *x, const double *z,
+                       float *e1) {
+    LAUNCH(k_harvest_e1, (n + kBlock - 1) / kBlock, n, xstar, x, z, e1);
 }
 
 void launch_outer_residual(hipStream_t s, const K0View &K, const double *b, const double *x,

@@ -3,14 +3,14 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
-#include <hip/hip_bf16.h>
 #include <cstdint>
+#include <stdexcept>
 
 #include "kernels.h"
 
 namespace ibpm {
 
-using bf16 = __hip_bfloat16;
+using bf16 = __bf16;
 
 constexpr int kNNLayers = 6;
 constexpr int kNNWidth = 32;        // hidden channels (and padded output channels)
@@ -57,22 +57,34 @@ void launch_dw_reduce(hipStream_t s, int blocks, int nk, const float *partials, 
 void launch_pack_weights(hipStream_t s, int cin, int cout, const float *master, bf16 *fwd,
                          bf16 *bwd);
 
+// y = BF16(x), n values
+void launch_to_bf16(hipStream_t s, size_t n, const float *x, bf16 *y);
+
 // Adam step on n FP32 parameters (bias-corrected, step t >= 1)
 void launch_adam(hipStream_t s, int n, float *w, const float *g, float *m, float *v, int t,
                  float lr, float beta1, float beta2, float eps);
 
-// features: residual r (lambda layout, FP64) scaled by 1/scale -> X [H][W][8] BF16
+// RMS scale of a lambda vector: scale[0] = sqrt(sum r^2 / n) (1 if zero);
+// parts needs 1024 doubles
+template <class T>
+void launch_nn_scale(hipStream_t s, int n, const T *r, double *parts, double *scale);
+
+// features: residual r (lambda layout) scaled by 1/scale -> X [H][W][8] BF16
 //   ch0 pressure residual, ch1/ch2 force residuals spread to cell centres,
 //   ch3/ch4 log of the cell widths over the finest width, ch5-7 zero
-void launch_nn_features(hipStream_t s, GridView g, int nb, const double *r, const double *scale,
+template <class T>
+void launch_nn_features(hipStream_t s, GridView g, int nb, const T *r, const double *scale,
                         double inv_hmin, CellDelta cd, bf16 *X);
 // network output Y32 [H][W][32] -> correction e (lambda layout, FP64) times
 // scale/dt: pressure from channel 0, forces interpolated from channels 1, 2
 void launch_nn_output(hipStream_t s, int n_cell, int nb, const float *Y32, const double *scale,
                       double inv_dt, CellDelta cd, double *e);
-// training loss (normalised squared error per part, pressure and force) of
-// Y32 against the target t (lambda layout, FP32, already scaled) and dL/dY32
-void launch_nn_loss(hipStream_t s, int n_cell, int nb, const float *Y32, const float *t,
-                    CellDelta cd, float *dY, double *parts, SolveStatus *st);
+// training loss of Y32 against the target t * dt / scale (t in lambda layout,
+// FP32): L_phi / D_phi + L_f / D_f (squared errors over squared targets,
+// pressure cells and interpolated forces) into st->rr, and dL/dY32 into dY
+// ([H][W][32] FP32).  fdiff holds 2 nb floats of scratch.
+void launch_nn_loss(hipStream_t s, GridView g, int nb, const float *Y32, const float *t,
+                    const double *scale, double dt, CellDelta cd, float *fdiff, float *dY,
+                    double *parts, SolveStatus *st);
 
 }  // namespace ibpm

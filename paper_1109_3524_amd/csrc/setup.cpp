@@ -330,6 +330,63 @@ void build_full_K(Model &m) {
     }
 }
 
+// Delta weights at cell centres for the learned stage's force channels.
+void build_cell_delta(Model &m, const double *xb, const double *yb) {
+    const GridMetrics &g = m.g;
+    int nb = m.nb;
+    std::vector<std::vector<std::pair<int64_t, double>>> rows(nb);
+    int i0 = g.nx, i1 = -1, j0 = g.ny, j1 = -1;
+    for (int k = 0; k < nb; ++k) {
+        double X = xb[k], Y = yb[k];
+        double hx = local_width(g.xf, g.dx, X, "x");
+        double hy = local_width(g.yf, g.dy, Y, "y");
+        int ic = cell_of(g.xf, X), jc = cell_of(g.yf, Y);
+        for (int j = std::max(0, jc - 2); j <= std::min(g.ny - 1, jc + 2); ++j) {
+            if (!(std::fabs(g.yc[j] - Y) < 1.5 * hy)) continue;
+            for (int i = std::max(0, ic - 2); i <= std::min(g.nx - 1, ic + 2); ++i) {
+                if (!(std::fabs(g.xc[i] - X) < 1.5 * hx)) continue;
+                double w = roma_phi((g.xc[i] - X) / hx) * roma_phi((g.yc[j] - Y) / hy);
+                rows[k].push_back({(int64_t)j * g.nx + i, w});
+                i0 = std::min(i0, i); i1 = std::max(i1, i);
+                j0 = std::min(j0, j); j1 = std::max(j1, j);
+            }
+        }
+    }
+    m.Dp2c = CSR();
+    m.Dp2c.nrows = nb;
+    m.Dp2c.ncols = (int32_t)g.n_cell;
+    m.Dp2c.ptr.assign(nb + 1, 0);
+    for (int k = 0; k < nb; ++k) {
+        for (auto &e : rows[k]) {
+            m.Dp2c.col.push_back((int32_t)e.first);
+            m.Dp2c.val.push_back(e.second);
+        }
+        m.Dp2c.ptr[k + 1] = (int32_t)m.Dp2c.col.size();
+    }
+    if (i1 < 0) { i0 = 0; i1 = -1; j0 = 0; j1 = -1; }
+    m.dc_i0 = i0; m.dc_i1 = i1; m.dc_j0 = j0; m.dc_j1 = j1;
+    int bw = i1 - i0 + 1, bh = j1 - j0 + 1;
+    std::vector<std::vector<std::pair<int32_t, double>>> cells(std::max(0, bw * bh));
+    for (int k = 0; k < nb; ++k)
+        for (auto &e : rows[k]) {
+            int i = (int)(e.first % g.nx), j = (int)(e.first / g.nx);
+            cells[(j - j0) * bw + (i - i0)].push_back({k, e.second});
+        }
+    m.Dc2p = CSR();
+    m.Dc2p.nrows = std::max(0, bw * bh);
+    m.Dc2p.ncols = nb;
+    m.Dc2p.ptr.assign(m.Dc2p.nrows + 1, 0);
+    for (int r = 0; r < m.Dc2p.nrows; ++r) {
+        for (auto &e : cells[r]) {
+            m.Dc2p.col.push_back(e.first);
+            m.Dc2p.val.push_back(e.second);
+        }
+        m.Dc2p.ptr[r + 1] = (int32_t)m.Dc2p.col.size();
+    }
+    m.hmin = *std::min_element(g.dx.begin(), g.dx.end());
+    m.hmin = std::min(m.hmin, *std::min_element(g.dy.begin(), g.dy.end()));
+}
+
 }  // namespace
 
 void build_model(Model &m, int nx, int ny, const double *xf, const double *yf, int nb,
@@ -350,6 +407,7 @@ void build_model(Model &m, int nx, int ny, const double *xf, const double *yf, i
     build_E(m, xb, yb);
     build_coupling(m);
     build_full_K(m);
+    build_cell_delta(m, xb, yb);
 }
 
 // ---------------------------------------------------------------------------

@@ -46,6 +46,12 @@ struct Model {
     CSR Etu;                         // rows: u faces of the box, cols: force index 0..nb-1
     CSR Etv;                         // rows: v faces of the box, cols: force index 0..nb-1
     CSR K;                           // full pinned K (for the hierarchy setup)
+    // delta weights between the points and the cell centres (learned stage):
+    // phi((xc_i - xi_k)/h) phi((yc_j - eta_k)/h), cells of a box -> points and back
+    int32_t dc_i0 = 0, dc_i1 = -1, dc_j0 = 0, dc_j1 = -1;
+    CSR Dc2p;                        // rows: box cells, cols: point 0..nb-1
+    CSR Dp2c;                        // rows: points, cols: cell index (j*nx + i)
+    double hmin = 0;                 // smallest cell width
 };
 
 struct Level {

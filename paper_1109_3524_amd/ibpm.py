@@ -35,8 +35,13 @@ EXPORTED = (
     "ibpm_apply_K", "ibpm_apply_A", "ibpm_stage_walls", "ibpm_stage_rhs1",
     "ibpm_stage_rhs2", "ibpm_stage_project", "ibpm_get_walls", "ibpm_set_walls",
     "ibpm_get_step", "ibpm_set_step", "ibpm_get_forces", "ibpm_hierarchy_info",
-    "ibpm_get_aggregates", "ibpm_time_kernel",
+    "ibpm_get_aggregates", "ibpm_time_kernel", "ibpm_nn_init", "ibpm_nn_get_weights",
+    "ibpm_nn_set_weights", "ibpm_nn_layer", "ibpm_nn_apply", "ibpm_nn_train",
+    "ibpm_nn_loss_grad", "ibpm_harvest",
 )
+
+NN_PARAMS = 39168                     # IBPM_NN_PARAMS
+NN_SHAPES = [(32, 5), (32, 32), (32, 32), (32, 32), (32, 32), (3, 32)]   # (out, in) per layer
 
 KERNELS = {"k0_jacobi": 0, "k0_pcg_spmv": 1, "a_pcg_spmv": 2, "k0_residual": 3,
            "restrict0": 4, "prolong0": 5, "pcg_update_k": 6, "coarse_cycle": 7}
@@ -123,6 +128,14 @@ def load():
         "ibpm_hierarchy_info": [P, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "ibpm_get_aggregates": [P, i32, ctypes.POINTER(i32)],
         "ibpm_time_kernel": [P, i32, i32, D, D],
+        "ibpm_nn_init": [P, ctypes.c_uint64],
+        "ibpm_nn_get_weights": [P, P, i64],
+        "ibpm_nn_set_weights": [P, P, i64],
+        "ibpm_nn_layer": [P, i32, i32, P, P, P, P],
+        "ibpm_nn_apply": [P, P, P],
+        "ibpm_nn_train": [P, P, P, i32, P, i32, i32, ctypes.c_float, D],
+        "ibpm_nn_loss_grad": [P, P, P, D, P],
+        "ibpm_harvest": [P, P, P, P, i32, P, P, ctypes.POINTER(i32)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -331,6 +344,86 @@ class Context:
         self._check(load().ibpm_time_kernel(self._h, KERNELS[name], int(reps),
                                             ctypes.byref(ms), ctypes.byref(by)))
         return ms.value, by.value
+
+    # -- learned stage ----------------------------------------------------------
+    def _f32(self, t, n, name):
+        torch = self._torch
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != torch.float32:
+            raise TypeError(f"{name} must be a float32 CUDA tensor")
+        if not t.is_contiguous() or t.numel() != n:
+            raise ValueError(f"{name} must be contiguous with {n} elements")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def nn_init(self, seed):
+        self._check(load().ibpm_nn_init(self._h, ctypes.c_uint64(int(seed))))
+
+    def nn_get_weights(self):
+        w = np.zeros(NN_PARAMS, dtype=np.float32)
+        self._check(load().ibpm_nn_get_weights(self._h, ctypes.c_void_p(w.ctypes.data), NN_PARAMS))
+        return w
+
+    def nn_set_weights(self, w):
+        a = np.ascontiguousarray(np.asarray(w, dtype=np.float32).reshape(-1))
+        if a.size != NN_PARAMS:
+            raise ValueError(f"expected {NN_PARAMS} weights")
+        self._check(load().ibpm_nn_set_weights(self._h, ctypes.c_void_p(a.ctypes.data), NN_PARAMS))
+
+    def nn_layer(self, layer, mode, x=None, dy=None, mask=None):
+        """One network layer on the device (see ibpm_nn_layer); images are
+        float32 CUDA tensors of shape (ny, nx, C)."""
+        torch = self._torch
+        cin = 8 if layer == 0 else 32
+        hw = self.nx * self.ny
+        xp = self._f32(x, hw * cin, "x") if x is not None else None
+        dp = self._f32(dy, hw * 32, "dy") if dy is not None else None
+        mp = self._f32(mask, hw * 32, "mask") if mask is not None else None
+        if mode == 2:
+            co, ci = NN_SHAPES[layer]
+            out = torch.zeros(co * ci * 9, dtype=torch.float32, device=self.device)
+        else:
+            out = torch.zeros(hw * 32, dtype=torch.float32, device=self.device)
+        self._check(load().ibpm_nn_layer(self._h, int(layer), int(mode), xp, dp, mp,
+                                         ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def nn_apply(self, r, e=None):
+        e = self.zeros_lambda() if e is None else e
+        self._check(load().ibpm_nn_apply(self._h, self._vec(r, self.n_lambda, "r"),
+                                         self._vec(e, self.n_lambda, "e")))
+        return e
+
+    def nn_train(self, r1, e1, order, batch, lr):
+        """One Adam pass over samples `order` of the (r1, e1) pair set
+        (float32 CUDA tensors of shape (nsamples, n_lambda)); returns the mean loss."""
+        S = r1.shape[0]
+        o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+        loss = ctypes.c_double()
+        self._check(load().ibpm_nn_train(self._h, self._f32(r1, S * self.n_lambda, "r1"),
+                                         self._f32(e1, S * self.n_lambda, "e1"), int(S),
+                                         ctypes.c_void_p(o.ctypes.data), int(o.size), int(batch),
+                                         ctypes.c_float(lr), ctypes.byref(loss)))
+        return loss.value
+
+    def nn_loss_grad(self, r1, e1):
+        g = np.zeros(NN_PARAMS, dtype=np.float32)
+        loss = ctypes.c_double()
+        self._check(load().ibpm_nn_loss_grad(self._h, self._f32(r1, self.n_lambda, "r1"),
+                                             self._f32(e1, self.n_lambda, "e1"),
+                                             ctypes.byref(loss), ctypes.c_void_p(g.ctypes.data)))
+        return loss.value, g
+
+    def harvest(self, rhs, x, xstar, npairs):
+        """Training pairs from an AMG-PCG solve started at x (updated in place)."""
+        torch = self._torch
+        r1 = torch.zeros((npairs, self.n_lambda), dtype=torch.float32, device=self.device)
+        e1 = torch.zeros((npairs, self.n_lambda), dtype=torch.float32, device=self.device)
+        nout = ctypes.c_int32()
+        self._check(load().ibpm_harvest(self._h, self._vec(rhs, self.n_lambda, "rhs"),
+                                        self._vec(x, self.n_lambda, "x"),
+                                        self._vec(xstar, self.n_lambda, "xstar"), int(npairs),
+                                        ctypes.c_void_p(r1.data_ptr()),
+                                        ctypes.c_void_p(e1.data_ptr()), ctypes.byref(nout)))
+        return r1[:nout.value], e1[:nout.value]
 
     def aggregates(self, level):
         sizes, _ = self.hierarchy()

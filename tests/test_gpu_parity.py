@@ -353,9 +353,20 @@ def test_mixed_precision_poisson_solve_against_fp64_oracle():
           f"lambda err {e64:.2e}, projection err {du64:.2e}")
     assert s["relres"] <= 1e-8 and s["outer_iters"] >= 1
     # lambda carries the ill-conditioned interior-pressure / force modes; the
-    # velocity correction it produces is the field the step uses
-    assert du < 1e-7
+    # velocity correction it produces is the field the step uses.  A 1e-8
+    # residual bounds that error only through the conditioning of K, so the
+    # bar is the FP64 solver's own error at the same stopping test
+    assert du < max(3.0 * du64, 1e-7)
     assert e < 1e-4
+    # refinement carries the FP32 inner solves to FP64 accuracy: at a 1e-11
+    # stopping test the projection error drops with the residual
+    ctx.close()
+    ctx = ibpm.Context(wl, poisson_solver=2, poisson_rtol=1e-11, poisson_maxit=20000)
+    lam = _t(st.lam)
+    s2 = ctx.solve_poisson(_t(rhs), lam)
+    du2 = _rel(o.B1 * (o.Q @ _n(lam)) / R, o.B1 * (o.Q @ ref) / R)
+    print(f"  mixed at 1e-11: {s2['iters']} inner / {s2['outer_iters']} outer, projection err {du2:.2e}")
+    assert s2["relres"] <= 1e-11 and du2 < 1e-9
     ctx.close()
     ctx64.close()
 
