@@ -56,6 +56,8 @@ extern "C" {
 #define IBPM_SOLVER_AMG_PCG          1
 #define IBPM_SOLVER_AMG_PCG_MIXED    2   /* FP32 inner AMG-PCG inside FP64 iterative refinement */
 #define IBPM_SOLVER_AMG_FCG_LEARNED  3   /* flexible CG, AMG V-cycle plus a learned stage */
+#define IBPM_SOLVER_AMG_FCG_MIXED_LEARNED 4  /* FP32 inner flexible CG with the learned stage
+                                                inside FP64 iterative refinement */
 
 typedef struct ibpm_ctx ibpm_ctx;
 
@@ -78,6 +80,8 @@ typedef struct ibpm_params {
     int32_t amg_pre, amg_post;   /* Jacobi sweeps before / after the coarse correction */
     int32_t amg_coarse_max;      /* stop coarsening at or below this many unknowns */
     int32_t amg_max_levels;
+    double inner_rtol;           /* refinement (solvers 2, 4): floor of the relative tolerance
+                                    of an inner FP32 solve; 0 selects 1e-5 */
 } ibpm_params;
 
 typedef struct ibpm_solve_stats {

@@ -69,8 +69,8 @@ template <class T>
 struct PrecSet {
     K0T<T> K0{};
     std::vector<DevLevelT<T>> lev;
-    CoarseLevel<T> *coarse_dev = nullptr;
-    int lc = 1;                        // first level solved by the one-work-group coarse cycle
+    double *coarseC = nullptr;         // cycle on levels lc.. as a dense FP64 matrix
+    int lc = 1;                        // first level of the dense coarse cycle
     // PCG work vectors (n_lambda)
     T *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
 };
@@ -88,7 +88,8 @@ struct NNState {
     float *g[2] = {nullptr, nullptr}; // gradients [H][W][32]
     float *partials = nullptr, *fdiff = nullptr;
     double *scale = nullptr, *sparts = nullptr, *losses = nullptr;
-    double *d = nullptr, *r1 = nullptr, *z0 = nullptr;   // learned-stage work vectors
+    double *d = nullptr, *r1 = nullptr, *z0 = nullptr;   // learned-stage work vectors (FP64)
+    float *d32 = nullptr, *r132 = nullptr, *z032 = nullptr;   // and FP32 (mixed inner solve)
     SolveStatus *st = nullptr;
     CellDelta cd{};
     int adam_t = 0;
@@ -118,6 +119,9 @@ struct ibpm_ctx {
     PrecSet<float> p32;
     float *rin32 = nullptr, *d32 = nullptr;          // mixed: inner right-hand side and correction
     double *coarse_inv = nullptr;
+    std::vector<double> coarse_C;      // host copy of the dense coarse-cycle matrix
+    double *coarse_C_dev = nullptr;    // its device copy (shared by both precisions)
+    int coarse_C_lc = -1;
     // velocity PCG (n_q)
     double *vr = nullptr, *vz = nullptr, *vp[2] = {nullptr, nullptr}, *vq = nullptr;
     double *r1 = nullptr, *rhs2 = nullptr;
@@ -250,8 +254,8 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
         launch_csrv_residual(s, lv.A.view(), lv.A.lanes, (const T *)lv.b, (const T *)a, lv.r, st);
         launch_csrv_spmv(s, lv.R.view(), lv.R.lanes, (const T *)lv.r, P.lev[l + 1].b, false, st);
     }
-    launch_coarse_cycle(s, (const CoarseLevel<T> *)P.coarse_dev, P.lc, L, pre, post, c->coarse_inv,
-                        P.lev[L - 1].n, st);
+    launch_coarse_dense(s, P.lev[P.lc].n, (const double *)P.coarseC, (const T *)P.lev[P.lc].b,
+                        P.lev[P.lc].xa, st);
     cur[P.lc] = P.lev[P.lc].xa;
     for (int l = P.lc - 1; l >= 1; --l) {
         DevLevelT<T> &lv = P.lev[l];
@@ -365,16 +369,31 @@ int solve_poisson_fp64(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_s
 // solve are FP64; the inner SpMV, V-cycle and vectors are FP32 with FP64
 // dot products.  Each inner solve is asked for the reduction the outer
 // tolerance still needs (at least 1e-5, about what FP32 can deliver).
+template <class T>
+SolveStatus fcg_learned_drive(ibpm_ctx *c, PrecSet<T> &P, const T *b, T *x, SolveStatus *st,
+                              double rtol, int maxit, int &est, bool zero_guess, bool *stall);
+void learned_guess(ibpm_ctx *c, const double *b, double *x, SolveStatus *st);
+
+// FP64 iterative refinement: r = b - K x in FP64, an FP32 inner solve of
+// K d = r to a relative tolerance that aims at the outer one, x += d.  The
+// inner solve is AMG-PCG, or with the learned stage flexible CG with the
+// network (falling back to AMG-PCG for the remaining inner solves once a
+// learned inner solve stalls or breaks down).
 int solve_poisson_mixed(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
     hipStream_t s = c->stream;
     auto t0 = std::chrono::steady_clock::now();
     const K0View &K = c->p64.K0;
     const int n = K.n;
     const double rtol = c->prm.poisson_rtol;
+    const bool learned = c->learned;
+    if (learned && !c->nn.ready)
+        throw InvalidArg("the learned solver needs network weights (ibpm_nn_init or ibpm_nn_set_weights)");
+    if (learned) learned_guess(c, rhs, lam, c->st_poi);
     launch_outer_residual(s, K, rhs, lam, c->rin32, c->st_out, c->parts, 1);
     c->read_status(c->st_out);
     double bb = c->host_st->bb, rr = c->host_st->rr;
-    int inner_total = 0, outer = 0, code = IBPM_OK;
+    int inner_total = 0, outer = 0, code = IBPM_OK, fallbacks = 0;
+    bool plain = !learned;
     PrecSet<float> &P = c->p32;
     std::function<void(const float *, float *)> pre = [c](const float *r, float *z) {
         enqueue_vcycle(c, c->p32, r, z, c->st_poi);
@@ -383,6 +402,7 @@ int solve_poisson_mixed(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_
         HIPCHECK(hipMemsetAsync(lam, 0, n * sizeof(double), s));
         rr = 0.0;
     }
+    const double floor_in = c->prm.inner_rtol > 0 ? c->prm.inner_rtol : 1e-5;
     while (bb > 0.0 && rr > rtol * rtol * bb) {
         if (!(rr == rr)) {
             code = IBPM_ENAN;
@@ -393,18 +413,31 @@ int solve_poisson_mixed(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_
             break;
         }
         double need = rtol * std::sqrt(bb / rr);
-        double tol_in = std::max(0.5 * need, 1e-5);
-        ibpm_solve_stats is{};
-        int rc = pcg_drive<K0T<float>, float>(c, P.K0, n, false, pre, c->rin32, c->d32, P.r, P.z,
-                                              P.p, P.q, c->st_poi, tol_in,
-                                              c->prm.poisson_maxit - inner_total, c->est_inner,
-                                              true, false, &is);
-        inner_total += is.iters;
-        if (rc == IBPM_ENAN) {
-            code = IBPM_ENAN;
-            break;
+        double tol_in = std::max(0.5 * need, floor_in);
+        const int maxit_in = c->prm.poisson_maxit - inner_total;
+        bool add = true;
+        if (!plain) {
+            bool stall = false;
+            SolveStatus h = fcg_learned_drive<float>(c, P, c->rin32, c->d32, c->st_poi, tol_in,
+                                                     maxit_in, c->est_inner, true, &stall);
+            inner_total += h.iter;
+            if (h.done == ST_NAN) add = false;
+            if (stall || h.done == ST_NAN) {
+                plain = true;
+                fallbacks = 1;
+            }
+        } else {
+            ibpm_solve_stats is{};
+            int rc = pcg_drive<K0T<float>, float>(c, P.K0, n, false, pre, c->rin32, c->d32, P.r,
+                                                  P.z, P.p, P.q, c->st_poi, tol_in, maxit_in,
+                                                  c->est_inner, true, false, &is);
+            inner_total += is.iters;
+            if (rc == IBPM_ENAN) {
+                code = IBPM_ENAN;
+                break;
+            }
         }
-        launch_add_correction(s, n, lam, c->d32);
+        if (add) launch_add_correction(s, n, lam, c->d32);
         launch_outer_residual(s, K, rhs, lam, c->rin32, c->st_out, c->parts, 0);
         c->read_status(c->st_out);
         rr = c->host_st->rr;
@@ -417,7 +450,7 @@ int solve_poisson_mixed(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_
         out->relres = bb > 0 ? std::sqrt(rr / bb) : 0.0;
         out->ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
         out->outer_iters = outer;
-        out->fallbacks = 0;
+        out->fallbacks = fallbacks;
     }
     if (code == IBPM_ENAN) c->err = "residual became NaN";
     else if (code == IBPM_ENOTCONV) c->err = "iteration limit reached";
@@ -450,6 +483,11 @@ void nn_alloc(ibpm_ctx *c) {
     N.d = c->dalloc<double>(n);
     N.r1 = c->dalloc<double>(n);
     N.z0 = c->dalloc<double>(n);
+    if (c->mixed) {
+        N.d32 = c->dalloc<float>(n);
+        N.r132 = c->dalloc<float>(n);
+        N.z032 = c->dalloc<float>(n);
+    }
     N.st = c->dalloc<SolveStatus>(1);
     HIPCHECK(hipMemsetAsync(N.st, 0, sizeof(SolveStatus), c->stream));
     DevCSR c2p = c->upload_csr<double>(m.Dc2p), p2c = c->upload_csr<double>(m.Dp2c);
@@ -574,7 +612,8 @@ void nn_forward(ibpm_ctx *c) {
 
 // e = correction for the residual r (lambda layout): scale, features,
 // network, output (pressure and interpolated forces) times scale / dt
-void nn_apply(ibpm_ctx *c, const double *r, double *e) {
+template <class T>
+void nn_apply(ibpm_ctx *c, const T *r, T *e) {
     NNState &N = c->nn;
     hipStream_t s = c->stream;
     const Model &m = c->m;
@@ -669,50 +708,67 @@ double nn_train(ibpm_ctx *c, const float *r1, const float *e1, int S, const int3
 // Flexible CG (one-term recurrence) with the preconditioner
 //   M(r) = z0 + w d,  z0 = V(r),  r1 = r - K z0,  d = network(r1),
 //   w = (d . r1) / (d . K d)  (energy-optimal; 0 if the direction is useless)
-// and a fall-back to plain AMG-PCG from the current iterate if the residual
-// stalls or turns into NaN.
-void learned_precond(ibpm_ctx *c, const double *r, double *z, SolveStatus *st) {
+// in precision T (the V-cycle, K and the vectors; the network runs in BF16
+// with FP32 accumulation either way).
+template <class T> struct LearnedVecs { T *d, *r1, *z0; };
+LearnedVecs<double> learned_vecs(NNState &N, double *) { return {N.d, N.r1, N.z0}; }
+LearnedVecs<float> learned_vecs(NNState &N, float *) { return {N.d32, N.r132, N.z032}; }
+
+template <class T>
+void learned_precond(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *st) {
     NNState &N = c->nn;
-    PrecSet<double> &P = c->p64;
     hipStream_t s = c->stream;
-    enqueue_vcycle(c, P, r, N.z0, st, false);
-    launch_k0_residual(s, P.K0, r, (const double *)N.z0, N.r1, st);
-    nn_apply(c, N.r1, N.d);
-    launch_kd_omega(s, P.K0, N.d, N.r1, N.st, c->parts);
-    launch_axpy_omega(s, P.K0.n, N.z0, N.d, N.st, z, st);
+    LearnedVecs<T> w = learned_vecs(N, (T *)nullptr);
+    enqueue_vcycle(c, P, r, w.z0, st, false);
+    launch_k0_residual(s, P.K0, r, (const T *)w.z0, w.r1, st);
+    nn_apply<T>(c, (const T *)w.r1, w.d);
+    launch_kd_omega<T>(s, P.K0, w.d, w.r1, N.st, c->parts, st);
+    launch_axpy_omega<T>(s, P.K0.n, w.z0, w.d, N.st, z, st);
 }
 
-int solve_poisson_learned(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
-    if (!c->nn.ready) throw InvalidArg("the learned solver needs network weights (ibpm_nn_init or ibpm_nn_set_weights)");
+// Learned initial guess for K x = b from x: x += w N(b - K x) with the
+// energy-optimal w (x unchanged when w = 0).  FP64.
+void learned_guess(ibpm_ctx *c, const double *b, double *x, SolveStatus *st) {
+    NNState &N = c->nn;
     hipStream_t s = c->stream;
-    auto t0 = std::chrono::steady_clock::now();
     PrecSet<double> &P = c->p64;
-    const K0View &K = P.K0;
+    // a status that stays running (tolerance 0) so the predicated kernels act
+    launch_pcg_init(s, P.K0, b, (const double *)x, N.r1, (double *)nullptr, st, c->parts, false, 0.0, 1);
+    nn_apply<double>(c, (const double *)N.r1, N.d);
+    launch_kd_omega<double>(s, P.K0, N.d, N.r1, N.st, c->parts, st);
+    launch_axpy_omega<double>(s, P.K0.n, (const double *)x, N.d, N.st, x, st);
+}
+
+// The flexible-CG loop (iterations queued in predicated chunks as in
+// pcg_drive).  Returns the host copy of the final status; *stall is set when
+// a chunk of at least 8 iterations reduced ||r|| by less than 5 %.
+template <class T>
+SolveStatus fcg_learned_drive(ibpm_ctx *c, PrecSet<T> &P, const T *b, T *x, SolveStatus *st,
+                              double rtol, int maxit, int &est, bool zero_guess, bool *stall) {
+    hipStream_t s = c->stream;
+    const K0T<T> &K = P.K0;
     const int n = K.n;
-    SolveStatus *st = c->st_poi;
-    const double rtol = c->prm.poisson_rtol;
-    const int maxit = c->prm.poisson_maxit;
-    launch_pcg_init(s, K, rhs, (const double *)lam, P.r, (double *)nullptr, st, c->parts, false, rtol * rtol, maxit);
-    learned_precond(c, P.r, P.z, st);
-    int curp = 0, chunk = std::max(1, (int)(0.8 * c->est_poi)), queued = 0;
+    if (zero_guess) launch_pcg_init_zero(s, n, b, x, P.r, st, c->parts, rtol * rtol, maxit);
+    else launch_pcg_init(s, K, b, (const T *)x, P.r, (T *)nullptr, st, c->parts, false, rtol * rtol, maxit);
+    learned_precond<T>(c, P, P.r, P.z, st);
+    int curp = 0, chunk = std::max(1, (int)(0.8 * est)), queued = 0;
     double last_rr = -1, chunk_rr = -1;
-    int last_it = 0, fallbacks = 0;
-    bool stall = false;
+    int last_it = 0;
+    *stall = false;
     for (;;) {
         for (int k = 0; k < chunk; ++k) {
-            launch_fcg_spmv(s, K, P.z, P.p[curp], P.p[1 - curp], P.q, P.r, st, c->parts);
+            launch_fcg_spmv<T>(s, K, P.z, P.p[curp], P.p[1 - curp], P.q, P.r, st, c->parts);
             curp = 1 - curp;
-            launch_pcg_update(s, K, lam, P.r, (double *)nullptr, (const double *)P.p[curp], (const double *)P.q, st, c->parts, false);
-            learned_precond(c, P.r, P.z, st);
-            launch_fcg_beta(s, n, P.z, P.q, st, c->parts);
+            launch_pcg_update(s, K, x, P.r, (T *)nullptr, (const T *)P.p[curp], (const T *)P.q, st, c->parts, false);
+            learned_precond<T>(c, P, P.r, P.z, st);
+            launch_fcg_beta<T>(s, n, P.z, P.q, st, c->parts);
         }
         queued += chunk;
         c->read_status(st);
         const SolveStatus &h = *c->host_st;
         if (h.done != ST_RUNNING || queued > maxit + 1) break;
-        // stall: a chunk of at least 8 iterations that reduced ||r|| by less than 5 %
         if (chunk_rr > 0 && h.iter - last_it >= 8 && h.rr > 0.9025 * chunk_rr) {
-            stall = true;
+            *stall = true;
             break;
         }
         int rem = 8;
@@ -726,9 +782,25 @@ int solve_poisson_learned(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solv
         last_it = h.iter;
         chunk = std::min(std::max(rem, 8), 64);
     }
-    int fcg_iters = c->host_st->iter;
-    bool nan = c->host_st->done == ST_NAN;
-    int code = IBPM_OK;
+    if (c->host_st->iter > 0 && !*stall) est = c->host_st->iter;
+    return *c->host_st;
+}
+
+int solve_poisson_learned(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
+    if (!c->nn.ready) throw InvalidArg("the learned solver needs network weights (ibpm_nn_init or ibpm_nn_set_weights)");
+    hipStream_t s = c->stream;
+    auto t0 = std::chrono::steady_clock::now();
+    PrecSet<double> &P = c->p64;
+    const K0View &K = P.K0;
+    const int n = K.n;
+    SolveStatus *st = c->st_poi;
+    learned_guess(c, rhs, lam, st);
+    bool stall = false;
+    SolveStatus h = fcg_learned_drive<double>(c, P, rhs, lam, st, c->prm.poisson_rtol,
+                                              c->prm.poisson_maxit, c->est_poi, false, &stall);
+    const int fcg_iters = h.iter;
+    const bool nan = h.done == ST_NAN;
+    int code = IBPM_OK, fallbacks = 0;
     ibpm_solve_stats fb{};
     if (stall || nan) {
         // plain AMG-PCG from the current iterate (from zero if it is not finite)
@@ -739,10 +811,9 @@ int solve_poisson_learned(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solv
         launch_zero_if_zero_rhs(s, lam, n, st);
         launch_true_residual(s, K, rhs, (const double *)lam, st, c->parts);
         c->read_status(st);
-        const SolveStatus &h = *c->host_st;
-        if (h.iter > 0) c->est_poi = h.iter;
-        if (h.done == ST_MAXIT) code = IBPM_ENOTCONV;
-        fb.relres = h.bb > 0 ? std::sqrt(h.true_rr / h.bb) : 0.0;
+        const SolveStatus &hh = *c->host_st;
+        if (hh.done == ST_MAXIT || hh.done == ST_RUNNING) code = IBPM_ENOTCONV;
+        fb.relres = hh.bb > 0 ? std::sqrt(hh.true_rr / hh.bb) : 0.0;
     }
     auto t1 = std::chrono::steady_clock::now();
     if (out) {
@@ -753,12 +824,13 @@ int solve_poisson_learned(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solv
         out->outer_iters = 1;
         out->fallbacks = fallbacks;
     }
+    if (code == IBPM_ENOTCONV && c->err.empty()) c->err = "iteration limit reached";
     return code;
 }
 
 int solve_poisson_impl(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
-    if (c->learned) return solve_poisson_learned(c, rhs, lam, out);
     if (c->mixed) return solve_poisson_mixed(c, rhs, lam, out);
+    if (c->learned) return solve_poisson_learned(c, rhs, lam, out);
     return solve_poisson_fp64(c, rhs, lam, out);
 }
 
@@ -798,8 +870,9 @@ void check_params(const ibpm_params *p) {
     if (p->bn_order != 1) throw InvalidArg("only B^N with N = 1 is supported");
     if (!(p->vel_rtol > 0) || !(p->poisson_rtol > 0)) throw InvalidArg("tolerances must be > 0");
     if (p->vel_maxit < 1 || p->poisson_maxit < 1) throw InvalidArg("maxit must be >= 1");
-    if (p->poisson_solver < IBPM_SOLVER_JACOBI_PCG || p->poisson_solver > IBPM_SOLVER_AMG_FCG_LEARNED)
+    if (p->poisson_solver < IBPM_SOLVER_JACOBI_PCG || p->poisson_solver > IBPM_SOLVER_AMG_FCG_MIXED_LEARNED)
         throw InvalidArg("unknown Poisson solver");
+    if (!(p->inner_rtol >= 0) || p->inner_rtol >= 1) throw InvalidArg("inner_rtol must be in [0, 1)");
     if (p->poisson_solver != IBPM_SOLVER_JACOBI_PCG) {
         if (p->amg_pre < 1 || p->amg_post < 1) throw InvalidArg("AMG needs >= 1 pre and post sweep");
         if (p->amg_coarse_max < 1 || p->amg_max_levels < 1) throw InvalidArg("bad AMG limits");
@@ -872,32 +945,21 @@ void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
         dl.xa = c->dalloc<T>(dl.n);
         dl.xb = c->dalloc<T>(dl.n);
     }
-    // the one-work-group coarse cycle takes every level from the first with
-    // at most kCoarseRows unknowns (never level 0, which is matrix-free); a
-    // single work-group is latency-bound, so only the tiny levels go there
+    // levels from the first with at most kCoarseRows unknowns (never level 0,
+    // which is matrix-free) down to the coarsest are applied as one dense
+    // product: the cycle there is a fixed linear map, formed once on the host
     P.lc = L - 1;
     for (int l = 1; l < L; ++l)
         if (P.lev[l].n <= kCoarseRows) {
             P.lc = l;
             break;
         }
-    std::vector<CoarseLevel<T>> cl(L);
-    for (int l = 0; l < L; ++l) {
-        DevLevelT<T> &dl = P.lev[l];
-        CoarseLevel<T> &x = cl[l];
-        x.n = dl.n;
-        x.A = dl.A.view();
-        x.wdinv = dl.wdinv;
-        x.P = dl.P.view();
-        x.R = dl.R.view();
-        x.b = dl.b;
-        x.xa = dl.xa;
-        x.xb = dl.xb;
-        x.r = dl.r;
+    if (c->coarse_C_lc != P.lc) {
+        c->coarse_C = coarse_cycle_matrix(c->h, P.lc, c->prm.amg_pre, c->prm.amg_post);
+        c->coarse_C_lc = P.lc;
     }
-    std::vector<char> raw(sizeof(CoarseLevel<T>) * L);
-    std::memcpy(raw.data(), cl.data(), raw.size());
-    P.coarse_dev = (CoarseLevel<T> *)c->upload(raw);
+    if (!c->coarse_C_dev) c->coarse_C_dev = c->upload(c->coarse_C);
+    P.coarseC = c->coarse_C_dev;
 }
 
 template <class T>
@@ -921,8 +983,10 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
         throw InvalidArg(e.what());
     }
     c->amg = p->poisson_solver != IBPM_SOLVER_JACOBI_PCG;
-    c->mixed = p->poisson_solver == IBPM_SOLVER_AMG_PCG_MIXED;
-    c->learned = p->poisson_solver == IBPM_SOLVER_AMG_FCG_LEARNED;
+    c->mixed = p->poisson_solver == IBPM_SOLVER_AMG_PCG_MIXED ||
+               p->poisson_solver == IBPM_SOLVER_AMG_FCG_MIXED_LEARNED;
+    c->learned = p->poisson_solver == IBPM_SOLVER_AMG_FCG_LEARNED ||
+                 p->poisson_solver == IBPM_SOLVER_AMG_FCG_MIXED_LEARNED;
     if (c->amg) {
         AmgParams ap;
         ap.theta = p->amg_theta;
@@ -1294,9 +1358,10 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
             break;
         case IBPM_KERNEL_COARSE_CYCLE: {
             int L = (int)P.lev.size();
-            launch = [&] { launch_coarse_cycle(s, (const CoarseLevel<double> *)P.coarse_dev, P.lc, L, c->prm.amg_pre, c->prm.amg_post, c->coarse_inv, P.lev[L - 1].n, sb); };
-            by = 0.0;
-            for (int l = P.lc; l < L; ++l) by += (l < L - 1 ? csr_bytes(P.lev[l].A, false) : 0.0);
+            (void)L;
+            const int nlc = P.lev[P.lc].n;
+            launch = [&] { launch_coarse_dense(s, nlc, (const double *)P.coarseC, (const double *)P.lev[P.lc].b, P.lev[P.lc].xa, sb); };
+            by = 8.0 * nlc * (double)nlc + 16.0 * nlc;
             break;
         }
         default:

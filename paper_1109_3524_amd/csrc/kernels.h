@@ -7,7 +7,18 @@
 namespace ibpm {
 
 constexpr int kBlock = 256;        // threads per block (4 wave64)
-constexpr int kMaxParts = 8192;    // upper bound on blocks of a reducing kernel
+constexpr int kMaxParts = 32768;   // upper bound on blocks of a reducing kernel
+
+// Launch shapes of the reducing kernels: the largest 2-D grid of the stencil
+// walkers (the walk depth R grows until the grid fits; walk_rows > 0 forces
+// R) and the largest 1-D grid of the elementwise kernels.  Set once per
+// process (IBPM_WALK_ROWS, IBPM_MAX_BLOCKS override the defaults).
+struct LaunchShape {
+    int max_walk_blocks = 4096;
+    int walk_rows = 0;
+    int max_blocks = 8192;
+};
+LaunchShape &launch_shape();
 
 // Tensor-product staggered grid; metric arrays live on the device.
 template <class T>
@@ -164,37 +175,32 @@ void launch_csrv_spmv(hipStream_t s, CSRT<T> A, int lanes, const T *x, T *y, boo
                       const SolveStatus *st);
 
 // Coarse levels handled together by one work-group (levels lc .. L-1).
-template <class T>
-struct CoarseLevel {
-    int n;
-    CSRT<T> A;
-    const T *wdinv;
-    CSRT<T> P;     // n x n_next (unused on the coarsest level)
-    CSRT<T> R;     // n_next x n
-    T *b, *xa, *xb, *r;
-};
-constexpr int kCoarseBlock = 1024;
 constexpr int kCoarseRows = 1024;
 constexpr int kMaxLevels = 16;
-// V-cycle on levels lc..L-1 in one kernel; the input is lv[lc].b, the result
-// is left in lv[lc].xa
+// the V-cycle on the small levels (the first with at most kCoarseRows
+// unknowns and all below it) as one dense product x = C b, C row-major n x n
+// in FP64 for either precision of the cycle
 template <class T>
-void launch_coarse_cycle(hipStream_t s, const CoarseLevel<T> *lv_dev, int lc, int L, int pre,
-                         int post, const double *inv, int n_coarse, const SolveStatus *st);
+void launch_coarse_dense(hipStream_t s, int n, const double *C, const T *b, T *x,
+                         const SolveStatus *st);
 
-// flexible CG with a learned stage (FP64):
+// flexible CG with a learned stage (vectors of T, sums in FP64):
 //   p_new = z + beta p_old, q = K p_new, st->pq = p.q, st->rz = p.r
-void launch_fcg_spmv(hipStream_t s, const K0View &K, const double *z, const double *pold,
-                     double *pnew, double *q, const double *r, SolveStatus *st, double *parts);
-//   stw->beta = (d.r1) / (d.K d) (0 if not positive)
-void launch_kd_omega(hipStream_t s, const K0View &K, const double *d, const double *r1,
-                     SolveStatus *stw, double *parts);
-//   z = z0 + stw->beta d
-void launch_axpy_omega(hipStream_t s, int n, const double *z0, const double *d,
-                       const SolveStatus *stw, double *z, const SolveStatus *st);
+template <class T>
+void launch_fcg_spmv(hipStream_t s, const K0T<T> &K, const T *z, const T *pold, T *pnew, T *q,
+                     const T *r, SolveStatus *st, double *parts);
+//   stw->beta = (d.r1) / (d.K d) (0 if not positive or not finite); the sums
+//   are skipped once the solve with status st has finished
+template <class T>
+void launch_kd_omega(hipStream_t s, const K0T<T> &K, const T *d, const T *r1, SolveStatus *stw,
+                     double *parts, const SolveStatus *st);
+//   z = z0 + stw->beta d (z = z0 when the weight is 0)
+template <class T>
+void launch_axpy_omega(hipStream_t s, int n, const T *z0, const T *d, const SolveStatus *stw, T *z,
+                       const SolveStatus *st);
 //   st->beta = -(z.q) / st->pq
-void launch_fcg_beta(hipStream_t s, int n, const double *z, const double *q, SolveStatus *st,
-                     double *parts);
+template <class T>
+void launch_fcg_beta(hipStream_t s, int n, const T *z, const T *q, SolveStatus *st, double *parts);
 // harvest: e1 = x* - x - z (FP32)
 void launch_harvest_e1(hipStream_t s, int n, const double *xstar, const double *x, const double *z,
                        float *e1);

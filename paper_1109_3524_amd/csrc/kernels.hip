@@ -15,11 +15,33 @@
 // accumulate in double.
 #include "kernels.h"
 
+#include <cstdlib>
 #include <stdexcept>
 
 namespace ibpm {
 
+LaunchShape &launch_shape() {
+    static LaunchShape ls = [] {
+        LaunchShape v;
+        if (const char *e = std::getenv("IBPM_WALK_ROWS")) {
+            int r = std::atoi(e);
+            if (r == 1 || r == 2 || r == 4 || r == 8 || r == 16) v.walk_rows = r;
+        }
+        if (const char *e = std::getenv("IBPM_MAX_BLOCKS")) {
+            int b = std::atoi(e);
+            if (b >= 256 && b <= kMaxParts) v.max_blocks = b;
+        }
+        if (const char *e = std::getenv("IBPM_MAX_WALK_BLOCKS")) {
+            int b = std::atoi(e);
+            if (b >= 256 && b <= kMaxParts) v.max_walk_blocks = b;
+        }
+        return v;
+    }();
+    return ls;
+}
+
 namespace {
+
 
 __device__ __forceinline__ int remap_block(int b, int G) {
     int per = G >> 3;
@@ -44,7 +66,8 @@ __device__ __forceinline__ Tiles my_tiles(int n) {
 inline int grid_for(int n) {
     int ntiles = (n + kBlock - 1) / kBlock;
     if (ntiles < 1) ntiles = 1;
-    return ntiles < kMaxParts ? ntiles : kMaxParts;
+    const int cap = launch_shape().max_blocks;
+    return ntiles < cap ? ntiles : cap;
 }
 
 template <int N>
@@ -329,13 +352,14 @@ __global__ __launch_bounds__(kBlock) void k_pcg_init(Op op, const T *b, const T 
 
 // p_new = z + beta p_old, q = op p_new, pq = p_new . q
 template <int R, class Op, class T>
-__global__ __launch_bounds__(kBlock) void k_pcg_spmv(Op op, const T *z, const T *pold, T *pnew,
-                                                     T *q, SolveStatus *st, double *parts) {
+__global__ __launch_bounds__(kBlock) void k_pcg_spmv(Op op, const T *__restrict__ z,
+                                                     const T *__restrict__ pold,
+                                                     T *__restrict__ pnew, T *__restrict__ q,
+                                                     SolveStatus *st, double *parts) {
     if (st->done) return;
     const T beta = (T)st->beta;
     double v[1] = {0.0};
-    op_walk<R>(op, [&](int c) { return z[c] + beta * pold[c]; }, [&](int row, T qi, T, T) {
-        T pi = z[row] + beta * pold[row];
+    op_walk<R>(op, [&](int c) { return z[c] + beta * pold[c]; }, [&](int row, T qi, T, T pi) {
         pnew[row] = pi;
         q[row] = qi;
         v[0] += (double)pi * (double)qi;
@@ -362,8 +386,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(Op op, const T *x, T *y) {
 
 // x += alpha p, r -= alpha q (z = D^{-1} r for Jacobi); sums rr, rz
 template <class Op, class T>
-__global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *x, T *r, T *z, const T *p,
-                                                       const T *q, SolveStatus *st, double *parts,
+__global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *__restrict__ x, T *__restrict__ r, T *__restrict__ z, const T *__restrict__ p,
+                                                       const T *__restrict__ q, SolveStatus *st, double *parts,
                                                        int jacobi) {
     if (st->done) return;
     const int n = op_n(op);
@@ -391,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *x, T *r, T *z, 
 // V-cycle on level 0 (K0)
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_k0_jacobi_first(K0T<T> K, T omega, const T *b, T *x,
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi_first(K0T<T> K, T omega, const T *__restrict__ b, T *__restrict__ x,
                                                             const SolveStatus *st) {
     if (st->done) return;
     Tiles Tl = my_tiles(K.n);
@@ -402,8 +426,8 @@ __global__ __launch_bounds__(kBlock) void k_k0_jacobi_first(K0T<T> K, T omega, c
 }
 
 template <int R, class T>
-__global__ __launch_bounds__(kBlock) void k_k0_jacobi(K0T<T> K, T omega, const T *b, const T *xin,
-                                                      T *xout, const SolveStatus *st) {
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi(K0T<T> K, T omega, const T *__restrict__ b, const T *__restrict__ xin,
+                                                      T *__restrict__ xout, const SolveStatus *st) {
     if (st->done) return;
     k0_walk<R>(K, [&](int c) { return xin[c]; }, [&](int row, T ax, T d, T xr) {
         xout[row] = xr + omega / d * (b[row] - ax);
@@ -412,8 +436,8 @@ __global__ __launch_bounds__(kBlock) void k_k0_jacobi(K0T<T> K, T omega, const T
 
 // last post-smoothing sweep: also forms r . z for the PCG (b is the PCG residual)
 template <int R, class T>
-__global__ __launch_bounds__(kBlock) void k_k0_jacobi_rz(K0T<T> K, T omega, const T *b,
-                                                         const T *xin, T *xout, SolveStatus *st,
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi_rz(K0T<T> K, T omega, const T *__restrict__ b,
+                                                         const T *__restrict__ xin, T *__restrict__ xout, SolveStatus *st,
                                                          double *parts) {
     if (st->done) return;
     double v[1] = {0.0};
@@ -427,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_k0_jacobi_rz(K0T<T> K, T omega, cons
 }
 
 template <int R, class T>
-__global__ __launch_bounds__(kBlock) void k_k0_residual(K0T<T> K, const T *b, const T *x, T *r,
+__global__ __launch_bounds__(kBlock) void k_k0_residual(K0T<T> K, const T *__restrict__ b, const T *__restrict__ x, T *__restrict__ r,
                                                         const SolveStatus *st) {
     if (st->done) return;
     k0_walk<R>(K, [&](int c) { return x[c]; }, [&](int row, T ax, T, T) { r[row] = b[row] - ax; });
@@ -594,8 +618,8 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const doub
 
 // p_new = z + beta p_old, q = K p_new; sums p.q and p.r
 template <int R, class T>
-__global__ __launch_bounds__(kBlock) void k_fcg_spmv(K0T<T> K, const T *z, const T *pold, T *pnew,
-                                                     T *q, const T *r, SolveStatus *st,
+__global__ __launch_bounds__(kBlock) void k_fcg_spmv(K0T<T> K, const T *__restrict__ z, const T *__restrict__ pold, T *__restrict__ pnew,
+                                                     T *__restrict__ q, const T *__restrict__ r, SolveStatus *st,
                                                      double *parts) {
     if (st->done) return;
     const T beta = (T)st->beta;
@@ -610,26 +634,30 @@ __global__ __launch_bounds__(kBlock) void k_fcg_spmv(K0T<T> K, const T *z, const
 }
 
 // sums d.r1 and d.(K d)
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_kd_dots(K0View K, const double *d, const double *r1,
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_kd_dots(K0T<T> K, const T *__restrict__ d,
+                                                    const T *__restrict__ r1, const SolveStatus *st,
                                                     double *parts) {
+    if (st->done) return;
     double v[2] = {0.0, 0.0};
-    k0_walk<R>(K, [&](int c) { return d[c]; }, [&](int row, double kd, double, double dr) {
-        v[0] += dr * r1[row];
-        v[1] += dr * kd;
+    k0_walk<R>(K, [&](int c) { return d[c]; }, [&](int row, T kd, T, T dr) {
+        v[0] += (double)dr * (double)r1[row];
+        v[1] += (double)dr * (double)kd;
     });
     write_parts2<2>(v, parts);
 }
 
 // z = z0 + omega d (omega from the learned-stage status); omega = 0 drops the
-// correction altogether, so a non-finite network output never reaches z
-__global__ __launch_bounds__(kBlock) void k_axpy_omega(int n, const double *z0, const double *d,
-                                                       const SolveStatus *stw, double *z,
+// correction altogether, so a non-finite network output never reaches z.
+// z may be z0 (in-place update).
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_axpy_omega(int n, const T *z0, const T *d,
+                                                       const SolveStatus *stw, T *z,
                                                        const SolveStatus *st) {
     if (st->done) return;
     const int i = blockIdx.x * kBlock + threadIdx.x;
-    const double w = stw->beta;
-    if (i < n) z[i] = w != 0.0 ? z0[i] + w * d[i] : z0[i];
+    const T w = (T)stw->beta;
+    if (i < n) z[i] = w != T(0) ? z0[i] + w * d[i] : z0[i];
 }
 
 // generic predicated dot product a . b into a finalize kind
@@ -747,8 +775,8 @@ __device__ __forceinline__ T csrv_dot(const CSRT<T> &A, int row, const T *x, int
 }
 
 template <class T, int L>
-__global__ __launch_bounds__(kBlock) void k_csrv_jacobi(CSRT<T> A, const T *wdinv, const T *b,
-                                                        const T *xin, T *xout,
+__global__ __launch_bounds__(kBlock) void k_csrv_jacobi(CSRT<T> A, const T *__restrict__ wdinv, const T *__restrict__ b,
+                                                        const T *__restrict__ xin, T *__restrict__ xout,
                                                         const SolveStatus *st) {
     if (st->done) return;
     const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
@@ -759,7 +787,7 @@ __global__ __launch_bounds__(kBlock) void k_csrv_jacobi(CSRT<T> A, const T *wdin
 }
 
 template <class T, int L>
-__global__ __launch_bounds__(kBlock) void k_csrv_residual(CSRT<T> A, const T *b, const T *x, T *r,
+__global__ __launch_bounds__(kBlock) void k_csrv_residual(CSRT<T> A, const T *__restrict__ b, const T *__restrict__ x, T *__restrict__ r,
                                                           const SolveStatus *st) {
     if (st->done) return;
     const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
@@ -770,7 +798,7 @@ __global__ __launch_bounds__(kBlock) void k_csrv_residual(CSRT<T> A, const T *b,
 }
 
 template <class T, int L>
-__global__ __launch_bounds__(kBlock) void k_csrv_spmv(CSRT<T> A, const T *x, T *y, int add,
+__global__ __launch_bounds__(kBlock) void k_csrv_spmv(CSRT<T> A, const T *__restrict__ x, T *__restrict__ y, int add,
                                                       const SolveStatus *st) {
     if (st && st->done) return;
     const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
@@ -790,60 +818,22 @@ __device__ __forceinline__ T csr_row(const CSRT<T> &A, int row, const T *x) {
     return y;
 }
 
+// x = C b with one wave per row (C row-major FP64, FP64 accumulation; b and
+// x in the precision of the cycle)
 template <class T>
-__global__ __launch_bounds__(kCoarseBlock) void k_coarse_cycle(const CoarseLevel<T> *lv, int lc,
-                                                               int L, int pre, int post,
-                                                               const double *inv, int nc,
-                                                               const SolveStatus *st) {
+__global__ __launch_bounds__(kBlock) void k_coarse_dense(int n, const double *__restrict__ C,
+                                                         const T *__restrict__ b,
+                                                         T *__restrict__ x,
+                                                         const SolveStatus *st) {
     if (st->done) return;
-    const int tid = threadIdx.x;
-    T *cur[kMaxLevels];
-    for (int l = lc; l < L - 1; ++l) {
-        const CoarseLevel<T> d = lv[l];
-        T *a = d.xa, *o = d.xb;
-        for (int i = tid; i < d.n; i += kCoarseBlock) a[i] = d.wdinv[i] * d.b[i];
-        __syncthreads();
-        for (int k = 1; k < pre; ++k) {
-            for (int i = tid; i < d.n; i += kCoarseBlock)
-                o[i] = a[i] + d.wdinv[i] * (d.b[i] - csr_row(d.A, i, a));
-            __syncthreads();
-            T *t = a; a = o; o = t;
-        }
-        cur[l] = a;
-        for (int i = tid; i < d.n; i += kCoarseBlock) d.r[i] = d.b[i] - csr_row(d.A, i, a);
-        __syncthreads();
-        T *bn = lv[l + 1].b;
-        for (int i = tid; i < d.R.nrows; i += kCoarseBlock) bn[i] = csr_row(d.R, i, d.r);
-        __syncthreads();
-    }
-    {
-        const CoarseLevel<T> c = lv[L - 1];
-        for (int i = tid; i < nc; i += kCoarseBlock) {
-            double acc = 0.0;
-            for (int k = 0; k < nc; ++k) acc += inv[(size_t)k * nc + i] * (double)c.b[k];
-            c.xa[i] = (T)acc;
-        }
-        __syncthreads();
-        cur[L - 1] = c.xa;
-    }
-    for (int l = L - 2; l >= lc; --l) {
-        const CoarseLevel<T> d = lv[l];
-        T *a = cur[l];
-        T *o = (a == d.xa) ? d.xb : d.xa;
-        const T *xc = cur[l + 1];
-        for (int i = tid; i < d.n; i += kCoarseBlock) a[i] += csr_row(d.P, i, xc);
-        __syncthreads();
-        for (int k = 0; k < post; ++k) {
-            for (int i = tid; i < d.n; i += kCoarseBlock)
-                o[i] = a[i] + d.wdinv[i] * (d.b[i] - csr_row(d.A, i, a));
-            __syncthreads();
-            T *t = a; a = o; o = t;
-        }
-        cur[l] = a;
-    }
-    const CoarseLevel<T> d = lv[lc];
-    if (cur[lc] != d.xa)
-        for (int i = tid; i < d.n; i += kCoarseBlock) d.xa[i] = cur[lc][i];
+    const int row = blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (row >= n) return;
+    const double *c = C + (size_t)row * n;
+    double acc = 0.0;
+    for (int k = lane; k < n; k += 64) acc += c[k] * (double)b[k];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) x[row] = (T)acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -1141,16 +1131,31 @@ void launch_fill_walls(hipStream_t s, GridView g, double *w, double U, double V)
 
 
 // walk depth: the smallest R in {1, 2, 4, 8, 16} that keeps the grid within
-// 4096 blocks (the partial-sum buffer holds kMaxParts = 8192)
+// launch_shape().max_walk_blocks (or the forced depth), never beyond the
+// partial-sum buffer
+template <class Op>
+static long walk_blocks(const Op &op, int R) {
+    dim3 gd = R == 1 ? op_grid<1>(op) : R == 2 ? op_grid<2>(op) : R == 4 ? op_grid<4>(op)
+            : R == 8 ? op_grid<8>(op) : op_grid<16>(op);
+    return (long)gd.x * gd.y;
+}
+
 template <class Op>
 static int pick_R(const Op &op) {
-    for (int R : {1, 2, 4, 8}) {
-        dim3 gd = R == 1 ? op_grid<1>(op) : R == 2 ? op_grid<2>(op) : R == 4 ? op_grid<4>(op) : op_grid<8>(op);
-        if ((long)gd.x * gd.y <= 4096) return R;
+    const LaunchShape &ls = launch_shape();
+    int R = 16;
+    if (ls.walk_rows > 0) {
+        R = ls.walk_rows;
+    } else {
+        for (int r : {1, 2, 4, 8})
+            if (walk_blocks(op, r) <= ls.max_walk_blocks) {
+                R = r;
+                break;
+            }
     }
-    dim3 gd = op_grid<16>(op);
-    if ((long)gd.x * gd.y > kMaxParts) throw std::runtime_error("grid too large for the reduction buffer");
-    return 16;
+    while (R < 16 && walk_blocks(op, R) > kMaxParts) R *= 2;
+    if (walk_blocks(op, R) > kMaxParts) throw std::runtime_error("grid too large for the reduction buffer");
+    return R;
 }
 
 #define WALK_SWITCH(R, BODY)                                   \
@@ -1347,43 +1352,46 @@ void launch_csrv_spmv(hipStream_t s, CSRT<T> A, int lanes, const T *x, T *y, boo
 }
 
 template <class T>
-void launch_coarse_cycle(hipStream_t s, const CoarseLevel<T> *lv_dev, int lc, int L, int pre,
-                         int post, const double *inv, int n_coarse, const SolveStatus *st) {
-    hipLaunchKernelGGL((k_coarse_cycle<T>), dim3(1), dim3(kCoarseBlock), 0, s, lv_dev, lc, L, pre,
-                       post, inv, n_coarse, st);
+void launch_coarse_dense(hipStream_t s, int n, const double *C, const T *b, T *x, const SolveStatus *st) {
+    const int rows_per_block = kBlock / 64;
+    LAUNCH((k_coarse_dense<T>), (n + rows_per_block - 1) / rows_per_block, n, C, b, x, st);
 }
 
-void launch_fcg_spmv(hipStream_t s, const K0View &K, const double *z, const double *pold,
-                     double *pnew, double *q, const double *r, SolveStatus *st, double *parts) {
+template <class T>
+void launch_fcg_spmv(hipStream_t s, const K0T<T> &K, const T *z, const T *pold, T *pnew, T *q,
+                     const T *r, SolveStatus *st, double *parts) {
     int G = 0;
     WALK_SWITCH(pick_R(K), {
         dim3 gd = op_grid<RR>(K);
         G = gd.x * gd.y;
-        LAUNCH2((k_fcg_spmv<RR, double>), gd, K, z, pold, pnew, q, r, st, parts);
+        LAUNCH2((k_fcg_spmv<RR, T>), gd, K, z, pold, pnew, q, r, st, parts);
     })
     LAUNCH(k_finalize, 1, (int)FIN_FCG_PQ, G, parts, st, 0, 0.0, 0);
 }
 
-void launch_kd_omega(hipStream_t s, const K0View &K, const double *d, const double *r1,
-                     SolveStatus *stw, double *parts) {
+// the learned-stage weight is only computed while the solve runs (st), into stw
+template <class T>
+void launch_kd_omega(hipStream_t s, const K0T<T> &K, const T *d, const T *r1, SolveStatus *stw,
+                     double *parts, const SolveStatus *st) {
     int G = 0;
     WALK_SWITCH(pick_R(K), {
         dim3 gd = op_grid<RR>(K);
         G = gd.x * gd.y;
-        LAUNCH2((k_kd_dots<RR>), gd, K, d, r1, parts);
+        LAUNCH2((k_kd_dots<RR, T>), gd, K, d, r1, st, parts);
     })
     LAUNCH(k_finalize, 1, (int)FIN_OMEGA, G, parts, stw, 0, 0.0, 0);
 }
 
-void launch_axpy_omega(hipStream_t s, int n, const double *z0, const double *d,
-                       const SolveStatus *stw, double *z, const SolveStatus *st) {
-    LAUNCH(k_axpy_omega, (n + kBlock - 1) / kBlock, n, z0, d, stw, z, st);
+template <class T>
+void launch_axpy_omega(hipStream_t s, int n, const T *z0, const T *d, const SolveStatus *stw, T *z,
+                       const SolveStatus *st) {
+    LAUNCH((k_axpy_omega<T>), (n + kBlock - 1) / kBlock, n, z0, d, stw, z, st);
 }
 
-void launch_fcg_beta(hipStream_t s, int n, const double *z, const double *q, SolveStatus *st,
-                     double *parts) {
+template <class T>
+void launch_fcg_beta(hipStream_t s, int n, const T *z, const T *q, SolveStatus *st, double *parts) {
     int G = grid_for(n);
-    LAUNCH((k_dot<double>), G, n, z, q, st, parts);
+    LAUNCH((k_dot<T>), G, n, z, q, st, parts);
     LAUNCH(k_finalize, 1, (int)FIN_FCG_BETA, G, parts, st, 0, 0.0, 0);
 }
 
@@ -1456,9 +1464,20 @@ INST_T(float)
                                           const SolveStatus *);                                  \
     template void launch_csrv_spmv<T>(hipStream_t, CSRT<T>, int, const T *, T *, bool,           \
                                       const SolveStatus *);                                      \
-    template void launch_coarse_cycle<T>(hipStream_t, const CoarseLevel<T> *, int, int, int, int, \
-                                         const double *, int, const SolveStatus *);
+    template void launch_coarse_dense<T>(hipStream_t, int, const double *, const T *, T *,        \
+                                         const SolveStatus *);
 INST_V(double)
 INST_V(float)
+
+#define INST_F(T)                                                                                \
+    template void launch_fcg_spmv<T>(hipStream_t, const K0T<T> &, const T *, const T *, T *, T *,\
+                                     const T *, SolveStatus *, double *);                        \
+    template void launch_kd_omega<T>(hipStream_t, const K0T<T> &, const T *, const T *,          \
+                                     SolveStatus *, double *, const SolveStatus *);              \
+    template void launch_axpy_omega<T>(hipStream_t, int, const T *, const T *, const SolveStatus *,\
+                                       T *, const SolveStatus *);                                \
+    template void launch_fcg_beta<T>(hipStream_t, int, const T *, const T *, SolveStatus *, double *);
+INST_F(double)
+INST_F(float)
 
 }  // namespace ibpm

@@ -75,10 +75,11 @@ void launch_nn_scale(hipStream_t s, int n, const T *r, double *parts, double *sc
 template <class T>
 void launch_nn_features(hipStream_t s, GridView g, int nb, const T *r, const double *scale,
                         double inv_hmin, CellDelta cd, bf16 *X);
-// network output Y32 [H][W][32] -> correction e (lambda layout, FP64) times
+// network output Y32 [H][W][32] -> correction e (lambda layout, T) times
 // scale/dt: pressure from channel 0, forces interpolated from channels 1, 2
+template <class T>
 void launch_nn_output(hipStream_t s, int n_cell, int nb, const float *Y32, const double *scale,
-                      double inv_dt, CellDelta cd, double *e);
+                      double inv_dt, CellDelta cd, T *e);
 // training loss of Y32 against the target t * dt / scale (t in lambda layout,
 // FP32): L_phi / D_phi + L_f / D_f (squared errors over squared targets,
 // pressure cells and interpolated forces) into st->rr, and dL/dY32 into dY

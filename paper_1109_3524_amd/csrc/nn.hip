@@ -261,13 +261,14 @@ __global__ __launch_bounds__(kBlock) void k_nn_features(GridView g, int nb, cons
     *(bf16x8 *)&X[(size_t)p * 8] = v;
 }
 
+template <class T>
 __global__ __launch_bounds__(kBlock) void k_nn_output(int n_cell, int nb, const float *Y32,
                                                       const double *scale, double inv_dt,
-                                                      CellDelta cd, double *e) {
+                                                      CellDelta cd, T *e) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     const double sc = scale[0] * inv_dt;
     if (t < n_cell) {
-        e[t] = sc * (double)Y32[(size_t)t * 32];
+        e[t] = (T)(sc * (double)Y32[(size_t)t * 32]);
     } else if (t < n_cell + 2 * nb) {
         const int k = t - n_cell;
         const int pk = k < nb ? k : k - nb;
@@ -275,7 +276,7 @@ __global__ __launch_bounds__(kBlock) void k_nn_output(int n_cell, int nb, const 
         double s = 0.0;
         for (int q = cd.p2c.ptr[pk]; q < cd.p2c.ptr[pk + 1]; ++q)
             s += cd.p2c.val[q] * (double)Y32[(size_t)cd.p2c.col[q] * 32 + ch];
-        e[t] = sc * s;
+        e[t] = (T)(sc * s);
     }
 }
 
@@ -431,10 +432,11 @@ void launch_nn_features(hipStream_t s, GridView g, int nb, const T *r, const dou
     LAUNCH((k_nn_features<T>), (g.n_cell + kBlock - 1) / kBlock, g, nb, r, scale, inv_hmin, cd, X);
 }
 
+template <class T>
 void launch_nn_output(hipStream_t s, int n_cell, int nb, const float *Y32, const double *scale,
-                      double inv_dt, CellDelta cd, double *e) {
+                      double inv_dt, CellDelta cd, T *e) {
     int n = n_cell + 2 * nb;
-    LAUNCH(k_nn_output, (n + kBlock - 1) / kBlock, n_cell, nb, Y32, scale, inv_dt, cd, e);
+    LAUNCH((k_nn_output<T>), (n + kBlock - 1) / kBlock, n_cell, nb, Y32, scale, inv_dt, cd, e);
 }
 
 void launch_nn_loss(hipStream_t s, GridView g, int nb, const float *Y32, const float *t,
@@ -467,5 +469,10 @@ template void launch_nn_features<double>(hipStream_t, GridView, int, const doubl
                                          const double *, double, CellDelta, bf16 *);
 template void launch_nn_features<float>(hipStream_t, GridView, int, const float *,
                                         const double *, double, CellDelta, bf16 *);
+
+template void launch_nn_output<double>(hipStream_t, int, int, const float *, const double *, double,
+                                       CellDelta, double *);
+template void launch_nn_output<float>(hipStream_t, int, int, const float *, const double *, double,
+                                      CellDelta, float *);
 
 }  // namespace ibpm

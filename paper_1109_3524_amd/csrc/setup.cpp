@@ -658,4 +658,59 @@ void build_hierarchy(Hierarchy &h, const CSR &K, const AmgParams &prm) {
     dense_spd_inverse(Ac, h.coarse_inv);
 }
 
+namespace {
+
+void csr_apply(const CSR &A, const double *x, double *y) {
+    for (int i = 0; i < A.nrows; ++i) {
+        double s = 0.0;
+        for (int p = A.ptr[i]; p < A.ptr[i + 1]; ++p) s += A.val[p] * x[A.col[p]];
+        y[i] = s;
+    }
+}
+
+// x = cycle_l(b) on levels l..L-1 (x has n_l entries)
+void cycle_from(const Hierarchy &h, int l, int pre, int post, const std::vector<double> &b,
+                std::vector<double> &x) {
+    const int L = (int)h.levels.size();
+    const Level &lv = h.levels[l];
+    const int n = lv.A.nrows;
+    x.assign(n, 0.0);
+    if (l == L - 1) {
+        const int nc = h.n_coarse;
+        for (int k = 0; k < nc; ++k)
+            for (int i = 0; i < nc; ++i) x[i] += h.coarse_inv[(size_t)k * nc + i] * b[k];
+        return;
+    }
+    std::vector<double> ax(n), r(n);
+    auto sweep = [&]() {
+        csr_apply(lv.A, x.data(), ax.data());
+        for (int i = 0; i < n; ++i) x[i] += lv.wdinv[i] * (b[i] - ax[i]);
+    };
+    for (int i = 0; i < n; ++i) x[i] = lv.wdinv[i] * b[i];
+    for (int k = 1; k < pre; ++k) sweep();
+    csr_apply(lv.A, x.data(), ax.data());
+    for (int i = 0; i < n; ++i) r[i] = b[i] - ax[i];
+    std::vector<double> bc(lv.R.nrows), xc, px(n);
+    csr_apply(lv.R, r.data(), bc.data());
+    cycle_from(h, l + 1, pre, post, bc, xc);
+    csr_apply(lv.P, xc.data(), px.data());
+    for (int i = 0; i < n; ++i) x[i] += px[i];
+    for (int k = 0; k < post; ++k) sweep();
+}
+
+}  // namespace
+
+std::vector<double> coarse_cycle_matrix(const Hierarchy &h, int lc, int pre, int post) {
+    if (lc < 0 || lc >= (int)h.levels.size() || pre < 1) fail("coarse cycle: bad level or sweep count");
+    const int n = h.levels[lc].A.nrows;
+    std::vector<double> C((size_t)n * n), e(n, 0.0), x;
+    for (int j = 0; j < n; ++j) {
+        e[j] = 1.0;
+        cycle_from(h, lc, pre, post, e, x);
+        e[j] = 0.0;
+        for (int i = 0; i < n; ++i) C[(size_t)i * n + j] = x[i];
+    }
+    return C;
+}
+
 }  // namespace ibpm

@@ -80,6 +80,11 @@ void build_model(Model &m, int nx, int ny, const double *xf, const double *yf, i
                  const double *xb, const double *yb, const double *ubx, const double *uby,
                  double nu, double dt);
 void build_hierarchy(Hierarchy &h, const CSR &K, const AmgParams &p);
+// The V-cycle restricted to levels lc..L-1 (pre >= 1 damped-Jacobi sweeps,
+// the first from zero, restriction, recursion, exact solve on the coarsest
+// level, prolongation, post sweeps) is a fixed linear map b -> x; returns its
+// matrix, row-major n_lc x n_lc.
+std::vector<double> coarse_cycle_matrix(const Hierarchy &h, int lc, int pre, int post);
 
 // helpers exposed for the host tests
 double roma_phi(double s);

@@ -68,6 +68,7 @@ class Params(ctypes.Structure):
         ("poisson_maxit", ctypes.c_int32),
         ("amg_theta", ctypes.c_double), ("amg_pre", ctypes.c_int32), ("amg_post", ctypes.c_int32),
         ("amg_coarse_max", ctypes.c_int32), ("amg_max_levels", ctypes.c_int32),
+        ("inner_rtol", ctypes.c_double),
     ]
 
 
@@ -158,7 +159,7 @@ def params_from_workload(wl: W.Workload, **over) -> dict:
              poisson_solver=wl.poisson_solver, poisson_rtol=wl.poisson_rtol,
              poisson_maxit=wl.poisson_maxit, amg_theta=wl.amg_theta, amg_pre=wl.amg_pre,
              amg_post=wl.amg_post, amg_coarse_max=wl.amg_coarse_max,
-             amg_max_levels=wl.amg_max_levels)
+             amg_max_levels=wl.amg_max_levels, inner_rtol=0.0)
     p.update(over)
     return p
 

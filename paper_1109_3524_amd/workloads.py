@@ -26,6 +26,7 @@ SOLVER_JACOBI_PCG = 0
 SOLVER_AMG_PCG = 1
 SOLVER_AMG_PCG_MIXED = 2
 SOLVER_AMG_FCG_LEARNED = 3
+SOLVER_AMG_FCG_MIXED_LEARNED = 4
 
 
 def stretch_ratio(n_side: int, h: float, width: float) -> float:

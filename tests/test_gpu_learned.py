@@ -287,3 +287,25 @@ def test_learned_trajectory_velocity_and_drag():
     print(f"  96^2 learned x 10 steps: velocity err {eu:.2e}, Cd err {ecd:.2e}", flush=True)
     assert eu < 1e-7 and ecd < 1e-6
     ctx.close()
+
+
+def test_mixed_learned_trajectory_velocity_and_drag():
+    """FP32 inner flexible CG with the learned stage inside FP64 refinement:
+    fields within 1e-7 and drag within 1e-6 of the FP64 oracle."""
+    wl = W.cylinder_small(96, 60).replace(poisson_solver=4)
+    print(f"[mixed+learned trajectory] {wl.name}", flush=True)
+    ctx = ibpm.Context(wl, poisson_solver=4, poisson_rtol=1e-8)
+    ctx.nn_init(11)
+    q, conv, lam = ctx.init_state()
+    for _ in range(10):
+        sm = ctx.step(q, conv, lam, 1)
+    P = Problem(wl, poisson_solver=1, vel_rtol=TIGHT, poisson_rtol=TIGHT)
+    ost, infos = P.run(10)
+    R = P.grid.R_diag()
+    eu = _rel(_n(q) / R, ost.q / R)
+    ecd = abs(sm["fx"] - infos[-1].fx) / abs(infos[-1].fx)
+    print(f"  96^2 mixed+learned x 10 steps: velocity err {eu:.2e}, Cd err {ecd:.2e}, "
+          f"Poisson iters/step {sm['poisson_iters'] / 10:.1f}", flush=True)
+    assert sm["poisson_relres_max"] <= 1e-8
+    assert eu < 1e-7 and ecd < 1e-6
+    ctx.close()
