@@ -232,8 +232,14 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
     {
         DevLevelT<T> &l0 = P.lev[0];
         T *a = l0.xa, *b = l0.xb;
-        launch_k0_jacobi_first(s, K, l0.omega, r, a, st);
-        for (int k = 1; k < pre; ++k) {
+        int k = 1;
+        if (pre >= 2) {
+            launch_k0_presmooth2(s, K, (const T *)l0.wdinv, r, a, st);
+            k = 2;
+        } else {
+            launch_k0_jacobi_first(s, K, l0.omega, r, a, st);
+        }
+        for (; k < pre; ++k) {
             launch_k0_jacobi(s, K, l0.omega, r, a, b, st);
             std::swap(a, b);
         }
@@ -936,6 +942,11 @@ void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
             dl.A = c->upload_csr<T>(hl.A);
             dl.wdinv = c->upload(std::vector<T>(hl.wdinv.begin(), hl.wdinv.end()));
             dl.b = c->dalloc<T>(dl.n);
+        } else {
+            // level 0 is matrix-free; its smoother weights omega / k_ii are
+            // formed on the device from the same stencil
+            dl.wdinv = c->dalloc<T>(dl.n);
+            launch_k0_wdinv(c->stream, P.K0, hl.omega, dl.wdinv);
         }
         if (l < L - 1) {
             dl.P = c->upload_csr<T>(hl.P);
@@ -1319,48 +1330,74 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
         SolveStatus *sb = c->st_bench;
         double by = 0;
         std::function<void()> launch;
+        // every launch below captures its arguments by value: the lambda runs
+        // after the switch, when block-scoped locals no longer exist
+        const K0View K0 = K;
+        double *parts = c->parts;
         switch (kernel) {
         case IBPM_KERNEL_K0_JACOBI: {
-            DevLevelT<double> &l0 = P.lev[0];
-            launch = [&] { launch_k0_jacobi(s, K, l0.omega, (const double *)P.r, (const double *)l0.xa, l0.xb, sb); };
+            const DevLevelT<double> &l0 = P.lev[0];
+            const double omega = l0.omega, *r = P.r, *xa = l0.xa;
+            double *xb = l0.xb;
+            launch = [=] { launch_k0_jacobi(s, K0, omega, r, xa, xb, sb); };
             by = 24.0 * n + b_coupling + b_metric;
             break;
         }
-        case IBPM_KERNEL_K0_PCG_SPMV:
-            launch = [&] { launch_pcg_spmv(s, K, (const double *)P.z, (const double *)P.p[0], P.p[1], P.q, sb, c->parts); };
+        case IBPM_KERNEL_K0_PCG_SPMV: {
+            const double *z = P.z, *p0 = P.p[0];
+            double *p1 = P.p[1], *q = P.q;
+            launch = [=] { launch_pcg_spmv(s, K0, z, p0, p1, q, sb, parts); };
             by = 32.0 * n + b_coupling + b_metric;
             break;
-        case IBPM_KERNEL_A_PCG_SPMV:
-            launch = [&] { launch_pcg_spmv(s, c->A, (const double *)c->vz, (const double *)c->vp[0], c->vp[1], c->vq, sb, c->parts); };
+        }
+        case IBPM_KERNEL_A_PCG_SPMV: {
+            const AView A = c->A;
+            const double *z = c->vz, *p0 = c->vp[0];
+            double *p1 = c->vp[1], *q = c->vq;
+            launch = [=] { launch_pcg_spmv(s, A, z, p0, p1, q, sb, parts); };
             by = 32.0 * nq + b_metric;
             break;
+        }
         case IBPM_KERNEL_K0_RESIDUAL: {
-            DevLevelT<double> &l0 = P.lev[0];
-            launch = [&] { launch_k0_residual(s, K, (const double *)P.r, (const double *)l0.xa, l0.r, sb); };
+            const DevLevelT<double> &l0 = P.lev[0];
+            const double *r = P.r, *xa = l0.xa;
+            double *out = l0.r;
+            launch = [=] { launch_k0_residual(s, K0, r, xa, out, sb); };
             by = 24.0 * n + b_coupling + b_metric;
             break;
         }
         case IBPM_KERNEL_RESTRICT0: {
-            DevLevelT<double> &l0 = P.lev[0];
-            launch = [&] { launch_csrv_spmv(s, l0.R.view(), l0.R.lanes, (const double *)l0.r, P.lev[1].b, false, sb); };
+            const DevLevelT<double> &l0 = P.lev[0];
+            const CSRView R0 = l0.R.view();
+            const int lanes = l0.R.lanes;
+            const double *r = l0.r;
+            double *b1 = P.lev[1].b;
+            launch = [=] { launch_csrv_spmv(s, R0, lanes, r, b1, false, sb); };
             by = csr_bytes(l0.R, false);
             break;
         }
         case IBPM_KERNEL_PROLONG0: {
-            DevLevelT<double> &l0 = P.lev[0];
-            launch = [&] { launch_csrv_spmv(s, l0.P.view(), l0.P.lanes, (const double *)P.lev[1].xa, l0.xa, true, sb); };
+            const DevLevelT<double> &l0 = P.lev[0];
+            const CSRView P0 = l0.P.view();
+            const int lanes = l0.P.lanes;
+            const double *x1 = P.lev[1].xa;
+            double *x0 = l0.xa;
+            launch = [=] { launch_csrv_spmv(s, P0, lanes, x1, x0, true, sb); };
             by = csr_bytes(l0.P, true);
             break;
         }
-        case IBPM_KERNEL_PCG_UPDATE_K:
-            launch = [&] { launch_pcg_update(s, K, P.p[1], P.r, P.z, (const double *)P.p[0], (const double *)P.q, sb, c->parts, false); };
+        case IBPM_KERNEL_PCG_UPDATE_K: {
+            double *x = P.p[1], *r = P.r, *z = P.z;
+            const double *p0 = P.p[0], *q = P.q;
+            launch = [=] { launch_pcg_update(s, K0, x, r, z, p0, q, sb, parts, false); };
             by = 48.0 * n;
             break;
+        }
         case IBPM_KERNEL_COARSE_CYCLE: {
-            int L = (int)P.lev.size();
-            (void)L;
             const int nlc = P.lev[P.lc].n;
-            launch = [&] { launch_coarse_dense(s, nlc, (const double *)P.coarseC, (const double *)P.lev[P.lc].b, P.lev[P.lc].xa, sb); };
+            const double *C = P.coarseC, *b = P.lev[P.lc].b;
+            double *x = P.lev[P.lc].xa;
+            launch = [=] { launch_coarse_dense(s, nlc, C, b, x, sb); };
             by = 8.0 * nlc * (double)nlc + 16.0 * nlc;
             break;
         }

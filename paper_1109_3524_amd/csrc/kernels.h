@@ -134,6 +134,13 @@ template <class T>
 void launch_zero_if_zero_rhs(hipStream_t s, T *x, int n, const SolveStatus *st);
 
 // V-cycle pieces, predicated on st->done
+// wd = omega / diag(K0)
+template <class T>
+void launch_k0_wdinv(hipStream_t s, const K0T<T> &K, double omega, T *wd);
+// two damped-Jacobi sweeps from x = 0 in one pass: x = y + wd (b - K y), y = wd b
+template <class T>
+void launch_k0_presmooth2(hipStream_t s, const K0T<T> &K, const T *wd, const T *b, T *x,
+                          const SolveStatus *st);
 template <class T>
 void launch_k0_jacobi_first(hipStream_t s, const K0T<T> &K, double omega, const T *b, T *x,
                             const SolveStatus *st);

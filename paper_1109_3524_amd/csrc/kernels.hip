@@ -425,6 +425,26 @@ __global__ __launch_bounds__(kBlock) void k_k0_jacobi_first(K0T<T> K, T omega, c
     }
 }
 
+// wd = omega / diag(K) on level 0
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_k0_wdinv(K0T<T> K, T omega, T *__restrict__ wd) {
+    const int row = blockIdx.x * kBlock + threadIdx.x;
+    if (row < K.n) wd[row] = omega / k0_diag(K, row);
+}
+
+// the first two pre-smoothing sweeps in one pass: y = wd b (the sweep from
+// zero) is formed wherever K y needs it, then x = y + wd (b - K y)
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_k0_presmooth2(K0T<T> K, const T *__restrict__ wd,
+                                                          const T *__restrict__ b,
+                                                          T *__restrict__ x,
+                                                          const SolveStatus *st) {
+    if (st->done) return;
+    k0_walk<R>(K, [&](int c) { return wd[c] * b[c]; }, [&](int row, T ky, T, T yr) {
+        x[row] = yr + wd[row] * (b[row] - ky);
+    });
+}
+
 template <int R, class T>
 __global__ __launch_bounds__(kBlock) void k_k0_jacobi(K0T<T> K, T omega, const T *__restrict__ b, const T *__restrict__ xin,
                                                       T *__restrict__ xout, const SolveStatus *st) {
@@ -1242,6 +1262,17 @@ void launch_zero_if_zero_rhs(hipStream_t s, T *x, int n, const SolveStatus *st) 
 }
 
 template <class T>
+void launch_k0_wdinv(hipStream_t s, const K0T<T> &K, double omega, T *wd) {
+    LAUNCH((k_k0_wdinv<T>), (K.n + kBlock - 1) / kBlock, K, (T)omega, wd);
+}
+
+template <class T>
+void launch_k0_presmooth2(hipStream_t s, const K0T<T> &K, const T *wd, const T *b, T *x,
+                          const SolveStatus *st) {
+    WALK_SWITCH(pick_R(K), LAUNCH2((k_k0_presmooth2<RR, T>), op_grid<RR>(K), K, wd, b, x, st))
+}
+
+template <class T>
 void launch_k0_jacobi_first(hipStream_t s, const K0T<T> &K, double omega, const T *b, T *x,
                             const SolveStatus *st) {
     LAUNCH((k_k0_jacobi_first<T>), grid_for(K.n), K, (T)omega, b, x, st);
@@ -1353,6 +1384,8 @@ void launch_csrv_spmv(hipStream_t s, CSRT<T> A, int lanes, const T *x, T *y, boo
 
 template <class T>
 void launch_coarse_dense(hipStream_t s, int n, const double *C, const T *b, T *x, const SolveStatus *st) {
+    if (n < 1 || n > 8192 || !C || !b || !x)
+        throw std::runtime_error("coarse cycle: bad size or operand");
     const int rows_per_block = kBlock / 64;
     LAUNCH((k_coarse_dense<T>), (n + rows_per_block - 1) / rows_per_block, n, C, b, x, st);
 }
@@ -1435,6 +1468,9 @@ INST_OP(K0T<float>, float)
     template void launch_dot_rz<T>(hipStream_t, int, const T *, const T *, SolveStatus *,        \
                                    double *);                                                    \
     template void launch_zero_if_zero_rhs<T>(hipStream_t, T *, int, const SolveStatus *);        \
+    template void launch_k0_wdinv<T>(hipStream_t, const K0T<T> &, double, T *);                   \
+    template void launch_k0_presmooth2<T>(hipStream_t, const K0T<T> &, const T *, const T *, T *,  \
+                                          const SolveStatus *);                                   \
     template void launch_k0_jacobi_first<T>(hipStream_t, const K0T<T> &, double, const T *, T *, \
                                             const SolveStatus *);                                \
     template void launch_k0_jacobi<T>(hipStream_t, const K0T<T> &, double, const T *, const T *, \
