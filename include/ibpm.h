@@ -201,13 +201,18 @@ int ibpm_get_aggregates(const ibpm_ctx *ctx, int32_t level, int32_t *agg);
 #define IBPM_KERNEL_RESTRICT0     4   /* b1 = P0^T r (finest to first coarse level) */
 #define IBPM_KERNEL_PROLONG0      5   /* x += P0 x1 */
 #define IBPM_KERNEL_PCG_UPDATE_K  6   /* x += a p; r -= a q; r . r */
-#define IBPM_KERNEL_COARSE_CYCLE  7   /* the V-cycle on the small levels, one work-group */
+#define IBPM_KERNEL_COARSE_CYCLE  7   /* the V-cycle on the small levels as one dense product */
+#define IBPM_KERNEL_PRESMOOTH0    8   /* two damped Jacobi sweeps from zero on the finest level */
+#define IBPM_KERNEL_STREAM_COPY   9   /* y = x over 2^25 doubles (256 MiB each way): the
+                                         reference for bandwidth and for traffic counters */
 
 /* Time `reps` back-to-back launches of one kernel of the solver on the
  * context's stream with HIP events and return the mean duration of one
  * launch (ms) and the algorithmic bytes of one launch (every operand read
  * once, every result written once).  Overwrites the context's work vectors
- * (not the caller's).  Needs an AMG context for kernels 0, 3, 4, 5, 7. */
+ * (not the caller's).  Needs an AMG context for kernels 0, 3, 4, 5, 7, 8.
+ * The copy kernel's buffers are allocated on its first use and kept until
+ * ibpm_destroy. */
 int ibpm_time_kernel(ibpm_ctx *ctx, int32_t kernel, int32_t reps, double *avg_ms,
                      double *bytes);
 

@@ -121,6 +121,7 @@ struct ibpm_ctx {
     double *coarse_inv = nullptr;
     std::vector<double> coarse_C;      // host copy of the dense coarse-cycle matrix
     double *coarse_C_dev = nullptr;    // its device copy (shared by both precisions)
+    double *copy_x = nullptr, *copy_y = nullptr;   // bandwidth reference buffers
     int coarse_C_lc = -1;
     // velocity PCG (n_q)
     double *vr = nullptr, *vz = nullptr, *vp[2] = {nullptr, nullptr}, *vq = nullptr;
@@ -128,6 +129,7 @@ struct ibpm_ctx {
     SolveStatus *st_vel = nullptr, *st_poi = nullptr, *st_misc = nullptr, *st_bench = nullptr,
                 *st_out = nullptr;
     double *parts = nullptr;
+    double *parts2 = nullptr;          // second partial-sum buffer (read by the next kernel)
     SolveStatus *host_st = nullptr;   // pinned
     int est_vel = 8, est_poi = 32, est_inner = 32;
     bool learned = false;
@@ -311,9 +313,10 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
     int last_it = 0;
     for (;;) {
         for (int k = 0; k < chunk; ++k) {
-            launch_pcg_spmv(s, op, (const T *)z, (const T *)p[curp], p[1 - curp], q, st, c->parts);
+            launch_pcg_spmv(s, op, (const T *)z, (const T *)p[curp], p[1 - curp], q, st, c->parts2);
             curp = 1 - curp;
-            launch_pcg_update(s, op, x, r, z, (const T *)p[curp], (const T *)q, st, c->parts, jacobi);
+            launch_pcg_update(s, op, x, r, z, (const T *)p[curp], (const T *)q, st,
+                              (const double *)c->parts2, c->parts, jacobi);
             if (!jacobi) precond(r, z);
         }
         queued += chunk;
@@ -765,7 +768,8 @@ SolveStatus fcg_learned_drive(ibpm_ctx *c, PrecSet<T> &P, const T *b, T *x, Solv
         for (int k = 0; k < chunk; ++k) {
             launch_fcg_spmv<T>(s, K, P.z, P.p[curp], P.p[1 - curp], P.q, P.r, st, c->parts);
             curp = 1 - curp;
-            launch_pcg_update(s, K, x, P.r, (T *)nullptr, (const T *)P.p[curp], (const T *)P.q, st, c->parts, false);
+            launch_pcg_update(s, K, x, P.r, (T *)nullptr, (const T *)P.p[curp], (const T *)P.q, st,
+                              (const double *)nullptr, c->parts, false);
             learned_precond<T>(c, P, P.r, P.z, st);
             launch_fcg_beta<T>(s, n, P.z, P.q, st, c->parts);
         }
@@ -1067,6 +1071,7 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     c->st_bench = sts + 3;
     c->st_out = sts + 4;
     c->parts = c->dalloc<double>(4 * kMaxParts);
+    c->parts2 = c->dalloc<double>(4 * kMaxParts);
     HIPCHECK(hipHostMalloc((void **)&c->host_st, sizeof(SolveStatus), hipHostMallocDefault));
     double U = p->uinf * std::cos(p->alpha), V = p->uinf * std::sin(p->alpha);
     launch_fill_walls(c->stream, c->g, c->walls[0], U, V);
@@ -1298,7 +1303,7 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
         if (reps < 1 || !avg_ms) throw InvalidArg("bad arguments");
         const bool needs_amg = kernel == IBPM_KERNEL_K0_JACOBI || kernel == IBPM_KERNEL_K0_RESIDUAL ||
                                kernel == IBPM_KERNEL_RESTRICT0 || kernel == IBPM_KERNEL_PROLONG0 ||
-                               kernel == IBPM_KERNEL_COARSE_CYCLE;
+                               kernel == IBPM_KERNEL_COARSE_CYCLE || kernel == IBPM_KERNEL_PRESMOOTH0;
         PrecSet<double> &P = c->p64;
         if (needs_amg && (!c->amg || P.lev.size() < 2)) throw InvalidArg("kernel needs an AMG hierarchy");
         hipStream_t s = c->stream;
@@ -1389,7 +1394,10 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
         case IBPM_KERNEL_PCG_UPDATE_K: {
             double *x = P.p[1], *r = P.r, *z = P.z;
             const double *p0 = P.p[0], *q = P.q;
-            launch = [=] { launch_pcg_update(s, K0, x, r, z, p0, q, sb, parts, false); };
+            // p . q partials of the product kernel for the update to sum
+            launch_pcg_spmv(s, K0, (const double *)P.z, (const double *)P.p[0], P.p[1], P.q, sb, c->parts2);
+            const double *pq_parts = c->parts2;
+            launch = [=] { launch_pcg_update(s, K0, x, r, z, p0, q, sb, pq_parts, parts, false); };
             by = 48.0 * n;
             break;
         }
@@ -1399,6 +1407,27 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
             double *x = P.lev[P.lc].xa;
             launch = [=] { launch_coarse_dense(s, nlc, C, b, x, sb); };
             by = 8.0 * nlc * (double)nlc + 16.0 * nlc;
+            break;
+        }
+        case IBPM_KERNEL_PRESMOOTH0: {
+            const DevLevelT<double> &l0 = P.lev[0];
+            const double *wd = l0.wdinv, *r = P.r;
+            double *xa = l0.xa;
+            launch = [=] { launch_k0_presmooth2(s, K0, wd, r, xa, sb); };
+            by = 24.0 * n + b_coupling + b_metric;
+            break;
+        }
+        case IBPM_KERNEL_STREAM_COPY: {
+            const size_t nc = (size_t)1 << 25;
+            if (!c->copy_x) {
+                c->copy_x = c->dalloc<double>(nc);
+                c->copy_y = c->dalloc<double>(nc);
+                HIPCHECK(hipMemsetAsync(c->copy_x, 0, nc * sizeof(double), s));
+            }
+            const double *x = c->copy_x;
+            double *y = c->copy_y;
+            launch = [=] { launch_stream_copy(s, nc, x, y); };
+            by = 16.0 * nc;
             break;
         }
         default:
@@ -1549,9 +1578,10 @@ int ibpm_harvest(ibpm_ctx *c, const double *rhs, double *x, const double *xstar,
             // r1 = r - K V(r) (FP32) and e1 = x* - x - V(r)
             launch_outer_residual(s, K, P.r, P.z, r1_out + (size_t)k * n, c->st_bench, c->parts, 1);
             launch_harvest_e1(s, n, xstar, x, P.z, e1_out + (size_t)k * n);
-            launch_pcg_spmv(s, K, (const double *)P.z, (const double *)P.p[curp], P.p[1 - curp], P.q, st, c->parts);
+            launch_pcg_spmv(s, K, (const double *)P.z, (const double *)P.p[curp], P.p[1 - curp], P.q, st, c->parts2);
             curp = 1 - curp;
-            launch_pcg_update(s, K, x, P.r, (double *)nullptr, (const double *)P.p[curp], (const double *)P.q, st, c->parts, false);
+            launch_pcg_update(s, K, x, P.r, (double *)nullptr, (const double *)P.p[curp], (const double *)P.q, st,
+                              (const double *)c->parts2, c->parts, false);
             enqueue_vcycle(c, P, (const double *)P.r, P.z, st);
         }
         HIPCHECK(hipStreamSynchronize(s));

@@ -117,14 +117,17 @@ void launch_pcg_init(hipStream_t s, const Op &op, const T *b, const T *x, T *r, 
 template <class T>
 void launch_pcg_init_zero(hipStream_t s, int n, const T *b, T *x, T *r, SolveStatus *st,
                           double *parts, double rtol2, int maxit);
-// p_new = z + beta p_old; q = op p_new
+// p_new = z + beta p_old; q = op p_new; per-block partials of p . q in parts
+// (no finalize: the update below sums them)
 template <class Op, class T>
 void launch_pcg_spmv(hipStream_t s, const Op &op, const T *z, const T *pold, T *pnew, T *q,
                      SolveStatus *st, double *parts);
-// x += alpha p; r -= alpha q (and z = D^{-1} r for Jacobi)
+// x += alpha p; r -= alpha q (and z = D^{-1} r for Jacobi), alpha = rz / pq
+// with pq summed from pq_parts (the product kernel's partials; another
+// buffer than parts) or, when pq_parts is null, taken from st->pq
 template <class Op, class T>
 void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, T *z, const T *p, const T *q,
-                       SolveStatus *st, double *parts, bool jacobi);
+                       SolveStatus *st, const double *pq_parts, double *parts, bool jacobi);
 template <class Op, class T>
 void launch_true_residual(hipStream_t s, const Op &op, const T *b, const T *x, SolveStatus *st,
                           double *parts);
@@ -190,6 +193,9 @@ constexpr int kMaxLevels = 16;
 template <class T>
 void launch_coarse_dense(hipStream_t s, int n, const double *C, const T *b, T *x,
                          const SolveStatus *st);
+
+// y = x (n even), a plain streaming copy for bandwidth reference
+void launch_stream_copy(hipStream_t s, size_t n, const double *x, double *y);
 
 // flexible CG with a learned stage (vectors of T, sums in FP64):
 //   p_new = z + beta p_old, q = K p_new, st->pq = p.q, st->rz = p.r

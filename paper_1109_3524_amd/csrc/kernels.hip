@@ -72,20 +72,26 @@ inline int grid_for(int n) {
 
 template <int N>
 __device__ __forceinline__ void block_sum(double (&v)[N]) {
-    __shared__ double sh[N][kBlock];
-    const int t = threadIdx.x;
+    // butterfly within each wave (no barriers), then the four wave sums in
+    // wave order: a fixed summation order, so results are reproducible
+    constexpr int kWaves = kBlock / 64;
+    __shared__ double sh[N][kWaves];
 #pragma unroll
-    for (int k = 0; k < N; ++k) sh[k][t] = v[k];
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v[k] += __shfl_xor(v[k], o, 64);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k) sh[k][w] = v[k];
     __syncthreads();
-    for (int s = kBlock / 2; s > 0; s >>= 1) {
-        if (t < s) {
 #pragma unroll
-            for (int k = 0; k < N; ++k) sh[k][t] += sh[k][t + s];
-        }
-        __syncthreads();
+    for (int k = 0; k < N; ++k) {
+        double a = sh[k][0];
+#pragma unroll
+        for (int q = 1; q < kWaves; ++q) a += sh[k][q];
+        v[k] = a;
     }
-#pragma unroll
-    for (int k = 0; k < N; ++k) v[k] = sh[k][0];
     __syncthreads();
 }
 
@@ -110,11 +116,19 @@ __device__ __forceinline__ bool bad(double v) { return !(v == v) || v > 1e300; }
 // walking up the column so that the south / centre / north operands stay in
 // registers (each is loaded once), east / west come from the neighbouring
 // lanes' loads (L1), and the 1-D metrics of a row are wave-uniform.  Rows
-// that are not on the tensor grid (the 2 nb force rows of K) are taken by
-// one extra band of blocks.  Every block reaches the reduction at the end.
+// that are not on the tensor grid (the 2 nb force rows of K, about 18
+// entries each) are taken by a band of blocks at the start of the grid, so
+// they are dispatched first, with kForceLanes lanes per row and a shuffle
+// reduction, so their gather chains are short.  Every block reaches the
+// reduction at the end.
 
 template <int R>
 __host__ __device__ inline int walk_by(int nj) { return (nj + 4 * R - 1) / (4 * R); }
+
+constexpr int kForceLanes = 8;
+__host__ __device__ inline int force_band(int nb, int gx) {
+    return (2 * nb * kForceLanes + gx * kBlock - 1) / (gx * kBlock);
+}
 
 // Pressure and force rows of K = Q^T B^1 Q (pinned), precision T.
 // act(row, Kx, diag, x_row) is called once per row.
@@ -122,10 +136,11 @@ template <int R, class T, class XV, class ACT>
 __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
     const GridT<T> &g = K.g;
     const int nx = g.nx, ny = g.ny;
-    const int gy = walk_by<R>(ny);
-    if ((int)blockIdx.y < gy) {
+    const int band = force_band(K.nb, (int)gridDim.x);
+    if ((int)blockIdx.y >= band) {
+        const int by = (int)blockIdx.y - band;
         const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-        const int j0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * R;
+        const int j0 = (by * 4 + (threadIdx.x >> 6)) * R;
         if (i < nx && j0 < ny) {
             const T dt = K.dt;
             const T dxi = g.dx[i];
@@ -167,20 +182,24 @@ __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
             }
         }
     } else {
-        const int t = (((int)blockIdx.y - gy) * gridDim.x + blockIdx.x) * kBlock + threadIdx.x;
-        if (t < 2 * K.nb) {
-            T y = T(0);
-            for (int p = K.kf.ptr[t]; p < K.kf.ptr[t + 1]; ++p) y += K.kf.val[p] * xv(K.kf.col[p]);
-            act(g.n_cell + t, y, K.kf_diag[t], xv(g.n_cell + t));
-        }
+        // kForceLanes consecutive lanes (one wave holds 64 / kForceLanes rows)
+        const int t = ((int)blockIdx.y * gridDim.x + blockIdx.x) * kBlock + threadIdx.x;
+        const int fr = t / kForceLanes, lane = t % kForceLanes;
+        const bool live = fr < 2 * K.nb;
+        T y = T(0);
+        if (live)
+            for (int p = K.kf.ptr[fr] + lane; p < K.kf.ptr[fr + 1]; p += kForceLanes)
+                y += K.kf.val[p] * xv(K.kf.col[p]);
+#pragma unroll
+        for (int o = kForceLanes / 2; o > 0; o >>= 1) y += __shfl_xor(y, o, kForceLanes);
+        if (live && lane == 0) act(g.n_cell + fr, y, K.kf_diag[fr], xv(g.n_cell + fr));
     }
 }
 
 template <int R, class T>
 inline dim3 k0_grid(const K0T<T> &K) {
     int gx = (K.g.nx + 63) / 64;
-    int extra = (2 * K.nb + gx * kBlock - 1) / (gx * kBlock);
-    return dim3(gx, walk_by<R>(K.g.ny) + extra);
+    return dim3(gx, walk_by<R>(K.g.ny) + force_band(K.nb, gx));
 }
 
 // Velocity rows of A = Mf/dt - (nu/2) M Lhat R^{-1}: u faces (nx-1) x ny,
@@ -386,12 +405,26 @@ __global__ __launch_bounds__(kBlock) void k_apply(Op op, const T *x, T *y) {
 
 // x += alpha p, r -= alpha q (z = D^{-1} r for Jacobi); sums rr, rz
 template <class Op, class T>
-__global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *__restrict__ x, T *__restrict__ r, T *__restrict__ z, const T *__restrict__ p,
-                                                       const T *__restrict__ q, SolveStatus *st, double *parts,
-                                                       int jacobi) {
+__global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *__restrict__ x, T *__restrict__ r,
+                                                       T *__restrict__ z, const T *__restrict__ p,
+                                                       const T *__restrict__ q, SolveStatus *st,
+                                                       const double *__restrict__ pq_parts, int G_pq,
+                                                       double *__restrict__ parts, int jacobi) {
     if (st->done) return;
     const int n = op_n(op);
-    const T alpha = (T)(st->rz / st->pq);
+    // p . q from the partials of the product kernel, summed by every block in
+    // the order the one-block finalize would use (so no separate launch)
+    double pq;
+    if (pq_parts) {
+        double a[1] = {0.0};
+        for (int b = threadIdx.x; b < G_pq; b += kBlock) a[0] += pq_parts[b];
+        block_sum<1>(a);
+        pq = a[0];
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->pq = pq;
+    } else {
+        pq = st->pq;
+    }
+    const T alpha = (T)(st->rz / pq);
     Tiles Tl = my_tiles(n);
     double v[2] = {0.0, 0.0};
     for (int t = Tl.t0; t < Tl.t1; ++t) {
@@ -856,6 +889,13 @@ __global__ __launch_bounds__(kBlock) void k_coarse_dense(int n, const double *__
     if (lane == 0) x[row] = (T)acc;
 }
 
+// y = x, two doubles per lane per step (grid-stride)
+__global__ __launch_bounds__(kBlock) void k_stream_copy(size_t n2, const double2 *__restrict__ x,
+                                                        double2 *__restrict__ y) {
+    for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n2; i += (size_t)gridDim.x * kBlock)
+        y[i] = x[i];
+}
+
 // ---------------------------------------------------------------------------
 // mixed precision: x += d
 
@@ -1217,23 +1257,32 @@ void launch_pcg_init_zero(hipStream_t s, int n, const T *b, T *x, T *r, SolveSta
     LAUNCH(k_finalize, 1, (int)FIN_INIT_ZERO, G, parts, st, 0, rtol2, maxit);
 }
 
-template <class Op, class T>
-void launch_pcg_spmv(hipStream_t s, const Op &op, const T *z, const T *pold, T *pnew, T *q,
-                     SolveStatus *st, double *parts) {
+template <class Op>
+static int walk_grid_blocks(const Op &op) {
     int G = 0;
     WALK_SWITCH(pick_R(op), {
         dim3 gd = op_grid<RR>(op);
         G = gd.x * gd.y;
+    })
+    return G;
+}
+
+template <class Op, class T>
+void launch_pcg_spmv(hipStream_t s, const Op &op, const T *z, const T *pold, T *pnew, T *q,
+                     SolveStatus *st, double *parts) {
+    WALK_SWITCH(pick_R(op), {
+        dim3 gd = op_grid<RR>(op);
         LAUNCH2((k_pcg_spmv<RR, Op, T>), gd, op, z, pold, pnew, q, st, parts);
     })
-    LAUNCH(k_finalize, 1, (int)FIN_PQ, G, parts, st, 0, 0.0, 0);
 }
 
 template <class Op, class T>
 void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, T *z, const T *p, const T *q,
-                       SolveStatus *st, double *parts, bool jacobi) {
+                       SolveStatus *st, const double *pq_parts, double *parts, bool jacobi) {
+    if (pq_parts == parts) throw std::runtime_error("pcg update: partial buffers must differ");
+    const int G_pq = pq_parts ? walk_grid_blocks(op) : 0;
     int G = grid_for(op_n(op));
-    LAUNCH((k_pcg_update<Op, T>), G, op, x, r, z, p, q, st, parts, (int)jacobi);
+    LAUNCH((k_pcg_update<Op, T>), G, op, x, r, z, p, q, st, pq_parts, G_pq, parts, (int)jacobi);
     LAUNCH(k_finalize, 1, (int)FIN_UPDATE, G, parts, st, (int)jacobi, 0.0, 0);
 }
 
@@ -1382,6 +1431,11 @@ void launch_csrv_spmv(hipStream_t s, CSRT<T> A, int lanes, const T *x, T *y, boo
     CSRV_SWITCH(csrv_dispatch_spmv, A, x, y, (int)add, st)
 }
 
+void launch_stream_copy(hipStream_t s, size_t n, const double *x, double *y) {
+    if (n % 2) throw std::runtime_error("stream copy: odd length");
+    LAUNCH(k_stream_copy, 8192, n / 2, (const double2 *)x, (double2 *)y);
+}
+
 template <class T>
 void launch_coarse_dense(hipStream_t s, int n, const double *C, const T *b, T *x, const SolveStatus *st) {
     if (n < 1 || n > 8192 || !C || !b || !x)
@@ -1455,7 +1509,8 @@ void launch_add_correction(hipStream_t s, int n, double *x, const float *d) {
     template void launch_pcg_spmv<OP, T>(hipStream_t, const OP &, const T *, const T *, T *, T *, \
                                          SolveStatus *, double *);                               \
     template void launch_pcg_update<OP, T>(hipStream_t, const OP &, T *, T *, T *, const T *,    \
-                                           const T *, SolveStatus *, double *, bool);            \
+                                           const T *, SolveStatus *, const double *, double *,   \
+                                           bool);                                                \
     template void launch_true_residual<OP, T>(hipStream_t, const OP &, const T *, const T *,     \
                                               SolveStatus *, double *);
 INST_OP(K0View, double)

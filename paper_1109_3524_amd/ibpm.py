@@ -44,7 +44,8 @@ NN_PARAMS = 39168                     # IBPM_NN_PARAMS
 NN_SHAPES = [(32, 5), (32, 32), (32, 32), (32, 32), (32, 32), (3, 32)]   # (out, in) per layer
 
 KERNELS = {"k0_jacobi": 0, "k0_pcg_spmv": 1, "a_pcg_spmv": 2, "k0_residual": 3,
-           "restrict0": 4, "prolong0": 5, "pcg_update_k": 6, "coarse_cycle": 7}
+           "restrict0": 4, "prolong0": 5, "pcg_update_k": 6, "coarse_cycle": 7,
+           "presmooth0": 8, "stream_copy": 9}
 
 
 class IBPMError(RuntimeError):

@@ -309,3 +309,48 @@ def test_mixed_learned_trajectory_velocity_and_drag():
     assert sm["poisson_relres_max"] <= 1e-8
     assert eu < 1e-7 and ecd < 1e-6
     ctx.close()
+
+
+WEIGHTS = __import__("os").path.join(__import__("os").path.dirname(ibpm.__file__), "weights", "cylinder_512.npy")
+
+
+def test_trained_network_reduces_iterations():
+    """What the trained network gains: on the 512^2 Re 40 flow (the network
+    was trained on Re 100 flows of the same grid at other inflow angles), the
+    flexible CG with the trained stage needs fewer iterations than AMG-PCG
+    and than the same solver with untrained weights, at the same 1e-8
+    residual and with the same solution."""
+    from paper_1109_3524_amd.train_learned import poisson_rhs
+    w = np.load(WEIGHTS)
+    wl = W.cylinder_512()
+    print(f"[learned gain] {wl.name}", flush=True)
+    ctx = ibpm.Context(wl, poisson_solver=1)
+    q, conv, lam = ctx.init_state()
+    ctx.step(q, conv, lam, 6)
+    rhs = poisson_rhs(ctx, q, conv, lam)
+    lam0 = lam.clone()
+    ref = lam0.clone()
+    s1 = ctx.solve_poisson(rhs, ref)
+    ctx.close()
+    out = {}
+    for name, weights in (("trained", w), ("untrained", None)):
+        c = ibpm.Context(wl, poisson_solver=3)
+        if weights is None:
+            c.nn_init(5)
+        else:
+            c.nn_set_weights(weights)
+        x = lam0.clone()
+        out[name] = (c.solve_poisson(rhs, x), x)
+        c.close()
+    st, xt = out["trained"]
+    su, _ = out["untrained"]
+    print(f"  AMG-PCG {s1['iters']} iterations; trained {st['iters']} (fallbacks {st['fallbacks']}); "
+          f"untrained {su['iters']}", flush=True)
+    assert st["relres"] <= 1e-8 and st["fallbacks"] == 0
+    assert st["iters"] < s1["iters"] and st["iters"] < su["iters"]
+    P = Problem(wl, poisson_solver=1)
+    o = P.ops
+    R = P.grid.R_diag()
+    du = _rel(o.B1 * (o.Q @ _n(xt)) / R, o.B1 * (o.Q @ _n(ref)) / R)
+    print(f"  projection difference to AMG-PCG: {du:.2e}", flush=True)
+    assert du < 1e-6
