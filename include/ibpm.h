@@ -256,8 +256,9 @@ int ibpm_nn_apply(ibpm_ctx *ctx, const double *r, double *e);
 
 /* One pass of Adam (lr, betas 0.9/0.999) over the samples order[0..norder)
  * in batches: r1 and e1 hold nsamples (residual after the V-cycle, remaining
- * error) pairs in lambda layout, FP32 device.  The loss per sample is
- * |N_phi - t_phi|^2/|t_phi|^2 + |N_f - t_f|^2/|t_f|^2 with t = e1 dt / s;
+ * error, K e1 = r1) pairs in lambda layout, FP32 device.  The loss per sample
+ * is the share of the energy-norm error that the optimally scaled correction
+ * d = ibpm_nn_apply(r1) removes, -(d.r1)^2 / ((d.K d)(r1.e1)), in [-1, 0];
  * *mean_loss (host) receives the mean over the pass. */
 int ibpm_nn_train(ibpm_ctx *ctx, const float *r1, const float *e1, int32_t nsamples,
                   const int32_t *order, int32_t norder, int32_t batch, float lr,

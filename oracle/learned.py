@@ -17,10 +17,19 @@ The stage maps a residual r of the modified Poisson system (Eq. 11b; layout
   network  = y = N(features) (3 output channels)
   e        = (s / dt) [y_0 on the cells; D^T y_1; D^T y_2]
 
-Training target for a pair (r1, e1) is t = e1 dt / s, and the loss is
-  |y_0 - t_phi|^2 / |t_phi|^2 + (|D^T y_1 - t_fx|^2 + |D^T y_2 - t_fy|^2) / |t_f|^2
-(a part whose target is zero is left out).  The 1/dt scaling reflects
-B^1 = dt M^-1 in K = Q^T B^1 Q, so that K^-1 r ~ r / dt.
+The 1/dt scaling reflects B^1 = dt M^-1 in K = Q^T B^1 Q, so that
+K^-1 r ~ r / dt.
+
+Training loss for a pair (r1, e1) with K e1 = r1 (e1 the error left after
+the V-cycle) is the share of the energy-norm error that the correction d
+removes when the flexible-CG step scales it optimally:
+
+    loss = -(d . r1)^2 / ((d . K d) (r1 . e1)),   -1 <= loss <= 0
+
+((d . r1)^2 = (d . K e1)^2 <= (d . K d)(e1 . K e1) by Cauchy-Schwarz in the
+K inner product, with equality for d parallel to e1).  It weighs the error's
+modes by their eigenvalue, so the smooth modes that a local network cannot
+represent (and whose amplitude dominates |e1|) do not swamp the ones it can.
 """
 from __future__ import annotations
 
@@ -79,37 +88,47 @@ def correction(grid, D, y, s, dt):
     return (s / dt) * np.concatenate([yp, fx, fy])
 
 
-def loss_and_grad(grid, D, y, t):
-    """Loss of the output y against the scaled target t (lambda layout) and dL/dy."""
+def energy_loss(d, Kd, r1, e1):
+    """-(d.r1)^2 / ((d.Kd)(r1.e1)) and its gradient with respect to d (0 where
+    d.Kd <= 0)."""
+    a = float(d @ r1)
+    b = float(d @ Kd)
+    c = float(r1 @ e1)
+    if not (b > 0.0) or not (c > 0.0):
+        return 0.0, np.zeros_like(d)
+    loss = -a * a / (b * c)
+    grad = -(2.0 * a / (b * c)) * (r1 - (a / b) * Kd)
+    return loss, grad
+
+
+def correction_adjoint(grid, D, gd, s, dt):
+    """Gradient with respect to the network output y of a function of the
+    correction e = correction(grid, D, y, s, dt), given its gradient gd."""
     nc, nb = grid.nx * grid.ny, D.shape[1]
-    yp = y[0].reshape(nc)
-    fx = D.T @ y[1].reshape(nc)
-    fy = D.T @ y[2].reshape(nc)
-    tp, tx, ty = t[:nc], t[nc:nc + nb], t[nc + nb:nc + 2 * nb]
-    dp = float(tp @ tp)
-    df = float(tx @ tx + ty @ ty)
-    g = np.zeros_like(y)
-    loss = 0.0
-    if dp > 0:
-        loss += float((yp - tp) @ (yp - tp)) / dp
-        g[0] = (2.0 * (yp - tp) / dp).reshape(grid.ny, grid.nx)
-    if df > 0:
-        loss += float((fx - tx) @ (fx - tx) + (fy - ty) @ (fy - ty)) / df
-        g[1] = (2.0 * (D @ (fx - tx)) / df).reshape(grid.ny, grid.nx)
-        g[2] = (2.0 * (D @ (fy - ty)) / df).reshape(grid.ny, grid.nx)
-    return loss, g
+    g = np.zeros((3, grid.ny, grid.nx))
+    g[0] = (s / dt) * gd[:nc].reshape(grid.ny, grid.nx)
+    g[1] = (s / dt) * (D @ gd[nc:nc + nb]).reshape(grid.ny, grid.nx)
+    g[2] = (s / dt) * (D @ gd[nc + nb:nc + 2 * nb]).reshape(grid.ny, grid.nx)
+    return g
 
 
 def apply(grid, D, weights, r, dt):
-    """e = learned correction of r with the network stored in BF16."""
+    """e = learned correction of r with the network stored in BF16 (the
+    first layer takes the 5 real feature channels)."""
     X, s = features(grid, D, r)
-    y = nn.forward_bf16(weights, X)
+    y = nn.forward_bf16(weights, X[:5])
     return correction(grid, D, y, s, dt)
 
 
-def sample_loss_grad(grid, D, weights, r1, e1, dt):
-    """Loss of one training pair and the weight gradients (BF16 storage)."""
+def sample_loss_grad(grid, D, K, weights, r1, e1, dt):
+    """Energy loss of one training pair and the weight gradients (BF16
+    storage of weights, activations and back-propagated gradients)."""
+    r1 = np.asarray(r1, dtype=np.float64)
+    e1 = np.asarray(e1, dtype=np.float64)
     X, s = features(grid, D, r1)
-    y, acts = nn.forward_bf16(weights, X, keep=True)
-    loss, dy = loss_and_grad(grid, D, y, np.asarray(e1, dtype=np.float64) * dt / s)
+    y, acts = nn.forward_bf16(weights, X[:5], keep=True)
+    d = correction(grid, D, y, s, dt)
+    loss, gd = energy_loss(d, K @ d, r1, e1)
+    dy = np.zeros_like(y)
+    dy[:3] = correction_adjoint(grid, D, gd, s, dt)
     return loss, nn.backward_bf16(weights, acts, dy)

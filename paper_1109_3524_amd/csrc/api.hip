@@ -130,6 +130,7 @@ struct ibpm_ctx {
                 *st_out = nullptr;
     double *parts = nullptr;
     double *parts2 = nullptr;          // second partial-sum buffer (read by the next kernel)
+    int rz_G = 0;                      // partials of r . z left in parts by the last V-cycle
     SolveStatus *host_st = nullptr;   // pinned
     int est_vel = 8, est_poi = 32, est_inner = 32;
     bool learned = false;
@@ -227,7 +228,7 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
     const K0T<T> &K = P.K0;
     if (L == 1) {
         launch_dense_solve(s, K.n, c->coarse_inv, r, z, st);
-        if (with_rz) launch_dot_rz(s, K.n, r, z, st, c->parts);
+        if (with_rz) c->rz_G = launch_dot_rz_parts(s, K.n, r, z, st, c->parts);
         return;
     }
     std::vector<T *> cur(L);
@@ -286,7 +287,7 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
             launch_k0_jacobi(s, K, l0.omega, r, (const T *)a, b, st);
             std::swap(a, b);
         }
-        if (with_rz) launch_k0_jacobi_rz(s, K, l0.omega, r, (const T *)a, z, st, c->parts);
+        if (with_rz) c->rz_G = launch_k0_jacobi_rz(s, K, l0.omega, r, (const T *)a, z, st, c->parts);
         else launch_k0_jacobi(s, K, l0.omega, r, (const T *)a, z, st);
     }
 }
@@ -313,10 +314,13 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
     int last_it = 0;
     for (;;) {
         for (int k = 0; k < chunk; ++k) {
-            launch_pcg_spmv(s, op, (const T *)z, (const T *)p[curp], p[1 - curp], q, st, c->parts2);
+            // with the V-cycle the product sums its r . z partials (in parts)
+            launch_pcg_spmv(s, op, (const T *)z, (const T *)p[curp], p[1 - curp], q, st,
+                            jacobi ? (const double *)nullptr : (const double *)c->parts, c->rz_G,
+                            c->parts2);
             curp = 1 - curp;
             launch_pcg_update(s, op, x, r, z, (const T *)p[curp], (const T *)q, st,
-                              (const double *)c->parts2, c->parts, jacobi);
+                              (const double *)c->parts2, c->parts, jacobi, !jacobi);
             if (!jacobi) precond(r, z);
         }
         queued += chunk;
@@ -642,7 +646,8 @@ void nn_sample_grad(ibpm_ctx *c, const float *r, const float *t, double *loss) {
     launch_nn_scale(s, n, r, N.sparts, N.scale);
     launch_nn_features(s, c->g, m.nb, r, (const double *)N.scale, N.inv_hmin, N.cd, N.act[0]);
     nn_forward(c);
-    launch_nn_loss(s, c->g, m.nb, N.y32, t, N.scale, c->prm.dt, N.cd, N.fdiff, N.g[0], c->parts, N.st);
+    launch_nn_energy_loss(s, c->p64.K0, m.nb, N.y32, r, t, N.scale, c->prm.dt, N.cd, N.d, N.z0,
+                          N.g[0], c->parts, N.st);
     HIPCHECK(hipMemcpyAsync(loss, &N.st->rr, sizeof(double), hipMemcpyDeviceToDevice, s));
     int cur = 0;
     for (int l = kNNLayers - 1; l >= 0; --l) {
@@ -769,7 +774,7 @@ SolveStatus fcg_learned_drive(ibpm_ctx *c, PrecSet<T> &P, const T *b, T *x, Solv
             launch_fcg_spmv<T>(s, K, P.z, P.p[curp], P.p[1 - curp], P.q, P.r, st, c->parts);
             curp = 1 - curp;
             launch_pcg_update(s, K, x, P.r, (T *)nullptr, (const T *)P.p[curp], (const T *)P.q, st,
-                              (const double *)nullptr, c->parts, false);
+                              (const double *)nullptr, c->parts, false, false);
             learned_precond<T>(c, P, P.r, P.z, st);
             launch_fcg_beta<T>(s, n, P.z, P.q, st, c->parts);
         }
@@ -1351,7 +1356,7 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
         case IBPM_KERNEL_K0_PCG_SPMV: {
             const double *z = P.z, *p0 = P.p[0];
             double *p1 = P.p[1], *q = P.q;
-            launch = [=] { launch_pcg_spmv(s, K0, z, p0, p1, q, sb, parts); };
+            launch = [=] { launch_pcg_spmv(s, K0, z, p0, p1, q, sb, (const double *)nullptr, 0, parts); };
             by = 32.0 * n + b_coupling + b_metric;
             break;
         }
@@ -1359,7 +1364,7 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
             const AView A = c->A;
             const double *z = c->vz, *p0 = c->vp[0];
             double *p1 = c->vp[1], *q = c->vq;
-            launch = [=] { launch_pcg_spmv(s, A, z, p0, p1, q, sb, parts); };
+            launch = [=] { launch_pcg_spmv(s, A, z, p0, p1, q, sb, (const double *)nullptr, 0, parts); };
             by = 32.0 * nq + b_metric;
             break;
         }
@@ -1394,10 +1399,16 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
         case IBPM_KERNEL_PCG_UPDATE_K: {
             double *x = P.p[1], *r = P.r, *z = P.z;
             const double *p0 = P.p[0], *q = P.q;
-            // p . q partials of the product kernel for the update to sum
-            launch_pcg_spmv(s, K0, (const double *)P.z, (const double *)P.p[0], P.p[1], P.q, sb, c->parts2);
+            // p . q partials for the update to sum: 1/G each, so p . q = 1 and the
+            // status stays finite over the repetitions
+            {
+                const int G_pq = walk_blocks_of(K0);
+                std::vector<double> ones(G_pq, 1.0 / G_pq);
+                HIPCHECK(hipMemcpyAsync(c->parts2, ones.data(), G_pq * sizeof(double), hipMemcpyHostToDevice, s));
+                HIPCHECK(hipStreamSynchronize(s));
+            }
             const double *pq_parts = c->parts2;
-            launch = [=] { launch_pcg_update(s, K0, x, r, z, p0, q, sb, pq_parts, parts, false); };
+            launch = [=] { launch_pcg_update(s, K0, x, r, z, p0, q, sb, pq_parts, parts, false, false); };
             by = 48.0 * n;
             break;
         }
@@ -1578,10 +1589,11 @@ int ibpm_harvest(ibpm_ctx *c, const double *rhs, double *x, const double *xstar,
             // r1 = r - K V(r) (FP32) and e1 = x* - x - V(r)
             launch_outer_residual(s, K, P.r, P.z, r1_out + (size_t)k * n, c->st_bench, c->parts, 1);
             launch_harvest_e1(s, n, xstar, x, P.z, e1_out + (size_t)k * n);
-            launch_pcg_spmv(s, K, (const double *)P.z, (const double *)P.p[curp], P.p[1 - curp], P.q, st, c->parts2);
+            launch_pcg_spmv(s, K, (const double *)P.z, (const double *)P.p[curp], P.p[1 - curp], P.q, st,
+                            (const double *)c->parts, c->rz_G, c->parts2);
             curp = 1 - curp;
             launch_pcg_update(s, K, x, P.r, (double *)nullptr, (const double *)P.p[curp], (const double *)P.q, st,
-                              (const double *)c->parts2, c->parts, false);
+                              (const double *)c->parts2, c->parts, false, true);
             enqueue_vcycle(c, P, (const double *)P.r, P.z, st);
         }
         HIPCHECK(hipStreamSynchronize(s));

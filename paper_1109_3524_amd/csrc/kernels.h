@@ -81,6 +81,7 @@ struct AView {
 enum : int { ST_RUNNING = 0, ST_CONVERGED = 1, ST_MAXIT = 2, ST_NAN = 3, ST_ZERO_RHS = 4 };
 struct SolveStatus {
     double bb, rr, rz, pq, beta, tol2, true_rr;
+    double rz_next;                  // r . z of the new preconditioned residual (fused path)
     double fx, fy;
     int iter, maxit, done, first;
     unsigned int counter;
@@ -117,22 +118,30 @@ void launch_pcg_init(hipStream_t s, const Op &op, const T *b, const T *x, T *r, 
 template <class T>
 void launch_pcg_init_zero(hipStream_t s, int n, const T *b, T *x, T *r, SolveStatus *st,
                           double *parts, double rtol2, int maxit);
+// number of blocks (and of partials) of a level-0 stencil kernel
+int walk_blocks_of(const K0View &K);
 // p_new = z + beta p_old; q = op p_new; per-block partials of p . q in parts
-// (no finalize: the update below sums them)
+// (no finalize: the update below sums them).  beta is st->beta, or, when
+// rz_parts is given (G_rz partials of r . z from the preconditioner's last
+// kernel), beta = rz_new / st->rz (0 on the first iteration) with rz_new
+// summed here and left in st->rz_next.
 template <class Op, class T>
 void launch_pcg_spmv(hipStream_t s, const Op &op, const T *z, const T *pold, T *pnew, T *q,
-                     SolveStatus *st, double *parts);
+                     SolveStatus *st, const double *rz_parts, int G_rz, double *parts);
 // x += alpha p; r -= alpha q (and z = D^{-1} r for Jacobi), alpha = rz / pq
 // with pq summed from pq_parts (the product kernel's partials; another
-// buffer than parts) or, when pq_parts is null, taken from st->pq
+// buffer than parts) or, when pq_parts is null, taken from st->pq; rz is
+// st->rz_next after a product with rz_parts (fused_rz), else st->rz
 template <class Op, class T>
 void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, T *z, const T *p, const T *q,
-                       SolveStatus *st, const double *pq_parts, double *parts, bool jacobi);
+                       SolveStatus *st, const double *pq_parts, double *parts, bool jacobi,
+                       bool fused_rz);
 template <class Op, class T>
 void launch_true_residual(hipStream_t s, const Op &op, const T *b, const T *x, SolveStatus *st,
                           double *parts);
+// per-block partials of r . z (no finalize); returns the number of partials
 template <class T>
-void launch_dot_rz(hipStream_t s, int n, const T *r, const T *z, SolveStatus *st, double *parts);
+int launch_dot_rz_parts(hipStream_t s, int n, const T *r, const T *z, SolveStatus *st, double *parts);
 template <class T>
 void launch_zero_if_zero_rhs(hipStream_t s, T *x, int n, const SolveStatus *st);
 
@@ -150,9 +159,11 @@ void launch_k0_jacobi_first(hipStream_t s, const K0T<T> &K, double omega, const 
 template <class T>
 void launch_k0_jacobi(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
                       T *xout, const SolveStatus *st);
+// last post-sweep; per-block partials of b . xout in parts (no finalize:
+// the next product kernel sums them); returns the number of partials
 template <class T>
-void launch_k0_jacobi_rz(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
-                         T *xout, SolveStatus *st, double *parts);
+int launch_k0_jacobi_rz(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
+                        T *xout, SolveStatus *st, double *parts);
 template <class T>
 void launch_k0_residual(hipStream_t s, const K0T<T> &K, const T *b, const T *x, T *r,
                         const SolveStatus *st);

@@ -126,8 +126,8 @@ template <int R>
 __host__ __device__ inline int walk_by(int nj) { return (nj + 4 * R - 1) / (4 * R); }
 
 constexpr int kForceLanes = 8;
-__host__ __device__ inline int force_band(int nb, int gx) {
-    return (2 * nb * kForceLanes + gx * kBlock - 1) / (gx * kBlock);
+__host__ __device__ inline int force_band(int nb) {
+    return (2 * nb * kForceLanes + kBlock - 1) / kBlock;
 }
 
 // Pressure and force rows of K = Q^T B^1 Q (pinned), precision T.
@@ -136,11 +136,17 @@ template <int R, class T, class XV, class ACT>
 __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
     const GridT<T> &g = K.g;
     const int nx = g.nx, ny = g.ny;
-    const int band = force_band(K.nb, (int)gridDim.x);
-    if ((int)blockIdx.y >= band) {
-        const int by = (int)blockIdx.y - band;
-        const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-        const int j0 = (by * 4 + (threadIdx.x >> 6)) * R;
+    const int band = force_band(K.nb);
+    const int b = (int)blockIdx.x;
+    if (b >= band) {
+        // tile of 256 columns x R rows; the tiles of one XCD are contiguous in
+        // (row-band, column-chunk) order, so halos are shared through its L2
+        const int cx_n = (nx + kBlock - 1) / kBlock;
+        const int Gw = (int)gridDim.x - band;
+        const int w = remap_block(b - band, Gw);
+        const int cy = w / cx_n, cx = w - cy * cx_n;
+        const int i = cx * kBlock + threadIdx.x;
+        const int j0 = cy * R;
         if (i < nx && j0 < ny) {
             const T dt = K.dt;
             const T dxi = g.dx[i];
@@ -183,7 +189,7 @@ __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
         }
     } else {
         // kForceLanes consecutive lanes (one wave holds 64 / kForceLanes rows)
-        const int t = ((int)blockIdx.y * gridDim.x + blockIdx.x) * kBlock + threadIdx.x;
+        const int t = b * kBlock + threadIdx.x;
         const int fr = t / kForceLanes, lane = t % kForceLanes;
         const bool live = fr < 2 * K.nb;
         T y = T(0);
@@ -196,10 +202,12 @@ __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
     }
 }
 
+// 1-D grid: the force band, then one block per 256 columns x R rows
 template <int R, class T>
 inline dim3 k0_grid(const K0T<T> &K) {
-    int gx = (K.g.nx + 63) / 64;
-    return dim3(gx, walk_by<R>(K.g.ny) + force_band(K.nb, gx));
+    const int cx_n = (K.g.nx + kBlock - 1) / kBlock;
+    const int cy_n = (K.g.ny + R - 1) / R;
+    return dim3(force_band(K.nb) + cx_n * cy_n);
 }
 
 // Velocity rows of A = Mf/dt - (nu/2) M Lhat R^{-1}: u faces (nx-1) x ny,
@@ -374,9 +382,27 @@ template <int R, class Op, class T>
 __global__ __launch_bounds__(kBlock) void k_pcg_spmv(Op op, const T *__restrict__ z,
                                                      const T *__restrict__ pold,
                                                      T *__restrict__ pnew, T *__restrict__ q,
-                                                     SolveStatus *st, double *parts) {
+                                                     SolveStatus *st,
+                                                     const double *__restrict__ rz_parts, int G_rz,
+                                                     double *__restrict__ parts) {
     if (st->done) return;
-    const T beta = (T)st->beta;
+    T beta;
+    if (rz_parts) {
+        // r . z of the new preconditioned residual from the preconditioner's
+        // partials (every block sums them in the same order); st->rz and
+        // st->first are only read here, the new value goes to st->rz_next
+        double a[1] = {0.0};
+        for (int b = threadIdx.x; b < G_rz; b += kBlock) a[0] += rz_parts[b];
+        block_sum<1>(a);
+        const double bt = st->first ? 0.0 : a[0] / st->rz;
+        beta = (T)bt;
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+            st->rz_next = a[0];
+            st->beta = bt;
+        }
+    } else {
+        beta = (T)st->beta;
+    }
     double v[1] = {0.0};
     op_walk<R>(op, [&](int c) { return z[c] + beta * pold[c]; }, [&](int row, T qi, T, T pi) {
         pnew[row] = pi;
@@ -409,7 +435,8 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *__restrict__ x,
                                                        T *__restrict__ z, const T *__restrict__ p,
                                                        const T *__restrict__ q, SolveStatus *st,
                                                        const double *__restrict__ pq_parts, int G_pq,
-                                                       double *__restrict__ parts, int jacobi) {
+                                                       double *__restrict__ parts, int jacobi,
+                                                       int fused_rz) {
     if (st->done) return;
     const int n = op_n(op);
     // p . q from the partials of the product kernel, summed by every block in
@@ -424,7 +451,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *__restrict__ x,
     } else {
         pq = st->pq;
     }
-    const T alpha = (T)(st->rz / pq);
+    const T alpha = (T)((fused_rz ? st->rz_next : st->rz) / pq);
     Tiles Tl = my_tiles(n);
     double v[2] = {0.0, 0.0};
     for (int t = Tl.t0; t < Tl.t1; ++t) {
@@ -619,15 +646,19 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const doub
     case FIN_PQ:
         st->pq = acc[0];
         break;
-    case FIN_UPDATE:   // acc = (rr, rz); flag = jacobi
+    case FIN_UPDATE:   // acc = (rr, rz); flag bit 0: Jacobi (rz here), bit 1: rz from the product
         st->rr = acc[0];
         st->iter += 1;
         if (bad(acc[0])) st->done = ST_NAN;
         else if (acc[0] <= st->tol2 * st->bb) st->done = ST_CONVERGED;
         else if (st->iter >= st->maxit) st->done = ST_MAXIT;
-        if (flag) {
+        if (flag & 1) {
             st->beta = acc[1] / st->rz;
             st->rz = acc[1];
+        }
+        if (flag & 2) {
+            st->rz = st->rz_next;
+            st->first = 0;
         }
         break;
     case FIN_TRUE:
@@ -1267,23 +1298,29 @@ static int walk_grid_blocks(const Op &op) {
     return G;
 }
 
+int walk_blocks_of(const K0View &K) { return walk_grid_blocks(K); }
+
 template <class Op, class T>
 void launch_pcg_spmv(hipStream_t s, const Op &op, const T *z, const T *pold, T *pnew, T *q,
-                     SolveStatus *st, double *parts) {
+                     SolveStatus *st, const double *rz_parts, int G_rz, double *parts) {
+    if (rz_parts && (rz_parts == parts || G_rz < 1 || G_rz > kMaxParts))
+        throw std::runtime_error("pcg product: bad partial buffers");
     WALK_SWITCH(pick_R(op), {
         dim3 gd = op_grid<RR>(op);
-        LAUNCH2((k_pcg_spmv<RR, Op, T>), gd, op, z, pold, pnew, q, st, parts);
+        LAUNCH2((k_pcg_spmv<RR, Op, T>), gd, op, z, pold, pnew, q, st, rz_parts, G_rz, parts);
     })
 }
 
 template <class Op, class T>
 void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, T *z, const T *p, const T *q,
-                       SolveStatus *st, const double *pq_parts, double *parts, bool jacobi) {
+                       SolveStatus *st, const double *pq_parts, double *parts, bool jacobi,
+                       bool fused_rz) {
     if (pq_parts == parts) throw std::runtime_error("pcg update: partial buffers must differ");
     const int G_pq = pq_parts ? walk_grid_blocks(op) : 0;
     int G = grid_for(op_n(op));
-    LAUNCH((k_pcg_update<Op, T>), G, op, x, r, z, p, q, st, pq_parts, G_pq, parts, (int)jacobi);
-    LAUNCH(k_finalize, 1, (int)FIN_UPDATE, G, parts, st, (int)jacobi, 0.0, 0);
+    LAUNCH((k_pcg_update<Op, T>), G, op, x, r, z, p, q, st, pq_parts, G_pq, parts, (int)jacobi,
+           (int)fused_rz);
+    LAUNCH(k_finalize, 1, (int)FIN_UPDATE, G, parts, st, (int)jacobi | (fused_rz ? 2 : 0), 0.0, 0);
 }
 
 template <class Op, class T>
@@ -1299,10 +1336,10 @@ void launch_true_residual(hipStream_t s, const Op &op, const T *b, const T *x, S
 }
 
 template <class T>
-void launch_dot_rz(hipStream_t s, int n, const T *r, const T *z, SolveStatus *st, double *parts) {
+int launch_dot_rz_parts(hipStream_t s, int n, const T *r, const T *z, SolveStatus *st, double *parts) {
     int G = grid_for(n);
     LAUNCH((k_dot_rz<T>), G, n, r, z, st, parts);
-    LAUNCH(k_finalize, 1, (int)FIN_RZ, G, parts, st, 0, 0.0, 0);
+    return G;
 }
 
 template <class T>
@@ -1334,15 +1371,15 @@ void launch_k0_jacobi(hipStream_t s, const K0T<T> &K, double omega, const T *b, 
 }
 
 template <class T>
-void launch_k0_jacobi_rz(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
-                         T *xout, SolveStatus *st, double *parts) {
+int launch_k0_jacobi_rz(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
+                        T *xout, SolveStatus *st, double *parts) {
     int G = 0;
     WALK_SWITCH(pick_R(K), {
         dim3 gd = op_grid<RR>(K);
         G = gd.x * gd.y;
         LAUNCH2((k_k0_jacobi_rz<RR, T>), gd, K, (T)omega, b, xin, xout, st, parts);
     })
-    LAUNCH(k_finalize, 1, (int)FIN_RZ, G, parts, st, 0, 0.0, 0);
+    return G;
 }
 
 template <class T>
@@ -1507,10 +1544,10 @@ void launch_add_correction(hipStream_t s, int n, double *x, const float *d) {
     template void launch_pcg_init<OP, T>(hipStream_t, const OP &, const T *, const T *, T *, T *,\
                                          SolveStatus *, double *, bool, double, int);            \
     template void launch_pcg_spmv<OP, T>(hipStream_t, const OP &, const T *, const T *, T *, T *, \
-                                         SolveStatus *, double *);                               \
+                                         SolveStatus *, const double *, int, double *);          \
     template void launch_pcg_update<OP, T>(hipStream_t, const OP &, T *, T *, T *, const T *,    \
                                            const T *, SolveStatus *, const double *, double *,   \
-                                           bool);                                                \
+                                           bool, bool);                                          \
     template void launch_true_residual<OP, T>(hipStream_t, const OP &, const T *, const T *,     \
                                               SolveStatus *, double *);
 INST_OP(K0View, double)
@@ -1520,8 +1557,8 @@ INST_OP(K0T<float>, float)
 #define INST_T(T)                                                                                \
     template void launch_pcg_init_zero<T>(hipStream_t, int, const T *, T *, T *, SolveStatus *,  \
                                           double *, double, int);                                \
-    template void launch_dot_rz<T>(hipStream_t, int, const T *, const T *, SolveStatus *,        \
-                                   double *);                                                    \
+    template int launch_dot_rz_parts<T>(hipStream_t, int, const T *, const T *, SolveStatus *,   \
+                                        double *);                                               \
     template void launch_zero_if_zero_rhs<T>(hipStream_t, T *, int, const SolveStatus *);        \
     template void launch_k0_wdinv<T>(hipStream_t, const K0T<T> &, double, T *);                   \
     template void launch_k0_presmooth2<T>(hipStream_t, const K0T<T> &, const T *, const T *, T *,  \
@@ -1530,8 +1567,8 @@ INST_OP(K0T<float>, float)
                                             const SolveStatus *);                                \
     template void launch_k0_jacobi<T>(hipStream_t, const K0T<T> &, double, const T *, const T *, \
                                       T *, const SolveStatus *);                                 \
-    template void launch_k0_jacobi_rz<T>(hipStream_t, const K0T<T> &, double, const T *,         \
-                                         const T *, T *, SolveStatus *, double *);               \
+    template int launch_k0_jacobi_rz<T>(hipStream_t, const K0T<T> &, double, const T *,          \
+                                        const T *, T *, SolveStatus *, double *);                \
     template void launch_k0_residual<T>(hipStream_t, const K0T<T> &, const T *, const T *, T *,  \
                                         const SolveStatus *);                                    \
     template void launch_csr_jacobi_first<T>(hipStream_t, CSRT<T>, const T *, const T *, T *,    \

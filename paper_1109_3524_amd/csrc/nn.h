@@ -80,12 +80,14 @@ void launch_nn_features(hipStream_t s, GridView g, int nb, const T *r, const dou
 template <class T>
 void launch_nn_output(hipStream_t s, int n_cell, int nb, const float *Y32, const double *scale,
                       double inv_dt, CellDelta cd, T *e);
-// training loss of Y32 against the target t * dt / scale (t in lambda layout,
-// FP32): L_phi / D_phi + L_f / D_f (squared errors over squared targets,
-// pressure cells and interpolated forces) into st->rr, and dL/dY32 into dY
-// ([H][W][32] FP32).  fdiff holds 2 nb floats of scratch.
-void launch_nn_loss(hipStream_t s, GridView g, int nb, const float *Y32, const float *t,
-                    const double *scale, double dt, CellDelta cd, float *fdiff, float *dY,
-                    double *parts, SolveStatus *st);
+// training loss of the correction d = output map of Y32 for the pair (r1,
+// e1) (FP32, lambda layout, K e1 = r1): the share of the energy-norm error
+// that the optimally scaled d removes, -(d.r1)^2 / ((d.Kd)(r1.e1)), into
+// st->rr, and dL/dY32 into dY ([H][W][32] FP32).  d and Kd are FP64 work
+// vectors of n entries; parts holds 3 x 1024 partial sums.
+void launch_nn_energy_loss(hipStream_t s, const K0View &K, int nb, const float *Y32,
+                           const float *r1, const float *e1, const double *scale, double dt,
+                           CellDelta cd, double *d, double *Kd, float *dY, double *parts,
+                           SolveStatus *st);
 
 }  // namespace ibpm

@@ -280,92 +280,86 @@ __global__ __launch_bounds__(kBlock) void k_nn_output(int n_cell, int nb, const 
     }
 }
 
-// squared errors of the prediction against the target t * (dt / scale)
-// (pressure cells and interpolated forces separately) and the interpolated
-// force differences, kept for the gradient
-__global__ __launch_bounds__(kBlock) void k_nn_loss_sums(int n_cell, int nb, const float *Y32,
-                                                         const float *t, const double *scale,
-                                                         double dt, CellDelta cd, float *fdiff,
-                                                         double *parts) {
-    const int row = blockIdx.x * kBlock + threadIdx.x;
-    const double ts = dt / scale[0];
-    double v[4] = {0.0, 0.0, 0.0, 0.0};   // L_phi, D_phi, L_f, D_f
-    if (row < n_cell) {
-        const double tv = (double)t[row] * ts;
-        const double d = (double)Y32[(size_t)row * 32] - tv;
-        v[0] = d * d;
-        v[1] = tv * tv;
-    } else if (row < n_cell + 2 * nb) {
-        const int k = row - n_cell;
-        const int pk = k < nb ? k : k - nb;
-        const int ch = k < nb ? 1 : 2;
-        double s = 0.0;
-        for (int q = cd.p2c.ptr[pk]; q < cd.p2c.ptr[pk + 1]; ++q)
-            s += cd.p2c.val[q] * (double)Y32[(size_t)cd.p2c.col[q] * 32 + ch];
-        const double tv = (double)t[row] * ts;
-        const double d = s - tv;
-        fdiff[k] = (float)d;
-        v[2] = d * d;
-        v[3] = tv * tv;
+// Energy loss of a correction d (lambda layout, FP64) for a training pair
+// (r1, e1) with K e1 = r1:  loss = -(d.r1)^2 / ((d.Kd)(r1.e1)).  Partial sums
+// of d.r1, d.Kd and r1.e1 per block, then one block forms the loss and the
+// two coefficients of its gradient  dL/dd = coef (r1 - ratio K d).
+__global__ __launch_bounds__(kBlock) void k_energy_sums(int n, const double *d, const double *Kd,
+                                                        const float *r1, const float *e1,
+                                                        double *parts) {
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const double ri = (double)r1[i];
+        v[0] += d[i] * ri;
+        v[1] += d[i] * Kd[i];
+        v[2] += ri * (double)e1[i];
     }
-    __shared__ double sh[4][kBlock];
-    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = v[k];
+    __shared__ double sh[3][kBlock];
+    for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = v[k];
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s)
-            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x == 0)
-        for (int k = 0; k < 4; ++k) parts[k * kMaxParts + blockIdx.x] = sh[k][0];
+        for (int k = 0; k < 3; ++k) parts[k * kMaxParts + blockIdx.x] = sh[k][0];
 }
 
-// loss = L_phi / D_phi + L_f / D_f (a part with D = 0 is left out)
-__global__ __launch_bounds__(kBlock) void k_nn_loss_finalize(int G, const double *parts,
-                                                             SolveStatus *st) {
-    __shared__ double sh[4][kBlock];
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
+// st->rr = loss, st->beta = coef, st->pq = ratio (all 0 when d.Kd <= 0 or
+// r1.e1 <= 0 or a sum is not finite)
+__global__ __launch_bounds__(kBlock) void k_energy_finalize(int G, const double *parts,
+                                                            SolveStatus *st) {
+    __shared__ double sh[3][kBlock];
+    double v[3] = {0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < G; b += kBlock)
-        for (int k = 0; k < 4; ++k) v[k] += parts[k * kMaxParts + b];
-    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = v[k];
+        for (int k = 0; k < 3; ++k) v[k] += parts[k * kMaxParts + b];
+    for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] = v[k];
     __syncthreads();
     for (int s = kBlock / 2; s > 0; s >>= 1) {
         if (threadIdx.x < s)
-            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+            for (int k = 0; k < 3; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        const double dp = sh[1][0] > 0.0 ? sh[1][0] : 1.0, df = sh[3][0] > 0.0 ? sh[3][0] : 1.0;
-        st->bb = dp;
-        st->pq = df;
-        st->rr = sh[0][0] / dp + (sh[3][0] > 0.0 ? sh[2][0] / df : 0.0);
+        const double a = sh[0][0], b = sh[1][0], c = sh[2][0];
+        const bool ok = b > 0.0 && c > 0.0 && isfinite(a) && isfinite(b) && isfinite(c);
+        st->rr = ok ? -a * a / (b * c) : 0.0;
+        st->beta = ok ? -2.0 * a / (b * c) : 0.0;
+        st->pq = ok ? a / b : 0.0;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_nn_loss_grad(GridView g, int nb, const float *Y32,
-                                                         const float *t, const double *scale,
-                                                         double dt, CellDelta cd,
-                                                         const float *fdiff, const SolveStatus *st,
-                                                         float *dY) {
+// gd = coef (r1 - ratio K d), in place of d
+__global__ __launch_bounds__(kBlock) void k_energy_grad(int n, const float *r1, const double *Kd,
+                                                        const SolveStatus *st, double *gd) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) gd[i] = st->beta * ((double)r1[i] - st->pq * Kd[i]);
+}
+
+// dL/dY of the output map e = (s/dt) [Y0; D^T Y1; D^T Y2]:
+// channel 0 = (s/dt) gd_cell, channels 1, 2 = (s/dt) D gd_force, others 0
+__global__ __launch_bounds__(kBlock) void k_output_adjoint(GridView g, int nb, const double *gd,
+                                                           const double *scale, double inv_dt,
+                                                           CellDelta cd, float *dY) {
     const int p = blockIdx.x * kBlock + threadIdx.x;
     if (p >= g.n_cell) return;
-    const double ts = dt / scale[0];
-    const double dp = st->bb, df = st->pq;
     const int j = p / g.nx, i = p - j * g.nx;
+    const double sc = scale[0] * inv_dt;
     float out[32];
 #pragma unroll
     for (int k = 0; k < 32; ++k) out[k] = 0.0f;
-    out[0] = (float)(2.0 * ((double)Y32[(size_t)p * 32] - (double)t[p] * ts) / dp);
+    out[0] = (float)(sc * gd[p]);
     if (i >= cd.i0 && i <= cd.i1 && j >= cd.j0 && j <= cd.j1) {
         const int rb = (j - cd.j0) * (cd.i1 - cd.i0 + 1) + (i - cd.i0);
         double gx = 0.0, gy = 0.0;
         for (int e = cd.c2p.ptr[rb]; e < cd.c2p.ptr[rb + 1]; ++e) {
             const int k = cd.c2p.col[e];
-            gx += cd.c2p.val[e] * (double)fdiff[k];
-            gy += cd.c2p.val[e] * (double)fdiff[nb + k];
+            gx += cd.c2p.val[e] * gd[g.n_cell + k];
+            gy += cd.c2p.val[e] * gd[g.n_cell + nb + k];
         }
-        out[1] = (float)(2.0 * gx / df);
-        out[2] = (float)(2.0 * gy / df);
+        out[1] = (float)(sc * gx);
+        out[2] = (float)(sc * gy);
     }
 #pragma unroll
     for (int k = 0; k < 32; ++k) dY[(size_t)p * 32 + k] = out[k];
@@ -439,16 +433,21 @@ void launch_nn_output(hipStream_t s, int n_cell, int nb, const float *Y32, const
     LAUNCH((k_nn_output<T>), (n + kBlock - 1) / kBlock, n_cell, nb, Y32, scale, inv_dt, cd, e);
 }
 
-void launch_nn_loss(hipStream_t s, GridView g, int nb, const float *Y32, const float *t,
-                    const double *scale, double dt, CellDelta cd, float *fdiff, float *dY,
-                    double *parts, SolveStatus *st) {
-    int n = g.n_cell + 2 * nb;
+void launch_nn_energy_loss(hipStream_t s, const K0View &K, int nb, const float *Y32,
+                           const float *r1, const float *e1, const double *scale, double dt,
+                           CellDelta cd, double *d, double *Kd, float *dY, double *parts,
+                           SolveStatus *st) {
+    const int n = K.n;
+    launch_nn_output<double>(s, K.g.n_cell, nb, Y32, scale, 1.0 / dt, cd, d);
+    launch_apply_K0(s, K, (const double *)d, Kd);
     int G = (n + kBlock - 1) / kBlock;
-    if (G > kMaxParts) throw std::runtime_error("image too large for the loss reduction");
-    LAUNCH(k_nn_loss_sums, G, g.n_cell, nb, Y32, t, scale, dt, cd, fdiff, parts);
-    LAUNCH(k_nn_loss_finalize, 1, G, parts, st);
-    LAUNCH(k_nn_loss_grad, (g.n_cell + kBlock - 1) / kBlock, g, nb, Y32, t, scale, dt, cd, fdiff,
-           st, dY);
+    if (G > 1024) G = 1024;
+    LAUNCH(k_energy_sums, G, n, (const double *)d, (const double *)Kd, r1, e1, parts);
+    LAUNCH(k_energy_finalize, 1, G, (const double *)parts, st);
+    LAUNCH(k_energy_grad, (n + kBlock - 1) / kBlock, n, r1, (const double *)Kd,
+           (const SolveStatus *)st, d);
+    LAUNCH(k_output_adjoint, (K.g.n_cell + kBlock - 1) / kBlock, K.g, nb, (const double *)d, scale,
+           1.0 / dt, cd, dY);
 }
 
 template void launch_conv3x3<bf16, 8>(hipStream_t, int, int, const bf16 *, const bf16 *,

@@ -1,8 +1,8 @@
 """Pins of the learned-stage oracle: the cell-centre delta weights against
 the moment conditions of the delta of Eq. (6), the feature and output maps
-against closed forms, the loss gradient against finite differences, and
-the BF16-storage network against the FP64 one on exactly representable
-values."""
+against closed forms, the energy loss against its bounds, optimum and
+finite differences, and the BF16-storage network against the FP64 one on
+exactly representable values."""
 import numpy as np
 
 from oracle import learned, nn
@@ -67,27 +67,6 @@ def test_correction_reproduces_constant_force_field():
     np.testing.assert_allclose(e[nc + 8:], -24.0, rtol=1e-14)
 
 
-def test_loss_gradient_matches_finite_differences():
-    wl = W.tiny(16, 14, 6, radius=0.3)
-    g = _grid(wl)
-    D = learned.cell_delta(g, wl.xb, wl.yb)
-    rng = np.random.default_rng(5)
-    y = rng.standard_normal((3, g.ny, g.nx))
-    t = rng.standard_normal(g.nx * g.ny + 2 * wl.nb)
-    L, dy = learned.loss_and_grad(g, D, y, t)
-    # at y = target-consistent values the loss is zero
-    yt = np.zeros_like(y)
-    yt[0] = t[:g.nx * g.ny].reshape(g.ny, g.nx)
-    assert learned.loss_and_grad(g, D, yt, np.concatenate([t[:g.nx * g.ny], np.zeros(2 * wl.nb)]))[0] == 0.0
-    eps = 1e-6
-    for idx in [(0, 3, 4), (1, 7, 8), (2, 6, 7), (1, 0, 0)]:
-        yp, ym = y.copy(), y.copy()
-        yp[idx] += eps
-        ym[idx] -= eps
-        fd = (learned.loss_and_grad(g, D, yp, t)[0] - learned.loss_and_grad(g, D, ym, t)[0]) / (2 * eps)
-        assert abs(fd - dy[idx]) <= 1e-7 * max(1.0, abs(fd)), (idx, fd, dy[idx])
-
-
 def test_bf16_network_equals_fp64_network_on_representable_values():
     # weights in {-1, 0, 1} and small integer inputs keep every activation an
     # integer below 256, which BF16 holds exactly
@@ -111,3 +90,71 @@ def test_bf16_rounding_ties_to_even():
     vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 2 ** -9, -2.5, 0.0])
     out = nn.bf16_round(vals)
     np.testing.assert_array_equal(out, [1.0, 1.0, 1.0 + 2 ** -6 * 1.0, 1.0, -2.5, 0.0])
+
+
+def test_correction_is_positively_homogeneous_in_the_residual():
+    # the features see r / rms(r) and the output is scaled back by rms(r), so
+    # doubling r doubles the correction exactly (powers of two are exact)
+    wl = W.tiny(14, 12, 6, radius=0.3)
+    g = _grid(wl)
+    D = learned.cell_delta(g, wl.xb, wl.yb)
+    ws = nn.init_weights([5, 8, 8, 3], seed=4)
+    r = W.random_vector(g.nx * g.ny + 2 * wl.nb, 9)
+    e1 = learned.apply(g, D, ws, r, 0.01)
+    e2 = learned.apply(g, D, ws, 2.0 * r, 0.01)
+    np.testing.assert_array_equal(e2, 2.0 * e1)
+    assert np.linalg.norm(e1) > 0
+
+
+def _tiny_system():
+    from oracle.problem import Problem
+    wl = W.tiny(16, 14, 8, 0.3)
+    P = Problem(wl, poisson_solver=0)
+    g = P.grid
+    D = learned.cell_delta(g, wl.xb, wl.yb)
+    return wl, P, g, D
+
+
+def test_energy_loss_bounds_and_optimum():
+    # -1 <= loss <= 0 (Cauchy-Schwarz in the K inner product), -1 exactly for
+    # a correction parallel to the error, 0 for one K-orthogonal to it
+    wl, P, g, D = _tiny_system()
+    K = P.ops.K
+    rng = np.random.default_rng(3)
+    e1 = rng.standard_normal(K.shape[0])
+    r1 = K @ e1
+    for _ in range(5):
+        d = rng.standard_normal(K.shape[0])
+        L, _ = learned.energy_loss(d, K @ d, r1, e1)
+        assert -1.0 - 1e-12 <= L <= 0.0
+    L, gd = learned.energy_loss(-3.0 * e1, K @ (-3.0 * e1), r1, e1)
+    assert abs(L + 1.0) < 1e-12 and np.linalg.norm(gd) < 1e-9 * np.linalg.norm(r1)
+    d = rng.standard_normal(K.shape[0])
+    d -= (d @ (K @ e1)) / (e1 @ (K @ e1)) * e1
+    assert abs(learned.energy_loss(d, K @ d, r1, e1)[0]) < 1e-20
+
+
+def test_energy_loss_gradient_through_the_output_map():
+    wl, P, g, D = _tiny_system()
+    K = P.ops.K
+    rng = np.random.default_rng(4)
+    e1 = rng.standard_normal(K.shape[0])
+    r1 = K @ e1
+    y = rng.standard_normal((3, g.ny, g.nx))
+    s, dt = 0.7, wl.dt
+
+    def f(yy):
+        d = learned.correction(g, D, yy, s, dt)
+        return learned.energy_loss(d, K @ d, r1, e1)
+
+    L, gd = f(y)
+    gy = learned.correction_adjoint(g, D, gd, s, dt)
+    eps = 1e-6
+    for idx in [(0, 2, 3), (1, 7, 8), (2, 6, 9), (0, 13, 15)]:
+        yp, ym = y.copy(), y.copy()
+        yp[idx] += eps
+        ym[idx] -= eps
+        fd = (f(yp)[0] - f(ym)[0]) / (2 * eps)
+        assert abs(fd - gy[idx]) <= 1e-6 * max(1e-3, abs(fd)), (idx, fd, gy[idx])
+    # the loss does not change when y is scaled
+    assert abs(f(3.5 * y)[0] - L) < 1e-12
