@@ -82,6 +82,11 @@ typedef struct ibpm_params {
     int32_t amg_max_levels;
     double inner_rtol;           /* refinement (solvers 2, 4): floor of the relative tolerance
                                     of an inner FP32 solve; 0 selects 1e-5 */
+    int32_t learned_every;       /* solvers 3, 4: the network runs on every learned_every-th
+                                    preconditioner application, the V-cycle alone on the
+                                    others; 0 or 1 = every application */
+    int32_t fcg_depth;           /* solvers 3, 4: directions kept by the truncated flexible
+                                    CG, FCG(m); 0 selects 4, at most 8 */
 } ibpm_params;
 
 typedef struct ibpm_solve_stats {
@@ -226,7 +231,8 @@ int ibpm_time_kernel(ibpm_ctx *ctx, int32_t kernel, int32_t reps, double *avg_ms
  * BF16 operands and FP32 accumulation.  Its input is scaled by the RMS s of
  * the residual and its output by s / dt.  Solver IBPM_SOLVER_AMG_FCG_LEARNED
  * uses it in flexible CG: M(r) = z0 + w N(r - K z0) with z0 the AMG V-cycle
- * and w = (d . r1) / (d . K d); when the residual stalls (a chunk of >= 8
+ * and w = (d . r1) / (d . K d), each new direction K-orthogonal to the
+ * last fcg_depth ones; when the residual stalls (a chunk of >= 8
  * iterations reducing it by < 5 %) or turns NaN the solve falls back to plain
  * AMG-PCG from the current iterate (ibpm_solve_stats.fallbacks).
  * Weights are given per layer as [out][in][3][3] FP32, layers concatenated:

@@ -97,6 +97,9 @@ struct NNState {
     int max_losses = 0;
 };
 
+// ring of FCG(m) directions for precision T (allocated on first use)
+template <class T> struct FcgStore { FcgVecs<T> P{}, Q{}; int m = 0; };
+
 }  // namespace
 
 struct ibpm_ctx {
@@ -122,6 +125,9 @@ struct ibpm_ctx {
     std::vector<double> coarse_C;      // host copy of the dense coarse-cycle matrix
     double *coarse_C_dev = nullptr;    // its device copy (shared by both precisions)
     double *copy_x = nullptr, *copy_y = nullptr;   // bandwidth reference buffers
+    FcgStore<double> fcg64;                        // FCG(m) direction rings
+    FcgStore<float> fcg32;
+    FcgRing *fcg_ring = nullptr;
     int coarse_C_lc = -1;
     // velocity PCG (n_q)
     double *vr = nullptr, *vz = nullptr, *vp[2] = {nullptr, nullptr}, *vq = nullptr;
@@ -132,7 +138,9 @@ struct ibpm_ctx {
     double *parts2 = nullptr;          // second partial-sum buffer (read by the next kernel)
     int rz_G = 0;                      // partials of r . z left in parts by the last V-cycle
     SolveStatus *host_st = nullptr;   // pinned
-    int est_vel = 8, est_poi = 32, est_inner = 32;
+    int est_vel = 8, est_poi = 32;
+    int est_inner[32];                 // iterations of the k-th inner solve of a refinement
+    ibpm_ctx() { for (int &e : est_inner) e = 32; }
     bool learned = false;
     NNState nn;
 
@@ -366,6 +374,9 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
     return code;
 }
 
+FcgStore<double> &fcg_store(ibpm_ctx *c, double *) { return c->fcg64; }
+FcgStore<float> &fcg_store(ibpm_ctx *c, float *) { return c->fcg32; }
+
 int solve_poisson_fp64(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
     bool jacobi = !c->amg;
     PrecSet<double> &P = c->p64;
@@ -432,7 +443,7 @@ int solve_poisson_mixed(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_
         if (!plain) {
             bool stall = false;
             SolveStatus h = fcg_learned_drive<float>(c, P, c->rin32, c->d32, c->st_poi, tol_in,
-                                                     maxit_in, c->est_inner, true, &stall);
+                                                     maxit_in, c->est_inner[std::min(outer, 31)], true, &stall);
             inner_total += h.iter;
             if (h.done == ST_NAN) add = false;
             if (stall || h.done == ST_NAN) {
@@ -443,7 +454,7 @@ int solve_poisson_mixed(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_
             ibpm_solve_stats is{};
             int rc = pcg_drive<K0T<float>, float>(c, P.K0, n, false, pre, c->rin32, c->d32, P.r,
                                                   P.z, P.p, P.q, c->st_poi, tol_in, maxit_in,
-                                                  c->est_inner, true, false, &is);
+                                                  c->est_inner[std::min(outer, 31)], true, false, &is);
             inner_total += is.iters;
             if (rc == IBPM_ENAN) {
                 code = IBPM_ENAN;
@@ -756,32 +767,65 @@ void learned_guess(ibpm_ctx *c, const double *b, double *x, SolveStatus *st) {
 // The flexible-CG loop (iterations queued in predicated chunks as in
 // pcg_drive).  Returns the host copy of the final status; *stall is set when
 // a chunk of at least 8 iterations reduced ||r|| by less than 5 %.
+FcgStore<double> &fcg_store(ibpm_ctx *c, double *);
+FcgStore<float> &fcg_store(ibpm_ctx *c, float *);
+
+template <class T>
+FcgStore<T> &fcg_ring(ibpm_ctx *c, int m, int n) {
+    FcgStore<T> &F = fcg_store(c, (T *)nullptr);
+    for (int j = F.m; j < m; ++j) {
+        F.P.v[j] = c->dalloc<T>(n);
+        F.Q.v[j] = c->dalloc<T>(n);
+    }
+    if (m > F.m) F.m = m;
+    return F;
+}
+
 template <class T>
 SolveStatus fcg_learned_drive(ibpm_ctx *c, PrecSet<T> &P, const T *b, T *x, SolveStatus *st,
                               double rtol, int maxit, int &est, bool zero_guess, bool *stall) {
     hipStream_t s = c->stream;
     const K0T<T> &K = P.K0;
     const int n = K.n;
+    const int m = std::min(kFcgMax, c->prm.fcg_depth > 0 ? c->prm.fcg_depth : 4);
+    FcgStore<T> &F = fcg_ring<T>(c, m, n);
+    if (!c->fcg_ring) c->fcg_ring = c->dalloc<FcgRing>(1);
+    FcgRing *ring = c->fcg_ring;
     if (zero_guess) launch_pcg_init_zero(s, n, b, x, P.r, st, c->parts, rtol * rtol, maxit);
     else launch_pcg_init(s, K, b, (const T *)x, P.r, (T *)nullptr, st, c->parts, false, rtol * rtol, maxit);
-    learned_precond<T>(c, P, P.r, P.z, st);
-    int curp = 0, chunk = std::max(1, (int)(0.8 * est)), queued = 0;
+    // the network runs on every `every`-th preconditioner application, the
+    // plain V-cycle on the others (flexible CG allows the change)
+    const int every = std::max(1, c->prm.learned_every);
+    long napp = 0;
+    auto precond = [&](const T *r, T *z) {
+        if (napp++ % every == 0) learned_precond<T>(c, P, r, z, st);
+        else enqueue_vcycle(c, P, r, z, st, false);
+    };
+    long k = 0;   // iterations queued so far (direction k goes to slot k % m)
+    auto iteration = [&]() {
+        precond(P.r, P.z);
+        const int cnt = (int)std::min<long>(k, m);
+        FcgSlots sl{};
+        for (int j = 0; j < cnt; ++j) sl.s[j] = (int)((k - cnt + j) % m);
+        launch_fcg_betas<T>(s, n, P.z, F.Q, cnt, sl, ring, st, c->parts);
+        const int slot = (int)(k % m);
+        launch_fcg_direction<T>(s, n, P.z, F.P, cnt, sl, ring, F.P.v[slot], st);
+        launch_fcg_product<T>(s, K, F.P.v[slot], F.Q.v[slot], P.r, slot, ring, st, c->parts);
+        launch_pcg_update(s, K, x, P.r, (T *)nullptr, (const T *)F.P.v[slot], (const T *)F.Q.v[slot],
+                          st, (const double *)nullptr, c->parts, false, false);
+        ++k;
+    };
+    int chunk = std::max(1, (int)(0.8 * est)), queued = 0;
     double last_rr = -1, chunk_rr = -1;
     int last_it = 0;
     *stall = false;
     for (;;) {
-        for (int k = 0; k < chunk; ++k) {
-            launch_fcg_spmv<T>(s, K, P.z, P.p[curp], P.p[1 - curp], P.q, P.r, st, c->parts);
-            curp = 1 - curp;
-            launch_pcg_update(s, K, x, P.r, (T *)nullptr, (const T *)P.p[curp], (const T *)P.q, st,
-                              (const double *)nullptr, c->parts, false, false);
-            learned_precond<T>(c, P, P.r, P.z, st);
-            launch_fcg_beta<T>(s, n, P.z, P.q, st, c->parts);
-        }
+        for (int i = 0; i < chunk; ++i) iteration();
         queued += chunk;
         c->read_status(st);
         const SolveStatus &h = *c->host_st;
         if (h.done != ST_RUNNING || queued > maxit + 1) break;
+        // stall: a chunk of at least 8 iterations that reduced ||r|| by less than 5 %
         if (chunk_rr > 0 && h.iter - last_it >= 8 && h.rr > 0.9025 * chunk_rr) {
             *stall = true;
             break;
@@ -888,6 +932,8 @@ void check_params(const ibpm_params *p) {
     if (p->poisson_solver < IBPM_SOLVER_JACOBI_PCG || p->poisson_solver > IBPM_SOLVER_AMG_FCG_MIXED_LEARNED)
         throw InvalidArg("unknown Poisson solver");
     if (!(p->inner_rtol >= 0) || p->inner_rtol >= 1) throw InvalidArg("inner_rtol must be in [0, 1)");
+    if (p->learned_every < 0) throw InvalidArg("learned_every must be >= 0");
+    if (p->fcg_depth < 0 || p->fcg_depth > kFcgMax) throw InvalidArg("fcg_depth must be in [0, 8]");
     if (p->poisson_solver != IBPM_SOLVER_JACOBI_PCG) {
         if (p->amg_pre < 1 || p->amg_post < 1) throw InvalidArg("AMG needs >= 1 pre and post sweep");
         if (p->amg_coarse_max < 1 || p->amg_max_levels < 1) throw InvalidArg("bad AMG limits");
@@ -1075,8 +1121,9 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     c->st_misc = sts + 2;
     c->st_bench = sts + 3;
     c->st_out = sts + 4;
-    c->parts = c->dalloc<double>(4 * kMaxParts);
-    c->parts2 = c->dalloc<double>(4 * kMaxParts);
+    // partial sums of up to kFcgMax components per block (FCG multi-dot)
+    c->parts = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
+    c->parts2 = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
     HIPCHECK(hipHostMalloc((void **)&c->host_st, sizeof(SolveStatus), hipHostMallocDefault));
     double U = p->uinf * std::cos(p->alpha), V = p->uinf * std::sin(p->alpha);
     launch_fill_walls(c->stream, c->g, c->walls[0], U, V);

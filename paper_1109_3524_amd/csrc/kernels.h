@@ -14,9 +14,9 @@ constexpr int kMaxParts = 32768;   // upper bound on blocks of a reducing kernel
 // R) and the largest 1-D grid of the elementwise kernels.  Set once per
 // process (IBPM_WALK_ROWS, IBPM_MAX_BLOCKS override the defaults).
 struct LaunchShape {
-    int max_walk_blocks = 4096;
+    int max_walk_blocks = 8448;
     int walk_rows = 0;
-    int max_blocks = 8192;
+    int max_blocks = 2048;
 };
 LaunchShape &launch_shape();
 
@@ -207,6 +207,34 @@ void launch_coarse_dense(hipStream_t s, int n, const double *C, const T *b, T *x
 
 // y = x (n even), a plain streaming copy for bandwidth reference
 void launch_stream_copy(hipStream_t s, size_t n, const double *x, double *y);
+
+// Truncated flexible CG, FCG(m) (Notay): the new direction is made
+// K-orthogonal to the last m directions.  Directions and their products are
+// kept in a ring of m slots; ring->pq holds p_i . q_i of each slot.
+constexpr int kFcgMax = 8;
+struct FcgRing {
+    double pq[kFcgMax];
+    double beta[kFcgMax];
+};
+template <class T>
+struct FcgVecs {
+    T *v[kFcgMax];
+};
+struct FcgSlots {
+    int s[kFcgMax];
+};
+//   beta_j = -(z . q_{slot j}) / pq_{slot j}, j < cnt (into ring->beta)
+template <class T>
+void launch_fcg_betas(hipStream_t s, int n, const T *z, FcgVecs<T> Q, int cnt, FcgSlots sl,
+                      FcgRing *ring, const SolveStatus *st, double *parts);
+//   p = z + sum_j beta_j P_{slot j}
+template <class T>
+void launch_fcg_direction(hipStream_t s, int n, const T *z, FcgVecs<T> P, int cnt, FcgSlots sl,
+                          const FcgRing *ring, T *p, const SolveStatus *st);
+//   q = K p; st->pq = p . q, st->rz = p . r, ring->pq[slot] = p . q
+template <class T>
+void launch_fcg_product(hipStream_t s, const K0T<T> &K, const T *p, T *q, const T *r, int slot,
+                        FcgRing *ring, SolveStatus *st, double *parts);
 
 // flexible CG with a learned stage (vectors of T, sums in FP64):
 //   p_new = z + beta p_old, q = K p_new, st->pq = p.q, st->rz = p.r

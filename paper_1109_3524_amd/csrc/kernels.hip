@@ -147,7 +147,52 @@ __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
         const int cy = w / cx_n, cx = w - cy * cx_n;
         const int i = cx * kBlock + threadIdx.x;
         const int j0 = cy * R;
-        if (i < nx && j0 < ny) {
+        if (i < nx && j0 + R < ny) {
+            // interior tile: every row has a north neighbour; all operand
+            // loads of the R rows are issued before the arithmetic
+            const T dt = K.dt;
+            const T dxi = g.dx[i];
+            const T cw = i > 0 ? dt * g.iDx[i] : T(0);
+            const T ce = i < nx - 1 ? dt * g.iDx[i + 1] : T(0);
+            const bool in_box_i = i >= K.cb_i0 && i <= K.cb_i1;
+            const int bw_ = K.cb_i1 - K.cb_i0 + 1;
+            const int row0 = j0 * nx + i;
+            T xcol[R + 2], xwr[R], xer[R], dyr[R], iyr[R + 1];
+            xcol[0] = j0 > 0 ? xv(row0 - nx) : T(0);
+#pragma unroll
+            for (int k = 0; k <= R; ++k) xcol[k + 1] = xv(row0 + k * nx);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                xwr[r] = i > 0 ? xv(row0 + r * nx - 1) : T(0);
+                xer[r] = i < nx - 1 ? xv(row0 + r * nx + 1) : T(0);
+                dyr[r] = g.dy[j0 + r];
+            }
+#pragma unroll
+            for (int r = 0; r <= R; ++r) iyr[r] = g.iDy[j0 + r];
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int j = j0 + r;
+                const int row = row0 + r * nx;
+                const T bw = cw * dyr[r], be = ce * dyr[r];
+                const T bs = j > 0 ? dt * dxi * iyr[r] : T(0);
+                const T bn = dt * dxi * iyr[r + 1];
+                const T diag = ((bw + be) + bs) + bn;
+                const T xc = xcol[r + 1];
+                T y = diag * xc;
+                if (row != 0) {
+                    if (row - nx != 0) y -= bs * xcol[r];
+                    if (row - 1 != 0) y -= bw * xwr[r];
+                    y -= be * xer[r];
+                    y -= bn * xcol[r + 2];
+                    if (in_box_i && j >= K.cb_j0 && j <= K.cb_j1) {
+                        const int rb = (j - K.cb_j0) * bw_ + (i - K.cb_i0);
+                        for (int p = K.cf.ptr[rb]; p < K.cf.ptr[rb + 1]; ++p)
+                            y += K.cf.val[p] * xv(g.n_cell + K.cf.col[p]);
+                    }
+                }
+                act(row, y, diag, xc);
+            }
+        } else if (i < nx && j0 < ny) {
             const T dt = K.dt;
             const T dxi = g.dx[i];
             const T cw = i > 0 ? dt * g.iDx[i] : T(0);
@@ -218,76 +263,139 @@ __device__ __forceinline__ void a_walk(const AView &A, XV xv, ACT act) {
     const GridView &g = A.g;
     const int nx = g.nx, ny = g.ny, nxm = nx - 1;
     const double hnu = 0.5 * A.nu;
-    const int gyu = walk_by<R>(ny);
-    if ((int)blockIdx.y < gyu) {
-        const int i = blockIdx.x * 64 + (threadIdx.x & 63) + 1;       // 1..nx-1
-        const int j0 = (blockIdx.y * 4 + (threadIdx.x >> 6)) * R;
-        if (i <= nx - 1 && j0 < ny) {
-            const double idxi = g.idx[i], idxm = g.idx[i - 1], iDxi = g.iDx[i], Dxi = g.Dx[i];
-            int f = j0 * nxm + (i - 1);
-            double us = j0 > 0 ? xv(f - nxm) * g.idy[j0 - 1] : 0.0;
-            double xc = xv(f);
-            double uc = xc * g.idy[j0];
+    // 1-D grid of 256-column x R-row tiles, u faces then v faces, the tiles
+    // of one XCD contiguous
+    const int cxu = (nxm + kBlock - 1) / kBlock, cyu = (ny + R - 1) / R;
+    const int cxv = (nx + kBlock - 1) / kBlock;
+    const int Gu = cxu * cyu;
+    const int w = remap_block((int)blockIdx.x, (int)gridDim.x);
+    if (w < Gu) {
+        const int cy = w / cxu, cx = w - cy * cxu;
+        const int i = cx * kBlock + threadIdx.x + 1;                   // 1..nx-1
+        const int j0 = cy * R;
+        if (i > nx - 1 || j0 >= ny) return;
+        const double idxi = g.idx[i], idxm = g.idx[i - 1], iDxi = g.iDx[i], Dxi = g.Dx[i];
+        const int f0 = j0 * nxm + (i - 1);
+        if (j0 + R < ny) {
+            double xcol[R + 2], xe[R], xw[R];
+            xcol[0] = j0 > 0 ? xv(f0 - nxm) : 0.0;
+#pragma unroll
+            for (int k = 0; k <= R; ++k) xcol[k + 1] = xv(f0 + k * nxm);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                xe[r] = i < nx - 1 ? xv(f0 + r * nxm + 1) : 0.0;
+                xw[r] = i > 1 ? xv(f0 + r * nxm - 1) : 0.0;
+            }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int j = j0 + r;
-                if (j >= ny) break;
                 const double idyj = g.idy[j];
-                const double xn = j < ny - 1 ? xv(f + nxm) : 0.0;
-                const double un = j < ny - 1 ? xn * g.idy[j + 1] : 0.0;
-                const double uE = i < nx - 1 ? xv(f + 1) * idyj : 0.0;
-                const double uW = i > 1 ? xv(f - 1) * idyj : 0.0;
+                const double xc = xcol[r + 1];
+                const double uc = xc * idyj;
+                const double us = j > 0 ? xcol[r] * g.idy[j - 1] : 0.0;
+                const double un = xcol[r + 2] * g.idy[j + 1];
+                const double uE = xe[r] * idyj, uW = xw[r] * idyj;
                 const double lapx = ((uE - uc) * idxi - (uc - uW) * idxm) * iDxi;
                 const double lapy = ((un - uc) * g.iDy[j + 1] - (uc - us) * g.iDy[j]) * idyj;
                 const double mf = Dxi * idyj;
                 const double diag = mf * A.idt + hnu * ((idxi + idxm) * idyj +
                                                          Dxi * (g.iDy[j + 1] + g.iDy[j]) * idyj * idyj);
-                act(f, mf * A.idt * xc - hnu * (Dxi * (lapx + lapy)), diag, xc);
-                us = uc;
-                uc = un;
-                xc = xn;
-                f += nxm;
+                act(f0 + r * nxm, mf * A.idt * xc - hnu * (Dxi * (lapx + lapy)), diag, xc);
             }
+            return;
+        }
+        int f = f0;
+        double us = j0 > 0 ? xv(f - nxm) * g.idy[j0 - 1] : 0.0;
+        double xc = xv(f);
+        double uc = xc * g.idy[j0];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = j0 + r;
+            if (j >= ny) break;
+            const double idyj = g.idy[j];
+            const double xn = j < ny - 1 ? xv(f + nxm) : 0.0;
+            const double un = j < ny - 1 ? xn * g.idy[j + 1] : 0.0;
+            const double uE = i < nx - 1 ? xv(f + 1) * idyj : 0.0;
+            const double uW = i > 1 ? xv(f - 1) * idyj : 0.0;
+            const double lapx = ((uE - uc) * idxi - (uc - uW) * idxm) * iDxi;
+            const double lapy = ((un - uc) * g.iDy[j + 1] - (uc - us) * g.iDy[j]) * idyj;
+            const double mf = Dxi * idyj;
+            const double diag = mf * A.idt + hnu * ((idxi + idxm) * idyj +
+                                                     Dxi * (g.iDy[j + 1] + g.iDy[j]) * idyj * idyj);
+            act(f, mf * A.idt * xc - hnu * (Dxi * (lapx + lapy)), diag, xc);
+            us = uc;
+            uc = un;
+            xc = xn;
+            f += nxm;
         }
     } else {
-        const int by = blockIdx.y - gyu;
-        const int i = blockIdx.x * 64 + (threadIdx.x & 63);           // 0..nx-1
-        const int j0 = (by * 4 + (threadIdx.x >> 6)) * R + 1;        // 1..ny-1
-        if (i < nx && j0 <= ny - 1) {
-            const double idxi = g.idx[i], dxr = g.iDx[i + 1], dxl = g.iDx[i];
-            const double idxe = i < nx - 1 ? g.idx[i + 1] : 0.0, idxw = i > 0 ? g.idx[i - 1] : 0.0;
-            int f = g.n_u + (j0 - 1) * nx + i;
-            double vs = j0 > 1 ? xv(f - nx) * idxi : 0.0;
-            double xc = xv(f);
-            double vc = xc * idxi;
+        const int wv = w - Gu;
+        const int cy = wv / cxv, cx = wv - cy * cxv;
+        const int i = cx * kBlock + threadIdx.x;                       // 0..nx-1
+        const int j0 = cy * R + 1;                                     // 1..ny-1
+        if (i >= nx || j0 > ny - 1) return;
+        const double idxi = g.idx[i], dxr = g.iDx[i + 1], dxl = g.iDx[i];
+        const double idxe = i < nx - 1 ? g.idx[i + 1] : 0.0, idxw = i > 0 ? g.idx[i - 1] : 0.0;
+        const int f0 = g.n_u + (j0 - 1) * nx + i;
+        if (j0 + R < ny) {
+            double xcol[R + 2], xe[R], xw[R];
+            xcol[0] = j0 > 1 ? xv(f0 - nx) : 0.0;
+#pragma unroll
+            for (int k = 0; k <= R; ++k) xcol[k + 1] = xv(f0 + k * nx);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                xe[r] = i < nx - 1 ? xv(f0 + r * nx + 1) : 0.0;
+                xw[r] = i > 0 ? xv(f0 + r * nx - 1) : 0.0;
+            }
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int j = j0 + r;
-                if (j > ny - 1) break;
-                const double xn = j < ny - 1 ? xv(f + nx) : 0.0;
-                const double vn = xn * idxi;
-                const double vE = i < nx - 1 ? xv(f + 1) * idxe : 0.0;
-                const double vW = i > 0 ? xv(f - 1) * idxw : 0.0;
+                const double xc = xcol[r + 1];
+                const double vc = xc * idxi, vs = xcol[r] * idxi, vn = xcol[r + 2] * idxi;
+                const double vE = xe[r] * idxe, vW = xw[r] * idxw;
                 const double lapx = ((vE - vc) * dxr - (vc - vW) * dxl) * idxi;
                 const double lapy = ((vn - vc) * g.idy[j] - (vc - vs) * g.idy[j - 1]) * g.iDy[j];
                 const double Dyj = g.Dy[j];
                 const double mf = Dyj * idxi;
                 const double diag = mf * A.idt + hnu * (Dyj * (dxr + dxl) * idxi * idxi +
                                                          (g.idy[j] + g.idy[j - 1]) * idxi);
-                act(f, mf * A.idt * xc - hnu * (Dyj * (lapx + lapy)), diag, xc);
-                vs = vc;
-                vc = vn;
-                xc = xn;
-                f += nx;
+                act(f0 + r * nx, mf * A.idt * xc - hnu * (Dyj * (lapx + lapy)), diag, xc);
             }
+            return;
+        }
+        int f = f0;
+        double vs = j0 > 1 ? xv(f - nx) * idxi : 0.0;
+        double xc = xv(f);
+        double vc = xc * idxi;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int j = j0 + r;
+            if (j > ny - 1) break;
+            const double xn = j < ny - 1 ? xv(f + nx) : 0.0;
+            const double vn = xn * idxi;
+            const double vE = i < nx - 1 ? xv(f + 1) * idxe : 0.0;
+            const double vW = i > 0 ? xv(f - 1) * idxw : 0.0;
+            const double lapx = ((vE - vc) * dxr - (vc - vW) * dxl) * idxi;
+            const double lapy = ((vn - vc) * g.idy[j] - (vc - vs) * g.idy[j - 1]) * g.iDy[j];
+            const double Dyj = g.Dy[j];
+            const double mf = Dyj * idxi;
+            const double diag = mf * A.idt + hnu * (Dyj * (dxr + dxl) * idxi * idxi +
+                                                     (g.idy[j] + g.idy[j - 1]) * idxi);
+            act(f, mf * A.idt * xc - hnu * (Dyj * (lapx + lapy)), diag, xc);
+            vs = vc;
+            vc = vn;
+            xc = xn;
+            f += nx;
         }
     }
 }
 
 template <int R>
 inline dim3 a_grid(const AView &A) {
-    int gx = (A.g.nx + 63) / 64;
-    return dim3(gx, walk_by<R>(A.g.ny) + walk_by<R>(A.g.ny - 1));
+    const int nx = A.g.nx, ny = A.g.ny;
+    const int gu = ((nx - 1 + kBlock - 1) / kBlock) * ((ny + R - 1) / R);
+    const int gv = ((nx + kBlock - 1) / kBlock) * ((ny - 1 + R - 1) / R);
+    return dim3(gu + gv);
 }
 
 // diagonal of A for one face (used by elementwise kernels)
@@ -597,13 +705,13 @@ __global__ __launch_bounds__(kBlock) void k_dot_rz(int n, const T *r, const T *z
 // and the status update that goes with them.  One block.
 enum : int {
     FIN_INIT = 0, FIN_INIT_ZERO, FIN_PQ, FIN_UPDATE, FIN_TRUE, FIN_RZ, FIN_OUTER,
-    FIN_FCG_PQ, FIN_OMEGA, FIN_FCG_BETA
+    FIN_FCG_PQ, FIN_OMEGA, FIN_FCG_BETA, FIN_RZ_NEXT
 };
 
 __global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const double *parts,
                                                      SolveStatus *st, int flag, double rtol2,
                                                      int maxit) {
-    if ((kind == FIN_PQ || kind == FIN_UPDATE || kind == FIN_RZ || kind == FIN_FCG_PQ ||
+    if ((kind == FIN_PQ || kind == FIN_UPDATE || kind == FIN_RZ || kind == FIN_RZ_NEXT || kind == FIN_FCG_PQ ||
          kind == FIN_FCG_BETA) && st->done)
         return;
     const int N = (kind == FIN_INIT) ? 3
@@ -664,6 +772,10 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const doub
     case FIN_TRUE:
         st->true_rr = acc[0];
         break;
+    case FIN_RZ_NEXT:   // as the product kernel's own sum of the r . z partials
+        st->beta = st->first ? 0.0 : acc[0] / st->rz;
+        st->rz_next = acc[0];
+        break;
     case FIN_RZ:
         if (st->first) {
             st->beta = 0.0;
@@ -715,6 +827,91 @@ __global__ __launch_bounds__(kBlock) void k_fcg_spmv(K0T<T> K, const T *__restri
         v[1] += (double)pi * (double)r[row];
     });
     write_parts2<2>(v, parts);
+}
+
+// --- FCG(m) -----------------------------------------------------------------
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_fcg_multidot(int n, const T *__restrict__ z,
+                                                         FcgVecs<T> Q, int cnt, FcgSlots sl,
+                                                         const SolveStatus *st, double *parts) {
+    if (st->done) return;
+    Tiles Tl = my_tiles(n);
+    double v[kFcgMax];
+#pragma unroll
+    for (int j = 0; j < kFcgMax; ++j) v[j] = 0.0;
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
+        const int row = t * kBlock + threadIdx.x;
+        if (row < n) {
+            const double zr = (double)z[row];
+#pragma unroll
+            for (int j = 0; j < kFcgMax; ++j)
+                if (j < cnt) v[j] += zr * (double)Q.v[sl.s[j]][row];
+        }
+    }
+    write_parts<kFcgMax>(v, parts);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fcg_betas_finalize(int G, int cnt, FcgSlots sl,
+                                                               const double *parts, FcgRing *ring,
+                                                               const SolveStatus *st) {
+    if (st->done) return;
+    double acc[kFcgMax];
+#pragma unroll
+    for (int j = 0; j < kFcgMax; ++j) acc[j] = 0.0;
+    for (int b = threadIdx.x; b < G; b += kBlock)
+#pragma unroll
+        for (int j = 0; j < kFcgMax; ++j)
+            if (j < cnt) acc[j] += parts[j * kMaxParts + b];
+    block_sum<kFcgMax>(acc);
+    if (threadIdx.x == 0)
+        for (int j = 0; j < cnt; ++j) {
+            const double pq = ring->pq[sl.s[j]];
+            ring->beta[j] = pq != 0.0 ? -acc[j] / pq : 0.0;
+        }
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_fcg_direction(int n, const T *__restrict__ z,
+                                                          FcgVecs<T> P, int cnt, FcgSlots sl,
+                                                          const FcgRing *ring, T *p,
+                                                          const SolveStatus *st) {
+    // p may be the slot of the oldest direction in the window: each element
+    // is read before it is overwritten, by the same thread
+    if (st->done) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    T v = z[i];
+    for (int j = 0; j < cnt; ++j) v += (T)ring->beta[j] * P.v[sl.s[j]][i];
+    p[i] = v;
+}
+
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_fcg_product(K0T<T> K, const T *__restrict__ p,
+                                                        T *__restrict__ q, const T *__restrict__ r,
+                                                        const SolveStatus *st, double *parts) {
+    if (st->done) return;
+    double v[2] = {0.0, 0.0};
+    k0_walk<R>(K, [&](int c) { return p[c]; }, [&](int row, T qi, T, T pi) {
+        q[row] = qi;
+        v[0] += (double)pi * (double)qi;
+        v[1] += (double)pi * (double)r[row];
+    });
+    write_parts2<2>(v, parts);
+}
+
+__global__ __launch_bounds__(kBlock) void k_fcg_pq_finalize(int G, const double *parts, int slot,
+                                                            FcgRing *ring, SolveStatus *st) {
+    if (st->done) return;
+    double acc[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < G; b += kBlock)
+        for (int k = 0; k < 2; ++k) acc[k] += parts[k * kMaxParts + b];
+    block_sum<2>(acc);
+    if (threadIdx.x == 0) {
+        st->pq = acc[0];
+        st->rz = acc[1];
+        ring->pq[slot] = acc[0];
+    }
 }
 
 // sums d.r1 and d.(K d)
@@ -1300,11 +1497,19 @@ static int walk_grid_blocks(const Op &op) {
 
 int walk_blocks_of(const K0View &K) { return walk_grid_blocks(K); }
 
+// above this many partials a sum read by every block of the consumer costs
+// more than a one-block finalize launch
+constexpr int kFuseMaxParts = 1024;
+
 template <class Op, class T>
 void launch_pcg_spmv(hipStream_t s, const Op &op, const T *z, const T *pold, T *pnew, T *q,
                      SolveStatus *st, const double *rz_parts, int G_rz, double *parts) {
     if (rz_parts && (rz_parts == parts || G_rz < 1 || G_rz > kMaxParts))
         throw std::runtime_error("pcg product: bad partial buffers");
+    if (rz_parts && G_rz > kFuseMaxParts) {
+        LAUNCH(k_finalize, 1, (int)FIN_RZ_NEXT, G_rz, rz_parts, st, 0, 0.0, 0);
+        rz_parts = nullptr;
+    }
     WALK_SWITCH(pick_R(op), {
         dim3 gd = op_grid<RR>(op);
         LAUNCH2((k_pcg_spmv<RR, Op, T>), gd, op, z, pold, pnew, q, st, rz_parts, G_rz, parts);
@@ -1316,7 +1521,12 @@ void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, T *z, const T *p
                        SolveStatus *st, const double *pq_parts, double *parts, bool jacobi,
                        bool fused_rz) {
     if (pq_parts == parts) throw std::runtime_error("pcg update: partial buffers must differ");
-    const int G_pq = pq_parts ? walk_grid_blocks(op) : 0;
+    int G_pq = pq_parts ? walk_grid_blocks(op) : 0;
+    if (pq_parts && G_pq > kFuseMaxParts) {
+        LAUNCH(k_finalize, 1, (int)FIN_PQ, G_pq, pq_parts, st, 0, 0.0, 0);
+        pq_parts = nullptr;
+        G_pq = 0;
+    }
     int G = grid_for(op_n(op));
     LAUNCH((k_pcg_update<Op, T>), G, op, x, r, z, p, q, st, pq_parts, G_pq, parts, (int)jacobi,
            (int)fused_rz);
@@ -1493,6 +1703,35 @@ void launch_fcg_spmv(hipStream_t s, const K0T<T> &K, const T *z, const T *pold, 
     LAUNCH(k_finalize, 1, (int)FIN_FCG_PQ, G, parts, st, 0, 0.0, 0);
 }
 
+template <class T>
+void launch_fcg_betas(hipStream_t s, int n, const T *z, FcgVecs<T> Q, int cnt, FcgSlots sl,
+                      FcgRing *ring, const SolveStatus *st, double *parts) {
+    if (cnt < 1) return;
+    if (cnt > kFcgMax) throw std::runtime_error("fcg: too many directions");
+    int G = grid_for(n);
+    LAUNCH((k_fcg_multidot<T>), G, n, z, Q, cnt, sl, st, parts);
+    LAUNCH(k_fcg_betas_finalize, 1, G, cnt, sl, (const double *)parts, ring, st);
+}
+
+template <class T>
+void launch_fcg_direction(hipStream_t s, int n, const T *z, FcgVecs<T> P, int cnt, FcgSlots sl,
+                          const FcgRing *ring, T *p, const SolveStatus *st) {
+    if (cnt < 0 || cnt > kFcgMax) throw std::runtime_error("fcg: too many directions");
+    LAUNCH((k_fcg_direction<T>), (n + kBlock - 1) / kBlock, n, z, P, cnt, sl, ring, p, st);
+}
+
+template <class T>
+void launch_fcg_product(hipStream_t s, const K0T<T> &K, const T *p, T *q, const T *r, int slot,
+                        FcgRing *ring, SolveStatus *st, double *parts) {
+    int G = 0;
+    WALK_SWITCH(pick_R(K), {
+        dim3 gd = op_grid<RR>(K);
+        G = gd.x * gd.y;
+        LAUNCH2((k_fcg_product<RR, T>), gd, K, p, q, r, (const SolveStatus *)st, parts);
+    })
+    LAUNCH(k_fcg_pq_finalize, 1, G, (const double *)parts, slot, ring, st);
+}
+
 // the learned-stage weight is only computed while the solve runs (st), into stw
 template <class T>
 void launch_kd_omega(hipStream_t s, const K0T<T> &K, const T *d, const T *r1, SolveStatus *stw,
@@ -1607,5 +1846,15 @@ INST_V(float)
     template void launch_fcg_beta<T>(hipStream_t, int, const T *, const T *, SolveStatus *, double *);
 INST_F(double)
 INST_F(float)
+
+#define INST_M(T)                                                                                \
+    template void launch_fcg_betas<T>(hipStream_t, int, const T *, FcgVecs<T>, int, FcgSlots,   \
+                                      FcgRing *, const SolveStatus *, double *);                 \
+    template void launch_fcg_direction<T>(hipStream_t, int, const T *, FcgVecs<T>, int, FcgSlots,\
+                                          const FcgRing *, T *, const SolveStatus *);            \
+    template void launch_fcg_product<T>(hipStream_t, const K0T<T> &, const T *, T *, const T *,  \
+                                        int, FcgRing *, SolveStatus *, double *);
+INST_M(double)
+INST_M(float)
 
 }  // namespace ibpm

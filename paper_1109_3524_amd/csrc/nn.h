@@ -18,6 +18,7 @@ constexpr int kNNIn = 5;            // input channels (padded to 8)
 constexpr int kNNInPad = 8;
 constexpr int kNNOut = 3;           // output channels (padded to 32)
 constexpr int kConvTile = 128;      // pixels of one image row per block (4 waves x 32)
+constexpr int kConvRows = 4;        // image rows per block of the convolution
 
 // K of the implicit GEMM padded to the MFMA step (16)
 __host__ __device__ constexpr int conv_kp(int cin) { return ((9 * cin + 15) / 16) * 16; }

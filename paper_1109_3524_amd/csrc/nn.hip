@@ -28,17 +28,18 @@ constexpr int kDS = kConvTile + 8;      // row stride of the transposed dY tile
 __device__ __forceinline__ float to_f(float v) { return v; }
 __device__ __forceinline__ float to_f(__bf16 v) { return (float)v; }
 
-// stage rows y-1..y+1, pixels x0-1..x0+128 of an H x W x CIN image into LDS
-template <class TIn, int CIN>
+// stage NR image rows from ytop, pixels x0-1..x0+128 of an H x W x CIN image
+// into LDS (zero outside the image; where mask <= 0 the value is taken as 0)
+template <class TIn, int CIN, int NR>
 __device__ __forceinline__ void stage_rows(__bf16 *xs, const TIn *X, const __bf16 *mask, int H,
-                                           int W, int x0, int y) {
+                                           int W, int x0, int ytop) {
     constexpr int CH = CIN / 8;
-    for (int e = threadIdx.x; e < 3 * kTW * CH; e += kBlock) {
+    for (int e = threadIdx.x; e < NR * kTW * CH; e += kBlock) {
         int dy = e / (kTW * CH);
         int rem = e - dy * kTW * CH;
         int px = rem / CH;
         int cg = rem - px * CH;
-        int gy = y + dy - 1, gx = x0 + px - 1;
+        int gy = ytop + dy, gx = x0 + px - 1;
         bf16x8 v;
 #pragma unroll
         for (int k = 0; k < 8; ++k) v[k] = (__bf16)0.0f;
@@ -55,49 +56,56 @@ __device__ __forceinline__ void stage_rows(__bf16 *xs, const TIn *X, const __bf1
     }
 }
 
+// One block: 128 pixels x kConvRows rows.  Each wave keeps the B fragments
+// of every K step (its 32 x K_pad slice of the weights) in registers for all
+// the rows of the tile; the input rows with their halo are staged once.
 template <class TIn, int CIN>
 __global__ __launch_bounds__(kBlock) void k_conv3x3(int H, int W, const TIn *X, const __bf16 *mask,
                                                     const __bf16 *Wp, float *Y32, __bf16 *Y16,
                                                     int relu) {
     constexpr int KP = conv_kp(CIN);
-    __shared__ __attribute__((aligned(16))) __bf16 xs[3 * kTW * CIN];
-    __shared__ __attribute__((aligned(16))) __bf16 ws[32 * KP];
-    const int x0 = blockIdx.x * kConvTile, y = blockIdx.y;
-    stage_rows<TIn, CIN>(xs, X, mask, H, W, x0, y);
-    for (int e = threadIdx.x; e < 32 * KP / 8; e += kBlock)
-        *(bf16x8 *)&ws[e * 8] = *(const bf16x8 *)&Wp[e * 8];
-    __syncthreads();
+    constexpr int NS = KP / 16;
+    __shared__ __attribute__((aligned(16))) __bf16 xs[(kConvRows + 2) * kTW * CIN];
+    const int x0 = blockIdx.x * kConvTile, y0 = blockIdx.y * kConvRows;
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int pl = w * 32 + (l & 31);
     const int kh = (l >> 5) * 8;
-    f32x16 acc;
+    bf16x8 bw[NS];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
-#pragma unroll
-    for (int s = 0; s < KP / 16; ++s) {
-        const int k0 = s * 16 + kh;
-        const int tap = k0 / CIN, c0 = k0 - tap * CIN;
-        bf16x8 a;
-        if (tap < 9) {
-            const int dy = tap / 3, dx = tap - dy * 3;
-            a = *(const bf16x8 *)&xs[(dy * kTW + pl + dx) * CIN + c0];
-        } else {
-#pragma unroll
-            for (int k = 0; k < 8; ++k) a[k] = (__bf16)0.0f;
-        }
-        const bf16x8 b = *(const bf16x8 *)&ws[(l & 31) * KP + k0];
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
-    }
+    for (int s = 0; s < NS; ++s) bw[s] = *(const bf16x8 *)&Wp[(l & 31) * KP + s * 16 + kh];
+    stage_rows<TIn, CIN, kConvRows + 2>(xs, X, mask, H, W, x0, y0 - 1);
+    __syncthreads();
+    const int pl = w * 32 + (l & 31);
     const int n = l & 31;
+    for (int r = 0; r < kConvRows; ++r) {
+        const int y = y0 + r;
+        if (y >= H) break;
+        f32x16 acc;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int p = w * 32 + 8 * (j >> 2) + 4 * (l >> 5) + (j & 3);
-        const int gx = x0 + p;
-        if (gx < W) {
-            const size_t o = ((size_t)y * W + gx) * 32 + n;
-            const float v = acc[j];
-            if (Y32) Y32[o] = v;
-            if (Y16) Y16[o] = (__bf16)(relu ? fmaxf(v, 0.0f) : v);
+        for (int j = 0; j < 16; ++j) acc[j] = 0.0f;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const int k0 = s * 16 + kh;
+            const int tap = k0 / CIN, c0 = k0 - tap * CIN;
+            bf16x8 a;
+            if (tap < 9) {
+                const int dy = tap / 3, dx = tap - dy * 3;
+                a = *(const bf16x8 *)&xs[((r + dy) * kTW + pl + dx) * CIN + c0];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 8; ++k) a[k] = (__bf16)0.0f;
+            }
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, bw[s], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int p = w * 32 + 8 * (j >> 2) + 4 * (l >> 5) + (j & 3);
+            const int gx = x0 + p;
+            if (gx < W) {
+                const size_t o = ((size_t)y * W + gx) * 32 + n;
+                const float v = acc[j];
+                if (Y32) Y32[o] = v;
+                if (Y16) Y16[o] = (__bf16)(relu ? fmaxf(v, 0.0f) : v);
+            }
         }
     }
 }
@@ -111,7 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_conv3x3_dw(int H, int W, const __bf1
     __shared__ __attribute__((aligned(16))) __bf16 xs[3 * kTW * CIN];
     __shared__ __attribute__((aligned(16))) __bf16 dyt[32 * kDS];
     const int x0 = blockIdx.x * kConvTile, y = blockIdx.y;
-    stage_rows<__bf16, CIN>(xs, X, nullptr, H, W, x0, y);
+    stage_rows<__bf16, CIN, 3>(xs, X, nullptr, H, W, x0, y - 1);
     for (int e = threadIdx.x; e < kConvTile * 32; e += kBlock) {
         const int p = e >> 5, n = e & 31;
         const int gx = x0 + p;
@@ -377,7 +385,7 @@ __global__ __launch_bounds__(kBlock) void k_to_bf16(size_t n, const float *x, __
 template <class TIn, int CIN>
 void launch_conv3x3(hipStream_t s, int H, int W, const TIn *X, const bf16 *mask, const bf16 *Wp,
                     float *Y32, bf16 *Y16, int relu) {
-    dim3 grid((W + kConvTile - 1) / kConvTile, H);
+    dim3 grid((W + kConvTile - 1) / kConvTile, (H + kConvRows - 1) / kConvRows);
     hipLaunchKernelGGL((k_conv3x3<TIn, CIN>), grid, dim3(kBlock), 0, s, H, W, X, mask, Wp, Y32, Y16,
                        relu);
 }
