@@ -261,8 +261,14 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
     for (int l = 1; l < P.lc; ++l) {
         DevLevelT<T> &lv = P.lev[l];
         T *a = lv.xa, *b = lv.xb;
-        launch_csr_jacobi_first(s, lv.A.view(), (const T *)lv.wdinv, (const T *)lv.b, a, st);
-        for (int k = 1; k < pre; ++k) {
+        int k = 1;
+        if (pre >= 2) {
+            launch_csrv_presmooth2(s, lv.A.view(), lv.A.lanes, (const T *)lv.wdinv, (const T *)lv.b, a, st);
+            k = 2;
+        } else {
+            launch_csr_jacobi_first(s, lv.A.view(), (const T *)lv.wdinv, (const T *)lv.b, a, st);
+        }
+        for (; k < pre; ++k) {
             launch_csrv_jacobi(s, lv.A.view(), lv.A.lanes, (const T *)lv.wdinv, (const T *)lv.b,
                                (const T *)a, b, st);
             std::swap(a, b);
@@ -278,8 +284,11 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
         DevLevelT<T> &lv = P.lev[l];
         T *a = cur[l];
         T *b = (a == lv.xa) ? lv.xb : lv.xa;
-        launch_csrv_spmv(s, lv.P.view(), lv.P.lanes, (const T *)cur[l + 1], a, true, st);
-        for (int k = 0; k < post; ++k) {
+        // coarse-grid correction fused into the first post-sweep
+        launch_csrv_prolong_jacobi(s, lv.A.view(), lv.A.lanes, (const T *)lv.wdinv, (const T *)lv.b,
+                                   (const T *)a, lv.P.view(), (const T *)cur[l + 1], b, st);
+        std::swap(a, b);
+        for (int k = 1; k < post; ++k) {
             launch_csrv_jacobi(s, lv.A.view(), lv.A.lanes, (const T *)lv.wdinv, (const T *)lv.b,
                                (const T *)a, b, st);
             std::swap(a, b);
@@ -290,8 +299,17 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
         DevLevelT<T> &l0 = P.lev[0];
         T *a = cur[0];
         T *b = (a == l0.xa) ? l0.xb : l0.xa;
-        launch_csrv_spmv(s, l0.P.view(), l0.P.lanes, (const T *)cur[1], a, true, st);
-        for (int k = 0; k < post - 1; ++k) {
+        int k = 0;
+        if (post >= 2) {
+            // coarse-grid correction fused into the first post-sweep
+            launch_k0_prolong_jacobi(s, K, (const T *)l0.wdinv, r, (const T *)a, l0.P.view(),
+                                     (const T *)cur[1], b, st);
+            std::swap(a, b);
+            k = 1;
+        } else {
+            launch_csrv_spmv(s, l0.P.view(), l0.P.lanes, (const T *)cur[1], a, true, st);
+        }
+        for (; k < post - 1; ++k) {
             launch_k0_jacobi(s, K, l0.omega, r, (const T *)a, b, st);
             std::swap(a, b);
         }

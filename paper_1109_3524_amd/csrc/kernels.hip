@@ -1089,6 +1089,77 @@ __global__ __launch_bounds__(kBlock) void k_csrv_spmv(CSRT<T> A, const T *__rest
     if (lane == 0) y[row] = add ? y[row] + v : v;
 }
 
+// the first two damped-Jacobi sweeps from zero in one pass on a CSR level:
+// x = y + W (b - A y) with y = W b formed at every column
+template <class T, int L>
+__global__ __launch_bounds__(kBlock) void k_csrv_presmooth2(CSRT<T> A, const T *__restrict__ wdinv,
+                                                            const T *__restrict__ b,
+                                                            T *__restrict__ x,
+                                                            const SolveStatus *st) {
+    if (st->done) return;
+    const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    if (row >= A.nrows) return;
+    T ay = T(0);
+    const int e = A.ptr[row + 1];
+    for (int p = A.ptr[row] + lane; p < e; p += L) {
+        const int c = A.col[p];
+        ay += A.val[p] * (wdinv[c] * b[c]);
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) ay += __shfl_xor(ay, off, L);
+    if (lane == 0) {
+        const T w = wdinv[row], bi = b[row];
+        x[row] = w * bi + w * (bi - ay);
+    }
+}
+
+// (x + P xc)_c: the prolongation of the coarse correction added at column c
+template <class T>
+__device__ __forceinline__ T corrected(const T *x, const CSRT<T> &P, const T *xc, int c) {
+    T v = x[c];
+    for (int q = P.ptr[c]; q < P.ptr[c + 1]; ++q) v += P.val[q] * xc[P.col[q]];
+    return v;
+}
+
+// the coarse-grid correction and the first post-smoothing sweep in one pass:
+// xhat = x + P xc formed at every column, xout = xhat + W (b - A xhat)
+template <class T, int L>
+__global__ __launch_bounds__(kBlock) void k_csrv_prolong_jacobi(CSRT<T> A, const T *__restrict__ wdinv,
+                                                                const T *__restrict__ b,
+                                                                const T *__restrict__ x, CSRT<T> P,
+                                                                const T *__restrict__ xc,
+                                                                T *__restrict__ xout,
+                                                                const SolveStatus *st) {
+    if (st->done) return;
+    const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    if (row >= A.nrows) return;
+    T ax = T(0);
+    const int e = A.ptr[row + 1];
+    for (int p = A.ptr[row] + lane; p < e; p += L) ax += A.val[p] * corrected(x, P, xc, A.col[p]);
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) ax += __shfl_xor(ax, off, L);
+    if (lane == 0) {
+        const T xr = corrected(x, P, xc, row);
+        xout[row] = xr + wdinv[row] * (b[row] - ax);
+    }
+}
+
+// level 0: the coarse-grid correction and the first post-sweep in one pass
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_k0_prolong_jacobi(K0T<T> K, const T *__restrict__ wd,
+                                                              const T *__restrict__ b,
+                                                              const T *__restrict__ x, CSRT<T> P,
+                                                              const T *__restrict__ xc,
+                                                              T *__restrict__ xout,
+                                                              const SolveStatus *st) {
+    if (st->done) return;
+    k0_walk<R>(K, [&](int c) { return corrected(x, P, xc, c); }, [&](int row, T ax, T, T xr) {
+        xout[row] = xr + wd[row] * (b[row] - ax);
+    });
+}
+
 // ---------------------------------------------------------------------------
 // the small coarse levels, all in one work-group (barriers instead of launches)
 
@@ -1662,6 +1733,37 @@ static void csrv_dispatch_spmv(hipStream_t s, CSRT<T> A, const T *x, T *y, int a
     default: FN<T, 64>(s, __VA_ARGS__); break;            \
     }
 
+template <class T, int L>
+static void csrv_dispatch_presmooth2(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b, T *x,
+                                     const SolveStatus *st) {
+    int nb = (A.nrows + kBlock / L - 1) / (kBlock / L);
+    LAUNCH((k_csrv_presmooth2<T, L>), nb > 0 ? nb : 1, A, wdinv, b, x, st);
+}
+template <class T, int L>
+static void csrv_dispatch_prolong_jacobi(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b,
+                                         const T *x, CSRT<T> P, const T *xc, T *xout,
+                                         const SolveStatus *st) {
+    int nb = (A.nrows + kBlock / L - 1) / (kBlock / L);
+    LAUNCH((k_csrv_prolong_jacobi<T, L>), nb > 0 ? nb : 1, A, wdinv, b, x, P, xc, xout, st);
+}
+template <class T>
+void launch_csrv_presmooth2(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b, T *x,
+                            const SolveStatus *st) {
+    CSRV_SWITCH(csrv_dispatch_presmooth2, A, wdinv, b, x, st)
+}
+template <class T>
+void launch_csrv_prolong_jacobi(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b,
+                                const T *x, CSRT<T> P, const T *xc, T *xout, const SolveStatus *st) {
+    if (P.nrows != A.nrows) throw std::runtime_error("prolong-sweep: shape mismatch");
+    CSRV_SWITCH(csrv_dispatch_prolong_jacobi, A, wdinv, b, x, P, xc, xout, st)
+}
+template <class T>
+void launch_k0_prolong_jacobi(hipStream_t s, const K0T<T> &K, const T *wd, const T *b, const T *x,
+                              CSRT<T> P, const T *xc, T *xout, const SolveStatus *st) {
+    if (P.nrows != K.n) throw std::runtime_error("prolong-sweep: shape mismatch");
+    WALK_SWITCH(pick_R(K), LAUNCH2((k_k0_prolong_jacobi<RR, T>), op_grid<RR>(K), K, wd, b, x, P, xc, xout, st))
+}
+
 template <class T>
 void launch_csrv_jacobi(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b,
                         const T *xin, T *xout, const SolveStatus *st) {
@@ -1846,6 +1948,18 @@ INST_V(float)
     template void launch_fcg_beta<T>(hipStream_t, int, const T *, const T *, SolveStatus *, double *);
 INST_F(double)
 INST_F(float)
+
+#define INST_P(T)                                                                                \
+    template void launch_csrv_presmooth2<T>(hipStream_t, CSRT<T>, int, const T *, const T *, T *, \
+                                            const SolveStatus *);                                 \
+    template void launch_csrv_prolong_jacobi<T>(hipStream_t, CSRT<T>, int, const T *, const T *,  \
+                                                const T *, CSRT<T>, const T *, T *,               \
+                                                const SolveStatus *);                             \
+    template void launch_k0_prolong_jacobi<T>(hipStream_t, const K0T<T> &, const T *, const T *,  \
+                                              const T *, CSRT<T>, const T *, T *,                 \
+                                              const SolveStatus *);
+INST_P(double)
+INST_P(float)
 
 #define INST_M(T)                                                                                \
     template void launch_fcg_betas<T>(hipStream_t, int, const T *, FcgVecs<T>, int, FcgSlots,   \

@@ -11,9 +11,10 @@ Recipe (all seeded):
      lambda is replayed with ibpm_harvest, which stores before each iteration
      the residual left by one V-cycle, r1 = r - K V(r), and the error that
      remains, e1 = x* - x - V(r).  Every k-th pair is kept.
-  3. The network is trained on these pairs with Adam (ibpm_nn_train), the
-     pairs shuffled by a seeded generator each epoch, the learning rate
-     halved at fixed epochs.
+  3. The network is trained on these pairs with Adam (ibpm_nn_train) on the
+     energy-norm loss (the share of the error that the optimally scaled
+     correction removes), the pairs shuffled by a seeded generator each
+     epoch, the learning rate halved at fixed epochs.
 
 The weights are written as a float32 .npy file of IBPM_NN_PARAMS values and
 a JSON record of the recipe, pair counts and losses.
@@ -99,10 +100,10 @@ def main(argv=None):
     ap.add_argument("--out", required=True, help="weights file (.npy)")
     ap.add_argument("--seed", type=int, default=2024)
     ap.add_argument("--angles", type=int, default=6, help="number of inflow angles")
-    ap.add_argument("--steps-at", default="1,4,12,30", help="time steps at which to harvest")
-    ap.add_argument("--npairs", type=int, default=240)
-    ap.add_argument("--keep-every", type=int, default=6)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--steps-at", default="2,6,15,30", help="time steps at which to harvest")
+    ap.add_argument("--npairs", type=int, default=500)
+    ap.add_argument("--keep-every", type=int, default=10)
+    ap.add_argument("--epochs", type=int, default=60)
     ap.add_argument("--batch", type=int, default=8)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--init-seed", type=int, default=1)
