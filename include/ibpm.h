@@ -87,6 +87,9 @@ typedef struct ibpm_params {
                                     others; 0 or 1 = every application */
     int32_t fcg_depth;           /* solvers 3, 4: directions kept by the truncated flexible
                                     CG, FCG(m); 0 selects 4, at most 8 */
+    int32_t use_graphs;          /* 1: replay the launches of CG iterations as HIP graphs
+                                    (recorded once per solve kind and operand set on a
+                                    stream of the context's own); 0: launch them one by one */
 } ibpm_params;
 
 typedef struct ibpm_solve_stats {

@@ -191,8 +191,19 @@ struct ibpm_ctx {
         HIPCHECK(hipMemcpyAsync(host_st, st, sizeof(SolveStatus), hipMemcpyDeviceToHost, stream));
         HIPCHECK(hipStreamSynchronize(stream));
     }
+    // HIP graphs of two PCG iterations, one per solve kind (velocity,
+    // Poisson FP64, inner FP32), with the operand addresses they were made for
+    struct IterGraph {
+        hipGraphExec_t exec = nullptr;
+        std::vector<const void *> key;
+    };
+    IterGraph graphs[3];
+    hipStream_t cap_stream = nullptr;  // used only to record the graphs
     ~ibpm_ctx() {
         if (stream) (void)hipStreamSynchronize(stream);
+        for (IterGraph &g : graphs)
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
         for (void *p : allocs) (void)hipFree(p);
         if (host_st) (void)hipHostFree(host_st);
     }
@@ -284,11 +295,8 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
         DevLevelT<T> &lv = P.lev[l];
         T *a = cur[l];
         T *b = (a == lv.xa) ? lv.xb : lv.xa;
-        // coarse-grid correction fused into the first post-sweep
-        launch_csrv_prolong_jacobi(s, lv.A.view(), lv.A.lanes, (const T *)lv.wdinv, (const T *)lv.b,
-                                   (const T *)a, lv.P.view(), (const T *)cur[l + 1], b, st);
-        std::swap(a, b);
-        for (int k = 1; k < post; ++k) {
+        launch_csrv_spmv(s, lv.P.view(), lv.P.lanes, (const T *)cur[l + 1], a, true, st);
+        for (int k = 0; k < post; ++k) {
             launch_csrv_jacobi(s, lv.A.view(), lv.A.lanes, (const T *)lv.wdinv, (const T *)lv.b,
                                (const T *)a, b, st);
             std::swap(a, b);
@@ -299,17 +307,8 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
         DevLevelT<T> &l0 = P.lev[0];
         T *a = cur[0];
         T *b = (a == l0.xa) ? l0.xb : l0.xa;
-        int k = 0;
-        if (post >= 2) {
-            // coarse-grid correction fused into the first post-sweep
-            launch_k0_prolong_jacobi(s, K, (const T *)l0.wdinv, r, (const T *)a, l0.P.view(),
-                                     (const T *)cur[1], b, st);
-            std::swap(a, b);
-            k = 1;
-        } else {
-            launch_csrv_spmv(s, l0.P.view(), l0.P.lanes, (const T *)cur[1], a, true, st);
-        }
-        for (; k < post - 1; ++k) {
+        launch_csrv_spmv(s, l0.P.view(), l0.P.lanes, (const T *)cur[1], a, true, st);
+        for (int k = 0; k < post - 1; ++k) {
             launch_k0_jacobi(s, K, l0.omega, r, (const T *)a, b, st);
             std::swap(a, b);
         }
@@ -327,27 +326,78 @@ template <class Op, class T>
 int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
               const std::function<void(const T *, T *)> &precond, const T *b, T *x, T *r, T *z,
               T **p, T *q, SolveStatus *st, double rtol, int maxit, int &est, bool zero_guess,
-              bool true_residual, ibpm_solve_stats *out) {
+              bool true_residual, ibpm_solve_stats *out, int graph_slot = -1) {
     hipStream_t s = c->stream;
     auto t0 = std::chrono::steady_clock::now();
     if (zero_guess) launch_pcg_init_zero(s, n, b, x, r, st, c->parts, rtol * rtol, maxit);
     else launch_pcg_init(s, op, b, (const T *)x, r, z, st, c->parts, jacobi, rtol * rtol, maxit);
     if (!jacobi) precond(r, z);
     int curp = 0;
+    auto iteration = [&]() {
+        // with the V-cycle the product sums its r . z partials (in parts)
+        launch_pcg_spmv(s, op, (const T *)z, (const T *)p[curp], p[1 - curp], q, st,
+                        jacobi ? (const double *)nullptr : (const double *)c->parts, c->rz_G,
+                        c->parts2);
+        curp = 1 - curp;
+        launch_pcg_update(s, op, x, r, z, (const T *)p[curp], (const T *)q, st,
+                          (const double *)c->parts2, c->parts, jacobi, !jacobi);
+        if (!jacobi) precond(r, z);
+    };
+    // the iterations are identical launches (the two direction buffers swap
+    // every iteration), so a graph of two of them is replayed
+    hipGraphExec_t gexec = nullptr;
+    if (c->prm.use_graphs && graph_slot >= 0) {
+        ibpm_ctx::IterGraph &G = c->graphs[graph_slot];
+        std::vector<const void *> key = {&op, b, x, r, z, p[0], p[1], q, st,
+                                         (const void *)(intptr_t)jacobi,
+                                         (const void *)(intptr_t)c->rz_G};
+        if (!G.exec || G.key != key) {
+            if (G.exec) (void)hipGraphExecDestroy(G.exec);
+            G.exec = nullptr;
+            // capture on the context's own capture stream (the caller's
+            // stream may be the legacy default stream, which cannot be
+            // captured); the graph is then launched on the caller's stream
+            if (!c->cap_stream) HIPCHECK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+            hipGraph_t graph = nullptr;
+            HIPCHECK(hipStreamSynchronize(s));
+            const hipStream_t user = c->stream;
+            c->stream = c->cap_stream;
+            s = c->cap_stream;
+            HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            try {
+                iteration();
+                iteration();
+            } catch (...) {
+                (void)hipStreamEndCapture(s, &graph);
+                if (graph) (void)hipGraphDestroy(graph);
+                c->stream = user;
+                s = user;
+                throw;
+            }
+            hipError_t ec = hipStreamEndCapture(s, &graph);
+            c->stream = user;
+            s = user;
+            if (ec != hipSuccess) throw HipError(std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+            hipError_t e = hipGraphInstantiate(&G.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                G.exec = nullptr;
+                throw HipError(std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+            }
+            G.key = key;
+        }
+        gexec = G.exec;
+    }
     int chunk = std::max(1, (int)(0.8 * est));
     int queued = 0;
     double last_rr = -1;
     int last_it = 0;
     for (;;) {
-        for (int k = 0; k < chunk; ++k) {
-            // with the V-cycle the product sums its r . z partials (in parts)
-            launch_pcg_spmv(s, op, (const T *)z, (const T *)p[curp], p[1 - curp], q, st,
-                            jacobi ? (const double *)nullptr : (const double *)c->parts, c->rz_G,
-                            c->parts2);
-            curp = 1 - curp;
-            launch_pcg_update(s, op, x, r, z, (const T *)p[curp], (const T *)q, st,
-                              (const double *)c->parts2, c->parts, jacobi, !jacobi);
-            if (!jacobi) precond(r, z);
+        if (gexec) {
+            chunk += chunk & 1;
+            for (int k = 0; k < chunk; k += 2) HIPCHECK(hipGraphLaunch(gexec, s));
+        } else {
+            for (int k = 0; k < chunk; ++k) iteration();
         }
         queued += chunk;
         c->read_status(st);
@@ -403,7 +453,7 @@ int solve_poisson_fp64(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_s
     };
     return pcg_drive<K0View, double>(c, P.K0, P.K0.n, jacobi, pre, rhs, lam, P.r, P.z, P.p, P.q,
                                      c->st_poi, c->prm.poisson_rtol, c->prm.poisson_maxit,
-                                     c->est_poi, false, true, out);
+                                     c->est_poi, false, true, out, 1);
 }
 
 // Mixed precision: FP64 iterative refinement around an FP32 AMG-PCG.  The
@@ -472,7 +522,7 @@ int solve_poisson_mixed(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_
             ibpm_solve_stats is{};
             int rc = pcg_drive<K0T<float>, float>(c, P.K0, n, false, pre, c->rin32, c->d32, P.r,
                                                   P.z, P.p, P.q, c->st_poi, tol_in, maxit_in,
-                                                  c->est_inner[std::min(outer, 31)], true, false, &is);
+                                                  c->est_inner[std::min(outer, 31)], true, false, &is, 2);
             inner_total += is.iters;
             if (rc == IBPM_ENAN) {
                 code = IBPM_ENAN;
@@ -915,7 +965,7 @@ int solve_velocity_impl(ibpm_ctx *c, const double *rhs, double *q, ibpm_solve_st
     std::function<void(const double *, double *)> none;
     return pcg_drive<AView, double>(c, c->A, c->g.n_q, true, none, rhs, q, c->vr, c->vz, c->vp,
                                     c->vq, c->st_vel, c->prm.vel_rtol, c->prm.vel_maxit, c->est_vel,
-                                    false, true, out);
+                                    false, true, out, 0);
 }
 
 void stage_walls(ibpm_ctx *c, const double *q) {

@@ -118,18 +118,10 @@ void launch_pcg_init(hipStream_t s, const Op &op, const T *b, const T *x, T *r, 
 template <class T>
 void launch_pcg_init_zero(hipStream_t s, int n, const T *b, T *x, T *r, SolveStatus *st,
                           double *parts, double rtol2, int maxit);
-// fused V-cycle passes: the first two pre-sweeps from zero on a CSR level;
-// the coarse-grid correction x + P xc with the first post-sweep (CSR level
-// and level 0), written to xout (x is not changed)
+// the first two damped-Jacobi sweeps from zero on a CSR level in one pass
 template <class T>
 void launch_csrv_presmooth2(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b, T *x,
                             const SolveStatus *st);
-template <class T>
-void launch_csrv_prolong_jacobi(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b,
-                                const T *x, CSRT<T> P, const T *xc, T *xout, const SolveStatus *st);
-template <class T>
-void launch_k0_prolong_jacobi(hipStream_t s, const K0T<T> &K, const T *wd, const T *b, const T *x,
-                              CSRT<T> P, const T *xc, T *xout, const SolveStatus *st);
 
 // number of blocks (and of partials) of a level-0 stencil kernel
 int walk_blocks_of(const K0View &K);

@@ -95,6 +95,28 @@ __device__ __forceinline__ void block_sum(double (&v)[N]) {
     __syncthreads();
 }
 
+// acc[k] += the partials parts[k * kMaxParts + b], b = threadIdx.x, + kBlock, ...
+// (b < G), for k < n, in increasing b; the loads of up to 8 rounds are issued
+// before they are added (the partials come from other XCDs, so each round
+// would otherwise wait a memory latency)
+template <int N>
+__device__ __forceinline__ void gather_parts(const double *parts, int G, int n, double (&acc)[N]) {
+    constexpr int U = 8;
+    for (int b0 = 0; b0 < G; b0 += U * kBlock) {
+        double v[N][U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u * kBlock + threadIdx.x;
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k][u] = (b < G && k < n) ? parts[k * kMaxParts + b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int k = 0; k < N; ++k) acc[k] += v[k][u];
+    }
+}
+
 // Per-block partial sums of N values: block tree in LDS (fixed order), then
 // one store per value.  The grid-wide sums are formed by k_finalize, a
 // one-block kernel queued right after, which adds the partials in block
@@ -500,7 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv(Op op, const T *__restrict_
         // partials (every block sums them in the same order); st->rz and
         // st->first are only read here, the new value goes to st->rz_next
         double a[1] = {0.0};
-        for (int b = threadIdx.x; b < G_rz; b += kBlock) a[0] += rz_parts[b];
+        gather_parts<1>(rz_parts, G_rz, 1, a);
         block_sum<1>(a);
         const double bt = st->first ? 0.0 : a[0] / st->rz;
         beta = (T)bt;
@@ -552,7 +574,7 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *__restrict__ x,
     double pq;
     if (pq_parts) {
         double a[1] = {0.0};
-        for (int b = threadIdx.x; b < G_pq; b += kBlock) a[0] += pq_parts[b];
+        gather_parts<1>(pq_parts, G_pq, 1, a);
         block_sum<1>(a);
         pq = a[0];
         if (blockIdx.x == 0 && threadIdx.x == 0) st->pq = pq;
@@ -719,8 +741,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const doub
                       ? 2
                       : 1;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int b = threadIdx.x; b < G; b += kBlock)
-        for (int k = 0; k < N; ++k) acc[k] += parts[k * kMaxParts + b];
+    gather_parts<3>(parts, G, N, acc);
     block_sum<3>(acc);
     if (threadIdx.x != 0) return;
     switch (kind) {
@@ -859,10 +880,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_betas_finalize(int G, int cnt, F
     double acc[kFcgMax];
 #pragma unroll
     for (int j = 0; j < kFcgMax; ++j) acc[j] = 0.0;
-    for (int b = threadIdx.x; b < G; b += kBlock)
-#pragma unroll
-        for (int j = 0; j < kFcgMax; ++j)
-            if (j < cnt) acc[j] += parts[j * kMaxParts + b];
+    gather_parts<kFcgMax>(parts, G, cnt, acc);
     block_sum<kFcgMax>(acc);
     if (threadIdx.x == 0)
         for (int j = 0; j < cnt; ++j) {
@@ -904,8 +922,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_pq_finalize(int G, const double 
                                                             FcgRing *ring, SolveStatus *st) {
     if (st->done) return;
     double acc[2] = {0.0, 0.0};
-    for (int b = threadIdx.x; b < G; b += kBlock)
-        for (int k = 0; k < 2; ++k) acc[k] += parts[k * kMaxParts + b];
+    gather_parts<2>(parts, G, 2, acc);
     block_sum<2>(acc);
     if (threadIdx.x == 0) {
         st->pq = acc[0];
@@ -1112,52 +1129,6 @@ __global__ __launch_bounds__(kBlock) void k_csrv_presmooth2(CSRT<T> A, const T *
         const T w = wdinv[row], bi = b[row];
         x[row] = w * bi + w * (bi - ay);
     }
-}
-
-// (x + P xc)_c: the prolongation of the coarse correction added at column c
-template <class T>
-__device__ __forceinline__ T corrected(const T *x, const CSRT<T> &P, const T *xc, int c) {
-    T v = x[c];
-    for (int q = P.ptr[c]; q < P.ptr[c + 1]; ++q) v += P.val[q] * xc[P.col[q]];
-    return v;
-}
-
-// the coarse-grid correction and the first post-smoothing sweep in one pass:
-// xhat = x + P xc formed at every column, xout = xhat + W (b - A xhat)
-template <class T, int L>
-__global__ __launch_bounds__(kBlock) void k_csrv_prolong_jacobi(CSRT<T> A, const T *__restrict__ wdinv,
-                                                                const T *__restrict__ b,
-                                                                const T *__restrict__ x, CSRT<T> P,
-                                                                const T *__restrict__ xc,
-                                                                T *__restrict__ xout,
-                                                                const SolveStatus *st) {
-    if (st->done) return;
-    const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
-    const int lane = threadIdx.x % L;
-    if (row >= A.nrows) return;
-    T ax = T(0);
-    const int e = A.ptr[row + 1];
-    for (int p = A.ptr[row] + lane; p < e; p += L) ax += A.val[p] * corrected(x, P, xc, A.col[p]);
-#pragma unroll
-    for (int off = L / 2; off > 0; off >>= 1) ax += __shfl_xor(ax, off, L);
-    if (lane == 0) {
-        const T xr = corrected(x, P, xc, row);
-        xout[row] = xr + wdinv[row] * (b[row] - ax);
-    }
-}
-
-// level 0: the coarse-grid correction and the first post-sweep in one pass
-template <int R, class T>
-__global__ __launch_bounds__(kBlock) void k_k0_prolong_jacobi(K0T<T> K, const T *__restrict__ wd,
-                                                              const T *__restrict__ b,
-                                                              const T *__restrict__ x, CSRT<T> P,
-                                                              const T *__restrict__ xc,
-                                                              T *__restrict__ xout,
-                                                              const SolveStatus *st) {
-    if (st->done) return;
-    k0_walk<R>(K, [&](int c) { return corrected(x, P, xc, c); }, [&](int row, T ax, T, T xr) {
-        xout[row] = xr + wd[row] * (b[row] - ax);
-    });
 }
 
 // ---------------------------------------------------------------------------
@@ -1570,7 +1541,7 @@ int walk_blocks_of(const K0View &K) { return walk_grid_blocks(K); }
 
 // above this many partials a sum read by every block of the consumer costs
 // more than a one-block finalize launch
-constexpr int kFuseMaxParts = 1024;
+constexpr int kFuseMaxParts = 2048;
 
 template <class Op, class T>
 void launch_pcg_spmv(hipStream_t s, const Op &op, const T *z, const T *pold, T *pnew, T *q,
@@ -1739,31 +1710,11 @@ static void csrv_dispatch_presmooth2(hipStream_t s, CSRT<T> A, const T *wdinv, c
     int nb = (A.nrows + kBlock / L - 1) / (kBlock / L);
     LAUNCH((k_csrv_presmooth2<T, L>), nb > 0 ? nb : 1, A, wdinv, b, x, st);
 }
-template <class T, int L>
-static void csrv_dispatch_prolong_jacobi(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b,
-                                         const T *x, CSRT<T> P, const T *xc, T *xout,
-                                         const SolveStatus *st) {
-    int nb = (A.nrows + kBlock / L - 1) / (kBlock / L);
-    LAUNCH((k_csrv_prolong_jacobi<T, L>), nb > 0 ? nb : 1, A, wdinv, b, x, P, xc, xout, st);
-}
 template <class T>
 void launch_csrv_presmooth2(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b, T *x,
                             const SolveStatus *st) {
     CSRV_SWITCH(csrv_dispatch_presmooth2, A, wdinv, b, x, st)
 }
-template <class T>
-void launch_csrv_prolong_jacobi(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b,
-                                const T *x, CSRT<T> P, const T *xc, T *xout, const SolveStatus *st) {
-    if (P.nrows != A.nrows) throw std::runtime_error("prolong-sweep: shape mismatch");
-    CSRV_SWITCH(csrv_dispatch_prolong_jacobi, A, wdinv, b, x, P, xc, xout, st)
-}
-template <class T>
-void launch_k0_prolong_jacobi(hipStream_t s, const K0T<T> &K, const T *wd, const T *b, const T *x,
-                              CSRT<T> P, const T *xc, T *xout, const SolveStatus *st) {
-    if (P.nrows != K.n) throw std::runtime_error("prolong-sweep: shape mismatch");
-    WALK_SWITCH(pick_R(K), LAUNCH2((k_k0_prolong_jacobi<RR, T>), op_grid<RR>(K), K, wd, b, x, P, xc, xout, st))
-}
-
 template <class T>
 void launch_csrv_jacobi(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b,
                         const T *xin, T *xout, const SolveStatus *st) {
@@ -1951,13 +1902,8 @@ INST_F(float)
 
 #define INST_P(T)                                                                                \
     template void launch_csrv_presmooth2<T>(hipStream_t, CSRT<T>, int, const T *, const T *, T *, \
-                                            const SolveStatus *);                                 \
-    template void launch_csrv_prolong_jacobi<T>(hipStream_t, CSRT<T>, int, const T *, const T *,  \
-                                                const T *, CSRT<T>, const T *, T *,               \
-                                                const SolveStatus *);                             \
-    template void launch_k0_prolong_jacobi<T>(hipStream_t, const K0T<T> &, const T *, const T *,  \
-                                              const T *, CSRT<T>, const T *, T *,                 \
-                                              const SolveStatus *);
+                                            const SolveStatus *);
+
 INST_P(double)
 INST_P(float)
 

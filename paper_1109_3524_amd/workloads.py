@@ -181,12 +181,13 @@ def cylinder_512(steps: int = 200) -> Workload:
 def cylinder_1024(steps: int = 500) -> Workload:
     """1024^2 Re 100 workload used for the mixed-precision comparison."""
     return cylinder_stretched(1024, 0.01, 314, 100.0, 0.0025, steps,
-                              solver=SOLVER_AMG_PCG_MIXED)
+                              solver=SOLVER_AMG_PCG_MIXED).replace(poisson_maxit=20000)
 
 
 def cylinder_2048(steps: int = 2000) -> Workload:
-    """2048^2 (4.2M cells) Re 100 workload."""
-    return cylinder_stretched(2048, 0.005, 628, 100.0, 0.002, steps)
+    """2048^2 (4.2M cells) Re 100 workload (the Poisson solve needs a few
+    thousand AMG-PCG iterations on this grid)."""
+    return cylinder_stretched(2048, 0.005, 628, 100.0, 0.002, steps).replace(poisson_maxit=20000)
 
 
 def cylinder_512_re100(steps: int = 200) -> Workload:

@@ -415,3 +415,29 @@ def test_mixed_precision_trajectory_velocity_and_drag():
     print(f"  96^2 mixed x 10 steps: velocity err {eu:.2e}, Cd err {ecd:.2e}")
     assert eu < 1e-7 and ecd < 1e-6
     ctx.close()
+
+
+def test_graph_replay_matches_eager_launches():
+    """CG iterations replayed as HIP graphs give bitwise the results of the
+    same launches made one by one, over repeated solves (the graph is reused)
+    with eager work in between, for the velocity, Poisson FP64 and inner FP32
+    solves."""
+    wl = W.cylinder_small(96, 60).replace(poisson_solver=1)
+    out = {}
+    for graphs in (0, 1):
+        for solver in (1, 2):
+            ctx = ibpm.Context(wl, poisson_solver=solver, use_graphs=graphs)
+            q, conv, lam = ctx.init_state()
+            stats = []
+            for _ in range(3):
+                stats.append(ctx.step(q, conv, lam, 1))
+                _ = ctx.apply_K(lam)          # eager work between the replays
+            out[(graphs, solver)] = (_n(q).copy(), _n(lam).copy(),
+                                     [s["poisson_iters"] for s in stats])
+            ctx.close()
+    for solver in (1, 2):
+        a, b = out[(0, solver)], out[(1, solver)]
+        print(f"  solver {solver}: iterations eager {a[2]} graph {b[2]}")
+        assert a[2] == b[2]
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
