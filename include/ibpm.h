@@ -58,6 +58,8 @@ extern "C" {
 #define IBPM_SOLVER_AMG_FCG_LEARNED  3   /* flexible CG, AMG V-cycle plus a learned stage */
 #define IBPM_SOLVER_AMG_FCG_MIXED_LEARNED 4  /* FP32 inner flexible CG with the learned stage
                                                 inside FP64 iterative refinement */
+#define IBPM_SOLVER_AMG_PCG_FP32_CYCLE 5     /* FP64 CG whose V-cycle runs in FP32 (the
+                                                residual rounded to FP32 on entry) */
 
 typedef struct ibpm_ctx ibpm_ctx;
 

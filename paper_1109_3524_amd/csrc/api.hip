@@ -62,6 +62,8 @@ struct DevLevelT {
     DevCSRT<T> A, P, R;
     T *wdinv = nullptr;
     T *b = nullptr, *xa = nullptr, *xb = nullptr, *r = nullptr;
+    int32_t *agg = nullptr;            // level 0: aggregates (matrix-free prolongation)
+    double pomega = 0;                 // level 0: prolongator smoothing weight
 };
 
 // Everything one precision needs for the Poisson solve
@@ -108,7 +110,7 @@ struct ibpm_ctx {
     ibpm_params prm{};
     Model m;
     Hierarchy h;
-    bool amg = false, mixed = false;
+    bool amg = false, mixed = false, mixed_precond = false;
     std::vector<void *> allocs;
     GridView g{};
     AView A{};
@@ -307,7 +309,7 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
         DevLevelT<T> &l0 = P.lev[0];
         T *a = cur[0];
         T *b = (a == l0.xa) ? l0.xb : l0.xa;
-        launch_csrv_spmv(s, l0.P.view(), l0.P.lanes, (const T *)cur[1], a, true, st);
+        launch_k0_prolong_mf(s, K, (const int *)l0.agg, (const T *)cur[1], l0.pomega, a, st);
         for (int k = 0; k < post - 1; ++k) {
             launch_k0_jacobi(s, K, l0.omega, r, (const T *)a, b, st);
             std::swap(a, b);
@@ -955,7 +957,25 @@ int solve_poisson_learned(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solv
     return code;
 }
 
+// FP64 CG (product, update, dot products and the iterate in FP64) with the
+// V-cycle in FP32: r is rounded to FP32, the FP32 cycle gives z32, and z is
+// its FP64 value, so the preconditioner is a fixed linear map
+int solve_poisson_mixed_precond(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
+    PrecSet<double> &P = c->p64;
+    const int n = P.K0.n;
+    std::function<void(const double *, double *)> pre = [c, n](const double *r, double *z) {
+        hipStream_t s = c->stream;
+        launch_to_f32(s, n, r, c->rin32, c->st_poi);
+        enqueue_vcycle(c, c->p32, (const float *)c->rin32, c->d32, c->st_poi, false);
+        c->rz_G = launch_widen_dot(s, n, (const float *)c->d32, z, r, c->st_poi, c->parts);
+    };
+    return pcg_drive<K0View, double>(c, P.K0, n, false, pre, rhs, lam, P.r, P.z, P.p, P.q,
+                                     c->st_poi, c->prm.poisson_rtol, c->prm.poisson_maxit,
+                                     c->est_poi, false, true, out, 1);
+}
+
 int solve_poisson_impl(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
+    if (c->mixed_precond) return solve_poisson_mixed_precond(c, rhs, lam, out);
     if (c->mixed) return solve_poisson_mixed(c, rhs, lam, out);
     if (c->learned) return solve_poisson_learned(c, rhs, lam, out);
     return solve_poisson_fp64(c, rhs, lam, out);
@@ -997,7 +1017,7 @@ void check_params(const ibpm_params *p) {
     if (p->bn_order != 1) throw InvalidArg("only B^N with N = 1 is supported");
     if (!(p->vel_rtol > 0) || !(p->poisson_rtol > 0)) throw InvalidArg("tolerances must be > 0");
     if (p->vel_maxit < 1 || p->poisson_maxit < 1) throw InvalidArg("maxit must be >= 1");
-    if (p->poisson_solver < IBPM_SOLVER_JACOBI_PCG || p->poisson_solver > IBPM_SOLVER_AMG_FCG_MIXED_LEARNED)
+    if (p->poisson_solver < IBPM_SOLVER_JACOBI_PCG || p->poisson_solver > IBPM_SOLVER_AMG_PCG_FP32_CYCLE)
         throw InvalidArg("unknown Poisson solver");
     if (!(p->inner_rtol >= 0) || p->inner_rtol >= 1) throw InvalidArg("inner_rtol must be in [0, 1)");
     if (p->learned_every < 0) throw InvalidArg("learned_every must be >= 0");
@@ -1067,12 +1087,18 @@ void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
             dl.b = c->dalloc<T>(dl.n);
         } else {
             // level 0 is matrix-free; its smoother weights omega / k_ii are
-            // formed on the device from the same stencil
+            // formed on the device from the same stencil, and its prolongator
+            // is applied from the aggregates and the stencil
             dl.wdinv = c->dalloc<T>(dl.n);
             launch_k0_wdinv(c->stream, P.K0, hl.omega, dl.wdinv);
+            if (L > 1) {
+                dl.agg = c->upload(hl.agg);
+                dl.pomega = hl.pomega;
+            }
         }
         if (l < L - 1) {
-            dl.P = c->upload_csr<T>(hl.P);
+            // level 0 applies its prolongator matrix-free (aggregates + stencil)
+            if (l > 0) dl.P = c->upload_csr<T>(hl.P);
             dl.R = c->upload_csr<T>(hl.R);
             dl.r = c->dalloc<T>(dl.n);
         }
@@ -1118,7 +1144,9 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     }
     c->amg = p->poisson_solver != IBPM_SOLVER_JACOBI_PCG;
     c->mixed = p->poisson_solver == IBPM_SOLVER_AMG_PCG_MIXED ||
-               p->poisson_solver == IBPM_SOLVER_AMG_FCG_MIXED_LEARNED;
+               p->poisson_solver == IBPM_SOLVER_AMG_FCG_MIXED_LEARNED ||
+               p->poisson_solver == IBPM_SOLVER_AMG_PCG_FP32_CYCLE;
+    c->mixed_precond = p->poisson_solver == IBPM_SOLVER_AMG_PCG_FP32_CYCLE;
     c->learned = p->poisson_solver == IBPM_SOLVER_AMG_FCG_LEARNED ||
                  p->poisson_solver == IBPM_SOLVER_AMG_FCG_MIXED_LEARNED;
     if (c->amg) {
@@ -1503,12 +1531,13 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
         }
         case IBPM_KERNEL_PROLONG0: {
             const DevLevelT<double> &l0 = P.lev[0];
-            const CSRView P0 = l0.P.view();
-            const int lanes = l0.P.lanes;
+            const int *agg = l0.agg;
+            const double w = l0.pomega;
             const double *x1 = P.lev[1].xa;
             double *x0 = l0.xa;
-            launch = [=] { launch_csrv_spmv(s, P0, lanes, x1, x0, true, sb); };
-            by = csr_bytes(l0.P, true);
+            launch = [=] { launch_k0_prolong_mf(s, K0, agg, x1, w, x0, sb); };
+            // aggregates, x read and written, the coarse vector, coupling and metrics
+            by = 4.0 * n + 16.0 * n + 8.0 * P.lev[1].n + b_coupling + b_metric;
             break;
         }
         case IBPM_KERNEL_PCG_UPDATE_K: {

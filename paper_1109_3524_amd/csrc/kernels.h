@@ -151,6 +151,11 @@ template <class T>
 void launch_zero_if_zero_rhs(hipStream_t s, T *x, int n, const SolveStatus *st);
 
 // V-cycle pieces, predicated on st->done
+// x += P x1 on level 0 with the smoothed prolongator applied matrix-free:
+// P = (I - w D^-1 K) T, T the aggregates (agg[i] = aggregate of unknown i)
+template <class T>
+void launch_k0_prolong_mf(hipStream_t s, const K0T<T> &K, const int *agg, const T *x1, double w,
+                          T *x, const SolveStatus *st);
 // wd = omega / diag(K0)
 template <class T>
 void launch_k0_wdinv(hipStream_t s, const K0T<T> &K, double omega, T *wd);
@@ -266,5 +271,10 @@ void launch_harvest_e1(hipStream_t s, int n, const double *xstar, const double *
 void launch_outer_residual(hipStream_t s, const K0View &K, const double *b, const double *x,
                            float *r32, SolveStatus *st, double *parts, int first);
 void launch_add_correction(hipStream_t s, int n, double *x, const float *d);
+// FP64 CG with an FP32 V-cycle: y = FP32(x); z = FP64(z32) with the per-block
+// partials of r . z (returns their number)
+void launch_to_f32(hipStream_t s, int n, const double *x, float *y, const SolveStatus *st);
+int launch_widen_dot(hipStream_t s, int n, const float *z32, double *z, const double *r,
+                     const SolveStatus *st, double *parts);
 
 }  // namespace ibpm

@@ -615,6 +615,19 @@ __global__ __launch_bounds__(kBlock) void k_k0_jacobi_first(K0T<T> K, T omega, c
     }
 }
 
+// coarse-grid correction on level 0 without the stored prolongator:
+// x += P x1 with P = (I - w D^-1 K) T, i.e. x += t - w (K t) / d where
+// t = x1[agg] is the piecewise-constant interpolation
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_k0_prolong_mf(K0T<T> K, const int *__restrict__ agg,
+                                                          const T *__restrict__ x1, T w,
+                                                          T *__restrict__ x, const SolveStatus *st) {
+    if (st->done) return;
+    k0_walk<R>(K, [&](int c) { return x1[agg[c]]; }, [&](int row, T kt, T d, T t) {
+        x[row] += t - w * (kt / d);
+    });
+}
+
 // wd = omega / diag(K) on level 0
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_k0_wdinv(K0T<T> K, T omega, T *__restrict__ wd) {
@@ -1169,6 +1182,33 @@ __global__ __launch_bounds__(kBlock) void k_stream_copy(size_t n2, const double2
 // ---------------------------------------------------------------------------
 // mixed precision: x += d
 
+// y = FP32(x) (predicated on the solve's status)
+__global__ __launch_bounds__(kBlock) void k_to_f32(int n, const double *__restrict__ x,
+                                                   float *__restrict__ y, const SolveStatus *st) {
+    if (st->done) return;
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = (float)x[i];
+}
+
+// z = FP64(z32) and per-block partials of r . z
+__global__ __launch_bounds__(kBlock) void k_widen_dot(int n, const float *__restrict__ z32,
+                                                      double *__restrict__ z,
+                                                      const double *__restrict__ r,
+                                                      const SolveStatus *st, double *parts) {
+    if (st->done) return;
+    Tiles Tl = my_tiles(n);
+    double v[1] = {0.0};
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
+        const int i = t * kBlock + threadIdx.x;
+        if (i < n) {
+            const double zi = (double)z32[i];
+            z[i] = zi;
+            v[0] += r[i] * zi;
+        }
+    }
+    write_parts<1>(v, parts);
+}
+
 __global__ __launch_bounds__(kBlock) void k_add_correction(int n, double *x, const float *d) {
     int i = blockIdx.x * kBlock + threadIdx.x;
     if (i < n) x[i] += (double)d[i];
@@ -1600,6 +1640,12 @@ void launch_zero_if_zero_rhs(hipStream_t s, T *x, int n, const SolveStatus *st) 
 }
 
 template <class T>
+void launch_k0_prolong_mf(hipStream_t s, const K0T<T> &K, const int *agg, const T *x1, double w,
+                          T *x, const SolveStatus *st) {
+    WALK_SWITCH(pick_R(K), LAUNCH2((k_k0_prolong_mf<RR, T>), op_grid<RR>(K), K, agg, x1, (T)w, x, st))
+}
+
+template <class T>
 void launch_k0_wdinv(hipStream_t s, const K0T<T> &K, double omega, T *wd) {
     LAUNCH((k_k0_wdinv<T>), (K.n + kBlock - 1) / kBlock, K, (T)omega, wd);
 }
@@ -1827,6 +1873,17 @@ void launch_outer_residual(hipStream_t s, const K0View &K, const double *b, cons
     LAUNCH(k_finalize, 1, (int)FIN_OUTER, G, parts, st, first, 0.0, 0);
 }
 
+void launch_to_f32(hipStream_t s, int n, const double *x, float *y, const SolveStatus *st) {
+    LAUNCH(k_to_f32, (n + kBlock - 1) / kBlock, n, x, y, st);
+}
+
+int launch_widen_dot(hipStream_t s, int n, const float *z32, double *z, const double *r,
+                     const SolveStatus *st, double *parts) {
+    int G = grid_for(n);
+    LAUNCH(k_widen_dot, G, n, z32, z, r, st, parts);
+    return G;
+}
+
 void launch_add_correction(hipStream_t s, int n, double *x, const float *d) {
     LAUNCH(k_add_correction, (n + kBlock - 1) / kBlock, n, x, d);
 }
@@ -1853,6 +1910,8 @@ INST_OP(K0T<float>, float)
                                         double *);                                               \
     template void launch_zero_if_zero_rhs<T>(hipStream_t, T *, int, const SolveStatus *);        \
     template void launch_k0_wdinv<T>(hipStream_t, const K0T<T> &, double, T *);                   \
+    template void launch_k0_prolong_mf<T>(hipStream_t, const K0T<T> &, const int *, const T *,    \
+                                          double, T *, const SolveStatus *);                      \
     template void launch_k0_presmooth2<T>(hipStream_t, const K0T<T> &, const T *, const T *, T *,  \
                                           const SolveStatus *);                                   \
     template void launch_k0_jacobi_first<T>(hipStream_t, const K0T<T> &, double, const T *, T *, \

@@ -648,6 +648,7 @@ void build_hierarchy(Hierarchy &h, const CSR &K, const AmgParams &prm) {
         L.P = std::move(P);
         L.R = std::move(R);
         L.agg = std::move(agg);
+        L.pomega = w;
         h.levels.emplace_back();
         h.levels.back().A = std::move(Ac);
         finish_level(h.levels.back());

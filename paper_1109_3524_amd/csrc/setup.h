@@ -60,6 +60,7 @@ struct Level {
     double omega = 0;
     CSR P, R;                        // prolongator to this level from the next, and P^T
     std::vector<int32_t> agg;
+    double pomega = 0;               // P = (I - pomega D^-1 A) T (T: aggregates)
 };
 
 struct Hierarchy {

@@ -27,6 +27,7 @@ SOLVER_AMG_PCG = 1
 SOLVER_AMG_PCG_MIXED = 2
 SOLVER_AMG_FCG_LEARNED = 3
 SOLVER_AMG_FCG_MIXED_LEARNED = 4
+SOLVER_AMG_PCG_FP32_CYCLE = 5
 
 
 def stretch_ratio(n_side: int, h: float, width: float) -> float:

@@ -441,3 +441,28 @@ def test_graph_replay_matches_eager_launches():
         assert a[2] == b[2]
         np.testing.assert_array_equal(a[0], b[0])
         np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_fp32_cycle_solver_matches_fp64():
+    """FP64 CG with the V-cycle in FP32 (a fixed linear preconditioner): the
+    same 1e-8 true residual, the projected velocity within the FP64 solver's
+    own error, and about the FP64 iteration count."""
+    wl = W.cylinder_512()
+    P = Problem(wl, poisson_solver=1, vel_rtol=TIGHT, poisson_rtol=TIGHT)
+    rhs, st = _poisson_rhs_after(P, 1)
+    ref, _, _ = P.solve_poisson(rhs, st.lam, rtol=TIGHT, maxit=50000)
+    o = P.ops
+    R = P.grid.R_diag()
+    out = {}
+    for solver in (1, 5):
+        ctx = ibpm.Context(wl, poisson_solver=solver, poisson_rtol=1e-8)
+        lam = _t(st.lam)
+        s = ctx.solve_poisson(_t(rhs), lam)
+        out[solver] = (s, _rel(o.B1 * (o.Q @ _n(lam)) / R, o.B1 * (o.Q @ ref) / R))
+        ctx.close()
+    (s1, d1), (s5, d5) = out[1], out[5]
+    print(f"  FP64 cycle {s1['iters']} iters, projection err {d1:.2e}; "
+          f"FP32 cycle {s5['iters']} iters, projection err {d5:.2e}")
+    assert s5["relres"] <= 1e-8
+    assert d5 < max(3.0 * d1, 1e-7)
+    assert s5["iters"] <= 1.2 * s1["iters"]

@@ -62,7 +62,7 @@ def _params(wl, **over):
     (dict(nu=-1.0), "positive"),
     (dict(poisson_solver=7), "solver"),
     (dict(poisson_solver=2, amg_pre=0), "sweep"),
-    (dict(poisson_solver=5), "solver"),
+    (dict(poisson_solver=6), "solver"),
     (dict(poisson_solver=4, inner_rtol=1.5), "inner_rtol"),
     (dict(poisson_solver=2, inner_rtol=-1e-3), "inner_rtol"),
 ])
