@@ -66,6 +66,27 @@ def test_operators_match_oracle(name):
     ctx.close()
 
 
+def test_operator_dense_body():
+    """A body with about four points per cell width: each cell couples to up
+    to 36 force unknowns and each force row has up to 44 entries (against 9
+    and 19 on the cylinder workloads); the operator must still match the
+    oracle."""
+    wl = W.cylinder_small(96, 300)
+    print("[apply] cyl96 with 300 body points", flush=True)
+    P = Problem(wl, poisson_solver=0)
+    Kc = P.ops.K.tocsr()
+    nc = wl.nx * wl.ny
+    cols = [Kc.indices[Kc.indptr[i]:Kc.indptr[i + 1]] for i in range(nc)]
+    assert max(int((c >= nc).sum()) for c in cols) > 10
+    assert np.diff(Kc[nc:].tocsr().indptr).max() > 24
+    ctx = ibpm.Context(wl, poisson_solver=0)
+    rng = np.random.default_rng(12)
+    x = rng.standard_normal(ctx.n_lambda)
+    y = _n(ctx.apply_K(_t(x)))
+    assert _maxrel(y, P.ops.K @ x) < 1e-13
+    ctx.close()
+
+
 def _oracle_state(P, steps):
     st = P.initial_state()
     for _ in range(steps):
