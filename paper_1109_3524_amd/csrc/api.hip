@@ -1030,10 +1030,69 @@ void check_params(const ibpm_params *p) {
     }
 }
 
+// The stored rows of level-0 K as the walker's bands take them: fixed-width
+// (ELL) copies of the force rows and of the coupled cells' rows (slot q of
+// a row is CSR entry q; empty slots hold column -1 and value 0), the list of
+// coupled cells (box cells with at least one coupling entry) and one bit per
+// box cell marking them.
+struct BandHost {
+    bool kf_ok = true, cc_ok = true;
+    std::vector<int32_t> kf_col, cc_row, cc_col;
+    std::vector<double> kf_val, cc_val;
+    std::vector<uint32_t> bits;
+};
+
+BandHost make_bands(const Model &m) {
+    BandHost h;
+    const CSR &kf = m.Kf, &cf = m.Kcf;
+    h.kf_col.assign((size_t)kKfW * kf.nrows, -1);
+    h.kf_val.assign((size_t)kKfW * kf.nrows, 0.0);
+    for (int r = 0; r < kf.nrows; ++r) {
+        const int p0 = kf.ptr[r], len = kf.ptr[r + 1] - p0;
+        if (len > kKfW) {
+            h.kf_ok = false;
+            continue;
+        }
+        for (int q = 0; q < len; ++q) {
+            h.kf_col[(size_t)r * kKfW + q] = kf.col[p0 + q];
+            h.kf_val[(size_t)r * kKfW + q] = kf.val[p0 + q];
+        }
+    }
+    const int bw = m.cb_i1 - m.cb_i0 + 1;
+    h.bits.assign(((size_t)cf.nrows + 31) / 32, 0u);
+    for (int rb = 0; rb < cf.nrows; ++rb) {
+        const int p0 = cf.ptr[rb], len = cf.ptr[rb + 1] - p0;
+        if (len == 0) continue;
+        h.bits[rb >> 5] |= 1u << (rb & 31);
+        const int q = (int)h.cc_row.size();
+        h.cc_row.push_back((m.cb_j0 + rb / bw) * m.g.nx + (m.cb_i0 + rb % bw));
+        h.cc_col.resize((size_t)(q + 1) * kCcW, -1);
+        h.cc_val.resize((size_t)(q + 1) * kCcW, 0.0);
+        if (len > kCcW) {
+            h.cc_ok = false;
+            continue;
+        }
+        for (int k = 0; k < len; ++k) {
+            h.cc_col[(size_t)q * kCcW + k] = cf.col[p0 + k];
+            h.cc_val[(size_t)q * kCcW + k] = cf.val[p0 + k];
+        }
+    }
+    return h;
+}
+
+// device copies of the band arrays in precision T (indices shared)
+template <class T>
+struct BandDev {
+    int kf_ok = 0, cc_ok = 0, ncc = 0;
+    const int32_t *kf_col = nullptr, *cc_row = nullptr, *cc_col = nullptr;
+    const uint32_t *bits = nullptr;
+    const T *kf_val = nullptr, *cc_val = nullptr;
+};
+
 // K0 view in precision T over device metric / coupling arrays
 template <class T>
 K0T<T> make_k0(const GridT<T> &g, double dt, const Model &m, const DevCSRT<T> &cf,
-               const DevCSRT<T> &kf, const T *kfd) {
+               const DevCSRT<T> &kf, const T *kfd, const BandDev<T> &bd) {
     K0T<T> K;
     K.g = g;
     K.dt = (T)dt;
@@ -1043,6 +1102,15 @@ K0T<T> make_k0(const GridT<T> &g, double dt, const Model &m, const DevCSRT<T> &c
     K.cf = cf.view();
     K.kf = kf.view();
     K.kf_diag = kfd;
+    K.kf_ell = bd.kf_ok;
+    K.kfe_col = bd.kf_col;
+    K.kfe_val = bd.kf_val;
+    K.ncc = bd.ncc;
+    K.cc_ell = bd.cc_ok;
+    K.cc_row = bd.cc_row;
+    K.cc_bits = bd.bits;
+    K.cce_col = bd.cc_col;
+    K.cce_val = bd.cc_val;
     return K;
 }
 
@@ -1173,7 +1241,23 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     c->ub = c->upload(m.ub);
     DevCSR cf = c->upload_csr<double>(m.Kcf), kf = c->upload_csr<double>(m.Kf);
     double *kfd = c->upload(m.Kf_diag);
-    c->p64.K0 = make_k0<double>(c->g, p->dt, m, cf, kf, kfd);
+    {
+        const long nbox = m.cb_i1 >= m.cb_i0 && m.cb_j1 >= m.cb_j0
+                              ? (long)(m.cb_i1 - m.cb_i0 + 1) * (m.cb_j1 - m.cb_j0 + 1) : 0;
+        if (nbox != (long)m.Kcf.nrows) throw std::runtime_error("coupling rows do not match the coupling box");
+    }
+    const BandHost bh = make_bands(m);
+    BandDev<double> bd64;
+    bd64.kf_ok = bh.kf_ok;
+    bd64.cc_ok = bh.cc_ok;
+    bd64.ncc = (int)bh.cc_row.size();
+    bd64.kf_col = c->upload(bh.kf_col);
+    bd64.cc_row = c->upload(bh.cc_row);
+    bd64.cc_col = c->upload(bh.cc_col);
+    bd64.bits = c->upload(bh.bits);
+    bd64.kf_val = c->upload(bh.kf_val);
+    bd64.cc_val = c->upload(bh.cc_val);
+    c->p64.K0 = make_k0<double>(c->g, p->dt, m, cf, kf, kfd, bd64);
     c->A.g = c->g;
     c->A.dt = p->dt;
     c->A.idt = 1.0 / p->dt;
@@ -1187,7 +1271,17 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
         GridT<float> g32 = make_grid<float>(c, G);
         DevCSRT<float> cf32 = c->values32(cf, m.Kcf), kf32 = c->values32(kf, m.Kf);
         float *kfd32 = c->upload(std::vector<float>(m.Kf_diag.begin(), m.Kf_diag.end()));
-        c->p32.K0 = make_k0<float>(g32, p->dt, m, cf32, kf32, kfd32);
+        BandDev<float> bd32;
+        bd32.kf_ok = bd64.kf_ok;
+        bd32.cc_ok = bd64.cc_ok;
+        bd32.ncc = bd64.ncc;
+        bd32.kf_col = bd64.kf_col;
+        bd32.cc_row = bd64.cc_row;
+        bd32.cc_col = bd64.cc_col;
+        bd32.bits = bd64.bits;
+        bd32.kf_val = c->upload(std::vector<float>(bh.kf_val.begin(), bh.kf_val.end()));
+        bd32.cc_val = c->upload(std::vector<float>(bh.cc_val.begin(), bh.cc_val.end()));
+        c->p32.K0 = make_k0<float>(g32, p->dt, m, cf32, kf32, kfd32, bd32);
         upload_levels<float>(c, c->p32);
         alloc_pcg(c, c->p32, nl);
         c->rin32 = c->dalloc<float>(nl);

@@ -56,6 +56,15 @@ struct CSRT {
 };
 using CSRView = CSRT<double>;
 
+// Rows of K with stored entries are taken by bands of blocks ahead of the
+// stencil tiles, 8 lanes per row, from fixed-width (ELL) copies of the CSR
+// rows so that a row's entries are fetched in one round of independent
+// loads: slot k * 8 + l of a row is CSR entry k * 8 + l, taken by lane l;
+// empty slots hold column -1 and value 0.  Rows longer than the width are
+// read from the CSR instead (the ELL flag of the matrix is 0).
+constexpr int kKfW = 24;   // slots per force row
+constexpr int kCcW = 16;   // slots per coupled cell (force unknowns it meets)
+
 // Level-0 Poisson operator K = Q^T B^1 Q (pinned), matrix-free pressure
 // stencil plus stored coupling rows, in precision T.
 template <class T>
@@ -67,6 +76,18 @@ struct K0T {
     CSRT<T> cf;                      // box cells -> (force 0..2nb-1, value)
     CSRT<T> kf;                      // force rows, columns in lambda numbering
     const T *kf_diag;
+    // ELL copies of the force rows ([row * kKfW + slot])
+    int kf_ell;
+    const int32_t *kfe_col;
+    const T *kfe_val;
+    // the ncc box cells with coupling entries: their cell indices, one bit
+    // per box cell (row-major in the box) marking them, and the ELL copy of
+    // their coupling ([q * kCcW + slot], columns 0..2nb-1)
+    int ncc, cc_ell;
+    const int32_t *cc_row;
+    const uint32_t *cc_bits;
+    const int32_t *cce_col;
+    const T *cce_val;
 };
 using K0View = K0T<double>;
 

@@ -53,15 +53,20 @@ struct Tiles {
     int t0, t1;
 };
 
+// Tiles of 256 elements of the block: the ntiles tiles are split in
+// proportion over the G blocks in remapped order, so that XCD x takes the
+// x-th eighth of the vector, the same elements its blocks take in every
+// other kernel (the stencil walkers, the CSR kernels, the one-tile kernels):
+// a vector written by one kernel is read from the same L2 by the next.
 __device__ __forceinline__ Tiles my_tiles(int n) {
-    int ntiles = (n + kBlock - 1) / kBlock;
-    int G = gridDim.x;
-    int l = remap_block(blockIdx.x, G);
-    int T = (ntiles + G - 1) / G;
-    int t0 = l * T;
-    int t1 = min(t0 + T, ntiles);
-    return {t0, t1};
+    const int ntiles = (n + kBlock - 1) / kBlock;
+    const int G = gridDim.x;
+    const long long l = remap_block(blockIdx.x, G);
+    return {(int)(l * ntiles / G), (int)((l + 1) * ntiles / G)};
 }
+
+// first element of a one-tile-per-block kernel (grid = number of tiles)
+__device__ __forceinline__ int tile_base() { return remap_block(blockIdx.x, gridDim.x) * kBlock; }
 
 inline int grid_for(int n) {
     int ntiles = (n + kBlock - 1) / kBlock;
@@ -133,23 +138,147 @@ __device__ __forceinline__ void write_parts(double (&v)[N], double *parts) {
 __device__ __forceinline__ bool bad(double v) { return !(v == v) || v > 1e300; }
 
 // ---------------------------------------------------------------------------
-// Level-0 operators as 2-D walks.  A block is 64 x 4 threads; thread (tx, ty)
-// takes unknown column i = 64 bx + tx and the R rows j = (4 by + ty) R + r,
-// walking up the column so that the south / centre / north operands stay in
-// registers (each is loaded once), east / west come from the neighbouring
-// lanes' loads (L1), and the 1-D metrics of a row are wave-uniform.  Rows
-// that are not on the tensor grid (the 2 nb force rows of K, about 18
-// entries each) are taken by a band of blocks at the start of the grid, so
-// they are dispatched first, with kForceLanes lanes per row and a shuffle
-// reduction, so their gather chains are short.  Every block reaches the
-// reduction at the end.
-
-template <int R>
-__host__ __device__ inline int walk_by(int nj) { return (nj + 4 * R - 1) / (4 * R); }
+// Level-0 operators as walks over tiles of 256 columns x R rows of cells
+// (one thread per column, walking its R rows), in a 1-D grid remapped so
+// that the tiles of one XCD are contiguous.  The rows of K with stored
+// entries are taken by two bands of blocks at the start of the grid, so they
+// are dispatched first: the 2 nb force rows (about 18 entries each) and the
+// cells of the coupling box that meet a force unknown (up to 9 entries on
+// the cylinder workloads), 8 lanes per row with a shuffle reduction.  The
+// tiles skip those cells (one bit each), so a tile is the plain 5-point
+// stencil with every operand load issued before the arithmetic.
 
 constexpr int kForceLanes = 8;
-__host__ __device__ inline int force_band(int nb) {
-    return (2 * nb * kForceLanes + kBlock - 1) / kBlock;
+static_assert(kKfW % kForceLanes == 0 && kCcW % kForceLanes == 0, "ELL widths must be multiples of 8");
+
+template <class T>
+__host__ __device__ inline int force_blocks(const K0T<T> &K) {
+    return (2 * K.nb * kForceLanes + kBlock - 1) / kBlock;
+}
+// both bands, padded to a multiple of 8 blocks, so that block b of the
+// tiles that follow runs on XCD b mod 8 (the XCD a block is sent to) and
+// the tile remap keeps XCD x on the x-th eighth of the cells
+template <class T>
+__host__ __device__ inline int k0_band(const K0T<T> &K) {
+    const int nbk = force_blocks(K) + (K.ncc * kForceLanes + kBlock - 1) / kBlock;
+    return (nbk + 7) & ~7;
+}
+
+// 5-point part of the pressure row of cell (i, j), any position on the grid
+template <class T, class XV>
+__device__ __forceinline__ T k0_cell_stencil(const K0T<T> &K, int i, int j, XV xv, T &diag, T &xc) {
+    const GridT<T> &g = K.g;
+    const int nx = g.nx, ny = g.ny;
+    const int row = j * nx + i;
+    const T dt = K.dt;
+    const T dxi = g.dx[i];
+    const T dyj = g.dy[j];
+    const T bw = i > 0 ? dt * g.iDx[i] * dyj : T(0);
+    const T be = i < nx - 1 ? dt * g.iDx[i + 1] * dyj : T(0);
+    const T bs = j > 0 ? dt * dxi * g.iDy[j] : T(0);
+    const T bn = j < ny - 1 ? dt * dxi * g.iDy[j + 1] : T(0);
+    xc = xv(row);
+    const T xs = j > 0 ? xv(row - nx) : T(0);
+    const T xn = j < ny - 1 ? xv(row + nx) : T(0);
+    const T xw = i > 0 ? xv(row - 1) : T(0);
+    const T xe = i < nx - 1 ? xv(row + 1) : T(0);
+    diag = ((bw + be) + bs) + bn;
+    T y = diag * xc;
+    if (row != 0) {
+        if (row - nx != 0) y -= bs * xs;
+        if (row - 1 != 0) y -= bw * xw;
+        y -= be * xe;
+        y -= bn * xn;
+    }
+    return y;
+}
+
+// sum of the row's stored entries over the 8 lanes of the row: from the ELL
+// slots (all loads issued at once; a clamped row for the lanes past the
+// last row, and the terms of empty slots dropped by a select) or, for rows
+// longer than the width, from the CSR row
+template <int W, class T, class XV>
+__device__ __forceinline__ T band_row_sum(bool live, int q, int lane, bool ell, const int32_t *ecol,
+                                          const T *eval, const CSRT<T> &csr, int crow, int col_off, XV xv) {
+    T y = T(0);
+    if (ell) {
+        constexpr int kS = W / kForceLanes;
+        const int base = (live ? q : 0) * W + lane;
+        int cc[kS];
+        T cv[kS], cx[kS];
+#pragma unroll
+        for (int k = 0; k < kS; ++k) {
+            cc[k] = ecol[base + k * kForceLanes];
+            cv[k] = eval[base + k * kForceLanes];
+        }
+#pragma unroll
+        for (int k = 0; k < kS; ++k) cx[k] = xv(col_off + (cc[k] >= 0 ? cc[k] : 0));
+#pragma unroll
+        for (int k = 0; k < kS; ++k) {
+            const T t = y + cv[k] * cx[k];
+            y = (live && cc[k] >= 0) ? t : y;
+        }
+    } else if (live) {
+        for (int p = csr.ptr[crow] + lane; p < csr.ptr[crow + 1]; p += kForceLanes)
+            y += csr.val[p] * xv(col_off + csr.col[p]);
+    }
+#pragma unroll
+    for (int o = kForceLanes / 2; o > 0; o >>= 1) y += __shfl_xor(y, o, kForceLanes);
+    return y;
+}
+
+// is cell (i, j) one of the coupled cells (taken by the band)?
+template <class T>
+__device__ __forceinline__ bool k0_coupled(const K0T<T> &K, int i, int j) {
+    if (i < K.cb_i0 || i > K.cb_i1 || j < K.cb_j0 || j > K.cb_j1) return false;
+    const int rb = (j - K.cb_j0) * (K.cb_i1 - K.cb_i0 + 1) + (i - K.cb_i0);
+    return (K.cc_bits[rb >> 5] >> (rb & 31)) & 1u;
+}
+
+// Interior tile of R rows (every row has a north neighbour): all operand
+// loads of the R rows are issued before the arithmetic.  BOX: the tile
+// meets the coupling box, and its coupled cells are left to the band.
+template <int R, bool BOX, class T, class XV, class ACT>
+__device__ __forceinline__ void k0_tile(const K0T<T> &K, int i, int j0, XV xv, ACT act) {
+    const GridT<T> &g = K.g;
+    const int nx = g.nx;
+    const T dt = K.dt;
+    const T dxi = g.dx[i];
+    const T cw = i > 0 ? dt * g.iDx[i] : T(0);
+    const T ce = i < nx - 1 ? dt * g.iDx[i + 1] : T(0);
+    const int row0 = j0 * nx + i;
+    T xcol[R + 2], xwr[R], xer[R], dyr[R], iyr[R + 1];
+    bool skip[R];
+    xcol[0] = j0 > 0 ? xv(row0 - nx) : T(0);
+#pragma unroll
+    for (int k = 0; k <= R; ++k) xcol[k + 1] = xv(row0 + k * nx);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        xwr[r] = i > 0 ? xv(row0 + r * nx - 1) : T(0);
+        xer[r] = i < nx - 1 ? xv(row0 + r * nx + 1) : T(0);
+        dyr[r] = g.dy[j0 + r];
+        skip[r] = BOX ? k0_coupled(K, i, j0 + r) : false;
+    }
+#pragma unroll
+    for (int r = 0; r <= R; ++r) iyr[r] = g.iDy[j0 + r];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = j0 + r;
+        const int row = row0 + r * nx;
+        const T bw = cw * dyr[r], be = ce * dyr[r];
+        const T bs = j > 0 ? dt * dxi * iyr[r] : T(0);
+        const T bn = dt * dxi * iyr[r + 1];
+        const T diag = ((bw + be) + bs) + bn;
+        const T xc = xcol[r + 1];
+        T y = diag * xc;
+        if (row != 0) {
+            if (row - nx != 0) y -= bs * xcol[r];
+            if (row - 1 != 0) y -= bw * xwr[r];
+            y -= be * xer[r];
+            y -= bn * xcol[r + 2];
+        }
+        if (!BOX || !skip[r]) act(row, y, diag, xc);
+    }
 }
 
 // Pressure and force rows of K = Q^T B^1 Q (pinned), precision T.
@@ -158,7 +287,8 @@ template <int R, class T, class XV, class ACT>
 __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
     const GridT<T> &g = K.g;
     const int nx = g.nx, ny = g.ny;
-    const int band = force_band(K.nb);
+    const int band = k0_band(K);
+    const int fbk = force_blocks(K);
     const int b = (int)blockIdx.x;
     if (b >= band) {
         // tile of 256 columns x R rows; the tiles of one XCD are contiguous in
@@ -169,112 +299,57 @@ __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
         const int cy = w / cx_n, cx = w - cy * cx_n;
         const int i = cx * kBlock + threadIdx.x;
         const int j0 = cy * R;
+        // the same for every lane of the block
+        const bool box_tile = K.ncc > 0 && j0 <= K.cb_j1 && j0 + R - 1 >= K.cb_j0 &&
+                              cx * kBlock <= K.cb_i1 && cx * kBlock + kBlock - 1 >= K.cb_i0;
         if (i < nx && j0 + R < ny) {
-            // interior tile: every row has a north neighbour; all operand
-            // loads of the R rows are issued before the arithmetic
-            const T dt = K.dt;
-            const T dxi = g.dx[i];
-            const T cw = i > 0 ? dt * g.iDx[i] : T(0);
-            const T ce = i < nx - 1 ? dt * g.iDx[i + 1] : T(0);
-            const bool in_box_i = i >= K.cb_i0 && i <= K.cb_i1;
-            const int bw_ = K.cb_i1 - K.cb_i0 + 1;
-            const int row0 = j0 * nx + i;
-            T xcol[R + 2], xwr[R], xer[R], dyr[R], iyr[R + 1];
-            xcol[0] = j0 > 0 ? xv(row0 - nx) : T(0);
-#pragma unroll
-            for (int k = 0; k <= R; ++k) xcol[k + 1] = xv(row0 + k * nx);
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                xwr[r] = i > 0 ? xv(row0 + r * nx - 1) : T(0);
-                xer[r] = i < nx - 1 ? xv(row0 + r * nx + 1) : T(0);
-                dyr[r] = g.dy[j0 + r];
-            }
-#pragma unroll
-            for (int r = 0; r <= R; ++r) iyr[r] = g.iDy[j0 + r];
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const int j = j0 + r;
-                const int row = row0 + r * nx;
-                const T bw = cw * dyr[r], be = ce * dyr[r];
-                const T bs = j > 0 ? dt * dxi * iyr[r] : T(0);
-                const T bn = dt * dxi * iyr[r + 1];
-                const T diag = ((bw + be) + bs) + bn;
-                const T xc = xcol[r + 1];
-                T y = diag * xc;
-                if (row != 0) {
-                    if (row - nx != 0) y -= bs * xcol[r];
-                    if (row - 1 != 0) y -= bw * xwr[r];
-                    y -= be * xer[r];
-                    y -= bn * xcol[r + 2];
-                    if (in_box_i && j >= K.cb_j0 && j <= K.cb_j1) {
-                        const int rb = (j - K.cb_j0) * bw_ + (i - K.cb_i0);
-                        for (int p = K.cf.ptr[rb]; p < K.cf.ptr[rb + 1]; ++p)
-                            y += K.cf.val[p] * xv(g.n_cell + K.cf.col[p]);
-                    }
-                }
-                act(row, y, diag, xc);
-            }
+            if (box_tile)
+                k0_tile<R, true>(K, i, j0, xv, act);
+            else
+                k0_tile<R, false>(K, i, j0, xv, act);
         } else if (i < nx && j0 < ny) {
-            const T dt = K.dt;
-            const T dxi = g.dx[i];
-            const T cw = i > 0 ? dt * g.iDx[i] : T(0);
-            const T ce = i < nx - 1 ? dt * g.iDx[i + 1] : T(0);
-            const bool in_box_i = i >= K.cb_i0 && i <= K.cb_i1;
-            const int bw_ = K.cb_i1 - K.cb_i0 + 1;
-            int row = j0 * nx + i;
-            T xs = j0 > 0 ? xv(row - nx) : T(0);
-            T xc = xv(row);
+            // top rows: one row at a time
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const int j = j0 + r;
                 if (j >= ny) break;
-                const T xn = j < ny - 1 ? xv(row + nx) : T(0);
-                const T xw = i > 0 ? xv(row - 1) : T(0);
-                const T xe = i < nx - 1 ? xv(row + 1) : T(0);
-                const T dyj = g.dy[j];
-                const T bw = cw * dyj, be = ce * dyj;
-                const T bs = j > 0 ? dt * dxi * g.iDy[j] : T(0);
-                const T bn = j < ny - 1 ? dt * dxi * g.iDy[j + 1] : T(0);
-                const T diag = ((bw + be) + bs) + bn;
-                T y = diag * xc;
-                if (row != 0) {
-                    if (row - nx != 0) y -= bs * xs;
-                    if (row - 1 != 0) y -= bw * xw;
-                    y -= be * xe;
-                    y -= bn * xn;
-                    if (in_box_i && j >= K.cb_j0 && j <= K.cb_j1) {
-                        const int rb = (j - K.cb_j0) * bw_ + (i - K.cb_i0);
-                        for (int p = K.cf.ptr[rb]; p < K.cf.ptr[rb + 1]; ++p)
-                            y += K.cf.val[p] * xv(g.n_cell + K.cf.col[p]);
-                    }
-                }
-                act(row, y, diag, xc);
-                xs = xc;
-                xc = xn;
-                row += nx;
+                if (box_tile && k0_coupled(K, i, j)) continue;
+                T diag, xc;
+                const T y = k0_cell_stencil(K, i, j, xv, diag, xc);
+                act(j * nx + i, y, diag, xc);
             }
         }
-    } else {
-        // kForceLanes consecutive lanes (one wave holds 64 / kForceLanes rows)
+    } else if (b < fbk) {
+        // force rows
         const int t = b * kBlock + threadIdx.x;
         const int fr = t / kForceLanes, lane = t % kForceLanes;
         const bool live = fr < 2 * K.nb;
-        T y = T(0);
-        if (live)
-            for (int p = K.kf.ptr[fr] + lane; p < K.kf.ptr[fr + 1]; p += kForceLanes)
-                y += K.kf.val[p] * xv(K.kf.col[p]);
-#pragma unroll
-        for (int o = kForceLanes / 2; o > 0; o >>= 1) y += __shfl_xor(y, o, kForceLanes);
+        const T y = band_row_sum<kKfW>(live, fr, lane, K.kf_ell, K.kfe_col, K.kfe_val, K.kf, fr, 0, xv);
         if (live && lane == 0) act(g.n_cell + fr, y, K.kf_diag[fr], xv(g.n_cell + fr));
+    } else {
+        // coupled cells: the stencil (every lane forms it, so its loads go
+        // out with the coupling slots) plus the force coupling
+        if (K.ncc == 0) return;
+        const int t = (b - fbk) * kBlock + threadIdx.x;
+        const int q = t / kForceLanes, lane = t % kForceLanes;
+        const bool live = q < K.ncc;
+        const int row = K.cc_row[live ? q : 0];
+        const int j = row / nx, i = row - j * nx;
+        T diag, xc;
+        const T ys = k0_cell_stencil(K, i, j, xv, diag, xc);
+        const int rb = (j - K.cb_j0) * (K.cb_i1 - K.cb_i0 + 1) + (i - K.cb_i0);
+        const T yc = band_row_sum<kCcW>(live, q, lane, K.cc_ell, K.cce_col, K.cce_val, K.cf, rb,
+                                        g.n_cell, xv);
+        if (live && lane == 0) act(row, row != 0 ? ys + yc : ys, diag, xc);
     }
 }
 
-// 1-D grid: the force band, then one block per 256 columns x R rows
+// 1-D grid: the bands, then one block per 256 columns x R rows
 template <int R, class T>
 inline dim3 k0_grid(const K0T<T> &K) {
     const int cx_n = (K.g.nx + kBlock - 1) / kBlock;
     const int cy_n = (K.g.ny + R - 1) / R;
-    return dim3(force_band(K.nb) + cx_n * cy_n);
+    return dim3(k0_band(K) + cx_n * cy_n);
 }
 
 // Velocity rows of A = Mf/dt - (nu/2) M Lhat R^{-1}: u faces (nx-1) x ny,
@@ -910,7 +985,7 @@ __global__ __launch_bounds__(kBlock) void k_fcg_direction(int n, const T *__rest
     // p may be the slot of the oldest direction in the window: each element
     // is read before it is overwritten, by the same thread
     if (st->done) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = tile_base() + threadIdx.x;
     if (i >= n) return;
     T v = z[i];
     for (int j = 0; j < cnt; ++j) v += (T)ring->beta[j] * P.v[sl.s[j]][i];
@@ -966,7 +1041,7 @@ __global__ __launch_bounds__(kBlock) void k_axpy_omega(int n, const T *z0, const
                                                        const SolveStatus *stw, T *z,
                                                        const SolveStatus *st) {
     if (st->done) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = tile_base() + threadIdx.x;
     const T w = (T)stw->beta;
     if (i < n) z[i] = w != T(0) ? z0[i] + w * d[i] : z0[i];
 }
@@ -1090,7 +1165,7 @@ __global__ __launch_bounds__(kBlock) void k_csrv_jacobi(CSRT<T> A, const T *__re
                                                         const T *__restrict__ xin, T *__restrict__ xout,
                                                         const SolveStatus *st) {
     if (st->done) return;
-    const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
+    const int row = remap_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
     const int lane = threadIdx.x % L;
     if (row >= A.nrows) return;
     T ax = csrv_dot<T, L>(A, row, xin, lane);
@@ -1101,7 +1176,7 @@ template <class T, int L>
 __global__ __launch_bounds__(kBlock) void k_csrv_residual(CSRT<T> A, const T *__restrict__ b, const T *__restrict__ x, T *__restrict__ r,
                                                           const SolveStatus *st) {
     if (st->done) return;
-    const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
+    const int row = remap_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
     const int lane = threadIdx.x % L;
     if (row >= A.nrows) return;
     T ax = csrv_dot<T, L>(A, row, x, lane);
@@ -1112,7 +1187,7 @@ template <class T, int L>
 __global__ __launch_bounds__(kBlock) void k_csrv_spmv(CSRT<T> A, const T *__restrict__ x, T *__restrict__ y, int add,
                                                       const SolveStatus *st) {
     if (st && st->done) return;
-    const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
+    const int row = remap_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
     const int lane = threadIdx.x % L;
     if (row >= A.nrows) return;
     T v = csrv_dot<T, L>(A, row, x, lane);
@@ -1127,7 +1202,7 @@ __global__ __launch_bounds__(kBlock) void k_csrv_presmooth2(CSRT<T> A, const T *
                                                             T *__restrict__ x,
                                                             const SolveStatus *st) {
     if (st->done) return;
-    const int row = blockIdx.x * (kBlock / L) + threadIdx.x / L;
+    const int row = remap_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
     const int lane = threadIdx.x % L;
     if (row >= A.nrows) return;
     T ay = T(0);
@@ -1186,7 +1261,7 @@ __global__ __launch_bounds__(kBlock) void k_stream_copy(size_t n2, const double2
 __global__ __launch_bounds__(kBlock) void k_to_f32(int n, const double *__restrict__ x,
                                                    float *__restrict__ y, const SolveStatus *st) {
     if (st->done) return;
-    const int i = blockIdx.x * kBlock + threadIdx.x;
+    const int i = tile_base() + threadIdx.x;
     if (i < n) y[i] = (float)x[i];
 }
 
@@ -1210,7 +1285,7 @@ __global__ __launch_bounds__(kBlock) void k_widen_dot(int n, const float *__rest
 }
 
 __global__ __launch_bounds__(kBlock) void k_add_correction(int n, double *x, const float *d) {
-    int i = blockIdx.x * kBlock + threadIdx.x;
+    int i = tile_base() + threadIdx.x;
     if (i < n) x[i] += (double)d[i];
 }
 
