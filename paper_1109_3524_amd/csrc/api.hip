@@ -138,6 +138,7 @@ struct ibpm_ctx {
                 *st_out = nullptr;
     double *parts = nullptr;
     double *parts2 = nullptr;          // second partial-sum buffer (read by the next kernel)
+    double *parts3 = nullptr;          // r . r partials of a deferred PCG update
     int rz_G = 0;                      // partials of r . z left in parts by the last V-cycle
     SolveStatus *host_st = nullptr;   // pinned
     int est_vel = 8, est_poi = 32;
@@ -335,14 +336,22 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
     else launch_pcg_init(s, op, b, (const T *)x, r, z, st, c->parts, jacobi, rtol * rtol, maxit);
     if (!jacobi) precond(r, z);
     int curp = 0;
+    // With a preconditioner whose r . z partials the product sums itself,
+    // the update's stop test moves into the next product (no finalize
+    // launch per iteration): the update leaves its r . r partials in parts3
+    // and the preconditioner runs once more after the converged update, on
+    // a residual no later kernel uses.
+    const int G_rr = update_blocks_of(n);
+    const bool defer = !jacobi && c->rz_G <= kFuseMaxParts && G_rr <= kFuseMaxParts;
     auto iteration = [&]() {
         // with the V-cycle the product sums its r . z partials (in parts)
         launch_pcg_spmv(s, op, (const T *)z, (const T *)p[curp], p[1 - curp], q, st,
                         jacobi ? (const double *)nullptr : (const double *)c->parts, c->rz_G,
-                        c->parts2);
+                        c->parts2, defer ? (const double *)c->parts3 : (const double *)nullptr,
+                        defer ? G_rr : 0);
         curp = 1 - curp;
         launch_pcg_update(s, op, x, r, z, (const T *)p[curp], (const T *)q, st,
-                          (const double *)c->parts2, c->parts, jacobi, !jacobi);
+                          (const double *)c->parts2, defer ? c->parts3 : c->parts, jacobi, !jacobi, defer);
         if (!jacobi) precond(r, z);
     };
     // the iterations are identical launches (the two direction buffers swap
@@ -1314,6 +1323,8 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     // partial sums of up to kFcgMax components per block (FCG multi-dot)
     c->parts = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
     c->parts2 = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
+    // the update writes two rows of partials (r . r and, for Jacobi, r . z)
+    c->parts3 = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
     HIPCHECK(hipHostMalloc((void **)&c->host_st, sizeof(SolveStatus), hipHostMallocDefault));
     double U = p->uinf * std::cos(p->alpha), V = p->uinf * std::sin(p->alpha);
     launch_fill_walls(c->stream, c->g, c->walls[0], U, V);
@@ -1566,6 +1577,7 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
         st0.tol2 = -1.0;
         st0.rz = 1.0;
         st0.pq = 1.0;
+        st0.rz_next = 1.0;
         st0.maxit = 0x7fffffff;
         HIPCHECK(hipMemcpyAsync(c->st_bench, &st0, sizeof(st0), hipMemcpyHostToDevice, s));
         HIPCHECK(hipMemsetAsync(P.r, 0, n * sizeof(double), s));
@@ -1646,7 +1658,9 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
                 HIPCHECK(hipStreamSynchronize(s));
             }
             const double *pq_parts = c->parts2;
-            launch = [=] { launch_pcg_update(s, K0, x, r, z, p0, q, sb, pq_parts, parts, false, false); };
+            // as the AMG-PCG iteration launches it: alone, the stop test
+            // deferred to the next product (the status never stops here)
+            launch = [=] { launch_pcg_update(s, K0, x, r, z, p0, q, sb, pq_parts, parts, false, true, true); };
             by = 48.0 * n;
             break;
         }

@@ -7,7 +7,8 @@
 namespace ibpm {
 
 constexpr int kBlock = 256;        // threads per block (4 wave64)
-constexpr int kMaxParts = 32768;   // upper bound on blocks of a reducing kernel
+constexpr int kMaxParts = 32768;   // upper bound on blocks of a reducing kernel; a buffer of
+                                   // partials holds one row of kMaxParts per summed value
 
 // Launch shapes of the reducing kernels: the largest 2-D grid of the stencil
 // walkers (the walk depth R grows until the grid fits; walk_rows > 0 forces
@@ -146,22 +147,37 @@ void launch_csrv_presmooth2(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv,
 
 // number of blocks (and of partials) of a level-0 stencil kernel
 int walk_blocks_of(const K0View &K);
+// number of blocks (and of partials) of the PCG update on n unknowns
+int update_blocks_of(int n);
+// above this many partials a sum read by every block of the consumer costs
+// more than a one-block finalize launch
+constexpr int kFuseMaxParts = 2048;
 // p_new = z + beta p_old; q = op p_new; per-block partials of p . q in parts
 // (no finalize: the update below sums them).  beta is st->beta, or, when
 // rz_parts is given (G_rz partials of r . z from the preconditioner's last
 // kernel), beta = rz_new / st->rz (0 on the first iteration) with rz_new
-// summed here and left in st->rz_next.
+// summed here and left in st->rz_next.  With rr_parts (the G_rr partials of
+// r . r left by a deferred update, see below; needs rz_parts, both at most
+// kFuseMaxParts) every block also sums r . r and, except on the first
+// iteration, takes the stop decision the update's finalize would have taken
+// (NaN, converged, iteration limit): then it does nothing else and block 0
+// records it in st.
 template <class Op, class T>
 void launch_pcg_spmv(hipStream_t s, const Op &op, const T *z, const T *pold, T *pnew, T *q,
-                     SolveStatus *st, const double *rz_parts, int G_rz, double *parts);
+                     SolveStatus *st, const double *rz_parts, int G_rz, double *parts,
+                     const double *rr_parts = nullptr, int G_rr = 0);
 // x += alpha p; r -= alpha q (and z = D^{-1} r for Jacobi), alpha = rz / pq
 // with pq summed from pq_parts (the product kernel's partials; another
 // buffer than parts) or, when pq_parts is null, taken from st->pq; rz is
-// st->rz_next after a product with rz_parts (fused_rz), else st->rz
+// st->rz_next after a product with rz_parts (fused_rz), else st->rz.
+// Leaves the partials of r . r in parts; a one-block finalize then counts
+// the iteration and takes the stop decision, unless defer is set (needs
+// fused_rz, not Jacobi): then block 0 counts the iteration and moves
+// rz_next to rz, and the next product kernel takes the decision.
 template <class Op, class T>
 void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, T *z, const T *p, const T *q,
                        SolveStatus *st, const double *pq_parts, double *parts, bool jacobi,
-                       bool fused_rz);
+                       bool fused_rz, bool defer = false);
 template <class Op, class T>
 void launch_true_residual(hipStream_t s, const Op &op, const T *b, const T *x, SolveStatus *st,
                           double *parts);

@@ -589,17 +589,43 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv(Op op, const T *__restrict_
                                                      T *__restrict__ pnew, T *__restrict__ q,
                                                      SolveStatus *st,
                                                      const double *__restrict__ rz_parts, int G_rz,
-                                                     double *__restrict__ parts) {
+                                                     double *__restrict__ parts,
+                                                     const double *__restrict__ rr_parts, int G_rr) {
     if (st->done) return;
     T beta;
     if (rz_parts) {
         // r . z of the new preconditioned residual from the preconditioner's
         // partials (every block sums them in the same order); st->rz and
         // st->first are only read here, the new value goes to st->rz_next
-        double a[1] = {0.0};
-        gather_parts<1>(rz_parts, G_rz, 1, a);
-        block_sum<1>(a);
-        const double bt = st->first ? 0.0 : a[0] / st->rz;
+        const int first = st->first;
+        const double rz_old = st->rz;
+        double a[2] = {0.0, 0.0};
+        {
+            double a0[1] = {0.0};
+            gather_parts<1>(rz_parts, G_rz, 1, a0);
+            a[0] = a0[0];
+        }
+        if (rr_parts && !first) {
+            // the stop test of the previous update (the same decision in
+            // every block: it depends only on sums formed in a fixed order
+            // and on fields no block of this kernel writes before reading)
+            double b1[1] = {0.0};
+            gather_parts<1>(rr_parts, G_rr, 1, b1);
+            a[1] = b1[0];
+        }
+        block_sum<2>(a);
+        if (rr_parts && !first) {
+            const double rr = a[1];
+            const int stop = bad(rr) ? ST_NAN
+                             : rr <= st->tol2 * st->bb ? ST_CONVERGED
+                             : st->iter >= st->maxit ? ST_MAXIT : ST_RUNNING;
+            if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+                st->rr = rr;
+                if (stop != ST_RUNNING) st->done = stop;
+            }
+            if (stop != ST_RUNNING) return;
+        }
+        const double bt = first ? 0.0 : a[0] / rz_old;
         beta = (T)bt;
         if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
             st->rz_next = a[0];
@@ -640,10 +666,22 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *__restrict__ x,
                                                        T *__restrict__ z, const T *__restrict__ p,
                                                        const T *__restrict__ q, SolveStatus *st,
                                                        const double *__restrict__ pq_parts, int G_pq,
-                                                       double *__restrict__ parts, int jacobi,
-                                                       int fused_rz) {
+                                                       double *__restrict__ parts, int flags) {
     if (st->done) return;
+    // bit 0: Jacobi (z = D^-1 r here); bit 1: rz from the product (rz_next);
+    // bit 2: deferred stop test (block 0 counts the iteration and moves
+    // rz_next to rz: no block of this kernel reads iter, rz or first)
+    const bool jacobi = flags & 1, fused_rz = flags & 2;
     const int n = op_n(op);
+    // the status scalar and the operands of the block's first tile are read
+    // before the p . q sum below, whose barriers would otherwise make every
+    // later load wait for it (a clamped row where the block has none)
+    const double rz = fused_rz ? st->rz_next : st->rz;
+    const Tiles Tl = my_tiles(n);
+    const int row0 = Tl.t0 * kBlock + threadIdx.x;
+    const bool have0 = Tl.t0 < Tl.t1 && row0 < n;
+    const int rc = have0 ? row0 : 0;
+    const T x0 = x[rc], p0 = p[rc], r0 = r[rc], q0 = q[rc];
     // p . q from the partials of the product kernel, summed by every block in
     // the order the one-block finalize would use (so no separate launch)
     double pq;
@@ -656,22 +694,28 @@ __global__ __launch_bounds__(kBlock) void k_pcg_update(Op op, T *__restrict__ x,
     } else {
         pq = st->pq;
     }
-    const T alpha = (T)((fused_rz ? st->rz_next : st->rz) / pq);
-    Tiles Tl = my_tiles(n);
+    const T alpha = (T)(rz / pq);
+    if ((flags & 4) && blockIdx.x == 0 && threadIdx.x == 0) {
+        st->iter += 1;
+        st->rz = rz;
+        st->first = 0;
+    }
     double v[2] = {0.0, 0.0};
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < n) {
-            x[row] += alpha * p[row];
-            T ri = r[row] - alpha * q[row];
-            r[row] = ri;
-            v[0] += (double)ri * (double)ri;
-            if (jacobi) {
-                T zi = ri / op_diag(op, row);
-                z[row] = zi;
-                v[1] += (double)ri * (double)zi;
-            }
+    auto one = [&](int row, T xi, T pi, T ri, T qi) {
+        x[row] = xi + alpha * pi;
+        ri = ri - alpha * qi;
+        r[row] = ri;
+        v[0] += (double)ri * (double)ri;
+        if (jacobi) {
+            T zi = ri / op_diag(op, row);
+            z[row] = zi;
+            v[1] += (double)ri * (double)zi;
         }
+    };
+    if (have0) one(row0, x0, p0, r0, q0);
+    for (int t = Tl.t0 + 1; t < Tl.t1; ++t) {
+        int row = t * kBlock + threadIdx.x;
+        if (row < n) one(row, x[row], p[row], r[row], q[row]);
     }
     write_parts<2>(v, parts);
 }
@@ -1150,16 +1194,30 @@ __global__ __launch_bounds__(kBlock) void k_dense_solve(int n, const double *inv
 // CSR with a subgroup of L lanes per row: lane k takes entries k, k+L, ...,
 // then a butterfly over the subgroup (fixed order, so deterministic)
 
-template <class T, int L>
-__device__ __forceinline__ T csrv_dot(const CSRT<T> &A, int row, const T *x, int lane) {
+// sum over the row's entries [p0, e) of val * xv(col), L lanes per row:
+// each lane takes entries lane, lane + L, ... two per round with both
+// rounds' loads issued together (rows up to 2L long take one round), in the
+// same order as one entry per round; then a butterfly over the L lanes
+template <class T, int L, class XV>
+__device__ __forceinline__ T csrv_sum(const CSRT<T> &A, int p0, int e, int lane, XV xv) {
     T y = T(0);
-    const int e = A.ptr[row + 1];
-    for (int p = A.ptr[row] + lane; p < e; p += L) y += A.val[p] * x[A.col[p]];
+    for (int p = p0 + lane; p < e; p += 2 * L) {
+        const bool h1 = p + L < e;
+        const int q = h1 ? p + L : p;
+        const int c0 = A.col[p], c1 = A.col[q];
+        const T v0 = A.val[p], v1 = A.val[q];
+        const T x0 = xv(c0), x1 = xv(c1);
+        y += v0 * x0;
+        const T y1 = y + v1 * x1;
+        y = h1 ? y1 : y;
+    }
 #pragma unroll
     for (int off = L / 2; off > 0; off >>= 1) y += __shfl_xor(y, off, L);
     return y;
 }
 
+// The row's own operands are loaded by every lane of the row before the
+// sum, so that their latency overlaps the gather's.
 template <class T, int L>
 __global__ __launch_bounds__(kBlock) void k_csrv_jacobi(CSRT<T> A, const T *__restrict__ wdinv, const T *__restrict__ b,
                                                         const T *__restrict__ xin, T *__restrict__ xout,
@@ -1168,8 +1226,9 @@ __global__ __launch_bounds__(kBlock) void k_csrv_jacobi(CSRT<T> A, const T *__re
     const int row = remap_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
     const int lane = threadIdx.x % L;
     if (row >= A.nrows) return;
-    T ax = csrv_dot<T, L>(A, row, xin, lane);
-    if (lane == 0) xout[row] = xin[row] + wdinv[row] * (b[row] - ax);
+    const T xr = xin[row], wr = wdinv[row], br = b[row];
+    const T ax = csrv_sum<T, L>(A, A.ptr[row], A.ptr[row + 1], lane, [&](int c) { return xin[c]; });
+    if (lane == 0) xout[row] = xr + wr * (br - ax);
 }
 
 template <class T, int L>
@@ -1179,8 +1238,9 @@ __global__ __launch_bounds__(kBlock) void k_csrv_residual(CSRT<T> A, const T *__
     const int row = remap_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
     const int lane = threadIdx.x % L;
     if (row >= A.nrows) return;
-    T ax = csrv_dot<T, L>(A, row, x, lane);
-    if (lane == 0) r[row] = b[row] - ax;
+    const T br = b[row];
+    const T ax = csrv_sum<T, L>(A, A.ptr[row], A.ptr[row + 1], lane, [&](int c) { return x[c]; });
+    if (lane == 0) r[row] = br - ax;
 }
 
 template <class T, int L>
@@ -1190,8 +1250,9 @@ __global__ __launch_bounds__(kBlock) void k_csrv_spmv(CSRT<T> A, const T *__rest
     const int row = remap_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
     const int lane = threadIdx.x % L;
     if (row >= A.nrows) return;
-    T v = csrv_dot<T, L>(A, row, x, lane);
-    if (lane == 0) y[row] = add ? y[row] + v : v;
+    const T yr = add ? y[row] : T(0);
+    const T v = csrv_sum<T, L>(A, A.ptr[row], A.ptr[row + 1], lane, [&](int c) { return x[c]; });
+    if (lane == 0) y[row] = add ? yr + v : v;
 }
 
 // the first two damped-Jacobi sweeps from zero in one pass on a CSR level:
@@ -1205,29 +1266,14 @@ __global__ __launch_bounds__(kBlock) void k_csrv_presmooth2(CSRT<T> A, const T *
     const int row = remap_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
     const int lane = threadIdx.x % L;
     if (row >= A.nrows) return;
-    T ay = T(0);
-    const int e = A.ptr[row + 1];
-    for (int p = A.ptr[row] + lane; p < e; p += L) {
-        const int c = A.col[p];
-        ay += A.val[p] * (wdinv[c] * b[c]);
-    }
-#pragma unroll
-    for (int off = L / 2; off > 0; off >>= 1) ay += __shfl_xor(ay, off, L);
-    if (lane == 0) {
-        const T w = wdinv[row], bi = b[row];
-        x[row] = w * bi + w * (bi - ay);
-    }
+    const T w = wdinv[row], bi = b[row];
+    const T ay = csrv_sum<T, L>(A, A.ptr[row], A.ptr[row + 1], lane,
+                                [&](int c) { return wdinv[c] * b[c]; });
+    if (lane == 0) x[row] = w * bi + w * (bi - ay);
 }
 
 // ---------------------------------------------------------------------------
-// the small coarse levels, all in one work-group (barriers instead of launches)
-
-template <class T>
-__device__ __forceinline__ T csr_row(const CSRT<T> &A, int row, const T *x) {
-    T y = T(0);
-    for (int p = A.ptr[row]; p < A.ptr[row + 1]; ++p) y += A.val[p] * x[A.col[p]];
-    return y;
-}
+// the coarse part of the cycle as one dense matrix
 
 // x = C b with one wave per row (C row-major FP64, FP64 accumulation; b and
 // x in the precision of the cycle)
@@ -1653,31 +1699,34 @@ static int walk_grid_blocks(const Op &op) {
 }
 
 int walk_blocks_of(const K0View &K) { return walk_grid_blocks(K); }
-
-// above this many partials a sum read by every block of the consumer costs
-// more than a one-block finalize launch
-constexpr int kFuseMaxParts = 2048;
+int update_blocks_of(int n) { return grid_for(n); }
 
 template <class Op, class T>
 void launch_pcg_spmv(hipStream_t s, const Op &op, const T *z, const T *pold, T *pnew, T *q,
-                     SolveStatus *st, const double *rz_parts, int G_rz, double *parts) {
+                     SolveStatus *st, const double *rz_parts, int G_rz, double *parts,
+                     const double *rr_parts, int G_rr) {
     if (rz_parts && (rz_parts == parts || G_rz < 1 || G_rz > kMaxParts))
         throw std::runtime_error("pcg product: bad partial buffers");
+    if (rr_parts && (!rz_parts || rr_parts == parts || rr_parts == rz_parts || G_rz > kFuseMaxParts ||
+                     G_rr < 1 || G_rr > kFuseMaxParts))
+        throw std::runtime_error("pcg product: the deferred stop test needs fused sums");
     if (rz_parts && G_rz > kFuseMaxParts) {
         LAUNCH(k_finalize, 1, (int)FIN_RZ_NEXT, G_rz, rz_parts, st, 0, 0.0, 0);
         rz_parts = nullptr;
     }
     WALK_SWITCH(pick_R(op), {
         dim3 gd = op_grid<RR>(op);
-        LAUNCH2((k_pcg_spmv<RR, Op, T>), gd, op, z, pold, pnew, q, st, rz_parts, G_rz, parts);
+        LAUNCH2((k_pcg_spmv<RR, Op, T>), gd, op, z, pold, pnew, q, st, rz_parts, G_rz, parts,
+                rr_parts, G_rr);
     })
 }
 
 template <class Op, class T>
 void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, T *z, const T *p, const T *q,
                        SolveStatus *st, const double *pq_parts, double *parts, bool jacobi,
-                       bool fused_rz) {
+                       bool fused_rz, bool defer) {
     if (pq_parts == parts) throw std::runtime_error("pcg update: partial buffers must differ");
+    if (defer && (jacobi || !fused_rz)) throw std::runtime_error("pcg update: deferred stop test needs r . z from the product");
     int G_pq = pq_parts ? walk_grid_blocks(op) : 0;
     if (pq_parts && G_pq > kFuseMaxParts) {
         LAUNCH(k_finalize, 1, (int)FIN_PQ, G_pq, pq_parts, st, 0, 0.0, 0);
@@ -1685,9 +1734,10 @@ void launch_pcg_update(hipStream_t s, const Op &op, T *x, T *r, T *z, const T *p
         G_pq = 0;
     }
     int G = grid_for(op_n(op));
-    LAUNCH((k_pcg_update<Op, T>), G, op, x, r, z, p, q, st, pq_parts, G_pq, parts, (int)jacobi,
-           (int)fused_rz);
-    LAUNCH(k_finalize, 1, (int)FIN_UPDATE, G, parts, st, (int)jacobi | (fused_rz ? 2 : 0), 0.0, 0);
+    LAUNCH((k_pcg_update<Op, T>), G, op, x, r, z, p, q, st, pq_parts, G_pq, parts,
+           (int)jacobi | (fused_rz ? 2 : 0) | (defer ? 4 : 0));
+    if (!defer)
+        LAUNCH(k_finalize, 1, (int)FIN_UPDATE, G, parts, st, (int)jacobi | (fused_rz ? 2 : 0), 0.0, 0);
 }
 
 template <class Op, class T>
@@ -1968,10 +2018,11 @@ void launch_add_correction(hipStream_t s, int n, double *x, const float *d) {
     template void launch_pcg_init<OP, T>(hipStream_t, const OP &, const T *, const T *, T *, T *,\
                                          SolveStatus *, double *, bool, double, int);            \
     template void launch_pcg_spmv<OP, T>(hipStream_t, const OP &, const T *, const T *, T *, T *, \
-                                         SolveStatus *, const double *, int, double *);          \
+                                         SolveStatus *, const double *, int, double *,           \
+                                         const double *, int);                                   \
     template void launch_pcg_update<OP, T>(hipStream_t, const OP &, T *, T *, T *, const T *,    \
                                            const T *, SolveStatus *, const double *, double *,   \
-                                           bool, bool);                                          \
+                                           bool, bool, bool);                                          \
     template void launch_true_residual<OP, T>(hipStream_t, const OP &, const T *, const T *,     \
                                               SolveStatus *, double *);
 INST_OP(K0View, double)
