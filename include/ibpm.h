@@ -207,8 +207,11 @@ int ibpm_get_aggregates(const ibpm_ctx *ctx, int32_t level, int32_t *agg);
 #define IBPM_KERNEL_K0_JACOBI     0   /* damped Jacobi sweep with K, finest AMG level */
 #define IBPM_KERNEL_K0_PCG_SPMV   1   /* p = z + beta p; q = K p; p . q */
 #define IBPM_KERNEL_A_PCG_SPMV    2   /* velocity: p = D^{-1} r + beta p; q = A p; p . q */
-#define IBPM_KERNEL_K0_RESIDUAL   3   /* r = b - K x, finest AMG level */
-#define IBPM_KERNEL_RESTRICT0     4   /* b1 = P0^T r (finest to first coarse level) */
+#define IBPM_KERNEL_K0_RESIDUAL   3   /* r = b - K x, finest AMG level (in the cycle only where
+                                         the restriction does not fold it in) */
+#define IBPM_KERNEL_RESTRICT0     4   /* b1 = P0^T (b - K x) = P0^T b - (P0^T K) x with the
+                                         product formed at setup (finest levels up to 600,000
+                                         unknowns), else b1 = P0^T r */
 #define IBPM_KERNEL_PROLONG0      5   /* x += P0 x1 */
 #define IBPM_KERNEL_PCG_UPDATE_K  6   /* x += a p; r -= a q; r . r */
 #define IBPM_KERNEL_COARSE_CYCLE  7   /* the V-cycle on the small levels as one dense product */

@@ -60,6 +60,7 @@ struct DevLevelT {
     int n = 0;
     double omega = 0;
     DevCSRT<T> A, P, R;
+    DevCSRT<T> RA, AP;                 // fused transfers (nrows 0 where not formed)
     T *wdinv = nullptr;
     T *b = nullptr, *xa = nullptr, *xb = nullptr, *r = nullptr;
     int32_t *agg = nullptr;            // level 0: aggregates (matrix-free prolongation)
@@ -269,8 +270,12 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
             std::swap(a, b);
         }
         cur[0] = a;
-        launch_k0_residual(s, K, r, (const T *)a, l0.r, st);
-        launch_csrv_spmv(s, l0.R.view(), l0.R.lanes, (const T *)l0.r, P.lev[1].b, false, st);
+        if (l0.RA.nrows > 0) {
+            launch_csrv_restrict(s, l0.R.view(), l0.RA.view(), l0.RA.lanes, r, (const T *)a, P.lev[1].b, st);
+        } else {
+            launch_k0_residual(s, K, r, (const T *)a, l0.r, st);
+            launch_csrv_spmv(s, l0.R.view(), l0.R.lanes, (const T *)l0.r, P.lev[1].b, false, st);
+        }
     }
     for (int l = 1; l < P.lc; ++l) {
         DevLevelT<T> &lv = P.lev[l];
@@ -288,8 +293,13 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
             std::swap(a, b);
         }
         cur[l] = a;
-        launch_csrv_residual(s, lv.A.view(), lv.A.lanes, (const T *)lv.b, (const T *)a, lv.r, st);
-        launch_csrv_spmv(s, lv.R.view(), lv.R.lanes, (const T *)lv.r, P.lev[l + 1].b, false, st);
+        if (lv.RA.nrows > 0) {
+            launch_csrv_restrict(s, lv.R.view(), lv.RA.view(), lv.RA.lanes, (const T *)lv.b, (const T *)a,
+                                 P.lev[l + 1].b, st);
+        } else {
+            launch_csrv_residual(s, lv.A.view(), lv.A.lanes, (const T *)lv.b, (const T *)a, lv.r, st);
+            launch_csrv_spmv(s, lv.R.view(), lv.R.lanes, (const T *)lv.r, P.lev[l + 1].b, false, st);
+        }
     }
     launch_coarse_dense(s, P.lev[P.lc].n, (const double *)P.coarseC, (const T *)P.lev[P.lc].b,
                         P.lev[P.lc].xa, st);
@@ -298,8 +308,18 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
         DevLevelT<T> &lv = P.lev[l];
         T *a = cur[l];
         T *b = (a == lv.xa) ? lv.xb : lv.xa;
-        launch_csrv_spmv(s, lv.P.view(), lv.P.lanes, (const T *)cur[l + 1], a, true, st);
-        for (int k = 0; k < post; ++k) {
+        int k = 0;
+        if (lv.AP.nrows > 0) {
+            // prolongation and the first post-sweep in one pass
+            launch_csrv_prolong_jacobi(s, lv.A.view(), lv.AP.view(), lv.P.view(), lv.AP.lanes,
+                                       (const T *)lv.wdinv, (const T *)lv.b, (const T *)a,
+                                       (const T *)cur[l + 1], b, st);
+            std::swap(a, b);
+            k = 1;
+        } else {
+            launch_csrv_spmv(s, lv.P.view(), lv.P.lanes, (const T *)cur[l + 1], a, true, st);
+        }
+        for (; k < post; ++k) {
             launch_csrv_jacobi(s, lv.A.view(), lv.A.lanes, (const T *)lv.wdinv, (const T *)lv.b,
                                (const T *)a, b, st);
             std::swap(a, b);
@@ -1148,6 +1168,38 @@ GridT<T> make_grid(ibpm_ctx *c, const GridMetrics &G) {
     return g;
 }
 
+// First level of the dense coarse cycle: the first level below level 0 with
+// at most kCoarseRows unknowns (the coarsest if none)
+int dense_level(const Hierarchy &h) {
+    const int L = (int)h.levels.size();
+    for (int l = 1; l < L; ++l)
+        if (h.levels[l].A.nrows <= kCoarseRows) return l;
+    return L - 1;
+}
+
+// Where a V-cycle kernel is bound by launch and memory latency rather than
+// by bandwidth, two launches per level are saved with products formed once:
+//   restriction  b_{l+1} = R (b - A x) = R b - (R A) x   (one gather kernel)
+//   prolongation and first post-sweep
+//     x'' = x + P e + W (b - A x - (A P) e)             (one gather kernel)
+// R A is formed on every CSR level, where it holds fewer entries than A, and
+// on level 0 (whose K is applied matrix-free, so R A adds stored entries)
+// only up to kFuseRows0 unknowns; A P adds entries to the sweep and is
+// formed up to kFuseRowsP unknowns.
+constexpr int kFuseRows0 = 600000;
+constexpr int kFuseRowsP = 200000;
+
+void fused_transfer_products(Hierarchy &h) {
+    const int L = (int)h.levels.size();
+    if (L < 2) return;
+    const int lc = dense_level(h);
+    for (int l = 0; l < lc; ++l) {
+        Level &lv = h.levels[l];
+        if (l > 0 || lv.A.nrows <= kFuseRows0) lv.RA = csr_multiply(lv.R, lv.A);
+        if (l > 0 && lv.A.nrows <= kFuseRowsP) lv.AP = csr_multiply(lv.A, lv.P);
+    }
+}
+
 // Upload the hierarchy in precision T (values converted from FP64)
 template <class T>
 void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
@@ -1178,6 +1230,8 @@ void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
             if (l > 0) dl.P = c->upload_csr<T>(hl.P);
             dl.R = c->upload_csr<T>(hl.R);
             dl.r = c->dalloc<T>(dl.n);
+            if (hl.RA.nrows > 0) dl.RA = c->upload_csr<T>(hl.RA);
+            if (hl.AP.nrows > 0) dl.AP = c->upload_csr<T>(hl.AP);
         }
         dl.xa = c->dalloc<T>(dl.n);
         dl.xb = c->dalloc<T>(dl.n);
@@ -1185,12 +1239,7 @@ void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
     // levels from the first with at most kCoarseRows unknowns (never level 0,
     // which is matrix-free) down to the coarsest are applied as one dense
     // product: the cycle there is a fixed linear map, formed once on the host
-    P.lc = L - 1;
-    for (int l = 1; l < L; ++l)
-        if (P.lev[l].n <= kCoarseRows) {
-            P.lc = l;
-            break;
-        }
+    P.lc = dense_level(c->h);
     if (c->coarse_C_lc != P.lc) {
         c->coarse_C = coarse_cycle_matrix(c->h, P.lc, c->prm.amg_pre, c->prm.amg_post);
         c->coarse_C_lc = P.lc;
@@ -1236,6 +1285,7 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
         } catch (const std::runtime_error &e) {
             throw InvalidArg(e.what());
         }
+        fused_transfer_products(c->h);
     }
     const GridMetrics &G = m.g;
     c->g = make_grid<double>(c, G);
@@ -1301,6 +1351,8 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
         for (auto &hl : c->h.levels) {
             hl.P = CSR();
             hl.R = CSR();
+            hl.RA = CSR();
+            hl.AP = CSR();
             hl.wdinv.clear();
         }
     }
@@ -1628,11 +1680,20 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
         case IBPM_KERNEL_RESTRICT0: {
             const DevLevelT<double> &l0 = P.lev[0];
             const CSRView R0 = l0.R.view();
-            const int lanes = l0.R.lanes;
-            const double *r = l0.r;
             double *b1 = P.lev[1].b;
-            launch = [=] { launch_csrv_spmv(s, R0, lanes, r, b1, false, sb); };
-            by = csr_bytes(l0.R, false);
+            if (l0.RA.nrows > 0) {
+                // the residual folded into the restriction: R b - (R A) x
+                const CSRView RA0 = l0.RA.view();
+                const int lanes = l0.RA.lanes;
+                const double *b0 = P.r, *x0 = l0.xa;
+                launch = [=] { launch_csrv_restrict(s, R0, RA0, lanes, b0, x0, b1, sb); };
+                by = csr_bytes(l0.R, false) + csr_bytes(l0.RA, false) - 8.0 * l0.RA.nrows;
+            } else {
+                const int lanes = l0.R.lanes;
+                const double *r = l0.r;
+                launch = [=] { launch_csrv_spmv(s, R0, lanes, r, b1, false, sb); };
+                by = csr_bytes(l0.R, false);
+            }
             break;
         }
         case IBPM_KERNEL_PROLONG0: {

@@ -140,6 +140,15 @@ void launch_pcg_init(hipStream_t s, const Op &op, const T *b, const T *x, T *r, 
 template <class T>
 void launch_pcg_init_zero(hipStream_t s, int n, const T *b, T *x, T *r, SolveStatus *st,
                           double *parts, double rtol2, int maxit);
+// restriction with the residual folded in: bc = R b - (R A) x
+template <class T>
+void launch_csrv_restrict(hipStream_t s, CSRT<T> R, CSRT<T> RA, int lanes, const T *b, const T *x, T *bc,
+                          const SolveStatus *st);
+// prolongation and the first post-sweep: xout = x + P e + W (b - A x - (A P) e)
+template <class T>
+void launch_csrv_prolong_jacobi(hipStream_t s, CSRT<T> A, CSRT<T> AP, CSRT<T> P, int lanes,
+                                const T *wdinv, const T *b, const T *x, const T *e, T *xout,
+                                const SolveStatus *st);
 // the first two damped-Jacobi sweeps from zero on a CSR level in one pass
 template <class T>
 void launch_csrv_presmooth2(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b, T *x,

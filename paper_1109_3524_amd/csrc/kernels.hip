@@ -1272,6 +1272,85 @@ __global__ __launch_bounds__(kBlock) void k_csrv_presmooth2(CSRT<T> A, const T *
     if (lane == 0) x[row] = w * bi + w * (bi - ay);
 }
 
+// Restriction with the residual folded in: b_c = (R b)_c - (R A x)_c, the
+// two rows walked in one loop (L lanes per coarse row; entry k of each row
+// taken by lane k mod L, both matrices' loads of a round issued together)
+template <class T, int L>
+__global__ __launch_bounds__(kBlock) void k_csrv_restrict(CSRT<T> R, CSRT<T> RA, const T *__restrict__ b,
+                                                          const T *__restrict__ x, T *__restrict__ bc,
+                                                          const SolveStatus *st) {
+    if (st->done) return;
+    const int row = remap_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    if (row >= R.nrows) return;
+    const int r0 = R.ptr[row], nr = R.ptr[row + 1] - r0;
+    const int a0 = RA.ptr[row], na = RA.ptr[row + 1] - a0;
+    const int nm = nr > na ? nr : na;
+    T sr = T(0), sa = T(0);
+    for (int k = lane; k < nm; k += L) {
+        // a slot past the end of its row reads entry 0 (every array holds
+        // at least one element) and gathers column 0; its term is dropped
+        const bool hr = k < nr, ha = k < na;
+        const int pr = hr ? r0 + k : 0, pa = ha ? a0 + k : 0;
+        const int cr0 = R.col[pr], ca0 = RA.col[pa];
+        const int cr = hr ? cr0 : 0, ca = ha ? ca0 : 0;
+        const T vr = R.val[pr], va = RA.val[pa];
+        const T xr = b[cr], xa = x[ca];
+        const T tr = sr + vr * xr, ta = sa + va * xa;
+        sr = hr ? tr : sr;
+        sa = ha ? ta : sa;
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) {
+        sr += __shfl_xor(sr, off, L);
+        sa += __shfl_xor(sa, off, L);
+    }
+    if (lane == 0) bc[row] = sr - sa;
+}
+
+// Prolongation and the first post-sweep in one pass:
+// x_out = x + P e + W (b - A x - (A P) e), the three rows walked in one loop
+template <class T, int L>
+__global__ __launch_bounds__(kBlock) void k_csrv_prolong_jacobi(CSRT<T> A, CSRT<T> AP, CSRT<T> P,
+                                                                const T *__restrict__ wdinv,
+                                                                const T *__restrict__ b,
+                                                                const T *__restrict__ x,
+                                                                const T *__restrict__ e,
+                                                                T *__restrict__ xout,
+                                                                const SolveStatus *st) {
+    if (st->done) return;
+    const int row = remap_block(blockIdx.x, gridDim.x) * (kBlock / L) + threadIdx.x / L;
+    const int lane = threadIdx.x % L;
+    if (row >= A.nrows) return;
+    const T xr = x[row], wr = wdinv[row], br = b[row];
+    const int a0 = A.ptr[row], na = A.ptr[row + 1] - a0;
+    const int q0 = AP.ptr[row], nq = AP.ptr[row + 1] - q0;
+    const int p0 = P.ptr[row], np = P.ptr[row + 1] - p0;
+    int nm = na > nq ? na : nq;
+    nm = nm > np ? nm : np;
+    T sa = T(0), sq = T(0), sp = T(0);
+    for (int k = lane; k < nm; k += L) {
+        // slots past the end of a row: entry 0 and column 0, term dropped
+        const bool ha = k < na, hq = k < nq, hp = k < np;
+        const int pa = ha ? a0 + k : 0, pq = hq ? q0 + k : 0, pp = hp ? p0 + k : 0;
+        const int ca0 = A.col[pa], cq0 = AP.col[pq], cp0 = P.col[pp];
+        const int ca = ha ? ca0 : 0, cq = hq ? cq0 : 0, cp = hp ? cp0 : 0;
+        const T va = A.val[pa], vq = AP.val[pq], vp = P.val[pp];
+        const T xa = x[ca], eq = e[cq], ep = e[cp];
+        const T ta = sa + va * xa, tq = sq + vq * eq, tp = sp + vp * ep;
+        sa = ha ? ta : sa;
+        sq = hq ? tq : sq;
+        sp = hp ? tp : sp;
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) {
+        sa += __shfl_xor(sa, off, L);
+        sq += __shfl_xor(sq, off, L);
+        sp += __shfl_xor(sp, off, L);
+    }
+    if (lane == 0) xout[row] = (xr + sp) + wr * ((br - sa) - sq);
+}
+
 // ---------------------------------------------------------------------------
 // the coarse part of the cycle as one dense matrix
 
@@ -1876,6 +1955,19 @@ static void csrv_dispatch_spmv(hipStream_t s, CSRT<T> A, const T *x, T *y, int a
     }
 
 template <class T, int L>
+static void csrv_dispatch_restrict(hipStream_t s, CSRT<T> R, CSRT<T> RA, const T *b, const T *x, T *bc,
+                                   const SolveStatus *st) {
+    int nb = (R.nrows + kBlock / L - 1) / (kBlock / L);
+    LAUNCH((k_csrv_restrict<T, L>), nb > 0 ? nb : 1, R, RA, b, x, bc, st);
+}
+template <class T, int L>
+static void csrv_dispatch_prolong_jacobi(hipStream_t s, CSRT<T> A, CSRT<T> AP, CSRT<T> P, const T *wdinv,
+                                         const T *b, const T *x, const T *e, T *xout,
+                                         const SolveStatus *st) {
+    int nb = (A.nrows + kBlock / L - 1) / (kBlock / L);
+    LAUNCH((k_csrv_prolong_jacobi<T, L>), nb > 0 ? nb : 1, A, AP, P, wdinv, b, x, e, xout, st);
+}
+template <class T, int L>
 static void csrv_dispatch_presmooth2(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b, T *x,
                                      const SolveStatus *st) {
     int nb = (A.nrows + kBlock / L - 1) / (kBlock / L);
@@ -1885,6 +1977,20 @@ template <class T>
 void launch_csrv_presmooth2(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b, T *x,
                             const SolveStatus *st) {
     CSRV_SWITCH(csrv_dispatch_presmooth2, A, wdinv, b, x, st)
+}
+template <class T>
+void launch_csrv_restrict(hipStream_t s, CSRT<T> R, CSRT<T> RA, int lanes, const T *b, const T *x, T *bc,
+                          const SolveStatus *st) {
+    if (R.nrows != RA.nrows) throw std::runtime_error("fused restriction: R and R A differ in rows");
+    CSRV_SWITCH(csrv_dispatch_restrict, R, RA, b, x, bc, st)
+}
+template <class T>
+void launch_csrv_prolong_jacobi(hipStream_t s, CSRT<T> A, CSRT<T> AP, CSRT<T> P, int lanes,
+                                const T *wdinv, const T *b, const T *x, const T *e, T *xout,
+                                const SolveStatus *st) {
+    if (A.nrows != AP.nrows || A.nrows != P.nrows || AP.ncols != P.ncols)
+        throw std::runtime_error("fused prolongation: A, A P and P do not match");
+    CSRV_SWITCH(csrv_dispatch_prolong_jacobi, A, AP, P, wdinv, b, x, e, xout, st)
 }
 template <class T>
 void launch_csrv_jacobi(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b,
@@ -2069,6 +2175,11 @@ INST_T(float)
                                           const SolveStatus *);                                  \
     template void launch_csrv_spmv<T>(hipStream_t, CSRT<T>, int, const T *, T *, bool,           \
                                       const SolveStatus *);                                      \
+    template void launch_csrv_restrict<T>(hipStream_t, CSRT<T>, CSRT<T>, int, const T *, const T *, \
+                                          T *, const SolveStatus *);                             \
+    template void launch_csrv_prolong_jacobi<T>(hipStream_t, CSRT<T>, CSRT<T>, CSRT<T>, int,      \
+                                                const T *, const T *, const T *, const T *, T *,  \
+                                                const SolveStatus *);                             \
     template void launch_coarse_dense<T>(hipStream_t, int, const double *, const T *, T *,        \
                                          const SolveStatus *);
 INST_V(double)

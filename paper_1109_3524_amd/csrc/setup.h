@@ -59,6 +59,9 @@ struct Level {
     std::vector<double> wdinv;       // omega / a_ii
     double omega = 0;
     CSR P, R;                        // prolongator to this level from the next, and P^T
+    CSR RA, AP;                      // R A and A P where the device fuses the
+                                     // residual into the restriction and the
+                                     // prolongation into the first post-sweep
     std::vector<int32_t> agg;
     double pomega = 0;               // P = (I - pomega D^-1 A) T (T: aggregates)
 };
