@@ -76,6 +76,7 @@ struct PrecSet {
     int lc = 1;                        // first level of the dense coarse cycle
     // PCG work vectors (n_lambda)
     T *r = nullptr, *z = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
+    T *r2 = nullptr;                   // second residual (the update folded into the cycle)
 };
 
 // The residual-to-correction network (weights, Adam moments, activations)
@@ -242,13 +243,30 @@ int guarded(ibpm_ctx *c, F &&f) {
 // post-smoothing sweep forms r . z.  Levels lc.. run in one work-group.
 // Every kernel is predicated on st->done.
 
+// A PCG update left for the preconditioner's first kernel to apply:
+// alpha = st->rz_next / (p . q) with p . q summed from pq_parts, x += alpha p,
+// r_out = r_in - alpha q (the residual the preconditioner is applied to)
+template <class T>
+struct UpdArgs {
+    T *x;
+    const T *r_in;
+    T *r_out;
+    const T *p, *q;
+    const double *pq_parts;
+};
+
+// With u, the cycle starts with the update (folded into the first two
+// pre-smoothing sweeps) and is applied to u->r_out; the partials of the new
+// r . r go to c->parts3 (one per block of the level-0 walker grid).
 template <class T>
 void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *st,
-                    bool with_rz = true) {
+                    bool with_rz = true, const UpdArgs<T> *u = nullptr) {
     hipStream_t s = c->stream;
     const int pre = c->prm.amg_pre, post = c->prm.amg_post;
     const int L = (int)P.lev.size();
     const K0T<T> &K = P.K0;
+    if (u && (L == 1 || pre < 2)) throw std::runtime_error("V-cycle: the update folds into two pre-sweeps only");
+    if (u) r = u->r_out;
     if (L == 1) {
         launch_dense_solve(s, K.n, c->coarse_inv, r, z, st);
         if (with_rz) c->rz_G = launch_dot_rz_parts(s, K.n, r, z, st, c->parts);
@@ -259,7 +277,11 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
         DevLevelT<T> &l0 = P.lev[0];
         T *a = l0.xa, *b = l0.xb;
         int k = 1;
-        if (pre >= 2) {
+        if (u) {
+            launch_k0_update_presmooth2(s, K, (const T *)l0.wdinv, u->x, u->r_in, u->r_out, u->p, u->q, a, st,
+                                        u->pq_parts, c->parts3);
+            k = 2;
+        } else if (pre >= 2) {
             launch_k0_presmooth2(s, K, (const T *)l0.wdinv, r, a, st);
             k = 2;
         } else {
@@ -340,6 +362,17 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
     }
 }
 
+// A preconditioner that can start with the pending PCG update (see
+// UpdArgs): fn(u, z) queues the update and z = M u.r_out; r2 is the second
+// residual buffer; G_pq and G_rr are the partial counts of the product and
+// of the folded update (both at most kFuseMaxParts for it to be used).
+template <class T>
+struct FusedPre {
+    std::function<void(const UpdArgs<T> &, T *)> fn;
+    T *r2;
+    int G_pq, G_rr;
+};
+
 // Generic PCG driver.  Iterations are queued in chunks; every kernel of an
 // iteration is predicated on the device status, so iterations queued past
 // convergence do nothing.  The chunk length is estimated from the observed
@@ -349,7 +382,8 @@ template <class Op, class T>
 int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
               const std::function<void(const T *, T *)> &precond, const T *b, T *x, T *r, T *z,
               T **p, T *q, SolveStatus *st, double rtol, int maxit, int &est, bool zero_guess,
-              bool true_residual, ibpm_solve_stats *out, int graph_slot = -1) {
+              bool true_residual, ibpm_solve_stats *out, int graph_slot = -1,
+              const FusedPre<T> *fpre = nullptr) {
     hipStream_t s = c->stream;
     auto t0 = std::chrono::steady_clock::now();
     if (zero_guess) launch_pcg_init_zero(s, n, b, x, r, st, c->parts, rtol * rtol, maxit);
@@ -361,8 +395,12 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
     // launch per iteration): the update leaves its r . r partials in parts3
     // and the preconditioner runs once more after the converged update, on
     // a residual no later kernel uses.
-    const int G_rr = update_blocks_of(n);
-    const bool defer = !jacobi && c->rz_G <= kFuseMaxParts && G_rr <= kFuseMaxParts;
+    const bool defer = !jacobi && c->rz_G <= kFuseMaxParts && update_blocks_of(n) <= kFuseMaxParts;
+    // With a preconditioner that starts with the update, the update kernel
+    // goes too: the residual then alternates between r and fpre->r2
+    const bool fuse = defer && fpre && fpre->G_pq <= kFuseMaxParts && fpre->G_rr <= kFuseMaxParts;
+    const int G_rr = fuse ? fpre->G_rr : update_blocks_of(n);
+    T *rcur = r, *rnext = fuse ? fpre->r2 : nullptr;
     auto iteration = [&]() {
         // with the V-cycle the product sums its r . z partials (in parts)
         launch_pcg_spmv(s, op, (const T *)z, (const T *)p[curp], p[1 - curp], q, st,
@@ -370,9 +408,17 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
                         c->parts2, defer ? (const double *)c->parts3 : (const double *)nullptr,
                         defer ? G_rr : 0);
         curp = 1 - curp;
-        launch_pcg_update(s, op, x, r, z, (const T *)p[curp], (const T *)q, st,
-                          (const double *)c->parts2, defer ? c->parts3 : c->parts, jacobi, !jacobi, defer);
-        if (!jacobi) precond(r, z);
+        if (fuse) {
+            const UpdArgs<T> u{x, (const T *)rcur, rnext, (const T *)p[curp], (const T *)q,
+                               (const double *)c->parts2};
+            fpre->fn(u, z);
+            std::swap(rcur, rnext);
+        } else {
+            launch_pcg_update(s, op, x, rcur, z, (const T *)p[curp], (const T *)q, st,
+                              (const double *)c->parts2, defer ? c->parts3 : c->parts, jacobi, !jacobi,
+                              defer);
+            if (!jacobi) precond(rcur, z);
+        }
     };
     // the iterations are identical launches (the two direction buffers swap
     // every iteration), so a graph of two of them is replayed
@@ -381,7 +427,7 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
         ibpm_ctx::IterGraph &G = c->graphs[graph_slot];
         std::vector<const void *> key = {&op, b, x, r, z, p[0], p[1], q, st,
                                          (const void *)(intptr_t)jacobi,
-                                         (const void *)(intptr_t)c->rz_G};
+                                         (const void *)(intptr_t)c->rz_G, rnext};
         if (!G.exec || G.key != key) {
             if (G.exec) (void)hipGraphExecDestroy(G.exec);
             G.exec = nullptr;
@@ -482,9 +528,14 @@ int solve_poisson_fp64(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_s
     std::function<void(const double *, double *)> pre = [c](const double *r, double *z) {
         enqueue_vcycle(c, c->p64, r, z, c->st_poi);
     };
+    FusedPre<double> fpre{[c](const UpdArgs<double> &u, double *z) {
+                              enqueue_vcycle(c, c->p64, (const double *)u.r_out, z, c->st_poi, true, &u);
+                          },
+                          P.r2, walk_blocks_of(P.K0), walk_blocks_of(P.K0)};
+    const bool can_fuse = !jacobi && P.lev.size() > 1 && c->prm.amg_pre >= 2;
     return pcg_drive<K0View, double>(c, P.K0, P.K0.n, jacobi, pre, rhs, lam, P.r, P.z, P.p, P.q,
                                      c->st_poi, c->prm.poisson_rtol, c->prm.poisson_maxit,
-                                     c->est_poi, false, true, out, 1);
+                                     c->est_poi, false, true, out, 1, can_fuse ? &fpre : nullptr);
 }
 
 // Mixed precision: FP64 iterative refinement around an FP32 AMG-PCG.  The
@@ -521,6 +572,11 @@ int solve_poisson_mixed(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_
     std::function<void(const float *, float *)> pre = [c](const float *r, float *z) {
         enqueue_vcycle(c, c->p32, r, z, c->st_poi);
     };
+    FusedPre<float> fpre{[c](const UpdArgs<float> &u, float *z) {
+                             enqueue_vcycle(c, c->p32, (const float *)u.r_out, z, c->st_poi, true, &u);
+                         },
+                         P.r2, walk_blocks_of(K), walk_blocks_of(K)};
+    const bool can_fuse = P.lev.size() > 1 && c->prm.amg_pre >= 2;
     if (bb == 0.0) {
         HIPCHECK(hipMemsetAsync(lam, 0, n * sizeof(double), s));
         rr = 0.0;
@@ -553,7 +609,8 @@ int solve_poisson_mixed(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_
             ibpm_solve_stats is{};
             int rc = pcg_drive<K0T<float>, float>(c, P.K0, n, false, pre, c->rin32, c->d32, P.r,
                                                   P.z, P.p, P.q, c->st_poi, tol_in, maxit_in,
-                                                  c->est_inner[std::min(outer, 31)], true, false, &is, 2);
+                                                  c->est_inner[std::min(outer, 31)], true, false, &is, 2,
+                                                  can_fuse ? &fpre : nullptr);
             inner_total += is.iters;
             if (rc == IBPM_ENAN) {
                 code = IBPM_ENAN;
@@ -1255,6 +1312,7 @@ void alloc_pcg(ibpm_ctx *c, PrecSet<T> &P, int n) {
     P.p[0] = c->dalloc<T>(n);
     P.p[1] = c->dalloc<T>(n);
     P.q = c->dalloc<T>(n);
+    P.r2 = c->dalloc<T>(n);
     for (T *v : {P.p[0], P.p[1]}) HIPCHECK(hipMemsetAsync(v, 0, n * sizeof(T), c->stream));
 }
 

@@ -206,6 +206,15 @@ void launch_k0_prolong_mf(hipStream_t s, const K0T<T> &K, const int *agg, const 
 template <class T>
 void launch_k0_wdinv(hipStream_t s, const K0T<T> &K, double omega, T *wd);
 // two damped-Jacobi sweeps from x = 0 in one pass: x = y + wd (b - K y), y = wd b
+// the PCG update (alpha = st->rz_next / p.q, p.q summed from the product's
+// partials) and the first two pre-smoothing sweeps on level 0 in one pass:
+// b = r_in - alpha q to r_out, x += alpha p, xs = the two sweeps from zero
+// for b; partials of b.b in parts (the deferred stop test), block 0 counts
+// the iteration.  Returns the number of partials.
+template <class T>
+int launch_k0_update_presmooth2(hipStream_t s, const K0T<T> &K, const T *wd, T *x, const T *rin, T *rout,
+                                const T *p, const T *q, T *xs, SolveStatus *st, const double *pq_parts,
+                                double *parts);
 template <class T>
 void launch_k0_presmooth2(hipStream_t s, const K0T<T> &K, const T *wd, const T *b, T *x,
                           const SolveStatus *st);

@@ -767,6 +767,42 @@ __global__ __launch_bounds__(kBlock) void k_k0_presmooth2(K0T<T> K, const T *__r
     });
 }
 
+// The PCG update and the first two pre-smoothing sweeps of the V-cycle in
+// one pass.  alpha = rz_next / (p . q), p . q summed from the product's
+// partials; the new residual b = r_in - alpha q is formed wherever the sweep
+// needs it and written to r_out (r_in stays intact: other blocks still read
+// it), x += alpha p, xs = y + wd (b - K y) with y = wd b.  Partials of b . b
+// go to parts (the next product takes the stop test), and block 0 counts
+// the iteration and moves rz_next to rz (no block here reads those fields).
+template <int R, class T>
+__global__ __launch_bounds__(kBlock) void k_k0_update_presmooth2(
+    K0T<T> K, const T *__restrict__ wd, T *__restrict__ x, const T *__restrict__ rin, T *__restrict__ rout,
+    const T *__restrict__ p, const T *__restrict__ q, T *__restrict__ xs, SolveStatus *st,
+    const double *__restrict__ pq_parts, int G_pq, double *__restrict__ parts) {
+    if (st->done) return;
+    const double rz = st->rz_next;
+    double a[1] = {0.0};
+    gather_parts<1>(pq_parts, G_pq, 1, a);
+    block_sum<1>(a);
+    const double pq = a[0];
+    const T alpha = (T)(rz / pq);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->pq = pq;
+        st->iter += 1;
+        st->rz = rz;
+        st->first = 0;
+    }
+    double v[1] = {0.0};
+    k0_walk<R>(K, [&](int c) { return wd[c] * (rin[c] - alpha * q[c]); }, [&](int row, T ky, T, T yr) {
+        const T bi = rin[row] - alpha * q[row];
+        xs[row] = yr + wd[row] * (bi - ky);
+        rout[row] = bi;
+        x[row] += alpha * p[row];
+        v[0] += (double)bi * (double)bi;
+    });
+    write_parts2<1>(v, parts);
+}
+
 template <int R, class T>
 __global__ __launch_bounds__(kBlock) void k_k0_jacobi(K0T<T> K, T omega, const T *__restrict__ b, const T *__restrict__ xin,
                                                       T *__restrict__ xout, const SolveStatus *st) {
@@ -1855,6 +1891,21 @@ void launch_k0_wdinv(hipStream_t s, const K0T<T> &K, double omega, T *wd) {
 }
 
 template <class T>
+int launch_k0_update_presmooth2(hipStream_t s, const K0T<T> &K, const T *wd, T *x, const T *rin, T *rout,
+                                const T *p, const T *q, T *xs, SolveStatus *st, const double *pq_parts,
+                                double *parts) {
+    if (rin == rout || pq_parts == parts) throw std::runtime_error("update + pre-smoothing: buffers must differ");
+    const int G_pq = walk_grid_blocks(K);
+    if (G_pq > kFuseMaxParts) throw std::runtime_error("update + pre-smoothing: too many product partials");
+    int G = 0;
+    WALK_SWITCH(pick_R(K), {
+        dim3 gd = op_grid<RR>(K);
+        G = gd.x * gd.y;
+        LAUNCH2((k_k0_update_presmooth2<RR, T>), gd, K, wd, x, rin, rout, p, q, xs, st, pq_parts, G_pq, parts);
+    })
+    return G;
+}
+template <class T>
 void launch_k0_presmooth2(hipStream_t s, const K0T<T> &K, const T *wd, const T *b, T *x,
                           const SolveStatus *st) {
     WALK_SWITCH(pick_R(K), LAUNCH2((k_k0_presmooth2<RR, T>), op_grid<RR>(K), K, wd, b, x, st))
@@ -2146,6 +2197,9 @@ INST_OP(K0T<float>, float)
                                           double, T *, const SolveStatus *);                      \
     template void launch_k0_presmooth2<T>(hipStream_t, const K0T<T> &, const T *, const T *, T *,  \
                                           const SolveStatus *);                                   \
+    template int launch_k0_update_presmooth2<T>(hipStream_t, const K0T<T> &, const T *, T *,       \
+                                                const T *, T *, const T *, const T *, T *,          \
+                                                SolveStatus *, const double *, double *);           \
     template void launch_k0_jacobi_first<T>(hipStream_t, const K0T<T> &, double, const T *, T *, \
                                             const SolveStatus *);                                \
     template void launch_k0_jacobi<T>(hipStream_t, const K0T<T> &, double, const T *, const T *, \
