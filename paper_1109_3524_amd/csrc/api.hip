@@ -10,6 +10,7 @@
 #include <new>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ibpm.h"
@@ -255,18 +256,34 @@ struct UpdArgs {
     const double *pq_parts;
 };
 
+// An FP32 cycle inside FP64 CG: the residual r64 (FP64) and its FP32 copy
+// r32, the FP64 result z64; u, when given, is the FP64 update folded into
+// the first pass (which then writes r32).
+struct MixedIO {
+    const UpdArgs<double> *u;
+    const double *r64;
+    double *z64;
+    float *r32;
+};
+
 // With u, the cycle starts with the update (folded into the first two
 // pre-smoothing sweeps) and is applied to u->r_out; the partials of the new
-// r . r go to c->parts3 (one per block of the level-0 walker grid).
+// r . r go to c->parts3 (one per block of the level-0 walker grid).  With mx
+// (an FP32 cycle) the last sweep writes mx->z64 and the partials of
+// r64 . z64 instead of z.
 template <class T>
 void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *st,
-                    bool with_rz = true, const UpdArgs<T> *u = nullptr) {
+                    bool with_rz = true, const UpdArgs<T> *u = nullptr, const MixedIO *mx = nullptr) {
     hipStream_t s = c->stream;
     const int pre = c->prm.amg_pre, post = c->prm.amg_post;
     const int L = (int)P.lev.size();
     const K0T<T> &K = P.K0;
-    if (u && (L == 1 || pre < 2)) throw std::runtime_error("V-cycle: the update folds into two pre-sweeps only");
+    constexpr bool f32 = std::is_same<T, float>::value;
+    if ((u || (mx && mx->u)) && (L == 1 || pre < 2))
+        throw std::runtime_error("V-cycle: the update folds into two pre-sweeps only");
+    if (mx && (!f32 || u || L == 1)) throw std::runtime_error("V-cycle: bad mixed-precision request");
     if (u) r = u->r_out;
+    if (mx && mx->u) r = (const T *)mx->r32;
     if (L == 1) {
         launch_dense_solve(s, K.n, c->coarse_inv, r, z, st);
         if (with_rz) c->rz_G = launch_dot_rz_parts(s, K.n, r, z, st, c->parts);
@@ -280,6 +297,13 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
         if (u) {
             launch_k0_update_presmooth2(s, K, (const T *)l0.wdinv, u->x, u->r_in, u->r_out, u->p, u->q, a, st,
                                         u->pq_parts, c->parts3);
+            k = 2;
+        } else if (mx && mx->u) {
+            if constexpr (f32) {
+                const UpdArgs<double> *v = mx->u;
+                launch_k0_update_presmooth2_mixed(s, K, (const float *)l0.wdinv, v->x, v->r_in, v->r_out, v->p,
+                                                  v->q, a, mx->r32, st, v->pq_parts, c->parts3);
+            }
             k = 2;
         } else if (pre >= 2) {
             launch_k0_presmooth2(s, K, (const T *)l0.wdinv, r, a, st);
@@ -357,8 +381,15 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
             launch_k0_jacobi(s, K, l0.omega, r, (const T *)a, b, st);
             std::swap(a, b);
         }
-        if (with_rz) c->rz_G = launch_k0_jacobi_rz(s, K, l0.omega, r, (const T *)a, z, st, c->parts);
-        else launch_k0_jacobi(s, K, l0.omega, r, (const T *)a, z, st);
+        if (mx) {
+            if constexpr (f32)
+                c->rz_G = launch_k0_jacobi_widen_rz(s, K, l0.omega, r, (const float *)a, mx->z64, mx->r64, st,
+                                                    c->parts);
+        } else if (with_rz) {
+            c->rz_G = launch_k0_jacobi_rz(s, K, l0.omega, r, (const T *)a, z, st, c->parts);
+        } else {
+            launch_k0_jacobi(s, K, l0.omega, r, (const T *)a, z, st);
+        }
     }
 }
 
@@ -1049,15 +1080,24 @@ int solve_poisson_learned(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solv
 int solve_poisson_mixed_precond(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
     PrecSet<double> &P = c->p64;
     const int n = P.K0.n;
+    // the residual goes to FP32 on entry to the cycle and the cycle's result
+    // back to FP64 in its last sweep (with r . z); in the iterations the
+    // FP64 update is folded into the FP32 first pass
     std::function<void(const double *, double *)> pre = [c, n](const double *r, double *z) {
-        hipStream_t s = c->stream;
-        launch_to_f32(s, n, r, c->rin32, c->st_poi);
-        enqueue_vcycle(c, c->p32, (const float *)c->rin32, c->d32, c->st_poi, false);
-        c->rz_G = launch_widen_dot(s, n, (const float *)c->d32, z, r, c->st_poi, c->parts);
+        launch_to_f32(c->stream, n, r, c->rin32, c->st_poi);
+        const MixedIO mx{nullptr, r, z, c->rin32};
+        enqueue_vcycle(c, c->p32, (const float *)c->rin32, c->d32, c->st_poi, false, (const UpdArgs<float> *)nullptr, &mx);
     };
+    FusedPre<double> fpre{[c](const UpdArgs<double> &u, double *z) {
+                              const MixedIO mx{&u, u.r_out, z, c->rin32};
+                              enqueue_vcycle(c, c->p32, (const float *)c->rin32, c->d32, c->st_poi, false,
+                                             (const UpdArgs<float> *)nullptr, &mx);
+                          },
+                          P.r2, walk_blocks_of(P.K0), walk_blocks_of(P.K0)};
+    const bool can_fuse = c->p32.lev.size() > 1 && c->prm.amg_pre >= 2;
     return pcg_drive<K0View, double>(c, P.K0, n, false, pre, rhs, lam, P.r, P.z, P.p, P.q,
                                      c->st_poi, c->prm.poisson_rtol, c->prm.poisson_maxit,
-                                     c->est_poi, false, true, out, 1);
+                                     c->est_poi, false, true, out, 1, can_fuse ? &fpre : nullptr);
 }
 
 int solve_poisson_impl(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {

@@ -206,6 +206,18 @@ void launch_k0_prolong_mf(hipStream_t s, const K0T<T> &K, const int *agg, const 
 template <class T>
 void launch_k0_wdinv(hipStream_t s, const K0T<T> &K, double omega, T *wd);
 // two damped-Jacobi sweeps from x = 0 in one pass: x = y + wd (b - K y), y = wd b
+// FP64 CG around an FP32 V-cycle: the FP64 update folded into the FP32
+// first pass (b = r_in - alpha q in FP64 to r_out, x += alpha p, FP32(b) to
+// r32, the two FP32 sweeps from zero to xs; partials of b.b), and the last
+// FP32 post-sweep with its result widened to z64 and the partials of
+// r64 . z64.  Both return the number of partials.
+int launch_k0_update_presmooth2_mixed(hipStream_t s, const K0T<float> &K, const float *wd, double *x,
+                                      const double *rin, double *rout, const double *p, const double *q,
+                                      float *xs, float *r32, SolveStatus *st, const double *pq_parts,
+                                      double *parts);
+int launch_k0_jacobi_widen_rz(hipStream_t s, const K0T<float> &K, double omega, const float *b,
+                              const float *xin, double *z64, const double *r64, const SolveStatus *st,
+                              double *parts);
 // the PCG update (alpha = st->rz_next / p.q, p.q summed from the product's
 // partials) and the first two pre-smoothing sweeps on level 0 in one pass:
 // b = r_in - alpha q to r_out, x += alpha p, xs = the two sweeps from zero

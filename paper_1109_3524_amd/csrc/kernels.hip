@@ -803,6 +803,65 @@ __global__ __launch_bounds__(kBlock) void k_k0_update_presmooth2(
     write_parts2<1>(v, parts);
 }
 
+// FP64 CG with an FP32 V-cycle: the FP64 update folded into the FP32 first
+// pass.  b = r_in - alpha q in FP64 (to r_out, with x += alpha p and the
+// partials of b . b), its FP32 rounding to r32, and the two FP32 sweeps
+// from zero for it: exactly the rounding of b to FP32 followed by the FP32
+// pass.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_k0_update_presmooth2_mixed(
+    K0T<float> K, const float *__restrict__ wd, double *__restrict__ x, const double *__restrict__ rin,
+    double *__restrict__ rout, const double *__restrict__ p, const double *__restrict__ q,
+    float *__restrict__ xs, float *__restrict__ r32, SolveStatus *st, const double *__restrict__ pq_parts,
+    int G_pq, double *__restrict__ parts) {
+    if (st->done) return;
+    const double rz = st->rz_next;
+    double a[1] = {0.0};
+    gather_parts<1>(pq_parts, G_pq, 1, a);
+    block_sum<1>(a);
+    const double pq = a[0];
+    const double alpha = rz / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->pq = pq;
+        st->iter += 1;
+        st->rz = rz;
+        st->first = 0;
+    }
+    double v[1] = {0.0};
+    k0_walk<R>(K, [&](int c) { return wd[c] * (float)(rin[c] - alpha * q[c]); },
+               [&](int row, float ky, float, float yr) {
+                   const double bi = rin[row] - alpha * q[row];
+                   const float bf = (float)bi;
+                   xs[row] = yr + wd[row] * (bf - ky);
+                   r32[row] = bf;
+                   rout[row] = bi;
+                   x[row] += alpha * p[row];
+                   v[0] += bi * bi;
+               });
+    write_parts2<1>(v, parts);
+}
+
+// The last FP32 post-sweep of that cycle with its result widened: z64 =
+// FP64(x + omega/d (b - K x)), and the partials of r64 . z64 (the FP64
+// residual), as the FP32 sweep followed by the widening would give.
+template <int R>
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi_widen_rz(K0T<float> K, float omega,
+                                                               const float *__restrict__ b,
+                                                               const float *__restrict__ xin,
+                                                               double *__restrict__ z64,
+                                                               const double *__restrict__ r64,
+                                                               const SolveStatus *st, double *parts) {
+    if (st->done) return;
+    double v[1] = {0.0};
+    k0_walk<R>(K, [&](int c) { return xin[c]; }, [&](int row, float ax, float d, float xr) {
+        const float z = xr + omega / d * (b[row] - ax);
+        const double zd = (double)z;
+        z64[row] = zd;
+        v[0] += r64[row] * zd;
+    });
+    write_parts2<1>(v, parts);
+}
+
 template <int R, class T>
 __global__ __launch_bounds__(kBlock) void k_k0_jacobi(K0T<T> K, T omega, const T *__restrict__ b, const T *__restrict__ xin,
                                                       T *__restrict__ xout, const SolveStatus *st) {
@@ -1888,6 +1947,35 @@ void launch_k0_prolong_mf(hipStream_t s, const K0T<T> &K, const int *agg, const 
 template <class T>
 void launch_k0_wdinv(hipStream_t s, const K0T<T> &K, double omega, T *wd) {
     LAUNCH((k_k0_wdinv<T>), (K.n + kBlock - 1) / kBlock, K, (T)omega, wd);
+}
+
+int launch_k0_update_presmooth2_mixed(hipStream_t s, const K0T<float> &K, const float *wd, double *x,
+                                      const double *rin, double *rout, const double *p, const double *q,
+                                      float *xs, float *r32, SolveStatus *st, const double *pq_parts,
+                                      double *parts) {
+    if (rin == rout || pq_parts == parts) throw std::runtime_error("update + pre-smoothing: buffers must differ");
+    const int G_pq = walk_grid_blocks(K);
+    if (G_pq > kFuseMaxParts) throw std::runtime_error("update + pre-smoothing: too many product partials");
+    int G = 0;
+    WALK_SWITCH(pick_R(K), {
+        dim3 gd = op_grid<RR>(K);
+        G = gd.x * gd.y;
+        LAUNCH2((k_k0_update_presmooth2_mixed<RR>), gd, K, wd, x, rin, rout, p, q, xs, r32, st, pq_parts,
+                G_pq, parts);
+    })
+    return G;
+}
+
+int launch_k0_jacobi_widen_rz(hipStream_t s, const K0T<float> &K, double omega, const float *b,
+                              const float *xin, double *z64, const double *r64, const SolveStatus *st,
+                              double *parts) {
+    int G = 0;
+    WALK_SWITCH(pick_R(K), {
+        dim3 gd = op_grid<RR>(K);
+        G = gd.x * gd.y;
+        LAUNCH2((k_k0_jacobi_widen_rz<RR>), gd, K, (float)omega, b, xin, z64, r64, st, parts);
+    })
+    return G;
 }
 
 template <class T>
