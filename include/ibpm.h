@@ -92,6 +92,12 @@ typedef struct ibpm_params {
     int32_t use_graphs;          /* 1: replay the launches of CG iterations as HIP graphs
                                     (recorded once per solve kind and operand set on a
                                     stream of the context's own); 0: launch them one by one */
+    int32_t fuse_transfers;      /* 1: the V-cycle folds the residual into the restriction
+                                    (R b - (R A) x) on every CSR level and on a finest level of
+                                    at most 600,000 unknowns, and the prolongation into the
+                                    first post-sweep on CSR levels of at most 200,000 unknowns,
+                                    with R A and A P formed at build time; 0: separate kernels
+                                    (the same V-cycle, other rounding) */
 } ibpm_params;
 
 typedef struct ibpm_solve_stats {

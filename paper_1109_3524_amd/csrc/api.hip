@@ -1148,6 +1148,7 @@ void check_params(const ibpm_params *p) {
     if (!(p->inner_rtol >= 0) || p->inner_rtol >= 1) throw InvalidArg("inner_rtol must be in [0, 1)");
     if (p->learned_every < 0) throw InvalidArg("learned_every must be >= 0");
     if (p->fcg_depth < 0 || p->fcg_depth > kFcgMax) throw InvalidArg("fcg_depth must be in [0, 8]");
+    if (p->fuse_transfers != 0 && p->fuse_transfers != 1) throw InvalidArg("fuse_transfers must be 0 or 1");
     if (p->poisson_solver != IBPM_SOLVER_JACOBI_PCG) {
         if (p->amg_pre < 1 || p->amg_post < 1) throw InvalidArg("AMG needs >= 1 pre and post sweep");
         if (p->amg_coarse_max < 1 || p->amg_max_levels < 1) throw InvalidArg("bad AMG limits");
@@ -1383,7 +1384,7 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
         } catch (const std::runtime_error &e) {
             throw InvalidArg(e.what());
         }
-        fused_transfer_products(c->h);
+        if (p->fuse_transfers) fused_transfer_products(c->h);
     }
     const GridMetrics &G = m.g;
     c->g = make_grid<double>(c, G);

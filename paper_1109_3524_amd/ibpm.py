@@ -71,6 +71,7 @@ class Params(ctypes.Structure):
         ("amg_coarse_max", ctypes.c_int32), ("amg_max_levels", ctypes.c_int32),
         ("inner_rtol", ctypes.c_double), ("learned_every", ctypes.c_int32),
         ("fcg_depth", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
+        ("fuse_transfers", ctypes.c_int32),
     ]
 
 
@@ -161,7 +162,8 @@ def params_from_workload(wl: W.Workload, **over) -> dict:
              poisson_solver=wl.poisson_solver, poisson_rtol=wl.poisson_rtol,
              poisson_maxit=wl.poisson_maxit, amg_theta=wl.amg_theta, amg_pre=wl.amg_pre,
              amg_post=wl.amg_post, amg_coarse_max=wl.amg_coarse_max,
-             amg_max_levels=wl.amg_max_levels, inner_rtol=0.0, learned_every=1, fcg_depth=0, use_graphs=1)
+             amg_max_levels=wl.amg_max_levels, inner_rtol=0.0, learned_every=1, fcg_depth=0, use_graphs=1,
+             fuse_transfers=1)
     p.update(over)
     return p
 

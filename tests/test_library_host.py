@@ -65,6 +65,7 @@ def _params(wl, **over):
     (dict(poisson_solver=6), "solver"),
     (dict(poisson_solver=4, inner_rtol=1.5), "inner_rtol"),
     (dict(poisson_solver=2, inner_rtol=-1e-3), "inner_rtol"),
+    (dict(fuse_transfers=2), "fuse_transfers"),
 ])
 def test_invalid_parameters_are_rejected_on_the_host(over, msg):
     L = ibpm.load()
