@@ -122,6 +122,29 @@ __device__ __forceinline__ void gather_parts(const double *parts, int G, int n, 
     }
 }
 
+// acc[0] += the Ga partials in pa, acc[1] += the Gb partials in pb (first
+// row of each buffer), as gather_parts does each, with the loads of both
+// issued together
+__device__ __forceinline__ void gather_parts2(const double *pa, int Ga, const double *pb, int Gb,
+                                              double (&acc)[2]) {
+    constexpr int U = 8;
+    const int G = Ga > Gb ? Ga : Gb;
+    for (int b0 = 0; b0 < G; b0 += U * kBlock) {
+        double va[U], vb[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u * kBlock + threadIdx.x;
+            va[u] = b < Ga ? pa[b] : 0.0;
+            vb[u] = b < Gb ? pb[b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            acc[0] += va[u];
+            acc[1] += vb[u];
+        }
+    }
+}
+
 // Per-block partial sums of N values: block tree in LDS (fixed order), then
 // one store per value.  The grid-wide sums are formed by k_finalize, a
 // one-block kernel queued right after, which adds the partials in block
@@ -146,7 +169,9 @@ __device__ __forceinline__ bool bad(double v) { return !(v == v) || v > 1e300; }
 // cells of the coupling box that meet a force unknown (up to 9 entries on
 // the cylinder workloads), 8 lanes per row with a shuffle reduction.  The
 // tiles skip those cells (one bit each), so a tile is the plain 5-point
-// stencil with every operand load issued before the arithmetic.
+// stencil with every operand load issued before the arithmetic; tiles of
+// two or more rows (the large grids) form each operand once per column and
+// exchange the east / west values through LDS.
 
 constexpr int kForceLanes = 8;
 static_assert(kKfW % kForceLanes == 0 && kCcW % kForceLanes == 0, "ELL widths must be multiples of 8");
@@ -281,6 +306,68 @@ __device__ __forceinline__ void k0_tile(const K0T<T> &K, int i, int j0, XV xv, A
     }
 }
 
+// Interior tile without coupled cells, east / west operands through LDS:
+// every lane forms xv once at each of the R + 2 rows of its column, the R
+// centre rows go to LDS, the two edge lanes form the halo columns, and the
+// east / west values are read back after one barrier.  Every lane of the
+// block calls this (lanes past the last column only take the barrier).
+template <int R, class T, class XV, class ACT>
+__device__ __forceinline__ void k0_tile_lds(const K0T<T> &K, int i, int j0, XV xv, ACT act) {
+    __shared__ T sh[R][kBlock + 2];
+    const GridT<T> &g = K.g;
+    const int nx = g.nx;
+    const bool on = i < nx;
+    const int ic = on ? i : nx - 1;
+    const T dt = K.dt;
+    const T dxi = g.dx[ic];
+    const T cw = ic > 0 ? dt * g.iDx[ic] : T(0);
+    const T ce = ic < nx - 1 ? dt * g.iDx[ic + 1] : T(0);
+    const int row0 = j0 * nx + ic;
+    T xcol[R + 2], dyr[R], iyr[R + 1];
+    xcol[0] = j0 > 0 ? xv(row0 - nx) : T(0);
+#pragma unroll
+    for (int k = 0; k <= R; ++k) xcol[k + 1] = xv(row0 + k * nx);
+    const int tx = threadIdx.x;
+    T hw[R], he[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        dyr[r] = g.dy[j0 + r];
+        hw[r] = (tx == 0 && ic > 0) ? xv(row0 + r * nx - 1) : T(0);
+        he[r] = (tx == kBlock - 1 && ic < nx - 1) ? xv(row0 + r * nx + 1) : T(0);
+    }
+#pragma unroll
+    for (int r = 0; r <= R; ++r) iyr[r] = g.iDy[j0 + r];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        sh[r][tx + 1] = xcol[r + 1];
+        if (tx == 0) sh[r][0] = hw[r];
+        if (tx == kBlock - 1) sh[r][kBlock + 1] = he[r];
+    }
+    __syncthreads();
+    if (!on) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int j = j0 + r;
+        const int row = row0 + r * nx;
+        // the neighbour past the last column of the grid is zero
+        const T xw = ic > 0 ? sh[r][tx] : T(0);
+        const T xe = ic < nx - 1 ? sh[r][tx + 2] : T(0);
+        const T bw = cw * dyr[r], be = ce * dyr[r];
+        const T bs = j > 0 ? dt * dxi * iyr[r] : T(0);
+        const T bn = dt * dxi * iyr[r + 1];
+        const T diag = ((bw + be) + bs) + bn;
+        const T xc = xcol[r + 1];
+        T y = diag * xc;
+        if (row != 0) {
+            if (row - nx != 0) y -= bs * xcol[r];
+            if (row - 1 != 0) y -= bw * xw;
+            y -= be * xe;
+            y -= bn * xcol[r + 2];
+        }
+        act(row, y, diag, xc);
+    }
+}
+
 // Pressure and force rows of K = Q^T B^1 Q (pinned), precision T.
 // act(row, Kx, diag, x_row) is called once per row.
 template <int R, class T, class XV, class ACT>
@@ -302,7 +389,11 @@ __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
         // the same for every lane of the block
         const bool box_tile = K.ncc > 0 && j0 <= K.cb_j1 && j0 + R - 1 >= K.cb_j0 &&
                               cx * kBlock <= K.cb_i1 && cx * kBlock + kBlock - 1 >= K.cb_i0;
-        if (i < nx && j0 + R < ny) {
+        if (j0 + R < ny && !box_tile && R >= 2) {
+            // tiles of 2 or more rows (the large grids) exchange east / west
+            // values through LDS; every lane of the block reaches its barrier
+            k0_tile_lds<R>(K, i, j0, xv, act);
+        } else if (i < nx && j0 + R < ny) {
             if (box_tile)
                 k0_tile<R, true>(K, i, j0, xv, act);
             else
@@ -600,19 +691,16 @@ __global__ __launch_bounds__(kBlock) void k_pcg_spmv(Op op, const T *__restrict_
         const int first = st->first;
         const double rz_old = st->rz;
         double a[2] = {0.0, 0.0};
-        {
+        if (rr_parts && !first) {
+            gather_parts2(rz_parts, G_rz, rr_parts, G_rr, a);
+        } else {
             double a0[1] = {0.0};
             gather_parts<1>(rz_parts, G_rz, 1, a0);
             a[0] = a0[0];
         }
-        if (rr_parts && !first) {
-            // the stop test of the previous update (the same decision in
-            // every block: it depends only on sums formed in a fixed order
-            // and on fields no block of this kernel writes before reading)
-            double b1[1] = {0.0};
-            gather_parts<1>(rr_parts, G_rr, 1, b1);
-            a[1] = b1[0];
-        }
+        // with rr_parts: the stop test of the previous update (the same
+        // decision in every block: it depends only on sums formed in a fixed
+        // order and on fields no block of this kernel writes before reading)
         block_sum<2>(a);
         if (rr_parts && !first) {
             const double rr = a[1];
