@@ -461,6 +461,46 @@ __device__ __forceinline__ void a_walk(const AView &A, XV xv, ACT act) {
         const int cy = w / cxu, cx = w - cy * cxu;
         const int i = cx * kBlock + threadIdx.x + 1;                   // 1..nx-1
         const int j0 = cy * R;
+        if (R >= 2 && j0 + R < ny) {
+            // east / west through LDS (every lane of the block comes here)
+            __shared__ double sh[R][kBlock + 2];
+            const int tx = threadIdx.x;
+            const bool on = i <= nx - 1;
+            const int ic = on ? i : nx - 1;
+            const int f0 = j0 * nxm + (ic - 1);
+            double xcol[R + 2];
+            xcol[0] = j0 > 0 ? xv(f0 - nxm) : 0.0;
+#pragma unroll
+            for (int k = 0; k <= R; ++k) xcol[k + 1] = xv(f0 + k * nxm);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                sh[r][tx + 1] = xcol[r + 1];
+                if (tx == 0) sh[r][0] = ic > 1 ? xv(f0 + r * nxm - 1) : 0.0;
+                if (tx == kBlock - 1) sh[r][kBlock + 1] = ic < nx - 1 ? xv(f0 + r * nxm + 1) : 0.0;
+            }
+            const double idxi = g.idx[ic], idxm = g.idx[ic - 1], iDxi = g.iDx[ic], Dxi = g.Dx[ic];
+            __syncthreads();
+            if (!on) return;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int j = j0 + r;
+                const double xe = ic < nx - 1 ? sh[r][tx + 2] : 0.0;
+                const double xw = ic > 1 ? sh[r][tx] : 0.0;
+                const double idyj = g.idy[j];
+                const double xc = xcol[r + 1];
+                const double uc = xc * idyj;
+                const double us = j > 0 ? xcol[r] * g.idy[j - 1] : 0.0;
+                const double un = xcol[r + 2] * g.idy[j + 1];
+                const double uE = xe * idyj, uW = xw * idyj;
+                const double lapx = ((uE - uc) * idxi - (uc - uW) * idxm) * iDxi;
+                const double lapy = ((un - uc) * g.iDy[j + 1] - (uc - us) * g.iDy[j]) * idyj;
+                const double mf = Dxi * idyj;
+                const double diag = mf * A.idt + hnu * ((idxi + idxm) * idyj +
+                                                         Dxi * (g.iDy[j + 1] + g.iDy[j]) * idyj * idyj);
+                act(f0 + r * nxm, mf * A.idt * xc - hnu * (Dxi * (lapx + lapy)), diag, xc);
+            }
+            return;
+        }
         if (i > nx - 1 || j0 >= ny) return;
         const double idxi = g.idx[i], idxm = g.idx[i - 1], iDxi = g.iDx[i], Dxi = g.Dx[i];
         const int f0 = j0 * nxm + (i - 1);
@@ -521,6 +561,45 @@ __device__ __forceinline__ void a_walk(const AView &A, XV xv, ACT act) {
         const int cy = wv / cxv, cx = wv - cy * cxv;
         const int i = cx * kBlock + threadIdx.x;                       // 0..nx-1
         const int j0 = cy * R + 1;                                     // 1..ny-1
+        if (R >= 2 && j0 + R < ny) {
+            // east / west through LDS (every lane of the block comes here)
+            __shared__ double sh[R][kBlock + 2];
+            const int tx = threadIdx.x;
+            const bool on = i < nx;
+            const int ic = on ? i : nx - 1;
+            const int f0 = g.n_u + (j0 - 1) * nx + ic;
+            double xcol[R + 2];
+            xcol[0] = j0 > 1 ? xv(f0 - nx) : 0.0;
+#pragma unroll
+            for (int k = 0; k <= R; ++k) xcol[k + 1] = xv(f0 + k * nx);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                sh[r][tx + 1] = xcol[r + 1];
+                if (tx == 0) sh[r][0] = ic > 0 ? xv(f0 + r * nx - 1) : 0.0;
+                if (tx == kBlock - 1) sh[r][kBlock + 1] = ic < nx - 1 ? xv(f0 + r * nx + 1) : 0.0;
+            }
+            const double idxi = g.idx[ic], dxr = g.iDx[ic + 1], dxl = g.iDx[ic];
+            const double idxe = ic < nx - 1 ? g.idx[ic + 1] : 0.0, idxw = ic > 0 ? g.idx[ic - 1] : 0.0;
+            __syncthreads();
+            if (!on) return;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int j = j0 + r;
+                const double xe = ic < nx - 1 ? sh[r][tx + 2] : 0.0;
+                const double xw = ic > 0 ? sh[r][tx] : 0.0;
+                const double xc = xcol[r + 1];
+                const double vc = xc * idxi, vs = xcol[r] * idxi, vn = xcol[r + 2] * idxi;
+                const double vE = xe * idxe, vW = xw * idxw;
+                const double lapx = ((vE - vc) * dxr - (vc - vW) * dxl) * idxi;
+                const double lapy = ((vn - vc) * g.idy[j] - (vc - vs) * g.idy[j - 1]) * g.iDy[j];
+                const double Dyj = g.Dy[j];
+                const double mf = Dyj * idxi;
+                const double diag = mf * A.idt + hnu * (Dyj * (dxr + dxl) * idxi * idxi +
+                                                         (g.idy[j] + g.idy[j - 1]) * idxi);
+                act(f0 + r * nx, mf * A.idt * xc - hnu * (Dyj * (lapx + lapy)), diag, xc);
+            }
+            return;
+        }
         if (i >= nx || j0 > ny - 1) return;
         const double idxi = g.idx[i], dxr = g.iDx[i + 1], dxl = g.iDx[i];
         const double idxe = i < nx - 1 ? g.idx[i + 1] : 0.0, idxw = i > 0 ? g.idx[i - 1] : 0.0;
