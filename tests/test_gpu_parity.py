@@ -87,6 +87,26 @@ def test_operator_dense_body():
     ctx.close()
 
 
+def test_operators_two_row_tiles_with_a_ragged_last_column():
+    """A 1500^2 grid: the operators run in tiles of two rows (east / west
+    values through LDS, one barrier per block) and the last tile of each
+    row band is ragged (1500 = 5 x 256 + 220 cells, 1499 u faces), so lanes
+    past the last column take the barrier without a column; K and A must
+    still match the oracle on every row."""
+    wl = W.cylinder_stretched(1500, 0.005, 628, 100.0, 0.002, 0)
+    print("[apply] cylinder 1500^2", flush=True)
+    P = Problem(wl, poisson_solver=0)
+    ctx = ibpm.Context(wl, poisson_solver=0)
+    rng = np.random.default_rng(13)
+    x = rng.standard_normal(ctx.n_lambda)
+    y = _n(ctx.apply_K(_t(x)))
+    assert _maxrel(y, P.ops.K @ x) < 1e-13
+    xq = rng.standard_normal(ctx.n_q)
+    yq = _n(ctx.apply_A(_t(xq)))
+    assert _maxrel(yq, P.ops.A @ xq) < 1e-13
+    ctx.close()
+
+
 def _oracle_state(P, steps):
     st = P.initial_state()
     for _ in range(steps):
