@@ -248,16 +248,6 @@ template <class T>
 void launch_csr_jacobi_first(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b, T *x,
                              const SolveStatus *st);
 template <class T>
-void launch_csr_jacobi(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b, const T *xin,
-                       T *xout, const SolveStatus *st);
-template <class T>
-void launch_csr_residual(hipStream_t s, CSRT<T> A, const T *b, const T *x, T *r,
-                         const SolveStatus *st);
-template <class T>
-void launch_csr_spmv(hipStream_t s, CSRT<T> A, const T *x, T *y, const SolveStatus *st);
-template <class T>
-void launch_csr_spmv_add(hipStream_t s, CSRT<T> A, const T *x, T *y, const SolveStatus *st);
-template <class T>
 void launch_dense_solve(hipStream_t s, int n, const double *inv_colmajor, const T *b, T *x,
                         const SolveStatus *st);
 
@@ -314,10 +304,6 @@ void launch_fcg_product(hipStream_t s, const K0T<T> &K, const T *p, T *q, const 
                         FcgRing *ring, SolveStatus *st, double *parts);
 
 // flexible CG with a learned stage (vectors of T, sums in FP64):
-//   p_new = z + beta p_old, q = K p_new, st->pq = p.q, st->rz = p.r
-template <class T>
-void launch_fcg_spmv(hipStream_t s, const K0T<T> &K, const T *z, const T *pold, T *pnew, T *q,
-                     const T *r, SolveStatus *st, double *parts);
 //   stw->beta = (d.r1) / (d.K d) (0 if not positive or not finite); the sums
 //   are skipped once the solve with status st has finished
 template <class T>
@@ -327,9 +313,6 @@ void launch_kd_omega(hipStream_t s, const K0T<T> &K, const T *d, const T *r1, So
 template <class T>
 void launch_axpy_omega(hipStream_t s, int n, const T *z0, const T *d, const SolveStatus *stw, T *z,
                        const SolveStatus *st);
-//   st->beta = -(z.q) / st->pq
-template <class T>
-void launch_fcg_beta(hipStream_t s, int n, const T *z, const T *q, SolveStatus *st, double *parts);
 // harvest: e1 = x* - x - z (FP32)
 void launch_harvest_e1(hipStream_t s, int n, const double *xstar, const double *x, const double *z,
                        float *e1);
@@ -338,10 +321,7 @@ void launch_harvest_e1(hipStream_t s, int n, const double *xstar, const double *
 void launch_outer_residual(hipStream_t s, const K0View &K, const double *b, const double *x,
                            float *r32, SolveStatus *st, double *parts, int first);
 void launch_add_correction(hipStream_t s, int n, double *x, const float *d);
-// FP64 CG with an FP32 V-cycle: y = FP32(x); z = FP64(z32) with the per-block
-// partials of r . z (returns their number)
+// FP64 CG with an FP32 V-cycle: y = FP32(x) (the residual on entry to the cycle)
 void launch_to_f32(hipStream_t s, int n, const double *x, float *y, const SolveStatus *st);
-int launch_widen_dot(hipStream_t s, int n, const float *z32, double *z, const double *r,
-                     const SolveStatus *st, double *parts);
 
 }  // namespace ibpm

@@ -1121,17 +1121,16 @@ __global__ __launch_bounds__(kBlock) void k_dot_rz(int n, const T *r, const T *z
 // and the status update that goes with them.  One block.
 enum : int {
     FIN_INIT = 0, FIN_INIT_ZERO, FIN_PQ, FIN_UPDATE, FIN_TRUE, FIN_RZ, FIN_OUTER,
-    FIN_FCG_PQ, FIN_OMEGA, FIN_FCG_BETA, FIN_RZ_NEXT
+    FIN_OMEGA, FIN_RZ_NEXT
 };
 
 __global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const double *parts,
                                                      SolveStatus *st, int flag, double rtol2,
                                                      int maxit) {
-    if ((kind == FIN_PQ || kind == FIN_UPDATE || kind == FIN_RZ || kind == FIN_RZ_NEXT || kind == FIN_FCG_PQ ||
-         kind == FIN_FCG_BETA) && st->done)
+    if ((kind == FIN_PQ || kind == FIN_UPDATE || kind == FIN_RZ || kind == FIN_RZ_NEXT) && st->done)
         return;
     const int N = (kind == FIN_INIT) ? 3
-                  : (kind == FIN_UPDATE || kind == FIN_OUTER || kind == FIN_FCG_PQ || kind == FIN_OMEGA)
+                  : (kind == FIN_UPDATE || kind == FIN_OUTER || kind == FIN_OMEGA)
                       ? 2
                       : 1;
     double acc[3] = {0.0, 0.0, 0.0};
@@ -1200,18 +1199,11 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const doub
         }
         st->rz = acc[0];
         break;
-    case FIN_FCG_PQ:   // acc = (p.q, p.r): the flexible-CG step length is (p.r)/(p.q)
-        st->pq = acc[0];
-        st->rz = acc[1];
-        break;
     case FIN_OMEGA: {  // acc = (d.r1, d.K d): energy-optimal weight of the learned correction
         double w = (acc[1] > 0.0 && !bad(acc[0]) && !bad(acc[1])) ? acc[0] / acc[1] : 0.0;
         st->beta = w;
         break;
     }
-    case FIN_FCG_BETA:   // acc = z.q (q of the current direction)
-        st->beta = -acc[0] / st->pq;
-        break;
     case FIN_OUTER:   // acc = (rr, bb); flag = first outer residual
         st->rr = acc[0];
         if (flag) {
@@ -1226,23 +1218,6 @@ __global__ __launch_bounds__(kBlock) void k_finalize(int kind, int G, const doub
 
 // ---------------------------------------------------------------------------
 // flexible CG with the learned stage
-
-// p_new = z + beta p_old, q = K p_new; sums p.q and p.r
-template <int R, class T>
-__global__ __launch_bounds__(kBlock) void k_fcg_spmv(K0T<T> K, const T *__restrict__ z, const T *__restrict__ pold, T *__restrict__ pnew,
-                                                     T *__restrict__ q, const T *__restrict__ r, SolveStatus *st,
-                                                     double *parts) {
-    if (st->done) return;
-    const T beta = (T)st->beta;
-    double v[2] = {0.0, 0.0};
-    k0_walk<R>(K, [&](int c) { return z[c] + beta * pold[c]; }, [&](int row, T qi, T, T pi) {
-        pnew[row] = pi;
-        q[row] = qi;
-        v[0] += (double)pi * (double)qi;
-        v[1] += (double)pi * (double)r[row];
-    });
-    write_parts2<2>(v, parts);
-}
 
 // --- FCG(m) -----------------------------------------------------------------
 
@@ -1352,20 +1327,6 @@ __global__ __launch_bounds__(kBlock) void k_axpy_omega(int n, const T *z0, const
     if (i < n) z[i] = w != T(0) ? z0[i] + w * d[i] : z0[i];
 }
 
-// generic predicated dot product a . b into a finalize kind
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_dot(int n, const T *a, const T *b, SolveStatus *st,
-                                                double *parts) {
-    if (st->done) return;
-    Tiles Tl = my_tiles(n);
-    double v[1] = {0.0};
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < n) v[0] += (double)a[row] * (double)b[row];
-    }
-    write_parts<1>(v, parts);
-}
-
 // harvest: e1 = x* - x - z in FP32
 __global__ __launch_bounds__(kBlock) void k_harvest_e1(int n, const double *xstar, const double *x,
                                                        const double *z, float *e1) {
@@ -1391,43 +1352,6 @@ __global__ __launch_bounds__(kBlock) void k_csr_jacobi_first(CSRT<T> A, const T 
     for (int t = Tl.t0; t < Tl.t1; ++t) {
         int row = t * kBlock + threadIdx.x;
         if (row < A.nrows) x[row] = wdinv[row] * b[row];
-    }
-}
-
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_csr_jacobi(CSRT<T> A, const T *wdinv, const T *b,
-                                                       const T *xin, T *xout,
-                                                       const SolveStatus *st) {
-    if (st->done) return;
-    Tiles Tl = my_tiles(A.nrows);
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < A.nrows) xout[row] = xin[row] + wdinv[row] * (b[row] - csr_dot(A, row, xin));
-    }
-}
-
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_csr_residual(CSRT<T> A, const T *b, const T *x, T *r,
-                                                         const SolveStatus *st) {
-    if (st->done) return;
-    Tiles Tl = my_tiles(A.nrows);
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < A.nrows) r[row] = b[row] - csr_dot(A, row, x);
-    }
-}
-
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_csr_spmv(CSRT<T> A, const T *x, T *y, int add,
-                                                     const SolveStatus *st) {
-    if (st && st->done) return;
-    Tiles Tl = my_tiles(A.nrows);
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        int row = t * kBlock + threadIdx.x;
-        if (row < A.nrows) {
-            T v = csr_dot(A, row, x);
-            y[row] = add ? y[row] + v : v;
-        }
     }
 }
 
@@ -1650,25 +1574,6 @@ __global__ __launch_bounds__(kBlock) void k_to_f32(int n, const double *__restri
     if (st->done) return;
     const int i = tile_base() + threadIdx.x;
     if (i < n) y[i] = (float)x[i];
-}
-
-// z = FP64(z32) and per-block partials of r . z
-__global__ __launch_bounds__(kBlock) void k_widen_dot(int n, const float *__restrict__ z32,
-                                                      double *__restrict__ z,
-                                                      const double *__restrict__ r,
-                                                      const SolveStatus *st, double *parts) {
-    if (st->done) return;
-    Tiles Tl = my_tiles(n);
-    double v[1] = {0.0};
-    for (int t = Tl.t0; t < Tl.t1; ++t) {
-        const int i = t * kBlock + threadIdx.x;
-        if (i < n) {
-            const double zi = (double)z32[i];
-            z[i] = zi;
-            v[0] += r[i] * zi;
-        }
-    }
-    write_parts<1>(v, parts);
 }
 
 __global__ __launch_bounds__(kBlock) void k_add_correction(int n, double *x, const float *d) {
@@ -2203,28 +2108,6 @@ void launch_csr_jacobi_first(hipStream_t s, CSRT<T> A, const T *wdinv, const T *
 }
 
 template <class T>
-void launch_csr_jacobi(hipStream_t s, CSRT<T> A, const T *wdinv, const T *b, const T *xin,
-                       T *xout, const SolveStatus *st) {
-    LAUNCH((k_csr_jacobi<T>), grid_for(A.nrows), A, wdinv, b, xin, xout, st);
-}
-
-template <class T>
-void launch_csr_residual(hipStream_t s, CSRT<T> A, const T *b, const T *x, T *r,
-                         const SolveStatus *st) {
-    LAUNCH((k_csr_residual<T>), grid_for(A.nrows), A, b, x, r, st);
-}
-
-template <class T>
-void launch_csr_spmv(hipStream_t s, CSRT<T> A, const T *x, T *y, const SolveStatus *st) {
-    LAUNCH((k_csr_spmv<T>), grid_for(A.nrows), A, x, y, 0, st);
-}
-
-template <class T>
-void launch_csr_spmv_add(hipStream_t s, CSRT<T> A, const T *x, T *y, const SolveStatus *st) {
-    LAUNCH((k_csr_spmv<T>), grid_for(A.nrows), A, x, y, 1, st);
-}
-
-template <class T>
 void launch_dense_solve(hipStream_t s, int n, const double *inv, const T *b, T *x,
                         const SolveStatus *st) {
     LAUNCH((k_dense_solve<T>), (n + kBlock - 1) / kBlock, n, inv, b, x, st);
@@ -2328,18 +2211,6 @@ void launch_coarse_dense(hipStream_t s, int n, const double *C, const T *b, T *x
 }
 
 template <class T>
-void launch_fcg_spmv(hipStream_t s, const K0T<T> &K, const T *z, const T *pold, T *pnew, T *q,
-                     const T *r, SolveStatus *st, double *parts) {
-    int G = 0;
-    WALK_SWITCH(pick_R(K), {
-        dim3 gd = op_grid<RR>(K);
-        G = gd.x * gd.y;
-        LAUNCH2((k_fcg_spmv<RR, T>), gd, K, z, pold, pnew, q, r, st, parts);
-    })
-    LAUNCH(k_finalize, 1, (int)FIN_FCG_PQ, G, parts, st, 0, 0.0, 0);
-}
-
-template <class T>
 void launch_fcg_betas(hipStream_t s, int n, const T *z, FcgVecs<T> Q, int cnt, FcgSlots sl,
                       FcgRing *ring, const SolveStatus *st, double *parts) {
     if (cnt < 1) return;
@@ -2387,13 +2258,6 @@ void launch_axpy_omega(hipStream_t s, int n, const T *z0, const T *d, const Solv
     LAUNCH((k_axpy_omega<T>), (n + kBlock - 1) / kBlock, n, z0, d, stw, z, st);
 }
 
-template <class T>
-void launch_fcg_beta(hipStream_t s, int n, const T *z, const T *q, SolveStatus *st, double *parts) {
-    int G = grid_for(n);
-    LAUNCH((k_dot<T>), G, n, z, q, st, parts);
-    LAUNCH(k_finalize, 1, (int)FIN_FCG_BETA, G, parts, st, 0, 0.0, 0);
-}
-
 void launch_harvest_e1(hipStream_t s, int n, const double *xstar, const double *x, const double *z,
                        float *e1) {
     LAUNCH(k_harvest_e1, (n + kBlock - 1) / kBlock, n, xstar, x, z, e1);
@@ -2413,14 +2277,6 @@ void launch_outer_residual(hipStream_t s, const K0View &K, const double *b, cons
 void launch_to_f32(hipStream_t s, int n, const double *x, float *y, const SolveStatus *st) {
     LAUNCH(k_to_f32, (n + kBlock - 1) / kBlock, n, x, y, st);
 }
-
-int launch_widen_dot(hipStream_t s, int n, const float *z32, double *z, const double *r,
-                     const SolveStatus *st, double *parts) {
-    int G = grid_for(n);
-    LAUNCH(k_widen_dot, G, n, z32, z, r, st, parts);
-    return G;
-}
-
 void launch_add_correction(hipStream_t s, int n, double *x, const float *d) {
     LAUNCH(k_add_correction, (n + kBlock - 1) / kBlock, n, x, d);
 }
@@ -2465,13 +2321,6 @@ INST_OP(K0T<float>, float)
                                         const SolveStatus *);                                    \
     template void launch_csr_jacobi_first<T>(hipStream_t, CSRT<T>, const T *, const T *, T *,    \
                                              const SolveStatus *);                               \
-    template void launch_csr_jacobi<T>(hipStream_t, CSRT<T>, const T *, const T *, const T *,    \
-                                       T *, const SolveStatus *);                                \
-    template void launch_csr_residual<T>(hipStream_t, CSRT<T>, const T *, const T *, T *,        \
-                                         const SolveStatus *);                                   \
-    template void launch_csr_spmv<T>(hipStream_t, CSRT<T>, const T *, T *, const SolveStatus *); \
-    template void launch_csr_spmv_add<T>(hipStream_t, CSRT<T>, const T *, T *,                   \
-                                         const SolveStatus *);                                   \
     template void launch_dense_solve<T>(hipStream_t, int, const double *, const T *, T *,        \
                                         const SolveStatus *);
 INST_T(double)
@@ -2495,13 +2344,10 @@ INST_V(double)
 INST_V(float)
 
 #define INST_F(T)                                                                                \
-    template void launch_fcg_spmv<T>(hipStream_t, const K0T<T> &, const T *, const T *, T *, T *,\
-                                     const T *, SolveStatus *, double *);                        \
     template void launch_kd_omega<T>(hipStream_t, const K0T<T> &, const T *, const T *,          \
                                      SolveStatus *, double *, const SolveStatus *);              \
     template void launch_axpy_omega<T>(hipStream_t, int, const T *, const T *, const SolveStatus *,\
-                                       T *, const SolveStatus *);                                \
-    template void launch_fcg_beta<T>(hipStream_t, int, const T *, const T *, SolveStatus *, double *);
+                                       T *, const SolveStatus *);
 INST_F(double)
 INST_F(float)
 
