@@ -404,6 +404,10 @@ struct FusedPre {
     int G_pq, G_rr;
 };
 
+// CG iterations per recorded graph (even: the direction and residual
+// buffers swap every iteration, so a replay leaves them as it found them)
+constexpr int kGraphIters = 8;
+
 // Generic PCG driver.  Iterations are queued in chunks; every kernel of an
 // iteration is predicated on the device status, so iterations queued past
 // convergence do nothing.  The chunk length is estimated from the observed
@@ -452,7 +456,7 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
         }
     };
     // the iterations are identical launches (the two direction buffers swap
-    // every iteration), so a graph of two of them is replayed
+    // every iteration), so a graph of kGraphIters of them is replayed
     hipGraphExec_t gexec = nullptr;
     if (c->prm.use_graphs && graph_slot >= 0) {
         ibpm_ctx::IterGraph &G = c->graphs[graph_slot];
@@ -473,8 +477,7 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
             s = c->cap_stream;
             HIPCHECK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
             try {
-                iteration();
-                iteration();
+                for (int k = 0; k < kGraphIters; ++k) iteration();
             } catch (...) {
                 (void)hipStreamEndCapture(s, &graph);
                 if (graph) (void)hipGraphDestroy(graph);
@@ -502,8 +505,8 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
     int last_it = 0;
     for (;;) {
         if (gexec) {
-            chunk += chunk & 1;
-            for (int k = 0; k < chunk; k += 2) HIPCHECK(hipGraphLaunch(gexec, s));
+            chunk = (chunk + kGraphIters - 1) / kGraphIters * kGraphIters;
+            for (int k = 0; k < chunk; k += kGraphIters) HIPCHECK(hipGraphLaunch(gexec, s));
         } else {
             for (int k = 0; k < chunk; ++k) iteration();
         }
