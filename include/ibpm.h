@@ -21,15 +21,20 @@
  *    i = 0..nx-1, j = 1..ny-1, stored as q = v * dx_i.
  *  - lambda (length n_lambda = nx*ny + 2*nb): cell pressures phi (x fastest),
  *    then the nb x-forces, then the nb y-forces on the Lagrangian points.
- *    Pressure cell 0 is pinned (its row and column carry only the diagonal,
- *    Sec. 2 last paragraph), so phi[0] = 0 when rhs[0] = 0.
+ *    One pressure cell (ibpm_params.pin_cell, default 0) is pinned: its row
+ *    and column carry only the diagonal (Sec. 2, last paragraph), so
+ *    phi[pin_cell] = 0 when rhs[pin_cell] = 0.
  *  - Device pointers are HIP device memory owned by the caller (for example
  *    torch tensors); they must stay valid until the work queued on the
  *    context's stream has completed.  Host pointers are read during the
  *    call only.
- *  - Every call queues work on the stream given to ibpm_build_operators and
- *    returns without waiting, except where a host output (stats, forces,
- *    walls) is requested: then it waits for the stream.
+ *  - Every call queues work on the stream given to ibpm_build_operators.
+ *    The solves (ibpm_solve_poisson, ibpm_solve_velocity and the solves
+ *    inside ibpm_step) wait for the stream: their iterations are queued in
+ *    chunks, and the host reads the device status (a few bytes) after each
+ *    chunk to decide how many more to queue.  The other calls return without
+ *    waiting, except where a host output (stats, forces, walls) is
+ *    requested: then they wait for the stream.
  *  - Return codes: IBPM_OK or a negative IBPM_E* code; ibpm_last_error()
  *    returns a text description.  No C++ exception crosses this boundary.
  *  - One context serves one stream; calls on one context must not overlap.
@@ -60,6 +65,15 @@ extern "C" {
                                                 inside FP64 iterative refinement */
 #define IBPM_SOLVER_AMG_PCG_FP32_CYCLE 5     /* FP64 CG whose V-cycle runs in FP32 (the
                                                 residual rounded to FP32 on entry) */
+
+/* Wall kinds (ibpm_params.bc_kind, per side: left x = xf[0], right
+ * x = xf[nx], bottom y = yf[0], top y = yf[ny]). */
+#define IBPM_BC_DIRICHLET  0   /* the wall velocity is (bc_u, bc_v) of that side at all times */
+#define IBPM_BC_CONVECTIVE 1   /* right wall only: du/dt + U du/dx = 0 with U = uinf cos(alpha)
+                                  (Sec. 5.2), explicit in time from the adjacent interior
+                                  values; the wall starts at the freestream (uinf, alpha), and
+                                  its normal velocity is shifted uniformly each step so that
+                                  the net flux through the walls is zero */
 
 typedef struct ibpm_ctx ibpm_ctx;
 
@@ -98,6 +112,16 @@ typedef struct ibpm_params {
                                     first post-sweep on CSR levels of at most 200,000 unknowns,
                                     with R A and A P formed at build time; 0: separate kernels
                                     (the same V-cycle, other rounding) */
+    int32_t pin_cell;            /* pressure cell (j * nx + i) whose value is pinned: its row
+                                    and column of K carry only the diagonal and its right-hand
+                                    side entry is 0 (Sec. 2, last paragraph); 0..nx*ny-1 */
+    int32_t bc_kind[4];          /* IBPM_BC_* of the left, right, bottom and top walls.  The
+                                    paper's cylinder runs: DIRICHLET at the freestream on the
+                                    left, bottom and top, CONVECTIVE on the right (Sec. 5.2).
+                                    Without a convective wall the Dirichlet walls must carry
+                                    zero net flux (else IBPM_EINVAL) */
+    double bc_u[4], bc_v[4];     /* wall velocity (u, v) of each Dirichlet side (same order);
+                                    ignored for a convective side */
 } ibpm_params;
 
 typedef struct ibpm_solve_stats {
@@ -139,9 +163,10 @@ const char *ibpm_last_error(const ibpm_ctx *ctx);
 /* Sizes of the flux and lambda vectors. */
 int ibpm_sizes(const ibpm_ctx *ctx, int64_t *n_q, int64_t *n_lambda);
 
-/* Impulsive start (Sec. 5.2): q = freestream everywhere (device, n_q),
- * conv_prev = 0 (device, n_q), lambda = 0 (device, n_lambda), wall values
- * freestream and the step counter reset to 0. */
+/* Impulsive start (Sec. 5.2): q = freestream (uinf, alpha) everywhere
+ * (device, n_q), conv_prev = 0 (device, n_q), lambda = 0 (device, n_lambda),
+ * the Dirichlet walls at their (bc_u, bc_v), a convective wall at the
+ * freestream, and the step counter reset to 0. */
 int ibpm_init_state(ibpm_ctx *ctx, double *q, double *conv_prev, double *lambda);
 
 /* Advance nsteps time steps of Eq. (11) in place.
@@ -207,6 +232,22 @@ int ibpm_hierarchy_info(const ibpm_ctx *ctx, int32_t *levels, int64_t *sizes,
 
 /* Aggregate index of every unknown of `level` (host, sizes[level] int32s). */
 int ibpm_get_aggregates(const ibpm_ctx *ctx, int32_t level, int32_t *agg);
+
+/* Host-only preview of the set-up of Sec. 3 for the parameters p: the
+ * operators and the smoothed-aggregation hierarchy that
+ * ibpm_build_operators would build, formed on the host without touching the
+ * GPU (p->poisson_solver must select an AMG solver).  Outputs (host, each
+ * may be NULL): *levels the level count; per level, in arrays with room for
+ * `cap` levels, the unknowns (sizes), the stored non-zeros (nnz) and the
+ * estimate rho of the spectral radius of D^{-1} A behind that level's
+ * Jacobi weights 4 / (3 rho); agg the aggregate of every unknown of level
+ * agg_level (sizes[agg_level] int32s, agg_level < levels - 1); *seconds the
+ * host set-up time.  err (may be NULL) receives up to errlen bytes of an
+ * error text.  Returns IBPM_OK, IBPM_EINVAL (bad parameters, a cap below
+ * the level count, agg_level out of range) or IBPM_ENOMEM. */
+int ibpm_plan_hierarchy(const ibpm_params *p, int32_t cap, int32_t *levels, int64_t *sizes,
+                        int64_t *nnz, double *rho, int32_t agg_level, int32_t *agg,
+                        double *seconds, char *err, int32_t errlen);
 
 /* Kernels that ibpm_time_kernel can time (the launch configuration and
  * operands are those of the time step). */

@@ -5,11 +5,12 @@ the boundary conditions).
 Oracle code: test infrastructure only.
 
 One step from (q^n, N(q^{n-1}), lambda^n, walls^n):
-  1. walls^{n+1}: Dirichlet freestream on left, bottom, top; convective
-     outflow du/dt + U du/dx = 0 on the right (Sec. 5.2), explicit upwind
-     in time; then a uniform shift of the outflow normal velocity so that
-     the net flux through the walls is zero (reading: the paper is silent;
-     without it the pinned cell would absorb the imbalance).
+  1. walls^{n+1}: Dirichlet walls keep their values (the paper's cylinder
+     runs: the freestream on left, bottom, top); a convective outflow
+     du/dt + U du/dx = 0 on the right (Sec. 5.2), explicit upwind in time,
+     then a uniform shift of the outflow normal velocity so that the net
+     flux through the walls is zero (reading: the paper is silent; without
+     it the pinned cell would absorb the imbalance).
   2. N(q^n): conservative central differences of div(u u), row-scaled by M.
   3. r1 = (Mf/dt + nu/2 L) q^n + nu/2 (bc_L^n + bc_L^{n+1})
           - 3/2 N(q^n) + 1/2 N(q^{n-1})             (AB2 + Crank-Nicolson)
@@ -53,13 +54,36 @@ class Walls:
         return Walls(*(getattr(self, f.name).copy() for f in dataclasses.fields(self)))
 
 
+def side_walls(grid, u, v):
+    """Walls from one velocity per side, (u, v) each ordered left, right,
+    bottom, top: a side's value goes to its normal and tangential entries."""
+    nx, ny = grid.nx, grid.ny
+    uL, uR, uB, uT = u
+    vL, vR, vB, vT = v
+    return Walls(uL=np.full(ny, float(uL)), uR=np.full(ny, float(uR)),
+                 vB=np.full(nx, float(vB)), vT=np.full(nx, float(vT)),
+                 uBt=np.full(nx + 1, float(uB)), uTt=np.full(nx + 1, float(uT)),
+                 vLt=np.full(ny + 1, float(vL)), vRt=np.full(ny + 1, float(vR)))
+
+
 def freestream_walls(grid, uinf, alpha):
     U = uinf * math.cos(alpha)
     V = uinf * math.sin(alpha)
-    nx, ny = grid.nx, grid.ny
-    return Walls(uL=np.full(ny, U), uR=np.full(ny, U), vB=np.full(nx, V), vT=np.full(nx, V),
-                 uBt=np.full(nx + 1, U), uTt=np.full(nx + 1, U),
-                 vLt=np.full(ny + 1, V), vRt=np.full(ny + 1, V))
+    return side_walls(grid, (U, U, U, U), (V, V, V, V))
+
+
+BC_DIRICHLET = 0
+BC_CONVECTIVE = 1
+
+
+def initial_walls(grid, kinds, bc_u, bc_v, uinf, alpha):
+    """Walls at the start: a Dirichlet side at its (bc_u, bc_v), a convective
+    side at the freestream (the initial field, Sec. 5.2)."""
+    U = uinf * math.cos(alpha)
+    V = uinf * math.sin(alpha)
+    u = [U if k == BC_CONVECTIVE else bu for k, bu in zip(kinds, bc_u)]
+    v = [V if k == BC_CONVECTIVE else bv for k, bv in zip(kinds, bc_v)]
+    return side_walls(grid, u, v)
 
 
 def velocities(grid, q):
@@ -76,8 +100,11 @@ def freestream_flux(grid, uinf, alpha):
     return grid.join_q(qu, qv)
 
 
-def update_walls(grid, walls, q, uinf, alpha, dt):
-    """walls^n, q^n -> walls^{n+1} (step 1 above)."""
+def update_walls(grid, walls, q, uinf, alpha, dt, convective=True):
+    """walls^n, q^n -> walls^{n+1} (step 1 above).  Without a convective
+    (right) wall every wall keeps its value."""
+    if not convective:
+        return walls.copy()
     u, v = velocities(grid, q)
     Uc = uinf * math.cos(alpha)
     out = walls.copy()
@@ -230,11 +257,15 @@ class State:
     step: int = 0
 
 
-def initial_state(ops, uinf, alpha):
+def initial_state(ops, uinf, alpha, walls=None):
+    """Impulsive start: the freestream everywhere, lambda = 0; the walls at
+    the freestream unless given."""
     grid = ops.grid
     q = freestream_flux(grid, uinf, alpha)
+    if walls is None:
+        walls = freestream_walls(grid, uinf, alpha)
     return State(q=q, conv_prev=np.zeros(grid.n_q), lam=np.zeros(ops.n_lambda),
-                 walls=freestream_walls(grid, uinf, alpha), step=0)
+                 walls=walls, step=0)
 
 
 @dataclasses.dataclass
@@ -247,10 +278,10 @@ class StepInfo:
     fy: float
 
 
-def step(ops, state, ub, uinf, alpha, vel_rtol, vel_maxit, poisson_solve):
+def step(ops, state, ub, uinf, alpha, vel_rtol, vel_maxit, poisson_solve, convective=True):
     """Advance one time step.  `poisson_solve(rhs, x0)` -> (x, iters, relres)."""
     grid = ops.grid
-    walls_np1 = update_walls(grid, state.walls, state.q, uinf, alpha, ops.dt)
+    walls_np1 = update_walls(grid, state.walls, state.q, uinf, alpha, ops.dt, convective)
     conv_now = convection(grid, state.q, state.walls)
     conv_prev = conv_now if state.step == 0 else state.conv_prev
     r1 = momentum_rhs(ops, state.q, conv_now, conv_prev, state.walls, walls_np1)

@@ -19,7 +19,13 @@ class Problem:
         self.wl = wl
         self.grid = Grid(wl.xf, wl.yf)
         self.E_hat, self.E = delta.interpolation_matrices(self.grid, wl.xb, wl.yb)
-        self.ops = operators.Operators(self.grid, self.E, wl.nu, wl.dt)
+        self.ops = operators.Operators(self.grid, self.E, wl.nu, wl.dt, pin=wl.pin_cell)
+        kinds = tuple(wl.bc_kind)
+        if any(k not in (flow.BC_DIRICHLET, flow.BC_CONVECTIVE) for k in kinds) or \
+                any(k == flow.BC_CONVECTIVE for k in kinds[0:1] + kinds[2:]):
+            raise ValueError("wall kinds: Dirichlet anywhere, convective on the right only")
+        self.convective = kinds[1] == flow.BC_CONVECTIVE
+        self.bc_u, self.bc_v = wl.wall_velocities()
         self.ub = np.concatenate([np.asarray(wl.ubx, float), np.asarray(wl.uby, float)])
         self.solver = wl.poisson_solver if poisson_solver is None else poisson_solver
         self.vel_rtol = wl.vel_rtol if vel_rtol is None else vel_rtol
@@ -39,11 +45,14 @@ class Problem:
         return solvers.amg_pcg(self.H, self.ops.K, rhs, x0, rtol, maxit)
 
     def initial_state(self):
-        return flow.initial_state(self.ops, self.wl.uinf, self.wl.alpha)
+        walls = flow.initial_walls(self.grid, self.wl.bc_kind, self.bc_u, self.bc_v,
+                                   self.wl.uinf, self.wl.alpha)
+        return flow.initial_state(self.ops, self.wl.uinf, self.wl.alpha, walls)
 
     def step(self, state):
         return flow.step(self.ops, state, self.ub, self.wl.uinf, self.wl.alpha,
-                         self.vel_rtol, self.wl.vel_maxit, self.solve_poisson)
+                         self.vel_rtol, self.wl.vel_maxit, self.solve_poisson,
+                         self.convective)
 
     def run(self, nsteps, state=None, callback=None):
         state = self.initial_state() if state is None else state

@@ -16,11 +16,19 @@ names no parameters; the reading used (and matched by the library) is:
     (lowest-index) strong neighbour aggregated in pass 1, (3) a node still
     free roots an aggregate with its free strong neighbours;
   * tentative prolongator T_{i,agg(i)} = 1 (constant near-null space);
-  * prolongator P = (I - w D^{-1} K) T with w = 4 / (3 rho), rho the
-    Gershgorin bound max_i sum_j |k_ij| / |k_ii|;
+  * prolongator P = (I - w D^{-1} K) T with w = 4 / (3 rho), rho an
+    estimate of the spectral radius of D^{-1} K: the largest Ritz value of
+    LANCZOS_STEPS Lanczos steps on the similar symmetric matrix
+    D^{-1/2} K D^{-1/2} (full reorthogonalisation) from a fixed start vector
+    (splitmix64 of the unknown index, mapped to [-1/2, 1/2)).  The paper only
+    names Cusp's smoothed aggregation, whose Jacobi weights are scaled by
+    rho(D^{-1} A); the Gershgorin bound is not used because on the coupled
+    system the pressure rows next to force unknowns push it 3-4 times above
+    rho, which shrinks every weight by that factor;
   * Galerkin coarse operator P^T K P; coarsen until <= coarse_max unknowns
     or max_levels levels; dense Cholesky on the coarsest level;
-  * V-cycle with weighted Jacobi smoothing (weight 4 / (3 rho_level)),
+  * V-cycle with weighted Jacobi smoothing (weight 4 / (3 rho_level), the
+    same estimate),
     `pre` sweeps down and `post` sweeps up, zero initial guess per level.
 """
 from __future__ import annotations
@@ -32,6 +40,7 @@ import scipy.linalg as sla
 import scipy.sparse as sp
 
 STRENGTH_FLOOR = 1e-12
+LANCZOS_STEPS = 20
 
 
 def pcg(apply_A, b, x0, apply_M, rtol, maxit):
@@ -131,11 +140,58 @@ def gershgorin_rho(A):
     return float(np.max(rowsum / np.abs(A.diagonal())))
 
 
+def splitmix64_unit(n):
+    """Start vector of the Lanczos estimate: entry i is the splitmix64 output
+    for the counter i + 1 (Steele, Lea & Flood 2014: add the golden-ratio
+    increment, then two xor-shift-multiply rounds and a final xor-shift),
+    its top 53 bits scaled to [0, 1), minus 1/2."""
+    u64 = np.uint64
+    with np.errstate(over="ignore"):
+        z = (np.arange(n, dtype=u64) + u64(1)) * u64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> u64(30))) * u64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> u64(27))) * u64(0x94D049BB133111EB)
+        z = z ^ (z >> u64(31))
+    return (z >> u64(11)).astype(np.float64) / 2.0 ** 53 - 0.5
+
+
+def lanczos_rho(A, steps=LANCZOS_STEPS):
+    """Largest Ritz value of `steps` Lanczos steps on S = D^{-1/2} A D^{-1/2}
+    (similar to D^{-1} A, so it has the same eigenvalues), every new vector
+    reorthogonalised twice against all earlier ones; the iteration stops
+    early when the new vector vanishes (below 1e-12 of |S v|: the Krylov
+    space is invariant).  A lower bound of rho(D^{-1} A) that converges to it
+    from below."""
+    A = A.tocsr()
+    n = A.shape[0]
+    s = 1.0 / np.sqrt(A.diagonal())
+    k = min(steps, n)
+    V = np.zeros((k, n))
+    alpha = []
+    beta = []
+    v = splitmix64_unit(n)
+    v /= np.linalg.norm(v)
+    for j in range(k):
+        V[j] = v
+        w = s * (A @ (s * v))
+        alpha.append(float(v @ w))
+        wnorm = float(np.linalg.norm(w))
+        for _ in range(2):
+            w = w - V[:j + 1].T @ (V[:j + 1] @ w)
+        b = float(np.linalg.norm(w))
+        if j == k - 1 or b <= 1e-12 * wnorm:
+            break
+        beta.append(b)
+        v = w / b
+    T = np.diag(alpha) + np.diag(beta, 1) + np.diag(beta, -1)
+    return float(np.linalg.eigvalsh(T)[-1])
+
+
 class Level:
     def __init__(self, A):
         self.A = A.tocsr()
         self.dinv = 1.0 / self.A.diagonal()
-        self.omega = 4.0 / (3.0 * gershgorin_rho(self.A))
+        self.rho = lanczos_rho(self.A)
+        self.omega = 4.0 / (3.0 * self.rho)
         self.P = None
         self.agg = None
 
@@ -153,8 +209,7 @@ class SAHierarchy:
                 break
             n = lev.A.shape[0]
             T = sp.csr_matrix((np.ones(n), (np.arange(n), agg)), shape=(n, nagg))
-            rho = gershgorin_rho(lev.A)
-            w = 4.0 / (3.0 * rho)
+            w = lev.omega
             P = (T - w * (sp.diags(lev.dinv) @ (lev.A @ T))).tocsr()
             P.sort_indices()
             Ac = (P.T @ lev.A @ P).tocsr()

@@ -30,16 +30,26 @@ def _run(cmd):
     subprocess.run(cmd, check=True)
 
 
+def _run_all(cmds):
+    """Run the compile commands side by side; raise if any fails."""
+    procs = []
+    for cmd in cmds:
+        print(" ".join(cmd), flush=True)
+        procs.append((cmd, subprocess.Popen(cmd)))
+    bad = [cmd for cmd, p in procs if p.wait() != 0]
+    if bad:
+        raise subprocess.CalledProcessError(1, bad[0])
+
+
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    objs = []
-    o = os.path.join(BUILD, "setup.o")
-    _run(["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "setup.cpp"), "-o", o])
-    objs.append(o)
+    objs = [os.path.join(BUILD, "setup.o")]
+    cmds = [["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "setup.cpp"), "-o", objs[0]]]
     for name in ("kernels.hip", "nn.hip", "api.hip"):
         o = os.path.join(BUILD, name.replace(".hip", ".o"))
-        _run([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, name), "-o", o])
+        cmds.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, name), "-o", o])
         objs.append(o)
+    _run_all(cmds)
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp])
     shutil.move(tmp, LIB)

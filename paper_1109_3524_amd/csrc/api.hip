@@ -118,6 +118,8 @@ struct ibpm_ctx {
     GridView g{};
     AView A{};
     double ly = 0;
+    WallSides wall_init{};             // wall velocities at the start (per side)
+    int convective = 0;                // 1: the right wall is a convective outflow
     double *walls[2] = {nullptr, nullptr};
     int cur = 0;
     int64_t step = 0;
@@ -1119,8 +1121,8 @@ int solve_velocity_impl(ibpm_ctx *c, const double *rhs, double *q, ibpm_solve_st
 
 void stage_walls(ibpm_ctx *c, const double *q) {
     double uconv = c->prm.uinf * std::cos(c->prm.alpha);
-    launch_walls_update(c->stream, c->g, c->walls[c->cur], c->walls[1 - c->cur], q, uconv,
-                        c->prm.dt, c->ly);
+    launch_walls_update(c->stream, c->g, c->walls[c->cur], c->walls[1 - c->cur], q, c->convective,
+                        uconv, c->prm.dt, c->ly);
 }
 
 void stage_rhs1(ibpm_ctx *c, const double *q, const double *conv_prev, double *r1,
@@ -1130,7 +1132,7 @@ void stage_rhs1(ibpm_ctx *c, const double *q, const double *conv_prev, double *r
 }
 
 void stage_rhs2(ibpm_ctx *c, const double *qstar, double *rhs) {
-    launch_poisson_rhs(c->stream, c->g, c->m.nb, qstar, c->walls[1 - c->cur], c->E.view(), c->ub,
+    launch_poisson_rhs(c->stream, c->g, c->m.nb, c->m.pin, qstar, c->walls[1 - c->cur], c->E.view(), c->ub,
                        rhs);
 }
 
@@ -1139,6 +1141,35 @@ void stage_project(ibpm_ctx *c, const double *qstar, const double *lam, double *
     launch_project(c->stream, c->g, c->prm.dt, m.nb, qstar, lam, qout, c->Etu.view(), m.fu_i0,
                    m.fu_i1, m.fu_j0, m.fu_j1, c->Etv.view(), m.fv_i0, m.fv_i1, m.fv_j0, m.fv_j1);
     launch_forces(c->stream, (int)m.g.n_cell, m.nb, lam, c->st_misc);
+}
+
+// Wall velocities at the start from the wall kinds: a Dirichlet side keeps
+// (bc_u, bc_v), the convective right side starts at the freestream.  Without
+// a convective wall nothing can balance the wall fluxes, so the Dirichlet
+// walls must carry zero net flux (else the pinned system has no solution).
+void set_walls_spec(ibpm_ctx *c, const GridMetrics &G) {
+    const ibpm_params &p = c->prm;
+    const double U = p.uinf * std::cos(p.alpha), V = p.uinf * std::sin(p.alpha);
+    c->convective = 0;
+    for (int side = 0; side < 4; ++side) {
+        if (p.bc_kind[side] == IBPM_BC_CONVECTIVE) {
+            c->convective = 1;
+            c->wall_init.u[side] = U;
+            c->wall_init.v[side] = V;
+        } else {
+            c->wall_init.u[side] = p.bc_u[side];
+            c->wall_init.v[side] = p.bc_v[side];
+        }
+    }
+    if (!c->convective) {
+        const double lx = G.xf[G.nx] - G.xf[0], ly = G.yf[G.ny] - G.yf[0];
+        const WallSides &w = c->wall_init;
+        const double net = (w.u[1] - w.u[0]) * ly + (w.v[3] - w.v[2]) * lx;
+        const double scale = (std::fabs(w.u[1]) + std::fabs(w.u[0])) * ly +
+                             (std::fabs(w.v[3]) + std::fabs(w.v[2])) * lx;
+        if (std::fabs(net) > 1e-12 * scale)
+            throw InvalidArg("Dirichlet walls (bc_u, bc_v) must carry zero net flux when no wall is convective");
+    }
 }
 
 void check_params(const ibpm_params *p) {
@@ -1152,6 +1183,14 @@ void check_params(const ibpm_params *p) {
     if (p->learned_every < 0) throw InvalidArg("learned_every must be >= 0");
     if (p->fcg_depth < 0 || p->fcg_depth > kFcgMax) throw InvalidArg("fcg_depth must be in [0, 8]");
     if (p->fuse_transfers != 0 && p->fuse_transfers != 1) throw InvalidArg("fuse_transfers must be 0 or 1");
+    for (int side = 0; side < 4; ++side) {
+        const int k = p->bc_kind[side];
+        if (k != IBPM_BC_DIRICHLET && k != IBPM_BC_CONVECTIVE) throw InvalidArg("unknown wall kind (bc_kind)");
+        if (k == IBPM_BC_CONVECTIVE && side != 1)
+            throw InvalidArg("a convective wall (bc_kind) is supported on the right side only");
+        if (k == IBPM_BC_DIRICHLET && (!std::isfinite(p->bc_u[side]) || !std::isfinite(p->bc_v[side])))
+            throw InvalidArg("Dirichlet wall velocities (bc_u, bc_v) must be finite");
+    }
     if (p->poisson_solver != IBPM_SOLVER_JACOBI_PCG) {
         if (p->amg_pre < 1 || p->amg_post < 1) throw InvalidArg("AMG needs >= 1 pre and post sweep");
         if (p->amg_coarse_max < 1 || p->amg_max_levels < 1) throw InvalidArg("bad AMG limits");
@@ -1227,6 +1266,7 @@ K0T<T> make_k0(const GridT<T> &g, double dt, const Model &m, const DevCSRT<T> &c
     K.g = g;
     K.dt = (T)dt;
     K.nb = m.nb;
+    K.pin = m.pin;
     K.n = (int)m.g.n_cell + 2 * m.nb;
     K.cb_i0 = m.cb_i0; K.cb_i1 = m.cb_i1; K.cb_j0 = m.cb_j0; K.cb_j1 = m.cb_j1;
     K.cf = cf.view();
@@ -1366,10 +1406,12 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     c->prm.xf = c->prm.yf = c->prm.xb = c->prm.yb = c->prm.ubx = c->prm.uby = nullptr;
     Model &m = c->m;
     try {
-        build_model(m, p->nx, p->ny, p->xf, p->yf, p->nb, p->xb, p->yb, p->ubx, p->uby, p->nu, p->dt);
+        build_model(m, p->nx, p->ny, p->xf, p->yf, p->nb, p->xb, p->yb, p->ubx, p->uby, p->nu, p->dt,
+                    p->pin_cell);
     } catch (const std::runtime_error &e) {
         throw InvalidArg(e.what());
     }
+    set_walls_spec(c, m.g);
     c->amg = p->poisson_solver != IBPM_SOLVER_JACOBI_PCG;
     c->mixed = p->poisson_solver == IBPM_SOLVER_AMG_PCG_MIXED ||
                p->poisson_solver == IBPM_SOLVER_AMG_FCG_MIXED_LEARNED ||
@@ -1480,9 +1522,8 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     // the update writes two rows of partials (r . r and, for Jacobi, r . z)
     c->parts3 = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
     HIPCHECK(hipHostMalloc((void **)&c->host_st, sizeof(SolveStatus), hipHostMallocDefault));
-    double U = p->uinf * std::cos(p->alpha), V = p->uinf * std::sin(p->alpha);
-    launch_fill_walls(c->stream, c->g, c->walls[0], U, V);
-    launch_fill_walls(c->stream, c->g, c->walls[1], U, V);
+    launch_fill_walls(c->stream, c->g, c->walls[0], c->wall_init);
+    launch_fill_walls(c->stream, c->g, c->walls[1], c->wall_init);
     HIPCHECK(hipStreamSynchronize(c->stream));
 }
 
@@ -1526,8 +1567,8 @@ int ibpm_init_state(ibpm_ctx *c, double *q, double *conv, double *lam) {
         if (!q || !conv || !lam) throw InvalidArg("NULL vector");
         double U = c->prm.uinf * std::cos(c->prm.alpha), V = c->prm.uinf * std::sin(c->prm.alpha);
         launch_init_state(c->stream, c->g, q, conv, lam, c->p64.K0.n, U, V);
-        launch_fill_walls(c->stream, c->g, c->walls[0], U, V);
-        launch_fill_walls(c->stream, c->g, c->walls[1], U, V);
+        launch_fill_walls(c->stream, c->g, c->walls[0], c->wall_init);
+        launch_fill_walls(c->stream, c->g, c->walls[1], c->wall_init);
         c->cur = 0;
         c->step = 0;
         return IBPM_OK;
@@ -1703,6 +1744,62 @@ int ibpm_get_aggregates(const ibpm_ctx *c, int32_t level, int32_t *agg) {
     const std::vector<int32_t> &a = c->h.levels[level].agg;
     std::copy(a.begin(), a.end(), agg);
     return IBPM_OK;
+}
+
+int ibpm_plan_hierarchy(const ibpm_params *p, int32_t cap, int32_t *levels, int64_t *sizes,
+                        int64_t *nnz, double *rho, int32_t agg_level, int32_t *agg,
+                        double *seconds, char *err, int32_t errlen) {
+    auto report = [&](int code, const char *msg) {
+        if (err && errlen > 0) {
+            std::strncpy(err, msg, (size_t)errlen - 1);
+            err[errlen - 1] = '\0';
+        }
+        return code;
+    };
+    try {
+        check_params(p);
+        if (p->poisson_solver == IBPM_SOLVER_JACOBI_PCG) throw InvalidArg("no hierarchy: the Poisson solver is Jacobi-PCG");
+        const auto t0 = std::chrono::steady_clock::now();
+        Model m;
+        try {
+            build_model(m, p->nx, p->ny, p->xf, p->yf, p->nb, p->xb, p->yb, p->ubx, p->uby, p->nu, p->dt,
+                        p->pin_cell);
+        } catch (const std::runtime_error &e) {
+            throw InvalidArg(e.what());
+        }
+        AmgParams ap;
+        ap.theta = p->amg_theta;
+        ap.coarse_max = p->amg_coarse_max;
+        ap.max_levels = p->amg_max_levels;
+        Hierarchy h;
+        try {
+            build_hierarchy(h, m.K, ap);
+        } catch (const std::runtime_error &e) {
+            throw InvalidArg(e.what());
+        }
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        const int L = (int)h.levels.size();
+        if (levels) *levels = L;
+        if ((sizes || nnz || rho) && cap < L) throw InvalidArg("cap is below the level count");
+        for (int l = 0; l < L; ++l) {
+            if (sizes) sizes[l] = h.levels[l].A.nrows;
+            if (nnz) nnz[l] = h.levels[l].A.nnz();
+            if (rho) rho[l] = h.levels[l].rho;
+        }
+        if (agg) {
+            if (agg_level < 0 || agg_level + 1 >= L) throw InvalidArg("agg_level out of range");
+            const std::vector<int32_t> &a = h.levels[agg_level].agg;
+            std::copy(a.begin(), a.end(), agg);
+        }
+        if (seconds) *seconds = secs;
+        return report(IBPM_OK, "");
+    } catch (const InvalidArg &e) {
+        return report(IBPM_EINVAL, e.what());
+    } catch (const std::bad_alloc &) {
+        return report(IBPM_ENOMEM, "out of memory");
+    } catch (const std::exception &e) {
+        return report(IBPM_EINVAL, e.what());
+    }
 }
 
 int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, double *bytes) {

@@ -49,6 +49,11 @@ struct WallOffsets {
     }
 };
 
+// Velocity of each wall side, in the order left, right, bottom, top
+struct WallSides {
+    double u[4], v[4];
+};
+
 template <class T>
 struct CSRT {
     int nrows, ncols;
@@ -73,6 +78,7 @@ struct K0T {
     GridT<T> g;
     T dt;
     int nb, n;                       // n = n_cell + 2 nb
+    int pin;                         // pinned cell: row and column cleared but the diagonal
     int cb_i0, cb_i1, cb_j0, cb_j1;  // box of cells coupled to forces
     CSRT<T> cf;                      // box cells -> (force 0..2nb-1, value)
     CSRT<T> kf;                      // force rows, columns in lambda numbering
@@ -113,19 +119,19 @@ struct SolveStatus {
 // --- launchers (all asynchronous on `s`) ---------------------------------
 // step stages (FP64)
 void launch_walls_update(hipStream_t s, GridView g, const double *w0, double *w1,
-                         const double *q, double uconv, double dt, double ly);
+                         const double *q, int convective, double uconv, double dt, double ly);
 void launch_momentum_rhs(hipStream_t s, GridView g, const double *q, const double *conv_prev,
                          double *conv_now, double *r1, const double *w0, const double *w1,
                          double nu, double dt, int first_step);
-void launch_poisson_rhs(hipStream_t s, GridView g, int nb, const double *qstar, const double *w1,
-                        CSRView E, const double *ub, double *rhs);
+void launch_poisson_rhs(hipStream_t s, GridView g, int nb, int pin, const double *qstar,
+                        const double *w1, CSRView E, const double *ub, double *rhs);
 void launch_project(hipStream_t s, GridView g, double dt, int nb, const double *qstar,
                     const double *lam, double *qout, CSRView etu, int fu_i0, int fu_i1, int fu_j0,
                     int fu_j1, CSRView etv, int fv_i0, int fv_i1, int fv_j0, int fv_j1);
 void launch_forces(hipStream_t s, int n_cell, int nb, const double *lam, SolveStatus *st);
 void launch_init_state(hipStream_t s, GridView g, double *q, double *conv, double *lam, int n_lam,
                        double U, double V);
-void launch_fill_walls(hipStream_t s, GridView g, double *w, double U, double V);
+void launch_fill_walls(hipStream_t s, GridView g, double *w, const WallSides &ws);
 
 // operators
 void launch_apply_K0(hipStream_t s, const K0View &K, const double *x, double *y);

@@ -209,11 +209,12 @@ __device__ __forceinline__ T k0_cell_stencil(const K0T<T> &K, int i, int j, XV x
     const T xe = i < nx - 1 ? xv(row + 1) : T(0);
     diag = ((bw + be) + bs) + bn;
     T y = diag * xc;
-    if (row != 0) {
-        if (row - nx != 0) y -= bs * xs;
-        if (row - 1 != 0) y -= bw * xw;
-        y -= be * xe;
-        y -= bn * xn;
+    const int P = K.pin;
+    if (row != P) {
+        if (row - nx != P) y -= bs * xs;
+        if (row - 1 != P) y -= bw * xw;
+        if (row + 1 != P) y -= be * xe;
+        if (row + nx != P) y -= bn * xn;
     }
     return y;
 }
@@ -296,11 +297,11 @@ __device__ __forceinline__ void k0_tile(const K0T<T> &K, int i, int j0, XV xv, A
         const T diag = ((bw + be) + bs) + bn;
         const T xc = xcol[r + 1];
         T y = diag * xc;
-        if (row != 0) {
-            if (row - nx != 0) y -= bs * xcol[r];
-            if (row - 1 != 0) y -= bw * xwr[r];
-            y -= be * xer[r];
-            y -= bn * xcol[r + 2];
+        if (row != K.pin) {
+            if (row - nx != K.pin) y -= bs * xcol[r];
+            if (row - 1 != K.pin) y -= bw * xwr[r];
+            if (row + 1 != K.pin) y -= be * xer[r];
+            if (row + nx != K.pin) y -= bn * xcol[r + 2];
         }
         if (!BOX || !skip[r]) act(row, y, diag, xc);
     }
@@ -358,11 +359,11 @@ __device__ __forceinline__ void k0_tile_lds(const K0T<T> &K, int i, int j0, XV x
         const T diag = ((bw + be) + bs) + bn;
         const T xc = xcol[r + 1];
         T y = diag * xc;
-        if (row != 0) {
-            if (row - nx != 0) y -= bs * xcol[r];
-            if (row - 1 != 0) y -= bw * xw;
-            y -= be * xe;
-            y -= bn * xcol[r + 2];
+        if (row != K.pin) {
+            if (row - nx != K.pin) y -= bs * xcol[r];
+            if (row - 1 != K.pin) y -= bw * xw;
+            if (row + 1 != K.pin) y -= be * xe;
+            if (row + nx != K.pin) y -= bn * xcol[r + 2];
         }
         act(row, y, diag, xc);
     }
@@ -431,7 +432,7 @@ __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
         const int rb = (j - K.cb_j0) * (K.cb_i1 - K.cb_i0 + 1) + (i - K.cb_i0);
         const T yc = band_row_sum<kCcW>(live, q, lane, K.cc_ell, K.cce_col, K.cce_val, K.cf, rb,
                                         g.n_cell, xv);
-        if (live && lane == 0) act(row, row != 0 ? ys + yc : ys, diag, xc);
+        if (live && lane == 0) act(row, row != K.pin ? ys + yc : ys, diag, xc);
     }
 }
 
@@ -1688,11 +1689,13 @@ __global__ __launch_bounds__(kBlock) void k_momentum_rhs(GridView g, const doubl
 // upwind in time), then a uniform shift of the outflow normal velocity so
 // the net wall flux is zero.  One block.
 __global__ __launch_bounds__(kBlock) void k_walls_update(GridView g, const double *w0, double *w1,
-                                                         const double *q, double uconv, double dt,
-                                                         double ly) {
+                                                         const double *q, int convective,
+                                                         double uconv, double dt, double ly) {
     WallOffsets o = WallOffsets::make(g.nx, g.ny);
     const int t = threadIdx.x;
     for (int k = t; k < o.total; k += kBlock) w1[k] = w0[k];
+    // Dirichlet walls keep their values
+    if (!convective) return;
     __syncthreads();
     const int nx = g.nx, ny = g.ny;
     const double dxl = g.dx[nx - 1];
@@ -1721,8 +1724,8 @@ __global__ __launch_bounds__(kBlock) void k_walls_update(GridView g, const doubl
     for (int j = t; j < ny; j += kBlock) w1[o.uR + j] -= net / ly;
 }
 
-// [-D q* + bc2 ; E q* - u_B] with the n+1 walls; entry 0 (pinned) cleared
-__global__ __launch_bounds__(kBlock) void k_poisson_rhs(GridView g, int nb, const double *qs,
+// [-D q* + bc2 ; E q* - u_B] with the n+1 walls; the pinned entry cleared
+__global__ __launch_bounds__(kBlock) void k_poisson_rhs(GridView g, int nb, int pin, const double *qs,
                                                         const double *w1, CSRView E,
                                                         const double *ub, double *rhs) {
     int row = blockIdx.x * kBlock + threadIdx.x;
@@ -1735,7 +1738,7 @@ __global__ __launch_bounds__(kBlock) void k_poisson_rhs(GridView g, int nb, cons
         double fw = i > 0 ? qs[(size_t)j * nxm + i - 1] : w1[o.uL + j] * g.dy[j];
         double fn = j < g.ny - 1 ? qs[g.n_u + (size_t)j * g.nx + i] : w1[o.vT + i] * g.dx[i];
         double fs = j > 0 ? qs[g.n_u + (size_t)(j - 1) * g.nx + i] : w1[o.vB + i] * g.dx[i];
-        rhs[row] = row == 0 ? 0.0 : -(((fe - fw) + fn) - fs);
+        rhs[row] = row == pin ? 0.0 : -(((fe - fw) + fn) - fs);
     } else if (row < g.n_cell + 2 * nb) {
         int k = row - g.n_cell;
         double s = 0.0;
@@ -1811,11 +1814,20 @@ __global__ __launch_bounds__(kBlock) void k_init_state(GridView g, double *q, do
     if (f < n_lam) lam[f] = 0.0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_fill_walls(GridView g, double *w, double U, double V) {
+// every wall value from the side velocities (left, right, bottom, top)
+__global__ __launch_bounds__(kBlock) void k_fill_walls(GridView g, double *w, WallSides ws) {
     WallOffsets o = WallOffsets::make(g.nx, g.ny);
     for (int k = threadIdx.x; k < o.total; k += kBlock) {
-        bool is_u = (k < o.vB) || (k >= o.uBt && k < o.vLt);
-        w[k] = is_u ? U : V;
+        double v;
+        if (k < o.uR) v = ws.u[0];            // uL: normal, left
+        else if (k < o.vB) v = ws.u[1];       // uR: normal, right
+        else if (k < o.vT) v = ws.v[2];       // vB: normal, bottom
+        else if (k < o.uBt) v = ws.v[3];      // vT: normal, top
+        else if (k < o.uTt) v = ws.u[2];      // uBt: tangential, bottom
+        else if (k < o.vLt) v = ws.u[3];      // uTt: tangential, top
+        else if (k < o.vRt) v = ws.v[0];      // vLt: tangential, left
+        else v = ws.v[1];                     // vRt: tangential, right
+        w[k] = v;
     }
 }
 
@@ -1828,8 +1840,8 @@ __global__ __launch_bounds__(kBlock) void k_fill_walls(GridView g, double *w, do
 #define LAUNCH(kernel, grid, ...) hipLaunchKernelGGL(kernel, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__)
 
 void launch_walls_update(hipStream_t s, GridView g, const double *w0, double *w1, const double *q,
-                         double uconv, double dt, double ly) {
-    LAUNCH(k_walls_update, 1, g, w0, w1, q, uconv, dt, ly);
+                         int convective, double uconv, double dt, double ly) {
+    LAUNCH(k_walls_update, 1, g, w0, w1, q, convective, uconv, dt, ly);
 }
 
 void launch_momentum_rhs(hipStream_t s, GridView g, const double *q, const double *conv_prev,
@@ -1839,10 +1851,10 @@ void launch_momentum_rhs(hipStream_t s, GridView g, const double *q, const doubl
            1.0 / dt, first_step);
 }
 
-void launch_poisson_rhs(hipStream_t s, GridView g, int nb, const double *qstar, const double *w1,
-                        CSRView E, const double *ub, double *rhs) {
+void launch_poisson_rhs(hipStream_t s, GridView g, int nb, int pin, const double *qstar,
+                        const double *w1, CSRView E, const double *ub, double *rhs) {
     int n = g.n_cell + 2 * nb;
-    LAUNCH(k_poisson_rhs, (n + kBlock - 1) / kBlock, g, nb, qstar, w1, E, ub, rhs);
+    LAUNCH(k_poisson_rhs, (n + kBlock - 1) / kBlock, g, nb, pin, qstar, w1, E, ub, rhs);
 }
 
 void launch_project(hipStream_t s, GridView g, double dt, int nb, const double *qstar,
@@ -1862,8 +1874,8 @@ void launch_init_state(hipStream_t s, GridView g, double *q, double *conv, doubl
     LAUNCH(k_init_state, (n + kBlock - 1) / kBlock, g, q, conv, lam, n_lam, U, V);
 }
 
-void launch_fill_walls(hipStream_t s, GridView g, double *w, double U, double V) {
-    LAUNCH(k_fill_walls, 1, g, w, U, V);
+void launch_fill_walls(hipStream_t s, GridView g, double *w, const WallSides &ws) {
+    LAUNCH(k_fill_walls, 1, g, w, ws);
 }
 
 

@@ -9,7 +9,8 @@
 //   G = -D^T with D the interior-face divergence;  E = E^ R^{-1} with
 //   E^_{k,i} = dA_i d_h(x_i - xi_k) d_h(y_i - eta_k)   (Eq. 7),
 //   dA = Dx_i dy_j on u faces and dx_i Dy_j on v faces;
-//   K = Q^T B^1 Q with Q = [G, E^T], pressure cell 0 pinned.
+//   K = Q^T B^1 Q with Q = [G, E^T], one pressure cell pinned (row and
+//   column cleared except the diagonal).
 #include "setup.h"
 
 #include <algorithm>
@@ -166,7 +167,7 @@ void build_coupling(Model &m) {
     int nb = m.nb;
     int64_t nc = g.n_cell;
     const CSR &E = m.E;
-    // cell -> (force, value) for K_{phi f} = G^T B^1 E^T (pinned cell 0 dropped)
+    // cell -> (force, value) for K_{phi f} = G^T B^1 E^T (pinned cell dropped)
     std::map<int64_t, std::map<int32_t, double>> cf;
     // face -> list of (force row, E value), for K_ff and for E^T gathers
     std::map<int64_t, std::vector<std::pair<int32_t, double>>> ft;
@@ -181,8 +182,8 @@ void build_coupling(Model &m) {
             // G^T: a face adds +1 to the cell on its high side, -1 to the low side
             int64_t c_hi = (int64_t)j * g.nx + i;
             int64_t c_lo = is_v ? (int64_t)(j - 1) * g.nx + i : (int64_t)j * g.nx + (i - 1);
-            if (c_hi != 0) cf[c_hi][k] += t;
-            if (c_lo != 0) cf[c_lo][k] -= t;
+            if (c_hi != m.pin) cf[c_hi][k] += t;
+            if (c_lo != m.pin) cf[c_lo][k] -= t;
             ft[f].push_back({k, e});
         }
     }
@@ -305,14 +306,14 @@ void build_full_K(Model &m) {
                 K.col.push_back((int32_t)col);
                 K.val.push_back(v);
             };
-            if (c == 0) {
-                push(0, diag);
-            } else {
-                if (j > 0 && c - nx != 0) push(c - nx, -bs_);
-                if (i > 0 && c - 1 != 0) push(c - 1, -bw_);
+            if (c == m.pin) {
                 push(c, diag);
-                if (i < nx - 1) push(c + 1, -be_);
-                if (j < ny - 1) push(c + nx, -bn_);
+            } else {
+                if (j > 0 && c - nx != m.pin) push(c - nx, -bs_);
+                if (i > 0 && c - 1 != m.pin) push(c - 1, -bw_);
+                push(c, diag);
+                if (i < nx - 1 && c + 1 != m.pin) push(c + 1, -be_);
+                if (j < ny - 1 && c + nx != m.pin) push(c + nx, -bn_);
                 if (i >= m.cb_i0 && i <= m.cb_i1 && j >= m.cb_j0 && j <= m.cb_j1) {
                     int r = (j - m.cb_j0) * bw + (i - m.cb_i0);
                     for (int p = m.Kcf.ptr[r]; p < m.Kcf.ptr[r + 1]; ++p)
@@ -391,8 +392,10 @@ void build_cell_delta(Model &m, const double *xb, const double *yb) {
 
 void build_model(Model &m, int nx, int ny, const double *xf, const double *yf, int nb,
                  const double *xb, const double *yb, const double *ubx, const double *uby,
-                 double nu, double dt) {
+                 double nu, double dt, int pin) {
     build_grid(m.g, nx, ny, xf, yf);
+    if (pin < 0 || (int64_t)pin >= m.g.n_cell) fail("pin_cell must be a cell index in 0..nx*ny-1");
+    m.pin = pin;
     if (nb < 0) fail("nb must be >= 0");
     if (nb > 0 && (!xb || !yb)) fail("body point arrays must not be NULL");
     if (!(nu > 0) || !(dt > 0)) fail("nu and dt must be positive");
@@ -473,8 +476,13 @@ CSR csr_multiply(const CSR &A, const CSR &B) {
 // preconditioner).  Reading of the unstated parameters: strength
 // |a_ij| >= max(theta, 1e-12) sqrt(|a_ii a_jj|); three greedy aggregation
 // passes in natural order; constant tentative prolongator; one damped
-// Jacobi smoothing step of it with weight 4 / (3 rho), rho the Gershgorin
-// bound of D^{-1} A; Galerkin coarse operator.
+// Jacobi smoothing step of it with weight 4 / (3 rho); Galerkin coarse
+// operator.  rho estimates the spectral radius of D^{-1} A (the scaling of
+// the Jacobi weights in Cusp's smoothed aggregation, which Sec. 3 uses): the
+// largest Ritz value of a fixed number of Lanczos steps on D^{-1/2} A D^{-1/2}
+// from a fixed pseudo-random start.  A row-sum (Gershgorin) bound is no
+// substitute on the coupled system: the pressure rows next to the force
+// unknowns push it several times above rho.
 
 namespace {
 
@@ -484,14 +492,105 @@ double diag_of(const CSR &A, int r) {
     return 0.0;
 }
 
-double gershgorin(const CSR &A, const std::vector<double> &d) {
-    double rho = 0.0;
-    for (int r = 0; r < A.nrows; ++r) {
-        double s = 0.0;
-        for (int p = A.ptr[r]; p < A.ptr[r + 1]; ++p) s += std::fabs(A.val[p]);
-        rho = std::max(rho, s / std::fabs(d[r]));
+// splitmix64 output for counter k (Steele, Lea & Flood, OOPSLA 2014): the
+// state advanced k times by the golden-ratio increment, then mixed
+uint64_t splitmix64_at(uint64_t k) {
+    uint64_t z = k * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Number of eigenvalues of the symmetric tridiagonal (a, b) below x
+// (Sturm sequence of the LDL^T pivots).
+int sturm_below(const std::vector<double> &a, const std::vector<double> &b, double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (size_t i = 0; i < a.size(); ++i) {
+        double off = i > 0 ? b[i - 1] * b[i - 1] : 0.0;
+        q = (a[i] - x) - (i > 0 ? off / q : 0.0);
+        if (q == 0.0) q = -1e-300;
+        if (q < 0.0) ++cnt;
     }
-    return rho;
+    return cnt;
+}
+
+// Largest eigenvalue of the symmetric tridiagonal (a, b) by bisection
+// between its Gershgorin limits.
+double tridiag_max_eig(const std::vector<double> &a, const std::vector<double> &b) {
+    const size_t k = a.size();
+    double lo = a[0], hi = a[0];
+    for (size_t i = 0; i < k; ++i) {
+        double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < k ? std::fabs(b[i]) : 0.0);
+        lo = std::min(lo, a[i] - r);
+        hi = std::max(hi, a[i] + r);
+    }
+    for (int it = 0; it < 200 && hi - lo > 1e-15 * std::max(std::fabs(lo), std::fabs(hi)); ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (sturm_below(a, b, mid) == (int)k) hi = mid;   // every eigenvalue below mid
+        else lo = mid;
+    }
+    return hi;
+}
+
+constexpr int kLanczosSteps = 20;
+
+// Spectral radius estimate of D^{-1} A (A symmetric, positive diagonal d):
+// Lanczos on S = D^{-1/2} A D^{-1/2}, which is similar to D^{-1} A, from the
+// start v_i = u(i) - 1/2 with u(i) the top 53 bits of splitmix64(i + 1)
+// over 2^53; each new vector is orthogonalised twice against all earlier
+// ones (classical Gram-Schmidt, repeated), and the iteration ends early when
+// what is left of it is below 1e-12 of |S v| (an invariant Krylov space);
+// the estimate is the largest eigenvalue of the Lanczos tridiagonal.
+double lanczos_rho(const CSR &A, const std::vector<double> &d) {
+    const int n = A.nrows;
+    const int k = std::min(kLanczosSteps, n);
+    std::vector<double> s(n);
+    for (int i = 0; i < n; ++i) s[i] = 1.0 / std::sqrt(d[i]);
+    std::vector<std::vector<double>> V;
+    std::vector<double> v(n), w(n), sv(n), h;
+    double nrm = 0.0;
+    for (int i = 0; i < n; ++i) {
+        v[i] = (double)(splitmix64_at((uint64_t)i + 1) >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        nrm += v[i] * v[i];
+    }
+    nrm = std::sqrt(nrm);
+    for (int i = 0; i < n; ++i) v[i] /= nrm;
+    std::vector<double> alpha, beta;
+    for (int j = 0; j < k; ++j) {
+        V.push_back(v);
+        for (int i = 0; i < n; ++i) sv[i] = s[i] * v[i];
+        double a = 0.0;
+        for (int r = 0; r < n; ++r) {
+            double t = 0.0;
+            for (int p = A.ptr[r]; p < A.ptr[r + 1]; ++p) t += A.val[p] * sv[A.col[p]];
+            w[r] = s[r] * t;
+            a += v[r] * w[r];
+        }
+        alpha.push_back(a);
+        double wn = 0.0;
+        for (int i = 0; i < n; ++i) wn += w[i] * w[i];
+        wn = std::sqrt(wn);
+        for (int pass = 0; pass < 2; ++pass) {
+            h.assign(V.size(), 0.0);
+            for (size_t m = 0; m < V.size(); ++m) {
+                double t = 0.0;
+                for (int i = 0; i < n; ++i) t += V[m][i] * w[i];
+                h[m] = t;
+            }
+            for (size_t m = 0; m < V.size(); ++m)
+                for (int i = 0; i < n; ++i) w[i] -= h[m] * V[m][i];
+        }
+        double b = 0.0;
+        for (int i = 0; i < n; ++i) b += w[i] * w[i];
+        b = std::sqrt(b);
+        if (j == k - 1 || b <= 1e-12 * wn) break;
+        beta.push_back(b);
+        for (int i = 0; i < n; ++i) v[i] = w[i] / b;
+    }
+    beta.resize(alpha.size() > 0 ? alpha.size() - 1 : 0);
+    return tridiag_max_eig(alpha, beta);
 }
 
 // strong-neighbour lists (sorted, excluding the diagonal)
@@ -580,7 +679,9 @@ void finish_level(Level &L) {
         d[r] = diag_of(L.A, r);
         if (!(d[r] > 0)) fail("AMG: non-positive diagonal");
     }
-    L.omega = 4.0 / (3.0 * gershgorin(L.A, d));
+    L.rho = lanczos_rho(L.A, d);
+    if (!(L.rho > 0) || !std::isfinite(L.rho)) fail("AMG: spectral radius estimate failed");
+    L.omega = 4.0 / (3.0 * L.rho);
     L.wdinv.resize(n);
     for (int r = 0; r < n; ++r) L.wdinv[r] = L.omega / d[r];
 }
@@ -640,7 +741,7 @@ void build_hierarchy(Hierarchy &h, const CSR &K, const AmgParams &prm) {
         std::vector<int32_t> agg;
         int32_t nagg = aggregate(n, sptr, sidx, agg);
         if (nagg >= n) break;
-        double w = 4.0 / (3.0 * gershgorin(L.A, d));
+        double w = L.omega;
         CSR P = smoothed_prolongator(L.A, d, agg, nagg, w);
         CSR R = csr_transpose(P);
         CSR RA = csr_multiply(R, L.A);

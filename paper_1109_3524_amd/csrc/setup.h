@@ -33,6 +33,7 @@ struct GridMetrics {
 struct Model {
     GridMetrics g;
     int32_t nb = 0;
+    int32_t pin = 0;                 // pinned pressure cell (row and column cleared)
     double nu = 0, dt = 0;
     std::vector<double> ub;          // 2nb prescribed body velocity (x then y)
     CSR E;                           // 2nb x n_q interpolation (flux form)
@@ -57,7 +58,8 @@ struct Model {
 struct Level {
     CSR A;                           // operator of this level (level 0: copy of K)
     std::vector<double> wdinv;       // omega / a_ii
-    double omega = 0;
+    double rho = 0;                  // spectral radius estimate of D^{-1} A
+    double omega = 0;                // 4 / (3 rho)
     CSR P, R;                        // prolongator to this level from the next, and P^T
     CSR RA, AP;                      // R A and A P where the device fuses the
                                      // residual into the restriction and the
@@ -82,7 +84,7 @@ struct AmgParams {
 void build_grid(GridMetrics &g, int nx, int ny, const double *xf, const double *yf);
 void build_model(Model &m, int nx, int ny, const double *xf, const double *yf, int nb,
                  const double *xb, const double *yb, const double *ubx, const double *uby,
-                 double nu, double dt);
+                 double nu, double dt, int pin = 0);
 void build_hierarchy(Hierarchy &h, const CSR &K, const AmgParams &p);
 // The V-cycle restricted to levels lc..L-1 (pre >= 1 damped-Jacobi sweeps,
 // the first from zero, restriction, recursion, exact solve on the coarsest

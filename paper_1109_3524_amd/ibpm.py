@@ -37,7 +37,7 @@ EXPORTED = (
     "ibpm_get_step", "ibpm_set_step", "ibpm_get_forces", "ibpm_hierarchy_info",
     "ibpm_get_aggregates", "ibpm_time_kernel", "ibpm_nn_init", "ibpm_nn_get_weights",
     "ibpm_nn_set_weights", "ibpm_nn_layer", "ibpm_nn_apply", "ibpm_nn_train",
-    "ibpm_nn_loss_grad", "ibpm_harvest",
+    "ibpm_nn_loss_grad", "ibpm_harvest", "ibpm_plan_hierarchy",
 )
 
 NN_PARAMS = 39168                     # IBPM_NN_PARAMS
@@ -72,6 +72,9 @@ class Params(ctypes.Structure):
         ("inner_rtol", ctypes.c_double), ("learned_every", ctypes.c_int32),
         ("fcg_depth", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
         ("fuse_transfers", ctypes.c_int32),
+        ("pin_cell", ctypes.c_int32),
+        ("bc_kind", ctypes.c_int32 * 4),
+        ("bc_u", ctypes.c_double * 4), ("bc_v", ctypes.c_double * 4),
     ]
 
 
@@ -140,6 +143,9 @@ def load():
         "ibpm_nn_train": [P, P, P, i32, P, i32, i32, ctypes.c_float, D],
         "ibpm_nn_loss_grad": [P, P, P, D, P],
         "ibpm_harvest": [P, P, P, P, i32, P, P, ctypes.POINTER(i32)],
+        "ibpm_plan_hierarchy": [ctypes.POINTER(Params), i32, ctypes.POINTER(i32),
+                                ctypes.POINTER(i64), ctypes.POINTER(i64), D, i32,
+                                ctypes.POINTER(i32), D, ctypes.c_char_p, i32],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -163,9 +169,65 @@ def params_from_workload(wl: W.Workload, **over) -> dict:
              poisson_maxit=wl.poisson_maxit, amg_theta=wl.amg_theta, amg_pre=wl.amg_pre,
              amg_post=wl.amg_post, amg_coarse_max=wl.amg_coarse_max,
              amg_max_levels=wl.amg_max_levels, inner_rtol=0.0, learned_every=1, fcg_depth=0, use_graphs=1,
-             fuse_transfers=1)
+             fuse_transfers=1, pin_cell=wl.pin_cell, bc_kind=tuple(wl.bc_kind))
+    p["bc_u"], p["bc_v"] = wl.wall_velocities()
     p.update(over)
     return p
+
+
+_ARRAYS = ("xf", "yf", "xb", "yb", "ubx", "uby")
+
+
+def make_params(p: dict):
+    """ibpm_params from a dict of params_from_workload; returns the struct
+    and the numpy arrays its pointers refer to (keep them alive)."""
+    st = Params()
+    keep = {}
+    for k, ctype in Params._fields_:
+        v = p[k]
+        if k in _ARRAYS:
+            a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+            if a.size == 0:
+                a = np.zeros(1)
+            keep[k] = a
+            setattr(st, k, _dptr(a))
+        elif k in ("bc_kind", "bc_u", "bc_v"):
+            setattr(st, k, ctype(*v))
+        else:
+            setattr(st, k, v)
+    return st, keep
+
+
+def plan_hierarchy(wl: W.Workload, agg_level: int = -1, **overrides) -> dict:
+    """Host-only set-up of the AMG hierarchy (ibpm_plan_hierarchy): no GPU
+    is touched.  Returns sizes, nnz, rho per level, the aggregates of
+    `agg_level` (if >= 0) and the host set-up time."""
+    L = load()
+    st, keep = make_params(params_from_workload(wl, **overrides))
+    cap = 32
+    nlev = ctypes.c_int32()
+    sizes = np.zeros(cap, np.int64)
+    nnz = np.zeros(cap, np.int64)
+    rho = np.zeros(cap)
+    secs = ctypes.c_double()
+    err = ctypes.create_string_buffer(512)
+    rc = L.ibpm_plan_hierarchy(ctypes.byref(st), cap, ctypes.byref(nlev),
+                               sizes.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                               nnz.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                               _dptr(rho), -1, None, ctypes.byref(secs), err, 512)
+    if rc != IBPM_OK:
+        raise IBPMError(rc, err.value.decode())
+    n = nlev.value
+    out = dict(levels=n, sizes=sizes[:n].copy(), nnz=nnz[:n].copy(), rho=rho[:n].copy(),
+               seconds=secs.value)
+    if agg_level >= 0:
+        agg = np.zeros(int(sizes[agg_level]), np.int32)
+        rc = L.ibpm_plan_hierarchy(ctypes.byref(st), cap, None, None, None, None, agg_level,
+                                   agg.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None, err, 512)
+        if rc != IBPM_OK:
+            raise IBPMError(rc, err.value.decode())
+        out["agg"] = agg
+    return out
 
 
 class Context:
@@ -176,18 +238,7 @@ class Context:
         self._torch = torch
         L = load()
         p = params_from_workload(wl, **overrides)
-        self._arrays = {}
-        st = Params()
-        for k, _ in Params._fields_:
-            v = p[k]
-            if k in ("xf", "yf", "xb", "yb", "ubx", "uby"):
-                a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
-                if a.size == 0:
-                    a = np.zeros(1)
-                self._arrays[k] = a
-                setattr(st, k, _dptr(a))
-            else:
-                setattr(st, k, v)
+        st, self._arrays = make_params(p)
         self.params = p
         self.wl = wl
         self.device = torch.device("cuda", torch.cuda.current_device())

@@ -29,6 +29,12 @@ SOLVER_AMG_FCG_LEARNED = 3
 SOLVER_AMG_FCG_MIXED_LEARNED = 4
 SOLVER_AMG_PCG_FP32_CYCLE = 5
 
+# Wall kinds shared with the C header (ibpm.h), sides ordered left, right,
+# bottom, top.
+BC_DIRICHLET = 0
+BC_CONVECTIVE = 1
+PAPER_WALLS = (BC_DIRICHLET, BC_CONVECTIVE, BC_DIRICHLET, BC_DIRICHLET)
+
 
 def stretch_ratio(n_side: int, h: float, width: float) -> float:
     """Ratio r such that cells h*r, h*r^2, ..., h*r^n_side fill `width`.
@@ -117,7 +123,20 @@ class Workload:
     amg_post: int = 2         # post-smoothing Jacobi sweeps
     amg_coarse_max: int = 256
     amg_max_levels: int = 12
+    pin_cell: int = 0         # pressure cell pinned to 0 (j * nx + i)
+    bc_kind: tuple = PAPER_WALLS   # wall kinds, left / right / bottom / top
+    bc_u: Optional[tuple] = None   # Dirichlet wall velocities per side;
+    bc_v: Optional[tuple] = None   # None: the freestream on every side
     description: str = ""
+
+    def wall_velocities(self):
+        """(u, v) per side (left, right, bottom, top): the given Dirichlet
+        values, else the freestream (uinf, alpha)."""
+        U = self.uinf * math.cos(self.alpha)
+        V = self.uinf * math.sin(self.alpha)
+        bu = tuple(self.bc_u) if self.bc_u is not None else (U, U, U, U)
+        bv = tuple(self.bc_v) if self.bc_v is not None else (V, V, V, V)
+        return bu, bv
 
     @property
     def nx(self) -> int:

@@ -31,28 +31,22 @@ def test_header_symbols_are_exported():
 def test_param_struct_matches_header_order():
     text = open(HEADER).read()
     body = text[text.index("typedef struct ibpm_params"):text.index("} ibpm_params;")]
-    fields = re.findall(r"\b(?:int32_t|double|const double)\s*\*?\s*([a-z_0-9*, ]+);", body)
+    fields = re.findall(r"\b(?:int32_t|double|const double)\s*\*?\s*([a-z_0-9*, \[\]]+);", body)
     flat = []
     for f in fields:
         flat += [x.strip().lstrip("*") for x in f.split(",")]
-    assert flat == [k for k, _ in ibpm.Params._fields_]
+    names = [re.sub(r"\[\d+\]", "", x) for x in flat]
+    assert names == [k for k, _ in ibpm.Params._fields_]
+    # the array members keep their lengths
+    for x in flat:
+        m = re.match(r"([a-z_]+)\[(\d+)\]", x)
+        if m:
+            ctype = dict(ibpm.Params._fields_)[m.group(1)]
+            assert ctype._length_ == int(m.group(2))
 
 
 def _params(wl, **over):
-    p = ibpm.params_from_workload(wl, **over)
-    st = ibpm.Params()
-    keep = []
-    for k, _ in ibpm.Params._fields_:
-        v = p[k]
-        if k in ("xf", "yf", "xb", "yb", "ubx", "uby"):
-            a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
-            if a.size == 0:
-                a = np.zeros(1)
-            keep.append(a)
-            setattr(st, k, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
-        else:
-            setattr(st, k, v)
-    return st, keep
+    return ibpm.make_params(ibpm.params_from_workload(wl, **over))
 
 
 @pytest.mark.parametrize("over,msg", [
@@ -66,6 +60,13 @@ def _params(wl, **over):
     (dict(poisson_solver=4, inner_rtol=1.5), "inner_rtol"),
     (dict(poisson_solver=2, inner_rtol=-1e-3), "inner_rtol"),
     (dict(fuse_transfers=2), "fuse_transfers"),
+    (dict(bc_kind=(0, 2, 0, 0)), "wall kind"),
+    (dict(bc_kind=(1, 0, 0, 0)), "right side only"),
+    (dict(bc_kind=(0, 1, 1, 0)), "right side only"),
+    (dict(bc_kind=(0, 0, 0, 0), bc_u=(1.0, 0.5, 1.0, 1.0)), "zero net flux"),
+    (dict(bc_kind=(0, 1, 0, 0), bc_u=(1.0, 1.0, float("nan"), 1.0)), "finite"),
+    (dict(pin_cell=-1), "pin_cell"),
+    (dict(pin_cell=48 * 48), "pin_cell"),
 ])
 def test_invalid_parameters_are_rejected_on_the_host(over, msg):
     L = ibpm.load()
@@ -94,3 +95,38 @@ def test_null_arguments():
     assert L.ibpm_build_operators(None, None, None) == ibpm.IBPM_EINVAL
     assert L.ibpm_last_error(None) == b""
     assert L.ibpm_sizes(None, None, None) == ibpm.IBPM_EINVAL
+
+
+def test_dirichlet_walls_with_zero_net_flux_are_accepted_on_the_host():
+    # all four walls Dirichlet at the freestream: the net flux is zero, so
+    # the set-up passes the host checks (the plan call touches no GPU)
+    wl = W.cylinder_small(48, 30).replace(poisson_solver=1, bc_kind=(0, 0, 0, 0))
+    out = ibpm.plan_hierarchy(wl)
+    assert out["levels"] >= 2
+
+
+@pytest.mark.parametrize("wl", [W.cylinder_small(96, 60).replace(poisson_solver=1),
+                                W.cylinder_512()], ids=["96", "512"])
+def test_host_hierarchy_matches_the_oracle(wl):
+    """The library's host set-up against the oracle's, with no GPU: the same
+    level sizes, bit-identical aggregates on the finest level, and the same
+    Lanczos spectral-radius estimates (two independent implementations of
+    the same steps from the same start vector) to 1e-12."""
+    from oracle.problem import Problem
+    P = Problem(wl)
+    out = ibpm.plan_hierarchy(wl, agg_level=0)
+    assert list(out["sizes"]) == P.H.sizes()
+    np.testing.assert_array_equal(out["agg"], P.H.levels[0].agg)
+    rho_o = np.array([lev.rho for lev in P.H.levels])
+    np.testing.assert_allclose(out["rho"], rho_o, rtol=1e-12, atol=0)
+    nnz_o = [lev.A.nnz for lev in P.H.levels]
+    # the library keeps explicit zeros the oracle's scipy products drop
+    assert all(a >= b for a, b in zip(out["nnz"], nnz_o))
+
+
+def test_pin_cell_moves_the_pinned_row_on_the_host():
+    wl = W.cylinder_small(48, 30).replace(poisson_solver=1)
+    a = ibpm.plan_hierarchy(wl)
+    b = ibpm.plan_hierarchy(wl.replace(pin_cell=47 * 48 + 47))
+    assert a["levels"] == b["levels"] and list(a["sizes"])[0] == list(b["sizes"])[0]
+    assert a["rho"][0] != b["rho"][0]

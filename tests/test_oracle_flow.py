@@ -144,3 +144,50 @@ def test_convective_outflow_is_exact_for_linear_profiles():
     shift = w1.uR - (walls.uR - U * dt * b)
     np.testing.assert_allclose(shift, shift[0], rtol=0, atol=1e-14)
     np.testing.assert_allclose(w1.vRt[1:-1], walls.vRt[1:-1] - U * dt * c, rtol=0, atol=1e-14)
+
+
+def test_pin_cell_fixes_the_gauge_only():
+    """Pinning any one pressure cell selects the pressure gauge (phi is
+    determined up to a constant, Sec. 2 last paragraph): the projected
+    velocity and the forces are the same for two pin cells, phi vanishes at
+    the pinned cell, and the two pressures differ by a constant."""
+    wl = W.tiny(16, 14, 8, 0.25, dt=0.02, nu=0.05)
+    runs = []
+    for pin in (0, 7 * 16 + 9):
+        P = Problem(wl.replace(pin_cell=pin), vel_rtol=1e-14, poisson_rtol=1e-14)
+        st, infos = P.run(3)
+        assert st.lam[pin] == 0.0
+        runs.append((P, st))
+    (P0, s0), (P1, s1) = runs
+    nc = P0.grid.n_cell
+    assert np.linalg.norm(s0.q - s1.q) < 1e-11 * np.linalg.norm(s0.q)
+    assert np.linalg.norm(s0.lam[nc:] - s1.lam[nc:]) < 1e-9 * np.linalg.norm(s0.lam[nc:])
+    dphi = s0.lam[:nc] - s1.lam[:nc]
+    assert np.ptp(dphi) < 1e-9 * np.abs(s0.lam[:nc]).max()
+
+
+def test_dirichlet_walls_on_every_side():
+    """All four walls Dirichlet (no outflow wall): a uniform flow with the
+    same wall velocity is steady, the walls never change, and with the
+    walls at rest a rotating body sets the fluid in motion with zero net
+    wall flux (the pinned system stays consistent)."""
+    wl = W.tiny(16, 14, 0, stretched=True).replace(alpha=0.3, bc_kind=(0, 0, 0, 0))
+    P = Problem(wl, vel_rtol=1e-14, poisson_rtol=1e-14)
+    st0 = P.initial_state()
+    st, _ = P.run(3)
+    assert np.linalg.norm(st.q - st0.q) < 1e-12 * np.linalg.norm(st0.q)
+    for f in ("uL", "uR", "vB", "vT", "uBt", "uTt", "vLt", "vRt"):
+        assert np.array_equal(getattr(st.walls, f), getattr(st0.walls, f))
+    # a body spinning in a box at rest
+    xb, yb = W.circle_points(24, 0.0, 0.0, 0.4)
+    wl2 = W.tiny(20, 20, 0).replace(xb=xb, yb=yb, ubx=-0.5 * yb, uby=0.5 * xb, uinf=0.0,
+                                    bc_kind=(0, 0, 0, 0), bc_u=(0.0,) * 4, bc_v=(0.0,) * 4)
+    P2 = Problem(wl2, vel_rtol=1e-13, poisson_rtol=1e-13)
+    st2, infos = P2.run(3)
+    g = P2.grid
+    div = P2.ops.D @ st2.q
+    assert np.abs(div).max() < 1e-10 * np.abs(st2.q).max()
+    assert np.abs(st2.q).max() > 1e-3
+    # no-slip on the points to the solver tolerance
+    slip = P2.ops.E @ st2.q - P2.ub
+    assert np.abs(slip).max() < 1e-8

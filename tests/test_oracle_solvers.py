@@ -135,3 +135,51 @@ def test_pcg_zero_rhs_and_immediate_convergence():
     exact = np.linalg.solve(o.K.toarray(), b)
     x, it, res = solvers.jacobi_pcg(o.K, b, exact, 1e-8, 100)
     assert it == 0
+
+
+def test_splitmix64_start_vector_matches_published_outputs():
+    # splitmix64 seeded with 0 (Steele, Lea & Flood 2014; the generator of
+    # Java's SplittableRandom): the first two outputs are the published test
+    # values 0xe220a8397b1dcdaf and 0x6e789e6aa1b965f4
+    v = solvers.splitmix64_unit(2)
+    for got, word in zip(v, (0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4)):
+        assert got == (word >> 11) / 2.0 ** 53 - 0.5
+    w = solvers.splitmix64_unit(100000)
+    assert -0.5 <= w.min() and w.max() < 0.5 and abs(w.mean()) < 0.005
+
+
+@pytest.mark.parametrize("wl", [W.tiny(12, 10, 6), W.tiny(16, 14, 6, 0.2, stretched=True),
+                                W.cylinder_small(96, 60)])
+def test_lanczos_estimate_of_the_jacobi_spectral_radius(wl):
+    # the Ritz estimate behind the SA weights lies within 1 % below the true
+    # rho(D^-1 K) on every level (dense eigenvalues on the small levels,
+    # ARPACK on the 96^2 finest level), so every damped-Jacobi smoother
+    # w D^-1 with w = 4 / (3 rho_est) keeps w * rho_true < 2 (convergent)
+    import scipy.sparse.linalg as sla
+    o = _ops(wl)
+    H = solvers.SAHierarchy(o.K, coarse_max=16)
+    assert len(H.levels) >= 2
+    for lev in H.levels:
+        A = lev.A
+        s = sp.diags(1.0 / np.sqrt(A.diagonal()))
+        S = (s @ A @ s).tocsr()
+        if A.shape[0] <= 2000:
+            true = np.linalg.eigvalsh(S.toarray())[-1]
+        else:
+            true = sla.eigsh(S, k=1, which="LA", return_eigenvectors=False, tol=1e-12)[0]
+        assert lev.rho <= true * (1 + 1e-12)
+        assert lev.rho >= 0.99 * true, (A.shape[0], lev.rho, true)
+        assert lev.omega * true < 2.0
+        assert lev.rho < solvers.gershgorin_rho(A)
+
+
+def test_lanczos_estimate_is_exact_on_a_known_spectrum():
+    # D^-1 A for the 1-D Dirichlet Laplacian tridiag(-1, 2, -1) has the
+    # eigenvalues 1 - cos(k pi / (n + 1)); with as many steps as unknowns
+    # Lanczos reproduces the largest one to rounding
+    n = 20
+    A = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1], format="csr")
+    assert abs(solvers.lanczos_rho(A, steps=n) - (1 - np.cos(n * np.pi / (n + 1)))) < 1e-13
+    # a diagonal matrix with a scaled diagonal: D^-1 A = I, rho = 1 exactly
+    B = sp.diags(np.linspace(1.0, 5.0, 30), format="csr")
+    assert abs(solvers.lanczos_rho(B) - 1.0) < 1e-14
