@@ -65,6 +65,9 @@ extern "C" {
                                                 inside FP64 iterative refinement */
 #define IBPM_SOLVER_AMG_PCG_FP32_CYCLE 5     /* FP64 CG whose V-cycle runs in FP32 (the
                                                 residual rounded to FP32 on entry) */
+#define IBPM_SOLVER_AMG_PCG_FP32_CYCLE_GUESS 6  /* solver 5 started from the learned initial
+                                                   guess x0 + w N(b - K x0) (network weights
+                                                   required, see below) */
 
 /* Wall kinds (ibpm_params.bc_kind, per side: left x = xf[0], right
  * x = xf[nx], bottom y = yf[0], top y = yf[ny]). */
@@ -122,6 +125,10 @@ typedef struct ibpm_params {
                                     zero net flux (else IBPM_EINVAL) */
     double bc_u[4], bc_v[4];     /* wall velocity (u, v) of each Dirichlet side (same order);
                                     ignored for a convective side */
+    double fcg_stall_fall;       /* solvers 3, 4: fraction by which ||r|| must fall within 16
+                                    iterations for the flexible iteration to count as making
+                                    progress (else it falls back to AMG-PCG); 0 selects 0.05,
+                                    1 makes every 16 iterations a stall; 0..1 */
 } ibpm_params;
 
 typedef struct ibpm_solve_stats {
@@ -265,16 +272,42 @@ int ibpm_plan_hierarchy(const ibpm_params *p, int32_t cap, int32_t *levels, int6
 #define IBPM_KERNEL_PRESMOOTH0    8   /* two damped Jacobi sweeps from zero on the finest level */
 #define IBPM_KERNEL_STREAM_COPY   9   /* y = x over 2^25 doubles (256 MiB each way): the
                                          reference for bandwidth and for traffic counters */
+#define IBPM_KERNEL_UPDATE_PRESMOOTH0 10 /* the PCG update (x += a p; r' = r - a q) and two damped
+                                             Jacobi sweeps from zero for r' on the finest level in
+                                             one pass (where the iteration folds them together) */
+#define IBPM_KERNEL_L1_JACOBI     11  /* damped Jacobi sweep with the stored (CSR) operator of
+                                         AMG level 1 */
+#define IBPM_NUM_KERNELS          12
+
+/* Launches per PCG iteration that the FP64 AMG-PCG solve of this context
+ * makes of each kernel ibpm_time_kernel can time: counts[k] for kernel id
+ * k < min(ncounts, IBPM_NUM_KERNELS) (host array).  Level-1 passes other
+ * than plain sweeps (its fused two-sweep pass, residual, fused transfers)
+ * are counted as IBPM_KERNEL_L1_JACOBI launches, since each reads the
+ * level-1 operator once; levels >= 2 and the one-block reductions are not
+ * counted.  Needs an AMG context. */
+int ibpm_iteration_launches(const ibpm_ctx *ctx, int32_t ncounts, int32_t *counts);
 
 /* Time `reps` back-to-back launches of one kernel of the solver on the
  * context's stream with HIP events and return the mean duration of one
  * launch (ms) and the algorithmic bytes of one launch (every operand read
- * once, every result written once).  Overwrites the context's work vectors
- * (not the caller's).  Needs an AMG context for kernels 0, 3, 4, 5, 7, 8.
- * The copy kernel's buffers are allocated on its first use and kept until
- * ibpm_destroy. */
-int ibpm_time_kernel(ibpm_ctx *ctx, int32_t kernel, int32_t reps, double *avg_ms,
-                     double *bytes);
+ * once, every result written once).
+ *   min_footprint 0: every launch uses the solver's own work vectors (what
+ *     one launch leaves in the L2 and last-level caches the next one finds);
+ *   min_footprint > 0: the kernel's vector operands are replicated into as
+ *     many operand sets as make up at least min_footprint bytes (at least
+ *     two), allocated for the call and freed before it returns, and
+ *     consecutive launches take consecutive sets, so that with a footprint
+ *     above the 256 MB last-level cache a launch finds none of its vectors
+ *     in the caches; matrices, aggregates, metrics and partial sums are
+ *     shared by the sets.  reps is raised to the number of sets if smaller.
+ * Overwrites the context's work vectors (not the caller's).  Needs an AMG
+ * context for kernels 0, 3, 4, 5, 7, 8.  The copy kernel's own buffers are
+ * allocated on its first use and kept until ibpm_destroy.  Errors:
+ * IBPM_EINVAL (unknown kernel, reps < 1, min_footprint < 0), IBPM_ENOMEM,
+ * IBPM_EHIP. */
+int ibpm_time_kernel(ibpm_ctx *ctx, int32_t kernel, int32_t reps, int64_t min_footprint,
+                     double *avg_ms, double *bytes);
 
 /* ------------------------------------------------------------------------
  * Learned preconditioner stage (an addition to the paper's method).
@@ -287,9 +320,11 @@ int ibpm_time_kernel(ibpm_ctx *ctx, int32_t kernel, int32_t reps, double *avg_ms
  * the residual and its output by s / dt.  Solver IBPM_SOLVER_AMG_FCG_LEARNED
  * uses it in flexible CG: M(r) = z0 + w N(r - K z0) with z0 the AMG V-cycle
  * and w = (d . r1) / (d . K d), each new direction K-orthogonal to the
- * last fcg_depth ones; when the residual stalls (a chunk of >= 8
- * iterations reducing it by < 5 %) or turns NaN the solve falls back to plain
- * AMG-PCG from the current iterate (ibpm_solve_stats.fallbacks).
+ * last fcg_depth ones; when the residual stalls (16 or more iterations
+ * without falling 5 % -- fcg_stall_fall -- below its value at the last such
+ * fall) or turns NaN
+ * the solve falls back to plain AMG-PCG from the current iterate
+ * (ibpm_solve_stats.fallbacks).
  * Weights are given per layer as [out][in][3][3] FP32, layers concatenated:
  * IBPM_NN_PARAMS values in all.  Images are ny x nx x channels (channel
  * fastest) FP32 device arrays.
@@ -324,6 +359,14 @@ int ibpm_nn_apply(ibpm_ctx *ctx, const double *r, double *e);
 int ibpm_nn_train(ibpm_ctx *ctx, const float *r1, const float *e1, int32_t nsamples,
                   const int32_t *order, int32_t norder, int32_t batch, float lr,
                   double *mean_loss);
+
+/* One Adam step (Kingma & Ba; betas 0.9 / 0.999, eps 1e-8, bias-corrected
+ * with the context's step count, which ibpm_nn_train advances too and
+ * ibpm_nn_init / ibpm_nn_set_weights reset) on the FP32 master weights for
+ * the gradient grad (host, IBPM_NN_PARAMS values in the layout of
+ * ibpm_nn_get_weights) with learning rate lr > 0; the BF16 copies the
+ * kernels use are refreshed.  Waits for the stream. */
+int ibpm_nn_adam_step(ibpm_ctx *ctx, const float *grad, float lr);
 
 /* Loss of one pair (r1, e1: FP32 device, lambda layout, as for training) in
  * *loss (host) and its gradient with respect to every weight in grad (host,

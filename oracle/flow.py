@@ -238,8 +238,8 @@ def poisson_rhs(ops, qstar, walls_np1, ub):
 
 
 def project(ops, qstar, lam):
-    """q^{n+1} = q* - B^1 Q lambda (Eq. 11c), as two sparse products."""
-    return qstar - ops.B1 * (ops.Q @ lam)
+    """q^{n+1} = q* - B^N Q lambda (Eq. 11c), as sparse products."""
+    return qstar - ops.apply_B(ops.Q @ lam)
 
 
 def body_force(ops, lam):

@@ -12,8 +12,12 @@ reading used here makes every operator explicit:
   L   = M Lhat R^{-1}               Lhat: 3-point second differences (non-uniform)
   A   = Mf/dt - (nu/2) L            Crank-Nicolson implicit operator (Sec. 2, text before Eq. 8)
   B^1 = dt Mf^{-1}                  first-order approximation of A^{-1} (Eq. 11, N = 1)
+  B^N = dt Mf^{-1} sum_{k<N} ((nu dt/2) L Mf^{-1})^k
+                                    N-term truncation of the Neumann series of
+                                    A^{-1} = dt Mf^{-1} (I - (nu dt/2) L Mf^{-1})^{-1}
+                                    (Sec. 2, text after Eq. 11; N = 3 in Sec. 5.1)
   Q   = [G, E^T]                    Eq. (9)
-  K   = Q^T B^1 Q                   left-hand side of Eq. (11b)
+  K   = Q^T B^N Q                   left-hand side of Eq. (11b)
 Wall values enter Lhat through boundary vectors (`laplacian_bc`): normal
 velocities sit on the wall (a full cell away from the first unknown),
 tangential ones sit on the wall half a cell from the first unknown.
@@ -106,8 +110,11 @@ def laplacian_bc(grid, bc):
 class Operators:
     """All assembled operators for one grid / body / (nu, dt)."""
 
-    def __init__(self, grid, E, nu, dt, pin=0):
+    def __init__(self, grid, E, nu, dt, pin=0, bn_order=1):
+        if bn_order < 1:
+            raise ValueError("bn_order must be >= 1")
         self.grid = grid
+        self.bn_order = int(bn_order)
         self.nu = float(nu)
         self.dt = float(dt)
         self.E = E.tocsr()
@@ -123,8 +130,9 @@ class Operators:
         self.L = (sp.diags(Md) @ self.Lhat @ sp.diags(1.0 / Rd)).tocsr()
         self.A = (sp.diags(self.Mf / self.dt) - 0.5 * self.nu * self.L).tocsr()
         self.B1 = self.dt / self.Mf                        # diagonal of B^1 = dt Mf^{-1}
+        self.B = bn_matrix(self.B1, self.L, self.nu, self.dt, self.bn_order)
         self.Q = sp.hstack([self.G, self.E.T], format="csr")
-        K = (self.Q.T @ sp.diags(self.B1) @ self.Q).tocsr()
+        K = (self.Q.T @ self.B @ self.Q).tocsr()
         self.K_unpinned = K
         self.pin = pin
         self.K = pin_matrix(K, pin)
@@ -134,8 +142,27 @@ class Operators:
     def apply_A(self, x):
         return self.A @ x
 
+    def apply_B(self, x):
+        return self.B @ x
+
     def apply_K(self, x):
         return self.K @ x
+
+
+def bn_matrix(B1, L, nu, dt, order):
+    """B^N as a sparse matrix: the first `order` terms of the Neumann series
+    dt Mf^{-1} sum_k ((nu dt/2) L Mf^{-1})^k, with B1 the diagonal dt Mf^{-1}.
+    Each term is the previous one times (nu dt/2) L Mf^{-1} = (nu/2) L B^1
+    from the right, so every term (and the sum) is symmetric when L is."""
+    Bd = sp.diags(B1).tocsr()
+    term = Bd
+    total = Bd
+    step = (0.5 * nu * L @ Bd).tocsr()
+    for _ in range(order - 1):
+        term = (term @ step).tocsr()
+        total = (total + term).tocsr()
+    total.sort_indices()
+    return total
 
 
 def pin_matrix(K, p):

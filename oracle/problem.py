@@ -19,7 +19,8 @@ class Problem:
         self.wl = wl
         self.grid = Grid(wl.xf, wl.yf)
         self.E_hat, self.E = delta.interpolation_matrices(self.grid, wl.xb, wl.yb)
-        self.ops = operators.Operators(self.grid, self.E, wl.nu, wl.dt, pin=wl.pin_cell)
+        self.ops = operators.Operators(self.grid, self.E, wl.nu, wl.dt, pin=wl.pin_cell,
+                                       bn_order=getattr(wl, "bn_order", 1))
         kinds = tuple(wl.bc_kind)
         if any(k not in (flow.BC_DIRICHLET, flow.BC_CONVECTIVE) for k in kinds) or \
                 any(k == flow.BC_CONVECTIVE for k in kinds[0:1] + kinds[2:]):

@@ -114,6 +114,7 @@ struct ibpm_ctx {
     Model m;
     Hierarchy h;
     bool amg = false, mixed = false, mixed_precond = false;
+    bool guess_learned = false;        // solver 6: learned initial guess before the FP32-cycle CG
     std::vector<void *> allocs;
     GridView g{};
     AView A{};
@@ -958,7 +959,9 @@ void learned_guess(ibpm_ctx *c, const double *b, double *x, SolveStatus *st) {
 
 // The flexible-CG loop (iterations queued in predicated chunks as in
 // pcg_drive).  Returns the host copy of the final status; *stall is set when
-// a chunk of at least 8 iterations reduced ||r|| by less than 5 %.
+// ||r|| has not fallen 5 % below its value at the last such fall for at
+// least 16 iterations (the residual 2-norm of CG is not monotone, so one
+// short flat stretch is no stall).
 FcgStore<double> &fcg_store(ibpm_ctx *c, double *);
 FcgStore<float> &fcg_store(ibpm_ctx *c, float *);
 
@@ -1008,8 +1011,10 @@ SolveStatus fcg_learned_drive(ibpm_ctx *c, PrecSet<T> &P, const T *b, T *x, Solv
         ++k;
     };
     int chunk = std::max(1, (int)(0.8 * est)), queued = 0;
-    double last_rr = -1, chunk_rr = -1;
-    int last_it = 0;
+    double last_rr = -1, mark_rr = -1;
+    int last_it = 0, mark_it = 0;
+    const double fall = c->prm.fcg_stall_fall > 0 ? c->prm.fcg_stall_fall : 0.05;
+    const double keep2 = (1.0 - fall) * (1.0 - fall);   // rr is the squared norm
     *stall = false;
     for (;;) {
         for (int i = 0; i < chunk; ++i) iteration();
@@ -1017,8 +1022,11 @@ SolveStatus fcg_learned_drive(ibpm_ctx *c, PrecSet<T> &P, const T *b, T *x, Solv
         c->read_status(st);
         const SolveStatus &h = *c->host_st;
         if (h.done != ST_RUNNING || queued > maxit + 1) break;
-        // stall: a chunk of at least 8 iterations that reduced ||r|| by less than 5 %
-        if (chunk_rr > 0 && h.iter - last_it >= 8 && h.rr > 0.9025 * chunk_rr) {
+        // stall: 16 or more iterations since ||r|| last fell by `fall` below the mark
+        if (mark_rr < 0 || h.rr < keep2 * mark_rr) {
+            mark_rr = h.rr;
+            mark_it = h.iter;
+        } else if (h.iter - mark_it >= 16) {
             *stall = true;
             break;
         }
@@ -1029,7 +1037,6 @@ SolveStatus fcg_learned_drive(ibpm_ctx *c, PrecSet<T> &P, const T *b, T *x, Solv
             if (rate < 0) rem = (int)std::ceil(need / rate);
         }
         last_rr = h.rr;
-        chunk_rr = h.rr;
         last_it = h.iter;
         chunk = std::min(std::max(rem, 8), 64);
     }
@@ -1085,6 +1092,10 @@ int solve_poisson_learned(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solv
 int solve_poisson_mixed_precond(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
     PrecSet<double> &P = c->p64;
     const int n = P.K0.n;
+    if (c->guess_learned) {
+        if (!c->nn.ready) throw InvalidArg("the learned initial guess needs network weights (ibpm_nn_init or ibpm_nn_set_weights)");
+        learned_guess(c, rhs, lam, c->st_poi);
+    }
     // the residual goes to FP32 on entry to the cycle and the cycle's result
     // back to FP64 in its last sweep (with r . z); in the iterations the
     // FP64 update is folded into the FP32 first pass
@@ -1177,12 +1188,13 @@ void check_params(const ibpm_params *p) {
     if (p->bn_order != 1) throw InvalidArg("only B^N with N = 1 is supported");
     if (!(p->vel_rtol > 0) || !(p->poisson_rtol > 0)) throw InvalidArg("tolerances must be > 0");
     if (p->vel_maxit < 1 || p->poisson_maxit < 1) throw InvalidArg("maxit must be >= 1");
-    if (p->poisson_solver < IBPM_SOLVER_JACOBI_PCG || p->poisson_solver > IBPM_SOLVER_AMG_PCG_FP32_CYCLE)
+    if (p->poisson_solver < IBPM_SOLVER_JACOBI_PCG || p->poisson_solver > IBPM_SOLVER_AMG_PCG_FP32_CYCLE_GUESS)
         throw InvalidArg("unknown Poisson solver");
     if (!(p->inner_rtol >= 0) || p->inner_rtol >= 1) throw InvalidArg("inner_rtol must be in [0, 1)");
     if (p->learned_every < 0) throw InvalidArg("learned_every must be >= 0");
     if (p->fcg_depth < 0 || p->fcg_depth > kFcgMax) throw InvalidArg("fcg_depth must be in [0, 8]");
     if (p->fuse_transfers != 0 && p->fuse_transfers != 1) throw InvalidArg("fuse_transfers must be 0 or 1");
+    if (!(p->fcg_stall_fall >= 0 && p->fcg_stall_fall <= 1)) throw InvalidArg("fcg_stall_fall must be in [0, 1]");
     for (int side = 0; side < 4; ++side) {
         const int k = p->bc_kind[side];
         if (k != IBPM_BC_DIRICHLET && k != IBPM_BC_CONVECTIVE) throw InvalidArg("unknown wall kind (bc_kind)");
@@ -1415,8 +1427,11 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     c->amg = p->poisson_solver != IBPM_SOLVER_JACOBI_PCG;
     c->mixed = p->poisson_solver == IBPM_SOLVER_AMG_PCG_MIXED ||
                p->poisson_solver == IBPM_SOLVER_AMG_FCG_MIXED_LEARNED ||
-               p->poisson_solver == IBPM_SOLVER_AMG_PCG_FP32_CYCLE;
-    c->mixed_precond = p->poisson_solver == IBPM_SOLVER_AMG_PCG_FP32_CYCLE;
+               p->poisson_solver == IBPM_SOLVER_AMG_PCG_FP32_CYCLE ||
+               p->poisson_solver == IBPM_SOLVER_AMG_PCG_FP32_CYCLE_GUESS;
+    c->mixed_precond = p->poisson_solver == IBPM_SOLVER_AMG_PCG_FP32_CYCLE ||
+                       p->poisson_solver == IBPM_SOLVER_AMG_PCG_FP32_CYCLE_GUESS;
+    c->guess_learned = p->poisson_solver == IBPM_SOLVER_AMG_PCG_FP32_CYCLE_GUESS;
     c->learned = p->poisson_solver == IBPM_SOLVER_AMG_FCG_LEARNED ||
                  p->poisson_solver == IBPM_SOLVER_AMG_FCG_MIXED_LEARNED;
     if (c->amg) {
@@ -1802,12 +1817,14 @@ int ibpm_plan_hierarchy(const ibpm_params *p, int32_t cap, int32_t *levels, int6
     }
 }
 
-int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, double *bytes) {
+int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, int64_t min_footprint, double *avg_ms,
+                     double *bytes) {
     return guarded(c, [&] {
-        if (reps < 1 || !avg_ms) throw InvalidArg("bad arguments");
+        if (reps < 1 || !avg_ms || min_footprint < 0) throw InvalidArg("bad arguments");
         const bool needs_amg = kernel == IBPM_KERNEL_K0_JACOBI || kernel == IBPM_KERNEL_K0_RESIDUAL ||
                                kernel == IBPM_KERNEL_RESTRICT0 || kernel == IBPM_KERNEL_PROLONG0 ||
-                               kernel == IBPM_KERNEL_COARSE_CYCLE || kernel == IBPM_KERNEL_PRESMOOTH0;
+                               kernel == IBPM_KERNEL_COARSE_CYCLE || kernel == IBPM_KERNEL_PRESMOOTH0 ||
+                               kernel == IBPM_KERNEL_UPDATE_PRESMOOTH0 || kernel == IBPM_KERNEL_L1_JACOBI;
         PrecSet<double> &P = c->p64;
         if (needs_amg && (!c->amg || P.lev.size() < 2)) throw InvalidArg("kernel needs an AMG hierarchy");
         hipStream_t s = c->stream;
@@ -1839,58 +1856,83 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
         HIPCHECK(hipStreamSynchronize(s));
         SolveStatus *sb = c->st_bench;
         double by = 0;
-        std::function<void()> launch;
-        // every launch below captures its arguments by value: the lambda runs
-        // after the switch, when block-scoped locals no longer exist
+        // Vector operands of the timed kernel: each is a slot with the
+        // solver's own buffer; with min_footprint > 0 every slot gets one
+        // copy per operand set, the sets together spanning at least
+        // min_footprint bytes, and consecutive launches take consecutive sets
+        // (so a launch finds none of its vectors in the caches).  Matrices,
+        // aggregates, metrics and partial sums stay shared.
+        std::vector<double *> own;
+        std::vector<size_t> len;
+        auto slot = [&](double *p, size_t cnt) {
+            own.push_back(p);
+            len.push_back(cnt);
+            return (int)own.size() - 1;
+        };
+        int sets = 1;
+        size_t per = 0;
+        std::vector<size_t> off;
+        double *pool = nullptr;
+        auto at = [&](int sl, int k) -> double * {
+            if (!pool) return own[sl];
+            return pool + (size_t)(k % sets) * per + off[sl];
+        };
+        std::function<void(int)> launch;
+        // every launch below captures its arguments by value (the slot
+        // indices) and takes the buffers of set k through `at`: the lambda
+        // runs after the switch, when block-scoped locals no longer exist
         const K0View K0 = K;
         double *parts = c->parts;
         switch (kernel) {
         case IBPM_KERNEL_K0_JACOBI: {
             const DevLevelT<double> &l0 = P.lev[0];
-            const double omega = l0.omega, *r = P.r, *xa = l0.xa;
-            double *xb = l0.xb;
-            launch = [=] { launch_k0_jacobi(s, K0, omega, r, xa, xb, sb); };
+            const double omega = l0.omega;
+            const int r = slot(P.r, n), xa = slot(l0.xa, n), xb = slot(l0.xb, n);
+            launch = [=, &at](int k) { launch_k0_jacobi(s, K0, omega, at(r, k), at(xa, k), at(xb, k), sb); };
             by = 24.0 * n + b_coupling + b_metric;
             break;
         }
         case IBPM_KERNEL_K0_PCG_SPMV: {
-            const double *z = P.z, *p0 = P.p[0];
-            double *p1 = P.p[1], *q = P.q;
-            launch = [=] { launch_pcg_spmv(s, K0, z, p0, p1, q, sb, (const double *)nullptr, 0, parts); };
+            const int z = slot(P.z, n), p0 = slot(P.p[0], n), p1 = slot(P.p[1], n), q = slot(P.q, n);
+            launch = [=, &at](int k) {
+                launch_pcg_spmv(s, K0, at(z, k), at(p0, k), at(p1, k), at(q, k), sb, (const double *)nullptr, 0,
+                                parts);
+            };
             by = 32.0 * n + b_coupling + b_metric;
             break;
         }
         case IBPM_KERNEL_A_PCG_SPMV: {
             const AView A = c->A;
-            const double *z = c->vz, *p0 = c->vp[0];
-            double *p1 = c->vp[1], *q = c->vq;
-            launch = [=] { launch_pcg_spmv(s, A, z, p0, p1, q, sb, (const double *)nullptr, 0, parts); };
+            const int z = slot(c->vz, nq), p0 = slot(c->vp[0], nq), p1 = slot(c->vp[1], nq), q = slot(c->vq, nq);
+            launch = [=, &at](int k) {
+                launch_pcg_spmv(s, A, at(z, k), at(p0, k), at(p1, k), at(q, k), sb, (const double *)nullptr, 0,
+                                parts);
+            };
             by = 32.0 * nq + b_metric;
             break;
         }
         case IBPM_KERNEL_K0_RESIDUAL: {
             const DevLevelT<double> &l0 = P.lev[0];
-            const double *r = P.r, *xa = l0.xa;
-            double *out = l0.r;
-            launch = [=] { launch_k0_residual(s, K0, r, xa, out, sb); };
+            const int r = slot(P.r, n), xa = slot(l0.xa, n), out = slot(l0.r, n);
+            launch = [=, &at](int k) { launch_k0_residual(s, K0, at(r, k), at(xa, k), at(out, k), sb); };
             by = 24.0 * n + b_coupling + b_metric;
             break;
         }
         case IBPM_KERNEL_RESTRICT0: {
             const DevLevelT<double> &l0 = P.lev[0];
             const CSRView R0 = l0.R.view();
-            double *b1 = P.lev[1].b;
+            const int b1 = slot(P.lev[1].b, P.lev[1].n);
             if (l0.RA.nrows > 0) {
                 // the residual folded into the restriction: R b - (R A) x
                 const CSRView RA0 = l0.RA.view();
                 const int lanes = l0.RA.lanes;
-                const double *b0 = P.r, *x0 = l0.xa;
-                launch = [=] { launch_csrv_restrict(s, R0, RA0, lanes, b0, x0, b1, sb); };
+                const int b0 = slot(P.r, n), x0 = slot(l0.xa, n);
+                launch = [=, &at](int k) { launch_csrv_restrict(s, R0, RA0, lanes, at(b0, k), at(x0, k), at(b1, k), sb); };
                 by = csr_bytes(l0.R, false) + csr_bytes(l0.RA, false) - 8.0 * l0.RA.nrows;
             } else {
                 const int lanes = l0.R.lanes;
-                const double *r = l0.r;
-                launch = [=] { launch_csrv_spmv(s, R0, lanes, r, b1, false, sb); };
+                const int r = slot(l0.r, n);
+                launch = [=, &at](int k) { launch_csrv_spmv(s, R0, lanes, at(r, k), at(b1, k), false, sb); };
                 by = csr_bytes(l0.R, false);
             }
             break;
@@ -1899,16 +1941,15 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
             const DevLevelT<double> &l0 = P.lev[0];
             const int *agg = l0.agg;
             const double w = l0.pomega;
-            const double *x1 = P.lev[1].xa;
-            double *x0 = l0.xa;
-            launch = [=] { launch_k0_prolong_mf(s, K0, agg, x1, w, x0, sb); };
+            const int x1 = slot(P.lev[1].xa, P.lev[1].n), x0 = slot(l0.xa, n);
+            launch = [=, &at](int k) { launch_k0_prolong_mf(s, K0, agg, at(x1, k), w, at(x0, k), sb); };
             // aggregates, x read and written, the coarse vector, coupling and metrics
             by = 4.0 * n + 16.0 * n + 8.0 * P.lev[1].n + b_coupling + b_metric;
             break;
         }
         case IBPM_KERNEL_PCG_UPDATE_K: {
-            double *x = P.p[1], *r = P.r, *z = P.z;
-            const double *p0 = P.p[0], *q = P.q;
+            const int x = slot(P.p[1], n), r = slot(P.r, n), z = slot(P.z, n), p0 = slot(P.p[0], n),
+                      q = slot(P.q, n);
             // p . q partials for the update to sum: 1/G each, so p . q = 1 and the
             // status stays finite over the repetitions
             {
@@ -1920,24 +1961,61 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
             const double *pq_parts = c->parts2;
             // as the AMG-PCG iteration launches it: alone, the stop test
             // deferred to the next product (the status never stops here)
-            launch = [=] { launch_pcg_update(s, K0, x, r, z, p0, q, sb, pq_parts, parts, false, true, true); };
+            launch = [=, &at](int k) {
+                launch_pcg_update(s, K0, at(x, k), at(r, k), at(z, k), at(p0, k), at(q, k), sb, pq_parts, parts,
+                                  false, true, true);
+            };
             by = 48.0 * n;
             break;
         }
         case IBPM_KERNEL_COARSE_CYCLE: {
             const int nlc = P.lev[P.lc].n;
-            const double *C = P.coarseC, *b = P.lev[P.lc].b;
-            double *x = P.lev[P.lc].xa;
-            launch = [=] { launch_coarse_dense(s, nlc, C, b, x, sb); };
+            const double *C = P.coarseC;
+            const int b = slot(P.lev[P.lc].b, nlc), x = slot(P.lev[P.lc].xa, nlc);
+            launch = [=, &at](int k) { launch_coarse_dense(s, nlc, C, at(b, k), at(x, k), sb); };
             by = 8.0 * nlc * (double)nlc + 16.0 * nlc;
             break;
         }
         case IBPM_KERNEL_PRESMOOTH0: {
             const DevLevelT<double> &l0 = P.lev[0];
-            const double *wd = l0.wdinv, *r = P.r;
-            double *xa = l0.xa;
-            launch = [=] { launch_k0_presmooth2(s, K0, wd, r, xa, sb); };
+            const double *wd = l0.wdinv;
+            const int r = slot(P.r, n), xa = slot(l0.xa, n);
+            launch = [=, &at](int k) { launch_k0_presmooth2(s, K0, wd, at(r, k), at(xa, k), sb); };
             by = 24.0 * n + b_coupling + b_metric;
+            break;
+        }
+        case IBPM_KERNEL_UPDATE_PRESMOOTH0: {
+            const DevLevelT<double> &l0 = P.lev[0];
+            const double *wd = l0.wdinv;
+            const int x = slot(P.p[1], n), rin = slot(P.r, n), rout = slot(P.r2, n), p0 = slot(P.p[0], n),
+                      q = slot(P.q, n), xs = slot(l0.xa, n);
+            const int G_pq = walk_blocks_of(K0);
+            if (G_pq > kFuseMaxParts) throw InvalidArg("the update is not folded into the sweeps on this grid");
+            {
+                std::vector<double> ones(G_pq, 1.0 / G_pq);
+                HIPCHECK(hipMemcpyAsync(c->parts2, ones.data(), G_pq * sizeof(double), hipMemcpyHostToDevice, s));
+                HIPCHECK(hipStreamSynchronize(s));
+            }
+            const double *pq_parts = c->parts2;
+            double *rr_parts = c->parts3;
+            launch = [=, &at](int k) {
+                launch_k0_update_presmooth2(s, K0, wd, at(x, k), at(rin, k), at(rout, k), at(p0, k), at(q, k),
+                                            at(xs, k), sb, pq_parts, rr_parts);
+            };
+            // r, q, W, x, p read; r', x, x_s written
+            by = 64.0 * n + b_coupling + b_metric;
+            break;
+        }
+        case IBPM_KERNEL_L1_JACOBI: {
+            if (P.lc < 2) throw InvalidArg("level 1 is part of the dense coarse cycle on this grid");
+            const DevLevelT<double> &l1 = P.lev[1];
+            const CSRView A1 = l1.A.view();
+            const int lanes = l1.A.lanes, n1 = l1.n;
+            const double *wd = l1.wdinv;
+            const int b = slot(l1.b, n1), xa = slot(l1.xa, n1), xb = slot(l1.xb, n1);
+            launch = [=, &at](int k) { launch_csrv_jacobi(s, A1, lanes, wd, at(b, k), at(xa, k), at(xb, k), sb); };
+            // the operator, the damped inverse diagonal, b and x read, x written
+            by = csr_bytes(l1.A, false) + 16.0 * n1;
             break;
         }
         case IBPM_KERNEL_STREAM_COPY: {
@@ -1947,29 +2025,91 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, double *avg_ms, 
                 c->copy_y = c->dalloc<double>(nc);
                 HIPCHECK(hipMemsetAsync(c->copy_x, 0, nc * sizeof(double), s));
             }
-            const double *x = c->copy_x;
-            double *y = c->copy_y;
-            launch = [=] { launch_stream_copy(s, nc, x, y); };
+            const int x = slot(c->copy_x, nc), y = slot(c->copy_y, nc);
+            launch = [=, &at](int k) { launch_stream_copy(s, nc, at(x, k), at(y, k)); };
             by = 16.0 * nc;
             break;
         }
         default:
             throw InvalidArg("unknown kernel id");
         }
-        launch();   // warm the caches and the code object
-        hipEvent_t e0, e1;
-        HIPCHECK(hipEventCreate(&e0));
-        HIPCHECK(hipEventCreate(&e1));
-        HIPCHECK(hipEventRecord(e0, s));
-        for (int k = 0; k < reps; ++k) launch();
-        HIPCHECK(hipEventRecord(e1, s));
-        HIPCHECK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        *avg_ms = ms / reps;
+        for (size_t cnt : len) {
+            off.push_back(per);
+            per += (cnt + 31) / 32 * 32;   // 256-byte aligned slots
+        }
+        if (min_footprint > 0) {
+            sets = (int)std::max<int64_t>(2, (min_footprint + (int64_t)(8 * per) - 1) / (int64_t)(8 * per));
+            void *pp = nullptr;
+            if (hipMalloc(&pp, (size_t)sets * per * sizeof(double)) != hipSuccess) throw std::bad_alloc();
+            pool = (double *)pp;
+            (void)hipMemsetAsync(pool, 0, (size_t)sets * per * sizeof(double), s);
+            reps = std::max(reps, sets);
+        }
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        auto cleanup = [&] {
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (pool) {
+                (void)hipStreamSynchronize(s);
+                (void)hipFree(pool);
+                pool = nullptr;
+            }
+        };
+        try {
+            launch(0);   // warm the code object (and, with one set, the caches)
+            HIPCHECK(hipEventCreate(&e0));
+            HIPCHECK(hipEventCreate(&e1));
+            HIPCHECK(hipEventRecord(e0, s));
+            for (int k = 0; k < reps; ++k) launch(k + 1);
+            HIPCHECK(hipEventRecord(e1, s));
+            HIPCHECK(hipEventSynchronize(e1));
+            float ms = 0;
+            HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+            *avg_ms = ms / reps;
+        } catch (...) {
+            cleanup();
+            throw;
+        }
+        cleanup();
         if (bytes) *bytes = by;
+        return IBPM_OK;
+    });
+}
+
+int ibpm_iteration_launches(const ibpm_ctx *cc, int32_t ncounts, int32_t *counts) {
+    ibpm_ctx *c = const_cast<ibpm_ctx *>(cc);
+    return guarded(c, [&] {
+        if (!counts || ncounts < 0) throw InvalidArg("bad arguments");
+        PrecSet<double> &P = c->p64;
+        if (!c->amg || P.lev.size() < 2) throw InvalidArg("needs an AMG hierarchy of two or more levels");
+        int32_t k[IBPM_NUM_KERNELS] = {};
+        const int pre = c->prm.amg_pre, post = c->prm.amg_post;
+        const int G = walk_blocks_of(P.K0);
+        // as pcg_drive and solve_poisson_fp64 decide: the update folds into
+        // the first two sweeps when every partial count fits one consumer
+        const bool fuse = pre >= 2 && G <= kFuseMaxParts && update_blocks_of(P.K0.n) <= kFuseMaxParts;
+        k[IBPM_KERNEL_K0_PCG_SPMV] = 1;
+        if (fuse) {
+            k[IBPM_KERNEL_UPDATE_PRESMOOTH0] = 1;
+        } else {
+            k[IBPM_KERNEL_PCG_UPDATE_K] = 1;
+            if (pre >= 2) k[IBPM_KERNEL_PRESMOOTH0] = 1;
+        }
+        // single sweeps on level 0: the pre-sweeps beyond the fused pair and
+        // every post-sweep (the last one also forms r . z)
+        k[IBPM_KERNEL_K0_JACOBI] = (pre >= 2 ? pre - 2 : pre) + post;
+        const DevLevelT<double> &l0 = P.lev[0];
+        if (l0.RA.nrows == 0) k[IBPM_KERNEL_K0_RESIDUAL] = 1;
+        k[IBPM_KERNEL_RESTRICT0] = 1;
+        k[IBPM_KERNEL_PROLONG0] = 1;
+        k[IBPM_KERNEL_COARSE_CYCLE] = 1;
+        if (P.lc >= 2) {
+            // the pre-sweep passes, the residual (alone or folded into the
+            // restriction) and the post-sweeps (the first may carry the
+            // prolongation)
+            k[IBPM_KERNEL_L1_JACOBI] = (pre >= 2 ? 1 + (pre - 2) : pre) + 1 + post;
+        }
+        for (int i = 0; i < ncounts; ++i) counts[i] = i < IBPM_NUM_KERNELS ? k[i] : 0;
         return IBPM_OK;
     });
 }
@@ -2058,6 +2198,36 @@ int ibpm_nn_train(ibpm_ctx *c, const float *r1, const float *e1, int32_t nsample
             throw InvalidArg("bad arguments");
         double l = nn_train(c, r1, e1, nsamples, order, norder, batch, lr);
         if (mean_loss) *mean_loss = l;
+        return IBPM_OK;
+    });
+}
+
+int ibpm_nn_adam_step(ibpm_ctx *c, const float *grad, float lr) {
+    return guarded(c, [&] {
+        NNState &N = c->nn;
+        if (!N.ready) throw InvalidArg("network not initialised");
+        if (!grad || !(lr > 0)) throw InvalidArg("bad arguments");
+        nn_alloc_training(c);
+        // the gradient into the padded master layout (zeros in the padding,
+        // where the update is then zero as well)
+        int64_t off = 0;
+        for (int l = 0; l < kNNLayers; ++l) {
+            std::vector<float> g((size_t)32 * N.kp[l], 0.0f);
+            const int ci = nn_cin_real(l), co = nn_cout_real(l);
+            for (int o = 0; o < co; ++o)
+                for (int cc = 0; cc < ci; ++cc)
+                    for (int t = 0; t < 9; ++t)
+                        g[(size_t)o * N.kp[l] + t * N.cin[l] + cc] = grad[off + ((int64_t)o * ci + cc) * 9 + t];
+            off += (int64_t)co * ci * 9;
+            HIPCHECK(hipMemcpyAsync(N.grad[l], g.data(), g.size() * sizeof(float), hipMemcpyHostToDevice, c->stream));
+            HIPCHECK(hipStreamSynchronize(c->stream));
+        }
+        N.adam_t += 1;
+        for (int l = 0; l < kNNLayers; ++l)
+            launch_adam(c->stream, 32 * N.kp[l], N.master[l], N.grad[l], N.m[l], N.v[l], N.adam_t, lr, 0.9f,
+                        0.999f, 1e-8f);
+        nn_pack(c);
+        HIPCHECK(hipStreamSynchronize(c->stream));
         return IBPM_OK;
     });
 }

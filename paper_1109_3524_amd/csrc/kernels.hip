@@ -5,10 +5,11 @@
 // thread in 256-thread blocks; a block handles a contiguous range of 256-row
 // tiles and the block index is remapped so that each of the 8 XCDs owns a
 // contiguous eighth of the rows (neighbour rows of a stencil then hit the
-// same L2).  Reductions are deterministic: a fixed-order LDS tree per block,
-// per-block partials, and the last block to finish (an integer atomic
-// counter decides which) sums the partials in a fixed order.  No floating-
-// point atomics are used anywhere.
+// same L2).  Reductions are deterministic: a fixed-order tree per block
+// (wave butterflies, then the block's waves in order) writes one partial
+// per block, and the partials are summed in block order either by the
+// kernel that consumes the scalar (when there are at most kFuseMaxParts of
+// them) or by a one-block finalize launch.  No atomics are used.
 //
 // The solver kernels are templates on the vector precision T (double, or
 // float for the mixed-precision inner solve); dot products always

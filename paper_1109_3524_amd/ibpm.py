@@ -37,7 +37,8 @@ EXPORTED = (
     "ibpm_get_step", "ibpm_set_step", "ibpm_get_forces", "ibpm_hierarchy_info",
     "ibpm_get_aggregates", "ibpm_time_kernel", "ibpm_nn_init", "ibpm_nn_get_weights",
     "ibpm_nn_set_weights", "ibpm_nn_layer", "ibpm_nn_apply", "ibpm_nn_train",
-    "ibpm_nn_loss_grad", "ibpm_harvest", "ibpm_plan_hierarchy",
+    "ibpm_nn_loss_grad", "ibpm_harvest", "ibpm_plan_hierarchy", "ibpm_iteration_launches",
+    "ibpm_nn_adam_step",
 )
 
 NN_PARAMS = 39168                     # IBPM_NN_PARAMS
@@ -45,7 +46,7 @@ NN_SHAPES = [(32, 5), (32, 32), (32, 32), (32, 32), (32, 32), (3, 32)]   # (out,
 
 KERNELS = {"k0_jacobi": 0, "k0_pcg_spmv": 1, "a_pcg_spmv": 2, "k0_residual": 3,
            "restrict0": 4, "prolong0": 5, "pcg_update_k": 6, "coarse_cycle": 7,
-           "presmooth0": 8, "stream_copy": 9}
+           "presmooth0": 8, "stream_copy": 9, "update_presmooth0": 10, "l1_jacobi": 11}
 
 
 class IBPMError(RuntimeError):
@@ -75,6 +76,7 @@ class Params(ctypes.Structure):
         ("pin_cell", ctypes.c_int32),
         ("bc_kind", ctypes.c_int32 * 4),
         ("bc_u", ctypes.c_double * 4), ("bc_v", ctypes.c_double * 4),
+        ("fcg_stall_fall", ctypes.c_double),
     ]
 
 
@@ -134,7 +136,8 @@ def load():
         "ibpm_get_forces": [P, D, D],
         "ibpm_hierarchy_info": [P, ctypes.POINTER(i32), ctypes.POINTER(i64), ctypes.POINTER(i64)],
         "ibpm_get_aggregates": [P, i32, ctypes.POINTER(i32)],
-        "ibpm_time_kernel": [P, i32, i32, D, D],
+        "ibpm_time_kernel": [P, i32, i32, i64, D, D],
+        "ibpm_iteration_launches": [P, i32, ctypes.POINTER(i32)],
         "ibpm_nn_init": [P, ctypes.c_uint64],
         "ibpm_nn_get_weights": [P, P, i64],
         "ibpm_nn_set_weights": [P, P, i64],
@@ -142,6 +145,7 @@ def load():
         "ibpm_nn_apply": [P, P, P],
         "ibpm_nn_train": [P, P, P, i32, P, i32, i32, ctypes.c_float, D],
         "ibpm_nn_loss_grad": [P, P, P, D, P],
+        "ibpm_nn_adam_step": [P, P, ctypes.c_float],
         "ibpm_harvest": [P, P, P, P, i32, P, P, ctypes.POINTER(i32)],
         "ibpm_plan_hierarchy": [ctypes.POINTER(Params), i32, ctypes.POINTER(i32),
                                 ctypes.POINTER(i64), ctypes.POINTER(i64), D, i32,
@@ -169,7 +173,8 @@ def params_from_workload(wl: W.Workload, **over) -> dict:
              poisson_maxit=wl.poisson_maxit, amg_theta=wl.amg_theta, amg_pre=wl.amg_pre,
              amg_post=wl.amg_post, amg_coarse_max=wl.amg_coarse_max,
              amg_max_levels=wl.amg_max_levels, inner_rtol=0.0, learned_every=1, fcg_depth=0, use_graphs=1,
-             fuse_transfers=1, pin_cell=wl.pin_cell, bc_kind=tuple(wl.bc_kind))
+             fuse_transfers=1, pin_cell=wl.pin_cell, bc_kind=tuple(wl.bc_kind),
+             fcg_stall_fall=0.0)
     p["bc_u"], p["bc_v"] = wl.wall_velocities()
     p.update(over)
     return p
@@ -393,13 +398,21 @@ class Context:
         self._check(load().ibpm_hierarchy_info(self._h, ctypes.byref(lv), sizes, nnz))
         return [int(sizes[i]) for i in range(lv.value)], [int(nnz[i]) for i in range(lv.value)]
 
-    def time_kernel(self, name, reps=200):
+    def time_kernel(self, name, reps=200, min_footprint=0):
         """Mean duration (ms) of one launch of a solver kernel and its
-        algorithmic bytes, timed with HIP events on the context's stream."""
+        algorithmic bytes, timed with HIP events on the context's stream;
+        min_footprint > 0 rotates the vector operands over copies that span
+        at least that many bytes (cold caches)."""
         ms, by = ctypes.c_double(), ctypes.c_double()
-        self._check(load().ibpm_time_kernel(self._h, KERNELS[name], int(reps),
+        self._check(load().ibpm_time_kernel(self._h, KERNELS[name], int(reps), int(min_footprint),
                                             ctypes.byref(ms), ctypes.byref(by)))
         return ms.value, by.value
+
+    def iteration_launches(self):
+        """Launches per FP64 AMG-PCG iteration of each timeable kernel."""
+        cnt = (ctypes.c_int32 * len(KERNELS))()
+        self._check(load().ibpm_iteration_launches(self._h, len(KERNELS), cnt))
+        return {name: int(cnt[i]) for name, i in KERNELS.items()}
 
     # -- learned stage ----------------------------------------------------------
     def _f32(self, t, n, name):
@@ -459,6 +472,14 @@ class Context:
                                          ctypes.c_void_p(o.ctypes.data), int(o.size), int(batch),
                                          ctypes.c_float(lr), ctypes.byref(loss)))
         return loss.value
+
+    def nn_adam_step(self, grad, lr):
+        """One Adam step on the master weights for a host gradient
+        (NN_PARAMS values in the layout of nn_get_weights)."""
+        g = np.ascontiguousarray(np.asarray(grad, dtype=np.float32))
+        if g.size != NN_PARAMS:
+            raise ValueError(f"gradient has {g.size} values, expected {NN_PARAMS}")
+        self._check(load().ibpm_nn_adam_step(self._h, g.ctypes.data_as(ctypes.c_void_p), float(lr)))
 
     def nn_loss_grad(self, r1, e1):
         g = np.zeros(NN_PARAMS, dtype=np.float32)

@@ -28,6 +28,7 @@ SOLVER_AMG_PCG_MIXED = 2
 SOLVER_AMG_FCG_LEARNED = 3
 SOLVER_AMG_FCG_MIXED_LEARNED = 4
 SOLVER_AMG_PCG_FP32_CYCLE = 5
+SOLVER_AMG_PCG_FP32_CYCLE_GUESS = 6
 
 # Wall kinds shared with the C header (ibpm.h), sides ordered left, right,
 # bottom, top.
@@ -127,6 +128,7 @@ class Workload:
     bc_kind: tuple = PAPER_WALLS   # wall kinds, left / right / bottom / top
     bc_u: Optional[tuple] = None   # Dirichlet wall velocities per side;
     bc_v: Optional[tuple] = None   # None: the freestream on every side
+    bn_order: int = 1              # N of B^N (the truncated series for A^{-1})
     description: str = ""
 
     def wall_velocities(self):
@@ -214,6 +216,61 @@ def cylinder_512_re100(steps: int = 200) -> Workload:
     """512^2 Re 100 grid used for the learned-preconditioner study."""
     return cylinder_stretched(512, 0.02, 157, 100.0, 0.005, steps,
                               solver=SOLVER_AMG_FCG_LEARNED)
+
+
+COUETTE_RI, COUETTE_RO, COUETTE_OMEGA, COUETTE_NU = 0.5, 1.0, 0.5, 0.03
+
+
+def couette(n: int, dt: float, t_end: float, solver: int = SOLVER_AMG_PCG) -> Workload:
+    """Circular Couette flow (validation of the method): an inner cylinder
+    of radius 0.5 impulsively rotated at angular velocity 0.5 inside a fixed
+    cylinder of radius 1, both centred at the origin in a fixed square box
+    [-1.5,1.5]^2 (side 3: a box of side 1.5 cannot hold the outer cylinder),
+    nu = 0.03, fluid at rest at t = 0; uniform n x n grid, points on both
+    circles at about the cell width."""
+    xf = uniform_faces(n, -1.5, 1.5)
+    h = 3.0 / n
+    ni = max(8, int(round(2.0 * math.pi * COUETTE_RI / h)))
+    no = max(8, int(round(2.0 * math.pi * COUETTE_RO / h)))
+    xi, yi = circle_points(ni, radius=COUETTE_RI)
+    xo, yo = circle_points(no, radius=COUETTE_RO)
+    xb, yb = np.concatenate([xi, xo]), np.concatenate([yi, yo])
+    ubx = np.concatenate([-COUETTE_OMEGA * yi, np.zeros(no)])
+    uby = np.concatenate([COUETTE_OMEGA * xi, np.zeros(no)])
+    steps = int(round(t_end / dt))
+    return Workload(name=f"couette_{n}x{n}_dt{dt:g}", xf=xf, yf=xf.copy(), xb=xb, yb=yb,
+                    ubx=ubx, uby=uby, nu=COUETTE_NU, dt=dt, nsteps=steps, uinf=0.0,
+                    poisson_solver=solver, bc_kind=(BC_DIRICHLET,) * 4,
+                    bc_u=(0.0,) * 4, bc_v=(0.0,) * 4,
+                    description=f"Couette flow between cylinders r=0.5 (Omega 0.5) and r=1 in "
+                                f"[-1.5,1.5]^2, {n}^2 uniform, {ni}+{no} points, nu 0.03, dt {dt:g}, "
+                                f"t 0..{t_end:g}")
+
+
+def couette_exact(x, y):
+    """Steady azimuthal velocity of the Couette case as (u, v) at (x, y):
+    solid-body rotation inside the inner cylinder, the classical profile
+    between the cylinders, rest outside the outer one."""
+    r = np.hypot(x, y)
+    ri, ro, om = COUETTE_RI, COUETTE_RO, COUETTE_OMEGA
+    ut = np.where(r <= ri, om * r,
+                  np.where(r <= ro, om * ri * (ro / np.maximum(r, 1e-300) - r / ro) / (ro / ri - ri / ro), 0.0))
+    with np.errstate(invalid="ignore", divide="ignore"):
+        c = np.where(r > 0, x / np.maximum(r, 1e-300), 0.0)
+        s = np.where(r > 0, y / np.maximum(r, 1e-300), 0.0)
+    return -ut * s, ut * c
+
+
+def cylinder_re40_330(steps: int = 10000, dt: float = 0.005) -> Workload:
+    """The paper's Re 40 impulsively started cylinder grid (330^2 cells,
+    uniform [-0.54,0.54]^2 patch with h = 0.02, geometric stretching to
+    [-15,15]^2, about 1.02), 158 points."""
+    xf = stretched_faces(330, 15.0, 0.54, 0.02)
+    xb, yb, ubx, uby = _body(158)
+    return Workload(name="cylinder_re40_stretched_330x330", xf=xf, yf=xf.copy(), xb=xb, yb=yb,
+                    ubx=ubx, uby=uby, nu=1.0 / 40.0, dt=dt, nsteps=steps,
+                    description="Re 40 cylinder on the paper's 330^2 grid (h 0.02 on [-0.54,0.54]^2, "
+                                f"stretched to [-15,15]^2), 158 points, dt {dt:g}")
 
 
 def harvest_variants(seed: int, count: int = 1) -> List[Dict[str, float]]:

@@ -168,6 +168,41 @@ def test_adam_pass_lowers_loss_and_is_deterministic():
     np.testing.assert_array_equal(res[0][1], res[1][1])
 
 
+def test_adam_steps_match_oracle():
+    """The device Adam update (k_adam through ibpm_nn_adam_step) against the
+    oracle's Adam step (Kingma & Ba, bias-corrected): five steps from the
+    oracle's He-normal weights on a seeded sequence of gradients whose
+    elements change direction and scale from step to step (so that both
+    moment averages and both bias corrections enter), with two learning
+    rates.  FP32 on the device, FP64 in the oracle: every weight within ten
+    times the FP32 rounding of the weight and of the updates."""
+    wl = LAYER_WL()
+    print(f"[nn adam] {wl.name}", flush=True)
+    ctx = ibpm.Context(wl, poisson_solver=1)
+    chans = [ibpm.NN_SHAPES[0][1]] + [co for co, _ in ibpm.NN_SHAPES]
+    w0 = np.concatenate([x.ravel() for x in nn.init_weights(chans, 4)]).astype(np.float32)
+    ctx.nn_set_weights(w0)
+    w = w0.astype(np.float64)
+    m = np.zeros_like(w)
+    v = np.zeros_like(w)
+    rng = np.random.default_rng(21)
+    lrs = [1e-3, 1e-3, 5e-4, 5e-4, 1e-3]
+    for t, lr in enumerate(lrs, start=1):
+        g = (rng.standard_normal(w.size) * 10.0 ** rng.uniform(-4, 1, w.size)).astype(np.float32)
+        ctx.nn_adam_step(g, lr)
+        w, m, v = nn.adam_step(w, g.astype(np.float64), m, v, t, lr)
+    wg = ctx.nn_get_weights().astype(np.float64)
+    ctx.close()
+    # each update has |m^/(sqrt(v^)+eps)| <= a few units; FP32 evaluates it
+    # to a few ulps and rounds the weight once per step
+    bound = 10.0 * len(lrs) * (2.0 ** -23 * np.abs(w) + 3.0 * 2.0 ** -23 * max(lrs) * 4.0)
+    worst = float(np.max(np.abs(wg - w) / bound))
+    moved = float(np.median(np.abs(wg - w0)))
+    print(f"  worst |w_gpu - w_oracle| / bound {worst:.3f}; median move {moved:.2e}", flush=True)
+    assert worst <= 1.0
+    assert moved > 1e-3
+
+
 def _amg_problem():
     wl = W.cylinder_small(96, 60).replace(poisson_solver=1)
     return wl, Problem(wl, poisson_solver=1, vel_rtol=TIGHT, poisson_rtol=TIGHT)
@@ -242,19 +277,23 @@ def test_learned_solver_matches_oracle_with_any_weights():
     assert abs(s0["iters"] - s1["iters"]) <= 2
     assert _rel(lam0, ref) < 1e-10
     # random weights: the stage is a poor guess but the energy-optimal step
-    # keeps the iteration convergent
-    sr, lamr = _learned_solve(wl, rhs, st.lam, seed=5)
+    # keeps the iteration convergent.  A flexible iteration with a nonlinear
+    # stage stops with a residual of another direction than CG's, and K is
+    # ill-conditioned (cond ~7e6 here), so lambda is compared at a residual
+    # ten times smaller (at 1e-12 it lies 4e-10 from the oracle's)
+    sr, lamr = _learned_solve(wl, rhs, st.lam, seed=5, rtol=TIGHT / 10)
     print(f"  random weights: {sr['iters']} iters, fallbacks {sr['fallbacks']}, "
           f"lambda err {_rel(lamr, ref):.2e}", flush=True)
-    assert sr["relres"] <= TIGHT and _rel(lamr, ref) < 1e-10
+    assert sr["relres"] <= TIGHT / 10 and _rel(lamr, ref) < 1e-10
     # sign-flipped weights
     ctx = ibpm.Context(wl, poisson_solver=1)
     ctx.nn_init(5)
     wneg = -ctx.nn_get_weights()
     ctx.close()
-    sn, lamn = _learned_solve(wl, rhs, st.lam, weights=wneg)
-    print(f"  flipped weights: {sn['iters']} iters, fallbacks {sn['fallbacks']}", flush=True)
-    assert sn["relres"] <= TIGHT and _rel(lamn, ref) < 1e-10
+    sn, lamn = _learned_solve(wl, rhs, st.lam, weights=wneg, rtol=TIGHT / 10)
+    print(f"  flipped weights: {sn['iters']} iters, fallbacks {sn['fallbacks']}, "
+          f"lambda err {_rel(lamn, ref):.2e}", flush=True)
+    assert sn["relres"] <= TIGHT / 10 and _rel(lamn, ref) < 1e-10
     # non-finite weights: the energy-optimal weight of a non-finite correction
     # is taken as 0, so the solve is AMG-PCG
     wnan = np.full(ibpm.NN_PARAMS, np.nan, dtype=np.float32)
@@ -265,21 +304,38 @@ def test_learned_solver_matches_oracle_with_any_weights():
 
 
 def test_learned_solver_falls_back_when_the_residual_stalls():
-    """An unreachable tolerance makes the flexible iteration stall at
-    round-off; the solve hands over to AMG-PCG, whose recursively updated
-    residual keeps falling and meets the test, while the true residual
-    (reported) stays at round-off."""
+    """The stall is forced from the host: with fcg_stall_fall = 1 the
+    residual would have to reach zero within 16 iterations, so the flexible
+    iteration hands over to AMG-PCG after 16 to 23 iterations (checks come
+    at chunk ends), and AMG-PCG from that iterate reaches the oracle's
+    solution."""
     wl, P = _amg_problem()
     print(f"[learned stall] {wl.name}", flush=True)
+    rhs, st = _realistic_rhs(P, wl)
+    ref, _, _ = P.solve_poisson(rhs, st.lam, rtol=TIGHT, maxit=20000)
+    ctx = ibpm.Context(wl, poisson_solver=3, poisson_rtol=TIGHT, poisson_maxit=20000,
+                       fcg_stall_fall=1.0)
+    ctx.nn_init(5)
+    lam = _t(st.lam)
+    s = ctx.solve_poisson(_t(rhs), lam)
+    print(f"  {s}, lambda err {_rel(_n(lam), ref):.2e}", flush=True)
+    assert s["fallbacks"] == 1 and s["status"] == ibpm.IBPM_OK
+    assert s["relres"] <= TIGHT and _rel(_n(lam), ref) < 1e-10
+    ctx.close()
+
+
+def test_learned_solver_falls_back_from_zero_on_nan():
+    """A NaN right-hand side makes the flexible residual NaN; the solve hands
+    over to AMG-PCG from zero, which reports IBPM_ENAN."""
+    wl, P = _amg_problem()
     rhs = W.random_vector(P.ops.K.shape[0], 71)
-    ctx = ibpm.Context(wl, poisson_solver=3, poisson_rtol=1e-20, poisson_maxit=600)
+    rhs[17] = np.nan
+    ctx = ibpm.Context(wl, poisson_solver=3, poisson_rtol=TIGHT, poisson_maxit=200)
     ctx.nn_init(5)
     lam = ctx.zeros_lambda()
     s = ctx.solve_poisson(_t(rhs), lam, allow_fail=True)
     print(f"  {s}", flush=True)
-    assert s["fallbacks"] == 1
-    assert s["status"] in (ibpm.IBPM_OK, ibpm.IBPM_ENOTCONV)
-    assert s["relres"] < 1e-11
+    assert s["fallbacks"] == 1 and s["status"] == ibpm.IBPM_ENAN
     ctx.close()
 
 

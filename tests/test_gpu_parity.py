@@ -255,23 +255,58 @@ def test_trajectory_96_amg_production_tolerance():
 
 
 @pytest.mark.timeout(900)
-def test_trajectory_512_amg_two_steps():
-    """Velocity and lambda to the 1e-10 bar at a 1e-13 residual on both
-    sides.  K is ill-conditioned (its smallest eigenvalue belongs to the
-    interior-pressure / normal-force mode), but in the oracle last-bit
-    changes of K's entries move lambda by about 1e-12 and the AMG-PCG
-    solution at a 1e-13 residual lies 2e-12 from the direct one, so two
-    correct implementations agree far inside the bar.  The GPU lambda is also
-    checked by its backward error in the oracle's operator."""
+def test_lambda_512_solve_at_the_fp64_floor():
+    """One Poisson solve of the 512^2 trajectory (the second step's
+    right-hand side and warm start, both from the oracle) against the exact
+    solution of the oracle's system (sparse LU).  K is ill-conditioned
+    (condition number ~1e9: its smallest eigenvalue belongs to the interior
+    pressure / normal force mode), so two FP64 CG implementations stop at
+    different points of an error floor: as the tolerance tightens past 1e-13
+    the true residual of either levels off near 2.5e-14 and the error with it
+    (the oracle's own AMG-PCG at 1e-11 of the exact solution, the GPU's at
+    5e-11).  The GPU operator agrees with the oracle's to rounding on the
+    exact solution, and the GPU solution lies within the 1e-10 bar of both
+    the exact solution and the oracle's AMG-PCG solution."""
+    import scipy.sparse.linalg as spla
+    wl = W.cylinder_512()
+    P = Problem(wl, poisson_solver=1, vel_rtol=1e-13, poisson_rtol=1e-13)
+    rhs, st = _poisson_rhs_after(P, 1)
+    o = P.ops
+    exact = spla.splu(o.K.tocsc()).solve(rhs)
+    ref, _, _ = P.solve_poisson(rhs, st.lam, rtol=1e-13, maxit=50000)
+    ctx = ibpm.Context(wl, poisson_solver=1, poisson_rtol=1e-13, poisson_maxit=5000)
+    dK = _rel(_n(ctx.apply_K(_t(exact))), o.K @ exact)
+    lam = _t(st.lam)
+    s = ctx.solve_poisson(_t(rhs), lam)
+    ctx.close()
+    lg = _n(lam)
+    print(f"  K on the exact solution: GPU vs oracle {dK:.2e}; GPU solve: relres {s['relres']:.2e}, "
+          f"vs exact {_rel(lg, exact):.2e}, vs oracle AMG-PCG {_rel(lg, ref):.2e} "
+          f"(oracle vs exact {_rel(ref, exact):.2e})", flush=True)
+    assert dK < 1e-15
+    assert s["relres"] <= 1.2e-13
+    assert _rel(lg, exact) < 1e-10 and _rel(lg, ref) < 1e-10
+
+
+@pytest.mark.timeout(900)
+def test_trajectory_512_amg_ten_steps():
+    """Ten steps of the 512^2 cylinder at a 1e-13 residual on both sides:
+    velocity to the 1e-10 bar.  lambda is recomputed every step from the
+    (well-determined) predicted velocity, so its difference stays at the
+    FP64 floor of one ill-conditioned solve (see the test above: ~5e-11 of
+    the exact solution per solve, the oracle's own floor 1e-11) times the
+    spread of two implementations' stopping points, which is bounded here by
+    5e-10; the GPU lambda is also checked by its backward error in the
+    oracle's operator."""
     wl = W.cylinder_512()
     rtol = 1e-13
-    eu, el, g, o = _run_both(wl, 2, 1, rtol)
-    print(f"  512^2 x 2 steps AMG: velocity {eu:.2e} lambda {el:.2e}; iters {[s['last_poisson_iters'] for s in g]}")
-    assert eu < 1e-10 and el < 1e-10
+    eu, el, g, o = _run_both(wl, 10, 1, rtol)
+    print(f"  512^2 x 10 steps AMG: velocity {eu:.2e} lambda {el:.2e}; Fx {g[-1]['fx']:.12f} vs "
+          f"{o[-1].fx:.12f}; iters {[s['last_poisson_iters'] for s in g]} vs {[i.poisson_iters for i in o]}")
+    assert eu < 1e-10 and el < 5e-10
+    assert abs(g[-1]["fx"] - o[-1].fx) < 1e-10 * abs(o[-1].fx)
     # backward error of a GPU Poisson solve in the oracle's system, on the
-    # GPU's own right-hand side of step 2 (the right-hand side is a
-    # divergence, so the two runs' right-hand sides differ relatively more
-    # than their velocities do)
+    # GPU's own right-hand side of step 2
     P = Problem(wl, poisson_solver=1)
     ctx = ibpm.Context(wl, poisson_solver=1, vel_rtol=rtol, poisson_rtol=rtol, poisson_maxit=50000)
     q, conv, lam = ctx.init_state()
@@ -512,7 +547,10 @@ def test_fused_transfers_match_separate_kernels():
         ctx8.close()
         print(f"  1e-13: relres {s['relres']:.2e}, projection diff {d:.2e}; 1e-8: iters {s8['iters']} "
               f"(oracle {it8})")
-        assert s["relres"] <= 1e-13 * 1.01
+        # CG stops on its recursively updated residual; the true residual
+        # recomputed at exit drifts from it by rounding over ~260 iterations
+        # (the oracle's own solve of the second step ends at 1.05e-13)
+        assert s["relres"] <= 1e-13 * 1.2
         assert d < 1e-11
         assert abs(s8["iters"] - it8) <= 2
 
@@ -537,7 +575,7 @@ def test_amg_solve_1024_with_one_block_finalizes():
     K = P.ops.K.tocsr()
     rhs = np.random.default_rng(14).standard_normal(K.shape[0])
     rhs[0] = 0.0
-    for solver in (1, 5):
+    for solver in (1, 5, 2):
         for rtol in (1e-8, 1e-11):
             print(f"[poisson 1024] solver {solver} rtol {rtol:g}", flush=True)
             ctx = ibpm.Context(wl, poisson_solver=solver, poisson_rtol=rtol, poisson_maxit=20000)
@@ -546,7 +584,8 @@ def test_amg_solve_1024_with_one_block_finalizes():
             ctx.close()
             back = np.linalg.norm(rhs - K @ _n(lam)) / np.linalg.norm(rhs)
             print(f"  iters {s['iters']}, relres {s['relres']:.2e}, backward error in the oracle's system {back:.2e}")
-            bound = rtol if rtol >= 1e-8 else 1.5 * rtol
+            # the refinement (solver 2) stops on the FP64 outer residual itself
+            bound = rtol if (rtol >= 1e-8 or solver == 2) else 1.5 * rtol
             assert s["relres"] <= bound
             assert back <= 1.01 * bound
 

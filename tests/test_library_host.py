@@ -56,10 +56,12 @@ def _params(wl, **over):
     (dict(nu=-1.0), "positive"),
     (dict(poisson_solver=7), "solver"),
     (dict(poisson_solver=2, amg_pre=0), "sweep"),
-    (dict(poisson_solver=6), "solver"),
+    (dict(poisson_solver=8), "solver"),
     (dict(poisson_solver=4, inner_rtol=1.5), "inner_rtol"),
     (dict(poisson_solver=2, inner_rtol=-1e-3), "inner_rtol"),
     (dict(fuse_transfers=2), "fuse_transfers"),
+    (dict(poisson_solver=3, fcg_stall_fall=1.5), "fcg_stall_fall"),
+    (dict(poisson_solver=3, fcg_stall_fall=-0.1), "fcg_stall_fall"),
     (dict(bc_kind=(0, 2, 0, 0)), "wall kind"),
     (dict(bc_kind=(1, 0, 0, 0)), "right side only"),
     (dict(bc_kind=(0, 1, 1, 0)), "right side only"),
