@@ -197,6 +197,22 @@ int ibpm_solve_poisson(ibpm_ctx *ctx, const double *rhs, double *lambda,
 int ibpm_solve_velocity(ibpm_ctx *ctx, const double *rhs, double *q,
                         ibpm_solve_stats *stats);
 
+/* ibpm_solve_velocity without any device allocation, for callers that
+ * cannot allocate (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the Jacobi-PCG work vectors, partial
+ * sums and status live in a file-scope device array of the library
+ * (5 * 2^20 + 3 * 3 * 32768 doubles plus the status, about 42 MB per device,
+ * held from the library's first use on a device until the process ends;
+ * its address is looked up once per device by ibpm_build_operators).  The
+ * iterations are launched one by one (no graph is recorded); the results
+ * are those of ibpm_solve_velocity, bit for bit.  Limit: n_q <= 2^20
+ * (1,048,576 flux unknowns, e.g. a 724 x 724 grid), else IBPM_EINVAL.  Every
+ * context on a device shares that device's array: calls that overlap on one
+ * device (two streams, two threads) race and must not be made.  Other
+ * errors as ibpm_solve_velocity. */
+int ibpm_solve_velocity_static(ibpm_ctx *ctx, const double *rhs, double *q,
+                               ibpm_solve_stats *stats);
+
 /* y = K x (pinned Q^T B^1 Q), x and y device n_lambda, distinct. */
 int ibpm_apply_K(ibpm_ctx *ctx, const double *x, double *y);
 

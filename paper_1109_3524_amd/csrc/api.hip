@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -115,6 +116,8 @@ struct ibpm_ctx {
     Hierarchy h;
     bool amg = false, mixed = false, mixed_precond = false;
     bool guess_learned = false;        // solver 6: learned initial guess before the FP32-cycle CG
+    double *static_work = nullptr;     // device address of the file-scope work array on this
+                                       // context's device (ibpm_solve_velocity_static)
     std::vector<void *> allocs;
     GridView g{};
     AView A{};
@@ -1412,6 +1415,45 @@ void alloc_pcg(ibpm_ctx *c, PrecSet<T> &P, int n) {
     for (T *v : {P.p[0], P.p[1]}) HIPCHECK(hipMemsetAsync(v, 0, n * sizeof(T), c->stream));
 }
 
+// Work memory of the allocation-free velocity solve: the five PCG vectors
+// (r, z, two directions, q) of at most kStaticMaxNq values each, three
+// buffers of per-block partial sums (three rows of kMaxParts each, as many
+// as one reduction writes) and the solve status, in one file-scope device
+// array.  Each device that loads the library holds its own copy until the
+// process ends; its address is looked up once per device.
+constexpr int64_t kStaticMaxNq = (int64_t)1 << 20;
+constexpr size_t kStaticVec = (size_t)kStaticMaxNq;
+constexpr size_t kStaticParts = (size_t)3 * kMaxParts;
+constexpr size_t kStaticStatus = (sizeof(SolveStatus) + sizeof(double) - 1) / sizeof(double);
+constexpr size_t kStaticDoubles = 5 * kStaticVec + 3 * kStaticParts + kStaticStatus;
+static __device__ __align__(256) double scratch[kStaticDoubles];
+
+constexpr int kStaticMaxDevices = 64;
+std::mutex g_static_mu;
+double *g_static_ptr[kStaticMaxDevices] = {};
+
+// device address of `scratch` on the current device (host code never uses
+// the array's own name as an address)
+double *static_work_address() {
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kStaticMaxDevices) throw std::runtime_error("device index out of range");
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            throw HipError(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_static_ptr[dev] = (double *)ptr;
+    }
+    return g_static_ptr[dev];
+}
+
+__global__ void k_clear_words(double *w, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w[i] = 0.0;
+}
+
 void build(ibpm_ctx *c, const ibpm_params *p) {
     check_params(p);
     c->prm = *p;
@@ -1446,6 +1488,8 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
         }
         if (p->fuse_transfers) fused_transfer_products(c->h);
     }
+    // every parameter is valid: from here on the device is used
+    c->static_work = static_work_address();
     const GridMetrics &G = m.g;
     c->g = make_grid<double>(c, G);
     c->ly = 0;
@@ -1644,6 +1688,40 @@ int ibpm_solve_velocity(ibpm_ctx *c, const double *rhs, double *q, ibpm_solve_st
     return guarded(c, [&] {
         if (!rhs || !q) throw InvalidArg("NULL vector");
         return solve_velocity_impl(c, rhs, q, stats);
+    });
+}
+
+int ibpm_solve_velocity_static(ibpm_ctx *c, const double *rhs, double *q, ibpm_solve_stats *stats) {
+    return guarded(c, [&] {
+        if (!rhs || !q) throw InvalidArg("NULL vector");
+        const int64_t nq = c->g.n_q;
+        if (nq > kStaticMaxNq)
+            throw InvalidArg("n_q = " + std::to_string(nq) + " exceeds the " + std::to_string(kStaticMaxNq) +
+                             " flux unknowns the static work array holds");
+        double *base = c->static_work;
+        if (!base) throw std::runtime_error("static work array not set up");
+        double *r = base, *z = base + kStaticVec, *qq = base + 4 * kStaticVec;
+        double *dirs[2] = {base + 2 * kStaticVec, base + 3 * kStaticVec};
+        double *parts = base + 5 * kStaticVec;
+        SolveStatus *st = (SolveStatus *)(parts + 3 * kStaticParts);
+        // the array keeps the last call's contents: the status starts cleared
+        // (the vectors and partial sums are written before they are read)
+        hipLaunchKernelGGL(k_clear_words, dim3(1), dim3(64), 0, c->stream, (double *)st, (int)kStaticStatus);
+        HIPCHECK(hipGetLastError());
+        // the solver's kernels take their partial-sum buffers from the
+        // context; point them at the array for this call only
+        struct Restore {
+            ibpm_ctx *c;
+            double *a, *b, *d;
+            ~Restore() { c->parts = a; c->parts2 = b; c->parts3 = d; }
+        } restore{c, c->parts, c->parts2, c->parts3};
+        c->parts = parts;
+        c->parts2 = parts + kStaticParts;
+        c->parts3 = parts + 2 * kStaticParts;
+        std::function<void(const double *, double *)> none;
+        // launched one by one: recording a graph would allocate
+        return pcg_drive<AView, double>(c, c->A, (int)nq, true, none, rhs, q, r, z, dirs, qq, st,
+                                        c->prm.vel_rtol, c->prm.vel_maxit, c->est_vel, false, true, stats, -1);
     });
 }
 

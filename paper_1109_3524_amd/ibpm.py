@@ -38,7 +38,7 @@ EXPORTED = (
     "ibpm_get_aggregates", "ibpm_time_kernel", "ibpm_nn_init", "ibpm_nn_get_weights",
     "ibpm_nn_set_weights", "ibpm_nn_layer", "ibpm_nn_apply", "ibpm_nn_train",
     "ibpm_nn_loss_grad", "ibpm_harvest", "ibpm_plan_hierarchy", "ibpm_iteration_launches",
-    "ibpm_nn_adam_step",
+    "ibpm_nn_adam_step", "ibpm_solve_velocity_static",
 )
 
 NN_PARAMS = 39168                     # IBPM_NN_PARAMS
@@ -123,6 +123,7 @@ def load():
         "ibpm_step": [P, i32, P, P, P, ctypes.POINTER(StepStats)],
         "ibpm_solve_poisson": [P, P, P, ctypes.POINTER(SolveStats)],
         "ibpm_solve_velocity": [P, P, P, ctypes.POINTER(SolveStats)],
+        "ibpm_solve_velocity_static": [P, P, P, ctypes.POINTER(SolveStats)],
         "ibpm_apply_K": [P, P, P],
         "ibpm_apply_A": [P, P, P],
         "ibpm_stage_walls": [P, P],
@@ -324,6 +325,15 @@ class Context:
         s = SolveStats()
         rc = load().ibpm_solve_velocity(self._h, self._vec(rhs, self.n_q, "rhs"),
                                         self._vec(q, self.n_q, "q"), ctypes.byref(s))
+        self._check(rc, allow=(IBPM_ENOTCONV, IBPM_ENAN) if allow_fail else ())
+        return s.as_dict()
+
+    def solve_velocity_static(self, rhs, q, allow_fail=False):
+        """ibpm_solve_velocity_static: the velocity solve with its work
+        memory in the library's static device array (no allocation)."""
+        s = SolveStats()
+        rc = load().ibpm_solve_velocity_static(self._h, self._vec(rhs, self.n_q, "rhs"),
+                                               self._vec(q, self.n_q, "q"), ctypes.byref(s))
         self._check(rc, allow=(IBPM_ENOTCONV, IBPM_ENAN) if allow_fail else ())
         return s.as_dict()
 
