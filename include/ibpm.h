@@ -89,7 +89,12 @@ typedef struct ibpm_params {
     double nu;                   /* kinematic viscosity, > 0 */
     double dt;                   /* time step, > 0 */
     double uinf, alpha;          /* freestream speed and inflow angle (radians) */
-    int32_t bn_order;            /* order N of B^N; only 1 is supported */
+    int32_t bn_order;            /* order N of B^N, the N-term series of A^{-1} (Sec. 2, after
+                                    Eq. 11): 1 or 3 (the two of Sec. 5.1; B^2 is indefinite
+                                    where (nu dt / 2) rho(L Mf^{-1}) > 1).  N = 1 (B^1 = dt Mf^{-1}, diagonal)
+                                    keeps K matrix-free; N > 1 forms K = Q^T B^N Q on the
+                                    device by sliced sparse products (Sec. 4) and supports the
+                                    Jacobi-PCG and AMG-PCG Poisson solvers */
     double vel_rtol;             /* velocity solve: ||r|| <= vel_rtol ||b|| */
     int32_t vel_maxit;
     int32_t poisson_solver;      /* IBPM_SOLVER_* */
@@ -129,6 +134,10 @@ typedef struct ibpm_params {
                                     iterations for the flexible iteration to count as making
                                     progress (else it falls back to AMG-PCG); 0 selects 0.05,
                                     1 makes every 16 iterations a stall; 0..1 */
+    double body_ramp;            /* time over which the prescribed body velocity (ubx, uby) rises
+                                    from rest as sin^2(pi t / (2 body_ramp)), t the time the step
+                                    advances to; 0: the full velocity from the first step (the
+                                    impulsive start of Sec. 5.1); >= 0 */
 } ibpm_params;
 
 typedef struct ibpm_solve_stats {
@@ -213,7 +222,21 @@ int ibpm_solve_velocity(ibpm_ctx *ctx, const double *rhs, double *q,
 int ibpm_solve_velocity_static(ibpm_ctx *ctx, const double *rhs, double *q,
                                ibpm_solve_stats *stats);
 
-/* y = K x (pinned Q^T B^1 Q), x and y device n_lambda, distinct. */
+/* The pinned Poisson operator K = Q^T B^N Q as the context holds it on the
+ * host (for N > 1: the product formed on the device): *nnz receives its
+ * stored entries; ptr (n_lambda + 1), col and val (nnz each), host arrays,
+ * receive its CSR rows (sorted columns) when not NULL. */
+int ibpm_get_poisson_matrix(ibpm_ctx *ctx, int64_t *nnz, int32_t *ptr, int32_t *col, double *val);
+
+/* Sizes of the B^N operators: stored entries of K and of B^N (n_q for the
+ * diagonal B^1), and for N > 1 the device memory of the sliced triple
+ * product -- the largest slice (its B^N Q rows, its K rows and its rows of
+ * Q^T) against the rows of B^N Q over all slices, which an unsliced product
+ * would hold at once (0 for N = 1).  Host outputs, each may be NULL. */
+int ibpm_bn_info(const ibpm_ctx *ctx, int64_t *nnz_K, int64_t *nnz_B, int64_t *peak_bytes,
+                 int64_t *unsliced_bytes);
+
+/* y = K x (pinned Q^T B^N Q), x and y device n_lambda, distinct. */
 int ibpm_apply_K(ibpm_ctx *ctx, const double *x, double *y);
 
 /* y = A x (Mf/dt - nu/2 L on interior faces), x and y device n_q, distinct. */
@@ -297,11 +320,10 @@ int ibpm_plan_hierarchy(const ibpm_params *p, int32_t cap, int32_t *levels, int6
 
 /* Launches per PCG iteration that the FP64 AMG-PCG solve of this context
  * makes of each kernel ibpm_time_kernel can time: counts[k] for kernel id
- * k < min(ncounts, IBPM_NUM_KERNELS) (host array).  Level-1 passes other
- * than plain sweeps (its fused two-sweep pass, residual, fused transfers)
- * are counted as IBPM_KERNEL_L1_JACOBI launches, since each reads the
- * level-1 operator once; levels >= 2 and the one-block reductions are not
- * counted.  Needs an AMG context. */
+ * k < min(ncounts, IBPM_NUM_KERNELS) (host array).  Level 1 counts its plain
+ * damped-Jacobi sweeps only (not its fused two-sweep pass, restriction and
+ * prolongation); levels >= 2 and the one-block reductions are not counted.
+ * Needs an AMG context with B^1. */
 int ibpm_iteration_launches(const ibpm_ctx *ctx, int32_t ncounts, int32_t *counts);
 
 /* Time `reps` back-to-back launches of one kernel of the solver on the

@@ -49,12 +49,18 @@ def delta_h(r, h):
 
 
 def _local_h(faces, widths, x, what):
+    """Width h of the cell holding x.  Every cell that meets the open support
+    (x - 1.5h, x + 1.5h) must have width h: those are the cells whose widths
+    enter the weights (a face inside the support uses the two cells it
+    separates, a cell centre inside it its own cell)."""
     i0 = int(np.searchsorted(faces, x, side="right")) - 1
     n = len(widths)
     if i0 < 2 or i0 > n - 3:
         raise ValueError(f"Lagrangian point {what}={x} is too close to the domain edge")
     h = widths[i0]
-    near = widths[i0 - 2:i0 + 3]
+    first = int(np.searchsorted(faces, x - 1.5 * h, side="right")) - 1
+    last = int(np.searchsorted(faces, x + 1.5 * h, side="left")) - 1
+    near = widths[first:last + 1]
     if np.any(np.abs(near - h) > UNIFORM_RTOL * h):
         raise ValueError(f"grid is not uniform under the delta support at {what}={x}")
     return h

@@ -4,6 +4,8 @@ Oracle code: test infrastructure only.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from . import delta, flow, operators, solvers
@@ -50,8 +52,17 @@ class Problem:
                                    self.wl.uinf, self.wl.alpha)
         return flow.initial_state(self.ops, self.wl.uinf, self.wl.alpha, walls)
 
+    def body_velocity(self, step):
+        """Prescribed body velocity at the time step `step` advances to: the
+        full value, or its sin^2 start-up over the workload's body_ramp."""
+        T = getattr(self.wl, "body_ramp", 0.0)
+        t = (step + 1) * self.wl.dt
+        if T > 0 and t < T:
+            return math.sin(0.5 * math.pi * t / T) ** 2 * self.ub
+        return self.ub
+
     def step(self, state):
-        return flow.step(self.ops, state, self.ub, self.wl.uinf, self.wl.alpha,
+        return flow.step(self.ops, state, self.body_velocity(state.step), self.wl.uinf, self.wl.alpha,
                          self.vel_rtol, self.wl.vel_maxit, self.solve_poisson,
                          self.convective)
 

@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -18,6 +19,7 @@
 #include "kernels.h"
 #include "nn.h"
 #include "setup.h"
+#include "spgemm.h"
 
 using namespace ibpm;
 
@@ -118,6 +120,13 @@ struct ibpm_ctx {
     bool guess_learned = false;        // solver 6: learned initial guess before the FP32-cycle CG
     double *static_work = nullptr;     // device address of the file-scope work array on this
                                        // context's device (ibpm_solve_velocity_static)
+    // B^N with N > 1: the operator B^N and Q (device CSR) for the projection,
+    // the stored level-0 K = Q^T B^N Q with its diagonal, and Q lambda
+    int bn = 1;
+    DevCSR Bn{}, Qd{}, K0c{};
+    CsrOpView K0op{};
+    double *wq = nullptr;
+    int64_t bn_peak_bytes = 0, bn_unsliced_bytes = 0;
     std::vector<void *> allocs;
     GridView g{};
     AView A{};
@@ -164,6 +173,18 @@ struct ibpm_ctx {
         if (e != hipSuccess) throw std::bad_alloc();
         allocs.push_back(p);
         return (T *)p;
+    }
+    // device memory that does not live as long as the context (set-up
+    // temporaries): released by dfree
+    template <class T>
+    T *dtemp(size_t n) {
+        void *p = nullptr;
+        if (n == 0) n = 1;
+        if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+        return (T *)p;
+    }
+    void dfree(const void *p) {
+        if (p) (void)hipFree(const_cast<void *>(p));
     }
     template <class T>
     T *upload(const std::vector<T> &v) {
@@ -559,11 +580,23 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
     return code;
 }
 
+void enqueue_vcycle_csr(ibpm_ctx *c, PrecSet<double> &P, const double *r, double *z, SolveStatus *st);
+
 FcgStore<double> &fcg_store(ibpm_ctx *c, double *) { return c->fcg64; }
 FcgStore<float> &fcg_store(ibpm_ctx *c, float *) { return c->fcg32; }
 
 int solve_poisson_fp64(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
     bool jacobi = !c->amg;
+    if (c->bn > 1) {
+        // B^N with N > 1: the stored K and the all-CSR V-cycle
+        std::function<void(const double *, double *)> pre = [c](const double *r, double *z) {
+            enqueue_vcycle_csr(c, c->p64, r, z, c->st_poi);
+        };
+        PrecSet<double> &P = c->p64;
+        return pcg_drive<CsrOpView, double>(c, c->K0op, c->K0op.A.nrows, jacobi, pre, rhs, lam, P.r, P.z, P.p,
+                                            P.q, c->st_poi, c->prm.poisson_rtol, c->prm.poisson_maxit,
+                                            c->est_poi, false, true, out, 1, nullptr);
+    }
     PrecSet<double> &P = c->p64;
     std::function<void(const double *, double *)> pre = [c](const double *r, double *z) {
         enqueue_vcycle(c, c->p64, r, z, c->st_poi);
@@ -631,8 +664,12 @@ int solve_poisson_mixed(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_
             code = IBPM_ENOTCONV;
             break;
         }
+        // the inner solve aims at a tenth of the outer tolerance, so the last
+        // outer step ends well inside it: the force unknowns (and the drag)
+        // carry the slowest modes, and a residual just under rtol leaves them
+        // further from the FP64 solution than the FP64 solver's own stop does
         double need = rtol * std::sqrt(bb / rr);
-        double tol_in = std::max(0.5 * need, floor_in);
+        double tol_in = std::max(0.1 * need, floor_in);
         const int maxit_in = c->prm.poisson_maxit - inner_total;
         bool add = true;
         if (!plain) {
@@ -1145,13 +1182,31 @@ void stage_rhs1(ibpm_ctx *c, const double *q, const double *conv_prev, double *r
                         c->walls[1 - c->cur], c->prm.nu, c->prm.dt, c->step == 0 ? 1 : 0);
 }
 
+// share of the prescribed body velocity at the time the current step
+// advances to (the start-up ramp of ibpm_params.body_ramp)
+double body_velocity_scale(const ibpm_ctx *c) {
+    const double T = c->prm.body_ramp;
+    if (!(T > 0)) return 1.0;
+    const double t = (double)(c->step + 1) * c->prm.dt;
+    if (t >= T) return 1.0;
+    const double sn = std::sin(0.5 * M_PI * t / T);
+    return sn * sn;
+}
+
 void stage_rhs2(ibpm_ctx *c, const double *qstar, double *rhs) {
     launch_poisson_rhs(c->stream, c->g, c->m.nb, c->m.pin, qstar, c->walls[1 - c->cur], c->E.view(), c->ub,
-                       rhs);
+                       body_velocity_scale(c), rhs);
 }
 
 void stage_project(ibpm_ctx *c, const double *qstar, const double *lam, double *qout) {
     const Model &m = c->m;
+    if (c->bn > 1) {
+        // q = q* - B^N (Q lambda) as a pair of sparse products (Sec. 4)
+        launch_csr_gemv(c->stream, c->Qd.view(), lam, -1.0, nullptr, c->wq);
+        launch_csr_gemv(c->stream, c->Bn.view(), c->wq, 1.0, qstar, qout);
+        launch_forces(c->stream, (int)m.g.n_cell, m.nb, lam, c->st_misc);
+        return;
+    }
     launch_project(c->stream, c->g, c->prm.dt, m.nb, qstar, lam, qout, c->Etu.view(), m.fu_i0,
                    m.fu_i1, m.fu_j0, m.fu_j1, c->Etv.view(), m.fv_i0, m.fv_i1, m.fv_j0, m.fv_j1);
     launch_forces(c->stream, (int)m.g.n_cell, m.nb, lam, c->st_misc);
@@ -1188,7 +1243,11 @@ void set_walls_spec(ibpm_ctx *c, const GridMetrics &G) {
 
 void check_params(const ibpm_params *p) {
     if (!p) throw InvalidArg("params is NULL");
-    if (p->bn_order != 1) throw InvalidArg("only B^N with N = 1 is supported");
+    // N = 2 is left out: B^2 = B^1 (I + S) is indefinite wherever (nu dt / 2) rho(L Mf^-1) > 1
+    // (already on the 512^2 grid), while 1 + s + s^2 > 0 keeps B^3 positive definite
+    if (p->bn_order != 1 && p->bn_order != 3) throw InvalidArg("bn_order must be 1 or 3 (B^1 or B^3)");
+    if (p->bn_order > 1 && p->poisson_solver != IBPM_SOLVER_JACOBI_PCG && p->poisson_solver != IBPM_SOLVER_AMG_PCG)
+        throw InvalidArg("B^N with N > 1 supports the Jacobi-PCG and AMG-PCG Poisson solvers only");
     if (!(p->vel_rtol > 0) || !(p->poisson_rtol > 0)) throw InvalidArg("tolerances must be > 0");
     if (p->vel_maxit < 1 || p->poisson_maxit < 1) throw InvalidArg("maxit must be >= 1");
     if (p->poisson_solver < IBPM_SOLVER_JACOBI_PCG || p->poisson_solver > IBPM_SOLVER_AMG_PCG_FP32_CYCLE_GUESS)
@@ -1198,6 +1257,7 @@ void check_params(const ibpm_params *p) {
     if (p->fcg_depth < 0 || p->fcg_depth > kFcgMax) throw InvalidArg("fcg_depth must be in [0, 8]");
     if (p->fuse_transfers != 0 && p->fuse_transfers != 1) throw InvalidArg("fuse_transfers must be 0 or 1");
     if (!(p->fcg_stall_fall >= 0 && p->fcg_stall_fall <= 1)) throw InvalidArg("fcg_stall_fall must be in [0, 1]");
+    if (!(p->body_ramp >= 0) || !std::isfinite(p->body_ramp)) throw InvalidArg("body_ramp must be finite and >= 0");
     for (int side = 0; side < 4; ++side) {
         const int k = p->bc_kind[side];
         if (k != IBPM_BC_DIRICHLET && k != IBPM_BC_CONVECTIVE) throw InvalidArg("unknown wall kind (bc_kind)");
@@ -1366,10 +1426,18 @@ void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
         DevLevelT<T> &dl = P.lev[l];
         dl.n = hl.A.nrows;
         dl.omega = hl.omega;
-        if (l > 0) {
-            dl.A = c->upload_csr<T>(hl.A);
+        const bool stored = l > 0 || c->bn > 1;   // level 0 is matrix-free only for B^1
+        if (stored) {
+            bool shared = false;
+            if constexpr (std::is_same<T, double>::value) {
+                if (l == 0 && c->bn > 1) {
+                    dl.A = c->K0c;   // the finest operator is the stored K, uploaded once
+                    shared = true;
+                }
+            }
+            if (!shared) dl.A = c->upload_csr<T>(hl.A);
             dl.wdinv = c->upload(std::vector<T>(hl.wdinv.begin(), hl.wdinv.end()));
-            dl.b = c->dalloc<T>(dl.n);
+            if (l > 0) dl.b = c->dalloc<T>(dl.n);
         } else {
             // level 0 is matrix-free; its smoother weights omega / k_ii are
             // formed on the device from the same stencil, and its prolongator
@@ -1383,7 +1451,7 @@ void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
         }
         if (l < L - 1) {
             // level 0 applies its prolongator matrix-free (aggregates + stencil)
-            if (l > 0) dl.P = c->upload_csr<T>(hl.P);
+            if (stored) dl.P = c->upload_csr<T>(hl.P);
             dl.R = c->upload_csr<T>(hl.R);
             dl.r = c->dalloc<T>(dl.n);
             if (hl.RA.nrows > 0) dl.RA = c->upload_csr<T>(hl.RA);
@@ -1413,6 +1481,274 @@ void alloc_pcg(ibpm_ctx *c, PrecSet<T> &P, int n) {
     P.q = c->dalloc<T>(n);
     P.r2 = c->dalloc<T>(n);
     for (T *v : {P.p[0], P.p[1]}) HIPCHECK(hipMemsetAsync(v, 0, n * sizeof(T), c->stream));
+}
+
+// ---------------------------------------------------------------------------
+// B^N with N > 1 (Sec. 2, text after Eq. 11): B^N = B^1 (I + S + ... + S^{N-1})
+// with S = (nu/2) L B^1, formed on the device by row-merge products, and
+// K = Q^T B^N Q formed slice by slice (Sec. 4, triple matrix product): for a
+// slice of K's rows, the faces F its rows of Q^T touch, Y_F = B^N[F, :] Q
+// and then K_slice = Q^T[slice, F] Y_F; only one slice's Y_F and K_slice
+// are held at a time.  K comes back to the host (the smoothed-aggregation
+// set-up needs it there) and is pinned there.
+
+constexpr int kSliceRows = 1 << 18;   // rows of K per slice
+
+// A device CSR built by the product kernels, owned by the caller until
+// free_dev_csr (temporaries) or kept (c->allocs)
+struct ProdCSR {
+    DevCSR m{};
+    int64_t bytes = 0;
+};
+
+DevCSR upload_temp_csr(ibpm_ctx *c, const CSR &h) {
+    DevCSR d;
+    d.nrows = h.nrows;
+    d.ncols = h.ncols;
+    d.nnz = h.nnz();
+    d.lanes = lanes_for(d.nnz, d.nrows);
+    d.ptr = c->dtemp<int32_t>(h.ptr.size());
+    d.col = c->dtemp<int32_t>(h.col.size());
+    d.val = c->dtemp<double>(h.val.size());
+    HIPCHECK(hipMemcpyAsync(d.ptr, h.ptr.data(), h.ptr.size() * sizeof(int32_t), hipMemcpyHostToDevice, c->stream));
+    if (!h.col.empty()) {
+        HIPCHECK(hipMemcpyAsync(d.col, h.col.data(), h.col.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                c->stream));
+        HIPCHECK(hipMemcpyAsync(d.val, h.val.data(), h.val.size() * sizeof(double), hipMemcpyHostToDevice,
+                                c->stream));
+    }
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    return d;
+}
+
+void free_temp_csr(ibpm_ctx *c, DevCSR &d) {
+    c->dfree(d.ptr);
+    c->dfree(d.col);
+    c->dfree(d.val);
+    d = DevCSR();
+}
+
+// row counts (device) -> host offsets -> device CSR arrays of the product
+// rows; `fill` launches the fill kernel with the 64-bit offsets
+template <class Count, class Fill>
+ProdCSR product_rows(ibpm_ctx *c, int nrows, int ncols, Count count, Fill fill, bool keep) {
+    hipStream_t s = c->stream;
+    ProdCSR out;
+    out.m.nrows = nrows;
+    out.m.ncols = ncols;
+    int32_t *cnt = nrows > 0 ? c->dtemp<int32_t>(nrows) : nullptr;
+    int *err = c->dtemp<int>(1);
+    HIPCHECK(hipMemsetAsync(err, 0, sizeof(int), s));
+    count(cnt, err);
+    std::vector<int32_t> h(nrows);
+    int herr = 0;
+    if (nrows > 0) HIPCHECK(hipMemcpyAsync(h.data(), cnt, nrows * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    c->dfree(cnt);
+    c->dfree(err);
+    if (herr) throw InvalidArg("a row of a B^N product has more than 32 left entries");
+    std::vector<int64_t> off(nrows + 1, 0);
+    for (int i = 0; i < nrows; ++i) off[i + 1] = off[i] + h[i];
+    const int64_t nnz = off[nrows];
+    if (nnz >= INT32_MAX) throw InvalidArg("a B^N product has more than 2^31 entries");
+    std::vector<int32_t> p32(off.begin(), off.end());
+    int64_t *off_d = c->dtemp<int64_t>(nrows + 1);
+    HIPCHECK(hipMemcpyAsync(off_d, off.data(), (nrows + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    int32_t *ptr = keep ? c->dalloc<int32_t>(nrows + 1) : c->dtemp<int32_t>(nrows + 1);
+    int32_t *col = keep ? c->dalloc<int32_t>(nnz) : c->dtemp<int32_t>(nnz);
+    double *val = keep ? c->dalloc<double>(nnz) : c->dtemp<double>(nnz);
+    HIPCHECK(hipMemcpyAsync(ptr, p32.data(), (nrows + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    fill(off_d, col, val);
+    HIPCHECK(hipStreamSynchronize(s));
+    c->dfree(off_d);
+    out.m.ptr = ptr;
+    out.m.col = col;
+    out.m.val = val;
+    out.m.nnz = nnz;
+    out.m.lanes = lanes_for(nnz, nrows);
+    out.bytes = 12 * nnz + 4 * (int64_t)(nrows + 1);
+    return out;
+}
+
+void free_prod(ibpm_ctx *c, ProdCSR &p) {
+    free_temp_csr(c, p.m);
+    p = ProdCSR();
+}
+
+// C = A[rows] B (rows null: all rows of A)
+ProdCSR spgemm(ibpm_ctx *c, const DevCSR &A, const int32_t *rows, int nrows, const DevCSR &B, bool keep) {
+    hipStream_t s = c->stream;
+    const CSRView Av = A.view(), Bv = B.view();
+    return product_rows(
+        c, nrows, B.ncols,
+        [&](int32_t *cnt, int *err) { launch_spgemm_count(s, nrows, 0, rows, Av, Bv, cnt, err); },
+        [&](const int64_t *off, int32_t *col, double *val) {
+            launch_spgemm_fill(s, nrows, 0, rows, Av, Bv, off, col, val);
+        },
+        keep);
+}
+
+void form_bn_operators(ibpm_ctx *c) {
+    Model &m = c->m;
+    const ibpm_params &p = c->prm;
+    hipStream_t s = c->stream;
+    const GridMetrics &g = m.g;
+    const int nq = (int)g.n_q, nl = (int)(g.n_cell + 2 * m.nb);
+    // host: L, B^1, S = (nu/2) L B^1, Q^T and Q
+    CSR S = laplacian_csr(g);
+    const std::vector<double> b1 = b1_diagonal(g, p.dt);
+    for (size_t k = 0; k < S.val.size(); ++k) S.val[k] = 0.5 * p.nu * S.val[k] * b1[S.col[k]];
+    const CSR QT = poisson_qt(m);
+    const CSR Qh = csr_transpose(QT);
+    // device: B^N = B^1 (I + X + Y) with X = S and Y = S^2 (N = 3) or empty (N = 2)
+    DevCSR Sd = upload_temp_csr(c, S);
+    double *b1d = c->dtemp<double>(b1.size());
+    HIPCHECK(hipMemcpyAsync(b1d, b1.data(), b1.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    ProdCSR S2;
+    DevCSR Y{};
+    if (p.bn_order >= 3) {
+        S2 = spgemm(c, Sd, nullptr, nq, Sd, false);
+        Y = S2.m;
+    } else {
+        Y.nrows = Y.ncols = nq;
+        Y.ptr = c->dtemp<int32_t>(nq + 1);
+        HIPCHECK(hipMemsetAsync(Y.ptr, 0, (nq + 1) * sizeof(int32_t), s));
+    }
+    const CSRView Xv = Sd.view(), Yv = Y.view();
+    ProdCSR Bn = product_rows(
+        c, nq, nq, [&](int32_t *cnt, int *) { launch_diag_sum_count(s, nq, Xv, Yv, cnt); },
+        [&](const int64_t *off, int32_t *col, double *val) {
+            launch_diag_sum_fill(s, nq, b1d, Xv, Yv, off, col, val);
+        },
+        true);
+    if (p.bn_order >= 3) free_prod(c, S2);
+    else c->dfree(Y.ptr);
+    c->Bn = Bn.m;
+    c->Qd = c->upload_csr<double>(Qh);
+    // K = Q^T B^N Q in slices of rows
+    CSR K;
+    K.nrows = K.ncols = nl;
+    K.ptr.assign(1, 0);
+    std::vector<int32_t> local(nq, -1);
+    int64_t peak = 0, unsliced_y = 0;
+    std::vector<std::pair<int, int>> slices;
+    for (int r0 = 0; r0 < (int)g.n_cell; r0 += kSliceRows) slices.push_back({r0, std::min<int>(r0 + kSliceRows, (int)g.n_cell)});
+    if (m.nb > 0) slices.push_back({(int)g.n_cell, nl});
+    for (const auto &sl : slices) {
+        const int r0 = sl.first, r1 = sl.second, nr = r1 - r0;
+        // the faces these rows of Q^T touch, and the rows with local columns
+        std::vector<int32_t> F;
+        for (int32_t q = QT.ptr[r0]; q < QT.ptr[r1]; ++q) F.push_back(QT.col[q]);
+        std::sort(F.begin(), F.end());
+        F.erase(std::unique(F.begin(), F.end()), F.end());
+        for (size_t k = 0; k < F.size(); ++k) local[F[k]] = (int32_t)k;
+        CSR QTs;
+        QTs.nrows = nr;
+        QTs.ncols = (int32_t)F.size();
+        QTs.ptr.assign(1, 0);
+        for (int r = r0; r < r1; ++r) {
+            for (int32_t q = QT.ptr[r]; q < QT.ptr[r + 1]; ++q) {
+                QTs.col.push_back(local[QT.col[q]]);
+                QTs.val.push_back(QT.val[q]);
+            }
+            QTs.ptr.push_back((int32_t)QTs.col.size());
+        }
+        for (int32_t f : F) local[f] = -1;
+        int32_t *Fd = c->dtemp<int32_t>(F.size());
+        HIPCHECK(hipMemcpyAsync(Fd, F.data(), F.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        DevCSR QTd = upload_temp_csr(c, QTs);
+        ProdCSR YF = spgemm(c, c->Bn, Fd, (int)F.size(), c->Qd, false);
+        ProdCSR Ks = spgemm(c, QTd, nullptr, nr, YF.m, false);
+        peak = std::max<int64_t>(peak, YF.bytes + Ks.bytes + 12 * QTs.nnz() + 4 * (int64_t)(F.size() + nr + 1));
+        unsliced_y += YF.bytes;
+        // back to the host, appended to K
+        std::vector<int32_t> kp(nr + 1), kc(Ks.m.nnz);
+        std::vector<double> kv(Ks.m.nnz);
+        HIPCHECK(hipMemcpyAsync(kp.data(), Ks.m.ptr, (nr + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(kc.data(), Ks.m.col, Ks.m.nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipMemcpyAsync(kv.data(), Ks.m.val, Ks.m.nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        const int32_t base = K.ptr.back();
+        for (int i = 1; i <= nr; ++i) K.ptr.push_back(base + kp[i]);
+        K.col.insert(K.col.end(), kc.begin(), kc.end());
+        K.val.insert(K.val.end(), kv.begin(), kv.end());
+        free_prod(c, Ks);
+        free_prod(c, YF);
+        free_temp_csr(c, QTd);
+        c->dfree(Fd);
+    }
+    c->bn_peak_bytes = peak;
+    c->bn_unsliced_bytes = unsliced_y;
+    m.K = pin_rows_cols(K, m.pin);
+    free_temp_csr(c, Sd);
+    c->dfree(b1d);
+}
+
+// The V-cycle of Sec. 3 on a hierarchy whose finest level is stored too
+// (B^N with N > 1): every level runs the CSR kernels; the last post-sweep on
+// the finest level writes z, and r . z is summed after it.
+void enqueue_vcycle_csr(ibpm_ctx *c, PrecSet<double> &P, const double *r, double *z, SolveStatus *st) {
+    hipStream_t s = c->stream;
+    const int pre = c->prm.amg_pre, post = c->prm.amg_post;
+    const int L = (int)P.lev.size();
+    if (L == 1) {
+        launch_dense_solve(s, P.lev[0].n, c->coarse_inv, r, z, st);
+        c->rz_G = launch_dot_rz_parts(s, P.lev[0].n, r, z, st, c->parts);
+        return;
+    }
+    std::vector<double *> cur(L);
+    for (int l = 0; l < P.lc; ++l) {
+        DevLevelT<double> &lv = P.lev[l];
+        const double *b = l == 0 ? r : lv.b;
+        double *a = lv.xa, *bb = lv.xb;
+        int k = 1;
+        if (pre >= 2) {
+            launch_csrv_presmooth2(s, lv.A.view(), lv.A.lanes, (const double *)lv.wdinv, b, a, st);
+            k = 2;
+        } else {
+            launch_csr_jacobi_first(s, lv.A.view(), (const double *)lv.wdinv, b, a, st);
+        }
+        for (; k < pre; ++k) {
+            launch_csrv_jacobi(s, lv.A.view(), lv.A.lanes, (const double *)lv.wdinv, b, (const double *)a, bb, st);
+            std::swap(a, bb);
+        }
+        cur[l] = a;
+        if (lv.RA.nrows > 0) {
+            launch_csrv_restrict(s, lv.R.view(), lv.RA.view(), lv.RA.lanes, b, (const double *)a, P.lev[l + 1].b, st);
+        } else {
+            launch_csrv_residual(s, lv.A.view(), lv.A.lanes, b, (const double *)a, lv.r, st);
+            launch_csrv_spmv(s, lv.R.view(), lv.R.lanes, (const double *)lv.r, P.lev[l + 1].b, false, st);
+        }
+    }
+    launch_coarse_dense(s, P.lev[P.lc].n, (const double *)P.coarseC, (const double *)P.lev[P.lc].b,
+                        P.lev[P.lc].xa, st);
+    cur[P.lc] = P.lev[P.lc].xa;
+    for (int l = P.lc - 1; l >= 0; --l) {
+        DevLevelT<double> &lv = P.lev[l];
+        const double *b = l == 0 ? r : lv.b;
+        double *a = cur[l];
+        double *bb = (a == lv.xa) ? lv.xb : lv.xa;
+        int k = 0;
+        if (lv.AP.nrows > 0) {
+            launch_csrv_prolong_jacobi(s, lv.A.view(), lv.AP.view(), lv.P.view(), lv.AP.lanes,
+                                       (const double *)lv.wdinv, b, (const double *)a,
+                                       (const double *)cur[l + 1], bb, st);
+            std::swap(a, bb);
+            k = 1;
+        } else {
+            launch_csrv_spmv(s, lv.P.view(), lv.P.lanes, (const double *)cur[l + 1], a, true, st);
+        }
+        for (; k < post; ++k) {
+            double *dst = (l == 0 && k == post - 1) ? z : bb;
+            launch_csrv_jacobi(s, lv.A.view(), lv.A.lanes, (const double *)lv.wdinv, b, (const double *)a, dst, st);
+            if (dst == z) a = z;
+            else std::swap(a, bb);
+        }
+        if (l == 0 && a != z) HIPCHECK(hipMemcpyAsync(z, a, P.lev[0].n * sizeof(double), hipMemcpyDeviceToDevice, s));
+        cur[l] = a;
+    }
+    c->rz_G = launch_dot_rz_parts(s, P.lev[0].n, r, z, st, c->parts);
 }
 
 // Work memory of the allocation-free velocity solve: the five PCG vectors
@@ -1476,6 +1812,10 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     c->guess_learned = p->poisson_solver == IBPM_SOLVER_AMG_PCG_FP32_CYCLE_GUESS;
     c->learned = p->poisson_solver == IBPM_SOLVER_AMG_FCG_LEARNED ||
                  p->poisson_solver == IBPM_SOLVER_AMG_FCG_MIXED_LEARNED;
+    // every parameter is valid: from here on the device is used
+    c->static_work = static_work_address();
+    c->bn = p->bn_order;
+    if (c->bn > 1) form_bn_operators(c);   // replaces m.K by the pinned Q^T B^N Q
     if (c->amg) {
         AmgParams ap;
         ap.theta = p->amg_theta;
@@ -1488,8 +1828,6 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
         }
         if (p->fuse_transfers) fused_transfer_products(c->h);
     }
-    // every parameter is valid: from here on the device is used
-    c->static_work = static_work_address();
     const GridMetrics &G = m.g;
     c->g = make_grid<double>(c, G);
     c->ly = 0;
@@ -1525,6 +1863,17 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     c->A.idt = 1.0 / p->dt;
     c->A.nu = p->nu;
     const int nq = c->g.n_q, nl = c->p64.K0.n;
+    if (c->bn > 1) {
+        // the stored level-0 operator and its diagonal
+        c->K0c = c->upload_csr<double>(m.K);
+        std::vector<double> dg((size_t)m.K.nrows, 0.0);
+        for (int32_t r = 0; r < m.K.nrows; ++r)
+            for (int32_t q = m.K.ptr[r]; q < m.K.ptr[r + 1]; ++q)
+                if (m.K.col[q] == r) dg[r] = m.K.val[q];
+        c->K0op.A = c->K0c.view();
+        c->K0op.diag = c->upload(dg);
+        c->wq = c->dalloc<double>(nq);
+    }
     if (c->amg) {
         upload_levels<double>(c, c->p64);
         c->coarse_inv = c->upload(c->h.coarse_inv);
@@ -1728,7 +2077,8 @@ int ibpm_solve_velocity_static(ibpm_ctx *c, const double *rhs, double *q, ibpm_s
 int ibpm_apply_K(ibpm_ctx *c, const double *x, double *y) {
     return guarded(c, [&] {
         if (!x || !y || x == y) throw InvalidArg("x and y must be distinct device vectors");
-        launch_apply_K0(c->stream, c->p64.K0, x, y);
+        if (c->bn > 1) launch_csr_gemv(c->stream, c->K0c.view(), x, 1.0, nullptr, y);
+        else launch_apply_K0(c->stream, c->p64.K0, x, y);
         return IBPM_OK;
     });
 }
@@ -1737,6 +2087,30 @@ int ibpm_apply_A(ibpm_ctx *c, const double *x, double *y) {
     return guarded(c, [&] {
         if (!x || !y || x == y) throw InvalidArg("x and y must be distinct device vectors");
         launch_apply_A(c->stream, c->A, x, y);
+        return IBPM_OK;
+    });
+}
+
+int ibpm_get_poisson_matrix(ibpm_ctx *c, int64_t *nnz, int32_t *ptr, int32_t *col, double *val) {
+    return guarded(c, [&] {
+        if (!nnz) throw InvalidArg("nnz is NULL");
+        const CSR &K = c->m.K;
+        *nnz = K.nnz();
+        if (ptr) std::memcpy(ptr, K.ptr.data(), K.ptr.size() * sizeof(int32_t));
+        if (col) std::memcpy(col, K.col.data(), K.col.size() * sizeof(int32_t));
+        if (val) std::memcpy(val, K.val.data(), K.val.size() * sizeof(double));
+        return IBPM_OK;
+    });
+}
+
+int ibpm_bn_info(const ibpm_ctx *cc, int64_t *nnz_K, int64_t *nnz_B, int64_t *peak_bytes,
+                 int64_t *unsliced_bytes) {
+    ibpm_ctx *c = const_cast<ibpm_ctx *>(cc);
+    return guarded(c, [&] {
+        if (nnz_K) *nnz_K = c->m.K.nnz();
+        if (nnz_B) *nnz_B = c->bn > 1 ? c->Bn.nnz : (int64_t)c->g.n_q;
+        if (peak_bytes) *peak_bytes = c->bn_peak_bytes;
+        if (unsliced_bytes) *unsliced_bytes = c->bn_unsliced_bytes;
         return IBPM_OK;
     });
 }
@@ -1852,6 +2226,7 @@ int ibpm_plan_hierarchy(const ibpm_params *p, int32_t cap, int32_t *levels, int6
     try {
         check_params(p);
         if (p->poisson_solver == IBPM_SOLVER_JACOBI_PCG) throw InvalidArg("no hierarchy: the Poisson solver is Jacobi-PCG");
+        if (p->bn_order > 1) throw InvalidArg("Q^T B^N Q with N > 1 is formed on the device: build a context");
         const auto t0 = std::chrono::steady_clock::now();
         Model m;
         try {
@@ -1899,6 +2274,8 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, int64_t min_foot
                      double *bytes) {
     return guarded(c, [&] {
         if (reps < 1 || !avg_ms || min_footprint < 0) throw InvalidArg("bad arguments");
+        if (c->bn > 1 && kernel != IBPM_KERNEL_A_PCG_SPMV && kernel != IBPM_KERNEL_STREAM_COPY)
+            throw InvalidArg("the level-0 kernels time the matrix-free operator of B^1 only");
         const bool needs_amg = kernel == IBPM_KERNEL_K0_JACOBI || kernel == IBPM_KERNEL_K0_RESIDUAL ||
                                kernel == IBPM_KERNEL_RESTRICT0 || kernel == IBPM_KERNEL_PROLONG0 ||
                                kernel == IBPM_KERNEL_COARSE_CYCLE || kernel == IBPM_KERNEL_PRESMOOTH0 ||
@@ -2158,6 +2535,7 @@ int ibpm_iteration_launches(const ibpm_ctx *cc, int32_t ncounts, int32_t *counts
     ibpm_ctx *c = const_cast<ibpm_ctx *>(cc);
     return guarded(c, [&] {
         if (!counts || ncounts < 0) throw InvalidArg("bad arguments");
+        if (c->bn > 1) throw InvalidArg("launch counts are given for the B^1 iteration only");
         PrecSet<double> &P = c->p64;
         if (!c->amg || P.lev.size() < 2) throw InvalidArg("needs an AMG hierarchy of two or more levels");
         int32_t k[IBPM_NUM_KERNELS] = {};
@@ -2182,10 +2560,11 @@ int ibpm_iteration_launches(const ibpm_ctx *cc, int32_t ncounts, int32_t *counts
         k[IBPM_KERNEL_PROLONG0] = 1;
         k[IBPM_KERNEL_COARSE_CYCLE] = 1;
         if (P.lc >= 2) {
-            // the pre-sweep passes, the residual (alone or folded into the
-            // restriction) and the post-sweeps (the first may carry the
+            // the plain sweeps of level 1: the pre-sweeps beyond the fused
+            // pair and the post-sweeps (less the first where it carries the
             // prolongation)
-            k[IBPM_KERNEL_L1_JACOBI] = (pre >= 2 ? 1 + (pre - 2) : pre) + 1 + post;
+            const DevLevelT<double> &l1 = P.lev[1];
+            k[IBPM_KERNEL_L1_JACOBI] = (pre >= 2 ? pre - 2 : pre - 1) + (l1.AP.nrows > 0 ? post - 1 : post);
         }
         for (int i = 0; i < ncounts; ++i) counts[i] = i < IBPM_NUM_KERNELS ? k[i] : 0;
         return IBPM_OK;

@@ -98,6 +98,15 @@ struct K0T {
 };
 using K0View = K0T<double>;
 
+// A stored (CSR, sorted rows) operator for the Krylov kernels: the level-0
+// Poisson operator K = Q^T B^N Q when N > 1, its diagonal kept apart.
+template <class T>
+struct CsrOpT {
+    CSRT<T> A;
+    const T *diag;
+};
+using CsrOpView = CsrOpT<double>;
+
 // Velocity operator A = Mf/dt - (nu/2) L on interior faces (matrix-free, FP64).
 struct AView {
     GridView g;
@@ -124,7 +133,7 @@ void launch_momentum_rhs(hipStream_t s, GridView g, const double *q, const doubl
                          double *conv_now, double *r1, const double *w0, const double *w1,
                          double nu, double dt, int first_step);
 void launch_poisson_rhs(hipStream_t s, GridView g, int nb, int pin, const double *qstar,
-                        const double *w1, CSRView E, const double *ub, double *rhs);
+                        const double *w1, CSRView E, const double *ub, double ub_scale, double *rhs);
 void launch_project(hipStream_t s, GridView g, double dt, int nb, const double *qstar,
                     const double *lam, double *qout, CSRView etu, int fu_i0, int fu_i1, int fu_j0,
                     int fu_j1, CSRView etv, int fv_i0, int fv_i1, int fv_j0, int fv_j1);

@@ -718,6 +718,28 @@ inline dim3 op_grid(const K0T<T> &K) { return k0_grid<R>(K); }
 template <int R>
 inline dim3 op_grid(const AView &A) { return a_grid<R>(A); }
 
+// stored operator: one row per thread over the block's tiles (the walk
+// depth R does not apply), each row summed in column order
+template <int R, class T, class XV, class ACT>
+__device__ __forceinline__ void op_walk(const CsrOpT<T> &op, XV xv, ACT act) {
+    const int n = op.A.nrows;
+    const Tiles Tl = my_tiles(n);
+    for (int t = Tl.t0; t < Tl.t1; ++t) {
+        const int row = t * kBlock + threadIdx.x;
+        if (row < n) {
+            T s = T(0);
+            for (int p = op.A.ptr[row]; p < op.A.ptr[row + 1]; ++p) s += op.A.val[p] * xv(op.A.col[p]);
+            act(row, s, op.diag[row], xv(row));
+        }
+    }
+}
+template <class T>
+__device__ __forceinline__ T op_diag(const CsrOpT<T> &op, int r) { return op.diag[r]; }
+template <class T>
+__host__ __device__ inline int op_n(const CsrOpT<T> &op) { return op.A.nrows; }
+template <int R, class T>
+inline dim3 op_grid(const CsrOpT<T> &op) { return dim3(grid_for(op.A.nrows)); }
+
 __device__ __forceinline__ int block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
 
 // Per-block partials at the linear block index (the 2-D grids)
@@ -1728,7 +1750,7 @@ __global__ __launch_bounds__(kBlock) void k_walls_update(GridView g, const doubl
 // [-D q* + bc2 ; E q* - u_B] with the n+1 walls; the pinned entry cleared
 __global__ __launch_bounds__(kBlock) void k_poisson_rhs(GridView g, int nb, int pin, const double *qs,
                                                         const double *w1, CSRView E,
-                                                        const double *ub, double *rhs) {
+                                                        const double *ub, double ub_scale, double *rhs) {
     int row = blockIdx.x * kBlock + threadIdx.x;
     if (row < g.n_cell) {
         WallOffsets o = WallOffsets::make(g.nx, g.ny);
@@ -1744,7 +1766,7 @@ __global__ __launch_bounds__(kBlock) void k_poisson_rhs(GridView g, int nb, int 
         int k = row - g.n_cell;
         double s = 0.0;
         for (int p = E.ptr[k]; p < E.ptr[k + 1]; ++p) s += E.val[p] * qs[E.col[p]];
-        rhs[row] = s - ub[k];
+        rhs[row] = s - ub_scale * ub[k];
     }
 }
 
@@ -1853,9 +1875,9 @@ void launch_momentum_rhs(hipStream_t s, GridView g, const double *q, const doubl
 }
 
 void launch_poisson_rhs(hipStream_t s, GridView g, int nb, int pin, const double *qstar,
-                        const double *w1, CSRView E, const double *ub, double *rhs) {
+                        const double *w1, CSRView E, const double *ub, double ub_scale, double *rhs) {
     int n = g.n_cell + 2 * nb;
-    LAUNCH(k_poisson_rhs, (n + kBlock - 1) / kBlock, g, nb, pin, qstar, w1, E, ub, rhs);
+    LAUNCH(k_poisson_rhs, (n + kBlock - 1) / kBlock, g, nb, pin, qstar, w1, E, ub, ub_scale, rhs);
 }
 
 void launch_project(hipStream_t s, GridView g, double dt, int nb, const double *qstar,
@@ -2309,6 +2331,7 @@ void launch_add_correction(hipStream_t s, int n, double *x, const float *d) {
 INST_OP(K0View, double)
 INST_OP(AView, double)
 INST_OP(K0T<float>, float)
+INST_OP(CsrOpView, double)
 
 #define INST_T(T)                                                                                \
     template void launch_pcg_init_zero<T>(hipStream_t, int, const T *, T *, T *, SolveStatus *,  \

@@ -31,7 +31,9 @@ int cell_of(const std::vector<double> &f, double x) {
     return std::min(std::max(i, 0), n - 1);
 }
 
-// width h of the cell holding x; every cell within two cells must share it
+// width h of the cell holding x; every cell meeting the open support
+// (x - 1.5h, x + 1.5h) -- the cells whose widths enter the weights -- must
+// share it
 double local_width(const std::vector<double> &f, const std::vector<double> &w, double x,
                    const char *axis) {
     int n = (int)w.size();
@@ -39,7 +41,10 @@ double local_width(const std::vector<double> &f, const std::vector<double> &w, d
     if (i0 < 2 || i0 > n - 3)
         fail(std::string("Lagrangian point too close to the domain edge along ") + axis);
     double h = w[i0];
-    for (int i = i0 - 2; i <= i0 + 2; ++i)
+    // first cell with f[i+1] > x - 1.5h, last cell with f[i] < x + 1.5h
+    const int first = (int)(std::upper_bound(f.begin(), f.end(), x - 1.5 * h) - f.begin()) - 1;
+    const int last = (int)(std::lower_bound(f.begin(), f.end(), x + 1.5 * h) - f.begin()) - 1;
+    for (int i = std::max(first, 0); i <= std::min(last, n - 1); ++i)
         if (std::fabs(w[i] - h) > 1e-9 * h)
             fail(std::string("grid is not uniform under the delta support along ") + axis);
     return h;
@@ -415,6 +420,120 @@ void build_model(Model &m, int nx, int ny, const double *xf, const double *yf, i
 
 // ---------------------------------------------------------------------------
 // sparse helpers
+
+// ---------------------------------------------------------------------------
+// Operators of B^N for N > 1 (Sec. 2, text after Eq. 11)
+
+namespace {
+// one row of a CSR under construction: entries appended in any order, then
+// sorted by column (the columns of a row are distinct)
+void push_row(CSR &M, std::vector<std::pair<int32_t, double>> &row) {
+    std::sort(row.begin(), row.end());
+    for (const auto &e : row) {
+        M.col.push_back(e.first);
+        M.val.push_back(e.second);
+    }
+    M.ptr.push_back((int32_t)M.col.size());
+    row.clear();
+}
+}  // namespace
+
+CSR laplacian_csr(const GridMetrics &g) {
+    // L = M Lhat R^-1 on the interior faces: Lhat the 3-point second
+    // difference per direction with the gaps of the staggered grid, the
+    // wall values left out (they enter the right-hand side)
+    const int nx = g.nx, ny = g.ny;
+    CSR L;
+    L.nrows = L.ncols = (int32_t)g.n_q;
+    L.ptr.reserve(g.n_q + 1);
+    L.ptr.push_back(0);
+    L.col.reserve(5 * g.n_q);
+    L.val.reserve(5 * g.n_q);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 1; i < nx; ++i) {
+            // u at (x_i, yc_j): row weight Dx_i, unknown scale dy
+            const double lo_x = 1.0 / (g.dx[i - 1] * g.Dx[i]), hi_x = 1.0 / (g.dx[i] * g.Dx[i]);
+            const double lo_y = 1.0 / (g.Dy[j] * g.dy[j]), hi_y = 1.0 / (g.Dy[j + 1] * g.dy[j]);
+            const double m = g.Dx[i];
+            row.push_back({(int32_t)g.uidx(i, j), -m * (lo_x + hi_x + lo_y + hi_y) / g.dy[j]});
+            if (i > 1) row.push_back({(int32_t)g.uidx(i - 1, j), m * lo_x / g.dy[j]});
+            if (i < nx - 1) row.push_back({(int32_t)g.uidx(i + 1, j), m * hi_x / g.dy[j]});
+            if (j > 0) row.push_back({(int32_t)g.uidx(i, j - 1), m * lo_y / g.dy[j - 1]});
+            if (j < ny - 1) row.push_back({(int32_t)g.uidx(i, j + 1), m * hi_y / g.dy[j + 1]});
+            push_row(L, row);
+        }
+    for (int j = 1; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            // v at (xc_i, y_j): row weight Dy_j, unknown scale dx
+            const double lo_x = 1.0 / (g.Dx[i] * g.dx[i]), hi_x = 1.0 / (g.Dx[i + 1] * g.dx[i]);
+            const double lo_y = 1.0 / (g.dy[j - 1] * g.Dy[j]), hi_y = 1.0 / (g.dy[j] * g.Dy[j]);
+            const double m = g.Dy[j];
+            row.push_back({(int32_t)g.vidx(i, j), -m * (lo_x + hi_x + lo_y + hi_y) / g.dx[i]});
+            if (i > 0) row.push_back({(int32_t)g.vidx(i - 1, j), m * lo_x / g.dx[i - 1]});
+            if (i < nx - 1) row.push_back({(int32_t)g.vidx(i + 1, j), m * hi_x / g.dx[i + 1]});
+            if (j > 1) row.push_back({(int32_t)g.vidx(i, j - 1), m * lo_y / g.dx[i]});
+            if (j < ny - 1) row.push_back({(int32_t)g.vidx(i, j + 1), m * hi_y / g.dx[i]});
+            push_row(L, row);
+        }
+    return L;
+}
+
+std::vector<double> b1_diagonal(const GridMetrics &g, double dt) {
+    // B^1 = dt Mf^-1, Mf = M R^-1: dt dy_j / Dx_i on u faces, dt dx_i / Dy_j on v faces
+    std::vector<double> b((size_t)g.n_q);
+    for (int j = 0; j < g.ny; ++j)
+        for (int i = 1; i < g.nx; ++i) b[g.uidx(i, j)] = dt * g.dy[j] / g.Dx[i];
+    for (int j = 1; j < g.ny; ++j)
+        for (int i = 0; i < g.nx; ++i) b[g.vidx(i, j)] = dt * g.dx[i] / g.Dy[j];
+    return b;
+}
+
+CSR poisson_qt(const Model &m) {
+    // Q^T = [G^T; E] (n_lambda x n_q): G^T = -D on the cells (interior faces
+    // only), then the interpolation rows
+    const GridMetrics &g = m.g;
+    const int nx = g.nx, ny = g.ny;
+    CSR Q;
+    Q.nrows = (int32_t)(g.n_cell + 2 * m.nb);
+    Q.ncols = (int32_t)g.n_q;
+    Q.ptr.push_back(0);
+    std::vector<std::pair<int32_t, double>> row;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            if (i > 0) row.push_back({(int32_t)g.uidx(i, j), 1.0});
+            if (i < nx - 1) row.push_back({(int32_t)g.uidx(i + 1, j), -1.0});
+            if (j > 0) row.push_back({(int32_t)g.vidx(i, j), 1.0});
+            if (j < ny - 1) row.push_back({(int32_t)g.vidx(i, j + 1), -1.0});
+            push_row(Q, row);
+        }
+    for (int k = 0; k < m.E.nrows; ++k) {
+        for (int p = m.E.ptr[k]; p < m.E.ptr[k + 1]; ++p) row.push_back({m.E.col[p], m.E.val[p]});
+        push_row(Q, row);
+    }
+    return Q;
+}
+
+CSR pin_rows_cols(const CSR &K, int32_t pin) {
+    // clear row and column `pin` except the diagonal entry
+    CSR out;
+    out.nrows = K.nrows;
+    out.ncols = K.ncols;
+    out.ptr.reserve(K.nrows + 1);
+    out.ptr.push_back(0);
+    out.col.reserve(K.col.size());
+    out.val.reserve(K.val.size());
+    for (int32_t r = 0; r < K.nrows; ++r) {
+        for (int32_t p = K.ptr[r]; p < K.ptr[r + 1]; ++p) {
+            const int32_t c = K.col[p];
+            if ((r == pin || c == pin) && r != c) continue;
+            out.col.push_back(c);
+            out.val.push_back(K.val[p]);
+        }
+        out.ptr.push_back((int32_t)out.col.size());
+    }
+    return out;
+}
 
 CSR csr_transpose(const CSR &A) {
     CSR T;

@@ -92,6 +92,15 @@ void build_hierarchy(Hierarchy &h, const CSR &K, const AmgParams &p);
 // matrix, row-major n_lc x n_lc.
 std::vector<double> coarse_cycle_matrix(const Hierarchy &h, int lc, int pre, int post);
 
+// Operators of B^N for N > 1, built on the host for the device products:
+// L = M Lhat R^-1 on the interior faces (n_q x n_q, rows sorted), the
+// diagonal of B^1 = dt Mf^-1, Q^T = [G^T; E] (n_lambda x n_q), and a copy
+// of K with row and column `pin` cleared except the diagonal.
+CSR laplacian_csr(const GridMetrics &g);
+std::vector<double> b1_diagonal(const GridMetrics &g, double dt);
+CSR poisson_qt(const Model &m);
+CSR pin_rows_cols(const CSR &K, int32_t pin);
+
 // helpers exposed for the host tests
 double roma_phi(double s);
 CSR csr_transpose(const CSR &A);

@@ -38,7 +38,7 @@ EXPORTED = (
     "ibpm_get_aggregates", "ibpm_time_kernel", "ibpm_nn_init", "ibpm_nn_get_weights",
     "ibpm_nn_set_weights", "ibpm_nn_layer", "ibpm_nn_apply", "ibpm_nn_train",
     "ibpm_nn_loss_grad", "ibpm_harvest", "ibpm_plan_hierarchy", "ibpm_iteration_launches",
-    "ibpm_nn_adam_step", "ibpm_solve_velocity_static",
+    "ibpm_nn_adam_step", "ibpm_solve_velocity_static", "ibpm_get_poisson_matrix", "ibpm_bn_info",
 )
 
 NN_PARAMS = 39168                     # IBPM_NN_PARAMS
@@ -77,6 +77,7 @@ class Params(ctypes.Structure):
         ("bc_kind", ctypes.c_int32 * 4),
         ("bc_u", ctypes.c_double * 4), ("bc_v", ctypes.c_double * 4),
         ("fcg_stall_fall", ctypes.c_double),
+        ("body_ramp", ctypes.c_double),
     ]
 
 
@@ -139,6 +140,9 @@ def load():
         "ibpm_get_aggregates": [P, i32, ctypes.POINTER(i32)],
         "ibpm_time_kernel": [P, i32, i32, i64, D, D],
         "ibpm_iteration_launches": [P, i32, ctypes.POINTER(i32)],
+        "ibpm_get_poisson_matrix": [P, ctypes.POINTER(i64), P, P, P],
+        "ibpm_bn_info": [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
+                         ctypes.POINTER(i64)],
         "ibpm_nn_init": [P, ctypes.c_uint64],
         "ibpm_nn_get_weights": [P, P, i64],
         "ibpm_nn_set_weights": [P, P, i64],
@@ -169,13 +173,13 @@ def _dptr(a: np.ndarray):
 def params_from_workload(wl: W.Workload, **over) -> dict:
     p = dict(nx=wl.nx, ny=wl.ny, xf=wl.xf, yf=wl.yf, nb=wl.nb, xb=wl.xb, yb=wl.yb,
              ubx=wl.ubx, uby=wl.uby, nu=wl.nu, dt=wl.dt, uinf=wl.uinf, alpha=wl.alpha,
-             bn_order=1, vel_rtol=wl.vel_rtol, vel_maxit=wl.vel_maxit,
+             bn_order=wl.bn_order, vel_rtol=wl.vel_rtol, vel_maxit=wl.vel_maxit,
              poisson_solver=wl.poisson_solver, poisson_rtol=wl.poisson_rtol,
              poisson_maxit=wl.poisson_maxit, amg_theta=wl.amg_theta, amg_pre=wl.amg_pre,
              amg_post=wl.amg_post, amg_coarse_max=wl.amg_coarse_max,
              amg_max_levels=wl.amg_max_levels, inner_rtol=0.0, learned_every=1, fcg_depth=0, use_graphs=1,
              fuse_transfers=1, pin_cell=wl.pin_cell, bc_kind=tuple(wl.bc_kind),
-             fcg_stall_fall=0.0)
+             fcg_stall_fall=0.0, body_ramp=wl.body_ramp)
     p["bc_u"], p["bc_v"] = wl.wall_velocities()
     p.update(over)
     return p
@@ -417,6 +421,30 @@ class Context:
         self._check(load().ibpm_time_kernel(self._h, KERNELS[name], int(reps), int(min_footprint),
                                             ctypes.byref(ms), ctypes.byref(by)))
         return ms.value, by.value
+
+    def poisson_matrix(self):
+        """The pinned Poisson operator K as the library holds it on the host
+        (scipy CSR): for B^N with N > 1 the product formed on the device."""
+        import scipy.sparse as sp
+        L = load()
+        nnz = ctypes.c_int64()
+        self._check(L.ibpm_get_poisson_matrix(self._h, ctypes.byref(nnz), None, None, None))
+        n = self.n_lambda
+        ptr = np.zeros(n + 1, np.int32)
+        col = np.zeros(max(nnz.value, 1), np.int32)
+        val = np.zeros(max(nnz.value, 1), np.float64)
+        self._check(L.ibpm_get_poisson_matrix(self._h, ctypes.byref(nnz), ptr.ctypes.data_as(ctypes.c_void_p),
+                                              col.ctypes.data_as(ctypes.c_void_p),
+                                              val.ctypes.data_as(ctypes.c_void_p)))
+        return sp.csr_matrix((val[:nnz.value], col[:nnz.value], ptr), shape=(n, n))
+
+    def bn_info(self):
+        """Stored entries of K and of B^N, and the device memory of the sliced
+        triple product (largest slice) against the full intermediate."""
+        a, b, c, d = (ctypes.c_int64() for _ in range(4))
+        self._check(load().ibpm_bn_info(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c),
+                                        ctypes.byref(d)))
+        return {"nnz_K": a.value, "nnz_B": b.value, "peak_bytes": c.value, "unsliced_bytes": d.value}
 
     def iteration_launches(self):
         """Launches per FP64 AMG-PCG iteration of each timeable kernel."""

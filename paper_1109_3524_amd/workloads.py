@@ -129,6 +129,8 @@ class Workload:
     bc_u: Optional[tuple] = None   # Dirichlet wall velocities per side;
     bc_v: Optional[tuple] = None   # None: the freestream on every side
     bn_order: int = 1              # N of B^N (the truncated series for A^{-1})
+    body_ramp: float = 0.0         # time over which the body velocity rises from rest (sin^2);
+                                   # 0: impulsive
     description: str = ""
 
     def wall_velocities(self):

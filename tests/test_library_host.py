@@ -50,7 +50,11 @@ def _params(wl, **over):
 
 
 @pytest.mark.parametrize("over,msg", [
-    (dict(bn_order=3), "N = 1"),
+    (dict(bn_order=4), "bn_order must be 1 or 3"),
+    (dict(bn_order=2), "bn_order must be 1 or 3"),
+    (dict(bn_order=0), "bn_order must be 1 or 3"),
+    (dict(bn_order=3, poisson_solver=2), "Jacobi-PCG and AMG-PCG"),
+    (dict(bn_order=3, poisson_solver=5), "Jacobi-PCG and AMG-PCG"),
     (dict(poisson_rtol=0.0), "tolerances"),
     (dict(vel_maxit=0), "maxit"),
     (dict(nu=-1.0), "positive"),
@@ -90,6 +94,18 @@ def test_body_on_nonuniform_cells_is_rejected():
     assert rc == ibpm.IBPM_EINVAL
     assert "uniform" in L.ibpm_last_error(h).decode()
     L.ibpm_destroy(h)
+
+
+def test_paper_re40_grid_supports_are_accepted_on_the_host():
+    """Supports that reach the last cell of the uniform patch (the paper's
+    Re 40 grid) are accepted; one reaching a stretched cell is not."""
+    plan = ibpm.plan_hierarchy(W.cylinder_re40_330())
+    assert plan["levels"] >= 2
+    wl = W.cylinder_re40_330().replace(xb=np.array([0.515]), yb=np.array([0.0]), ubx=np.zeros(1),
+                                       uby=np.zeros(1))
+    with pytest.raises(ibpm.IBPMError) as e:
+        ibpm.plan_hierarchy(wl)
+    assert "uniform" in str(e.value)
 
 
 def test_null_arguments():

@@ -97,3 +97,17 @@ def test_nonuniform_support_rejected():
         delta.interpolation_matrices(g, np.array([0.99]), np.array([0.0]))
     with pytest.raises(ValueError):
         delta.interpolation_matrices(g, np.array([0.0]), np.array([3.0]))
+
+
+def test_support_up_to_the_edge_of_the_uniform_patch_is_accepted():
+    """The paper's Re 40 grid (Table 3) keeps a uniform patch [-0.54,0.54]
+    with h = 0.02 around a cylinder of radius 0.5: the supports reach 0.53,
+    inside the patch, and are accepted; a point 0.015 further out has a
+    support reaching a stretched cell and is rejected."""
+    wl = W.cylinder_re40_330()
+    g = Grid(wl.xf, wl.yf)
+    _, E = delta.interpolation_matrices(g, wl.xb, wl.yb)
+    assert E.shape[0] == 2 * wl.nb
+    delta.interpolation_matrices(g, np.array([0.51]), np.array([0.0]))
+    with pytest.raises(ValueError):
+        delta.interpolation_matrices(g, np.array([0.515]), np.array([0.0]))
