@@ -334,7 +334,7 @@ int ibpm_iteration_launches(const ibpm_ctx *ctx, int32_t ncounts, int32_t *count
  *     one launch leaves in the L2 and last-level caches the next one finds);
  *   min_footprint > 0: the kernel's vector operands are replicated into as
  *     many operand sets as make up at least min_footprint bytes (at least
- *     two), allocated for the call and freed before it returns, and
+ *     two, at most 256), allocated for the call and freed before it returns, and
  *     consecutive launches take consecutive sets, so that with a footprint
  *     above the 256 MB last-level cache a launch finds none of its vectors
  *     in the caches; matrices, aggregates, metrics and partial sums are

@@ -2493,7 +2493,10 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, int64_t min_foot
             per += (cnt + 31) / 32 * 32;   // 256-byte aligned slots
         }
         if (min_footprint > 0) {
-            sets = (int)std::max<int64_t>(2, (min_footprint + (int64_t)(8 * per) - 1) / (int64_t)(8 * per));
+            // at most 256 sets: a kernel whose vectors are that small is not
+            // bound by HBM anyway
+            sets = (int)std::min<int64_t>(256, std::max<int64_t>(2, (min_footprint + (int64_t)(8 * per) - 1) /
+                                                                        (int64_t)(8 * per)));
             void *pp = nullptr;
             if (hipMalloc(&pp, (size_t)sets * per * sizeof(double)) != hipSuccess) throw std::bad_alloc();
             pool = (double *)pp;
