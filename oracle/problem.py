@@ -40,6 +40,32 @@ class Problem:
                                          max_levels=wl.amg_max_levels,
                                          pre=wl.amg_pre, post=wl.amg_post)
 
+    def move_body(self, xb, yb, ubx, uby, hierarchy="new"):
+        """A body in prescribed motion (Sec. 6): the Lagrangian points and
+        their velocities at the time the next step advances to.  E and K are
+        formed anew for the new positions (the factorised system of Eq. 11 at
+        time n+1); the AMG hierarchy is set up anew ("new"), re-formed on the
+        aggregates and weights of its first set-up ("refresh"), or re-used
+        ("keep", Sec. 4: over several steps) with only its finest level --
+        the smoother's operator and diagonal -- following K."""
+        wl = self.wl
+        self.E_hat, self.E = delta.interpolation_matrices(self.grid, xb, yb)
+        self.ops = operators.Operators(self.grid, self.E, wl.nu, wl.dt, pin=wl.pin_cell,
+                                       bn_order=getattr(wl, "bn_order", 1))
+        self.ub = np.concatenate([np.asarray(ubx, float), np.asarray(uby, float)])
+        if hierarchy not in ("new", "refresh", "keep"):
+            raise ValueError("hierarchy must be 'new', 'refresh' or 'keep'")
+        if self.solver != JACOBI_PCG and hierarchy == "refresh":
+            self.H.refresh(self.ops.K)
+        elif self.solver != JACOBI_PCG and hierarchy == "keep":
+            self.H.levels[0].A = self.ops.K
+            self.H.levels[0].dinv = 1.0 / self.ops.K.diagonal()
+        elif self.solver != JACOBI_PCG and hierarchy == "new":
+            self.H = solvers.SAHierarchy(self.ops.K, theta=wl.amg_theta,
+                                         coarse_max=wl.amg_coarse_max,
+                                         max_levels=wl.amg_max_levels,
+                                         pre=wl.amg_pre, post=wl.amg_post)
+
     def solve_poisson(self, rhs, x0, rtol=None, maxit=None):
         rtol = self.poisson_rtol if rtol is None else rtol
         maxit = self.wl.poisson_maxit if maxit is None else maxit

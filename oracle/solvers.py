@@ -220,6 +220,28 @@ class SAHierarchy:
         Ac = self.levels[-1].A.toarray()
         self.coarse_chol = sla.cho_factor(Ac, lower=True)
 
+    def refresh(self, A):
+        """The hierarchy formed anew for a changed finest operator A (a moving
+        body, Sec. 4) with the aggregates and the smoothing weights of this
+        set-up kept: each level's P = (I - w D^-1 A) T and Galerkin product
+        P^T A P from the new operators, and the coarsest factorisation."""
+        self.levels[0].A = A.tocsr()
+        for l, lev in enumerate(self.levels):
+            lev.dinv = 1.0 / lev.A.diagonal()
+            if lev.P is None:
+                break
+            n = lev.A.shape[0]
+            nagg = self.levels[l + 1].A.shape[0]
+            T = sp.csr_matrix((np.ones(n), (np.arange(n), lev.agg)), shape=(n, nagg))
+            P = (T - lev.omega * (sp.diags(lev.dinv) @ (lev.A @ T))).tocsr()
+            P.sort_indices()
+            Ac = (P.T @ lev.A @ P).tocsr()
+            Ac.sort_indices()
+            lev.P = P
+            self.levels[l + 1].A = Ac
+        Ac = self.levels[-1].A.toarray()
+        self.coarse_chol = sla.cho_factor(Ac, lower=True)
+
     def vcycle(self, b, level=0):
         lev = self.levels[level]
         if level == len(self.levels) - 1:

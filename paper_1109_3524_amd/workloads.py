@@ -214,6 +214,32 @@ def cylinder_2048(steps: int = 2000) -> Workload:
     return cylinder_stretched(2048, 0.005, 628, 100.0, 0.002, steps).replace(poisson_maxit=20000)
 
 
+def heaving_cylinder(n: int = 512, steps: int = 200) -> Workload:
+    """A cylinder in prescribed motion across the stream (a rigid heave, see
+    `heave`) on the stretched grids of the fixed-cylinder runs: the 512^2
+    (h 0.02, 157 points, dt 0.005), 1024^2 (h 0.01, 314 points, dt 0.0025)
+    or 2048^2 (h 0.005, 628 points, dt 0.002) grid at Re 100.  The heave
+    keeps the body and its delta supports inside the uniform patch."""
+    h, nb, dt = {512: (0.02, 157, 0.005), 1024: (0.01, 314, 0.0025), 2048: (0.005, 628, 0.002)}[n]
+    wl = cylinder_stretched(n, h, nb, 100.0, dt, steps).replace(poisson_maxit=20000)
+    return wl.replace(name=f"heaving_cylinder_re100_{n}x{n}",
+                      description=f"Re 100 cylinder heaving with amplitude {HEAVE_AMPLITUDE} and period "
+                                  f"{HEAVE_PERIOD}, {n}^2 stretched grid on [-15,15]^2, h={h}, {nb} points, dt {dt}")
+
+
+HEAVE_AMPLITUDE = 0.25
+HEAVE_PERIOD = 2.0
+
+
+def heave(wl: Workload, t: float, amplitude: float = HEAVE_AMPLITUDE, period: float = HEAVE_PERIOD):
+    """Points and velocities at time t of the workload's body moved as a
+    rigid heave y_c(t) = amplitude sin(2 pi t / period): (xb, yb, ubx, uby)."""
+    ph = 2.0 * math.pi * t / period
+    v = amplitude * (2.0 * math.pi / period) * math.cos(ph)
+    return (np.array(wl.xb, dtype=float), np.asarray(wl.yb, dtype=float) + amplitude * math.sin(ph),
+            np.zeros(wl.nb), np.full(wl.nb, v))
+
+
 def cylinder_512_re100(steps: int = 200) -> Workload:
     """512^2 Re 100 grid used for the learned-preconditioner study."""
     return cylinder_stretched(512, 0.02, 157, 100.0, 0.005, steps,
