@@ -69,6 +69,7 @@ using CSRView = CSRT<double>;
 // empty slots hold column -1 and value 0.  Rows longer than the width are
 // read from the CSR instead (the ELL flag of the matrix is 0).
 constexpr int kKfW = 24;   // slots per force row
+constexpr int kStreamCap = 2048;   // entries one block of the row-block CSR kernels holds in LDS
 constexpr int kCcW = 16;   // slots per coupled cell (force unknowns it meets)
 
 // Level-0 Poisson operator K = Q^T B^1 Q (pinned), matrix-free pressure

@@ -1562,6 +1562,142 @@ __global__ __launch_bounds__(kBlock) void k_csrv_prolong_jacobi(CSRT<T> A, CSRT<
 }
 
 // ---------------------------------------------------------------------------
+// Stored-operator kernels in row blocks (the CSR levels of the V-cycle): a
+// block takes rpb consecutive rows, streams their entries -- all threads of
+// the block over one contiguous range of the value and column arrays, so
+// every load is coalesced -- multiplies each by the gathered operand into
+// LDS, and then each row's thread sums its products in column order.  rpb
+// is chosen on the host so that a block's entries (of every matrix the
+// kernel walks) fit in kStreamCap.
+
+template <class T, class XV>
+__device__ __forceinline__ void stream_fill(const CSRT<T> &A, int r0, int r1, T *lds, XV xv) {
+    const int base = A.ptr[r0], e = A.ptr[r1];
+    for (int k = base + (int)threadIdx.x; k < e; k += kBlock) lds[k - base] = A.val[k] * xv(A.col[k]);
+}
+
+template <class T>
+__device__ __forceinline__ T stream_row(const CSRT<T> &A, int row, int base, const T *lds) {
+    T s = T(0);
+    const int e = A.ptr[row + 1];
+    for (int p = A.ptr[row]; p < e; ++p) s += lds[p - base];
+    return s;
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_csrs_jacobi(CSRT<T> A, int rpb, const T *__restrict__ wdinv,
+                                                        const T *__restrict__ b, const T *__restrict__ xin,
+                                                        T *__restrict__ xout, const SolveStatus *st) {
+    if (st->done) return;
+    __shared__ T lds[kStreamCap];
+    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
+    if (r0 >= A.nrows) return;
+    const int r1 = min(r0 + rpb, A.nrows);
+    stream_fill(A, r0, r1, lds, [&](int c) { return xin[c]; });
+    __syncthreads();
+    const int base = A.ptr[r0];
+    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock)
+        xout[row] = xin[row] + wdinv[row] * (b[row] - stream_row(A, row, base, lds));
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_csrs_residual(CSRT<T> A, int rpb, const T *__restrict__ b,
+                                                          const T *__restrict__ x, T *__restrict__ r,
+                                                          const SolveStatus *st) {
+    if (st->done) return;
+    __shared__ T lds[kStreamCap];
+    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
+    if (r0 >= A.nrows) return;
+    const int r1 = min(r0 + rpb, A.nrows);
+    stream_fill(A, r0, r1, lds, [&](int c) { return x[c]; });
+    __syncthreads();
+    const int base = A.ptr[r0];
+    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock) r[row] = b[row] - stream_row(A, row, base, lds);
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_csrs_spmv(CSRT<T> A, int rpb, const T *__restrict__ x,
+                                                      T *__restrict__ y, int add, const SolveStatus *st) {
+    if (st && st->done) return;
+    __shared__ T lds[kStreamCap];
+    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
+    if (r0 >= A.nrows) return;
+    const int r1 = min(r0 + rpb, A.nrows);
+    stream_fill(A, r0, r1, lds, [&](int c) { return x[c]; });
+    __syncthreads();
+    const int base = A.ptr[r0];
+    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock) {
+        const T v = stream_row(A, row, base, lds);
+        y[row] = add ? y[row] + v : v;
+    }
+}
+
+// the first two damped-Jacobi sweeps from zero: x = y + W (b - A y), y = W b
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_csrs_presmooth2(CSRT<T> A, int rpb, const T *__restrict__ wdinv,
+                                                            const T *__restrict__ b, T *__restrict__ x,
+                                                            const SolveStatus *st) {
+    if (st->done) return;
+    __shared__ T lds[kStreamCap];
+    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
+    if (r0 >= A.nrows) return;
+    const int r1 = min(r0 + rpb, A.nrows);
+    stream_fill(A, r0, r1, lds, [&](int c) { return wdinv[c] * b[c]; });
+    __syncthreads();
+    const int base = A.ptr[r0];
+    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock) {
+        const T w = wdinv[row], bi = b[row];
+        x[row] = w * bi + w * (bi - stream_row(A, row, base, lds));
+    }
+}
+
+// b_c = R b - (R A) x: the block's entries of R, then of R A, in one buffer
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_csrs_restrict(CSRT<T> R, CSRT<T> RA, int rpb, const T *__restrict__ b,
+                                                          const T *__restrict__ x, T *__restrict__ bc,
+                                                          const SolveStatus *st) {
+    if (st->done) return;
+    __shared__ T lds[kStreamCap];
+    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
+    if (r0 >= R.nrows) return;
+    const int r1 = min(r0 + rpb, R.nrows);
+    const int nr = R.ptr[r1] - R.ptr[r0];
+    stream_fill(R, r0, r1, lds, [&](int c) { return b[c]; });
+    stream_fill(RA, r0, r1, lds + nr, [&](int c) { return x[c]; });
+    __syncthreads();
+    const int br = R.ptr[r0], ba = RA.ptr[r0];
+    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock)
+        bc[row] = stream_row(R, row, br, lds) - stream_row(RA, row, ba, lds + nr);
+}
+
+// x_out = x + P e + W (b - A x - (A P) e): entries of A, A P and P in turn
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_csrs_prolong_jacobi(CSRT<T> A, CSRT<T> AP, CSRT<T> P, int rpb,
+                                                                const T *__restrict__ wdinv,
+                                                                const T *__restrict__ b,
+                                                                const T *__restrict__ x,
+                                                                const T *__restrict__ e,
+                                                                T *__restrict__ xout,
+                                                                const SolveStatus *st) {
+    if (st->done) return;
+    __shared__ T lds[kStreamCap];
+    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
+    if (r0 >= A.nrows) return;
+    const int r1 = min(r0 + rpb, A.nrows);
+    const int na = A.ptr[r1] - A.ptr[r0], nq = AP.ptr[r1] - AP.ptr[r0];
+    stream_fill(A, r0, r1, lds, [&](int c) { return x[c]; });
+    stream_fill(AP, r0, r1, lds + na, [&](int c) { return e[c]; });
+    stream_fill(P, r0, r1, lds + na + nq, [&](int c) { return e[c]; });
+    __syncthreads();
+    const int ba = A.ptr[r0], bq = AP.ptr[r0], bp = P.ptr[r0];
+    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock) {
+        const T sa = stream_row(A, row, ba, lds), sq = stream_row(AP, row, bq, lds + na);
+        const T sp = stream_row(P, row, bp, lds + na + nq);
+        xout[row] = (x[row] + sp) + wdinv[row] * ((b[row] - sa) - sq);
+    }
+}
+
+// ---------------------------------------------------------------------------
 // the coarse part of the cycle as one dense matrix
 
 // x = C b with one wave per row (C row-major FP64, FP64 accumulation; b and
@@ -2197,15 +2333,29 @@ static void csrv_dispatch_presmooth2(hipStream_t s, CSRT<T> A, const T *wdinv, c
     int nb = (A.nrows + kBlock / L - 1) / (kBlock / L);
     LAUNCH((k_csrv_presmooth2<T, L>), nb > 0 ? nb : 1, A, wdinv, b, x, st);
 }
+// `lanes` > 0: the row-vector kernels with that many lanes per row;
+// `lanes` < 0: the row-block kernels with -lanes rows per block
+inline int stream_blocks(int nrows, int rpb) {
+    const int nb = (nrows + rpb - 1) / rpb;
+    return nb > 0 ? nb : 1;
+}
 template <class T>
 void launch_csrv_presmooth2(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b, T *x,
                             const SolveStatus *st) {
+    if (lanes < 0) {
+        LAUNCH((k_csrs_presmooth2<T>), stream_blocks(A.nrows, -lanes), A, -lanes, wdinv, b, x, st);
+        return;
+    }
     CSRV_SWITCH(csrv_dispatch_presmooth2, A, wdinv, b, x, st)
 }
 template <class T>
 void launch_csrv_restrict(hipStream_t s, CSRT<T> R, CSRT<T> RA, int lanes, const T *b, const T *x, T *bc,
                           const SolveStatus *st) {
     if (R.nrows != RA.nrows) throw std::runtime_error("fused restriction: R and R A differ in rows");
+    if (lanes < 0) {
+        LAUNCH((k_csrs_restrict<T>), stream_blocks(R.nrows, -lanes), R, RA, -lanes, b, x, bc, st);
+        return;
+    }
     CSRV_SWITCH(csrv_dispatch_restrict, R, RA, b, x, bc, st)
 }
 template <class T>
@@ -2214,21 +2364,38 @@ void launch_csrv_prolong_jacobi(hipStream_t s, CSRT<T> A, CSRT<T> AP, CSRT<T> P,
                                 const SolveStatus *st) {
     if (A.nrows != AP.nrows || A.nrows != P.nrows || AP.ncols != P.ncols)
         throw std::runtime_error("fused prolongation: A, A P and P do not match");
+    if (lanes < 0) {
+        LAUNCH((k_csrs_prolong_jacobi<T>), stream_blocks(A.nrows, -lanes), A, AP, P, -lanes, wdinv, b, x, e,
+               xout, st);
+        return;
+    }
     CSRV_SWITCH(csrv_dispatch_prolong_jacobi, A, AP, P, wdinv, b, x, e, xout, st)
 }
 template <class T>
 void launch_csrv_jacobi(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b,
                         const T *xin, T *xout, const SolveStatus *st) {
+    if (lanes < 0) {
+        LAUNCH((k_csrs_jacobi<T>), stream_blocks(A.nrows, -lanes), A, -lanes, wdinv, b, xin, xout, st);
+        return;
+    }
     CSRV_SWITCH(csrv_dispatch_jacobi, A, wdinv, b, xin, xout, st)
 }
 template <class T>
 void launch_csrv_residual(hipStream_t s, CSRT<T> A, int lanes, const T *b, const T *x, T *r,
                           const SolveStatus *st) {
+    if (lanes < 0) {
+        LAUNCH((k_csrs_residual<T>), stream_blocks(A.nrows, -lanes), A, -lanes, b, x, r, st);
+        return;
+    }
     CSRV_SWITCH(csrv_dispatch_residual, A, b, x, r, st)
 }
 template <class T>
 void launch_csrv_spmv(hipStream_t s, CSRT<T> A, int lanes, const T *x, T *y, bool add,
                       const SolveStatus *st) {
+    if (lanes < 0) {
+        LAUNCH((k_csrs_spmv<T>), stream_blocks(A.nrows, -lanes), A, -lanes, x, y, (int)add, st);
+        return;
+    }
     CSRV_SWITCH(csrv_dispatch_spmv, A, x, y, (int)add, st)
 }
 
