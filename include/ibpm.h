@@ -138,6 +138,15 @@ typedef struct ibpm_params {
                                     from rest as sin^2(pi t / (2 body_ramp)), t the time the step
                                     advances to; 0: the full velocity from the first step (the
                                     impulsive start of Sec. 5.1); >= 0 */
+    int32_t moving_body;         /* 1: the points may move between steps (ibpm_move_body, Sec. 6):
+                                    the level-0 K is stored and re-assembled on the device at
+                                    every move; B^1 only, Jacobi-PCG or AMG-PCG.  0: fixed body */
+    int32_t amg_rebuild_every;   /* moving body with AMG-PCG: at every n-th move (n >= 1) the
+                                    smoothed-aggregation hierarchy is formed anew from the moved K,
+                                    on the device, keeping the aggregates and smoothing weights of
+                                    the first set-up (the levels of the dense coarse cycle are
+                                    formed on the host); in between it is re-used with only its
+                                    finest level following K (Sec. 4).  0: never formed anew */
 } ibpm_params;
 
 typedef struct ibpm_solve_stats {
@@ -223,9 +232,10 @@ int ibpm_solve_velocity_static(ibpm_ctx *ctx, const double *rhs, double *q,
                                ibpm_solve_stats *stats);
 
 /* The pinned Poisson operator K = Q^T B^N Q as the context holds it on the
- * host (for N > 1: the product formed on the device): *nnz receives its
- * stored entries; ptr (n_lambda + 1), col and val (nnz each), host arrays,
- * receive its CSR rows (sorted columns) when not NULL. */
+ * host (for N > 1: the product formed on the device; for a moving body: the
+ * device K of the current positions, read back): *nnz receives its stored
+ * entries; ptr (n_lambda + 1), col and val (nnz each), host arrays, receive
+ * its CSR rows (sorted columns) when not NULL. */
 int ibpm_get_poisson_matrix(ibpm_ctx *ctx, int64_t *nnz, int32_t *ptr, int32_t *col, double *val);
 
 /* Sizes of the B^N operators: stored entries of K and of B^N (n_q for the
@@ -235,6 +245,26 @@ int ibpm_get_poisson_matrix(ibpm_ctx *ctx, int64_t *nnz, int32_t *ptr, int32_t *
  * would hold at once (0 for N = 1).  Host outputs, each may be NULL. */
 int ibpm_bn_info(const ibpm_ctx *ctx, int64_t *nnz_K, int64_t *nnz_B, int64_t *peak_bytes,
                  int64_t *unsliced_bytes);
+
+/* A body in prescribed motion (Sec. 6; the per-step update of the forcing
+ * rows of Q that Sec. 4 keeps apart from the rest of the solve): the nb
+ * Lagrangian points move to (xb, yb) with velocities (ubx, uby), host arrays
+ * of nb each, taken as those at the time the next step advances to (the
+ * body_ramp start-up scales the velocities as for a fixed body).  Needs a
+ * context built with moving_body = 1.  E and every row of K that couples to
+ * the forces are formed anew on the device (K is re-assembled in place as
+ * one CSR with the fixed pressure rows), and with AMG-PCG the hierarchy is
+ * formed anew at every amg_rebuild_every-th move.  Synchronises the stream.
+ * Points whose delta support leaves the uniform cells around them or the
+ * grid, or non-finite values: IBPM_EINVAL, the context unchanged. */
+int ibpm_move_body(ibpm_ctx *ctx, const double *xb, const double *yb, const double *ubx,
+                   const double *uby);
+
+/* Moving body: the moves made, the hierarchies formed anew since set-up,
+ * and box (4 entries: i0, i1, j0, j1) the cells whose faces E reaches at the
+ * current positions.  Host outputs, each may be NULL; IBPM_EINVAL for a
+ * fixed-body context. */
+int ibpm_moving_info(const ibpm_ctx *ctx, int64_t *moves, int64_t *refreshes, int32_t *box);
 
 /* y = K x (pinned Q^T B^N Q), x and y device n_lambda, distinct. */
 int ibpm_apply_K(ibpm_ctx *ctx, const double *x, double *y);

@@ -45,7 +45,7 @@ def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = [os.path.join(BUILD, "setup.o")]
     cmds = [["g++", *HOST_FLAGS, "-c", os.path.join(CSRC, "setup.cpp"), "-o", objs[0]]]
-    for name in ("kernels.hip", "nn.hip", "spgemm.hip", "api.hip"):
+    for name in ("kernels.hip", "nn.hip", "spgemm.hip", "moving.hip", "api.hip"):
         o = os.path.join(BUILD, name.replace(".hip", ".o"))
         cmds.append([HIPCC, *HIP_FLAGS, "-c", os.path.join(CSRC, name), "-o", o])
         objs.append(o)

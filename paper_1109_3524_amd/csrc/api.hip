@@ -7,7 +7,9 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <functional>
+#include <initializer_list>
 #include <mutex>
 #include <new>
 #include <stdexcept>
@@ -20,6 +22,7 @@
 #include "nn.h"
 #include "setup.h"
 #include "spgemm.h"
+#include "moving.h"
 
 using namespace ibpm;
 
@@ -125,6 +128,26 @@ struct ibpm_ctx {
     int bn = 1;
     DevCSR Bn{}, Qd{}, K0c{};
     CsrOpView K0op{};
+    // a body in prescribed motion: the level-0 K is stored and re-assembled
+    // on the device at every move (moving.hip); stored0 = the level-0
+    // operator is a stored CSR (B^N with N > 1, or a moving body)
+    bool moving = false, stored0 = false;
+    int64_t moves = 0, K_cap = 0;
+    DevCSR Kpp{};                                   // fixed pressure rows
+    double *xf_d = nullptr, *yf_d = nullptr, *xb_d = nullptr, *yb_d = nullptr;
+    int32_t *ecol = nullptr, *eptr = nullptr;       // E rows, kEllE entries each
+    double *eval = nullptr;
+    int32_t *len_all = nullptr, *force_len = nullptr, *box_len = nullptr;
+    int64_t *ptr64 = nullptr, *scan_tiles = nullptr, *scan_total = nullptr, *force_ptr = nullptr,
+            *box_ptr = nullptr;
+    int32_t *force_col = nullptr, *box_col = nullptr;
+    double *force_val = nullptr, *box_val = nullptr;
+    int64_t force_cap = 0, box_cap = 0, box_rows_cap = 0;
+    int box[4] = {0, -1, 0, -1};                    // cells whose faces E reaches (i0, i1, j0, j1)
+    double *K0diag = nullptr;
+    std::vector<int32_t *> agg_d;                   // aggregates of the levels formed on the device
+    std::vector<int64_t> level_nnz;                 // entries of each level's operator
+    int64_t refreshes = 0;
     double *wq = nullptr;
     int64_t bn_peak_bytes = 0, bn_unsliced_bytes = 0;
     std::vector<void *> allocs;
@@ -185,6 +208,15 @@ struct ibpm_ctx {
     }
     void dfree(const void *p) {
         if (p) (void)hipFree(const_cast<void *>(p));
+    }
+    // free memory taken with dalloc before the context ends
+    void release(const void *p) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), const_cast<void *>(p));
+        if (it != allocs.end()) {
+            allocs.erase(it);
+            (void)hipFree(const_cast<void *>(p));
+        }
     }
     template <class T>
     T *upload(const std::vector<T> &v) {
@@ -587,8 +619,8 @@ FcgStore<float> &fcg_store(ibpm_ctx *c, float *) { return c->fcg32; }
 
 int solve_poisson_fp64(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_stats *out) {
     bool jacobi = !c->amg;
-    if (c->bn > 1) {
-        // B^N with N > 1: the stored K and the all-CSR V-cycle
+    if (c->stored0) {
+        // B^N with N > 1 or a moving body: the stored K and the all-CSR V-cycle
         std::function<void(const double *, double *)> pre = [c](const double *r, double *z) {
             enqueue_vcycle_csr(c, c->p64, r, z, c->st_poi);
         };
@@ -1200,6 +1232,12 @@ void stage_rhs2(ibpm_ctx *c, const double *qstar, double *rhs) {
 
 void stage_project(ibpm_ctx *c, const double *qstar, const double *lam, double *qout) {
     const Model &m = c->m;
+    if (c->moving) {
+        launch_project_moving(c->stream, c->g, c->prm.dt, m.nb, c->ecol, c->eval, c->box[0], c->box[1],
+                              c->box[2], c->box[3], c->xf_d, c->yf_d, c->xb_d, c->yb_d, qstar, lam, qout);
+        launch_forces(c->stream, (int)m.g.n_cell, m.nb, lam, c->st_misc);
+        return;
+    }
     if (c->bn > 1) {
         // q = q* - B^N (Q lambda) as a pair of sparse products (Sec. 4)
         launch_csr_gemv(c->stream, c->Qd.view(), lam, -1.0, nullptr, c->wq);
@@ -1258,6 +1296,12 @@ void check_params(const ibpm_params *p) {
     if (p->fuse_transfers != 0 && p->fuse_transfers != 1) throw InvalidArg("fuse_transfers must be 0 or 1");
     if (!(p->fcg_stall_fall >= 0 && p->fcg_stall_fall <= 1)) throw InvalidArg("fcg_stall_fall must be in [0, 1]");
     if (!(p->body_ramp >= 0) || !std::isfinite(p->body_ramp)) throw InvalidArg("body_ramp must be finite and >= 0");
+    if (p->moving_body != 0 && p->moving_body != 1) throw InvalidArg("moving_body must be 0 or 1");
+    if (p->amg_rebuild_every < 0) throw InvalidArg("amg_rebuild_every must be >= 0");
+    if (p->moving_body && p->nb < 1) throw InvalidArg("a moving body needs at least one point");
+    if (p->moving_body && (p->bn_order != 1 || (p->poisson_solver != IBPM_SOLVER_JACOBI_PCG &&
+                                                p->poisson_solver != IBPM_SOLVER_AMG_PCG)))
+        throw InvalidArg("a moving body supports B^1 with the Jacobi-PCG and AMG-PCG Poisson solvers only");
     for (int side = 0; side < 4; ++side) {
         const int k = p->bc_kind[side];
         if (k != IBPM_BC_DIRICHLET && k != IBPM_BC_CONVECTIVE) throw InvalidArg("unknown wall kind (bc_kind)");
@@ -1417,6 +1461,40 @@ void fused_transfer_products(Hierarchy &h) {
 }
 
 // Upload the hierarchy in precision T (values converted from FP64)
+// Rows per block of the row-block CSR kernels for the matrices one kernel
+// walks together: the largest power of two up to 256 for which every
+// block's entries fit kStreamCap; 0 when a single row does not (then the
+// row-vector kernels run).  IBPM_CSR_STREAM=0 selects the row-vector kernels
+// everywhere.
+int stream_rows(std::initializer_list<const CSR *> ms) {
+    static const bool off = [] {
+        const char *e = std::getenv("IBPM_CSR_STREAM");
+        return e && e[0] == '0';
+    }();
+    if (off || ms.size() == 0) return 0;
+    const int n = (*ms.begin())->nrows;
+    for (const CSR *m : ms)
+        if (m->nrows != n || (int)m->ptr.size() != n + 1) return 0;
+    for (int rpb = 256; rpb >= 1; rpb /= 2) {
+        bool ok = true;
+        for (int r0 = 0; r0 < n && ok; r0 += rpb) {
+            const int r1 = std::min(r0 + rpb, n);
+            int64_t tot = 0;
+            for (const CSR *m : ms) tot += m->ptr[r1] - m->ptr[r0];
+            ok = tot <= kStreamCap;
+        }
+        if (ok) return rpb;
+    }
+    return 0;
+}
+
+// the launch shape of a CSR kernel: -rows per block for the row-block
+// kernels, else the lanes per row of the row-vector kernels
+int csr_shape(int lanes, std::initializer_list<const CSR *> ms) {
+    const int r = stream_rows(ms);
+    return r > 0 ? -r : lanes;
+}
+
 template <class T>
 void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
     int L = (int)c->h.levels.size();
@@ -1426,11 +1504,11 @@ void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
         DevLevelT<T> &dl = P.lev[l];
         dl.n = hl.A.nrows;
         dl.omega = hl.omega;
-        const bool stored = l > 0 || c->bn > 1;   // level 0 is matrix-free only for B^1
+        const bool stored = l > 0 || c->stored0;   // level 0 is matrix-free for a fixed body and B^1
         if (stored) {
             bool shared = false;
             if constexpr (std::is_same<T, double>::value) {
-                if (l == 0 && c->bn > 1) {
+                if (l == 0 && c->stored0) {
                     dl.A = c->K0c;   // the finest operator is the stored K, uploaded once
                     shared = true;
                 }
@@ -1457,6 +1535,18 @@ void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
             if (hl.RA.nrows > 0) dl.RA = c->upload_csr<T>(hl.RA);
             if (hl.AP.nrows > 0) dl.AP = c->upload_csr<T>(hl.AP);
         }
+        // launch shapes (the fused kernels walk their matrices together);
+        // a moving body changes the rows, so its levels keep row-vector shapes
+        if (c->moving) {
+            dl.xa = c->dalloc<T>(dl.n);
+            dl.xb = c->dalloc<T>(dl.n);
+            continue;
+        }
+        if (dl.A.nrows > 0) dl.A.lanes = csr_shape(dl.A.lanes, {&hl.A});
+        if (dl.R.nrows > 0) dl.R.lanes = csr_shape(dl.R.lanes, {&hl.R});
+        if (dl.P.nrows > 0) dl.P.lanes = csr_shape(dl.P.lanes, {&hl.P});
+        if (dl.RA.nrows > 0) dl.RA.lanes = csr_shape(dl.RA.lanes, {&hl.R, &hl.RA});
+        if (dl.AP.nrows > 0) dl.AP.lanes = csr_shape(dl.AP.lanes, {&hl.A, &hl.AP, &hl.P});
         dl.xa = c->dalloc<T>(dl.n);
         dl.xb = c->dalloc<T>(dl.n);
     }
@@ -1751,6 +1841,458 @@ void enqueue_vcycle_csr(ibpm_ctx *c, PrecSet<double> &P, const double *r, double
     c->rz_G = launch_dot_rz_parts(s, P.lev[0].n, r, z, st, c->parts);
 }
 
+// ---------------------------------------------------------------------------
+// A body in prescribed motion (Sec. 4 and 6).  E and every row of K that
+// couples to the forces are formed anew on the device at each move; the
+// level-0 K is a stored CSR rewritten in place.  The SA hierarchy is kept
+// for a number of moves and then formed anew on the device from the
+// current K: the aggregates and the smoothing weights of the first set-up
+// are kept (the aggregation follows the sparsity pattern, which a rigid
+// motion leaves as it was up to the cells near the body), the prolongators
+// P = (I - w D^-1 A) T, their transposes and the Galerkin products
+// P^T A P are recomputed down to the first level of the dense coarse cycle,
+// whose small levels and dense map are formed on the host.
+
+void invalidate_graphs(ibpm_ctx *c) {
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    for (ibpm_ctx::IterGraph &G : c->graphs) {
+        if (G.exec) (void)hipGraphExecDestroy(G.exec);
+        G.exec = nullptr;
+        G.key.clear();
+    }
+}
+
+// exclusive scan of cnt (n values) on the device into off64 (n + 1) and,
+// when non-null, off32; returns the total (read back)
+int64_t device_scan(ibpm_ctx *c, int n, const int32_t *cnt, int64_t *off64, int32_t *off32) {
+    hipStream_t s = c->stream;
+    int64_t *tiles = c->dtemp<int64_t>(scan_tiles_for(n) + 1);
+    int64_t *total = tiles + scan_tiles_for(n);
+    launch_exclusive_scan(s, n, cnt, off64, off32, tiles, total);
+    int64_t h = 0;
+    HIPCHECK(hipMemcpyAsync(&h, total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    c->dfree(tiles);
+    return h;
+}
+
+// product rows with the offsets scanned on the device; `count` may raise
+// *err (a left row longer than the merge allows), which is returned
+template <class Count, class Fill>
+bool product_rows_dev(ibpm_ctx *c, int nrows, int ncols, Count count, Fill fill, bool keep, DevCSR &out) {
+    hipStream_t s = c->stream;
+    int32_t *cnt = c->dtemp<int32_t>(nrows);
+    int *err = c->dtemp<int>(1);
+    HIPCHECK(hipMemsetAsync(err, 0, sizeof(int), s));
+    count(cnt, err);
+    int64_t *off = c->dtemp<int64_t>(nrows + 1);
+    int32_t *ptr = keep ? c->dalloc<int32_t>(nrows + 1) : c->dtemp<int32_t>(nrows + 1);
+    const int64_t nnz = device_scan(c, nrows, cnt, off, ptr);
+    int herr = 0;
+    HIPCHECK(hipMemcpy(&herr, err, sizeof(int), hipMemcpyDeviceToHost));
+    c->dfree(cnt);
+    c->dfree(err);
+    if (herr || nnz >= INT32_MAX) {
+        c->dfree(off);
+        if (keep) c->release(ptr);
+        else c->dfree(ptr);
+        if (!herr) throw InvalidArg("a hierarchy product has more than 2^31 entries");
+        return false;
+    }
+    out = DevCSR();
+    out.nrows = nrows;
+    out.ncols = ncols;
+    out.nnz = nnz;
+    out.lanes = lanes_for(nnz, nrows);
+    out.ptr = ptr;
+    out.col = keep ? c->dalloc<int32_t>(nnz) : c->dtemp<int32_t>(nnz);
+    out.val = keep ? c->dalloc<double>(nnz) : c->dtemp<double>(nnz);
+    fill(off, out.col, out.val);
+    HIPCHECK(hipStreamSynchronize(s));
+    c->dfree(off);
+    return true;
+}
+
+void drop_csr(ibpm_ctx *c, DevCSR &d, bool keep) {
+    if (keep) {
+        c->release(d.ptr);
+        c->release(d.col);
+        c->release(d.val);
+    } else {
+        free_temp_csr(c, d);
+    }
+    d = DevCSR();
+}
+
+// C = A B for left rows of any length: rows longer than kMergeMax are split
+// into chunks whose products are summed by a second product
+DevCSR spgemm_any(ibpm_ctx *c, const DevCSR &A, const DevCSR &B, bool keep) {
+    hipStream_t s = c->stream;
+    const CSRView Av = A.view(), Bv = B.view();
+    const int n = A.nrows;
+    DevCSR C;
+    if (product_rows_dev(
+            c, n, B.ncols, [&](int32_t *cnt, int *err) { launch_spgemm_count(s, n, 0, nullptr, Av, Bv, cnt, err); },
+            [&](const int64_t *off, int32_t *col, double *val) {
+                launch_spgemm_fill(s, n, 0, nullptr, Av, Bv, off, col, val);
+            },
+            keep, C))
+        return C;
+    int32_t *cnt = c->dtemp<int32_t>(n);
+    launch_chunk_count(s, n, A.ptr, cnt);
+    int64_t *off64 = c->dtemp<int64_t>(n + 1);
+    int32_t *off32 = c->dtemp<int32_t>(n + 1);
+    const int64_t nch = device_scan(c, n, cnt, off64, off32);
+    c->dfree(cnt);
+    c->dfree(off64);
+    DevCSR Ac{}, S{};
+    Ac.nrows = (int)nch;
+    Ac.ncols = A.ncols;
+    Ac.ptr = c->dtemp<int32_t>(nch + 1);
+    Ac.col = A.col;
+    Ac.val = A.val;
+    S.nrows = n;
+    S.ncols = (int)nch;
+    S.ptr = off32;
+    S.col = c->dtemp<int32_t>(nch);
+    S.val = c->dtemp<double>(nch);
+    launch_chunk_fill(s, n, A.ptr, off32, Ac.ptr, S.col, S.val);
+    DevCSR Z;
+    const CSRView Acv = Ac.view();
+    const int ncr = (int)nch;
+    if (!product_rows_dev(
+            c, ncr, B.ncols, [&](int32_t *cc, int *err) { launch_spgemm_count(s, ncr, 0, nullptr, Acv, Bv, cc, err); },
+            [&](const int64_t *off, int32_t *col, double *val) {
+                launch_spgemm_fill(s, ncr, 0, nullptr, Acv, Bv, off, col, val);
+            },
+            false, Z))
+        throw InvalidArg("hierarchy product: a chunk row exceeds the merge width");
+    const CSRView Sv = S.view(), Zv = Z.view();
+    const bool ok = product_rows_dev(
+        c, n, B.ncols, [&](int32_t *cc, int *err) { launch_spgemm_count(s, n, 0, nullptr, Sv, Zv, cc, err); },
+        [&](const int64_t *off, int32_t *col, double *val) {
+            launch_spgemm_fill(s, n, 0, nullptr, Sv, Zv, off, col, val);
+        },
+        keep, C);
+    free_temp_csr(c, Z);
+    c->dfree(Ac.ptr);
+    c->dfree(S.col);
+    c->dfree(S.val);
+    c->dfree(off32);
+    if (!ok) throw InvalidArg("hierarchy product: a row has more than kMergeMax^2 entries");
+    return C;
+}
+
+// A^T (rows sorted) in memory that lives as long as the context
+DevCSR transpose_dev(ibpm_ctx *c, const DevCSR &A) {
+    hipStream_t s = c->stream;
+    const int m = A.ncols;
+    int32_t *cnt = c->dtemp<int32_t>(m);
+    HIPCHECK(hipMemsetAsync(cnt, 0, (size_t)m * sizeof(int32_t), s));
+    launch_col_count(s, A.nnz, A.col, cnt);
+    DevCSR T;
+    T.nrows = m;
+    T.ncols = A.nrows;
+    T.ptr = c->dalloc<int32_t>(m + 1);
+    int64_t *off = c->dtemp<int64_t>(m + 1);
+    T.nnz = device_scan(c, m, cnt, off, T.ptr);
+    c->dfree(off);
+    if (T.nnz != A.nnz) throw HipError("transpose: entry count mismatch");
+    T.col = c->dalloc<int32_t>(T.nnz);
+    T.val = c->dalloc<double>(T.nnz);
+    HIPCHECK(hipMemsetAsync(cnt, 0, (size_t)m * sizeof(int32_t), s));
+    launch_transpose_fill(s, A.view(), T.ptr, cnt, T.col, T.val);
+    launch_sort_rows(s, m, T.ptr, T.col, T.val);
+    HIPCHECK(hipStreamSynchronize(s));
+    c->dfree(cnt);
+    T.lanes = lanes_for(T.nnz, T.nrows);
+    return T;
+}
+
+// Form the hierarchy anew from the current level-0 K (see above)
+void refresh_hierarchy(ibpm_ctx *c) {
+    hipStream_t s = c->stream;
+    PrecSet<double> &P = c->p64;
+    Hierarchy &h = c->h;
+    const int L = (int)P.lev.size();
+    if (L < 2) {
+        // one level: the dense solve of the moved K
+        const DevCSR &D = c->K0c;
+        CSR A;
+        A.nrows = D.nrows;
+        A.ncols = D.ncols;
+        A.ptr.resize(D.nrows + 1);
+        A.col.resize(D.nnz);
+        A.val.resize(D.nnz);
+        HIPCHECK(hipStreamSynchronize(s));
+        HIPCHECK(hipMemcpy(A.ptr.data(), D.ptr, A.ptr.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(A.col.data(), D.col, A.col.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPCHECK(hipMemcpy(A.val.data(), D.val, A.val.size() * sizeof(double), hipMemcpyDeviceToHost));
+        try {
+            regalerkin_from(h, 0, std::move(A));
+        } catch (const std::runtime_error &e) {
+            throw InvalidArg(e.what());
+        }
+        HIPCHECK(hipMemcpy(c->coarse_inv, h.coarse_inv.data(), h.coarse_inv.size() * sizeof(double),
+                           hipMemcpyHostToDevice));
+        h.levels[0].wdinv.clear();
+        c->refreshes++;
+        invalidate_graphs(c);
+        return;
+    }
+    const int lc = P.lc;
+    double *diag = c->dtemp<double>(P.lev[0].n);
+    int *err = c->dtemp<int>(1);
+    HIPCHECK(hipMemsetAsync(err, 0, sizeof(int), s));
+    for (int l = 0; l < lc; ++l) {
+        DevLevelT<double> &lv = P.lev[l];
+        const Level &hl = h.levels[l];
+        const DevCSR &A = lv.A;
+        launch_diag_weights(s, A.view(), hl.omega, diag, lv.wdinv);
+        const int nc = P.lev[l + 1].n;
+        DevCSR T{};
+        T.nrows = lv.n;
+        T.ncols = nc;
+        T.nnz = lv.n;
+        T.ptr = c->dtemp<int32_t>(lv.n + 1);
+        T.col = c->dtemp<int32_t>(lv.n);
+        T.val = c->dtemp<double>(lv.n);
+        launch_tentative(s, lv.n, c->agg_d[l], T.ptr, T.col, T.val);
+        DevCSR Pn = spgemm_any(c, A, T, true);
+        free_temp_csr(c, T);
+        launch_smooth_prolongator(s, lv.n, Pn.ptr, Pn.col, Pn.val, c->agg_d[l], diag, hl.pomega, err);
+        DevCSR Rn = transpose_dev(c, Pn);
+        DevCSR AP = spgemm_any(c, A, Pn, false);
+        DevCSR Ac = spgemm_any(c, Rn, AP, true);
+        free_temp_csr(c, AP);
+        drop_csr(c, lv.P, true);
+        drop_csr(c, lv.R, true);
+        lv.P = Pn;
+        lv.R = Rn;
+        drop_csr(c, P.lev[l + 1].A, true);
+        P.lev[l + 1].A = Ac;
+    }
+    int herr = 0;
+    HIPCHECK(hipMemcpyAsync(&herr, err, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHECK(hipStreamSynchronize(s));
+    c->dfree(err);
+    c->dfree(diag);
+    if (herr) throw InvalidArg("AMG: non-positive diagonal in the moved operator");
+    // the small levels on the host: A_lc back, the levels below it and the
+    // dense coarse cycle formed there
+    const DevCSR &Alc = P.lev[lc].A;
+    CSR A;
+    A.nrows = Alc.nrows;
+    A.ncols = Alc.ncols;
+    A.ptr.resize(Alc.nrows + 1);
+    A.col.resize(Alc.nnz);
+    A.val.resize(Alc.nnz);
+    HIPCHECK(hipMemcpy(A.ptr.data(), Alc.ptr, A.ptr.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(A.col.data(), Alc.col, A.col.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    HIPCHECK(hipMemcpy(A.val.data(), Alc.val, A.val.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (int l = 0; l < lc; ++l) c->level_nnz[l + 1] = P.lev[l + 1].A.nnz;
+    try {
+        regalerkin_from(h, lc, std::move(A));
+    } catch (const std::runtime_error &e) {
+        throw InvalidArg(e.what());
+    }
+    for (int l = lc + 1; l < L; ++l) c->level_nnz[l] = h.levels[l].A.nnz();
+    c->coarse_C = coarse_cycle_matrix(h, lc, c->prm.amg_pre, c->prm.amg_post);
+    HIPCHECK(hipMemcpy(c->coarse_C_dev, c->coarse_C.data(), c->coarse_C.size() * sizeof(double),
+                       hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(c->coarse_inv, h.coarse_inv.data(), h.coarse_inv.size() * sizeof(double),
+                       hipMemcpyHostToDevice));
+    for (int l = lc; l < L; ++l) {
+        Level &hl = h.levels[l];
+        hl.P = CSR();
+        hl.R = CSR();
+        hl.wdinv.clear();
+    }
+    c->refreshes++;
+    invalidate_graphs(c);
+}
+
+// K's level-0 storage with room for `cap` entries (the row starts stay)
+void grow_k0(ibpm_ctx *c, int64_t cap) {
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    c->release(c->K0c.col);
+    c->release(c->K0c.val);
+    c->K0c.col = c->dalloc<int32_t>(cap);
+    c->K0c.val = c->dalloc<double>(cap);
+    c->K_cap = cap;
+    c->K0op.A = c->K0c.view();
+    if (!c->p64.lev.empty()) {
+        c->p64.lev[0].A.col = c->K0c.col;
+        c->p64.lev[0].A.val = c->K0c.val;
+    }
+    invalidate_graphs(c);
+}
+
+// room for `need` entries of a (col, val) pair of row buffers
+void grow_pair(ibpm_ctx *c, int32_t *&col, double *&val, int64_t &cap, int64_t need) {
+    if (col && need <= cap) return;
+    HIPCHECK(hipStreamSynchronize(c->stream));
+    c->release(col);
+    c->release(val);
+    cap = std::max<int64_t>({need, cap + cap / 2, 1});
+    col = c->dalloc<int32_t>(cap);
+    val = c->dalloc<double>(cap);
+}
+
+// E and K for the point positions in xb_d / yb_d (host copies xb, yb)
+void assemble_moving(ibpm_ctx *c, const double *xb, const double *yb) {
+    hipStream_t s = c->stream;
+    const Model &m = c->m;
+    const GridMetrics &G = m.g;
+    const int nb = m.nb, nx = G.nx, ny = G.ny;
+    const int n_cell = (int)G.n_cell, nl = n_cell + 2 * nb;
+    // the cells whose faces the E rows reach: the point's cell +- 2
+    auto cell = [](const std::vector<double> &f, double x) {
+        return (int)(std::upper_bound(f.begin(), f.end(), x) - f.begin()) - 1;
+    };
+    int i0 = INT_MAX, i1 = INT_MIN, j0 = INT_MAX, j1 = INT_MIN;
+    double hmax = 0.0;
+    for (int k = 0; k < nb; ++k) {
+        const int i = cell(G.xf, xb[k]), j = cell(G.yf, yb[k]);
+        i0 = std::min(i0, i - 2);
+        i1 = std::max(i1, i + 2);
+        j0 = std::min(j0, j - 2);
+        j1 = std::max(j1, j + 2);
+        hmax = std::max({hmax, G.dx[i], G.dy[j]});
+    }
+    i0 = std::max(i0, 0);
+    j0 = std::max(j0, 0);
+    i1 = std::min(i1, nx - 1);
+    j1 = std::min(j1, ny - 1);
+    c->box[0] = i0;
+    c->box[1] = i1;
+    c->box[2] = j0;
+    c->box[3] = j1;
+    const int nbox = (i1 - i0 + 1) * (j1 - j0 + 1);
+    launch_e_rows(s, c->g, c->xf_d, c->yf_d, nb, c->xb_d, c->yb_d, c->ecol, c->eval);
+    const double reach = 3.5 * hmax;
+    const double dt = c->prm.dt;
+    const int pin = m.pin;
+    // force rows: lengths, offsets, rows
+    launch_force_rows(s, c->g, dt, nb, pin, c->ecol, c->eval, c->xb_d, c->yb_d, reach, c->force_len, nullptr,
+                      nullptr, nullptr);
+    const int64_t nf = device_scan(c, 2 * nb, c->force_len, c->force_ptr, nullptr);
+    grow_pair(c, c->force_col, c->force_val, c->force_cap, nf);
+    launch_force_rows(s, c->g, dt, nb, pin, c->ecol, c->eval, c->xb_d, c->yb_d, reach, nullptr, c->force_ptr,
+                      c->force_col, c->force_val);
+    // rows of the box cells
+    if (nbox > c->box_rows_cap) {
+        HIPCHECK(hipStreamSynchronize(s));
+        c->release(c->box_len);
+        c->release(c->box_ptr);
+        c->box_rows_cap = nbox;
+        c->box_len = c->dalloc<int32_t>(nbox);
+        c->box_ptr = c->dalloc<int64_t>(nbox + 1);
+    }
+    const CSRView Kpp = c->Kpp.view();
+    launch_box_rows(s, c->g, c->xf_d, c->yf_d, dt, nb, pin, i0, i1, j0, j1, Kpp, c->ecol, c->eval, c->xb_d, c->yb_d,
+                    c->box_len, nullptr, nullptr, nullptr);
+    const int64_t nbx = device_scan(c, nbox, c->box_len, c->box_ptr, nullptr);
+    grow_pair(c, c->box_col, c->box_val, c->box_cap, nbx);
+    launch_box_rows(s, c->g, c->xf_d, c->yf_d, dt, nb, pin, i0, i1, j0, j1, Kpp, c->ecol, c->eval, c->xb_d, c->yb_d,
+                    nullptr, c->box_ptr, c->box_col, c->box_val);
+    // the whole K: lengths, row starts, rows
+    launch_row_lengths(s, nx, n_cell, nl, i0, i1, j0, j1, Kpp, c->box_len, c->force_len, c->len_all);
+    const int64_t nnz = device_scan(c, nl, c->len_all, c->ptr64, c->K0c.ptr);
+    if (nnz >= INT32_MAX) throw InvalidArg("K has more than 2^31 entries");
+    if (nnz > c->K_cap) grow_k0(c, nnz + nnz / 8);
+    launch_assemble(s, nx, n_cell, nl, i0, i1, j0, j1, Kpp, c->box_ptr, c->box_col, c->box_val, c->force_ptr,
+                    c->force_col, c->force_val, c->K0c.ptr, c->K0c.col, c->K0c.val);
+    c->K0c.nnz = nnz;
+    if (!c->p64.lev.empty()) c->p64.lev[0].A.nnz = nnz;
+    c->level_nnz[0] = nnz;
+    const double w0 = c->amg ? c->h.levels[0].omega : 1.0;
+    launch_diag_weights(s, c->K0c.view(), w0, c->K0diag, c->amg ? c->p64.lev[0].wdinv : nullptr);
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+void upload_points(ibpm_ctx *c, const double *xb, const double *yb, const double *ubx, const double *uby) {
+    const int nb = c->m.nb;
+    if (nb == 0) return;
+    hipStream_t s = c->stream;
+    HIPCHECK(hipMemcpyAsync(c->xb_d, xb, nb * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(c->yb_d, yb, nb * sizeof(double), hipMemcpyHostToDevice, s));
+    if (ubx && uby) {
+        HIPCHECK(hipMemcpyAsync(c->ub, ubx, nb * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHECK(hipMemcpyAsync(c->ub + nb, uby, nb * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    HIPCHECK(hipStreamSynchronize(s));
+}
+
+// Device storage of the moving-body path, then E and K at the first
+// positions; called after the hierarchy is on the device
+void moving_setup(ibpm_ctx *c, const ibpm_params *p) {
+    const Model &m = c->m;
+    const GridMetrics &G = m.g;
+    const int nb = m.nb, n_cell = (int)G.n_cell, nl = n_cell + 2 * nb;
+    c->xf_d = c->upload(G.xf);
+    c->yf_d = c->upload(G.yf);
+    c->xb_d = c->dalloc<double>(nb);
+    c->yb_d = c->dalloc<double>(nb);
+    c->ecol = c->dalloc<int32_t>((size_t)2 * nb * kEllE);
+    c->eval = c->dalloc<double>((size_t)2 * nb * kEllE);
+    std::vector<int32_t> ep(2 * nb + 1);
+    for (int t = 0; t <= 2 * nb; ++t) ep[t] = t * kEllE;
+    c->eptr = c->upload(ep);
+    // E as a CSR view over its fixed-width rows (zero weights included)
+    c->E.nrows = 2 * nb;
+    c->E.ncols = (int)G.n_q;
+    c->E.nnz = (int64_t)2 * nb * kEllE;
+    c->E.ptr = c->eptr;
+    c->E.col = c->ecol;
+    c->E.val = c->eval;
+    // the pressure rows of K (cell rows, cell columns), fixed
+    CSR Kpp;
+    Kpp.nrows = n_cell;
+    Kpp.ncols = n_cell;
+    Kpp.ptr.assign(1, 0);
+    for (int r = 0; r < n_cell; ++r) {
+        for (int32_t q = m.K.ptr[r]; q < m.K.ptr[r + 1]; ++q)
+            if (m.K.col[q] < n_cell) {
+                Kpp.col.push_back(m.K.col[q]);
+                Kpp.val.push_back(m.K.val[q]);
+            }
+        Kpp.ptr.push_back((int32_t)Kpp.col.size());
+    }
+    c->Kpp = c->upload_csr<double>(Kpp);
+    c->len_all = c->dalloc<int32_t>(nl);
+    c->ptr64 = c->dalloc<int64_t>(nl + 1);
+    c->force_len = c->dalloc<int32_t>(std::max(1, 2 * nb));
+    c->force_ptr = c->dalloc<int64_t>(2 * nb + 1);
+    c->level_nnz.assign(std::max<size_t>(1, c->h.levels.size()), 0);
+    for (size_t l = 0; l < c->h.levels.size(); ++l) c->level_nnz[l] = c->h.levels[l].A.nnz();
+    if (c->amg) {
+        const int lc = c->p64.lc;
+        c->agg_d.assign(lc, nullptr);
+        for (int l = 0; l < lc; ++l) c->agg_d[l] = c->upload(c->h.levels[l].agg);
+    }
+    upload_points(c, p->xb, p->yb, nullptr, nullptr);
+    assemble_moving(c, p->xb, p->yb);
+}
+
+void move_body(ibpm_ctx *c, const double *xb, const double *yb, const double *ubx, const double *uby) {
+    if (!c->moving) throw InvalidArg("the context was built for a fixed body (moving_body = 0)");
+    const int nb = c->m.nb;
+    if (nb > 0 && (!xb || !yb || !ubx || !uby)) throw InvalidArg("NULL point array");
+    for (int k = 0; k < nb; ++k)
+        if (!std::isfinite(xb[k]) || !std::isfinite(yb[k]) || !std::isfinite(ubx[k]) || !std::isfinite(uby[k]))
+            throw InvalidArg("point positions and velocities must be finite");
+    try {
+        check_points(c->m.g, nb, xb, yb);
+    } catch (const std::runtime_error &e) {
+        throw InvalidArg(e.what());
+    }
+    upload_points(c, xb, yb, ubx, uby);
+    assemble_moving(c, xb, yb);
+    ++c->moves;
+    if (c->amg && c->prm.amg_rebuild_every > 0 && c->moves % c->prm.amg_rebuild_every == 0) refresh_hierarchy(c);
+}
+
 // Work memory of the allocation-free velocity solve: the five PCG vectors
 // (r, z, two directions, q) of at most kStaticMaxNq values each, three
 // buffers of per-block partial sums (three rows of kMaxParts each, as many
@@ -1815,6 +2357,8 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     // every parameter is valid: from here on the device is used
     c->static_work = static_work_address();
     c->bn = p->bn_order;
+    c->moving = p->moving_body != 0;
+    c->stored0 = c->bn > 1 || c->moving;
     if (c->bn > 1) form_bn_operators(c);   // replaces m.K by the pinned Q^T B^N Q
     if (c->amg) {
         AmgParams ap;
@@ -1826,7 +2370,8 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
         } catch (const std::runtime_error &e) {
             throw InvalidArg(e.what());
         }
-        if (p->fuse_transfers) fused_transfer_products(c->h);
+        // the fused products hold K, which a moving body changes
+        if (p->fuse_transfers && !c->moving) fused_transfer_products(c->h);
     }
     const GridMetrics &G = m.g;
     c->g = make_grid<double>(c, G);
@@ -1873,6 +2418,22 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
         c->K0op.A = c->K0c.view();
         c->K0op.diag = c->upload(dg);
         c->wq = c->dalloc<double>(nq);
+    }
+    if (c->moving) {
+        // the stored level-0 K with room for the rows of the moved body
+        const int64_t nnz = m.K.nnz();
+        c->K_cap = nnz + std::max<int64_t>(4096, (int64_t)256 * m.nb);
+        c->K0c.nrows = c->K0c.ncols = nl;
+        c->K0c.nnz = nnz;
+        c->K0c.lanes = lanes_for(nnz, nl);
+        c->K0c.ptr = c->upload(m.K.ptr);
+        c->K0c.col = c->dalloc<int32_t>(c->K_cap);
+        c->K0c.val = c->dalloc<double>(c->K_cap);
+        HIPCHECK(hipMemcpy(c->K0c.col, m.K.col.data(), nnz * sizeof(int32_t), hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(c->K0c.val, m.K.val.data(), nnz * sizeof(double), hipMemcpyHostToDevice));
+        c->K0diag = c->dalloc<double>(nl);
+        c->K0op.A = c->K0c.view();
+        c->K0op.diag = c->K0diag;
     }
     if (c->amg) {
         upload_levels<double>(c, c->p64);
@@ -1932,6 +2493,7 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     HIPCHECK(hipHostMalloc((void **)&c->host_st, sizeof(SolveStatus), hipHostMallocDefault));
     launch_fill_walls(c->stream, c->g, c->walls[0], c->wall_init);
     launch_fill_walls(c->stream, c->g, c->walls[1], c->wall_init);
+    if (c->moving) moving_setup(c, p);
     HIPCHECK(hipStreamSynchronize(c->stream));
 }
 
@@ -2077,7 +2639,7 @@ int ibpm_solve_velocity_static(ibpm_ctx *c, const double *rhs, double *q, ibpm_s
 int ibpm_apply_K(ibpm_ctx *c, const double *x, double *y) {
     return guarded(c, [&] {
         if (!x || !y || x == y) throw InvalidArg("x and y must be distinct device vectors");
-        if (c->bn > 1) launch_csr_gemv(c->stream, c->K0c.view(), x, 1.0, nullptr, y);
+        if (c->stored0) launch_csr_gemv(c->stream, c->K0c.view(), x, 1.0, nullptr, y);
         else launch_apply_K0(c->stream, c->p64.K0, x, y);
         return IBPM_OK;
     });
@@ -2094,6 +2656,16 @@ int ibpm_apply_A(ibpm_ctx *c, const double *x, double *y) {
 int ibpm_get_poisson_matrix(ibpm_ctx *c, int64_t *nnz, int32_t *ptr, int32_t *col, double *val) {
     return guarded(c, [&] {
         if (!nnz) throw InvalidArg("nnz is NULL");
+        if (c->moving) {
+            // the device K of the current positions
+            const DevCSR &D = c->K0c;
+            *nnz = D.nnz;
+            HIPCHECK(hipStreamSynchronize(c->stream));
+            if (ptr) HIPCHECK(hipMemcpy(ptr, D.ptr, (D.nrows + 1) * sizeof(int32_t), hipMemcpyDeviceToHost));
+            if (col) HIPCHECK(hipMemcpy(col, D.col, D.nnz * sizeof(int32_t), hipMemcpyDeviceToHost));
+            if (val) HIPCHECK(hipMemcpy(val, D.val, D.nnz * sizeof(double), hipMemcpyDeviceToHost));
+            return IBPM_OK;
+        }
         const CSR &K = c->m.K;
         *nnz = K.nnz();
         if (ptr) std::memcpy(ptr, K.ptr.data(), K.ptr.size() * sizeof(int32_t));
@@ -2107,10 +2679,29 @@ int ibpm_bn_info(const ibpm_ctx *cc, int64_t *nnz_K, int64_t *nnz_B, int64_t *pe
                  int64_t *unsliced_bytes) {
     ibpm_ctx *c = const_cast<ibpm_ctx *>(cc);
     return guarded(c, [&] {
-        if (nnz_K) *nnz_K = c->m.K.nnz();
+        if (nnz_K) *nnz_K = c->moving ? c->K0c.nnz : c->m.K.nnz();
         if (nnz_B) *nnz_B = c->bn > 1 ? c->Bn.nnz : (int64_t)c->g.n_q;
         if (peak_bytes) *peak_bytes = c->bn_peak_bytes;
         if (unsliced_bytes) *unsliced_bytes = c->bn_unsliced_bytes;
+        return IBPM_OK;
+    });
+}
+
+int ibpm_move_body(ibpm_ctx *c, const double *xb, const double *yb, const double *ubx, const double *uby) {
+    return guarded(c, [&] {
+        move_body(c, xb, yb, ubx, uby);
+        return IBPM_OK;
+    });
+}
+
+int ibpm_moving_info(const ibpm_ctx *cc, int64_t *moves, int64_t *refreshes, int32_t *box) {
+    ibpm_ctx *c = const_cast<ibpm_ctx *>(cc);
+    return guarded(c, [&] {
+        if (!c->moving) throw InvalidArg("the context was built for a fixed body (moving_body = 0)");
+        if (moves) *moves = c->moves;
+        if (refreshes) *refreshes = c->refreshes;
+        if (box)
+            for (int k = 0; k < 4; ++k) box[k] = c->box[k];
         return IBPM_OK;
     });
 }
@@ -2200,7 +2791,7 @@ int ibpm_hierarchy_info(const ibpm_ctx *c, int32_t *levels, int64_t *sizes, int6
     *levels = (int32_t)c->h.levels.size();
     for (size_t l = 0; l < c->h.levels.size(); ++l) {
         if (sizes) sizes[l] = c->h.levels[l].A.nrows;
-        if (nnz) nnz[l] = c->h.levels[l].A.nnz();
+        if (nnz) nnz[l] = c->moving ? c->level_nnz[l] : c->h.levels[l].A.nnz();
     }
     return IBPM_OK;
 }
@@ -2274,7 +2865,7 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, int64_t min_foot
                      double *bytes) {
     return guarded(c, [&] {
         if (reps < 1 || !avg_ms || min_footprint < 0) throw InvalidArg("bad arguments");
-        if (c->bn > 1 && kernel != IBPM_KERNEL_A_PCG_SPMV && kernel != IBPM_KERNEL_STREAM_COPY)
+        if (c->stored0 && kernel != IBPM_KERNEL_A_PCG_SPMV && kernel != IBPM_KERNEL_STREAM_COPY)
             throw InvalidArg("the level-0 kernels time the matrix-free operator of B^1 only");
         const bool needs_amg = kernel == IBPM_KERNEL_K0_JACOBI || kernel == IBPM_KERNEL_K0_RESIDUAL ||
                                kernel == IBPM_KERNEL_RESTRICT0 || kernel == IBPM_KERNEL_PROLONG0 ||
@@ -2538,7 +3129,7 @@ int ibpm_iteration_launches(const ibpm_ctx *cc, int32_t ncounts, int32_t *counts
     ibpm_ctx *c = const_cast<ibpm_ctx *>(cc);
     return guarded(c, [&] {
         if (!counts || ncounts < 0) throw InvalidArg("bad arguments");
-        if (c->bn > 1) throw InvalidArg("launch counts are given for the B^1 iteration only");
+        if (c->stored0) throw InvalidArg("launch counts are given for the matrix-free iteration only");
         PrecSet<double> &P = c->p64;
         if (!c->amg || P.lev.size() < 2) throw InvalidArg("needs an AMG hierarchy of two or more levels");
         int32_t k[IBPM_NUM_KERNELS] = {};

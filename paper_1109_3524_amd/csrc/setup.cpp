@@ -514,6 +514,14 @@ CSR poisson_qt(const Model &m) {
     return Q;
 }
 
+void check_points(const GridMetrics &g, int nb, const double *xb, const double *yb) {
+    for (int k = 0; k < nb; ++k) {
+        if (!std::isfinite(xb[k]) || !std::isfinite(yb[k])) fail("point positions must be finite");
+        (void)local_width(g.xf, g.dx, xb[k], "x");
+        (void)local_width(g.yf, g.dy, yb[k], "y");
+    }
+}
+
 CSR pin_rows_cols(const CSR &K, int32_t pin) {
     // clear row and column `pin` except the diagonal entry
     CSR out;
@@ -877,6 +885,31 @@ void build_hierarchy(Hierarchy &h, const CSR &K, const AmgParams &prm) {
     if (Ac.nrows > 4096) fail("AMG: coarsest level too large for a dense solve");
     h.n_coarse = Ac.nrows;
     dense_spd_inverse(Ac, h.coarse_inv);
+}
+
+void regalerkin_from(Hierarchy &h, int from, CSR &&A) {
+    const int L = (int)h.levels.size();
+    if (from < 0 || from >= L) fail("hierarchy refresh: bad level");
+    h.levels[from].A = std::move(A);
+    for (int l = from; l < L; ++l) {
+        Level &lv = h.levels[l];
+        const int n = lv.A.nrows;
+        std::vector<double> d(n);
+        for (int r = 0; r < n; ++r) {
+            d[r] = diag_of(lv.A, r);
+            if (!(d[r] > 0)) fail("AMG: non-positive diagonal");
+        }
+        lv.wdinv.resize(n);
+        for (int r = 0; r < n; ++r) lv.wdinv[r] = lv.omega / d[r];
+        if (l == L - 1) break;
+        CSR P = smoothed_prolongator(lv.A, d, lv.agg, h.levels[l + 1].A.nrows, lv.pomega);
+        CSR R = csr_transpose(P);
+        CSR RA = csr_multiply(R, lv.A);
+        h.levels[l + 1].A = csr_multiply(RA, P);
+        lv.P = std::move(P);
+        lv.R = std::move(R);
+    }
+    dense_spd_inverse(h.levels.back().A, h.coarse_inv);
 }
 
 namespace {

@@ -91,6 +91,11 @@ void build_hierarchy(Hierarchy &h, const CSR &K, const AmgParams &p);
 // level, prolongation, post sweeps) is a fixed linear map b -> x; returns its
 // matrix, row-major n_lc x n_lc.
 std::vector<double> coarse_cycle_matrix(const Hierarchy &h, int lc, int pre, int post);
+// Levels from..L-1 formed anew from a new operator A of level `from`, with
+// the aggregates and smoothing weights each level already holds: the
+// Jacobi weights, P = (I - pomega D^-1 A) T, R = P^T, the Galerkin
+// products and the inverse of the coarsest operator.
+void regalerkin_from(Hierarchy &h, int from, CSR &&A);
 
 // Operators of B^N for N > 1, built on the host for the device products:
 // L = M Lhat R^-1 on the interior faces (n_q x n_q, rows sorted), the
@@ -100,6 +105,9 @@ CSR laplacian_csr(const GridMetrics &g);
 std::vector<double> b1_diagonal(const GridMetrics &g, double dt);
 CSR poisson_qt(const Model &m);
 CSR pin_rows_cols(const CSR &K, int32_t pin);
+// Throws unless every point's delta support lies on cells of its own width
+// (Eq. 7) away from the domain edges: the test build_model makes
+void check_points(const GridMetrics &g, int nb, const double *xb, const double *yb);
 
 // helpers exposed for the host tests
 double roma_phi(double s);

@@ -2,7 +2,9 @@
 // N > 1 (Sec. 2, text after Eq. 11): B^N = dt Mf^{-1} sum_{k<N} S^k with
 // S = (nu/2) L B^1, and the Poisson operator K = Q^T B^N Q formed slice by
 // slice so that no full-size intermediate is ever held (the memory-bounded
-// triple product of Sec. 4).
+// triple product of Sec. 4); and for the smoothed-aggregation hierarchy
+// formed anew for a moving body (Sec. 4): P = (I - w D^-1 A) T, its
+// transpose, and the Galerkin product P^T A P.
 //
 // Every product row is a k-way merge: the rows of the right operand named by
 // the columns of one left row are walked together in column order, so the
@@ -147,6 +149,99 @@ __global__ __launch_bounds__(kBlock) void k_csr_gemv(CSRView A, const double *x,
     y[i] = base ? base[i] + alpha * s : alpha * s;
 }
 
+// Left rows longer than kMergeMax are taken in chunks of kMergeMax entries:
+// chunk k of row i is a row of its own (A' shares A's columns and values),
+// and the chunk products are summed by a second product whose left rows
+// hold a unit entry per chunk.  cnt[i] = the chunks of row i.
+__global__ __launch_bounds__(kBlock) void k_chunk_count(int n, const int32_t *ptr, int32_t *cnt) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) cnt[i] = (ptr[i + 1] - ptr[i] + kMergeMax - 1) / kMergeMax;
+}
+
+// A'.ptr (chunk starts, then nnz(A)) and the chunk-sum matrix S (row i:
+// unit entries at the chunks of row i), from the chunk offsets off (n + 1)
+__global__ __launch_bounds__(kBlock) void k_chunk_fill(int n, const int32_t *ptr, const int32_t *off,
+                                                       int32_t *cptr, int32_t *scol, double *sval) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i > n) return;
+    if (i == n) {
+        cptr[off[n]] = ptr[n];
+        return;
+    }
+    for (int k = off[i]; k < off[i + 1]; ++k) {
+        cptr[k] = ptr[i] + (k - off[i]) * kMergeMax;
+        scol[k] = k;
+        sval[k] = 1.0;
+    }
+}
+
+// Transpose: entries per column (atomic counts; the order of the fill below
+// is then fixed by sorting each row on its column)
+__global__ __launch_bounds__(kBlock) void k_col_count(int64_t nnz, const int32_t *col, int32_t *cnt) {
+    const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (p < nnz) atomicAdd(&cnt[col[p]], 1);
+}
+
+__global__ __launch_bounds__(kBlock) void k_transpose_fill(CSRView A, const int32_t *tptr, int32_t *cursor,
+                                                           int32_t *tcol, double *tval) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= A.nrows) return;
+    for (int p = A.ptr[i]; p < A.ptr[i + 1]; ++p) {
+        const int j = A.col[p];
+        const int w = tptr[j] + atomicAdd(&cursor[j], 1);
+        tcol[w] = i;
+        tval[w] = A.val[p];
+    }
+}
+
+// each row's entries sorted on their (distinct) columns
+__global__ __launch_bounds__(kBlock) void k_sort_rows(int n, const int32_t *ptr, int32_t *col, double *val) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const int p0 = ptr[i], p1 = ptr[i + 1];
+    for (int a = p0 + 1; a < p1; ++a) {
+        const int kc = col[a];
+        const double kv = val[a];
+        int b = a - 1;
+        while (b >= p0 && col[b] > kc) {
+            col[b + 1] = col[b];
+            val[b + 1] = val[b];
+            --b;
+        }
+        col[b + 1] = kc;
+        val[b + 1] = kv;
+    }
+}
+
+// T of the aggregation as CSR: row i holds a unit entry at aggregate agg[i]
+__global__ __launch_bounds__(kBlock) void k_tentative(int n, const int32_t *agg, int32_t *ptr, int32_t *col,
+                                                      double *val) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i > n) return;
+    ptr[i] = i;
+    if (i < n) {
+        col[i] = agg[i];
+        val[i] = 1.0;
+    }
+}
+
+// P = T - w D^{-1} (A T) in place on the pattern of A T (which holds
+// agg[i] in row i, from the diagonal of A); *err = 1 for a non-positive
+// diagonal
+__global__ __launch_bounds__(kBlock) void k_smooth_prolongator(int n, const int32_t *ptr, const int32_t *col,
+                                                               double *val, const int32_t *agg, const double *diag,
+                                                               double w, int *err) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= n) return;
+    const double d = diag[i];
+    if (!(d > 0)) *err = 1;
+    const double dinv = 1.0 / d;
+    for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+        const double t = col[p] == agg[i] ? 1.0 : 0.0;
+        val[p] = t - w * (dinv * val[p]);
+    }
+}
+
 int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 }  // namespace
@@ -170,6 +265,37 @@ void launch_diag_sum_count(hipStream_t s, int n, CSRView X, CSRView Y, int32_t *
 void launch_diag_sum_fill(hipStream_t s, int n, const double *d, CSRView X, CSRView Y, const int64_t *out_ptr,
                           int32_t *out_col, double *out_val) {
     if (n > 0) LAUNCHS(k_diag_sum_fill, blocks_for(n), n, d, X, Y, out_ptr, out_col, out_val);
+}
+
+void launch_chunk_count(hipStream_t s, int n, const int32_t *ptr, int32_t *cnt) {
+    if (n > 0) LAUNCHS(k_chunk_count, blocks_for(n), n, ptr, cnt);
+}
+
+void launch_chunk_fill(hipStream_t s, int n, const int32_t *ptr, const int32_t *off, int32_t *cptr, int32_t *scol,
+                       double *sval) {
+    LAUNCHS(k_chunk_fill, blocks_for(n + 1), n, ptr, off, cptr, scol, sval);
+}
+
+void launch_col_count(hipStream_t s, int64_t nnz, const int32_t *col, int32_t *cnt) {
+    if (nnz > 0) LAUNCHS(k_col_count, (int)((nnz + kBlock - 1) / kBlock), nnz, col, cnt);
+}
+
+void launch_transpose_fill(hipStream_t s, CSRView A, const int32_t *tptr, int32_t *cursor, int32_t *tcol,
+                           double *tval) {
+    if (A.nrows > 0) LAUNCHS(k_transpose_fill, blocks_for(A.nrows), A, tptr, cursor, tcol, tval);
+}
+
+void launch_sort_rows(hipStream_t s, int n, const int32_t *ptr, int32_t *col, double *val) {
+    if (n > 0) LAUNCHS(k_sort_rows, blocks_for(n), n, ptr, col, val);
+}
+
+void launch_tentative(hipStream_t s, int n, const int32_t *agg, int32_t *ptr, int32_t *col, double *val) {
+    LAUNCHS(k_tentative, blocks_for(n + 1), n, agg, ptr, col, val);
+}
+
+void launch_smooth_prolongator(hipStream_t s, int n, const int32_t *ptr, const int32_t *col, double *val,
+                               const int32_t *agg, const double *diag, double w, int *err) {
+    if (n > 0) LAUNCHS(k_smooth_prolongator, blocks_for(n), n, ptr, col, val, agg, diag, w, err);
 }
 
 void launch_csr_gemv(hipStream_t s, CSRView A, const double *x, double alpha, const double *base, double *y) {

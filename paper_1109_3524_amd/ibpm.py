@@ -39,6 +39,7 @@ EXPORTED = (
     "ibpm_nn_set_weights", "ibpm_nn_layer", "ibpm_nn_apply", "ibpm_nn_train",
     "ibpm_nn_loss_grad", "ibpm_harvest", "ibpm_plan_hierarchy", "ibpm_iteration_launches",
     "ibpm_nn_adam_step", "ibpm_solve_velocity_static", "ibpm_get_poisson_matrix", "ibpm_bn_info",
+    "ibpm_move_body", "ibpm_moving_info",
 )
 
 NN_PARAMS = 39168                     # IBPM_NN_PARAMS
@@ -78,6 +79,8 @@ class Params(ctypes.Structure):
         ("bc_u", ctypes.c_double * 4), ("bc_v", ctypes.c_double * 4),
         ("fcg_stall_fall", ctypes.c_double),
         ("body_ramp", ctypes.c_double),
+        ("moving_body", ctypes.c_int32),
+        ("amg_rebuild_every", ctypes.c_int32),
     ]
 
 
@@ -143,6 +146,8 @@ def load():
         "ibpm_get_poisson_matrix": [P, ctypes.POINTER(i64), P, P, P],
         "ibpm_bn_info": [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64),
                          ctypes.POINTER(i64)],
+        "ibpm_move_body": [P, D, D, D, D],
+        "ibpm_moving_info": [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)],
         "ibpm_nn_init": [P, ctypes.c_uint64],
         "ibpm_nn_get_weights": [P, P, i64],
         "ibpm_nn_set_weights": [P, P, i64],
@@ -179,7 +184,7 @@ def params_from_workload(wl: W.Workload, **over) -> dict:
              amg_post=wl.amg_post, amg_coarse_max=wl.amg_coarse_max,
              amg_max_levels=wl.amg_max_levels, inner_rtol=0.0, learned_every=1, fcg_depth=0, use_graphs=1,
              fuse_transfers=1, pin_cell=wl.pin_cell, bc_kind=tuple(wl.bc_kind),
-             fcg_stall_fall=0.0, body_ramp=wl.body_ramp)
+             fcg_stall_fall=0.0, body_ramp=wl.body_ramp, moving_body=0, amg_rebuild_every=0)
     p["bc_u"], p["bc_v"] = wl.wall_velocities()
     p.update(over)
     return p
@@ -437,6 +442,22 @@ class Context:
                                               col.ctypes.data_as(ctypes.c_void_p),
                                               val.ctypes.data_as(ctypes.c_void_p)))
         return sp.csr_matrix((val[:nnz.value], col[:nnz.value], ptr), shape=(n, n))
+
+    def move_body(self, xb, yb, ubx, uby):
+        """Move the body's points to (xb, yb) with velocities (ubx, uby) (host
+        arrays of nb): E and K are formed anew on the device."""
+        arrs = [np.ascontiguousarray(np.asarray(a, dtype=np.float64)) for a in (xb, yb, ubx, uby)]
+        for a in arrs:
+            if a.shape != (self.nb,):
+                raise ValueError(f"point arrays must have shape ({self.nb},)")
+        self._check(load().ibpm_move_body(self._h, *[_dptr(a) for a in arrs]))
+
+    def moving_info(self):
+        """Moves made, hierarchies formed anew, and the cell box E reaches."""
+        mv, rf = ctypes.c_int64(), ctypes.c_int64()
+        box = (ctypes.c_int32 * 4)()
+        self._check(load().ibpm_moving_info(self._h, ctypes.byref(mv), ctypes.byref(rf), box))
+        return {"moves": mv.value, "refreshes": rf.value, "box": tuple(int(b) for b in box)}
 
     def bn_info(self):
         """Stored entries of K and of B^N, and the device memory of the sliced

@@ -71,6 +71,11 @@ def _params(wl, **over):
     (dict(bc_kind=(0, 1, 1, 0)), "right side only"),
     (dict(bc_kind=(0, 0, 0, 0), bc_u=(1.0, 0.5, 1.0, 1.0)), "zero net flux"),
     (dict(bc_kind=(0, 1, 0, 0), bc_u=(1.0, 1.0, float("nan"), 1.0)), "finite"),
+    (dict(moving_body=2), "moving_body must be 0 or 1"),
+    (dict(moving_body=1, bn_order=3), "moving body supports B^1"),
+    (dict(moving_body=1, poisson_solver=2), "moving body supports B^1"),
+    (dict(moving_body=1, poisson_solver=6), "moving body supports B^1"),
+    (dict(moving_body=1, amg_rebuild_every=-1), "amg_rebuild_every"),
     (dict(pin_cell=-1), "pin_cell"),
     (dict(pin_cell=48 * 48), "pin_cell"),
 ])
