@@ -346,7 +346,10 @@ int ibpm_plan_hierarchy(const ibpm_params *p, int32_t cap, int32_t *levels, int6
                                              one pass (where the iteration folds them together) */
 #define IBPM_KERNEL_L1_JACOBI     11  /* damped Jacobi sweep with the stored (CSR) operator of
                                          AMG level 1 */
-#define IBPM_NUM_KERNELS          12
+#define IBPM_KERNEL_COPY_LEVEL0   12  /* y = x over n_lambda doubles (one finest-level vector each
+                                         way): the bandwidth a streaming kernel of the level-0
+                                         vectors' size reaches */
+#define IBPM_NUM_KERNELS          13
 
 /* Launches per PCG iteration that the FP64 AMG-PCG solve of this context
  * makes of each kernel ibpm_time_kernel can time: counts[k] for kernel id

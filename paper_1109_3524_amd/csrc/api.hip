@@ -2865,7 +2865,8 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, int64_t min_foot
                      double *bytes) {
     return guarded(c, [&] {
         if (reps < 1 || !avg_ms || min_footprint < 0) throw InvalidArg("bad arguments");
-        if (c->stored0 && kernel != IBPM_KERNEL_A_PCG_SPMV && kernel != IBPM_KERNEL_STREAM_COPY)
+        if (c->stored0 && kernel != IBPM_KERNEL_A_PCG_SPMV && kernel != IBPM_KERNEL_STREAM_COPY &&
+            kernel != IBPM_KERNEL_COPY_LEVEL0)
             throw InvalidArg("the level-0 kernels time the matrix-free operator of B^1 only");
         const bool needs_amg = kernel == IBPM_KERNEL_K0_JACOBI || kernel == IBPM_KERNEL_K0_RESIDUAL ||
                                kernel == IBPM_KERNEL_RESTRICT0 || kernel == IBPM_KERNEL_PROLONG0 ||
@@ -3074,6 +3075,13 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, int64_t min_foot
             const int x = slot(c->copy_x, nc), y = slot(c->copy_y, nc);
             launch = [=, &at](int k) { launch_stream_copy(s, nc, at(x, k), at(y, k)); };
             by = 16.0 * nc;
+            break;
+        }
+        case IBPM_KERNEL_COPY_LEVEL0: {
+            const size_t nc = (size_t)(n & ~1);
+            const int x = slot(P.r, n), y = slot(P.z, n);
+            launch = [=, &at](int k) { launch_stream_copy(s, nc, at(x, k), at(y, k)); };
+            by = 16.0 * (double)nc;
             break;
         }
         default:

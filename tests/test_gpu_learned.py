@@ -431,3 +431,47 @@ def test_trained_network_gain_on_held_out_flow():
     du = _rel(o.B1 * (o.Q @ _n(x)) / R, o.B1 * (o.Q @ _n(ref)) / R)
     print(f"  projection difference to AMG-PCG: {du:.2e}", flush=True)
     assert du < 1e-6
+
+
+@pytest.mark.xfail(reason="the trained stage does not bring the solve below plain AMG-PCG in time: a "
+                          "network application costs about as much as an AMG-PCG iteration and the "
+                          "flexible recurrence needs more iterations than CG", strict=False)
+def test_learned_stage_end_to_end_against_plain():
+    """End to end: the time of one 512^2 Poisson solve (step 6 of the Re 40
+    flow, from the previous lambda, 1e-8) with the trained stage in FCG(m)
+    against plain AMG-PCG, over the stage's schedule (every k-th application)
+    and the depth m of the flexible recurrence; the best setting is gated
+    against plain."""
+    from paper_1109_3524_amd.train_learned import poisson_rhs
+    w = np.load(WEIGHTS)
+    wl = W.cylinder_512()
+    ctx = ibpm.Context(wl, poisson_solver=1)
+    q, conv, lam = ctx.init_state()
+    ctx.step(q, conv, lam, 6)
+    rhs = poisson_rhs(ctx, q, conv, lam)
+    lam0 = lam.clone()
+
+    def timed(c):
+        x = lam0.clone()
+        c.solve_poisson(rhs, x)           # records the graphs
+        x = lam0.clone()
+        st = c.solve_poisson(rhs, x)
+        assert st["relres"] <= 1e-8
+        return st
+
+    plain = timed(ctx)
+    ctx.close()
+    rows = []
+    for every in (1, 2, 4):
+        for depth in (1, 4, 8):
+            c = ibpm.Context(wl, poisson_solver=3, learned_every=every, fcg_depth=depth)
+            c.nn_set_weights(w)
+            st = timed(c)
+            c.close()
+            rows.append((st["ms"], every, depth, st["iters"], st["fallbacks"]))
+            print(f"  learned every {every} depth {depth}: {st['iters']} iterations, {st['ms']:.2f} ms, "
+                  f"fallbacks {st['fallbacks']}", flush=True)
+    best = min(rows)
+    print(f"  plain AMG-PCG {plain['iters']} iterations, {plain['ms']:.2f} ms; best learned {best[0]:.2f} ms "
+          f"(every {best[1]}, depth {best[2]})", flush=True)
+    assert best[0] < plain["ms"]
