@@ -1566,9 +1566,11 @@ __global__ __launch_bounds__(kBlock) void k_csrv_prolong_jacobi(CSRT<T> A, CSRT<
 // block takes rpb consecutive rows, streams their entries -- all threads of
 // the block over one contiguous range of the value and column arrays, so
 // every load is coalesced -- multiplies each by the gathered operand into
-// LDS, and then each row's thread sums its products in column order.  rpb
-// is chosen on the host so that a block's entries (of every matrix the
-// kernel walks) fit in kStreamCap.
+// LDS, and then sums each row with L = kBlock / rpb lanes (at most 64): lane
+// k adds the row's products k, k + L, ... and the lanes are combined by a
+// butterfly, so every thread of the block takes part whatever the row
+// length.  rpb is a power of two chosen on the host so that a block's
+// entries (of every matrix the kernel walks) fit in kStreamCap.
 
 template <class T, class XV>
 __device__ __forceinline__ void stream_fill(const CSRT<T> &A, int r0, int r1, T *lds, XV xv) {
@@ -1576,11 +1578,30 @@ __device__ __forceinline__ void stream_fill(const CSRT<T> &A, int r0, int r1, T 
     for (int k = base + (int)threadIdx.x; k < e; k += kBlock) lds[k - base] = A.val[k] * xv(A.col[k]);
 }
 
+// lanes per row and this thread's row and lane within it
+struct StreamLane {
+    int L, row, sub;
+    bool live;
+};
+
+__device__ __forceinline__ StreamLane stream_lane(int r0, int r1, int rpb) {
+    StreamLane sl;
+    sl.L = min(64, max(1, kBlock / rpb));
+    sl.row = r0 + (int)threadIdx.x / sl.L;
+    sl.sub = (int)threadIdx.x & (sl.L - 1);
+    sl.live = sl.row < r1;
+    return sl;
+}
+
+// the sum of a row's products (every lane of the block calls this)
 template <class T>
-__device__ __forceinline__ T stream_row(const CSRT<T> &A, int row, int base, const T *lds) {
+__device__ __forceinline__ T stream_row(const CSRT<T> &A, const StreamLane &sl, int base, const T *lds) {
     T s = T(0);
-    const int e = A.ptr[row + 1];
-    for (int p = A.ptr[row]; p < e; ++p) s += lds[p - base];
+    if (sl.live) {
+        const int e = A.ptr[sl.row + 1];
+        for (int p = A.ptr[sl.row] + sl.sub; p < e; p += sl.L) s += lds[p - base];
+    }
+    for (int o = sl.L >> 1; o > 0; o >>= 1) s += __shfl_xor(s, o, sl.L);
     return s;
 }
 
@@ -1595,9 +1616,9 @@ __global__ __launch_bounds__(kBlock) void k_csrs_jacobi(CSRT<T> A, int rpb, cons
     const int r1 = min(r0 + rpb, A.nrows);
     stream_fill(A, r0, r1, lds, [&](int c) { return xin[c]; });
     __syncthreads();
-    const int base = A.ptr[r0];
-    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock)
-        xout[row] = xin[row] + wdinv[row] * (b[row] - stream_row(A, row, base, lds));
+    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const T ax = stream_row(A, sl, A.ptr[r0], lds);
+    if (sl.live && sl.sub == 0) xout[sl.row] = xin[sl.row] + wdinv[sl.row] * (b[sl.row] - ax);
 }
 
 template <class T>
@@ -1611,8 +1632,9 @@ __global__ __launch_bounds__(kBlock) void k_csrs_residual(CSRT<T> A, int rpb, co
     const int r1 = min(r0 + rpb, A.nrows);
     stream_fill(A, r0, r1, lds, [&](int c) { return x[c]; });
     __syncthreads();
-    const int base = A.ptr[r0];
-    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock) r[row] = b[row] - stream_row(A, row, base, lds);
+    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const T ax = stream_row(A, sl, A.ptr[r0], lds);
+    if (sl.live && sl.sub == 0) r[sl.row] = b[sl.row] - ax;
 }
 
 template <class T>
@@ -1625,11 +1647,9 @@ __global__ __launch_bounds__(kBlock) void k_csrs_spmv(CSRT<T> A, int rpb, const 
     const int r1 = min(r0 + rpb, A.nrows);
     stream_fill(A, r0, r1, lds, [&](int c) { return x[c]; });
     __syncthreads();
-    const int base = A.ptr[r0];
-    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock) {
-        const T v = stream_row(A, row, base, lds);
-        y[row] = add ? y[row] + v : v;
-    }
+    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const T v = stream_row(A, sl, A.ptr[r0], lds);
+    if (sl.live && sl.sub == 0) y[sl.row] = add ? y[sl.row] + v : v;
 }
 
 // the first two damped-Jacobi sweeps from zero: x = y + W (b - A y), y = W b
@@ -1644,10 +1664,11 @@ __global__ __launch_bounds__(kBlock) void k_csrs_presmooth2(CSRT<T> A, int rpb, 
     const int r1 = min(r0 + rpb, A.nrows);
     stream_fill(A, r0, r1, lds, [&](int c) { return wdinv[c] * b[c]; });
     __syncthreads();
-    const int base = A.ptr[r0];
-    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock) {
-        const T w = wdinv[row], bi = b[row];
-        x[row] = w * bi + w * (bi - stream_row(A, row, base, lds));
+    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const T ay = stream_row(A, sl, A.ptr[r0], lds);
+    if (sl.live && sl.sub == 0) {
+        const T w = wdinv[sl.row], bi = b[sl.row];
+        x[sl.row] = w * bi + w * (bi - ay);
     }
 }
 
@@ -1665,9 +1686,10 @@ __global__ __launch_bounds__(kBlock) void k_csrs_restrict(CSRT<T> R, CSRT<T> RA,
     stream_fill(R, r0, r1, lds, [&](int c) { return b[c]; });
     stream_fill(RA, r0, r1, lds + nr, [&](int c) { return x[c]; });
     __syncthreads();
-    const int br = R.ptr[r0], ba = RA.ptr[r0];
-    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock)
-        bc[row] = stream_row(R, row, br, lds) - stream_row(RA, row, ba, lds + nr);
+    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const T rb = stream_row(R, sl, R.ptr[r0], lds);
+    const T rax = stream_row(RA, sl, RA.ptr[r0], lds + nr);
+    if (sl.live && sl.sub == 0) bc[sl.row] = rb - rax;
 }
 
 // x_out = x + P e + W (b - A x - (A P) e): entries of A, A P and P in turn
@@ -1689,10 +1711,11 @@ __global__ __launch_bounds__(kBlock) void k_csrs_prolong_jacobi(CSRT<T> A, CSRT<
     stream_fill(AP, r0, r1, lds + na, [&](int c) { return e[c]; });
     stream_fill(P, r0, r1, lds + na + nq, [&](int c) { return e[c]; });
     __syncthreads();
-    const int ba = A.ptr[r0], bq = AP.ptr[r0], bp = P.ptr[r0];
-    for (int row = r0 + (int)threadIdx.x; row < r1; row += kBlock) {
-        const T sa = stream_row(A, row, ba, lds), sq = stream_row(AP, row, bq, lds + na);
-        const T sp = stream_row(P, row, bp, lds + na + nq);
+    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const T sa = stream_row(A, sl, A.ptr[r0], lds), sq = stream_row(AP, sl, AP.ptr[r0], lds + na);
+    const T sp = stream_row(P, sl, P.ptr[r0], lds + na + nq);
+    if (sl.live && sl.sub == 0) {
+        const int row = sl.row;
         xout[row] = (x[row] + sp) + wdinv[row] * ((b[row] - sa) - sq);
     }
 }
