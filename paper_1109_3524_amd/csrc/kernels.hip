@@ -265,8 +265,8 @@ __device__ __forceinline__ bool k0_coupled(const K0T<T> &K, int i, int j) {
 // Interior tile of R rows (every row has a north neighbour): all operand
 // loads of the R rows are issued before the arithmetic.  BOX: the tile
 // meets the coupling box, and its coupled cells are left to the band.
-template <int R, bool BOX, class T, class XV, class ACT>
-__device__ __forceinline__ void k0_tile(const K0T<T> &K, int i, int j0, XV xv, ACT act) {
+template <int R, bool BOX, class T, class XV, class PF, class ACT>
+__device__ __forceinline__ void k0_tile(const K0T<T> &K, int i, int j0, XV xv, PF pf, ACT act) {
     const GridT<T> &g = K.g;
     const int nx = g.nx;
     const T dt = K.dt;
@@ -304,17 +304,19 @@ __device__ __forceinline__ void k0_tile(const K0T<T> &K, int i, int j0, XV xv, A
             if (row + 1 != K.pin) y -= be * xer[r];
             if (row + nx != K.pin) y -= bn * xcol[r + 2];
         }
-        if (!BOX || !skip[r]) act(row, y, diag, xc);
+        if (!BOX || !skip[r]) act(row, y, diag, xc, pf(row));
     }
 }
 
 // Interior tile without coupled cells, east / west operands through LDS:
 // every lane forms xv once at each of the R + 2 rows of its column, the R
 // centre rows go to LDS, the two edge lanes form the halo columns, and the
-// east / west values are read back after one barrier.  Every lane of the
-// block calls this (lanes past the last column only take the barrier).
-template <int R, class T, class XV, class ACT>
-__device__ __forceinline__ void k0_tile_lds(const K0T<T> &K, int i, int j0, XV xv, ACT act) {
+// east / west values are read back after one barrier.  The operands the
+// per-row action reads (pf) are loaded before the barrier too, so that a
+// tile waits for memory once.  Every lane of the block calls this (lanes
+// past the last column only take the barrier).
+template <int R, class T, class XV, class PF, class ACT>
+__device__ __forceinline__ void k0_tile_lds(const K0T<T> &K, int i, int j0, XV xv, PF pf, ACT act) {
     __shared__ T sh[R][kBlock + 2];
     const GridT<T> &g = K.g;
     const int nx = g.nx;
@@ -339,6 +341,10 @@ __device__ __forceinline__ void k0_tile_lds(const K0T<T> &K, int i, int j0, XV x
     }
 #pragma unroll
     for (int r = 0; r <= R; ++r) iyr[r] = g.iDy[j0 + r];
+    using PV = decltype(pf(0));
+    PV pv[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) pv[r] = pf(row0 + r * nx);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         sh[r][tx + 1] = xcol[r + 1];
@@ -366,14 +372,15 @@ __device__ __forceinline__ void k0_tile_lds(const K0T<T> &K, int i, int j0, XV x
             if (row + 1 != K.pin) y -= be * xe;
             if (row + nx != K.pin) y -= bn * xcol[r + 2];
         }
-        act(row, y, diag, xc);
+        act(row, y, diag, xc, pv[r]);
     }
 }
 
 // Pressure and force rows of K = Q^T B^1 Q (pinned), precision T.
-// act(row, Kx, diag, x_row) is called once per row.
-template <int R, class T, class XV, class ACT>
-__device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
+// act(row, Kx, diag, x_row, pf(row)) is called once per row; pf(row) loads
+// what the action reads of the row besides x (before the tile's barrier).
+template <int R, class T, class XV, class PF, class ACT>
+__device__ __forceinline__ void k0_walk_pf(const K0T<T> &K, XV xv, PF pf, ACT act) {
     const GridT<T> &g = K.g;
     const int nx = g.nx, ny = g.ny;
     const int band = k0_band(K);
@@ -394,12 +401,12 @@ __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
         if (j0 + R < ny && !box_tile && R >= 2) {
             // tiles of 2 or more rows (the large grids) exchange east / west
             // values through LDS; every lane of the block reaches its barrier
-            k0_tile_lds<R>(K, i, j0, xv, act);
+            k0_tile_lds<R>(K, i, j0, xv, pf, act);
         } else if (i < nx && j0 + R < ny) {
             if (box_tile)
-                k0_tile<R, true>(K, i, j0, xv, act);
+                k0_tile<R, true>(K, i, j0, xv, pf, act);
             else
-                k0_tile<R, false>(K, i, j0, xv, act);
+                k0_tile<R, false>(K, i, j0, xv, pf, act);
         } else if (i < nx && j0 < ny) {
             // top rows: one row at a time
 #pragma unroll
@@ -409,7 +416,7 @@ __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
                 if (box_tile && k0_coupled(K, i, j)) continue;
                 T diag, xc;
                 const T y = k0_cell_stencil(K, i, j, xv, diag, xc);
-                act(j * nx + i, y, diag, xc);
+                act(j * nx + i, y, diag, xc, pf(j * nx + i));
             }
         }
     } else if (b < fbk) {
@@ -418,7 +425,7 @@ __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
         const int fr = t / kForceLanes, lane = t % kForceLanes;
         const bool live = fr < 2 * K.nb;
         const T y = band_row_sum<kKfW>(live, fr, lane, K.kf_ell, K.kfe_col, K.kfe_val, K.kf, fr, 0, xv);
-        if (live && lane == 0) act(g.n_cell + fr, y, K.kf_diag[fr], xv(g.n_cell + fr));
+        if (live && lane == 0) act(g.n_cell + fr, y, K.kf_diag[fr], xv(g.n_cell + fr), pf(g.n_cell + fr));
     } else {
         // coupled cells: the stencil (every lane forms it, so its loads go
         // out with the coupling slots) plus the force coupling
@@ -433,8 +440,23 @@ __device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
         const int rb = (j - K.cb_j0) * (K.cb_i1 - K.cb_i0 + 1) + (i - K.cb_i0);
         const T yc = band_row_sum<kCcW>(live, q, lane, K.cc_ell, K.cce_col, K.cce_val, K.cf, rb,
                                         g.n_cell, xv);
-        if (live && lane == 0) act(row, row != K.pin ? ys + yc : ys, diag, xc);
+        if (live && lane == 0) act(row, row != K.pin ? ys + yc : ys, diag, xc, pf(row));
     }
+}
+
+struct NoPrefetch {};
+
+// what the update-and-sweep pass reads of its own row
+template <class T>
+struct UpdRow {
+    T bi, w, x, p;
+};
+
+// the walk for actions that read nothing more of the row
+template <int R, class T, class XV, class ACT>
+__device__ __forceinline__ void k0_walk(const K0T<T> &K, XV xv, ACT act) {
+    k0_walk_pf<R>(K, xv, [](int) { return NoPrefetch{}; },
+                  [&](int row, T y, T d, T xc, NoPrefetch) { act(row, y, d, xc); });
 }
 
 // 1-D grid: the bands, then one block per 256 columns x R rows
@@ -933,9 +955,8 @@ __global__ __launch_bounds__(kBlock) void k_k0_prolong_mf(K0T<T> K, const int *_
                                                           const T *__restrict__ x1, T w,
                                                           T *__restrict__ x, const SolveStatus *st) {
     if (st->done) return;
-    k0_walk<R>(K, [&](int c) { return x1[agg[c]]; }, [&](int row, T kt, T d, T t) {
-        x[row] += t - w * (kt / d);
-    });
+    k0_walk_pf<R>(K, [&](int c) { return x1[agg[c]]; }, [&](int row) { return x[row]; },
+                  [&](int row, T kt, T d, T t, T xr) { x[row] = xr + (t - w * (kt / d)); });
 }
 
 // wd = omega / diag(K) on level 0
@@ -984,13 +1005,22 @@ __global__ __launch_bounds__(kBlock) void k_k0_update_presmooth2(
         st->first = 0;
     }
     double v[1] = {0.0};
-    k0_walk<R>(K, [&](int c) { return wd[c] * (rin[c] - alpha * q[c]); }, [&](int row, T ky, T, T yr) {
-        const T bi = rin[row] - alpha * q[row];
-        xs[row] = yr + wd[row] * (bi - ky);
-        rout[row] = bi;
-        x[row] += alpha * p[row];
-        v[0] += (double)bi * (double)bi;
-    });
+    k0_walk_pf<R>(
+        K, [&](int c) { return wd[c] * (rin[c] - alpha * q[c]); },
+        [&](int row) {
+            UpdRow<T> u;
+            u.bi = rin[row] - alpha * q[row];
+            u.w = wd[row];
+            u.x = x[row];
+            u.p = p[row];
+            return u;
+        },
+        [&](int row, T ky, T, T yr, UpdRow<T> u) {
+            xs[row] = yr + u.w * (u.bi - ky);
+            rout[row] = u.bi;
+            x[row] = u.x + alpha * u.p;
+            v[0] += (double)u.bi * (double)u.bi;
+        });
     write_parts2<1>(v, parts);
 }
 
@@ -1057,9 +1087,8 @@ template <int R, class T>
 __global__ __launch_bounds__(kBlock) void k_k0_jacobi(K0T<T> K, T omega, const T *__restrict__ b, const T *__restrict__ xin,
                                                       T *__restrict__ xout, const SolveStatus *st) {
     if (st->done) return;
-    k0_walk<R>(K, [&](int c) { return xin[c]; }, [&](int row, T ax, T d, T xr) {
-        xout[row] = xr + omega / d * (b[row] - ax);
-    });
+    k0_walk_pf<R>(K, [&](int c) { return xin[c]; }, [&](int row) { return b[row]; },
+                  [&](int row, T ax, T d, T xr, T br) { xout[row] = xr + omega / d * (br - ax); });
 }
 
 // last post-smoothing sweep: also forms r . z for the PCG (b is the PCG residual)
@@ -1069,12 +1098,12 @@ __global__ __launch_bounds__(kBlock) void k_k0_jacobi_rz(K0T<T> K, T omega, cons
                                                          double *parts) {
     if (st->done) return;
     double v[1] = {0.0};
-    k0_walk<R>(K, [&](int c) { return xin[c]; }, [&](int row, T ax, T d, T xr) {
-        T bi = b[row];
-        T z = xr + omega / d * (bi - ax);
-        xout[row] = z;
-        v[0] += (double)bi * (double)z;
-    });
+    k0_walk_pf<R>(K, [&](int c) { return xin[c]; }, [&](int row) { return b[row]; },
+                  [&](int row, T ax, T d, T xr, T bi) {
+                      T z = xr + omega / d * (bi - ax);
+                      xout[row] = z;
+                      v[0] += (double)bi * (double)z;
+                  });
     write_parts2<1>(v, parts);
 }
 
@@ -1082,7 +1111,8 @@ template <int R, class T>
 __global__ __launch_bounds__(kBlock) void k_k0_residual(K0T<T> K, const T *__restrict__ b, const T *__restrict__ x, T *__restrict__ r,
                                                         const SolveStatus *st) {
     if (st->done) return;
-    k0_walk<R>(K, [&](int c) { return x[c]; }, [&](int row, T ax, T, T) { r[row] = b[row] - ax; });
+    k0_walk_pf<R>(K, [&](int c) { return x[c]; }, [&](int row) { return b[row]; },
+                  [&](int row, T ax, T, T, T br) { r[row] = br - ax; });
 }
 
 // mixed precision outer loop: r = b - K x in FP64, r32 = (float) r, ||r||^2, ||b||^2
