@@ -43,6 +43,7 @@ def _couette_snapshots(n, dt, bn_order, ramp, times):
     for t in times:
         k = int(round(t / dt))
         st = ctx.step(q, conv, lam, k - done)
+        print(f"    Couette {n}^2 dt {dt} B^{bn_order}: t = {t}", flush=True)
         # CG stops on its recursive residual; the true one may drift past it
         assert st["poisson_relres_max"] <= 1.2e-11 and st["vel_relres_max"] <= 1.2e-11
         done = k
@@ -94,6 +95,7 @@ def test_couette_spatial_convergence_to_the_analytic_profile():
         ctx = ibpm.Context(wl, poisson_solver=1, poisson_maxit=20000)
         q, conv, lam = ctx.init_state()
         ctx.step(q, conv, lam, wl.nsteps)
+        print(f"    Couette {n}^2 at t = 15", flush=True)
         qh = _velocity(ctx, q)
         ctx.close()
         xf, yf = wl.xf, wl.yf
@@ -131,6 +133,7 @@ def test_re40_steady_drag_on_the_paper_grid():
     for _ in range(12):
         st = ctx.step(q, conv, lam, 1000)
         cds.append(2.0 * st["fx"])
+        print(f"    t = {5 * len(cds)}: C_d {cds[-1]:.5f}", flush=True)
     ctx.close()
     print("  C_d at t = 5, 10, ..., 60: " + ", ".join(f"{c:.4f}" for c in cds), flush=True)
     assert abs(cds[-1] - cds[-2]) < 2e-3 * cds[-1]       # steady
