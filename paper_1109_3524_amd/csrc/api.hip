@@ -353,15 +353,24 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
         DevLevelT<T> &l0 = P.lev[0];
         T *a = l0.xa, *b = l0.xb;
         int k = 1;
+        // on grids whose product has more partials than a block gathers, p.q
+        // and the update's stop test come from one-block finalizes
+        const int G_pq = walk_blocks_of(K);
+        const bool fin = G_pq > kFuseMaxParts;
         if (u) {
-            launch_k0_update_presmooth2(s, K, (const T *)l0.wdinv, u->x, u->r_in, u->r_out, u->p, u->q, a, st,
-                                        u->pq_parts, c->parts3);
+            if (fin) launch_finalize_pq(s, G_pq, u->pq_parts, st);
+            const int G = launch_k0_update_presmooth2(s, K, (const T *)l0.wdinv, u->x, u->r_in, u->r_out, u->p,
+                                                      u->q, a, st, fin ? nullptr : u->pq_parts, c->parts3);
+            if (fin) launch_finalize_update(s, G, c->parts3, st, 2);
             k = 2;
         } else if (mx && mx->u) {
             if constexpr (f32) {
                 const UpdArgs<double> *v = mx->u;
-                launch_k0_update_presmooth2_mixed(s, K, (const float *)l0.wdinv, v->x, v->r_in, v->r_out, v->p,
-                                                  v->q, a, mx->r32, st, v->pq_parts, c->parts3);
+                if (fin) launch_finalize_pq(s, G_pq, v->pq_parts, st);
+                const int G = launch_k0_update_presmooth2_mixed(s, K, (const float *)l0.wdinv, v->x, v->r_in,
+                                                                v->r_out, v->p, v->q, a, mx->r32, st,
+                                                                fin ? nullptr : v->pq_parts, c->parts3);
+                if (fin) launch_finalize_update(s, G, c->parts3, st, 2);
             }
             k = 2;
         } else if (pre >= 2) {
@@ -491,8 +500,11 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
     // a residual no later kernel uses.
     const bool defer = !jacobi && c->rz_G <= kFuseMaxParts && update_blocks_of(n) <= kFuseMaxParts;
     // With a preconditioner that starts with the update, the update kernel
-    // goes too: the residual then alternates between r and fpre->r2
-    const bool fuse = defer && fpre && fpre->G_pq <= kFuseMaxParts && fpre->G_rr <= kFuseMaxParts;
+    // goes too: the residual then alternates between r and fpre->r2.  With
+    // the deferred stop test the folded pass gathers the product's partials
+    // itself; without it (large grids) one-block finalizes around the pass
+    // give it p.q and take the stop test.
+    const bool fuse = fpre && (!defer || (fpre->G_pq <= kFuseMaxParts && fpre->G_rr <= kFuseMaxParts));
     const int G_rr = fuse ? fpre->G_rr : update_blocks_of(n);
     T *rcur = r, *rnext = fuse ? fpre->r2 : nullptr;
     auto iteration = [&]() {
@@ -3036,14 +3048,16 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, int64_t min_foot
             const double *wd = l0.wdinv;
             const int x = slot(P.p[1], n), rin = slot(P.r, n), rout = slot(P.r2, n), p0 = slot(P.p[0], n),
                       q = slot(P.q, n), xs = slot(l0.xa, n);
+            // p.q from the product's partials where a block gathers them,
+            // else from the status (the solver finalizes it beforehand)
             const int G_pq = walk_blocks_of(K0);
-            if (G_pq > kFuseMaxParts) throw InvalidArg("the update is not folded into the sweeps on this grid");
-            {
+            const bool gather = G_pq <= kFuseMaxParts;
+            if (gather) {
                 std::vector<double> ones(G_pq, 1.0 / G_pq);
                 HIPCHECK(hipMemcpyAsync(c->parts2, ones.data(), G_pq * sizeof(double), hipMemcpyHostToDevice, s));
                 HIPCHECK(hipStreamSynchronize(s));
             }
-            const double *pq_parts = c->parts2;
+            const double *pq_parts = gather ? c->parts2 : nullptr;
             double *rr_parts = c->parts3;
             launch = [=, &at](int k) {
                 launch_k0_update_presmooth2(s, K0, wd, at(x, k), at(rin, k), at(rout, k), at(p0, k), at(q, k),
@@ -3142,10 +3156,10 @@ int ibpm_iteration_launches(const ibpm_ctx *cc, int32_t ncounts, int32_t *counts
         if (!c->amg || P.lev.size() < 2) throw InvalidArg("needs an AMG hierarchy of two or more levels");
         int32_t k[IBPM_NUM_KERNELS] = {};
         const int pre = c->prm.amg_pre, post = c->prm.amg_post;
-        const int G = walk_blocks_of(P.K0);
         // as pcg_drive and solve_poisson_fp64 decide: the update folds into
-        // the first two sweeps when every partial count fits one consumer
-        const bool fuse = pre >= 2 && G <= kFuseMaxParts && update_blocks_of(P.K0.n) <= kFuseMaxParts;
+        // the first two sweeps (with one-block finalizes of p.q and of the
+        // stop test around it where the partials exceed what a block gathers)
+        const bool fuse = pre >= 2;
         k[IBPM_KERNEL_K0_PCG_SPMV] = 1;
         if (fuse) {
             k[IBPM_KERNEL_UPDATE_PRESMOOTH0] = 1;

@@ -172,6 +172,7 @@ void launch_csrv_presmooth2(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv,
 
 // number of blocks (and of partials) of a level-0 stencil kernel
 int walk_blocks_of(const K0View &K);
+int walk_blocks_of(const K0T<float> &K);
 // number of blocks (and of partials) of the PCG update on n unknowns
 int update_blocks_of(int n);
 // above this many partials a sum read by every block of the consumer costs
@@ -222,6 +223,11 @@ void launch_k0_prolong_mf(hipStream_t s, const K0T<T> &K, const int *agg, const 
 template <class T>
 void launch_k0_wdinv(hipStream_t s, const K0T<T> &K, double omega, T *wd);
 // two damped-Jacobi sweeps from x = 0 in one pass: x = y + wd (b - K y), y = wd b
+// one-block sums of partials into the status: p.q (FIN_PQ), and the stop
+// test of an update (FIN_UPDATE; flag bit 0: Jacobi r.z in the second row,
+// bit 1: r.z came from the product)
+void launch_finalize_pq(hipStream_t s, int G, const double *parts, SolveStatus *st);
+void launch_finalize_update(hipStream_t s, int G, const double *parts, SolveStatus *st, int flag);
 // FP64 CG around an FP32 V-cycle: the FP64 update folded into the FP32
 // first pass (b = r_in - alpha q in FP64 to r_out, x += alpha p, FP32(b) to
 // r32, the two FP32 sweeps from zero to xs; partials of b.b), and the last
@@ -234,11 +240,14 @@ int launch_k0_update_presmooth2_mixed(hipStream_t s, const K0T<float> &K, const 
 int launch_k0_jacobi_widen_rz(hipStream_t s, const K0T<float> &K, double omega, const float *b,
                               const float *xin, double *z64, const double *r64, const SolveStatus *st,
                               double *parts);
-// the PCG update (alpha = st->rz_next / p.q, p.q summed from the product's
-// partials) and the first two pre-smoothing sweeps on level 0 in one pass:
-// b = r_in - alpha q to r_out, x += alpha p, xs = the two sweeps from zero
-// for b; partials of b.b in parts (the deferred stop test), block 0 counts
-// the iteration.  Returns the number of partials.
+// the PCG update (alpha = st->rz_next / p.q) and the first two
+// pre-smoothing sweeps on level 0 in one pass: b = r_in - alpha q to r_out,
+// x += alpha p, xs = the two sweeps from zero for b; partials of b.b in
+// parts.  With pq_parts, p.q is summed from the product's partials (at most
+// kFuseMaxParts) and block 0 counts the iteration (the stop test deferred to
+// the next product); with pq_parts null, p.q is read from the status and
+// the caller finalizes (launch_finalize_pq before, launch_finalize_update
+// after).  Returns the number of partials.
 template <class T>
 int launch_k0_update_presmooth2(hipStream_t s, const K0T<T> &K, const T *wd, T *x, const T *rin, T *rout,
                                 const T *p, const T *q, T *xs, SolveStatus *st, const double *pq_parts,
