@@ -333,6 +333,97 @@ def tiny(nx: int = 12, ny: int = 10, n_b: int = 6, radius: float = 0.25,
                     poisson_solver=SOLVER_JACOBI_PCG)
 
 
+def sphere_points(n_b: int, radius: float = 0.5, cx: float = 0.0, cy: float = 0.0, cz: float = 0.0):
+    """n_b points spread evenly over a sphere (the golden-angle spiral:
+    point k at height 1 - (2k + 1)/n_b, turned by k times the golden
+    angle)."""
+    k = np.arange(n_b, dtype=np.float64)
+    zk = 1.0 - (2.0 * k + 1.0) / n_b
+    rk = np.sqrt(np.maximum(0.0, 1.0 - zk * zk))
+    th = k * math.pi * (3.0 - math.sqrt(5.0))
+    return cx + radius * rk * np.cos(th), cy + radius * rk * np.sin(th), cz + radius * zk
+
+
+@dataclasses.dataclass
+class Workload3:
+    """A three-dimensional problem: grid faces, a body's points, and the
+    solver settings of one time step's linear algebra (Eq. 11)."""
+    name: str
+    xf: np.ndarray
+    yf: np.ndarray
+    zf: np.ndarray
+    xb: np.ndarray
+    yb: np.ndarray
+    zb: np.ndarray
+    nu: float
+    dt: float
+    vel_rtol: float = 1e-8
+    vel_maxit: int = 2000
+    poisson_solver: int = SOLVER_AMG_PCG
+    poisson_rtol: float = 1e-8
+    poisson_maxit: int = 2000
+    amg_theta: float = 0.0
+    amg_pre: int = 2
+    amg_post: int = 2
+    amg_coarse_max: int = 256
+    amg_max_levels: int = 12
+    pin_cell: int = 0
+    description: str = ""
+
+    @property
+    def nx(self) -> int:
+        return len(self.xf) - 1
+
+    @property
+    def ny(self) -> int:
+        return len(self.yf) - 1
+
+    @property
+    def nz(self) -> int:
+        return len(self.zf) - 1
+
+    @property
+    def nb(self) -> int:
+        return len(self.xb)
+
+    @property
+    def n_cell(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def n_q(self) -> int:
+        nx, ny, nz = self.nx, self.ny, self.nz
+        return (nx - 1) * ny * nz + nx * (ny - 1) * nz + nx * ny * (nz - 1)
+
+    @property
+    def n_lambda(self) -> int:
+        return self.n_cell + 3 * self.nb
+
+    def replace(self, **kw) -> "Workload3":
+        return dataclasses.replace(self, **kw)
+
+
+def sphere3d(n: int, n_b: Optional[int] = None, radius: float = 0.5, stretched: bool = False,
+             re: float = 100.0, dt: float = 0.01) -> Workload3:
+    """A sphere in the box [-1, 1]^3 on an n^3 grid: uniform cells, or (with
+    `stretched`) uniform cells of 1/8 on the central n - 2 cells per axis
+    and one stretched cell at each end.  n_b points on the sphere (default:
+    about one per h^2 of its surface), nu = 2 radius / re."""
+    if stretched:
+        h = 0.125
+        f = stretched_faces(n, 1.0, 0.5 * h * (n - 2), h)
+    else:
+        f = uniform_faces(n, -1.0, 1.0)
+        h = 2.0 / n
+    if n_b is None:
+        n_b = max(4, int(round(4.0 * math.pi * radius * radius / (h * h))))
+    xb, yb, zb = sphere_points(n_b, radius)
+    return Workload3(name=f"sphere_re{int(re)}_{'stretched' if stretched else 'uniform'}_{n}^3", xf=f, yf=f.copy(),
+                     zf=f.copy(), xb=xb, yb=yb, zb=zb, nu=2.0 * radius / re, dt=dt,
+                     description=f"sphere of radius {radius} in [-1,1]^3, {n}^3 cells, {n_b} points, Re {re:g}, "
+                                 f"dt {dt}")
+
+
 def random_vector(n: int, seed: int) -> np.ndarray:
     """Seeded standard-normal FP64 vector."""
     return np.random.default_rng(seed).standard_normal(n)
