@@ -266,6 +266,63 @@ int ibpm_move_body(ibpm_ctx *ctx, const double *xb, const double *yb, const doub
  * fixed-body context. */
 int ibpm_moving_info(const ibpm_ctx *ctx, int64_t *moves, int64_t *refreshes, int32_t *box);
 
+/* ------------------------------------------------------------------------
+ * The three-dimensional extension (Sec. 7 names the 7-point pressure stencil
+ * in three dimensions as the method's next step): Eqs. 6-11 carried over
+ * axis by axis on an nx x ny x nz staggered grid.  Unknowns x fastest, then
+ * y, then z: q = [u faces (x_1..x_{nx-1}); v faces; w faces] as fluxes
+ * (velocity times face area), lambda = [nx ny nz cell pressures; 3 nb forces
+ * (x, y, z components)].  A context built here answers the calls below and
+ * ibpm_solve_poisson, ibpm_apply_K, ibpm_get_poisson_matrix,
+ * ibpm_hierarchy_info, ibpm_sizes, ibpm_destroy and ibpm_last_error; the
+ * two-dimensional time-step calls return IBPM_EINVAL on it.  The momentum
+ * right-hand side (convection, wall values) is the caller's: the library
+ * carries the linear algebra of a step, Eq. 11.
+ * ------------------------------------------------------------------------ */
+typedef struct ibpm3d_params {
+    int32_t nx, ny, nz;          /* cells per axis, >= 2 */
+    const double *xf, *yf, *zf;  /* host face coordinates (n + 1 each), strictly increasing */
+    int32_t nb;                  /* Lagrangian points (>= 0) */
+    const double *xb, *yb, *zb;  /* host point coordinates; every delta support must lie on
+                                    uniform cells inside the grid, else IBPM_EINVAL */
+    double nu, dt;               /* viscosity and time step (> 0) */
+    double vel_rtol;             /* velocity solve: Jacobi-PCG relative residual */
+    int32_t vel_maxit;
+    int32_t poisson_solver;      /* IBPM_SOLVER_JACOBI_PCG or IBPM_SOLVER_AMG_PCG */
+    double poisson_rtol;
+    int32_t poisson_maxit;
+    double amg_theta;            /* smoothed aggregation as in two dimensions (Sec. 3) */
+    int32_t amg_pre, amg_post, amg_coarse_max, amg_max_levels;
+    int32_t pin_cell;            /* pressure value pinned: cell (k ny + j) nx + i */
+    int32_t use_graphs;          /* 1: CG iterations replayed as HIP graphs */
+} ibpm3d_params;
+
+/* Operators on the host (A, Q^T = [-D; E], B^1 = dt R M^-1, K = Q^T B^1 Q
+ * pinned, the SA hierarchy of K), then stored on the device as CSR; the
+ * context as ibpm_build_operators. */
+int ibpm3d_build_operators(const ibpm3d_params *p, void *stream, ibpm_ctx **out);
+
+/* q: A q = rhs by Jacobi-PCG from q (Eq. 11a); device n_q vectors. */
+int ibpm3d_solve_velocity(ibpm_ctx *ctx, const double *rhs, double *q, ibpm_solve_stats *stats);
+
+/* y = A x, device n_q vectors, distinct. */
+int ibpm3d_apply_A(ibpm_ctx *ctx, const double *x, double *y);
+
+/* rhs = Q^T q* - r2 with the pinned entry cleared (Eq. 11b); q* device n_q,
+ * r2 and rhs device n_lambda, distinct. */
+int ibpm3d_poisson_rhs(ibpm_ctx *ctx, const double *qstar, const double *r2, double *rhs);
+
+/* qout = q* - B^1 Q lambda (Eq. 11c); device vectors, qout may be q*. */
+int ibpm3d_project(ibpm_ctx *ctx, const double *qstar, const double *lambda, double *qout);
+
+/* The linear algebra of one time step, Eq. 11: q* from A q* = r1 (starting
+ * from q), lambda from K lambda = Q^T q* - r2 (starting from lambda), then
+ * q = q* - B^1 Q lambda written over q.  Device vectors (r1, q: n_q; r2,
+ * lambda: n_lambda).  Stats of both solves (each may be NULL); returns the
+ * first solve's failure code, if any.  Synchronises the stream. */
+int ibpm3d_linear_step(ibpm_ctx *ctx, const double *r1, const double *r2, double *q, double *lambda,
+                       ibpm_solve_stats *vel_stats, ibpm_solve_stats *poisson_stats);
+
 /* y = K x (pinned Q^T B^N Q), x and y device n_lambda, distinct. */
 int ibpm_apply_K(ibpm_ctx *ctx, const double *x, double *y);
 

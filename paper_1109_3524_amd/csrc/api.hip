@@ -145,6 +145,12 @@ struct ibpm_ctx {
     int64_t force_cap = 0, box_cap = 0, box_rows_cap = 0;
     int box[4] = {0, -1, 0, -1};                    // cells whose faces E reaches (i0, i1, j0, j1)
     double *K0diag = nullptr;
+    // the three-dimensional extension: stored A (with its diagonal), Q,
+    // Q^T and B^1 (as a diagonal CSR) for the linear algebra of a step
+    bool three_d = false;
+    DevCSR A3{}, Q3{}, QT3{}, B3{};
+    CsrOpView A3op{};
+    int64_t n_q3 = 0;
     std::vector<int32_t *> agg_d;                   // aggregates of the levels formed on the device
     std::vector<int64_t> level_nnz;                 // entries of each level's operator
     int64_t refreshes = 0;
@@ -279,6 +285,11 @@ namespace {
 int fail(ibpm_ctx *c, int code, const std::string &msg) {
     if (c) c->err = msg;
     return code;
+}
+
+// the entry points of the two-dimensional time step refuse a 3-D context
+void need2d(const ibpm_ctx *c) {
+    if (c->three_d) throw InvalidArg("a two-dimensional entry point called on a three-dimensional context");
 }
 
 template <class F>
@@ -2344,6 +2355,166 @@ __global__ void k_clear_words(double *w, int n) {
     if (i < n) w[i] = 0.0;
 }
 
+// the solve vectors (velocity n_q, Poisson n_lambda), statuses, partial
+// sums and the pinned status copy
+void alloc_work(ibpm_ctx *c, int nq, int nl) {
+    c->vr = c->dalloc<double>(nq);
+    c->vz = c->dalloc<double>(nq);
+    c->vp[0] = c->dalloc<double>(nq);
+    c->vp[1] = c->dalloc<double>(nq);
+    c->vq = c->dalloc<double>(nq);
+    for (double *v : {c->vp[0], c->vp[1]}) HIPCHECK(hipMemsetAsync(v, 0, nq * sizeof(double), c->stream));
+    alloc_pcg(c, c->p64, nl);
+    c->r1 = c->dalloc<double>(nq);
+    c->rhs2 = c->dalloc<double>(nl);
+    SolveStatus *sts = c->dalloc<SolveStatus>(5);
+    HIPCHECK(hipMemsetAsync(sts, 0, 5 * sizeof(SolveStatus), c->stream));
+    c->st_vel = sts;
+    c->st_poi = sts + 1;
+    c->st_misc = sts + 2;
+    c->st_bench = sts + 3;
+    c->st_out = sts + 4;
+    // partial sums of up to kFcgMax components per block (FCG multi-dot)
+    c->parts = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
+    c->parts2 = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
+    // the update writes two rows of partials (r . r and, for Jacobi, r . z)
+    c->parts3 = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
+    HIPCHECK(hipHostMalloc((void **)&c->host_st, sizeof(SolveStatus), hipHostMallocDefault));
+}
+
+// a device CSR and its diagonal as a stored operator for the Krylov kernels
+CsrOpView stored_op(ibpm_ctx *c, const CSR &M, DevCSR &dev) {
+    dev = c->upload_csr<double>(M);
+    std::vector<double> d((size_t)M.nrows, 0.0);
+    for (int32_t r = 0; r < M.nrows; ++r)
+        for (int32_t q = M.ptr[r]; q < M.ptr[r + 1]; ++q)
+            if (M.col[q] == r) d[r] = M.val[q];
+    CsrOpView op{};
+    op.A = dev.view();
+    op.diag = c->upload(d);
+    return op;
+}
+
+void check_params3(const ibpm3d_params *p) {
+    if (!p) throw InvalidArg("params is NULL");
+    if (!(p->vel_rtol > 0) || !(p->poisson_rtol > 0)) throw InvalidArg("tolerances must be > 0");
+    if (p->vel_maxit < 1 || p->poisson_maxit < 1) throw InvalidArg("maxit must be >= 1");
+    if (p->poisson_solver != IBPM_SOLVER_JACOBI_PCG && p->poisson_solver != IBPM_SOLVER_AMG_PCG)
+        throw InvalidArg("3-D: the Jacobi-PCG and AMG-PCG Poisson solvers only");
+    if (p->poisson_solver == IBPM_SOLVER_AMG_PCG) {
+        if (p->amg_pre < 1 || p->amg_post < 1) throw InvalidArg("AMG needs >= 1 pre and post sweep");
+        if (p->amg_coarse_max < 1 || p->amg_max_levels < 1 || p->amg_max_levels > kMaxLevels)
+            throw InvalidArg("bad AMG limits");
+        if (!(p->amg_theta >= 0)) throw InvalidArg("amg_theta must be >= 0");
+    }
+    if (p->use_graphs != 0 && p->use_graphs != 1) throw InvalidArg("use_graphs must be 0 or 1");
+}
+
+// Operators of the three-dimensional extension on the host, then stored on
+// the device: K (level 0 of an all-CSR hierarchy), A, Q, Q^T and B^1
+void build3(ibpm_ctx *c, const ibpm3d_params *p) {
+    check_params3(p);
+    Model3 m3;
+    try {
+        build_model3(m3, p->nx, p->ny, p->nz, p->xf, p->yf, p->zf, p->nb, p->xb, p->yb, p->zb, p->nu, p->dt,
+                     p->pin_cell);
+    } catch (const std::runtime_error &e) {
+        throw InvalidArg(e.what());
+    }
+    // the solver settings are kept in the fields of the 2-D parameter block
+    ibpm_params &q = c->prm;
+    q = ibpm_params{};
+    q.nu = p->nu;
+    q.dt = p->dt;
+    q.bn_order = 1;
+    q.vel_rtol = p->vel_rtol;
+    q.vel_maxit = p->vel_maxit;
+    q.poisson_solver = p->poisson_solver;
+    q.poisson_rtol = p->poisson_rtol;
+    q.poisson_maxit = p->poisson_maxit;
+    q.amg_theta = p->amg_theta;
+    q.amg_pre = p->amg_pre;
+    q.amg_post = p->amg_post;
+    q.amg_coarse_max = p->amg_coarse_max;
+    q.amg_max_levels = p->amg_max_levels;
+    q.use_graphs = p->use_graphs;
+    q.fuse_transfers = 1;
+    q.pin_cell = p->pin_cell;
+    c->three_d = true;
+    c->stored0 = true;
+    c->amg = p->poisson_solver == IBPM_SOLVER_AMG_PCG;
+    c->n_q3 = m3.n_q;
+    const int nq = (int)m3.n_q, nl = m3.K.nrows;
+    if (c->amg) {
+        AmgParams ap;
+        ap.theta = p->amg_theta;
+        ap.coarse_max = p->amg_coarse_max;
+        ap.max_levels = p->amg_max_levels;
+        try {
+            build_hierarchy(c->h, m3.K, ap);
+        } catch (const std::runtime_error &e) {
+            throw InvalidArg(e.what());
+        }
+        fused_transfer_products(c->h);
+    }
+    c->K0op = stored_op(c, m3.K, c->K0c);
+    c->A3op = stored_op(c, m3.A, c->A3);
+    c->QT3 = c->upload_csr<double>(m3.QT);
+    c->Q3 = c->upload_csr<double>(m3.Q);
+    {
+        // B^1 as a diagonal CSR, for the projection's product
+        CSR B;
+        B.nrows = B.ncols = nq;
+        B.ptr.resize(nq + 1);
+        B.col.resize(nq);
+        for (int f = 0; f <= nq; ++f) B.ptr[f] = f;
+        for (int f = 0; f < nq; ++f) B.col[f] = f;
+        B.val = m3.b1;
+        c->B3 = c->upload_csr<double>(B);
+    }
+    if (c->amg) {
+        upload_levels<double>(c, c->p64);
+        c->coarse_inv = c->upload(c->h.coarse_inv);
+        for (auto &hl : c->h.levels) {
+            hl.P = CSR();
+            hl.R = CSR();
+            hl.RA = CSR();
+            hl.AP = CSR();
+            hl.wdinv.clear();
+        }
+    }
+    c->wq = c->dalloc<double>(nq);
+    alloc_work(c, nq, nl);
+    HIPCHECK(hipStreamSynchronize(c->stream));
+}
+
+// q* = solution of A q* = rhs (Jacobi-PCG from q)
+int solve_velocity3(ibpm_ctx *c, const double *rhs, double *q, ibpm_solve_stats *out) {
+    std::function<void(const double *, double *)> none;
+    return pcg_drive<CsrOpView, double>(c, c->A3op, (int)c->n_q3, true, none, rhs, q, c->vr, c->vz, c->vp,
+                                        c->vq, c->st_vel, c->prm.vel_rtol, c->prm.vel_maxit, c->est_vel, false,
+                                        true, out, 0);
+}
+
+// rhs = Q^T q* - r2, the pinned entry cleared
+void poisson_rhs3(ibpm_ctx *c, const double *qstar, const double *r2, double *rhs) {
+    hipStream_t s = c->stream;
+    launch_csr_gemv(s, c->QT3.view(), qstar, 1.0, nullptr, rhs);
+    launch_axpby(s, c->QT3.nrows, -1.0, r2, 1.0, rhs);
+    HIPCHECK(hipMemsetAsync(rhs + c->prm.pin_cell, 0, sizeof(double), s));
+}
+
+// qout = q* - B^1 (Q lambda)
+void project3(ibpm_ctx *c, const double *qstar, const double *lam, double *qout) {
+    hipStream_t s = c->stream;
+    launch_csr_gemv(s, c->Q3.view(), lam, -1.0, nullptr, c->wq);
+    launch_csr_gemv(s, c->B3.view(), c->wq, 1.0, qstar, qout);
+}
+
+void need3d(const ibpm_ctx *c) {
+    if (!c->three_d) throw InvalidArg("a three-dimensional entry point called on a two-dimensional context");
+}
+
 void build(ibpm_ctx *c, const ibpm_params *p) {
     check_params(p);
     c->prm = *p;
@@ -2481,28 +2652,7 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
             hl.wdinv.clear();
         }
     }
-    c->vr = c->dalloc<double>(nq);
-    c->vz = c->dalloc<double>(nq);
-    c->vp[0] = c->dalloc<double>(nq);
-    c->vp[1] = c->dalloc<double>(nq);
-    c->vq = c->dalloc<double>(nq);
-    for (double *v : {c->vp[0], c->vp[1]}) HIPCHECK(hipMemsetAsync(v, 0, nq * sizeof(double), c->stream));
-    alloc_pcg(c, c->p64, nl);
-    c->r1 = c->dalloc<double>(nq);
-    c->rhs2 = c->dalloc<double>(nl);
-    SolveStatus *sts = c->dalloc<SolveStatus>(5);
-    HIPCHECK(hipMemsetAsync(sts, 0, 5 * sizeof(SolveStatus), c->stream));
-    c->st_vel = sts;
-    c->st_poi = sts + 1;
-    c->st_misc = sts + 2;
-    c->st_bench = sts + 3;
-    c->st_out = sts + 4;
-    // partial sums of up to kFcgMax components per block (FCG multi-dot)
-    c->parts = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
-    c->parts2 = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
-    // the update writes two rows of partials (r . r and, for Jacobi, r . z)
-    c->parts3 = c->dalloc<double>((size_t)kFcgMax * kMaxParts);
-    HIPCHECK(hipHostMalloc((void **)&c->host_st, sizeof(SolveStatus), hipHostMallocDefault));
+    alloc_work(c, nq, nl);
     launch_fill_walls(c->stream, c->g, c->walls[0], c->wall_init);
     launch_fill_walls(c->stream, c->g, c->walls[1], c->wall_init);
     if (c->moving) moving_setup(c, p);
@@ -2530,6 +2680,71 @@ int ibpm_build_operators(const ibpm_params *p, void *stream, ibpm_ctx **out) {
     return rc;
 }
 
+int ibpm3d_build_operators(const ibpm3d_params *p, void *stream, ibpm_ctx **out) {
+    if (!out) return IBPM_EINVAL;
+    *out = nullptr;
+    ibpm_ctx *c = new (std::nothrow) ibpm_ctx();
+    if (!c) return IBPM_ENOMEM;
+    c->stream = (hipStream_t)stream;
+    int rc = guarded(c, [&] {
+        build3(c, p);
+        return IBPM_OK;
+    });
+    *out = c;
+    return rc;
+}
+
+int ibpm3d_solve_velocity(ibpm_ctx *c, const double *rhs, double *q, ibpm_solve_stats *stats) {
+    return guarded(c, [&] {
+        need3d(c);
+        if (!rhs || !q) throw InvalidArg("NULL vector");
+        return solve_velocity3(c, rhs, q, stats);
+    });
+}
+
+int ibpm3d_apply_A(ibpm_ctx *c, const double *x, double *y) {
+    return guarded(c, [&] {
+        need3d(c);
+        if (!x || !y || x == y) throw InvalidArg("x and y must be distinct device vectors");
+        launch_csr_gemv(c->stream, c->A3.view(), x, 1.0, nullptr, y);
+        return IBPM_OK;
+    });
+}
+
+int ibpm3d_poisson_rhs(ibpm_ctx *c, const double *qstar, const double *r2, double *rhs) {
+    return guarded(c, [&] {
+        need3d(c);
+        if (!qstar || !r2 || !rhs || rhs == r2) throw InvalidArg("NULL or aliased vector");
+        poisson_rhs3(c, qstar, r2, rhs);
+        return IBPM_OK;
+    });
+}
+
+int ibpm3d_project(ibpm_ctx *c, const double *qstar, const double *lam, double *qout) {
+    return guarded(c, [&] {
+        need3d(c);
+        if (!qstar || !lam || !qout) throw InvalidArg("NULL vector");
+        project3(c, qstar, lam, qout);
+        return IBPM_OK;
+    });
+}
+
+int ibpm3d_linear_step(ibpm_ctx *c, const double *r1, const double *r2, double *q, double *lam,
+                       ibpm_solve_stats *vel_stats, ibpm_solve_stats *poisson_stats) {
+    return guarded(c, [&] {
+        need3d(c);
+        if (!r1 || !r2 || !q || !lam) throw InvalidArg("NULL vector");
+        int rc = solve_velocity3(c, r1, q, vel_stats);
+        if (rc != IBPM_OK) return rc;
+        poisson_rhs3(c, q, r2, c->rhs2);
+        rc = solve_poisson_impl(c, c->rhs2, lam, poisson_stats);
+        if (rc != IBPM_OK) return rc;
+        project3(c, q, lam, q);
+        HIPCHECK(hipStreamSynchronize(c->stream));
+        return IBPM_OK;
+    });
+}
+
 int ibpm_destroy(ibpm_ctx *ctx) {
     delete ctx;
     return IBPM_OK;
@@ -2538,6 +2753,11 @@ int ibpm_destroy(ibpm_ctx *ctx) {
 const char *ibpm_last_error(const ibpm_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
 
 int ibpm_sizes(const ibpm_ctx *c, int64_t *nq, int64_t *nl) {
+    if (c && c->three_d) {
+        if (nq) *nq = c->n_q3;
+        if (nl) *nl = c->K0c.nrows;
+        return IBPM_OK;
+    }
     if (!c || c->g.nx == 0) return IBPM_EINVAL;
     if (nq) *nq = c->g.n_q;
     if (nl) *nl = c->p64.K0.n;
@@ -2546,6 +2766,7 @@ int ibpm_sizes(const ibpm_ctx *c, int64_t *nq, int64_t *nl) {
 
 int ibpm_init_state(ibpm_ctx *c, double *q, double *conv, double *lam) {
     return guarded(c, [&] {
+        need2d(c);
         if (!q || !conv || !lam) throw InvalidArg("NULL vector");
         double U = c->prm.uinf * std::cos(c->prm.alpha), V = c->prm.uinf * std::sin(c->prm.alpha);
         launch_init_state(c->stream, c->g, q, conv, lam, c->p64.K0.n, U, V);
@@ -2560,6 +2781,7 @@ int ibpm_init_state(ibpm_ctx *c, double *q, double *conv, double *lam) {
 int ibpm_step(ibpm_ctx *c, int32_t nsteps, double *q, double *conv, double *lam,
               ibpm_step_stats *stats) {
     return guarded(c, [&] {
+        need2d(c);
         if (!q || !conv || !lam) throw InvalidArg("NULL vector");
         if (nsteps < 0) throw InvalidArg("nsteps < 0");
         auto t0 = std::chrono::steady_clock::now();
@@ -2609,6 +2831,7 @@ int ibpm_solve_poisson(ibpm_ctx *c, const double *rhs, double *lam, ibpm_solve_s
 
 int ibpm_solve_velocity(ibpm_ctx *c, const double *rhs, double *q, ibpm_solve_stats *stats) {
     return guarded(c, [&] {
+        need2d(c);
         if (!rhs || !q) throw InvalidArg("NULL vector");
         return solve_velocity_impl(c, rhs, q, stats);
     });
@@ -2616,6 +2839,7 @@ int ibpm_solve_velocity(ibpm_ctx *c, const double *rhs, double *q, ibpm_solve_st
 
 int ibpm_solve_velocity_static(ibpm_ctx *c, const double *rhs, double *q, ibpm_solve_stats *stats) {
     return guarded(c, [&] {
+        need2d(c);
         if (!rhs || !q) throw InvalidArg("NULL vector");
         const int64_t nq = c->g.n_q;
         if (nq > kStaticMaxNq)
@@ -2659,6 +2883,7 @@ int ibpm_apply_K(ibpm_ctx *c, const double *x, double *y) {
 
 int ibpm_apply_A(ibpm_ctx *c, const double *x, double *y) {
     return guarded(c, [&] {
+        need2d(c);
         if (!x || !y || x == y) throw InvalidArg("x and y must be distinct device vectors");
         launch_apply_A(c->stream, c->A, x, y);
         return IBPM_OK;
@@ -2668,7 +2893,7 @@ int ibpm_apply_A(ibpm_ctx *c, const double *x, double *y) {
 int ibpm_get_poisson_matrix(ibpm_ctx *c, int64_t *nnz, int32_t *ptr, int32_t *col, double *val) {
     return guarded(c, [&] {
         if (!nnz) throw InvalidArg("nnz is NULL");
-        if (c->moving) {
+        if (c->moving || c->three_d) {
             // the device K of the current positions
             const DevCSR &D = c->K0c;
             *nnz = D.nnz;
@@ -2701,6 +2926,7 @@ int ibpm_bn_info(const ibpm_ctx *cc, int64_t *nnz_K, int64_t *nnz_B, int64_t *pe
 
 int ibpm_move_body(ibpm_ctx *c, const double *xb, const double *yb, const double *ubx, const double *uby) {
     return guarded(c, [&] {
+        need2d(c);
         move_body(c, xb, yb, ubx, uby);
         return IBPM_OK;
     });
@@ -2720,6 +2946,7 @@ int ibpm_moving_info(const ibpm_ctx *cc, int64_t *moves, int64_t *refreshes, int
 
 int ibpm_stage_walls(ibpm_ctx *c, const double *q) {
     return guarded(c, [&] {
+        need2d(c);
         if (!q) throw InvalidArg("NULL vector");
         stage_walls(c, q);
         return IBPM_OK;
@@ -2729,6 +2956,7 @@ int ibpm_stage_walls(ibpm_ctx *c, const double *q) {
 int ibpm_stage_rhs1(ibpm_ctx *c, const double *q, const double *conv_prev, double *r1,
                     double *conv_now) {
     return guarded(c, [&] {
+        need2d(c);
         if (!q || !conv_prev || !r1 || !conv_now) throw InvalidArg("NULL vector");
         stage_rhs1(c, q, conv_prev, r1, conv_now);
         return IBPM_OK;
@@ -2737,6 +2965,7 @@ int ibpm_stage_rhs1(ibpm_ctx *c, const double *q, const double *conv_prev, doubl
 
 int ibpm_stage_rhs2(ibpm_ctx *c, const double *qstar, double *rhs) {
     return guarded(c, [&] {
+        need2d(c);
         if (!qstar || !rhs) throw InvalidArg("NULL vector");
         stage_rhs2(c, qstar, rhs);
         return IBPM_OK;
@@ -2745,6 +2974,7 @@ int ibpm_stage_rhs2(ibpm_ctx *c, const double *qstar, double *rhs) {
 
 int ibpm_stage_project(ibpm_ctx *c, const double *qstar, const double *lam, double *qout) {
     return guarded(c, [&] {
+        need2d(c);
         if (!qstar || !lam || !qout) throw InvalidArg("NULL vector");
         stage_project(c, qstar, lam, qout);
         return IBPM_OK;
@@ -2753,6 +2983,7 @@ int ibpm_stage_project(ibpm_ctx *c, const double *qstar, const double *lam, doub
 
 int ibpm_get_walls(ibpm_ctx *c, int32_t which, double *host) {
     return guarded(c, [&] {
+        need2d(c);
         if (!host || (which != 0 && which != 1)) throw InvalidArg("bad arguments");
         WallOffsets wo = WallOffsets::make(c->g.nx, c->g.ny);
         const double *src = c->walls[which == 0 ? c->cur : 1 - c->cur];
@@ -2764,6 +2995,7 @@ int ibpm_get_walls(ibpm_ctx *c, int32_t which, double *host) {
 
 int ibpm_set_walls(ibpm_ctx *c, int32_t which, const double *host) {
     return guarded(c, [&] {
+        need2d(c);
         if (!host || (which != 0 && which != 1)) throw InvalidArg("bad arguments");
         WallOffsets wo = WallOffsets::make(c->g.nx, c->g.ny);
         double *dst = c->walls[which == 0 ? c->cur : 1 - c->cur];
@@ -2876,6 +3108,7 @@ int ibpm_plan_hierarchy(const ibpm_params *p, int32_t cap, int32_t *levels, int6
 int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, int64_t min_footprint, double *avg_ms,
                      double *bytes) {
     return guarded(c, [&] {
+        need2d(c);
         if (reps < 1 || !avg_ms || min_footprint < 0) throw InvalidArg("bad arguments");
         if (c->stored0 && kernel != IBPM_KERNEL_A_PCG_SPMV && kernel != IBPM_KERNEL_STREAM_COPY &&
             kernel != IBPM_KERNEL_COPY_LEVEL0)
@@ -3189,6 +3422,7 @@ int ibpm_iteration_launches(const ibpm_ctx *cc, int32_t ncounts, int32_t *counts
 
 int ibpm_nn_init(ibpm_ctx *c, uint64_t seed) {
     return guarded(c, [&] {
+        need2d(c);
         nn_alloc(c);
         nn_init_weights(c, seed);
         HIPCHECK(hipStreamSynchronize(c->stream));
@@ -3207,6 +3441,7 @@ int ibpm_nn_get_weights(ibpm_ctx *c, float *host, int64_t n) {
 
 int ibpm_nn_set_weights(ibpm_ctx *c, const float *host, int64_t n) {
     return guarded(c, [&] {
+        need2d(c);
         if (!host || n != nn_param_count()) throw InvalidArg("wrong weight count");
         nn_alloc(c);
         nn_set_master(c, host);
@@ -3218,6 +3453,7 @@ int ibpm_nn_set_weights(ibpm_ctx *c, const float *host, int64_t n) {
 int ibpm_nn_layer(ibpm_ctx *c, int32_t layer, int32_t mode, const float *x, const float *dy,
                   const float *mask, float *out) {
     return guarded(c, [&] {
+        need2d(c);
         NNState &N = c->nn;
         if (!N.ready) throw InvalidArg("network not initialised");
         if (layer < 0 || layer >= kNNLayers || mode < 0 || mode > 2 || !out) throw InvalidArg("bad arguments");
@@ -3256,6 +3492,7 @@ int ibpm_nn_layer(ibpm_ctx *c, int32_t layer, int32_t mode, const float *x, cons
 
 int ibpm_nn_apply(ibpm_ctx *c, const double *r, double *e) {
     return guarded(c, [&] {
+        need2d(c);
         if (!c->nn.ready) throw InvalidArg("network not initialised");
         if (!r || !e) throw InvalidArg("NULL vector");
         nn_apply(c, r, e);
@@ -3266,6 +3503,7 @@ int ibpm_nn_apply(ibpm_ctx *c, const double *r, double *e) {
 int ibpm_nn_train(ibpm_ctx *c, const float *r1, const float *e1, int32_t nsamples,
                   const int32_t *order, int32_t norder, int32_t batch, float lr, double *mean_loss) {
     return guarded(c, [&] {
+        need2d(c);
         if (!c->nn.ready) throw InvalidArg("network not initialised");
         if (!r1 || !e1 || !order || nsamples < 1 || norder < 1 || batch < 1 || !(lr > 0))
             throw InvalidArg("bad arguments");
@@ -3277,6 +3515,7 @@ int ibpm_nn_train(ibpm_ctx *c, const float *r1, const float *e1, int32_t nsample
 
 int ibpm_nn_adam_step(ibpm_ctx *c, const float *grad, float lr) {
     return guarded(c, [&] {
+        need2d(c);
         NNState &N = c->nn;
         if (!N.ready) throw InvalidArg("network not initialised");
         if (!grad || !(lr > 0)) throw InvalidArg("bad arguments");
@@ -3307,6 +3546,7 @@ int ibpm_nn_adam_step(ibpm_ctx *c, const float *grad, float lr) {
 
 int ibpm_nn_loss_grad(ibpm_ctx *c, const float *r1, const float *e1, double *loss, float *grad) {
     return guarded(c, [&] {
+        need2d(c);
         NNState &N = c->nn;
         if (!N.ready) throw InvalidArg("network not initialised");
         if (!r1 || !e1 || !loss || !grad) throw InvalidArg("NULL argument");
@@ -3327,6 +3567,7 @@ int ibpm_nn_loss_grad(ibpm_ctx *c, const float *r1, const float *e1, double *los
 int ibpm_harvest(ibpm_ctx *c, const double *rhs, double *x, const double *xstar, int32_t npairs,
                  float *r1_out, float *e1_out, int32_t *nout) {
     return guarded(c, [&] {
+        need2d(c);
         if (!c->amg) throw InvalidArg("harvesting needs an AMG context");
         if (!rhs || !x || !xstar || !r1_out || !e1_out || npairs < 1) throw InvalidArg("bad arguments");
         hipStream_t s = c->stream;

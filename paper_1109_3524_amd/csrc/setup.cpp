@@ -887,6 +887,216 @@ void build_hierarchy(Hierarchy &h, const CSR &K, const AmgParams &prm) {
     dense_spd_inverse(Ac, h.coarse_inv);
 }
 
+// ---------------------------------------------------------------------------
+// Three dimensions
+
+namespace {
+
+struct Axis {
+    std::vector<double> f, w, c, D;   // faces, widths, centres, centre-to-centre gaps (n + 1)
+    int n = 0;
+};
+
+Axis make_axis(int n, const double *f, const char *name) {
+    Axis a;
+    if (n < 2) fail(std::string("need at least 2 cells along ") + name);
+    a.n = n;
+    a.f.assign(f, f + n + 1);
+    a.w.resize(n);
+    a.c.resize(n);
+    for (int i = 0; i < n; ++i) {
+        a.w[i] = a.f[i + 1] - a.f[i];
+        if (!(a.w[i] > 0) || !std::isfinite(a.w[i])) fail(std::string("faces must be finite and increasing along ") + name);
+        a.c[i] = 0.5 * (a.f[i] + a.f[i + 1]);
+    }
+    a.D.resize(n + 1);
+    a.D[0] = 0.5 * a.w[0];
+    a.D[n] = 0.5 * a.w[n - 1];
+    for (int i = 1; i < n; ++i) a.D[i] = 0.5 * (a.w[i - 1] + a.w[i]);
+    return a;
+}
+
+}  // namespace
+
+void build_model3(Model3 &m, int nx, int ny, int nz, const double *xf, const double *yf, const double *zf, int nb,
+                  const double *xb, const double *yb, const double *zb, double nu, double dt, int pin) {
+    if (!xf || !yf || !zf) fail("face arrays are NULL");
+    if (nb < 0 || (nb > 0 && (!xb || !yb || !zb))) fail("bad body points");
+    if (!(nu > 0) || !(dt > 0)) fail("nu and dt must be positive");
+    const Axis ax[3] = {make_axis(nx, xf, "x"), make_axis(ny, yf, "y"), make_axis(nz, zf, "z")};
+    m = Model3();
+    m.nx = nx;
+    m.ny = ny;
+    m.nz = nz;
+    m.nb = nb;
+    m.n_cell = (int64_t)nx * ny * nz;
+    if (pin < 0 || pin >= m.n_cell) fail("pin_cell out of range");
+    m.pin = pin;
+    // component a: counts per axis and offset in q
+    int64_t cnt[3][3], off[3];
+    int64_t tot = 0;
+    for (int a = 0; a < 3; ++a) {
+        for (int b = 0; b < 3; ++b) cnt[a][b] = ax[b].n - (a == b ? 1 : 0);
+        off[a] = tot;
+        tot += cnt[a][0] * cnt[a][1] * cnt[a][2];
+    }
+    m.n_q = tot;
+    const int64_t n_l = m.n_cell + 3 * (int64_t)nb;
+    if (tot >= INT32_MAX || n_l >= INT32_MAX) fail("grid too large");
+    // index of component a at per-axis indices (the own axis counted from
+    // the first interior face line)
+    auto fidx = [&](int a, const int64_t *id) {
+        return off[a] + (id[2] * cnt[a][1] + id[1]) * cnt[a][0] + id[0];
+    };
+    // per-unknown metrics: M (gap across the face), R (face area)
+    m.b1.resize(tot);
+    std::vector<double> Mv(tot), Rv(tot);
+    for (int a = 0; a < 3; ++a)
+        for (int64_t k = 0; k < cnt[a][2]; ++k)
+            for (int64_t j = 0; j < cnt[a][1]; ++j)
+                for (int64_t i = 0; i < cnt[a][0]; ++i) {
+                    const int64_t id[3] = {i, j, k};
+                    const int64_t f = fidx(a, id);
+                    double M = 1.0, R = 1.0;
+                    for (int b = 0; b < 3; ++b) {
+                        if (b == a) M = ax[b].D[id[b] + 1];
+                        else R *= ax[b].w[id[b]];
+                    }
+                    Mv[f] = M;
+                    Rv[f] = R;
+                    m.b1[f] = dt * R / M;
+                }
+    // A: 7 points per row, columns in increasing order (z-, y-, x-, centre, x+, y+, z+)
+    {
+        CSR &A = m.A;
+        A.nrows = A.ncols = (int32_t)tot;
+        A.ptr.assign(1, 0);
+        A.col.reserve(7 * tot);
+        A.val.reserve(7 * tot);
+        for (int a = 0; a < 3; ++a)
+            for (int64_t k = 0; k < cnt[a][2]; ++k)
+                for (int64_t j = 0; j < cnt[a][1]; ++j)
+                    for (int64_t i = 0; i < cnt[a][0]; ++i) {
+                        const int64_t id[3] = {i, j, k};
+                        const int64_t f = fidx(a, id);
+                        double lo[3], hi[3];
+                        bool has_lo[3], has_hi[3];
+                        double diag_l = 0.0;
+                        for (int b = 0; b < 3; ++b) {
+                            double cg, lg, rg;
+                            if (b == a) {   // nodes on face lines 1..n-1: gaps are cell widths
+                                const int64_t t = id[b] + 1;
+                                cg = ax[b].D[t];
+                                lg = ax[b].w[t - 1];
+                                rg = ax[b].w[t];
+                            } else {        // nodes at cell centres: gaps are centre distances
+                                const int64_t t = id[b];
+                                cg = ax[b].w[t];
+                                lg = ax[b].D[t];
+                                rg = ax[b].D[t + 1];
+                            }
+                            lo[b] = 1.0 / (lg * cg);
+                            hi[b] = 1.0 / (rg * cg);
+                            diag_l -= lo[b] + hi[b];
+                            has_lo[b] = id[b] > 0;
+                            has_hi[b] = id[b] < cnt[a][b] - 1;
+                        }
+                        const double Mf = Mv[f] / Rv[f];
+                        auto push = [&](int64_t g, double lhat) {
+                            // L = M Lhat R^-1: row weight M_f, column scale 1 / R_g
+                            A.col.push_back((int32_t)g);
+                            A.val.push_back(-0.5 * nu * (Mv[f] * lhat / Rv[g]));
+                        };
+                        const int64_t stride[3] = {1, cnt[a][0], cnt[a][0] * cnt[a][1]};
+                        for (int b = 2; b >= 0; --b)
+                            if (has_lo[b]) push(f - stride[b], lo[b]);
+                        A.col.push_back((int32_t)f);
+                        A.val.push_back(Mf / dt - 0.5 * nu * (Mv[f] * diag_l / Rv[f]));
+                        for (int b = 0; b < 3; ++b)
+                            if (has_hi[b]) push(f + stride[b], hi[b]);
+                        A.ptr.push_back((int32_t)A.col.size());
+                    }
+    }
+    // Q^T = [-D; E]
+    CSR &QT = m.QT;
+    QT.nrows = (int32_t)n_l;
+    QT.ncols = (int32_t)tot;
+    QT.ptr.assign(1, 0);
+    for (int64_t k = 0; k < nz; ++k)
+        for (int64_t j = 0; j < ny; ++j)
+            for (int64_t i = 0; i < nx; ++i) {
+                const int64_t cid[3] = {i, j, k};
+                for (int a = 0; a < 3; ++a) {
+                    // low face (outward flux -q): -D gives +1; high face: -1
+                    if (cid[a] >= 1) {
+                        int64_t id[3] = {i, j, k};
+                        id[a] -= 1;
+                        QT.col.push_back((int32_t)fidx(a, id));
+                        QT.val.push_back(1.0);
+                    }
+                    if (cid[a] <= ax[a].n - 2) {
+                        QT.col.push_back((int32_t)fidx(a, cid));
+                        QT.val.push_back(-1.0);
+                    }
+                }
+                QT.ptr.push_back((int32_t)QT.col.size());
+            }
+    const double *P[3] = {xb, yb, zb};
+    std::vector<double> h(3 * (size_t)nb);
+    std::vector<int> cell(3 * (size_t)nb);
+    for (int p = 0; p < nb; ++p)
+        for (int b = 0; b < 3; ++b) {
+            if (!std::isfinite(P[b][p])) fail("point positions must be finite");
+            static const char *const names[3] = {"x", "y", "z"};
+            h[3 * p + b] = local_width(ax[b].f, ax[b].w, P[b][p], names[b]);
+            cell[3 * p + b] = cell_of(ax[b].f, P[b][p]);
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int p = 0; p < nb; ++p) {
+            // candidate indices per axis (own axis: face lines 1..n-1, as
+            // component indices 0..n-2; others: cells 0..n-1)
+            std::vector<int64_t> near[3];
+            std::vector<double> wt[3];
+            for (int b = 0; b < 3; ++b) {
+                const double X = P[b][p], hb = h[3 * p + b];
+                const int c0 = cell[3 * p + b];
+                for (int t = c0 - 2; t <= c0 + 3; ++t) {
+                    double pos;
+                    int64_t idx;
+                    if (b == a) {
+                        if (t < 1 || t > ax[b].n - 1) continue;
+                        pos = ax[b].f[t];
+                        idx = t - 1;
+                    } else {
+                        if (t < 0 || t > ax[b].n - 1) continue;
+                        pos = ax[b].c[t];
+                        idx = t;
+                    }
+                    if (!(std::fabs(pos - X) < 1.5 * hb)) continue;
+                    near[b].push_back(idx);
+                    wt[b].push_back(delta_h(pos - X, hb));
+                }
+            }
+            for (size_t kk = 0; kk < near[2].size(); ++kk)
+                for (size_t jj = 0; jj < near[1].size(); ++jj)
+                    for (size_t ii = 0; ii < near[0].size(); ++ii) {
+                        const int64_t id[3] = {near[0][ii], near[1][jj], near[2][kk]};
+                        const int64_t f = fidx(a, id);
+                        // control volume M R times the three deltas, then R^-1
+                        const double v = (Mv[f] * Rv[f]) * (wt[0][ii] * wt[1][jj] * wt[2][kk]);
+                        QT.col.push_back((int32_t)f);
+                        QT.val.push_back(v * (1.0 / Rv[f]));
+                    }
+            QT.ptr.push_back((int32_t)QT.col.size());
+        }
+    m.Q = csr_transpose(QT);
+    // K = Q^T (B^1 Q), pinned
+    CSR BQ = m.Q;
+    for (int32_t r = 0; r < BQ.nrows; ++r)
+        for (int32_t q = BQ.ptr[r]; q < BQ.ptr[r + 1]; ++q) BQ.val[q] *= m.b1[r];
+    m.K = pin_rows_cols(csr_multiply(QT, BQ), pin);
+}
+
 void regalerkin_from(Hierarchy &h, int from, CSR &&A) {
     const int L = (int)h.levels.size();
     if (from < 0 || from >= L) fail("hierarchy refresh: bad level");

@@ -112,6 +112,23 @@ void check_points(const GridMetrics &g, int nb, const double *xb, const double *
 // helpers exposed for the host tests
 double roma_phi(double s);
 CSR csr_transpose(const CSR &A);
+
+// The three-dimensional extension (the 7-point pressure stencil named as
+// the next step in Sec. 7): Eqs. 6-11 carried over axis by axis.  Unknowns
+// x fastest, then y, then z: u (faces x_1..x_{nx-1}) | v | w, then the
+// cells and the 3 nb forces (x, y, z components) of lambda.  q = R u with
+// R the face areas, M the centre-to-centre gaps across the faces,
+// A = M R^-1 / dt - (nu/2) M Lhat R^-1 (7 points per row), B^1 = dt R M^-1,
+// Q^T = [-D; E] with E = (control volume x product of three deltas) R^-1,
+// K = Q^T B^1 Q with cell `pin` pinned.
+struct Model3 {
+    int32_t nx = 0, ny = 0, nz = 0, nb = 0, pin = 0;
+    int64_t n_q = 0, n_cell = 0;
+    CSR A, QT, Q, K;
+    std::vector<double> b1;
+};
+void build_model3(Model3 &m, int nx, int ny, int nz, const double *xf, const double *yf, const double *zf, int nb,
+                  const double *xb, const double *yb, const double *zb, double nu, double dt, int pin);
 CSR csr_multiply(const CSR &A, const CSR &B);
 
 }  // namespace ibpm

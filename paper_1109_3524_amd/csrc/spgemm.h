@@ -39,6 +39,8 @@ void launch_tentative(hipStream_t s, int n, const int32_t *agg, int32_t *ptr, in
 // diagonal entry is not positive
 void launch_smooth_prolongator(hipStream_t s, int n, const int32_t *ptr, const int32_t *col, double *val,
                                const int32_t *agg, const double *diag, double w, int *err);
+// y = a x + b y
+void launch_axpby(hipStream_t s, int n, double a, const double *x, double b, double *y);
 // y = base + alpha A x (base may be null)
 void launch_csr_gemv(hipStream_t s, CSRView A, const double *x, double alpha, const double *base, double *y);
 

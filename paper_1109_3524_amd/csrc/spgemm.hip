@@ -242,6 +242,12 @@ __global__ __launch_bounds__(kBlock) void k_smooth_prolongator(int n, const int3
     }
 }
 
+// y = a x + b y
+__global__ __launch_bounds__(kBlock) void k_axpby(int n, double a, const double *x, double b, double *y) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) y[i] = a * x[i] + b * y[i];
+}
+
 int blocks_for(int n) { return (n + kBlock - 1) / kBlock; }
 
 }  // namespace
@@ -296,6 +302,10 @@ void launch_tentative(hipStream_t s, int n, const int32_t *agg, int32_t *ptr, in
 void launch_smooth_prolongator(hipStream_t s, int n, const int32_t *ptr, const int32_t *col, double *val,
                                const int32_t *agg, const double *diag, double w, int *err) {
     if (n > 0) LAUNCHS(k_smooth_prolongator, blocks_for(n), n, ptr, col, val, agg, diag, w, err);
+}
+
+void launch_axpby(hipStream_t s, int n, double a, const double *x, double b, double *y) {
+    if (n > 0) LAUNCHS(k_axpby, blocks_for(n), n, a, x, b, y);
 }
 
 void launch_csr_gemv(hipStream_t s, CSRView A, const double *x, double alpha, const double *base, double *y) {

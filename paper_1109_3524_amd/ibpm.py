@@ -39,7 +39,8 @@ EXPORTED = (
     "ibpm_nn_set_weights", "ibpm_nn_layer", "ibpm_nn_apply", "ibpm_nn_train",
     "ibpm_nn_loss_grad", "ibpm_harvest", "ibpm_plan_hierarchy", "ibpm_iteration_launches",
     "ibpm_nn_adam_step", "ibpm_solve_velocity_static", "ibpm_get_poisson_matrix", "ibpm_bn_info",
-    "ibpm_move_body", "ibpm_moving_info",
+    "ibpm_move_body", "ibpm_moving_info", "ibpm3d_build_operators", "ibpm3d_solve_velocity",
+    "ibpm3d_apply_A", "ibpm3d_poisson_rhs", "ibpm3d_project", "ibpm3d_linear_step",
 )
 
 NN_PARAMS = 39168                     # IBPM_NN_PARAMS
@@ -82,6 +83,25 @@ class Params(ctypes.Structure):
         ("body_ramp", ctypes.c_double),
         ("moving_body", ctypes.c_int32),
         ("amg_rebuild_every", ctypes.c_int32),
+    ]
+
+
+class Params3(ctypes.Structure):
+    """ibpm3d_params (field order of include/ibpm.h)."""
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("xf", ctypes.POINTER(ctypes.c_double)), ("yf", ctypes.POINTER(ctypes.c_double)),
+        ("zf", ctypes.POINTER(ctypes.c_double)),
+        ("nb", ctypes.c_int32),
+        ("xb", ctypes.POINTER(ctypes.c_double)), ("yb", ctypes.POINTER(ctypes.c_double)),
+        ("zb", ctypes.POINTER(ctypes.c_double)),
+        ("nu", ctypes.c_double), ("dt", ctypes.c_double),
+        ("vel_rtol", ctypes.c_double), ("vel_maxit", ctypes.c_int32),
+        ("poisson_solver", ctypes.c_int32), ("poisson_rtol", ctypes.c_double),
+        ("poisson_maxit", ctypes.c_int32),
+        ("amg_theta", ctypes.c_double), ("amg_pre", ctypes.c_int32), ("amg_post", ctypes.c_int32),
+        ("amg_coarse_max", ctypes.c_int32), ("amg_max_levels", ctypes.c_int32),
+        ("pin_cell", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
     ]
 
 
@@ -149,6 +169,12 @@ def load():
                          ctypes.POINTER(i64)],
         "ibpm_move_body": [P, D, D, D, D],
         "ibpm_moving_info": [P, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i32)],
+        "ibpm3d_build_operators": [ctypes.POINTER(Params3), P, ctypes.POINTER(P)],
+        "ibpm3d_solve_velocity": [P, P, P, ctypes.POINTER(SolveStats)],
+        "ibpm3d_apply_A": [P, P, P],
+        "ibpm3d_poisson_rhs": [P, P, P, P],
+        "ibpm3d_project": [P, P, P, P],
+        "ibpm3d_linear_step": [P, P, P, P, P, ctypes.POINTER(SolveStats), ctypes.POINTER(SolveStats)],
         "ibpm_nn_init": [P, ctypes.c_uint64],
         "ibpm_nn_get_weights": [P, P, i64],
         "ibpm_nn_set_weights": [P, P, i64],
@@ -584,3 +610,94 @@ def unpack_walls(w: np.ndarray, nx: int, ny: int) -> dict:
 def pack_walls(parts: dict) -> np.ndarray:
     return np.concatenate([np.asarray(parts[k], dtype=np.float64)
                            for k in ("uL", "uR", "vB", "vT", "uBt", "uTt", "vLt", "vRt")])
+
+
+def params3_from_workload(wl: W.Workload3, **over) -> dict:
+    p = dict(nx=wl.nx, ny=wl.ny, nz=wl.nz, xf=wl.xf, yf=wl.yf, zf=wl.zf, nb=wl.nb, xb=wl.xb, yb=wl.yb,
+             zb=wl.zb, nu=wl.nu, dt=wl.dt, vel_rtol=wl.vel_rtol, vel_maxit=wl.vel_maxit,
+             poisson_solver=wl.poisson_solver, poisson_rtol=wl.poisson_rtol, poisson_maxit=wl.poisson_maxit,
+             amg_theta=wl.amg_theta, amg_pre=wl.amg_pre, amg_post=wl.amg_post, amg_coarse_max=wl.amg_coarse_max,
+             amg_max_levels=wl.amg_max_levels, pin_cell=wl.pin_cell, use_graphs=1)
+    p.update(over)
+    return p
+
+
+def make_params3(p: dict):
+    """ibpm3d_params from a dict of params3_from_workload; returns the struct
+    and the numpy arrays its pointers refer to (keep them alive)."""
+    st = Params3()
+    keep = {}
+    for k, _ in Params3._fields_:
+        v = p[k]
+        if k in ("xf", "yf", "zf", "xb", "yb", "zb"):
+            a = np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+            if a.size == 0:
+                a = np.zeros(1)
+            keep[k] = a
+            setattr(st, k, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+        else:
+            setattr(st, k, v)
+    return st, keep
+
+
+class Context3(Context):
+    """A three-dimensional context: the operators of one time step's linear
+    algebra (Eq. 11) on the device; the Poisson calls are those of Context."""
+
+    def __init__(self, wl: W.Workload3, **overrides):
+        import torch
+        self._torch = torch
+        L = load()
+        p = params3_from_workload(wl, **overrides)
+        st, self._arrays = make_params3(p)
+        self.params = p
+        self.wl = wl
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        rc = L.ibpm3d_build_operators(ctypes.byref(st), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        self._h = h
+        if rc != IBPM_OK:
+            msg = L.ibpm_last_error(h).decode() if h.value else ""
+            if h.value:
+                L.ibpm_destroy(h)
+            self._h = ctypes.c_void_p()
+            raise IBPMError(rc, msg)
+        nq, nl = ctypes.c_int64(), ctypes.c_int64()
+        self._check(L.ibpm_sizes(h, ctypes.byref(nq), ctypes.byref(nl)))
+        self.n_q, self.n_lambda = nq.value, nl.value
+        self.nx, self.ny, self.nz, self.nb = wl.nx, wl.ny, wl.nz, wl.nb
+
+    def solve_velocity(self, rhs, q, allow_fail=False):
+        s = SolveStats()
+        rc = load().ibpm3d_solve_velocity(self._h, self._vec(rhs, self.n_q, "rhs"), self._vec(q, self.n_q, "q"),
+                                          ctypes.byref(s))
+        self._check(rc, allow=(IBPM_ENOTCONV, IBPM_ENAN) if allow_fail else ())
+        return s.as_dict()
+
+    def apply_A(self, x, y=None):
+        y = self.zeros_q() if y is None else y
+        self._check(load().ibpm3d_apply_A(self._h, self._vec(x, self.n_q, "x"), self._vec(y, self.n_q, "y")))
+        return y
+
+    def poisson_rhs(self, qstar, r2, rhs=None):
+        rhs = self.zeros_lambda() if rhs is None else rhs
+        self._check(load().ibpm3d_poisson_rhs(self._h, self._vec(qstar, self.n_q, "qstar"),
+                                              self._vec(r2, self.n_lambda, "r2"),
+                                              self._vec(rhs, self.n_lambda, "rhs")))
+        return rhs
+
+    def project(self, qstar, lam, qout=None):
+        qout = self.zeros_q() if qout is None else qout
+        self._check(load().ibpm3d_project(self._h, self._vec(qstar, self.n_q, "qstar"),
+                                          self._vec(lam, self.n_lambda, "lambda"),
+                                          self._vec(qout, self.n_q, "qout")))
+        return qout
+
+    def linear_step(self, r1, r2, q, lam, allow_fail=False):
+        sv, sp = SolveStats(), SolveStats()
+        rc = load().ibpm3d_linear_step(self._h, self._vec(r1, self.n_q, "r1"), self._vec(r2, self.n_lambda, "r2"),
+                                       self._vec(q, self.n_q, "q"), self._vec(lam, self.n_lambda, "lambda"),
+                                       ctypes.byref(sv), ctypes.byref(sp))
+        self._check(rc, allow=(IBPM_ENOTCONV, IBPM_ENAN) if allow_fail else ())
+        return sv.as_dict(), sp.as_dict()

@@ -16,7 +16,7 @@ HEADER = os.path.join(ROOT, "include", "ibpm.h")
 
 def _declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(ibpm_[A-Za-z_0-9]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(ibpm(?:3d)?_[A-Za-z_0-9]+)\s*\(", text)))
 
 
 def test_header_symbols_are_exported():
@@ -153,3 +153,31 @@ def test_pin_cell_moves_the_pinned_row_on_the_host():
     b = ibpm.plan_hierarchy(wl.replace(pin_cell=47 * 48 + 47))
     assert a["levels"] == b["levels"] and list(a["sizes"])[0] == list(b["sizes"])[0]
     assert a["rho"][0] != b["rho"][0]
+
+
+@pytest.mark.parametrize("over,msg", [
+    (dict(poisson_solver=2), "Jacobi-PCG and AMG-PCG"),
+    (dict(vel_rtol=0.0), "tolerances"),
+    (dict(nu=-1.0), "positive"),
+    (dict(pin_cell=-1), "pin_cell"),
+    (dict(amg_pre=0), "sweep"),
+])
+def test_3d_invalid_parameters_are_rejected_on_the_host(over, msg):
+    L = ibpm.load()
+    st, keep = ibpm.make_params3(ibpm.params3_from_workload(W.sphere3d(12, radius=0.3), **over))
+    h = ctypes.c_void_p()
+    rc = L.ibpm3d_build_operators(ctypes.byref(st), None, ctypes.byref(h))
+    assert rc == ibpm.IBPM_EINVAL
+    assert msg in L.ibpm_last_error(h).decode()
+    L.ibpm_destroy(h)
+
+
+def test_3d_points_outside_the_uniform_cells_are_rejected_on_the_host():
+    L = ibpm.load()
+    wl = W.sphere3d(12, radius=0.3)
+    st, keep = ibpm.make_params3(ibpm.params3_from_workload(wl.replace(zb=wl.zb + 0.9)))
+    h = ctypes.c_void_p()
+    rc = L.ibpm3d_build_operators(ctypes.byref(st), None, ctypes.byref(h))
+    assert rc == ibpm.IBPM_EINVAL
+    assert "domain edge" in L.ibpm_last_error(h).decode()
+    L.ibpm_destroy(h)
