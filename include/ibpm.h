@@ -406,7 +406,12 @@ int ibpm_plan_hierarchy(const ibpm_params *p, int32_t cap, int32_t *levels, int6
 #define IBPM_KERNEL_COPY_LEVEL0   12  /* y = x over n_lambda doubles (one finest-level vector each
                                          way): the bandwidth a streaming kernel of the level-0
                                          vectors' size reaches */
-#define IBPM_NUM_KERNELS          13
+#define IBPM_KERNEL_PROLONG_POST0 13  /* the prolongation and both post-smoothing sweeps of the
+                                            finest level in one pass (strips, plus three small
+                                            passes over the box coupled to the forces), where the
+                                            iteration uses it (post = 2, grids of 2^22 cells and
+                                            more) */
+#define IBPM_NUM_KERNELS          14
 
 /* Launches per PCG iteration that the FP64 AMG-PCG solve of this context
  * makes of each kernel ibpm_time_kernel can time: counts[k] for kernel id

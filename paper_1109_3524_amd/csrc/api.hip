@@ -455,6 +455,21 @@ void enqueue_vcycle(ibpm_ctx *c, PrecSet<T> &P, const T *r, T *z, SolveStatus *s
         DevLevelT<T> &l0 = P.lev[0];
         T *a = cur[0];
         T *b = (a == l0.xa) ? l0.xb : l0.xa;
+        if (post == 2 && post2_rows(K) > 0) {
+            // the prolongation and both post-sweeps in one pass
+            if (mx) {
+                if constexpr (f32)
+                    c->rz_G = launch_k0_prolong_post2(s, K, (const int *)l0.agg, (const T *)cur[1], l0.pomega,
+                                                      l0.omega, r, (const T *)a, b, l0.r, (T *)nullptr, mx->z64,
+                                                      mx->r64, st, c->parts, POST_WIDEN);
+            } else {
+                const int G = launch_k0_prolong_post2(s, K, (const int *)l0.agg, (const T *)cur[1], l0.pomega,
+                                                      l0.omega, r, (const T *)a, b, l0.r, z, nullptr, nullptr, st,
+                                                      c->parts, with_rz ? POST_RZ : POST_PLAIN);
+                if (with_rz) c->rz_G = G;
+            }
+            return;
+        }
         launch_k0_prolong_mf(s, K, (const int *)l0.agg, (const T *)cur[1], l0.pomega, a, st);
         for (int k = 0; k < post - 1; ++k) {
             launch_k0_jacobi(s, K, l0.omega, r, (const T *)a, b, st);
@@ -509,13 +524,15 @@ int pcg_drive(ibpm_ctx *c, const Op &op, int n, bool jacobi,
     // launch per iteration): the update leaves its r . r partials in parts3
     // and the preconditioner runs once more after the converged update, on
     // a residual no later kernel uses.
-    const bool defer = !jacobi && c->rz_G <= kFuseMaxParts && update_blocks_of(n) <= kFuseMaxParts;
     // With a preconditioner that starts with the update, the update kernel
     // goes too: the residual then alternates between r and fpre->r2.  With
     // the deferred stop test the folded pass gathers the product's partials
-    // itself; without it (large grids) one-block finalizes around the pass
-    // give it p.q and take the stop test.
-    const bool fuse = fpre && (!defer || (fpre->G_pq <= kFuseMaxParts && fpre->G_rr <= kFuseMaxParts));
+    // itself; where it cannot (large grids) one-block finalizes around the
+    // pass give it p.q and take the stop test, and the fold is kept: it
+    // saves a whole pass, the deferred test only a one-block launch.
+    const bool fuse = fpre != nullptr;
+    const bool defer = !jacobi && c->rz_G <= kFuseMaxParts && update_blocks_of(n) <= kFuseMaxParts &&
+                       (!fuse || (fpre->G_pq <= kFuseMaxParts && fpre->G_rr <= kFuseMaxParts));
     const int G_rr = fuse ? fpre->G_rr : update_blocks_of(n);
     T *rcur = r, *rnext = fuse ? fpre->r2 : nullptr;
     auto iteration = [&]() {
@@ -3116,7 +3133,8 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, int64_t min_foot
         const bool needs_amg = kernel == IBPM_KERNEL_K0_JACOBI || kernel == IBPM_KERNEL_K0_RESIDUAL ||
                                kernel == IBPM_KERNEL_RESTRICT0 || kernel == IBPM_KERNEL_PROLONG0 ||
                                kernel == IBPM_KERNEL_COARSE_CYCLE || kernel == IBPM_KERNEL_PRESMOOTH0 ||
-                               kernel == IBPM_KERNEL_UPDATE_PRESMOOTH0 || kernel == IBPM_KERNEL_L1_JACOBI;
+                               kernel == IBPM_KERNEL_UPDATE_PRESMOOTH0 || kernel == IBPM_KERNEL_L1_JACOBI ||
+                               kernel == IBPM_KERNEL_PROLONG_POST0;
         PrecSet<double> &P = c->p64;
         if (needs_amg && (!c->amg || P.lev.size() < 2)) throw InvalidArg("kernel needs an AMG hierarchy");
         hipStream_t s = c->stream;
@@ -3237,6 +3255,23 @@ int ibpm_time_kernel(ibpm_ctx *c, int32_t kernel, int32_t reps, int64_t min_foot
             launch = [=, &at](int k) { launch_k0_prolong_mf(s, K0, agg, at(x1, k), w, at(x0, k), sb); };
             // aggregates, x read and written, the coarse vector, coupling and metrics
             by = 4.0 * n + 16.0 * n + 8.0 * P.lev[1].n + b_coupling + b_metric;
+            break;
+        }
+        case IBPM_KERNEL_PROLONG_POST0: {
+            if (post2_rows(K0) == 0) throw InvalidArg("the prolongation + post-smoothing pass is off for this grid");
+            const DevLevelT<double> &l0 = P.lev[0];
+            const int *agg = l0.agg;
+            const double pw = l0.pomega, omega = l0.omega;
+            const int x1 = slot(P.lev[1].xa, P.lev[1].n), a = slot(l0.xa, n), tmp = slot(l0.xb, n),
+                      tmp2 = slot(l0.r, n), r = slot(P.r, n), z = slot(P.z, n);
+            launch = [=, &at](int k) {
+                launch_k0_prolong_post2(s, K0, agg, (const double *)at(x1, k), pw, omega, (const double *)at(r, k),
+                                        (const double *)at(a, k), at(tmp, k), at(tmp2, k), at(z, k), nullptr,
+                                        nullptr, sb, parts, POST_RZ);
+            };
+            // aggregates, a and b read, z written, the coarse vector, the
+            // coupling rows and the metrics (each once)
+            by = 4.0 * n + 24.0 * n + 8.0 * P.lev[1].n + b_coupling + b_metric;
             break;
         }
         case IBPM_KERNEL_PCG_UPDATE_K: {
@@ -3401,12 +3436,15 @@ int ibpm_iteration_launches(const ibpm_ctx *cc, int32_t ncounts, int32_t *counts
             if (pre >= 2) k[IBPM_KERNEL_PRESMOOTH0] = 1;
         }
         // single sweeps on level 0: the pre-sweeps beyond the fused pair and
-        // every post-sweep (the last one also forms r . z)
-        k[IBPM_KERNEL_K0_JACOBI] = (pre >= 2 ? pre - 2 : pre) + post;
+        // every post-sweep (the last one also forms r . z), unless the
+        // prolongation and both post-sweeps go in one pass
+        const bool post_fused = post == 2 && post2_rows(P.K0) > 0;
+        k[IBPM_KERNEL_K0_JACOBI] = (pre >= 2 ? pre - 2 : pre) + (post_fused ? 0 : post);
         const DevLevelT<double> &l0 = P.lev[0];
         if (l0.RA.nrows == 0) k[IBPM_KERNEL_K0_RESIDUAL] = 1;
         k[IBPM_KERNEL_RESTRICT0] = 1;
-        k[IBPM_KERNEL_PROLONG0] = 1;
+        if (post_fused) k[IBPM_KERNEL_PROLONG_POST0] = 1;
+        else k[IBPM_KERNEL_PROLONG0] = 1;
         k[IBPM_KERNEL_COARSE_CYCLE] = 1;
         if (P.lc >= 2) {
             // the plain sweeps of level 1: the pre-sweeps beyond the fused

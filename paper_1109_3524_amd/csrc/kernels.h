@@ -261,6 +261,33 @@ void launch_k0_jacobi_first(hipStream_t s, const K0T<T> &K, double omega, const 
 template <class T>
 void launch_k0_jacobi(hipStream_t s, const K0T<T> &K, double omega, const T *b, const T *xin,
                       T *xout, const SolveStatus *st);
+// The prolongation and both post-smoothing sweeps of the level-0 V-cycle
+// (post = 2):  x' = a + P x1 (launch_k0_prolong_mf), y = x' + omega D^-1
+// (b - K x'), z = y + omega D^-1 (b - K y), as those three passes compute
+// them, cell for cell.  Away from the body it is one pass over strips of
+// post2_rows(K) rows of cells per block, each wave recomputing x' and y
+// three cells around its 58 columns; the cells within three of the box
+// coupled to the forces and the force rows, whose rows reach past any
+// strip, are done by three small passes over that box grown by 2, 1 and 0
+// more cells, through the level-0 work vectors tmp (x') and tmp2 (y).
+// a is only read.
+// mode 0: z in T and the partials of b . z; mode 1 (T = float): z widened to
+// z64 and the partials of r64 . z64; mode 2: z only.  Returns the number of
+// partials (the strip pass's, then the box pass's).
+enum { POST_RZ = 0, POST_WIDEN = 1, POST_PLAIN = 2 };
+// cells [i0, i1] x [j0, j1] of the level-0 grid (empty when i1 < i0)
+struct CellRect {
+    int i0, i1, j0, j1;
+};
+template <class T>
+int launch_k0_prolong_post2(hipStream_t s, const K0T<T> &K, const int *agg, const T *x1, double pw,
+                            double omega, const T *b, const T *a, T *tmp, T *tmp2, T *z, double *z64,
+                            const double *r64, const SolveStatus *st, double *parts, int mode);
+// rows of cells per block of that pass on this grid (8, 16 or 32); 0 when
+// the pass is off for it (IBPM_POST_FUSE=0, or a grid below 2^22 cells
+// unless IBPM_POST_FUSE=1; IBPM_POST_ROWS forces the depth)
+template <class T>
+int post2_rows(const K0T<T> &K);
 // last post-sweep; per-block partials of b . xout in parts (no finalize:
 // the next product kernel sums them); returns the number of partials
 template <class T>

@@ -16,8 +16,10 @@
 // accumulate in double.
 #include "kernels.h"
 
+#include <algorithm>
 #include <cstdlib>
 #include <stdexcept>
+#include <type_traits>
 
 namespace ibpm {
 
@@ -376,6 +378,39 @@ __device__ __forceinline__ void k0_tile_lds(const K0T<T> &K, int i, int j0, XV x
     }
 }
 
+// The rows of K with stored entries, for block b of the bands at the start
+// of a walker's grid: the force rows (blocks below force_blocks), then the
+// coupled cells, 8 lanes per row.
+template <class T, class XV, class PF, class ACT>
+__device__ __forceinline__ void k0_band_rows(const K0T<T> &K, int b, XV xv, PF pf, ACT act) {
+    const GridT<T> &g = K.g;
+    const int nx = g.nx;
+    const int fbk = force_blocks(K);
+    if (b < fbk) {
+        // force rows
+        const int t = b * kBlock + threadIdx.x;
+        const int fr = t / kForceLanes, lane = t % kForceLanes;
+        const bool live = fr < 2 * K.nb;
+        const T y = band_row_sum<kKfW>(live, fr, lane, K.kf_ell, K.kfe_col, K.kfe_val, K.kf, fr, 0, xv);
+        if (live && lane == 0) act(g.n_cell + fr, y, K.kf_diag[fr], xv(g.n_cell + fr), pf(g.n_cell + fr));
+    } else {
+        // coupled cells: the stencil (every lane forms it, so its loads go
+        // out with the coupling slots) plus the force coupling
+        if (K.ncc == 0) return;
+        const int t = (b - fbk) * kBlock + threadIdx.x;
+        const int q = t / kForceLanes, lane = t % kForceLanes;
+        const bool live = q < K.ncc;
+        const int row = K.cc_row[live ? q : 0];
+        const int j = row / nx, i = row - j * nx;
+        T diag, xc;
+        const T ys = k0_cell_stencil(K, i, j, xv, diag, xc);
+        const int rb = (j - K.cb_j0) * (K.cb_i1 - K.cb_i0 + 1) + (i - K.cb_i0);
+        const T yc = band_row_sum<kCcW>(live, q, lane, K.cc_ell, K.cce_col, K.cce_val, K.cf, rb,
+                                        g.n_cell, xv);
+        if (live && lane == 0) act(row, row != K.pin ? ys + yc : ys, diag, xc, pf(row));
+    }
+}
+
 // Pressure and force rows of K = Q^T B^1 Q (pinned), precision T.
 // act(row, Kx, diag, x_row, pf(row)) is called once per row; pf(row) loads
 // what the action reads of the row besides x (before the tile's barrier).
@@ -384,7 +419,6 @@ __device__ __forceinline__ void k0_walk_pf(const K0T<T> &K, XV xv, PF pf, ACT ac
     const GridT<T> &g = K.g;
     const int nx = g.nx, ny = g.ny;
     const int band = k0_band(K);
-    const int fbk = force_blocks(K);
     const int b = (int)blockIdx.x;
     if (b >= band) {
         // tile of 256 columns x R rows; the tiles of one XCD are contiguous in
@@ -419,28 +453,8 @@ __device__ __forceinline__ void k0_walk_pf(const K0T<T> &K, XV xv, PF pf, ACT ac
                 act(j * nx + i, y, diag, xc, pf(j * nx + i));
             }
         }
-    } else if (b < fbk) {
-        // force rows
-        const int t = b * kBlock + threadIdx.x;
-        const int fr = t / kForceLanes, lane = t % kForceLanes;
-        const bool live = fr < 2 * K.nb;
-        const T y = band_row_sum<kKfW>(live, fr, lane, K.kf_ell, K.kfe_col, K.kfe_val, K.kf, fr, 0, xv);
-        if (live && lane == 0) act(g.n_cell + fr, y, K.kf_diag[fr], xv(g.n_cell + fr), pf(g.n_cell + fr));
     } else {
-        // coupled cells: the stencil (every lane forms it, so its loads go
-        // out with the coupling slots) plus the force coupling
-        if (K.ncc == 0) return;
-        const int t = (b - fbk) * kBlock + threadIdx.x;
-        const int q = t / kForceLanes, lane = t % kForceLanes;
-        const bool live = q < K.ncc;
-        const int row = K.cc_row[live ? q : 0];
-        const int j = row / nx, i = row - j * nx;
-        T diag, xc;
-        const T ys = k0_cell_stencil(K, i, j, xv, diag, xc);
-        const int rb = (j - K.cb_j0) * (K.cb_i1 - K.cb_i0 + 1) + (i - K.cb_i0);
-        const T yc = band_row_sum<kCcW>(live, q, lane, K.cc_ell, K.cce_col, K.cce_val, K.cf, rb,
-                                        g.n_cell, xv);
-        if (live && lane == 0) act(row, row != K.pin ? ys + yc : ys, diag, xc, pf(row));
+        k0_band_rows<T>(K, b, xv, pf, act);
     }
 }
 
@@ -1124,6 +1138,293 @@ __global__ __launch_bounds__(kBlock) void k_k0_residual(K0T<T> K, const T *__res
     if (st->done) return;
     k0_walk_pf<R>(K, [&](int c) { return x[c]; }, [&](int row) { return b[row]; },
                   [&](int row, T ax, T, T, T br) { r[row] = br - ax; });
+}
+
+// --- prolongation and the two post-smoothing sweeps in one pass ----------
+//
+// Strips: a wave takes 64 columns of cells (58 written, 3 recomputed on
+// either side) and walks the RF rows of its block plus 3 above and below.
+// At the step that brings in row jw it forms x' at row jw-1, y at row jw-2
+// and z at row jw-3, each from the row above, the row itself and the row
+// below of the previous result (kept per lane) and its east / west values
+// (one lane over, by a cross-lane read): no LDS and no barrier.  The
+// arithmetic of every result is that of the three passes.  Cells of the
+// skipped box are left to the box passes; values the strip forms there (or
+// past the grid) are dropped, and a result is only written where all it
+// used lies outside the box coupled to the forces.
+
+constexpr int kPostHalo = 3;
+constexpr int kPostCols = 64 - 2 * kPostHalo;   // written columns of a wave
+constexpr int kPostBlockCols = 4 * kPostCols;   // of a block
+constexpr int kPostAhead = 3;                   // rows of operands in flight
+
+// 5-point part of the pressure row `row` (the pinned row and column
+// honoured), from the centre value and its south, west, east and north
+// neighbours, with the same association as the walkers
+template <class T>
+__device__ __forceinline__ T k0_row5(int row, int nx, int pin, T diag, T bs, T bw, T be, T bn, T xc,
+                                     T xs, T xw, T xe, T xn) {
+    T y = diag * xc;
+    if (row != pin) {
+        if (row - nx != pin) y -= bs * xs;
+        if (row - 1 != pin) y -= bw * xw;
+        if (row + 1 != pin) y -= be * xe;
+        if (row + nx != pin) y -= bn * xn;
+    }
+    return y;
+}
+
+// coefficients of the pressure row of cell (column with dxi, cw, ce; row j)
+template <class T>
+struct Row5 {
+    T bs, bw, be, bn, diag;
+};
+template <class T>
+__device__ __forceinline__ Row5<T> k0_coef(const GridT<T> &g, T dt, T dxi, T cw, T ce, int j) {
+    Row5<T> c;
+    const T dyj = g.dy[j];
+    c.bw = cw * dyj;
+    c.be = ce * dyj;
+    c.bs = j > 0 ? dt * dxi * g.iDy[j] : T(0);
+    c.bn = j < g.ny - 1 ? dt * dxi * g.iDy[j + 1] : T(0);
+    c.diag = ((c.bw + c.be) + c.bs) + c.bn;
+    return c;
+}
+
+__device__ __forceinline__ bool in_rect(const CellRect &r, int i, int j) {
+    return i >= r.i0 && i <= r.i1 && j >= r.j0 && j <= r.j1;
+}
+
+// value of lane k (uniform k) of v
+__device__ __forceinline__ double lane_value(double v, int k) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, k);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), k);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float lane_value(float v, int k) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
+}
+
+template <int RF, int MODE, class T>
+__global__ __launch_bounds__(kBlock) void k_k0_prolong_post2(
+    K0T<T> K, CellRect skip, const int *__restrict__ agg, const T *__restrict__ x1, T pw, T omega,
+    const T *__restrict__ b, const T *__restrict__ a, T *__restrict__ z, double *__restrict__ z64,
+    const double *__restrict__ r64, const SolveStatus *st, double *parts) {
+    constexpr int NS = RF + 2 * kPostHalo;       // rows walked
+    constexpr int D = kPostAhead;
+    static_assert(NS + 1 <= 64, "the row metrics of a walk are held one row per lane");
+    if (st->done) return;
+    const GridT<T> &g = K.g;
+    const int nx = g.nx, ny = g.ny, pin = K.pin;
+    const int ncs = (nx + kPostBlockCols - 1) / kPostBlockCols;
+    const int w = remap_block(blockIdx.x, gridDim.x);
+    const int cy = w / ncs, cx = w - cy * ncs;
+    const int lane = threadIdx.x & 63;
+    const int i = cx * kPostBlockCols + (threadIdx.x >> 6) * kPostCols - kPostHalo + lane;
+    const int j0 = cy * RF;
+    const int jt = j0 - kPostHalo;               // row of walk step 0
+    const bool cin = i >= 0 && i < nx;
+    const int ic = cin ? i : (i < 0 ? 0 : nx - 1);
+    const T dt = K.dt;
+    const T dxi = g.dx[ic];
+    const T cw = (cin && i > 0) ? dt * g.iDx[ic] : T(0);
+    const T ce = (cin && i < nx - 1) ? dt * g.iDx[ic + 1] : T(0);
+    const T cs = dt * dxi;
+    const bool wcol = cin && lane >= kPostHalo && lane < 64 - kPostHalo;
+    // lane k holds dy and iDy of walk row k (clamped to the grid)
+    T dyl, iyl;
+    {
+        const int jl = jt + lane;
+        dyl = g.dy[jl < 0 ? 0 : (jl > ny - 1 ? ny - 1 : jl)];
+        iyl = g.iDy[jl < 0 ? 0 : (jl > ny ? ny : jl)];
+    }
+    // Operand loads are unconditional, from the clamped cell, and zeroed
+    // where they are used, so that no branch or copy makes a step wait for
+    // loads still in flight: slot s % D holds the operands of walk row s,
+    // issued D steps ahead, and the aggregates D steps before that.
+    auto live = [&](int sr) { return cin && jt + sr >= 0 && jt + sr < ny; };
+    auto rix = [&](int sr) {
+        const int jr = jt + sr;
+        return (jr < 0 ? 0 : (jr > ny - 1 ? ny - 1 : jr)) * nx + ic;
+    };
+    constexpr bool widen = MODE == POST_WIDEN;
+    T ft[D], fa[D], fb[D];
+    double fr[D];                                // widen: the FP64 residual
+    int fg[D];
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+        const int rw = rix(k);
+        ft[k] = x1[agg[rw]];
+        fa[k] = a[rw];
+        fb[k] = b[rw];
+        fr[k] = widen ? r64[rw] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < D; ++k) fg[k] = agg[rix(D + k)];
+    // per lane: t at rows jw-2, jw-1; a at jw-1; b at jw-1..jw-3; x' at
+    // jw-2, jw-3; y at jw-3, jw-4 (zero outside the grid); the diagonal and
+    // omega / diagonal of rows jw-2 and jw-3
+    T tm2 = T(0), tm1 = T(0), am1 = T(0), bm1 = T(0), bm2 = T(0), bm3 = T(0);
+    T pm2 = T(0), pm3 = T(0), qm3 = T(0), qm4 = T(0);
+    T d2 = T(1), d3 = T(1), o2 = T(0), o3 = T(0);
+    double rm1 = 0.0, rm2 = 0.0, rm3 = 0.0;     // widen: r64 at rows jw-1..jw-3
+    double v = 0.0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int jw = jt + s;
+        const int sl = s % D;
+        const bool ls = live(s);
+        const T t0 = ls ? ft[sl] : T(0), a0 = ls ? fa[sl] : T(0), b0 = ls ? fb[sl] : T(0);
+        const double r0 = widen ? fr[sl] : 0.0;
+        if (s + D < NS) {
+            const int rw = rix(s + D);
+            ft[sl] = x1[fg[sl]];
+            fa[sl] = a[rw];
+            fb[sl] = b[rw];
+            if (widen) fr[sl] = r64[rw];
+            if (s + 2 * D < NS) fg[sl] = agg[rix(s + 2 * D)];
+        }
+        const T tw = __shfl_up(tm1, 1, 64), te = __shfl_down(tm1, 1, 64);
+        const T pwv = __shfl_up(pm2, 1, 64), pev = __shfl_down(pm2, 1, 64);
+        const T qw = __shfl_up(qm3, 1, 64), qe = __shfl_down(qm3, 1, 64);
+        // coefficients of walk row s - 1 (the walkers' association) and of
+        // rows s - 2, s - 3 (their diagonals kept from earlier steps)
+        auto coef = [&](int k, T &bs, T &bw, T &be, T &bn) {
+            const int j = jt + k;
+            const T dyj = lane_value(dyl, k);
+            bw = cw * dyj;
+            be = ce * dyj;
+            bs = j > 0 ? cs * lane_value(iyl, k) : T(0);
+            bn = j < ny - 1 ? cs * lane_value(iyl, k + 1) : T(0);
+        };
+        T p1 = T(0), d1 = T(1), o1 = T(0);
+        if (s >= 1) {
+            // x' = a + (t - pw (K t) / d) at row jw - 1
+            T bs, bw, be, bn;
+            coef(s - 1, bs, bw, be, bn);
+            d1 = ((bw + be) + bs) + bn;
+            o1 = omega / d1;
+            const int j = jw - 1;
+            const T kt = k0_row5(j * nx + i, nx, pin, d1, bs, bw, be, bn, tm1, tm2, tw, te, t0);
+            const T pv = am1 + (tm1 - pw * (kt / d1));
+            p1 = (cin && j >= 0 && j < ny) ? pv : T(0);
+        }
+        T q1 = T(0);
+        if (s >= 2) {
+            // y = x' + omega / d (b - K x') at row jw - 2
+            T bs, bw, be, bn;
+            coef(s - 2, bs, bw, be, bn);
+            const int j = jw - 2;
+            const T kp = k0_row5(j * nx + i, nx, pin, d2, bs, bw, be, bn, pm2, pm3, pwv, pev, p1);
+            const T qv = pm2 + o2 * (bm2 - kp);
+            q1 = (cin && j >= 0 && j < ny) ? qv : T(0);
+        }
+        if (s >= 3) {
+            // z = y + omega / d (b - K y) at row jw - 3, written in the strip
+            const int j = jw - 3;
+            if (j >= j0 && wcol && j < ny && !in_rect(skip, i, j)) {
+                T bs, bw, be, bn;
+                coef(s - 3, bs, bw, be, bn);
+                const int row = j * nx + i;
+                const T kq = k0_row5(row, nx, pin, d3, bs, bw, be, bn, qm3, qm4, qw, qe, q1);
+                const T zz = qm3 + o3 * (bm3 - kq);
+                if constexpr (MODE == POST_WIDEN) {
+                    const double zd = (double)zz;
+                    z64[row] = zd;
+                    v += rm3 * zd;
+                } else {
+                    z[row] = zz;
+                    if constexpr (MODE == POST_RZ) v += (double)bm3 * (double)zz;
+                }
+            }
+        }
+        rm3 = rm2;
+        rm2 = rm1;
+        rm1 = r0;
+        tm2 = tm1;
+        tm1 = t0;
+        am1 = a0;
+        bm3 = bm2;
+        bm2 = bm1;
+        bm1 = b0;
+        pm3 = pm2;
+        pm2 = p1;
+        qm4 = qm3;
+        qm3 = q1;
+        d3 = d2;
+        d2 = d1;
+        o3 = o2;
+        o2 = o1;
+    }
+    if constexpr (MODE != POST_PLAIN) {
+        double vv[1] = {v};
+        write_parts2<1>(vv, parts);
+    }
+}
+
+// The level-0 rows of a rectangle of cells (one thread per cell; coupled
+// cells are left to the band) and the band rows.
+template <class T, class XV, class PF, class ACT>
+__device__ __forceinline__ void k0_walk_rect(const K0T<T> &K, CellRect rc, XV xv, PF pf, ACT act) {
+    const int band = k0_band(K);
+    const int b = (int)blockIdx.x;
+    if (b < band) {
+        k0_band_rows<T>(K, b, xv, pf, act);
+        return;
+    }
+    const int wdt = rc.i1 - rc.i0 + 1;
+    const int idx = (b - band) * kBlock + threadIdx.x;
+    if (wdt <= 0 || idx >= wdt * (rc.j1 - rc.j0 + 1)) return;
+    const int j = rc.j0 + idx / wdt, i = rc.i0 + idx % wdt;
+    if (k0_coupled(K, i, j)) return;
+    T diag, xc;
+    const T y = k0_cell_stencil(K, i, j, xv, diag, xc);
+    const int row = j * K.g.nx + i;
+    act(row, y, diag, xc, pf(row));
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_k0_prolong_rect(K0T<T> K, CellRect rc, const int *__restrict__ agg,
+                                                            const T *__restrict__ x1, T w,
+                                                            const T *__restrict__ a, T *__restrict__ ap,
+                                                            const SolveStatus *st) {
+    if (st->done) return;
+    k0_walk_rect(K, rc, [&](int c) { return x1[agg[c]]; }, [&](int row) { return a[row]; },
+                 [&](int row, T kt, T d, T t, T ar) { ap[row] = ar + (t - w * (kt / d)); });
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi_rect(K0T<T> K, CellRect rc, T omega,
+                                                           const T *__restrict__ b, const T *__restrict__ xin,
+                                                           T *__restrict__ xout, const SolveStatus *st) {
+    if (st->done) return;
+    k0_walk_rect(K, rc, [&](int c) { return xin[c]; }, [&](int row) { return b[row]; },
+                 [&](int row, T ax, T d, T xr, T br) { xout[row] = xr + omega / d * (br - ax); });
+}
+
+template <int MODE, class T>
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi_last_rect(K0T<T> K, CellRect rc, T omega,
+                                                                const T *__restrict__ b,
+                                                                const T *__restrict__ xin, T *__restrict__ z,
+                                                                double *__restrict__ z64,
+                                                                const double *__restrict__ r64,
+                                                                const SolveStatus *st, double *parts) {
+    if (st->done) return;
+    double v[1] = {0.0};
+    k0_walk_rect(K, rc, [&](int c) { return xin[c]; }, [&](int row) { return b[row]; },
+                 [&](int row, T ax, T d, T xr, T br) {
+                     const T zz = xr + omega / d * (br - ax);
+                     if constexpr (MODE == POST_WIDEN) {
+                         const double zd = (double)zz;
+                         z64[row] = zd;
+                         v[0] += r64[row] * zd;
+                     } else {
+                         z[row] = zz;
+                         if constexpr (MODE == POST_RZ) v[0] += (double)br * (double)zz;
+                     }
+                 });
+    if constexpr (MODE != POST_PLAIN) write_parts2<1>(v, parts);
 }
 
 // mixed precision outer loop: r = b - K x in FP64, r32 = (float) r, ||r||^2, ||b||^2
@@ -2352,6 +2653,94 @@ int launch_k0_jacobi_rz(hipStream_t s, const K0T<T> &K, double omega, const T *b
 }
 
 template <class T>
+int post2_rows(const K0T<T> &K) {
+    // read at every call (the calls are queued once per recorded graph)
+    const char *ef = std::getenv("IBPM_POST_FUSE");
+    const int fuse = ef ? std::atoi(ef) : -1;
+    const char *er = std::getenv("IBPM_POST_ROWS");
+    const int rr = er ? std::atoi(er) : 0;
+    const int forced = (rr == 8 || rr == 16 || rr == 32) ? rr : 0;
+    // on by default from 2^22 cells: below that the three small box passes
+    // (about 18 us, mostly latency) outweigh what the one pass saves
+    if (fuse == 0 || (fuse < 0 && (long)K.g.nx * K.g.ny < (1L << 22))) return 0;
+    if (forced) return forced;
+    // the deepest strips that still give every CU four blocks
+    const long ncs = (K.g.nx + kPostBlockCols - 1) / kPostBlockCols;
+    for (int rf : {32, 16})
+        if (ncs * ((K.g.ny + rf - 1) / rf) >= 1024) return rf;
+    return 8;
+}
+
+// the box coupled to the forces grown by m cells, clipped to the grid
+// (empty without a body)
+template <class T>
+static CellRect grown_box(const K0T<T> &K, int m) {
+    if (K.nb == 0 || K.cb_i1 < K.cb_i0 || K.cb_j1 < K.cb_j0) return CellRect{0, -1, 0, -1};
+    return CellRect{std::max(K.cb_i0 - m, 0), std::min(K.cb_i1 + m, K.g.nx - 1), std::max(K.cb_j0 - m, 0),
+                    std::min(K.cb_j1 + m, K.g.ny - 1)};
+}
+
+template <class T>
+static int rect_blocks(const K0T<T> &K, const CellRect &r) {
+    const long cells = r.i1 < r.i0 ? 0L : (long)(r.i1 - r.i0 + 1) * (r.j1 - r.j0 + 1);
+    return k0_band(K) + (int)((cells + kBlock - 1) / kBlock);
+}
+
+template <class T>
+int launch_k0_prolong_post2(hipStream_t s, const K0T<T> &K, const int *agg, const T *x1, double pw,
+                            double omega, const T *b, const T *a, T *tmp, T *tmp2, T *z, double *z64,
+                            const double *r64, const SolveStatus *st, double *parts, int mode) {
+    const int RF = post2_rows(K);
+    if (RF == 0) throw std::runtime_error("prolongation + post-smoothing pass: off for this grid");
+    if (mode == POST_WIDEN && !std::is_same<T, float>::value)
+        throw std::runtime_error("prolongation + post-smoothing pass: widening needs the FP32 cycle");
+    if (a == tmp || a == tmp2 || tmp == tmp2 || (z && (a == z || tmp == z || tmp2 == z)))
+        throw std::runtime_error("prolongation + post-smoothing pass: buffers must differ");
+    const CellRect skip = grown_box(K, kPostHalo), r1 = grown_box(K, kPostHalo + 1),
+                   r2 = grown_box(K, kPostHalo + 2);
+    const int ncs = (K.g.nx + kPostBlockCols - 1) / kPostBlockCols;
+    const int Gf = ncs * ((K.g.ny + RF - 1) / RF);
+    const int Gb = rect_blocks(K, skip);
+    if (Gf + Gb > kMaxParts) throw std::runtime_error("prolongation + post-smoothing pass: grid too large");
+    const T tw = (T)pw, to = (T)omega;
+    // The box passes read a, x1 and b and write tmp, tmp2, z on the box and
+    // the force rows and their own partials; the strips read the same and
+    // write z elsewhere.
+    const int G1 = rect_blocks(K, r1), G2 = rect_blocks(K, r2);
+    auto box = [&](hipStream_t q) {
+        // x' on the box grown by 5 and the force rows, y on it grown by 4,
+        // then z on it grown by 3
+        if (G2 > 0) hipLaunchKernelGGL((k_k0_prolong_rect<T>), dim3(G2), dim3(kBlock), 0, q, K, r2, agg, x1, tw, a, tmp, st);
+        if (G1 > 0) hipLaunchKernelGGL((k_k0_jacobi_rect<T>), dim3(G1), dim3(kBlock), 0, q, K, r1, to, b, (const T *)tmp, tmp2, st);
+        if (Gb > 0) {
+            double *pb = parts + Gf;
+            if (mode == POST_RZ)
+                hipLaunchKernelGGL((k_k0_jacobi_last_rect<POST_RZ, T>), dim3(Gb), dim3(kBlock), 0, q, K, skip, to, b,
+                                   (const T *)tmp2, z, z64, r64, st, pb);
+            else if (mode == POST_PLAIN)
+                hipLaunchKernelGGL((k_k0_jacobi_last_rect<POST_PLAIN, T>), dim3(Gb), dim3(kBlock), 0, q, K, skip, to, b,
+                                   (const T *)tmp2, z, z64, r64, st, pb);
+            else if constexpr (std::is_same<T, float>::value)
+                hipLaunchKernelGGL((k_k0_jacobi_last_rect<POST_WIDEN, T>), dim3(Gb), dim3(kBlock), 0, q, K, skip, to, b,
+                                   (const T *)tmp2, z, z64, r64, st, pb);
+        }
+    };
+    box(s);
+#define POST_STRIPS(RFV, MODEV)                                                                   \
+    LAUNCH((k_k0_prolong_post2<RFV, MODEV, T>), Gf, K, skip, agg, x1, tw, to, b, a, z, z64, r64, st, parts)
+#define POST_MODES(RFV)                                                                           \
+    if (mode == POST_RZ) POST_STRIPS(RFV, POST_RZ);                                                \
+    else if (mode == POST_PLAIN) POST_STRIPS(RFV, POST_PLAIN);                                     \
+    else if constexpr (std::is_same<T, float>::value) POST_STRIPS(RFV, POST_WIDEN);
+    if (RF == 8) { POST_MODES(8) }
+    else if (RF == 16) { POST_MODES(16) }
+    else { POST_MODES(32) }
+#undef POST_MODES
+#undef POST_STRIPS
+    return mode == POST_PLAIN ? 0 : Gf + Gb;
+}
+
+template <class T>
 void launch_k0_residual(hipStream_t s, const K0T<T> &K, const T *b, const T *x, T *r,
                         const SolveStatus *st) {
     WALK_SWITCH(pick_R(K), LAUNCH2((k_k0_residual<RR, T>), op_grid<RR>(K), K, b, x, r, st))
@@ -2607,6 +2996,11 @@ INST_OP(CsrOpView, double)
                                         const T *, T *, SolveStatus *, double *);                \
     template void launch_k0_residual<T>(hipStream_t, const K0T<T> &, const T *, const T *, T *,  \
                                         const SolveStatus *);                                    \
+    template int launch_k0_prolong_post2<T>(hipStream_t, const K0T<T> &, const int *, const T *,  \
+                                            double, double, const T *, const T *, T *, T *, T *,  \
+                                            double *, const double *, const SolveStatus *, double *, \
+                                            int);                                                 \
+    template int post2_rows<T>(const K0T<T> &);                                                  \
     template void launch_csr_jacobi_first<T>(hipStream_t, CSRT<T>, const T *, const T *, T *,    \
                                              const SolveStatus *);                               \
     template void launch_dense_solve<T>(hipStream_t, int, const double *, const T *, T *,        \

@@ -49,7 +49,7 @@ NN_SHAPES = [(32, 5), (32, 32), (32, 32), (32, 32), (32, 32), (3, 32)]   # (out,
 KERNELS = {"k0_jacobi": 0, "k0_pcg_spmv": 1, "a_pcg_spmv": 2, "k0_residual": 3,
            "restrict0": 4, "prolong0": 5, "pcg_update_k": 6, "coarse_cycle": 7,
            "presmooth0": 8, "stream_copy": 9, "update_presmooth0": 10, "l1_jacobi": 11,
-           "copy_level0": 12}
+           "copy_level0": 12, "prolong_post0": 13}
 
 
 class IBPMError(RuntimeError):
