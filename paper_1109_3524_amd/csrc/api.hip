@@ -49,7 +49,10 @@ struct DevCSRT {
     int64_t nnz = 0;
     int32_t *ptr = nullptr, *col = nullptr;
     T *val = nullptr;
-    CSRT<T> view() const { return CSRT<T>{nrows, ncols, ptr, col, val}; }
+    int32_t *bst = nullptr;            // row blocks of the row-block kernels (nblk + 1 row starts),
+    int rpb = 0;                       // or rpb rows each
+    int nblk = 0;
+    CSRT<T> view() const { return CSRT<T>{nrows, ncols, ptr, col, val, bst, rpb, nblk}; }
 };
 using DevCSR = DevCSRT<double>;
 
@@ -1501,38 +1504,72 @@ void fused_transfer_products(Hierarchy &h) {
 }
 
 // Upload the hierarchy in precision T (values converted from FP64)
-// Rows per block of the row-block CSR kernels for the matrices one kernel
-// walks together: the largest power of two up to 256 for which every
-// block's entries fit kStreamCap; 0 when a single row does not (then the
-// row-vector kernels run).  IBPM_CSR_STREAM=0 selects the row-vector kernels
-// everywhere.
-int stream_rows(std::initializer_list<const CSR *> ms) {
+// Row blocks of the row-block CSR kernels for the matrices one kernel walks
+// together.  The plain partition takes rpb rows per block, rpb the largest
+// power of two up to kBlock for which every block's entries (in all the
+// matrices) fit kStreamCap.  Where a few long rows force rpb far below what
+// the other rows allow (the force rows of the three-dimensional K: 16 rows
+// per block where 256 cell rows fit), the blocks are formed greedily
+// instead: runs of at most kBlock rows whose entries fit kStreamCap, each
+// as long as that allows; this is taken when it needs under half the
+// blocks (on the 96^3 K it halved the time of a solve; runs of at most 64
+// rows gained only half as much).  Returns the plain rows per block (and no
+// row starts: the kernels form them) or the greedy row starts (rpb 0).
+// Empty when a single row does not fit (then the row-vector kernels run),
+// or when IBPM_CSR_STREAM=0 selects the row-vector kernels everywhere.
+std::vector<int32_t> stream_blocks_of(std::initializer_list<const CSR *> ms, int &rpb_out) {
     static const bool off = [] {
         const char *e = std::getenv("IBPM_CSR_STREAM");
         return e && e[0] == '0';
     }();
-    if (off || ms.size() == 0) return 0;
+    std::vector<int32_t> bst;
+    rpb_out = 0;
+    if (off || ms.size() == 0) return bst;
     const int n = (*ms.begin())->nrows;
     for (const CSR *m : ms)
-        if (m->nrows != n || (int)m->ptr.size() != n + 1) return 0;
-    for (int rpb = 256; rpb >= 1; rpb /= 2) {
+        if (m->nrows != n || (int)m->ptr.size() != n + 1) return bst;
+    auto entries = [&](int r0, int r1) {
+        int64_t tot = 0;
+        for (const CSR *m : ms) tot += m->ptr[r1] - m->ptr[r0];
+        return tot;
+    };
+    int rpb = 0;
+    for (int r = kBlock; r >= 1 && rpb == 0; r /= 2) {
         bool ok = true;
-        for (int r0 = 0; r0 < n && ok; r0 += rpb) {
-            const int r1 = std::min(r0 + rpb, n);
-            int64_t tot = 0;
-            for (const CSR *m : ms) tot += m->ptr[r1] - m->ptr[r0];
-            ok = tot <= kStreamCap;
-        }
-        if (ok) return rpb;
+        for (int r0 = 0; r0 < n && ok; r0 += r) ok = entries(r0, std::min(r0 + r, n)) <= kStreamCap;
+        if (ok) rpb = r;
     }
-    return 0;
+    if (rpb == 0) return bst;
+    std::vector<int32_t> greedy{0};
+    for (int r0 = 0; r0 < n;) {
+        int r1 = r0;
+        while (r1 < n && r1 - r0 < kBlock && entries(r0, r1 + 1) <= kStreamCap) ++r1;
+        greedy.push_back(r1);
+        r0 = r1;
+    }
+    const int64_t plain = n > 0 ? ((int64_t)n + rpb - 1) / rpb : 1;
+    if (n > 0 && 2 * ((int64_t)greedy.size() - 1) < plain) return greedy;
+    rpb_out = rpb;
+    return bst;
 }
 
-// the launch shape of a CSR kernel: -rows per block for the row-block
-// kernels, else the lanes per row of the row-vector kernels
-int csr_shape(int lanes, std::initializer_list<const CSR *> ms) {
-    const int r = stream_rows(ms);
-    return r > 0 ? -r : lanes;
+// Give a device matrix the row-block shape for the matrices its kernels
+// walk (lanes = -1 and its row blocks), or keep its row-vector lanes.
+template <class T>
+void set_stream_shape(ibpm_ctx *c, DevCSRT<T> &d, std::initializer_list<const CSR *> ms) {
+    int rpb = 0;
+    std::vector<int32_t> bst = stream_blocks_of(ms, rpb);
+    if (rpb > 0) {
+        const int64_t nb = std::max<int64_t>(1, ((int64_t)d.nrows + rpb - 1) / rpb);
+        if (nb > kMaxParts) return;
+        d.rpb = rpb;
+        d.nblk = (int)nb;
+    } else {
+        if (bst.empty() || (int64_t)bst.size() - 1 > kMaxParts) return;
+        d.bst = c->upload(bst);
+        d.nblk = (int)bst.size() - 1;
+    }
+    d.lanes = -1;
 }
 
 template <class T>
@@ -1582,11 +1619,11 @@ void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
             dl.xb = c->dalloc<T>(dl.n);
             continue;
         }
-        if (dl.A.nrows > 0) dl.A.lanes = csr_shape(dl.A.lanes, {&hl.A});
-        if (dl.R.nrows > 0) dl.R.lanes = csr_shape(dl.R.lanes, {&hl.R});
-        if (dl.P.nrows > 0) dl.P.lanes = csr_shape(dl.P.lanes, {&hl.P});
-        if (dl.RA.nrows > 0) dl.RA.lanes = csr_shape(dl.RA.lanes, {&hl.R, &hl.RA});
-        if (dl.AP.nrows > 0) dl.AP.lanes = csr_shape(dl.AP.lanes, {&hl.A, &hl.AP, &hl.P});
+        if (dl.A.nrows > 0) set_stream_shape(c, dl.A, {&hl.A});
+        if (dl.R.nrows > 0) set_stream_shape(c, dl.R, {&hl.R});
+        if (dl.P.nrows > 0) set_stream_shape(c, dl.P, {&hl.P});
+        if (dl.RA.nrows > 0) set_stream_shape(c, dl.RA, {&hl.R, &hl.RA});
+        if (dl.AP.nrows > 0) set_stream_shape(c, dl.AP, {&hl.A, &hl.AP, &hl.P});
         dl.xa = c->dalloc<T>(dl.n);
         dl.xb = c->dalloc<T>(dl.n);
     }
@@ -2406,6 +2443,7 @@ CsrOpView stored_op(ibpm_ctx *c, const CSR &M, DevCSR &dev) {
     for (int32_t r = 0; r < M.nrows; ++r)
         for (int32_t q = M.ptr[r]; q < M.ptr[r + 1]; ++q)
             if (M.col[q] == r) d[r] = M.val[q];
+    set_stream_shape(c, dev, {&M});
     CsrOpView op{};
     op.A = dev.view();
     op.diag = c->upload(d);
@@ -2611,6 +2649,7 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
     if (c->bn > 1) {
         // the stored level-0 operator and its diagonal
         c->K0c = c->upload_csr<double>(m.K);
+        set_stream_shape(c, c->K0c, {&m.K});
         std::vector<double> dg((size_t)m.K.nrows, 0.0);
         for (int32_t r = 0; r < m.K.nrows; ++r)
             for (int32_t q = m.K.ptr[r]; q < m.K.ptr[r + 1]; ++q)
@@ -2626,6 +2665,9 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
         c->K0c.nrows = c->K0c.ncols = nl;
         c->K0c.nnz = nnz;
         c->K0c.lanes = lanes_for(nnz, nl);
+        c->K0c.bst = nullptr;
+        c->K0c.rpb = 0;
+        c->K0c.nblk = 0;
         c->K0c.ptr = c->upload(m.K.ptr);
         c->K0c.col = c->dalloc<int32_t>(c->K_cap);
         c->K0c.val = c->dalloc<double>(c->K_cap);
@@ -2633,7 +2675,7 @@ void build(ibpm_ctx *c, const ibpm_params *p) {
         HIPCHECK(hipMemcpy(c->K0c.val, m.K.val.data(), nnz * sizeof(double), hipMemcpyHostToDevice));
         c->K0diag = c->dalloc<double>(nl);
         c->K0op.A = c->K0c.view();
-        c->K0op.diag = c->K0diag;
+        c->K0op.diag = c->K0diag;   // no row blocks: its rows change with every move
     }
     if (c->amg) {
         upload_levels<double>(c, c->p64);

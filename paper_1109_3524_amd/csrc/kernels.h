@@ -59,6 +59,13 @@ struct CSRT {
     int nrows, ncols;
     const int32_t *ptr, *col;
     const T *val;
+    // the row blocks of the row-block kernels, nblk of them, each at most
+    // kBlock rows whose entries (of every matrix the kernel walks) fit
+    // kStreamCap: block k takes rows k rpb .. (k + 1) rpb - 1 (rpb > 0), or
+    // bst[k] .. bst[k + 1] - 1; neither where the matrix has no row blocks
+    const int32_t *bst = nullptr;
+    int rpb = 0;
+    int nblk = 0;
 };
 using CSRView = CSRT<double>;
 
@@ -103,7 +110,7 @@ using K0View = K0T<double>;
 // Poisson operator K = Q^T B^N Q when N > 1, its diagonal kept apart.
 template <class T>
 struct CsrOpT {
-    CSRT<T> A;
+    CSRT<T> A;   // with row blocks the Krylov kernels take them, else one row per thread
     const T *diag;
 };
 using CsrOpView = CsrOpT<double>;

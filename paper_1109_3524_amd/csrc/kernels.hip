@@ -754,11 +754,42 @@ inline dim3 op_grid(const K0T<T> &K) { return k0_grid<R>(K); }
 template <int R>
 inline dim3 op_grid(const AView &A) { return a_grid<R>(A); }
 
-// stored operator: one row per thread over the block's tiles (the walk
-// depth R does not apply), each row summed in column order
+// rows r0 .. r1 - 1 of row block bi of M
+template <class T>
+__device__ __forceinline__ void block_rows(const CSRT<T> &M, int bi, int &r0, int &r1) {
+    if (M.rpb > 0) {
+        r0 = bi * M.rpb;
+        r1 = min(r0 + M.rpb, M.nrows);
+    } else {
+        r0 = M.bst[bi];
+        r1 = M.bst[bi + 1];
+    }
+}
+
+// stored operator (the walk depth R does not apply): in its row blocks where
+// it has them, as the CSR levels' kernels take them (every load coalesced,
+// each row summed by the block's lanes), else one row per thread over the
+// block's tiles, each row summed in column order
 template <int R, class T, class XV, class ACT>
 __device__ __forceinline__ void op_walk(const CsrOpT<T> &op, XV xv, ACT act) {
     const int n = op.A.nrows;
+    if (op.A.nblk > 0) {
+        __shared__ T lds[kStreamCap];
+        int r0, r1;
+        block_rows(op.A, remap_block(blockIdx.x, gridDim.x), r0, r1);
+        const int base = op.A.ptr[r0], e = op.A.ptr[r1];
+        for (int k = base + (int)threadIdx.x; k < e; k += kBlock) lds[k - base] = op.A.val[k] * xv(op.A.col[k]);
+        __syncthreads();
+        int L = 64;
+        while (L > 1 && L * (r1 - r0) > kBlock) L >>= 1;
+        const int row = r0 + (int)threadIdx.x / L, sub = (int)threadIdx.x & (L - 1);
+        T sum = T(0);
+        if (row < r1)
+            for (int p = op.A.ptr[row] + sub; p < op.A.ptr[row + 1]; p += L) sum += lds[p - base];
+        for (int o = L >> 1; o > 0; o >>= 1) sum += __shfl_xor(sum, o, L);
+        if (row < r1 && sub == 0) act(row, sum, op.diag[row], xv(row));
+        return;
+    }
     const Tiles Tl = my_tiles(n);
     for (int t = Tl.t0; t < Tl.t1; ++t) {
         const int row = t * kBlock + threadIdx.x;
@@ -774,7 +805,10 @@ __device__ __forceinline__ T op_diag(const CsrOpT<T> &op, int r) { return op.dia
 template <class T>
 __host__ __device__ inline int op_n(const CsrOpT<T> &op) { return op.A.nrows; }
 template <int R, class T>
-inline dim3 op_grid(const CsrOpT<T> &op) { return dim3(grid_for(op.A.nrows)); }
+inline dim3 op_grid(const CsrOpT<T> &op) {
+    if (op.A.nblk > 0) return dim3(op.A.nblk);
+    return dim3(grid_for(op.A.nrows));
+}
 
 __device__ __forceinline__ int block_linear() { return blockIdx.y * gridDim.x + blockIdx.x; }
 
@@ -1905,14 +1939,15 @@ __global__ __launch_bounds__(kBlock) void k_csrv_prolong_jacobi(CSRT<T> A, CSRT<
 
 // ---------------------------------------------------------------------------
 // Stored-operator kernels in row blocks (the CSR levels of the V-cycle): a
-// block takes rpb consecutive rows, streams their entries -- all threads of
-// the block over one contiguous range of the value and column arrays, so
-// every load is coalesced -- multiplies each by the gathered operand into
-// LDS, and then sums each row with L = kBlock / rpb lanes (at most 64): lane
-// k adds the row's products k, k + L, ... and the lanes are combined by a
-// butterfly, so every thread of the block takes part whatever the row
-// length.  rpb is a power of two chosen on the host so that a block's
-// entries (of every matrix the kernel walks) fit in kStreamCap.
+// block takes a run of consecutive rows (its row block, formed on the host:
+// at most kBlock rows whose entries, of every matrix the kernel walks, fit
+// kStreamCap), streams their entries -- all threads of the block over one
+// contiguous range of the value and column arrays, so every load is
+// coalesced -- multiplies each by the gathered operand into LDS, and then
+// sums each row with L lanes, the largest power of two (at most 64) with L
+// times the block's rows within kBlock: lane k adds the row's products k,
+// k + L, ... and the lanes are combined by a butterfly, so every thread of
+// the block takes part whatever the row length.
 
 template <class T, class XV>
 __device__ __forceinline__ void stream_fill(const CSRT<T> &A, int r0, int r1, T *lds, XV xv) {
@@ -1926,9 +1961,10 @@ struct StreamLane {
     bool live;
 };
 
-__device__ __forceinline__ StreamLane stream_lane(int r0, int r1, int rpb) {
+__device__ __forceinline__ StreamLane stream_lane(int r0, int r1) {
     StreamLane sl;
-    sl.L = min(64, max(1, kBlock / rpb));
+    sl.L = 64;
+    while (sl.L > 1 && sl.L * (r1 - r0) > kBlock) sl.L >>= 1;
     sl.row = r0 + (int)threadIdx.x / sl.L;
     sl.sub = (int)threadIdx.x & (sl.L - 1);
     sl.live = sl.row < r1;
@@ -1948,65 +1984,61 @@ __device__ __forceinline__ T stream_row(const CSRT<T> &A, const StreamLane &sl, 
 }
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_csrs_jacobi(CSRT<T> A, int rpb, const T *__restrict__ wdinv,
+__global__ __launch_bounds__(kBlock) void k_csrs_jacobi(CSRT<T> A, const T *__restrict__ wdinv,
                                                         const T *__restrict__ b, const T *__restrict__ xin,
                                                         T *__restrict__ xout, const SolveStatus *st) {
     if (st->done) return;
     __shared__ T lds[kStreamCap];
-    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
-    if (r0 >= A.nrows) return;
-    const int r1 = min(r0 + rpb, A.nrows);
+    int r0, r1;
+    block_rows(A, remap_block(blockIdx.x, gridDim.x), r0, r1);
     stream_fill(A, r0, r1, lds, [&](int c) { return xin[c]; });
     __syncthreads();
-    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const StreamLane sl = stream_lane(r0, r1);
     const T ax = stream_row(A, sl, A.ptr[r0], lds);
     if (sl.live && sl.sub == 0) xout[sl.row] = xin[sl.row] + wdinv[sl.row] * (b[sl.row] - ax);
 }
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_csrs_residual(CSRT<T> A, int rpb, const T *__restrict__ b,
+__global__ __launch_bounds__(kBlock) void k_csrs_residual(CSRT<T> A, const T *__restrict__ b,
                                                           const T *__restrict__ x, T *__restrict__ r,
                                                           const SolveStatus *st) {
     if (st->done) return;
     __shared__ T lds[kStreamCap];
-    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
-    if (r0 >= A.nrows) return;
-    const int r1 = min(r0 + rpb, A.nrows);
+    int r0, r1;
+    block_rows(A, remap_block(blockIdx.x, gridDim.x), r0, r1);
     stream_fill(A, r0, r1, lds, [&](int c) { return x[c]; });
     __syncthreads();
-    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const StreamLane sl = stream_lane(r0, r1);
     const T ax = stream_row(A, sl, A.ptr[r0], lds);
     if (sl.live && sl.sub == 0) r[sl.row] = b[sl.row] - ax;
 }
 
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_csrs_spmv(CSRT<T> A, int rpb, const T *__restrict__ x,
+__global__ __launch_bounds__(kBlock) void k_csrs_spmv(CSRT<T> A, const T *__restrict__ x,
                                                       T *__restrict__ y, int add, const SolveStatus *st) {
     if (st && st->done) return;
     __shared__ T lds[kStreamCap];
-    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
-    if (r0 >= A.nrows) return;
-    const int r1 = min(r0 + rpb, A.nrows);
+    int r0, r1;
+    block_rows(A, remap_block(blockIdx.x, gridDim.x), r0, r1);
     stream_fill(A, r0, r1, lds, [&](int c) { return x[c]; });
     __syncthreads();
-    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const StreamLane sl = stream_lane(r0, r1);
     const T v = stream_row(A, sl, A.ptr[r0], lds);
     if (sl.live && sl.sub == 0) y[sl.row] = add ? y[sl.row] + v : v;
 }
 
 // the first two damped-Jacobi sweeps from zero: x = y + W (b - A y), y = W b
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_csrs_presmooth2(CSRT<T> A, int rpb, const T *__restrict__ wdinv,
+__global__ __launch_bounds__(kBlock) void k_csrs_presmooth2(CSRT<T> A, const T *__restrict__ wdinv,
                                                             const T *__restrict__ b, T *__restrict__ x,
                                                             const SolveStatus *st) {
     if (st->done) return;
     __shared__ T lds[kStreamCap];
-    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
-    if (r0 >= A.nrows) return;
-    const int r1 = min(r0 + rpb, A.nrows);
+    int r0, r1;
+    block_rows(A, remap_block(blockIdx.x, gridDim.x), r0, r1);
     stream_fill(A, r0, r1, lds, [&](int c) { return wdinv[c] * b[c]; });
     __syncthreads();
-    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const StreamLane sl = stream_lane(r0, r1);
     const T ay = stream_row(A, sl, A.ptr[r0], lds);
     if (sl.live && sl.sub == 0) {
         const T w = wdinv[sl.row], bi = b[sl.row];
@@ -2016,19 +2048,18 @@ __global__ __launch_bounds__(kBlock) void k_csrs_presmooth2(CSRT<T> A, int rpb, 
 
 // b_c = R b - (R A) x: the block's entries of R, then of R A, in one buffer
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_csrs_restrict(CSRT<T> R, CSRT<T> RA, int rpb, const T *__restrict__ b,
+__global__ __launch_bounds__(kBlock) void k_csrs_restrict(CSRT<T> R, CSRT<T> RA, const T *__restrict__ b,
                                                           const T *__restrict__ x, T *__restrict__ bc,
                                                           const SolveStatus *st) {
     if (st->done) return;
     __shared__ T lds[kStreamCap];
-    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
-    if (r0 >= R.nrows) return;
-    const int r1 = min(r0 + rpb, R.nrows);
+    int r0, r1;
+    block_rows(RA, remap_block(blockIdx.x, gridDim.x), r0, r1);
     const int nr = R.ptr[r1] - R.ptr[r0];
     stream_fill(R, r0, r1, lds, [&](int c) { return b[c]; });
     stream_fill(RA, r0, r1, lds + nr, [&](int c) { return x[c]; });
     __syncthreads();
-    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const StreamLane sl = stream_lane(r0, r1);
     const T rb = stream_row(R, sl, R.ptr[r0], lds);
     const T rax = stream_row(RA, sl, RA.ptr[r0], lds + nr);
     if (sl.live && sl.sub == 0) bc[sl.row] = rb - rax;
@@ -2036,7 +2067,7 @@ __global__ __launch_bounds__(kBlock) void k_csrs_restrict(CSRT<T> R, CSRT<T> RA,
 
 // x_out = x + P e + W (b - A x - (A P) e): entries of A, A P and P in turn
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_csrs_prolong_jacobi(CSRT<T> A, CSRT<T> AP, CSRT<T> P, int rpb,
+__global__ __launch_bounds__(kBlock) void k_csrs_prolong_jacobi(CSRT<T> A, CSRT<T> AP, CSRT<T> P,
                                                                 const T *__restrict__ wdinv,
                                                                 const T *__restrict__ b,
                                                                 const T *__restrict__ x,
@@ -2045,15 +2076,14 @@ __global__ __launch_bounds__(kBlock) void k_csrs_prolong_jacobi(CSRT<T> A, CSRT<
                                                                 const SolveStatus *st) {
     if (st->done) return;
     __shared__ T lds[kStreamCap];
-    const int r0 = remap_block(blockIdx.x, gridDim.x) * rpb;
-    if (r0 >= A.nrows) return;
-    const int r1 = min(r0 + rpb, A.nrows);
+    int r0, r1;
+    block_rows(A, remap_block(blockIdx.x, gridDim.x), r0, r1);
     const int na = A.ptr[r1] - A.ptr[r0], nq = AP.ptr[r1] - AP.ptr[r0];
     stream_fill(A, r0, r1, lds, [&](int c) { return x[c]; });
     stream_fill(AP, r0, r1, lds + na, [&](int c) { return e[c]; });
     stream_fill(P, r0, r1, lds + na + nq, [&](int c) { return e[c]; });
     __syncthreads();
-    const StreamLane sl = stream_lane(r0, r1, rpb);
+    const StreamLane sl = stream_lane(r0, r1);
     const T sa = stream_row(A, sl, A.ptr[r0], lds), sq = stream_row(AP, sl, AP.ptr[r0], lds + na);
     const T sp = stream_row(P, sl, P.ptr[r0], lds + na + nq);
     if (sl.live && sl.sub == 0) {
@@ -2808,16 +2838,18 @@ static void csrv_dispatch_presmooth2(hipStream_t s, CSRT<T> A, const T *wdinv, c
     LAUNCH((k_csrv_presmooth2<T, L>), nb > 0 ? nb : 1, A, wdinv, b, x, st);
 }
 // `lanes` > 0: the row-vector kernels with that many lanes per row;
-// `lanes` < 0: the row-block kernels with -lanes rows per block
-inline int stream_blocks(int nrows, int rpb) {
-    const int nb = (nrows + rpb - 1) / rpb;
-    return nb > 0 ? nb : 1;
+// `lanes` < 0: the row-block kernels over the row blocks of the shape's
+// matrix (A, or R A and A P for the fused transfers)
+template <class T>
+static void need_blocks(const CSRT<T> &M) {
+    if ((!M.bst && M.rpb < 1) || M.nblk < 1) throw std::runtime_error("row-block CSR kernel: the matrix has no row blocks");
 }
 template <class T>
 void launch_csrv_presmooth2(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b, T *x,
                             const SolveStatus *st) {
     if (lanes < 0) {
-        LAUNCH((k_csrs_presmooth2<T>), stream_blocks(A.nrows, -lanes), A, -lanes, wdinv, b, x, st);
+        need_blocks(A);
+        LAUNCH((k_csrs_presmooth2<T>), A.nblk, A, wdinv, b, x, st);
         return;
     }
     CSRV_SWITCH(csrv_dispatch_presmooth2, A, wdinv, b, x, st)
@@ -2827,7 +2859,8 @@ void launch_csrv_restrict(hipStream_t s, CSRT<T> R, CSRT<T> RA, int lanes, const
                           const SolveStatus *st) {
     if (R.nrows != RA.nrows) throw std::runtime_error("fused restriction: R and R A differ in rows");
     if (lanes < 0) {
-        LAUNCH((k_csrs_restrict<T>), stream_blocks(R.nrows, -lanes), R, RA, -lanes, b, x, bc, st);
+        need_blocks(RA);
+        LAUNCH((k_csrs_restrict<T>), RA.nblk, R, RA, b, x, bc, st);
         return;
     }
     CSRV_SWITCH(csrv_dispatch_restrict, R, RA, b, x, bc, st)
@@ -2839,8 +2872,13 @@ void launch_csrv_prolong_jacobi(hipStream_t s, CSRT<T> A, CSRT<T> AP, CSRT<T> P,
     if (A.nrows != AP.nrows || A.nrows != P.nrows || AP.ncols != P.ncols)
         throw std::runtime_error("fused prolongation: A, A P and P do not match");
     if (lanes < 0) {
-        LAUNCH((k_csrs_prolong_jacobi<T>), stream_blocks(A.nrows, -lanes), A, AP, P, -lanes, wdinv, b, x, e,
-               xout, st);
+        // the blocks of A P's shape (formed over A, A P and P together)
+        need_blocks(AP);
+        CSRT<T> Ab = A;
+        Ab.bst = AP.bst;
+        Ab.rpb = AP.rpb;
+        Ab.nblk = AP.nblk;
+        LAUNCH((k_csrs_prolong_jacobi<T>), AP.nblk, Ab, AP, P, wdinv, b, x, e, xout, st);
         return;
     }
     CSRV_SWITCH(csrv_dispatch_prolong_jacobi, A, AP, P, wdinv, b, x, e, xout, st)
@@ -2849,7 +2887,8 @@ template <class T>
 void launch_csrv_jacobi(hipStream_t s, CSRT<T> A, int lanes, const T *wdinv, const T *b,
                         const T *xin, T *xout, const SolveStatus *st) {
     if (lanes < 0) {
-        LAUNCH((k_csrs_jacobi<T>), stream_blocks(A.nrows, -lanes), A, -lanes, wdinv, b, xin, xout, st);
+        need_blocks(A);
+        LAUNCH((k_csrs_jacobi<T>), A.nblk, A, wdinv, b, xin, xout, st);
         return;
     }
     CSRV_SWITCH(csrv_dispatch_jacobi, A, wdinv, b, xin, xout, st)
@@ -2858,7 +2897,8 @@ template <class T>
 void launch_csrv_residual(hipStream_t s, CSRT<T> A, int lanes, const T *b, const T *x, T *r,
                           const SolveStatus *st) {
     if (lanes < 0) {
-        LAUNCH((k_csrs_residual<T>), stream_blocks(A.nrows, -lanes), A, -lanes, b, x, r, st);
+        need_blocks(A);
+        LAUNCH((k_csrs_residual<T>), A.nblk, A, b, x, r, st);
         return;
     }
     CSRV_SWITCH(csrv_dispatch_residual, A, b, x, r, st)
@@ -2867,7 +2907,8 @@ template <class T>
 void launch_csrv_spmv(hipStream_t s, CSRT<T> A, int lanes, const T *x, T *y, bool add,
                       const SolveStatus *st) {
     if (lanes < 0) {
-        LAUNCH((k_csrs_spmv<T>), stream_blocks(A.nrows, -lanes), A, -lanes, x, y, (int)add, st);
+        need_blocks(A);
+        LAUNCH((k_csrs_spmv<T>), A.nblk, A, x, y, (int)add, st);
         return;
     }
     CSRV_SWITCH(csrv_dispatch_spmv, A, x, y, (int)add, st)
