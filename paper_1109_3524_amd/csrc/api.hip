@@ -1472,11 +1472,11 @@ GridT<T> make_grid(ibpm_ctx *c, const GridMetrics &G) {
 }
 
 // First level of the dense coarse cycle: the first level below level 0 with
-// at most kCoarseRows unknowns (the coarsest if none)
-int dense_level(const Hierarchy &h) {
+// at most `rows` unknowns (the coarsest if none)
+int dense_level(const Hierarchy &h, int rows) {
     const int L = (int)h.levels.size();
     for (int l = 1; l < L; ++l)
-        if (h.levels[l].A.nrows <= kCoarseRows) return l;
+        if (h.levels[l].A.nrows <= rows) return l;
     return L - 1;
 }
 
@@ -1488,17 +1488,26 @@ int dense_level(const Hierarchy &h) {
 // R A is formed on every CSR level, where it holds fewer entries than A, and
 // on level 0 (whose K is applied matrix-free, so R A adds stored entries)
 // only up to kFuseRows0 unknowns; A P adds entries to the sweep and is
-// formed up to kFuseRowsP unknowns.
+// formed up to kFuseRowsP unknowns.  R A is dropped where a row of R and R A
+// together would not fit the row-block kernels' LDS buffer (the 3-D levels
+// whose coarse rows gather thousands of entries): there one wave per row
+// took 36 us where the residual in row blocks and R take 20.
 constexpr int kFuseRows0 = 600000;
 constexpr int kFuseRowsP = 200000;
 
 void fused_transfer_products(Hierarchy &h) {
     const int L = (int)h.levels.size();
     if (L < 2) return;
-    const int lc = dense_level(h);
+    const int lc = dense_level(h, kCoarseRows);
     for (int l = 0; l < lc; ++l) {
         Level &lv = h.levels[l];
-        if (l > 0 || lv.A.nrows <= kFuseRows0) lv.RA = csr_multiply(lv.R, lv.A);
+        if (l > 0 || lv.A.nrows <= kFuseRows0) {
+            lv.RA = csr_multiply(lv.R, lv.A);
+            bool fits = true;
+            for (int32_t r = 0; r < lv.R.nrows && fits; ++r)
+                fits = (lv.R.ptr[r + 1] - lv.R.ptr[r]) + (lv.RA.ptr[r + 1] - lv.RA.ptr[r]) <= kStreamCap;
+            if (!fits) lv.RA = CSR();
+        }
         if (l > 0 && lv.A.nrows <= kFuseRowsP) lv.AP = csr_multiply(lv.A, lv.P);
     }
 }
@@ -1628,9 +1637,9 @@ void upload_levels(ibpm_ctx *c, PrecSet<T> &P) {
         dl.xb = c->dalloc<T>(dl.n);
     }
     // levels from the first with at most kCoarseRows unknowns (never level 0,
-    // which is matrix-free) down to the coarsest are applied as one dense
+    // which may be matrix-free) down to the coarsest are applied as one dense
     // product: the cycle there is a fixed linear map, formed once on the host
-    P.lc = dense_level(c->h);
+    P.lc = dense_level(c->h, c->moving ? kCoarseRowsMoving : kCoarseRows);
     if (c->coarse_C_lc != P.lc) {
         c->coarse_C = coarse_cycle_matrix(c->h, P.lc, c->prm.amg_pre, c->prm.amg_post);
         c->coarse_C_lc = P.lc;

@@ -321,12 +321,15 @@ template <class T>
 void launch_csrv_spmv(hipStream_t s, CSRT<T> A, int lanes, const T *x, T *y, bool add,
                       const SolveStatus *st);
 
-// Coarse levels handled together by one work-group (levels lc .. L-1).
-constexpr int kCoarseRows = 1024;
+// Coarse levels applied together as one dense map (levels lc .. L-1): the
+// first level below level 0 with at most kCoarseRows unknowns starts it
+// (kCoarseRowsMoving for a moving body, whose small levels and dense map are
+// formed anew on the host at every refresh of the hierarchy).
+constexpr int kCoarseRows = 4096;
+constexpr int kCoarseRowsMoving = 1024;
 constexpr int kMaxLevels = 16;
-// the V-cycle on the small levels (the first with at most kCoarseRows
-// unknowns and all below it) as one dense product x = C b, C row-major n x n
-// in FP64 for either precision of the cycle
+// the V-cycle on the small levels as one dense product x = C b, C row-major
+// n x n in FP64 for either precision of the cycle
 template <class T>
 void launch_coarse_dense(hipStream_t s, int n, const double *C, const T *b, T *x,
                          const SolveStatus *st);

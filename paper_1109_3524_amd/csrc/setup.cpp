@@ -14,6 +14,7 @@
 #include "setup.h"
 
 #include <algorithm>
+#include <thread>
 #include <cmath>
 #include <map>
 #include <stdexcept>
@@ -1167,13 +1168,24 @@ void cycle_from(const Hierarchy &h, int l, int pre, int post, const std::vector<
 std::vector<double> coarse_cycle_matrix(const Hierarchy &h, int lc, int pre, int post) {
     if (lc < 0 || lc >= (int)h.levels.size() || pre < 1) fail("coarse cycle: bad level or sweep count");
     const int n = h.levels[lc].A.nrows;
-    std::vector<double> C((size_t)n * n), e(n, 0.0), x;
-    for (int j = 0; j < n; ++j) {
-        e[j] = 1.0;
-        cycle_from(h, lc, pre, post, e, x);
-        e[j] = 0.0;
-        for (int i = 0; i < n; ++i) C[(size_t)i * n + j] = x[i];
-    }
+    std::vector<double> C((size_t)n * n);
+    // the columns are independent cycles on unit vectors: a few host threads
+    // take interleaved columns
+    auto cols = [&](int j0, int step) {
+        std::vector<double> e(n, 0.0), x;
+        for (int j = j0; j < n; j += step) {
+            e[j] = 1.0;
+            cycle_from(h, lc, pre, post, e, x);
+            e[j] = 0.0;
+            for (int i = 0; i < n; ++i) C[(size_t)i * n + j] = x[i];
+        }
+    };
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int nt = n < 256 ? 1 : (int)std::min<unsigned>(hw > 0 ? hw : 1, 8);
+    std::vector<std::thread> ts;
+    for (int t = 1; t < nt; ++t) ts.emplace_back(cols, t, nt);
+    cols(0, nt);
+    for (std::thread &t : ts) t.join();
     return C;
 }
 
