@@ -927,8 +927,11 @@ void nn_init_weights(ibpm_ctx *c, uint64_t seed) {
     nn_set_master(c, pt.data());
 }
 
-// forward pass from the features in act[0]; the output goes to y32
-void nn_forward(ibpm_ctx *c) {
+// forward pass from the features in act[0]; the output goes to y32, ys
+// channels per cell (32 for training, whose gradient takes every channel;
+// kOutRow at inference, where only the kNNOut output channels are read)
+constexpr int kOutRow = 4;
+void nn_forward(ibpm_ctx *c, int ys = 32) {
     NNState &N = c->nn;
     hipStream_t s = c->stream;
     for (int l = 0; l < kNNLayers; ++l) {
@@ -936,9 +939,9 @@ void nn_forward(ibpm_ctx *c) {
         float *y32 = last ? N.y32 : nullptr;
         bf16 *y16 = last ? nullptr : N.act[l + 1];
         if (N.cin[l] == kNNInPad)
-            launch_conv3x3<bf16, kNNInPad>(s, N.H, N.W, N.act[l], nullptr, N.fwd[l], y32, y16, last ? 0 : 1);
+            launch_conv3x3<bf16, kNNInPad>(s, N.H, N.W, N.act[l], nullptr, N.fwd[l], y32, y16, last ? 0 : 1, ys);
         else
-            launch_conv3x3<bf16, 32>(s, N.H, N.W, N.act[l], nullptr, N.fwd[l], y32, y16, last ? 0 : 1);
+            launch_conv3x3<bf16, 32>(s, N.H, N.W, N.act[l], nullptr, N.fwd[l], y32, y16, last ? 0 : 1, ys);
     }
 }
 
@@ -951,8 +954,8 @@ void nn_apply(ibpm_ctx *c, const T *r, T *e) {
     const Model &m = c->m;
     launch_nn_scale(s, c->p64.K0.n, r, N.sparts, N.scale);
     launch_nn_features(s, c->g, m.nb, r, (const double *)N.scale, N.inv_hmin, N.cd, N.act[0]);
-    nn_forward(c);
-    launch_nn_output(s, (int)m.g.n_cell, m.nb, N.y32, N.scale, 1.0 / c->prm.dt, N.cd, e);
+    nn_forward(c, kOutRow);
+    launch_nn_output(s, (int)m.g.n_cell, m.nb, N.y32, N.scale, 1.0 / c->prm.dt, N.cd, e, kOutRow);
 }
 
 // loss of one (residual, error) pair and its gradient, added to N.grad;

@@ -37,11 +37,13 @@ struct CellDelta {
 //   mask   optional BF16 [H][W][CIN]; where mask <= 0 the input is read as 0
 //          (the ReLU derivative in the backward pass)
 //   Wp     packed weights [32][conv_kp(CIN)] BF16 (out channel major, k = tap*CIN + c)
-//   Y32    optional FP32 [H][W][32] pre-activation output
+//   Y32    optional FP32 [H][W][ys] pre-activation output (output channels
+//          0 .. ys-1; ys = 32 keeps them all, the network's last layer at
+//          inference keeps its kNNOut channels in rows of 4)
 //   Y16    optional BF16 [H][W][32] output after ReLU (relu != 0) or as is
 template <class TIn, int CIN>
 void launch_conv3x3(hipStream_t s, int H, int W, const TIn *X, const bf16 *mask, const bf16 *Wp,
-                    float *Y32, bf16 *Y16, int relu);
+                    float *Y32, bf16 *Y16, int relu, int ys = 32);
 
 // Weight gradient of one layer for one image: per-block partials
 // [blocks][32][kp] of dW[n][k] = sum_p dY[p][n] X[p + tap][c]; dY is FP32
@@ -76,11 +78,11 @@ void launch_nn_scale(hipStream_t s, int n, const T *r, double *parts, double *sc
 template <class T>
 void launch_nn_features(hipStream_t s, GridView g, int nb, const T *r, const double *scale,
                         double inv_hmin, CellDelta cd, bf16 *X);
-// network output Y32 [H][W][32] -> correction e (lambda layout, T) times
+// network output Y32 [H][W][ys] -> correction e (lambda layout, T) times
 // scale/dt: pressure from channel 0, forces interpolated from channels 1, 2
 template <class T>
 void launch_nn_output(hipStream_t s, int n_cell, int nb, const float *Y32, const double *scale,
-                      double inv_dt, CellDelta cd, T *e);
+                      double inv_dt, CellDelta cd, T *e, int ys = 32);
 // training loss of the correction d = output map of Y32 for the pair (r1,
 // e1) (FP32, lambda layout, K e1 = r1): the share of the energy-norm error
 // that the optimally scaled d removes, -(d.r1)^2 / ((d.Kd)(r1.e1)), into

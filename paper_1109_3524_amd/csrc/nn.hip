@@ -62,7 +62,7 @@ __device__ __forceinline__ void stage_rows(__bf16 *xs, const TIn *X, const __bf1
 template <class TIn, int CIN>
 __global__ __launch_bounds__(kBlock) void k_conv3x3(int H, int W, const TIn *X, const __bf16 *mask,
                                                     const __bf16 *Wp, float *Y32, __bf16 *Y16,
-                                                    int relu) {
+                                                    int relu, int ys) {
     constexpr int KP = conv_kp(CIN);
     constexpr int NS = KP / 16;
     __shared__ __attribute__((aligned(16))) __bf16 xs[(kConvRows + 2) * kTW * CIN];
@@ -101,10 +101,10 @@ __global__ __launch_bounds__(kBlock) void k_conv3x3(int H, int W, const TIn *X, 
             const int p = w * 32 + 8 * (j >> 2) + 4 * (l >> 5) + (j & 3);
             const int gx = x0 + p;
             if (gx < W) {
-                const size_t o = ((size_t)y * W + gx) * 32 + n;
+                const size_t px = (size_t)y * W + gx;
                 const float v = acc[j];
-                if (Y32) Y32[o] = v;
-                if (Y16) Y16[o] = (__bf16)(relu ? fmaxf(v, 0.0f) : v);
+                if (Y32 && n < ys) Y32[px * ys + n] = v;
+                if (Y16) Y16[px * 32 + n] = (__bf16)(relu ? fmaxf(v, 0.0f) : v);
             }
         }
     }
@@ -272,18 +272,18 @@ __global__ __launch_bounds__(kBlock) void k_nn_features(GridView g, int nb, cons
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_nn_output(int n_cell, int nb, const float *Y32,
                                                       const double *scale, double inv_dt,
-                                                      CellDelta cd, T *e) {
+                                                      CellDelta cd, T *e, int ys) {
     const int t = blockIdx.x * kBlock + threadIdx.x;
     const double sc = scale[0] * inv_dt;
     if (t < n_cell) {
-        e[t] = (T)(sc * (double)Y32[(size_t)t * 32]);
+        e[t] = (T)(sc * (double)Y32[(size_t)t * ys]);
     } else if (t < n_cell + 2 * nb) {
         const int k = t - n_cell;
         const int pk = k < nb ? k : k - nb;
         const int ch = k < nb ? 1 : 2;
         double s = 0.0;
         for (int q = cd.p2c.ptr[pk]; q < cd.p2c.ptr[pk + 1]; ++q)
-            s += cd.p2c.val[q] * (double)Y32[(size_t)cd.p2c.col[q] * 32 + ch];
+            s += cd.p2c.val[q] * (double)Y32[(size_t)cd.p2c.col[q] * ys + ch];
         e[t] = (T)(sc * s);
     }
 }
@@ -384,10 +384,11 @@ __global__ __launch_bounds__(kBlock) void k_to_bf16(size_t n, const float *x, __
 
 template <class TIn, int CIN>
 void launch_conv3x3(hipStream_t s, int H, int W, const TIn *X, const bf16 *mask, const bf16 *Wp,
-                    float *Y32, bf16 *Y16, int relu) {
+                    float *Y32, bf16 *Y16, int relu, int ys) {
+    if (ys < 1 || ys > 32) throw std::runtime_error("conv3x3: bad channel stride of the FP32 output");
     dim3 grid((W + kConvTile - 1) / kConvTile, (H + kConvRows - 1) / kConvRows);
     hipLaunchKernelGGL((k_conv3x3<TIn, CIN>), grid, dim3(kBlock), 0, s, H, W, X, mask, Wp, Y32, Y16,
-                       relu);
+                       relu, ys);
 }
 
 void launch_to_bf16(hipStream_t s, size_t n, const float *x, bf16 *y) {
@@ -436,9 +437,10 @@ void launch_nn_features(hipStream_t s, GridView g, int nb, const T *r, const dou
 
 template <class T>
 void launch_nn_output(hipStream_t s, int n_cell, int nb, const float *Y32, const double *scale,
-                      double inv_dt, CellDelta cd, T *e) {
+                      double inv_dt, CellDelta cd, T *e, int ys) {
     int n = n_cell + 2 * nb;
-    LAUNCH((k_nn_output<T>), (n + kBlock - 1) / kBlock, n_cell, nb, Y32, scale, inv_dt, cd, e);
+    if (ys < kNNOut || ys > 32) throw std::runtime_error("nn output: bad channel stride");
+    LAUNCH((k_nn_output<T>), (n + kBlock - 1) / kBlock, n_cell, nb, Y32, scale, inv_dt, cd, e, ys);
 }
 
 void launch_nn_energy_loss(hipStream_t s, const K0View &K, int nb, const float *Y32,
@@ -459,13 +461,13 @@ void launch_nn_energy_loss(hipStream_t s, const K0View &K, int nb, const float *
 }
 
 template void launch_conv3x3<bf16, 8>(hipStream_t, int, int, const bf16 *, const bf16 *,
-                                      const bf16 *, float *, bf16 *, int);
+                                      const bf16 *, float *, bf16 *, int, int);
 template void launch_conv3x3<bf16, 32>(hipStream_t, int, int, const bf16 *, const bf16 *,
-                                       const bf16 *, float *, bf16 *, int);
+                                       const bf16 *, float *, bf16 *, int, int);
 template void launch_conv3x3<float, 32>(hipStream_t, int, int, const float *, const bf16 *,
-                                        const bf16 *, float *, bf16 *, int);
+                                        const bf16 *, float *, bf16 *, int, int);
 template void launch_conv3x3<float, 8>(hipStream_t, int, int, const float *, const bf16 *,
-                                       const bf16 *, float *, bf16 *, int);
+                                       const bf16 *, float *, bf16 *, int, int);
 template void launch_conv3x3_dw<8>(hipStream_t, int, int, const bf16 *, const float *,
                                    const bf16 *, float *);
 template void launch_conv3x3_dw<32>(hipStream_t, int, int, const bf16 *, const float *,
@@ -478,8 +480,8 @@ template void launch_nn_features<float>(hipStream_t, GridView, int, const float 
                                         const double *, double, CellDelta, bf16 *);
 
 template void launch_nn_output<double>(hipStream_t, int, int, const float *, const double *, double,
-                                       CellDelta, double *);
+                                       CellDelta, double *, int);
 template void launch_nn_output<float>(hipStream_t, int, int, const float *, const double *, double,
-                                      CellDelta, float *);
+                                      CellDelta, float *, int);
 
 }  // namespace ibpm
