@@ -275,9 +275,9 @@ void launch_k0_jacobi(hipStream_t s, const K0T<T> &K, double omega, const T *b, 
 // post2_rows(K) rows of cells per block, each wave recomputing x' and y
 // three cells around its 58 columns; the cells within three of the box
 // coupled to the forces and the force rows, whose rows reach past any
-// strip, are done by three small passes over that box grown by 2, 1 and 0
-// more cells, through the level-0 work vectors tmp (x') and tmp2 (y).
-// a is only read.
+// strip, are done over that box grown by 2, 1 and 0 more cells: x' by the
+// first blocks of the strip launch, y and z by two small launches after it,
+// through the level-0 work vectors tmp (x') and tmp2 (y).  a is only read.
 // mode 0: z in T and the partials of b . z; mode 1 (T = float): z widened to
 // z64 and the partials of r64 . z64; mode 2: z only.  Returns the number of
 // partials (the strip pass's, then the box pass's).

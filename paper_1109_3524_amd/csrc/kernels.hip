@@ -1240,19 +1240,82 @@ __device__ __forceinline__ float lane_value(float v, int k) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
 }
 
+// The level-0 rows of a rectangle of cells (one thread per cell; coupled
+// cells are left to the band) and the band rows.
+template <class T, class XV, class PF, class ACT>
+__device__ __forceinline__ void k0_walk_rect(const K0T<T> &K, CellRect rc, XV xv, PF pf, ACT act) {
+    const int band = k0_band(K);
+    const int b = (int)blockIdx.x;
+    if (b < band) {
+        k0_band_rows<T>(K, b, xv, pf, act);
+        return;
+    }
+    const int wdt = rc.i1 - rc.i0 + 1;
+    const int idx = (b - band) * kBlock + threadIdx.x;
+    if (wdt <= 0 || idx >= wdt * (rc.j1 - rc.j0 + 1)) return;
+    const int j = rc.j0 + idx / wdt, i = rc.i0 + idx % wdt;
+    if (k0_coupled(K, i, j)) return;
+    T diag, xc;
+    const T y = k0_cell_stencil(K, i, j, xv, diag, xc);
+    const int row = j * K.g.nx + i;
+    act(row, y, diag, xc, pf(row));
+}
+
+template <class T>
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi_rect(K0T<T> K, CellRect rc, T omega,
+                                                           const T *__restrict__ b, const T *__restrict__ xin,
+                                                           T *__restrict__ xout, const SolveStatus *st) {
+    if (st->done) return;
+    k0_walk_rect(K, rc, [&](int c) { return xin[c]; }, [&](int row) { return b[row]; },
+                 [&](int row, T ax, T d, T xr, T br) { xout[row] = xr + omega / d * (br - ax); });
+}
+
+template <int MODE, class T>
+__global__ __launch_bounds__(kBlock) void k_k0_jacobi_last_rect(K0T<T> K, CellRect rc, T omega,
+                                                                const T *__restrict__ b,
+                                                                const T *__restrict__ xin, T *__restrict__ z,
+                                                                double *__restrict__ z64,
+                                                                const double *__restrict__ r64,
+                                                                const SolveStatus *st, double *parts) {
+    if (st->done) return;
+    double v[1] = {0.0};
+    k0_walk_rect(K, rc, [&](int c) { return xin[c]; }, [&](int row) { return b[row]; },
+                 [&](int row, T ax, T d, T xr, T br) {
+                     const T zz = xr + omega / d * (br - ax);
+                     if constexpr (MODE == POST_WIDEN) {
+                         const double zd = (double)zz;
+                         z64[row] = zd;
+                         v[0] += r64[row] * zd;
+                     } else {
+                         z[row] = zz;
+                         if constexpr (MODE == POST_RZ) v[0] += (double)br * (double)zz;
+                     }
+                 });
+    if constexpr (MODE != POST_PLAIN) write_parts2<1>(v, parts);
+}
+
 template <int RF, int MODE, class T>
 __global__ __launch_bounds__(kBlock) void k_k0_prolong_post2(
     K0T<T> K, CellRect skip, const int *__restrict__ agg, const T *__restrict__ x1, T pw, T omega,
     const T *__restrict__ b, const T *__restrict__ a, T *__restrict__ z, double *__restrict__ z64,
-    const double *__restrict__ r64, const SolveStatus *st, double *parts) {
+    const double *__restrict__ r64, const SolveStatus *st, double *parts, CellRect r2, T *__restrict__ tmp,
+    int G2) {
     constexpr int NS = RF + 2 * kPostHalo;       // rows walked
     constexpr int D = kPostAhead;
     static_assert(NS + 1 <= 64, "the row metrics of a walk are held one row per lane");
     if (st->done) return;
+    if ((int)blockIdx.x < G2) {
+        // the first G2 blocks (dispatched first: their rows reach through
+        // gathers) form x' on the box grown by 5 and the force rows, into tmp
+        k0_walk_rect(K, r2, [&](int c) { return x1[agg[c]]; }, [&](int row) { return a[row]; },
+                     [&](int row, T kt, T d, T t, T ar) { tmp[row] = ar + (t - pw * (kt / d)); });
+        return;
+    }
     const GridT<T> &g = K.g;
     const int nx = g.nx, ny = g.ny, pin = K.pin;
     const int ncs = (nx + kPostBlockCols - 1) / kPostBlockCols;
-    const int w = remap_block(blockIdx.x, gridDim.x);
+    const int sb = (int)blockIdx.x - G2;         // strip block
+    const int w = remap_block(sb, (int)gridDim.x - G2);
     const int cy = w / ncs, cx = w - cy * ncs;
     const int lane = threadIdx.x & 63;
     const int i = cx * kPostBlockCols + (threadIdx.x >> 6) * kPostCols - kPostHalo + lane;
@@ -1393,72 +1456,9 @@ __global__ __launch_bounds__(kBlock) void k_k0_prolong_post2(
     }
     if constexpr (MODE != POST_PLAIN) {
         double vv[1] = {v};
-        write_parts2<1>(vv, parts);
+        block_sum<1>(vv);
+        if (threadIdx.x == 0) parts[sb] = vv[0];
     }
-}
-
-// The level-0 rows of a rectangle of cells (one thread per cell; coupled
-// cells are left to the band) and the band rows.
-template <class T, class XV, class PF, class ACT>
-__device__ __forceinline__ void k0_walk_rect(const K0T<T> &K, CellRect rc, XV xv, PF pf, ACT act) {
-    const int band = k0_band(K);
-    const int b = (int)blockIdx.x;
-    if (b < band) {
-        k0_band_rows<T>(K, b, xv, pf, act);
-        return;
-    }
-    const int wdt = rc.i1 - rc.i0 + 1;
-    const int idx = (b - band) * kBlock + threadIdx.x;
-    if (wdt <= 0 || idx >= wdt * (rc.j1 - rc.j0 + 1)) return;
-    const int j = rc.j0 + idx / wdt, i = rc.i0 + idx % wdt;
-    if (k0_coupled(K, i, j)) return;
-    T diag, xc;
-    const T y = k0_cell_stencil(K, i, j, xv, diag, xc);
-    const int row = j * K.g.nx + i;
-    act(row, y, diag, xc, pf(row));
-}
-
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_k0_prolong_rect(K0T<T> K, CellRect rc, const int *__restrict__ agg,
-                                                            const T *__restrict__ x1, T w,
-                                                            const T *__restrict__ a, T *__restrict__ ap,
-                                                            const SolveStatus *st) {
-    if (st->done) return;
-    k0_walk_rect(K, rc, [&](int c) { return x1[agg[c]]; }, [&](int row) { return a[row]; },
-                 [&](int row, T kt, T d, T t, T ar) { ap[row] = ar + (t - w * (kt / d)); });
-}
-
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_k0_jacobi_rect(K0T<T> K, CellRect rc, T omega,
-                                                           const T *__restrict__ b, const T *__restrict__ xin,
-                                                           T *__restrict__ xout, const SolveStatus *st) {
-    if (st->done) return;
-    k0_walk_rect(K, rc, [&](int c) { return xin[c]; }, [&](int row) { return b[row]; },
-                 [&](int row, T ax, T d, T xr, T br) { xout[row] = xr + omega / d * (br - ax); });
-}
-
-template <int MODE, class T>
-__global__ __launch_bounds__(kBlock) void k_k0_jacobi_last_rect(K0T<T> K, CellRect rc, T omega,
-                                                                const T *__restrict__ b,
-                                                                const T *__restrict__ xin, T *__restrict__ z,
-                                                                double *__restrict__ z64,
-                                                                const double *__restrict__ r64,
-                                                                const SolveStatus *st, double *parts) {
-    if (st->done) return;
-    double v[1] = {0.0};
-    k0_walk_rect(K, rc, [&](int c) { return xin[c]; }, [&](int row) { return b[row]; },
-                 [&](int row, T ax, T d, T xr, T br) {
-                     const T zz = xr + omega / d * (br - ax);
-                     if constexpr (MODE == POST_WIDEN) {
-                         const double zd = (double)zz;
-                         z64[row] = zd;
-                         v[0] += r64[row] * zd;
-                     } else {
-                         z[row] = zz;
-                         if constexpr (MODE == POST_RZ) v[0] += (double)br * (double)zz;
-                     }
-                 });
-    if constexpr (MODE != POST_PLAIN) write_parts2<1>(v, parts);
 }
 
 // mixed precision outer loop: r = b - K x in FP64, r32 = (float) r, ||r||^2, ||b||^2
@@ -2738,9 +2738,9 @@ int launch_k0_prolong_post2(hipStream_t s, const K0T<T> &K, const int *agg, cons
     // write z elsewhere.
     const int G1 = rect_blocks(K, r1), G2 = rect_blocks(K, r2);
     auto box = [&](hipStream_t q) {
-        // x' on the box grown by 5 and the force rows, y on it grown by 4,
-        // then z on it grown by 3
-        if (G2 > 0) hipLaunchKernelGGL((k_k0_prolong_rect<T>), dim3(G2), dim3(kBlock), 0, q, K, r2, agg, x1, tw, a, tmp, st);
+        // (x' on the box grown by 5 and the force rows is formed by the first
+        // blocks of the strip launch) y on it grown by 4, then z on it grown
+        // by 3
         if (G1 > 0) hipLaunchKernelGGL((k_k0_jacobi_rect<T>), dim3(G1), dim3(kBlock), 0, q, K, r1, to, b, (const T *)tmp, tmp2, st);
         if (Gb > 0) {
             double *pb = parts + Gf;
@@ -2755,9 +2755,12 @@ int launch_k0_prolong_post2(hipStream_t s, const K0T<T> &K, const int *agg, cons
                                    (const T *)tmp2, z, z64, r64, st, pb);
         }
     };
-    box(s);
+    // the strips, after G2p blocks that form x' on the box (G2 padded to a
+    // multiple of 8, so that the strips keep their XCD mapping)
+    const int G2p = (G2 + 7) & ~7;
 #define POST_STRIPS(RFV, MODEV)                                                                   \
-    LAUNCH((k_k0_prolong_post2<RFV, MODEV, T>), Gf, K, skip, agg, x1, tw, to, b, a, z, z64, r64, st, parts)
+    LAUNCH((k_k0_prolong_post2<RFV, MODEV, T>), G2p + Gf, K, skip, agg, x1, tw, to, b, a, z, z64, r64, st, \
+           parts, r2, tmp, G2p)
 #define POST_MODES(RFV)                                                                           \
     if (mode == POST_RZ) POST_STRIPS(RFV, POST_RZ);                                                \
     else if (mode == POST_PLAIN) POST_STRIPS(RFV, POST_PLAIN);                                     \
@@ -2767,6 +2770,7 @@ int launch_k0_prolong_post2(hipStream_t s, const K0T<T> &K, const int *agg, cons
     else { POST_MODES(32) }
 #undef POST_MODES
 #undef POST_STRIPS
+    box(s);
     return mode == POST_PLAIN ? 0 : Gf + Gb;
 }
 
