@@ -2108,7 +2108,23 @@ __global__ __launch_bounds__(kBlock) void k_coarse_dense(int n, const double *__
     if (row >= n) return;
     const double *c = C + (size_t)row * n;
     double acc = 0.0;
-    for (int k = lane; k < n; k += 64) acc += c[k] * (double)b[k];
+    if (((size_t)row * n) % 2 == 0) {
+        // the row starts on 16 bytes: pairs of entries per load, several
+        // loads in flight per lane
+        const int n2 = n & ~1;
+        double a1 = 0.0;
+#pragma unroll 4
+        for (int k = 2 * lane; k < n2; k += 128) {
+            const double2 cv = *(const double2 *)(c + k);
+            acc += cv.x * (double)b[k];
+            a1 += cv.y * (double)b[k + 1];
+        }
+        if ((n & 1) && lane == 0) acc += c[n - 1] * (double)b[n - 1];
+        acc += a1;
+    } else {
+#pragma unroll 4
+        for (int k = lane; k < n; k += 64) acc += c[k] * (double)b[k];
+    }
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if (lane == 0) x[row] = (T)acc;
 }
