@@ -181,3 +181,27 @@ def test_3d_points_outside_the_uniform_cells_are_rejected_on_the_host():
     assert rc == ibpm.IBPM_EINVAL
     assert "domain edge" in L.ibpm_last_error(h).decode()
     L.ibpm_destroy(h)
+
+
+def _defines(prefix):
+    text = open(HEADER).read()
+    return {m.group(1): int(m.group(2)) for m in re.finditer(rf"#define ({prefix}[A-Z_0-9]*)\s+(-?\d+)", text)}
+
+
+def test_binding_constants_match_the_header():
+    """The kernel ids of ibpm_time_kernel / ibpm_iteration_launches, the
+    solver ids and the status codes the binding uses are the header's."""
+    kern = _defines("IBPM_KERNEL_")
+    num = _defines("IBPM_NUM_KERNELS")["IBPM_NUM_KERNELS"]
+    assert sorted(kern.values()) == list(range(num))
+    assert len(ibpm.KERNELS) == num and sorted(ibpm.KERNELS.values()) == list(range(num))
+    for name, k in ibpm.KERNELS.items():
+        assert kern["IBPM_KERNEL_" + name.upper()] == k, name
+    solvers = _defines("IBPM_SOLVER_")
+    for name in ("JACOBI_PCG", "AMG_PCG", "AMG_PCG_MIXED", "AMG_FCG_LEARNED", "AMG_FCG_MIXED_LEARNED",
+                 "AMG_PCG_FP32_CYCLE", "AMG_PCG_FP32_CYCLE_GUESS"):
+        assert getattr(W, "SOLVER_" + name) == solvers["IBPM_SOLVER_" + name], name
+    codes = _defines("IBPM_E")
+    codes.update(_defines("IBPM_OK"))
+    for name in ("IBPM_OK", "IBPM_EINVAL", "IBPM_ENOMEM", "IBPM_ENOTCONV", "IBPM_EHIP", "IBPM_ENAN"):
+        assert getattr(ibpm, name) == codes[name], name
